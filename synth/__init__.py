@@ -1,0 +1,160 @@
+"""Seeded synthetic inputs shaped like the paper's workloads (Sec. 4.1.1).
+
+This module only produces data: a low-rank CP model with U[0,1) factors plus
+Gaussian noise at a given fraction of the tensor norm (dense), or nonzeros
+drawn from a nonnegative CP model with Zipf row popularity (sparse COO).  It
+contains none of the update's arithmetic.  The oracle and the HIP path both
+consume its outputs bit for bit.
+
+Randomness comes from NumPy's Philox bit generator keyed by SeedSequence
+(seed, stream, block), so a slice block can be regenerated on its own.
+"""
+
+import numpy as np
+
+STREAM_FACTOR = 11
+STREAM_NOISE = 12
+STREAM_SPARSE = 13
+STREAM_ARRIVAL = 14
+
+
+def _gen(seed, stream, block=0):
+    return np.random.Generator(np.random.Philox(np.random.SeedSequence([seed, stream, block])))
+
+
+class DenseCP:
+    """X = sum_r A(:,r) o B(:,r) o C(:,r) + N(0, sigma^2), factors U[0,1).
+
+    sigma = noise * ||X_clean||_F / sqrt(I*J*K), with ||X_clean||^2 taken in
+    closed form from the factor Gram matrices, so the noise is `noise` of the
+    tensor norm in expectation and slices can be produced in any order.
+    """
+
+    def __init__(self, I, J, K, R, seed, noise=0.01, dtype=np.float32):
+        self.I, self.J, self.K, self.R = int(I), int(J), int(K), int(R)
+        self.seed, self.noise, self.dtype = int(seed), float(noise), np.dtype(dtype)
+        g = _gen(seed, STREAM_FACTOR)
+        self.A = g.random((self.I, self.R))
+        self.B = g.random((self.J, self.R))
+        self.C = g.random((self.K, self.R))
+        H = (self.A.T @ self.A) * (self.B.T @ self.B) * (self.C.T @ self.C)
+        self.clean_norm2 = float(H.sum())
+        self.sigma = self.noise * np.sqrt(self.clean_norm2 / (self.I * self.J * self.K))
+
+    def slices(self, k0, k1, block=256):
+        """Frontal slices k0..k1-1 as an (I, J, k1-k0) Fortran-ordered array."""
+        out = np.empty((self.I, self.J, k1 - k0), dtype=self.dtype, order="F")
+        for b0 in range(k0, k1, block):
+            b1 = min(k1, b0 + block)
+            # X_(3) rows = C (B kr A)^T for the block, built slice by slice in FP64
+            for k in range(b0, b1):
+                S = (self.A * self.C[k][None, :]) @ self.B.T
+                if self.noise > 0:
+                    S = S + self.sigma * _gen(self.seed, STREAM_NOISE, k).standard_normal(
+                        (self.I, self.J))
+                out[:, :, k - k0] = S.astype(self.dtype)
+        return out
+
+    def true_model(self):
+        """Ground-truth factors normalised to unit columns, weights in lambda,
+        ordered by lambda descending."""
+        nA = np.linalg.norm(self.A, axis=0)
+        nB = np.linalg.norm(self.B, axis=0)
+        nC0 = np.linalg.norm(self.C, axis=0)
+        lam = nA * nB * nC0
+        order = np.argsort(-lam, kind="stable")
+        return (self.A[:, order] / nA[order], self.B[:, order] / nB[order],
+                self.C[:, order] / nC0[order], lam[order])
+
+    def true_model_prefix(self, K0):
+        """Unit A, B; C restricted to the first K0 slices, in the same units
+        as true_model() (so C rows of later slices continue the same scale)."""
+        A, B, C, lam = self.true_model()
+        return A, B, C[:K0].copy(), lam
+
+
+class SparseCP:
+    """COO nonzeros drawn from a nonnegative rank-R model.
+
+    For component r: Zipf(zipf) popularity over a random permutation of the
+    indices of modes 1 and 2, and a U[0,1) profile over mode 3.  A nonzero
+    picks a component uniformly, then i, j, k from the three profiles;
+    duplicates on the key (i*J + j)*K + k are dropped and the draw topped up
+    until nnz distinct coordinates exist.  The value is the model entry
+    sum_r lam_r a_r(i) b_r(j) c_r(k) (scaled to mean ~1) plus N(0, sigma^2),
+    sigma = noise * ||v_clean|| / sqrt(nnz).
+    """
+
+    def __init__(self, I, J, K, R, seed, zipf=1.1, noise=0.01):
+        self.I, self.J, self.K, self.R = int(I), int(J), int(K), int(R)
+        self.seed, self.zipf, self.noise = int(seed), float(zipf), float(noise)
+        g = _gen(seed, STREAM_FACTOR)
+        self.pa = np.empty((self.R, self.I))
+        self.pb = np.empty((self.R, self.J))
+        for r in range(self.R):
+            self.pa[r, g.permutation(self.I)] = (1.0 + np.arange(self.I)) ** (-self.zipf)
+            self.pb[r, g.permutation(self.J)] = (1.0 + np.arange(self.J)) ** (-self.zipf)
+        self.pc = g.random((self.R, self.K))
+        self.pa /= self.pa.sum(axis=1, keepdims=True)
+        self.pb /= self.pb.sum(axis=1, keepdims=True)
+        self.pc /= self.pc.sum(axis=1, keepdims=True)
+        self.scale = 1.0
+
+    def _model_values(self, idx):
+        v = np.zeros(idx.shape[0])
+        for r in range(self.R):
+            v += self.pa[r, idx[:, 0]] * self.pb[r, idx[:, 1]] * self.pc[r, idx[:, 2]]
+        return v
+
+    def slices(self, k0, k1, nnz, block_id=0):
+        """About `nnz` distinct nonzeros with k in [k0, k1); returns
+        (idx (nnz,3) int32 with k relative to k0, vals float32)."""
+        g = _gen(self.seed, STREAM_SPARSE, block_id)
+        keys = np.empty(0, dtype=np.int64)
+        span = k1 - k0
+        pc = self.pc[:, k0:k1]
+        pc = pc / pc.sum(axis=1, keepdims=True)
+        cum_a = np.cumsum(self.pa, axis=1)
+        cum_b = np.cumsum(self.pb, axis=1)
+        cum_c = np.cumsum(pc, axis=1)
+        while keys.size < nnz:
+            m = int((nnz - keys.size) * 1.2) + 16
+            comp = g.integers(0, self.R, size=m)
+            ii = np.empty(m, dtype=np.int64)
+            jj = np.empty(m, dtype=np.int64)
+            kk = np.empty(m, dtype=np.int64)
+            for r in range(self.R):
+                sel = comp == r
+                cnt = int(sel.sum())
+                if cnt == 0:
+                    continue
+                ii[sel] = np.minimum(np.searchsorted(cum_a[r], g.random(cnt) * cum_a[r, -1]),
+                                     self.I - 1)
+                jj[sel] = np.minimum(np.searchsorted(cum_b[r], g.random(cnt) * cum_b[r, -1]),
+                                     self.J - 1)
+                kk[sel] = np.minimum(np.searchsorted(cum_c[r], g.random(cnt) * cum_c[r, -1]),
+                                     span - 1)
+            new = (ii * self.J + jj) * span + kk
+            keys = np.unique(np.concatenate([keys, new]))
+        keys = keys[g.permutation(keys.size)[:nnz]]
+        keys.sort()
+        kk = keys % span
+        ij = keys // span
+        jj = ij % self.J
+        ii = ij // self.J
+        idx = np.stack([ii, jj, kk], axis=1)
+        full = idx.copy()
+        full[:, 2] += k0
+        v = self._model_values(full)
+        mean = v.mean() if v.size else 1.0
+        v = v / mean
+        if self.noise > 0 and v.size:
+            sigma = self.noise * np.linalg.norm(v) / np.sqrt(v.size)
+            v = v + sigma * g.standard_normal(v.size)
+        return idx.astype(np.int32), v.astype(np.float32)
+
+
+def poisson_arrivals(n, rate, seed):
+    """Arrival times (s) of a Poisson process with `rate` requests per second."""
+    g = _gen(seed, STREAM_ARRIVAL)
+    return np.cumsum(g.exponential(1.0 / rate, size=n))
