@@ -1,0 +1,204 @@
+/*
+ * sambaten.h - C ABI of the MI355X (gfx950) SamBaTen update library.
+ *
+ * SamBaTen: Sampling-based Batch Incremental Tensor Decomposition (Gujral,
+ * Pasricha, Papalexakis).  The library keeps a 3-mode tensor that grows along
+ * its third mode, its rank-R CP model (A, B, C, lambda) and the sampling
+ * state on one GPU, and applies the batch update of Algorithm 1 to each new
+ * batch of frontal slices.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Indices are 0-based.
+ * - A dense tensor is column-major: element (i, j, k) of an I x J x K tensor
+ *   sits at i + I*(j + J*k), so a batch of frontal slices is one contiguous
+ *   block.  Element type: double for SBT_P_F64, float otherwise.
+ * - A COO tensor is structure-of-arrays: int32 i, j, k and float values.
+ * - Factor matrices crossing the ABI are row-major double arrays
+ *   (A: I x R, B: J x R, C: K x R), lambda is R doubles.
+ * - Pointers named *_dev are device pointers; every other pointer is host
+ *   memory.  The caller owns all buffers it passes and keeps them valid until
+ *   the call returns (calls that take a stream are finished when they return
+ *   unless stated otherwise).  The library owns every buffer it allocates and
+ *   releases them in sbt_destroy.
+ * - `stream` is a hipStream_t (NULL = the default stream).
+ * - No C++ exception or abort crosses the ABI.  Every call returns an
+ *   sbt_status; sbt_last_error() gives a message for the last failure on a
+ *   tensor.  A failed sbt_update_* leaves the tensor exactly as it was.
+ * - An sbt_tensor is not thread-safe: one call at a time per tensor.
+ */
+#ifndef SAMBATEN_H
+#define SAMBATEN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sbt_tensor sbt_tensor;
+
+typedef enum {
+  SBT_OK = 0,
+  SBT_E_INVALID = 1,  /* bad argument (null pointer, rank out of range ...) */
+  SBT_E_SHAPE = 2,    /* I/J mismatch, empty batch, capacity exceeded */
+  SBT_E_NOMEM = 3,    /* device allocation failed */
+  SBT_E_DEVICE = 4,   /* a HIP runtime call failed */
+  SBT_E_NUMERIC = 5,  /* non-finite input, or the integer importance sums would overflow */
+  SBT_E_STATE = 6     /* call not valid in the tensor's current state */
+} sbt_status;
+
+typedef enum { SBT_DENSE = 0, SBT_COO = 1 } sbt_format;
+
+/* Arithmetic of the summaries and of MTTKRP.  Gram matrices, Cholesky
+ * solves, normalisation, matching and the row solve are FP64 in all cases.
+ *   SBT_P_F64  : FP64 store, FP64 summaries and MTTKRP
+ *   SBT_P_F32  : FP32 store, FP32 summaries, FP32 MTTKRP accumulation
+ *   SBT_P_BF16 : FP32 store, BF16 summaries (round to nearest even),
+ *                MTTKRP on BF16 MFMA with FP32 accumulation            */
+typedef enum { SBT_P_F64 = 0, SBT_P_F32 = 1, SBT_P_BF16 = 2 } sbt_precision;
+
+/* How the r repetitions are launched.
+ *   SBT_SCHED_BATCHED: every launch covers all r repetitions; the three
+ *     MTTKRPs of an ALS sweep take two passes over each summary (the mode-1
+ *     and mode-2 products share the contraction with C).
+ *   SBT_SCHED_PLAIN:   one launch sequence per repetition, three passes per
+ *     sweep (one per mode).  Same arithmetic, used as the baseline.        */
+typedef enum { SBT_SCHED_BATCHED = 0, SBT_SCHED_PLAIN = 1 } sbt_schedule;
+
+typedef struct {
+  int32_t rank;              /* R, 1..32 */
+  int32_t repetitions;       /* r >= 1 (Algorithm 1) */
+  int32_t als_iters;         /* CP-ALS sweeps on each summary (fixed count) */
+  int32_t init_iters;        /* CP-ALS sweeps of the initial decomposition */
+  int32_t sample_factor[3];  /* s per mode: n_m = ceil(N_m / s_m) (Sec. 3.1) */
+  int32_t format;            /* sbt_format */
+  int32_t precision;         /* sbt_precision */
+  int32_t schedule;          /* sbt_schedule */
+  uint64_t seed;             /* Philox key, low word */
+  uint32_t tensor_id;        /* xored into the high key word */
+  uint32_t flags;            /* reserved, must be 0 */
+  int64_t k_capacity;        /* largest third-mode size the tensor may reach */
+  int64_t max_batch;         /* largest K_new of one update */
+  int64_t nnz_capacity;      /* COO only: largest number of stored nonzeros */
+} sbt_config;
+
+/* --------------------------------------------------------------------------
+ * Lifecycle (problem statement of Sec. 2.2: the existing tensor and its
+ * R-component decomposition are the starting point).
+ * ------------------------------------------------------------------------ */
+
+/* Create a tensor from an existing dense I x J x K0 block X0_dev (device,
+ * column-major, element type per cfg->precision).  The library copies X0
+ * into its own storage sized for cfg->k_capacity.
+ * If A0, B0, C0, lambda0 (host, row-major) are all non-NULL they become the
+ * model as given; if all are NULL the library runs cfg->init_iters CP-ALS
+ * sweeps on X0 (random U[0,1) start) and orders the components by lambda,
+ * largest first.  Any other combination is SBT_E_INVALID. */
+sbt_status sbt_init_dense(const sbt_config* cfg, const void* X0_dev, int64_t I, int64_t J,
+                          int64_t K0, const double* A0, const double* B0, const double* C0,
+                          const double* lambda0, void* stream, sbt_tensor** out);
+
+/* Same for a COO tensor: nnz entries (i_dev[e], j_dev[e], k_dev[e], v_dev[e]),
+ * device arrays; coordinates must lie inside I x J x K0. */
+sbt_status sbt_init_coo(const sbt_config* cfg, const int32_t* i_dev, const int32_t* j_dev,
+                        const int32_t* k_dev, const float* v_dev, int64_t nnz, int64_t I,
+                        int64_t J, int64_t K0, const double* A0, const double* B0,
+                        const double* C0, const double* lambda0, void* stream,
+                        sbt_tensor** out);
+
+void sbt_destroy(sbt_tensor* t);
+
+/* --------------------------------------------------------------------------
+ * The update (Algorithm 1): append K_new frontal slices and update the model.
+ * Steps, all on the GPU: importance of the batch (Eq. 1) and input check;
+ * per repetition and mode, weighted sampling without replacement of
+ * ceil(N/s) indices from the tensor before the update; gather of the
+ * summaries X(I_s, J_s, K_s u new); CP-ALS on every summary; normalisation
+ * and optimal matching against A(I_s), B(J_s), C(K_s); least-squares rows of
+ * C for the summary's slices; zero-entry fill; average of the new rows over
+ * the repetitions; append.  lambda is left unchanged.
+ * Returns when the update is complete.  SBT_E_NUMERIC for a non-finite value
+ * or an importance overflow (tensor unchanged); SBT_E_SHAPE when K_new < 1,
+ * K_new > max_batch or K + K_new > k_capacity.
+ * ------------------------------------------------------------------------ */
+
+/* Y_dev: I x J x K_new dense batch, column-major, device. */
+sbt_status sbt_update_batch_dense(sbt_tensor* t, const void* Y_dev, int64_t K_new, void* stream);
+
+/* COO batch; k_dev holds batch-relative third-mode indices 0..K_new-1. */
+sbt_status sbt_update_batch_coo(sbt_tensor* t, const int32_t* i_dev, const int32_t* j_dev,
+                                const int32_t* k_dev, const float* v_dev, int64_t nnz,
+                                int64_t K_new, void* stream);
+
+/* --------------------------------------------------------------------------
+ * Queries.
+ * ------------------------------------------------------------------------ */
+
+sbt_status sbt_get_shape(const sbt_tensor* t, int64_t* I, int64_t* J, int64_t* K, int32_t* R);
+
+/* Copy the model to caller-owned host buffers (row-major A I x R, B J x R,
+ * C K x R, lambda R).  Any of the pointers may be NULL to skip it. */
+sbt_status sbt_get_factors(sbt_tensor* t, double* A, double* B, double* C, double* lambda,
+                           void* stream);
+
+/* fit = 1 - ||X - Xhat||_F / ||X||_F over every stored slice (the relative
+ * error of Sec. 4.2, as 1 - RE).  Computed on the GPU in FP64 from one pass
+ * over the tensor and the factor Gram matrices. */
+sbt_status sbt_fit(sbt_tensor* t, double* fit, void* stream);
+
+/* Number of completed updates (the batch counter that keys the sampler). */
+sbt_status sbt_get_batch_counter(const sbt_tensor* t, uint32_t* counter);
+
+/* --------------------------------------------------------------------------
+ * Inspection of the last update, for testing (host outputs).
+ * ------------------------------------------------------------------------ */
+
+/* Sampled indices of repetition `rep`, mode 0/1/2 (I_s, J_s, K_s), ascending.
+ * idx must hold at least the mode's sample size; *n receives it. */
+sbt_status sbt_last_sample(const sbt_tensor* t, int32_t rep, int32_t mode, int32_t* idx,
+                           int64_t* n);
+
+typedef enum {
+  SBT_REP_AP = 0,     /* summary factor A' (n1 x R), unit columns          */
+  SBT_REP_BP = 1,     /* summary factor B' (n2 x R)                        */
+  SBT_REP_CP = 2,     /* summary factor C' (K' x R)                        */
+  SBT_REP_LAMP = 3,   /* summary weights lambda' (R)                       */
+  SBT_REP_PI = 4,     /* matching: sample column matched to column f (R)   */
+  SBT_REP_VALID = 5,  /* 1 where the repetition is valid for column f (R)  */
+  SBT_REP_AT = 6,     /* matched, rescaled A rows (n1 x R)                 */
+  SBT_REP_BT = 7,     /* matched, rescaled B rows (n2 x R)                 */
+  SBT_REP_CT = 8      /* least-squares C rows of the summary (K' x R)      */
+} sbt_rep_item;
+
+/* Copy one per-repetition intermediate of the last update as doubles into
+ * `out` (host, capacity `cap` doubles); *rows receives the row count. */
+sbt_status sbt_last_rep(const sbt_tensor* t, int32_t rep, int32_t item, double* out,
+                        int64_t cap, int64_t* rows);
+
+/* --------------------------------------------------------------------------
+ * Stand-alone kernels (the same code the update runs), for parity tests and
+ * measurement.  All pointers are device pointers.
+ * ------------------------------------------------------------------------ */
+
+/* MTTKRP of a dense n1 x n2 x n3 tensor Z (column-major; element type per
+ * `precision`: double, float, or bfloat16 bits as uint16) with row-major
+ * double factors U0 (n1 x R), U1 (n2 x R), U2 (n3 x R):
+ *   mode 0: out(a,f) = sum_bc Z(a,b,c) U1(b,f) U2(c,f)     (n1 x R)
+ *   mode 1: out(b,f) = sum_ac Z(a,b,c) U0(a,f) U2(c,f)     (n2 x R)
+ *   mode 2: out(c,f) = sum_ab Z(a,b,c) U0(a,f) U1(b,f)     (n3 x R)
+ * out is row-major double.  The factor for `mode` itself is not read.
+ * Stream-ordered: returns after enqueueing. */
+sbt_status sbt_mttkrp_dense(int32_t precision, const void* Z_dev, int64_t n1, int64_t n2,
+                            int64_t n3, int32_t R, const double* U0_dev, const double* U1_dev,
+                            const double* U2_dev, int32_t mode, double* out_dev, void* stream);
+
+/* Human-readable text for a status, and the last error message of a tensor. */
+const char* sbt_status_str(sbt_status s);
+const char* sbt_last_error(const sbt_tensor* t);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SAMBATEN_H */

@@ -1,0 +1,748 @@
+// Tensor state, workspace and the C ABI of the SamBaTen update library.
+//
+// The library keeps, per tensor, on one GPU:
+//   X     the stored tensor (dense column-major, or COO structure of arrays),
+//         sized for k_capacity slices so that appending a batch is one copy;
+//   A,B,C the CP model (row-major FP64) and lambda;
+//   w1..3 the importance of every index of the three modes (exact uint64 sums
+//         of floor(x^2 2^S)), kept incrementally across batches;
+//   t     the batch counter that keys the sampler's random numbers.
+// An update runs entirely on the GPU; the host only enqueues kernels and reads
+// back one status word at the end.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/sambaten.h"
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+using namespace sbt;
+
+struct sbt_tensor {
+  sbt_config cfg{};
+  int64_t I = 0, J = 0, K = 0, Kcap = 0;
+  int R = 0;
+  int fmt = SBT_DENSE;
+  int store_prec = kF32;  // kF64 or kF32
+  int sum_prec = kF32;    // kF64, kF32 or kBF16
+  // stored tensor
+  void* X = nullptr;
+  int32_t *ci = nullptr, *cj = nullptr, *ck = nullptr;
+  float* cv = nullptr;
+  int64_t nnz = 0, nnz_cap = 0;
+  // model and importance
+  double *A = nullptr, *B = nullptr, *C = nullptr, *lam = nullptr;
+  uint64_t *w1 = nullptr, *w2 = nullptr, *w3 = nullptr;
+  int S = 0;
+  double scale = 1.0;
+  uint64_t qmax = 0, nmax = 1;
+  uint32_t t = 0;
+  // update workspace
+  int n1 = 0, n2 = 0, n3max = 0, Kpmax = 0;
+  int64_t idx_stride = 0, key_stride = 0;
+  uint64_t *dw1 = nullptr, *dw2 = nullptr, *dw3 = nullptr, *keys = nullptr, *bits = nullptr;
+  uint32_t *err = nullptr, *pinv = nullptr;
+  int32_t *idx = nullptr, *pi = nullptr, *valid = nullptr;
+  void *Z = nullptr, *W = nullptr;
+  double *Ap = nullptr, *Bp = nullptr, *Cp = nullptr, *GA = nullptr, *GB = nullptr, *GC = nullptr,
+         *Gt = nullptr, *ones = nullptr, *lamp = nullptr, *M = nullptr, *At = nullptr,
+         *Bt = nullptr, *Ct = nullptr, *M3 = nullptr, *nrm = nullptr, *fitv = nullptr;
+  uint32_t* h_err = nullptr;  // pinned
+  std::vector<void*> allocs;
+  // last update, for the inspection calls
+  bool has_last = false;
+  int last_n3old = 0, last_Kp = 0;
+  std::string errmsg;
+};
+
+namespace {
+
+struct Fail {
+  sbt_status st;
+};
+
+void set_err(sbt_tensor* t, const std::string& m) {
+  if (t) t->errmsg = m;
+}
+
+#define SBT_CK(expr)                                                                    \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) {                                                             \
+      set_err(t, std::string(#expr) + ": " + hipGetErrorString(e_));                    \
+      return e_ == hipErrorOutOfMemory ? SBT_E_NOMEM : SBT_E_DEVICE;                    \
+    }                                                                                   \
+  } while (0)
+
+template <typename T>
+sbt_status dalloc(sbt_tensor* t, T** p, size_t count) {
+  if (count == 0) count = 1;
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, count * sizeof(T));
+  if (e != hipSuccess) {
+    set_err(t, std::string("hipMalloc: ") + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? SBT_E_NOMEM : SBT_E_DEVICE;
+  }
+  t->allocs.push_back(q);
+  *p = (T*)q;
+  return SBT_OK;
+}
+
+sbt_status dalloc_bytes(sbt_tensor* t, void** p, size_t bytes) {
+  return dalloc<char>(t, (char**)p, bytes);
+}
+
+#define SBT_TRY(expr)                   \
+  do {                                  \
+    sbt_status s_ = (expr);             \
+    if (s_ != SBT_OK) return s_;        \
+  } while (0)
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+int64_t sample_size(int64_t N, int64_t s) {
+  int64_t n = ceil_div(N, s);
+  if (n < 1) n = 1;
+  if (n > N) n = N;
+  return n;
+}
+
+int bit_length(uint64_t v) {
+  int n = 0;
+  while (v) {
+    ++n;
+    v >>= 1;
+  }
+  return n;
+}
+
+sbt_status validate_config(const sbt_config* c, std::string& why) {
+  if (!c) { why = "null config"; return SBT_E_INVALID; }
+  if (c->rank < 1 || c->rank > kMaxRank) { why = "rank must be in 1..32"; return SBT_E_INVALID; }
+  if (c->repetitions < 1 || c->repetitions > 4096) { why = "repetitions must be in 1..4096"; return SBT_E_INVALID; }
+  if (c->als_iters < 1 || c->init_iters < 0) { why = "bad iteration counts"; return SBT_E_INVALID; }
+  for (int m = 0; m < 3; ++m)
+    if (c->sample_factor[m] < 1) { why = "sample factors must be >= 1"; return SBT_E_INVALID; }
+  if (c->format != SBT_DENSE && c->format != SBT_COO) { why = "bad format"; return SBT_E_INVALID; }
+  if (c->precision < SBT_P_F64 || c->precision > SBT_P_BF16) { why = "bad precision"; return SBT_E_INVALID; }
+  if (c->schedule != SBT_SCHED_BATCHED && c->schedule != SBT_SCHED_PLAIN) { why = "bad schedule"; return SBT_E_INVALID; }
+  if (c->flags != 0) { why = "flags must be 0"; return SBT_E_INVALID; }
+  if (c->max_batch < 1) { why = "max_batch must be >= 1"; return SBT_E_INVALID; }
+  return SBT_OK;
+}
+
+RepSet make_repset(const sbt_tensor* t, int n3, int rep0, int nrep) {
+  RepSet rs;
+  rs.n1 = t->n1;
+  rs.n2 = t->n2;
+  rs.n3 = n3;
+  rs.R = t->R;
+  rs.rep0 = rep0;
+  rs.nrep = nrep;
+  rs.sZ = (int64_t)t->n1 * t->n2 * t->Kpmax;
+  rs.sA = (int64_t)t->n1 * t->R;
+  rs.sB = (int64_t)t->n2 * t->R;
+  rs.sC = (int64_t)t->Kpmax * t->R;
+  rs.sW = (int64_t)t->n1 * t->n2 * t->R;
+  int64_t mx = t->n1 > t->n2 ? t->n1 : t->n2;
+  if (t->Kpmax > mx) mx = t->Kpmax;
+  rs.sM = mx * t->R;
+  rs.sG = (int64_t)t->R * t->R;
+  return rs;
+}
+
+// Common part of init: state buffers, workspace, scale of the importance.
+sbt_status alloc_state(sbt_tensor* t) {
+  const sbt_config& c = t->cfg;
+  const int R = t->R;
+  SBT_TRY(dalloc(t, &t->A, (size_t)t->I * R));
+  SBT_TRY(dalloc(t, &t->B, (size_t)t->J * R));
+  SBT_TRY(dalloc(t, &t->C, (size_t)t->Kcap * R));
+  SBT_TRY(dalloc(t, &t->lam, (size_t)R));
+  SBT_TRY(dalloc(t, &t->w1, (size_t)t->I));
+  SBT_TRY(dalloc(t, &t->w2, (size_t)t->J));
+  SBT_TRY(dalloc(t, &t->w3, (size_t)t->Kcap));
+  t->n1 = (int)sample_size(t->I, c.sample_factor[0]);
+  t->n2 = (int)sample_size(t->J, c.sample_factor[1]);
+  t->n3max = (int)sample_size(t->Kcap, c.sample_factor[2]);
+  t->Kpmax = t->n3max + (int)c.max_batch;
+  const int r = c.repetitions;
+  t->idx_stride = (int64_t)t->n1 + t->n2 + t->n3max;
+  t->key_stride = t->I + t->J + t->Kcap;
+  SBT_TRY(dalloc(t, &t->dw1, (size_t)t->I));
+  SBT_TRY(dalloc(t, &t->dw2, (size_t)t->J));
+  SBT_TRY(dalloc(t, &t->dw3, (size_t)c.max_batch));
+  SBT_TRY(dalloc(t, &t->keys, (size_t)r * t->key_stride));
+  SBT_TRY(dalloc(t, &t->bits, 1));
+  SBT_TRY(dalloc(t, &t->err, 1));
+  SBT_TRY(dalloc(t, &t->pinv, 1));
+  SBT_TRY(dalloc(t, &t->idx, (size_t)r * t->idx_stride));
+  SBT_TRY(dalloc(t, &t->pi, (size_t)r * R));
+  SBT_TRY(dalloc(t, &t->valid, (size_t)r * R));
+  RepSet rs = make_repset(t, t->Kpmax, 0, r);
+  if (t->fmt == SBT_DENSE) {
+    SBT_TRY(dalloc_bytes(t, &t->Z, (size_t)r * rs.sZ * prec_bytes(t->sum_prec)));
+    SBT_TRY(dalloc_bytes(t, &t->W, (size_t)r * rs.sW * acc_bytes(t->sum_prec)));
+  }
+  SBT_TRY(dalloc(t, &t->Ap, (size_t)r * rs.sA));
+  SBT_TRY(dalloc(t, &t->Bp, (size_t)r * rs.sB));
+  SBT_TRY(dalloc(t, &t->Cp, (size_t)r * rs.sC));
+  SBT_TRY(dalloc(t, &t->At, (size_t)r * rs.sA));
+  SBT_TRY(dalloc(t, &t->Bt, (size_t)r * rs.sB));
+  SBT_TRY(dalloc(t, &t->Ct, (size_t)r * rs.sC));
+  SBT_TRY(dalloc(t, &t->M, (size_t)r * rs.sM));
+  SBT_TRY(dalloc(t, &t->GA, (size_t)r * rs.sG));
+  SBT_TRY(dalloc(t, &t->GB, (size_t)r * rs.sG));
+  SBT_TRY(dalloc(t, &t->GC, (size_t)r * rs.sG));
+  SBT_TRY(dalloc(t, &t->Gt, (size_t)r * rs.sG));
+  SBT_TRY(dalloc(t, &t->ones, (size_t)rs.sG));
+  SBT_TRY(dalloc(t, &t->lamp, (size_t)r * R));
+  SBT_TRY(dalloc(t, &t->M3, (size_t)t->Kcap * R));
+  SBT_TRY(dalloc(t, &t->nrm, (size_t)t->Kcap));
+  SBT_TRY(dalloc(t, &t->fitv, 1));
+  void* h = nullptr;
+  hipError_t e = hipHostMalloc(&h, 64, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    set_err(t, "hipHostMalloc failed");
+    return SBT_E_NOMEM;
+  }
+  t->h_err = (uint32_t*)h;
+  return SBT_OK;
+}
+
+// Scale S of the importance from max x^2 of the initial tensor (device bits).
+sbt_status set_scale(sbt_tensor* t, hipStream_t st) {
+  uint64_t b = 0;
+  SBT_CK(hipMemcpyAsync(&b, t->bits, 8, hipMemcpyDeviceToHost, st));
+  SBT_CK(hipStreamSynchronize(st));
+  double mx;
+  std::memcpy(&mx, &b, 8);
+  if (!std::isfinite(mx)) {
+    set_err(t, "initial tensor holds a non-finite value");
+    return SBT_E_NUMERIC;
+  }
+  if (mx > 0.0) {
+    int e2 = 0;
+    std::frexp(mx, &e2);
+    t->S = 58 - e2 - bit_length(t->nmax);
+  } else {
+    t->S = 32;
+  }
+  if (t->S < -1000 || t->S > 1000) {
+    set_err(t, "importance scale out of range");
+    return SBT_E_NUMERIC;
+  }
+  t->scale = std::ldexp(1.0, t->S);
+  t->qmax = (uint64_t)((((unsigned __int128)1) << 63) / t->nmax);
+  return SBT_OK;
+}
+
+// CP-ALS on a set of summaries (or on the whole tensor with nrep = 1).
+sbt_status run_als(sbt_tensor* t, const void* Zp, RepSet rs, double* Ap, double* Bp, double* Cp,
+                   double* GA, double* GB, double* GC, double* lam_out, void* W, double* M,
+                   uint32_t stream, uint32_t t_ctr, int iters, bool plain, hipStream_t st) {
+  const int prec = t->sum_prec;
+  SBT_CK(launch_als_init(rs, t->cfg.seed, t->cfg.tensor_id, stream, t_ctr, Bp, Cp, st));
+  SBT_CK(launch_gram(rs, Bp, rs.sB, rs.n2, GB, st));
+  SBT_CK(launch_gram(rs, Cp, rs.sC, rs.n3, GC, st));
+  for (int it = 0; it < iters; ++it) {
+    // mode 1
+    SBT_CK(launch_p1(prec, rs, Zp, Cp, W, st));
+    SBT_CK(launch_cw1(prec, rs, W, Bp, M, st));
+    SBT_CK(launch_solve(rs, rs.n1, M, GB, rs.sG, GC, rs.sG, Ap, rs.sA, GA, lam_out, nullptr, 1, t->pinv,
+                        st));
+    // mode 2 (the plain schedule re-runs the contraction with C')
+    if (plain) SBT_CK(launch_p1(prec, rs, Zp, Cp, W, st));
+    SBT_CK(launch_cw2(prec, rs, W, Ap, M, st));
+    SBT_CK(launch_solve(rs, rs.n2, M, GA, rs.sG, GC, rs.sG, Bp, rs.sB, GB, lam_out, nullptr, 1, t->pinv,
+                        st));
+    // mode 3
+    SBT_CK(launch_p2(prec, rs, Zp, Ap, Bp, M, st));
+    SBT_CK(launch_solve(rs, rs.n3, M, GA, rs.sG, GB, rs.sG, Cp, rs.sC, GC, lam_out, nullptr, 1, t->pinv,
+                        st));
+  }
+  return SBT_OK;
+}
+
+sbt_status init_common(sbt_tensor* t, const double* A0, const double* B0, const double* C0,
+                       const double* lam0, hipStream_t st) {
+  const int R = t->R;
+  SBT_CK(launch_fill_f64(t->ones, (int64_t)R * R, 1.0, st));
+  SBT_CK(launch_fill_u32(t->pinv, 1, 0, st));
+  if (A0) {
+    SBT_CK(hipMemcpyAsync(t->A, A0, sizeof(double) * t->I * R, hipMemcpyHostToDevice, st));
+    SBT_CK(hipMemcpyAsync(t->B, B0, sizeof(double) * t->J * R, hipMemcpyHostToDevice, st));
+    SBT_CK(hipMemcpyAsync(t->C, C0, sizeof(double) * t->K * R, hipMemcpyHostToDevice, st));
+    SBT_CK(hipMemcpyAsync(t->lam, lam0, sizeof(double) * R, hipMemcpyHostToDevice, st));
+    SBT_CK(hipStreamSynchronize(st));
+    return SBT_OK;
+  }
+  if (t->fmt != SBT_DENSE) {
+    set_err(t, "the initial CP-ALS needs a dense tensor; pass A0, B0, C0, lambda0");
+    return SBT_E_INVALID;
+  }
+  // CP-ALS on the whole initial tensor, then components ordered by lambda.
+  RepSet rs;
+  rs.n1 = (int)t->I;
+  rs.n2 = (int)t->J;
+  rs.n3 = (int)t->K;
+  rs.R = R;
+  rs.rep0 = 0;
+  rs.nrep = 1;
+  rs.sZ = 0;
+  rs.sA = t->I * R;
+  rs.sB = t->J * R;
+  rs.sC = t->K * R;
+  rs.sW = t->I * t->J * R;
+  int64_t mx = t->I > t->J ? t->I : t->J;
+  if (t->K > mx) mx = t->K;
+  rs.sM = mx * R;
+  rs.sG = (int64_t)R * R;
+  void* W = nullptr;
+  double *M = nullptr, *G = nullptr;
+  const size_t wbytes = (size_t)rs.sW * acc_bytes(t->store_prec);
+  SBT_CK(hipMalloc(&W, wbytes));
+  hipError_t e1 = hipMalloc((void**)&M, sizeof(double) * rs.sM);
+  hipError_t e2 = hipMalloc((void**)&G, sizeof(double) * 3 * rs.sG);
+  sbt_status s = SBT_OK;
+  if (e1 != hipSuccess || e2 != hipSuccess) {
+    set_err(t, "hipMalloc failed for the initial CP-ALS workspace");
+    s = SBT_E_NOMEM;
+  } else {
+    const int keep = t->sum_prec;
+    t->sum_prec = t->store_prec;  // the whole tensor is read in its stored precision
+    s = run_als(t, t->X, rs, t->A, t->B, t->C, G, G + rs.sG, G + 2 * rs.sG, t->lam, W, M,
+                kStreamInit, 0u, t->cfg.init_iters, false, st);
+    t->sum_prec = keep;
+    if (s == SBT_OK && t->cfg.init_iters == 0) s = SBT_E_INVALID;
+    if (s == SBT_OK) {
+      hipError_t e = launch_sort_components(t->A, t->B, t->C, t->lam, t->I, t->J, t->K, R, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) {
+        set_err(t, std::string("initial CP-ALS: ") + hipGetErrorString(e));
+        s = SBT_E_DEVICE;
+      }
+    }
+  }
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(W);
+  if (M) (void)hipFree(M);
+  if (G) (void)hipFree(G);
+  return s;
+}
+
+void free_all(sbt_tensor* t) {
+  for (void* p : t->allocs) (void)hipFree(p);
+  t->allocs.clear();
+  if (t->h_err) (void)hipHostFree(t->h_err);
+  t->h_err = nullptr;
+}
+
+sbt_status check_factor_args(const double* A0, const double* B0, const double* C0,
+                             const double* lam0, std::string& why) {
+  const int n = (A0 != nullptr) + (B0 != nullptr) + (C0 != nullptr) + (lam0 != nullptr);
+  if (n != 0 && n != 4) {
+    why = "pass all of A0, B0, C0, lambda0 or none";
+    return SBT_E_INVALID;
+  }
+  return SBT_OK;
+}
+
+// The update after the batch is in the store and its importance is in dw*.
+sbt_status update_body(sbt_tensor* t, int64_t Kn, hipStream_t st) {
+  const sbt_config& c = t->cfg;
+  const int R = t->R, r = c.repetitions;
+  const int64_t Kold = t->K;
+  const int n3old = (int)sample_size(Kold, c.sample_factor[2]);
+  const int Kp = n3old + (int)Kn;
+  // sampling (from the tensor before the update)
+  SampleArgs sa;
+  sa.w[0] = t->w1;
+  sa.w[1] = t->w2;
+  sa.w[2] = t->w3;
+  sa.N[0] = t->I;
+  sa.N[1] = t->J;
+  sa.N[2] = Kold;
+  sa.n[0] = t->n1;
+  sa.n[1] = t->n2;
+  sa.n[2] = n3old;
+  sa.key_off[0] = 0;
+  sa.key_off[1] = t->I;
+  sa.key_off[2] = t->I + t->J;
+  sa.key_stride = t->key_stride;
+  sa.idx_off[0] = 0;
+  sa.idx_off[1] = t->n1;
+  sa.idx_off[2] = (int64_t)t->n1 + t->n2;
+  sa.idx_stride = t->idx_stride;
+  sa.seed = c.seed;
+  sa.tensor_id = c.tensor_id;
+  sa.t = t->t;
+  sa.nrep = r;
+  SBT_CK(launch_sample(sa, t->keys, t->idx, st));
+  const int64_t offJ = t->n1, offK = (int64_t)t->n1 + t->n2;
+  RepSet all = make_repset(t, Kp, 0, r);
+  const bool plain = c.schedule == SBT_SCHED_PLAIN;
+  if (t->fmt == SBT_DENSE) {
+    SBT_CK(launch_gather_dense(t->store_prec, t->sum_prec, t->X, t->I, t->J, t->idx,
+                               t->idx_stride, offJ, offK, n3old, Kold, all, t->Z, st));
+  }
+  const int nchunks = plain ? r : 1;
+  for (int q = 0; q < nchunks; ++q) {
+    RepSet rs = plain ? make_repset(t, Kp, q, 1) : all;
+    SBT_TRY(run_als(t, t->Z, rs, t->Ap, t->Bp, t->Cp, t->GA, t->GB, t->GC, t->lamp, t->W, t->M,
+                    kStreamAlsInit, t->t, c.als_iters, plain, st));
+    MatchArgs ma;
+    ma.A = t->A;
+    ma.B = t->B;
+    ma.C = t->C;
+    ma.idx = t->idx;
+    ma.idx_stride = t->idx_stride;
+    ma.offJ = offJ;
+    ma.offK = offK;
+    ma.n3old = n3old;
+    ma.Ap = t->Ap;
+    ma.Bp = t->Bp;
+    ma.Cp = t->Cp;
+    ma.At = t->At;
+    ma.Bt = t->Bt;
+    ma.Gt = t->Gt;
+    ma.pi = t->pi;
+    ma.valid = t->valid;
+    SBT_CK(launch_match(rs, ma, st));
+    // row least squares: D = Z_(3) (Bt kr At) Gt^-1, C~ = D / lambda
+    SBT_CK(launch_p2(t->sum_prec, rs, t->Z, t->At, t->Bt, t->M, st));
+    // Gt is already the Hadamard product; the second factor is all ones
+    SBT_CK(launch_solve(rs, Kp, t->M, t->Gt, rs.sG, t->ones, 0, t->Ct, rs.sC, nullptr, nullptr, t->lam,
+                        0, t->pinv, st));
+  }
+  CommitArgs ca;
+  ca.err = t->err;
+  ca.A = t->A;
+  ca.B = t->B;
+  ca.C = t->C;
+  ca.I = t->I;
+  ca.J = t->J;
+  ca.Kold = Kold;
+  ca.Knew = Kn;
+  ca.R = R;
+  ca.nrep = r;
+  ca.n1 = t->n1;
+  ca.n2 = t->n2;
+  ca.n3old = n3old;
+  ca.Kp = Kp;
+  ca.idx = t->idx;
+  ca.idx_stride = t->idx_stride;
+  ca.offJ = offJ;
+  ca.offK = offK;
+  ca.At = t->At;
+  ca.Bt = t->Bt;
+  ca.Ct = t->Ct;
+  ca.sA = all.sA;
+  ca.sB = all.sB;
+  ca.sC = all.sC;
+  ca.valid = t->valid;
+  ca.w1 = t->w1;
+  ca.w2 = t->w2;
+  ca.w3 = t->w3;
+  ca.dw1 = t->dw1;
+  ca.dw2 = t->dw2;
+  ca.dw3 = t->dw3;
+  SBT_CK(launch_commit(ca, st));
+  SBT_CK(hipMemcpyAsync(t->h_err, t->err, 4, hipMemcpyDeviceToHost, st));
+  SBT_CK(hipStreamSynchronize(st));
+  if (*t->h_err) {
+    set_err(t, (*t->h_err & 2u) ? "batch coordinate outside the tensor"
+                                : "batch holds a non-finite value or overflows the importance sums");
+    return (*t->h_err & 2u) ? SBT_E_SHAPE : SBT_E_NUMERIC;
+  }
+  t->K = Kold + Kn;
+  t->t += 1;
+  t->has_last = true;
+  t->last_n3old = n3old;
+  t->last_Kp = Kp;
+  return SBT_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* sbt_status_str(sbt_status s) {
+  switch (s) {
+    case SBT_OK: return "ok";
+    case SBT_E_INVALID: return "invalid argument";
+    case SBT_E_SHAPE: return "shape mismatch or capacity exceeded";
+    case SBT_E_NOMEM: return "out of device memory";
+    case SBT_E_DEVICE: return "HIP runtime error";
+    case SBT_E_NUMERIC: return "non-finite input or importance overflow";
+    case SBT_E_STATE: return "invalid state";
+  }
+  return "unknown status";
+}
+
+const char* sbt_last_error(const sbt_tensor* t) { return t ? t->errmsg.c_str() : ""; }
+
+sbt_status sbt_init_dense(const sbt_config* cfg, const void* X0_dev, int64_t I, int64_t J,
+                          int64_t K0, const double* A0, const double* B0, const double* C0,
+                          const double* lambda0, void* stream, sbt_tensor** out) {
+  if (!out) return SBT_E_INVALID;
+  *out = nullptr;
+  std::string why;
+  if (validate_config(cfg, why) != SBT_OK) return SBT_E_INVALID;
+  if (cfg->format != SBT_DENSE || !X0_dev) return SBT_E_INVALID;
+  if (check_factor_args(A0, B0, C0, lambda0, why) != SBT_OK) return SBT_E_INVALID;
+  if (I < 1 || J < 1 || K0 < 1 || I > INT32_MAX || J > INT32_MAX) return SBT_E_SHAPE;
+  if (cfg->k_capacity < K0 + 1) return SBT_E_SHAPE;
+  sbt_tensor* t = new (std::nothrow) sbt_tensor();
+  if (!t) return SBT_E_NOMEM;
+  t->cfg = *cfg;
+  t->I = I;
+  t->J = J;
+  t->K = K0;
+  t->Kcap = cfg->k_capacity;
+  t->R = cfg->rank;
+  t->fmt = SBT_DENSE;
+  t->store_prec = cfg->precision == SBT_P_F64 ? kF64 : kF32;
+  t->sum_prec = cfg->precision == SBT_P_F64 ? kF64 : (cfg->precision == SBT_P_F32 ? kF32 : kBF16);
+  int64_t nm = J * t->Kcap;
+  if (I * t->Kcap > nm) nm = I * t->Kcap;
+  if (I * J > nm) nm = I * J;
+  t->nmax = (uint64_t)nm;
+  hipStream_t st = (hipStream_t)stream;
+  const size_t esz = prec_bytes(t->store_prec);
+  sbt_status s = dalloc_bytes(t, &t->X, (size_t)I * J * t->Kcap * esz);
+  if (s == SBT_OK) s = alloc_state(t);
+  if (s == SBT_OK) {
+    hipError_t e = hipMemcpyAsync(t->X, X0_dev, (size_t)I * J * K0 * esz,
+                                  hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = launch_maxsq_dense(t->store_prec, t->X, I * J * K0, t->bits, st);
+    if (e != hipSuccess) {
+      set_err(t, hipGetErrorString(e));
+      s = SBT_E_DEVICE;
+    }
+  }
+  if (s == SBT_OK) s = set_scale(t, st);
+  if (s == SBT_OK) {
+    hipError_t e = launch_fill_u64(t->w1, I, 0, st);
+    if (e == hipSuccess) e = launch_fill_u64(t->w2, J, 0, st);
+    if (e == hipSuccess) e = launch_fill_u64(t->w3, K0, 0, st);
+    if (e == hipSuccess) e = launch_fill_u32(t->err, 1, 0, st);
+    if (e == hipSuccess)
+      e = launch_moi_dense(t->store_prec, t->X, I, J, K0, t->scale, t->qmax, t->w1, t->w2, t->w3,
+                           t->err, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(t->h_err, t->err, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      set_err(t, hipGetErrorString(e));
+      s = SBT_E_DEVICE;
+    } else if (*t->h_err) {
+      set_err(t, "initial tensor holds a non-finite value or overflows the importance sums");
+      s = SBT_E_NUMERIC;
+    }
+  }
+  if (s == SBT_OK) s = init_common(t, A0, B0, C0, lambda0, st);
+  if (s != SBT_OK) {
+    free_all(t);
+    delete t;
+    return s;
+  }
+  *out = t;
+  return SBT_OK;
+}
+
+sbt_status sbt_init_coo(const sbt_config* cfg, const int32_t* i_dev, const int32_t* j_dev,
+                        const int32_t* k_dev, const float* v_dev, int64_t nnz, int64_t I,
+                        int64_t J, int64_t K0, const double* A0, const double* B0,
+                        const double* C0, const double* lambda0, void* stream,
+                        sbt_tensor** out) {
+  (void)cfg; (void)i_dev; (void)j_dev; (void)k_dev; (void)v_dev; (void)nnz; (void)I; (void)J;
+  (void)K0; (void)A0; (void)B0; (void)C0; (void)lambda0; (void)stream;
+  if (out) *out = nullptr;
+  return SBT_E_STATE;
+}
+
+void sbt_destroy(sbt_tensor* t) {
+  if (!t) return;
+  (void)hipDeviceSynchronize();
+  free_all(t);
+  delete t;
+}
+
+sbt_status sbt_update_batch_dense(sbt_tensor* t, const void* Y_dev, int64_t K_new, void* stream) {
+  if (!t || !Y_dev) return SBT_E_INVALID;
+  if (t->fmt != SBT_DENSE) {
+    set_err(t, "tensor is not dense");
+    return SBT_E_STATE;
+  }
+  if (K_new < 1 || K_new > t->cfg.max_batch || t->K + K_new > t->Kcap) {
+    set_err(t, "batch size outside 1..max_batch or capacity exceeded");
+    return SBT_E_SHAPE;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const size_t esz = prec_bytes(t->store_prec);
+  const size_t slice = (size_t)t->I * t->J;
+  void* dst = (char*)t->X + (size_t)t->K * slice * esz;
+  // ingest: append the batch behind the stored slices (not yet part of the tensor)
+  SBT_CK(hipMemcpyAsync(dst, Y_dev, slice * K_new * esz, hipMemcpyDeviceToDevice, st));
+  SBT_CK(launch_fill_u64(t->dw1, t->I, 0, st));
+  SBT_CK(launch_fill_u64(t->dw2, t->J, 0, st));
+  SBT_CK(launch_fill_u64(t->dw3, K_new, 0, st));
+  SBT_CK(launch_fill_u32(t->err, 1, 0, st));
+  SBT_CK(launch_moi_dense(t->store_prec, dst, t->I, t->J, K_new, t->scale, t->qmax, t->dw1,
+                          t->dw2, t->dw3, t->err, st));
+  return update_body(t, K_new, st);
+}
+
+sbt_status sbt_update_batch_coo(sbt_tensor* t, const int32_t* i_dev, const int32_t* j_dev,
+                                const int32_t* k_dev, const float* v_dev, int64_t nnz,
+                                int64_t K_new, void* stream) {
+  (void)i_dev; (void)j_dev; (void)k_dev; (void)v_dev; (void)nnz; (void)K_new; (void)stream;
+  if (!t) return SBT_E_INVALID;
+  set_err(t, "tensor is not COO");
+  return SBT_E_STATE;
+}
+
+sbt_status sbt_get_shape(const sbt_tensor* t, int64_t* I, int64_t* J, int64_t* K, int32_t* R) {
+  if (!t) return SBT_E_INVALID;
+  if (I) *I = t->I;
+  if (J) *J = t->J;
+  if (K) *K = t->K;
+  if (R) *R = t->R;
+  return SBT_OK;
+}
+
+sbt_status sbt_get_batch_counter(const sbt_tensor* t, uint32_t* counter) {
+  if (!t || !counter) return SBT_E_INVALID;
+  *counter = t->t;
+  return SBT_OK;
+}
+
+sbt_status sbt_get_factors(sbt_tensor* t, double* A, double* B, double* C, double* lambda,
+                           void* stream) {
+  if (!t) return SBT_E_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  const int R = t->R;
+  if (A) SBT_CK(hipMemcpyAsync(A, t->A, sizeof(double) * t->I * R, hipMemcpyDeviceToHost, st));
+  if (B) SBT_CK(hipMemcpyAsync(B, t->B, sizeof(double) * t->J * R, hipMemcpyDeviceToHost, st));
+  if (C) SBT_CK(hipMemcpyAsync(C, t->C, sizeof(double) * t->K * R, hipMemcpyDeviceToHost, st));
+  if (lambda) SBT_CK(hipMemcpyAsync(lambda, t->lam, sizeof(double) * R, hipMemcpyDeviceToHost, st));
+  SBT_CK(hipStreamSynchronize(st));
+  return SBT_OK;
+}
+
+sbt_status sbt_fit(sbt_tensor* t, double* fit, void* stream) {
+  if (!t || !fit) return SBT_E_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  if (t->fmt == SBT_DENSE) {
+    SBT_CK(launch_fit_slices(t->store_prec, t->X, t->I, t->J, t->K, t->R, t->A, t->B, t->M3,
+                             t->nrm, st));
+  } else {
+    return SBT_E_STATE;
+  }
+  SBT_CK(launch_fit_final(t->A, t->B, t->C, t->lam, t->M3, t->nrm, t->I, t->J, t->K, t->R,
+                          t->fitv, st));
+  SBT_CK(hipMemcpyAsync(fit, t->fitv, sizeof(double), hipMemcpyDeviceToHost, st));
+  SBT_CK(hipStreamSynchronize(st));
+  return SBT_OK;
+}
+
+sbt_status sbt_last_sample(const sbt_tensor* tc, int32_t rep, int32_t mode, int32_t* idx,
+                           int64_t* n) {
+  sbt_tensor* t = const_cast<sbt_tensor*>(tc);
+  if (!t || !idx || !n || mode < 0 || mode > 2) return SBT_E_INVALID;
+  if (!t->has_last) return SBT_E_STATE;
+  if (rep < 0 || rep >= t->cfg.repetitions) return SBT_E_INVALID;
+  const int64_t cnt = mode == 0 ? t->n1 : (mode == 1 ? t->n2 : t->last_n3old);
+  const int64_t off = mode == 0 ? 0 : (mode == 1 ? t->n1 : (int64_t)t->n1 + t->n2);
+  SBT_CK(hipMemcpy(idx, t->idx + rep * t->idx_stride + off, sizeof(int32_t) * cnt,
+                   hipMemcpyDeviceToHost));
+  *n = cnt;
+  return SBT_OK;
+}
+
+sbt_status sbt_last_rep(const sbt_tensor* tc, int32_t rep, int32_t item, double* out,
+                        int64_t cap, int64_t* rows) {
+  sbt_tensor* t = const_cast<sbt_tensor*>(tc);
+  if (!t || !out || !rows) return SBT_E_INVALID;
+  if (!t->has_last) return SBT_E_STATE;
+  if (rep < 0 || rep >= t->cfg.repetitions) return SBT_E_INVALID;
+  const int R = t->R;
+  RepSet rs = make_repset(t, t->last_Kp, 0, t->cfg.repetitions);
+  const double* src = nullptr;
+  int64_t nr = 0, ncol = R;
+  const int32_t* isrc = nullptr;
+  switch (item) {
+    case SBT_REP_AP: src = t->Ap + rep * rs.sA; nr = t->n1; break;
+    case SBT_REP_BP: src = t->Bp + rep * rs.sB; nr = t->n2; break;
+    case SBT_REP_CP: src = t->Cp + rep * rs.sC; nr = t->last_Kp; break;
+    case SBT_REP_LAMP: src = t->lamp + rep * R; nr = 1; break;
+    case SBT_REP_PI: isrc = t->pi + rep * R; nr = 1; break;
+    case SBT_REP_VALID: isrc = t->valid + rep * R; nr = 1; break;
+    case SBT_REP_AT: src = t->At + rep * rs.sA; nr = t->n1; break;
+    case SBT_REP_BT: src = t->Bt + rep * rs.sB; nr = t->n2; break;
+    case SBT_REP_CT: src = t->Ct + rep * rs.sC; nr = t->last_Kp; break;
+    default: return SBT_E_INVALID;
+  }
+  if (cap < nr * ncol) return SBT_E_INVALID;
+  if (src) {
+    SBT_CK(hipMemcpy(out, src, sizeof(double) * nr * ncol, hipMemcpyDeviceToHost));
+  } else {
+    std::vector<int32_t> tmp((size_t)ncol);
+    SBT_CK(hipMemcpy(tmp.data(), isrc, sizeof(int32_t) * ncol, hipMemcpyDeviceToHost));
+    for (int64_t q = 0; q < ncol; ++q) out[q] = (double)tmp[(size_t)q];
+  }
+  *rows = nr;
+  return SBT_OK;
+}
+
+sbt_status sbt_mttkrp_dense(int32_t precision, const void* Z_dev, int64_t n1, int64_t n2,
+                            int64_t n3, int32_t R, const double* U0_dev, const double* U1_dev,
+                            const double* U2_dev, int32_t mode, double* out_dev, void* stream) {
+  sbt_tensor* t = nullptr;  // for SBT_CK: no tensor to record the message on
+  if (!Z_dev || !out_dev || R < 1 || R > kMaxRank || n1 < 1 || n2 < 1 || n3 < 1 || mode < 0 ||
+      mode > 2 || precision < SBT_P_F64 || precision > SBT_P_BF16)
+    return SBT_E_INVALID;
+  if (n1 > INT32_MAX || n2 > INT32_MAX || n3 > INT32_MAX) return SBT_E_SHAPE;
+  const int prec = precision == SBT_P_F64 ? kF64 : (precision == SBT_P_F32 ? kF32 : kBF16);
+  hipStream_t st = (hipStream_t)stream;
+  RepSet rs;
+  rs.n1 = (int)n1;
+  rs.n2 = (int)n2;
+  rs.n3 = (int)n3;
+  rs.R = R;
+  rs.rep0 = 0;
+  rs.nrep = 1;
+  rs.sZ = n1 * n2 * n3;
+  rs.sA = n1 * R;
+  rs.sB = n2 * R;
+  rs.sC = n3 * R;
+  rs.sW = n1 * n2 * R;
+  rs.sM = 0;
+  rs.sG = (int64_t)R * R;
+  if (mode == 2) {
+    if (!U0_dev || !U1_dev) return SBT_E_INVALID;
+    SBT_CK(launch_p2(prec, rs, Z_dev, U0_dev, U1_dev, out_dev, st));
+    return SBT_OK;
+  }
+  if (!U2_dev || (mode == 0 && !U1_dev) || (mode == 1 && !U0_dev)) return SBT_E_INVALID;
+  void* W = nullptr;
+  SBT_CK(hipMallocAsync(&W, (size_t)rs.sW * acc_bytes(prec), st));
+  SBT_CK(launch_p1(prec, rs, Z_dev, U2_dev, W, st));
+  if (mode == 0)
+    SBT_CK(launch_cw1(prec, rs, W, U1_dev, out_dev, st));
+  else
+    SBT_CK(launch_cw2(prec, rs, W, U0_dev, out_dev, st));
+  SBT_CK(hipFreeAsync(W, st));
+  return SBT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,408 @@
+// Normalise + match (Sec. 3.1 "Project back", Lemma 1), the zero-entry fill,
+// the average of the new rows over the repetitions, the append of C and the
+// importance commit (Algorithm 1), and the fit of Sec. 4.2.
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace sbt {
+
+namespace {
+
+constexpr double kInf = 1e300;
+
+__device__ inline void pair_fg2(int p, int R, int& f, int& g) {
+  f = 0;
+  while (p >= R - f) {
+    p -= R - f;
+    ++f;
+  }
+  g = f + p;
+}
+
+// G = U^T U, one block.
+__device__ void block_gram2(const double* U, int rows, int R, double* G, double* red) {
+  const int P = R * (R + 1) / 2;
+  const int tid = threadIdx.x;
+  if (P >= 256) {
+    for (int p = tid; p < P; p += 256) {
+      int f, g;
+      pair_fg2(p, R, f, g);
+      double acc = 0.0;
+      for (int i = 0; i < rows; ++i) acc += U[(int64_t)i * R + f] * U[(int64_t)i * R + g];
+      G[f * kMaxRank + g] = acc;
+      G[g * kMaxRank + f] = acc;
+    }
+    __syncthreads();
+    return;
+  }
+  const int nsl = 256 / P;
+  const int pl = tid % P, sl = tid / P;
+  double acc = 0.0;
+  if (sl < nsl) {
+    int f, g;
+    pair_fg2(pl, R, f, g);
+    for (int i = sl; i < rows; i += nsl) acc += U[(int64_t)i * R + f] * U[(int64_t)i * R + g];
+  }
+  red[tid] = acc;
+  __syncthreads();
+  if (tid < P) {
+    double s = 0.0;
+    for (int q = 0; q < nsl; ++q) s += red[q * P + tid];
+    int f, g;
+    pair_fg2(tid, R, f, g);
+    G[f * kMaxRank + g] = s;
+    G[g * kMaxRank + f] = s;
+  }
+  __syncthreads();
+}
+
+// Maximum-weight perfect assignment on S (R x R, R <= 32) by the Hungarian
+// method with potentials, run by one wavefront: lane j owns column j
+// (column 0 is the virtual start column), lane r owns the potential of row r.
+// Ties in the minimum slack go to the smallest column.  Output: pi[f] =
+// column assigned to row f (0-based).
+__device__ void hungarian_wave(const double (*S)[kMaxRank + 1], int R, int* pi) {
+  const int lane = lane_id();
+  double u = 0.0;            // potential of row `lane` (rows 1..R)
+  double v = 0.0;            // potential of column `lane` (0..R)
+  int p = 0;                 // row assigned to column `lane` (0 = none)
+  int way = 0;
+  for (int i = 1; i <= R; ++i) {
+    if (lane == 0) p = i;
+    int j0 = 0;
+    double minv = kInf;
+    bool used = false;
+    bool in_tree = false;  // row `lane` reached in this phase
+    // every step marks one more column used, so a phase takes at most R steps
+    for (int step = 0; step <= R; ++step) {
+      if (lane == j0) used = true;
+      const int i0 = __shfl(p, j0, kWave);
+      if (lane == i0) in_tree = true;
+      const double ui0 = __shfl(u, i0, kWave);
+      const bool elig = lane >= 1 && lane <= R && !used;
+      double cand = kInf;
+      int cj = kWave + lane;  // ineligible lanes never win a tie
+      if (elig) {
+        const double cur = -S[i0 - 1][lane - 1] - ui0 - v;
+        if (cur < minv) {
+          minv = cur;
+          way = j0;
+        }
+        cand = minv;
+        cj = lane;
+      }
+      // wave argmin of (cand, cj), ties to the smaller column
+      double bv = cand;
+      int bj = cj;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(bv, off, kWave);
+        const int oj = __shfl_xor(bj, off, kWave);
+        if (ov < bv || (ov == bv && oj < bj)) {
+          bv = ov;
+          bj = oj;
+        }
+      }
+      if (bj >= kWave) break;  // no eligible column: cannot happen for finite S
+      const double delta = bv;
+      if (lane <= R) {
+        if (used)
+          v -= delta;
+        else if (lane >= 1)
+          minv -= delta;
+      }
+      if (in_tree && lane >= 1 && lane <= R) u += delta;
+      j0 = bj;
+      if (__shfl(p, j0, kWave) == 0) break;
+    }
+    // augment along the alternating path back to the virtual column
+    for (int step = 0; step <= R && j0 != 0; ++step) {
+      const int j1 = __shfl(way, j0, kWave);
+      const int pj1 = __shfl(p, j1, kWave);
+      if (lane == j0) p = pj1;
+      j0 = j1;
+    }
+  }
+  if (lane >= 1 && lane <= R && p >= 1 && p <= R) pi[p - 1] = lane - 1;
+}
+
+__global__ __launch_bounds__(256) void match_kernel(RepSet rs, MatchArgs m) {
+  const int rep = rs.rep0 + blockIdx.x;
+  const int R = rs.R, n1 = rs.n1, n2 = rs.n2, n3 = m.n3old;
+  const int tid = threadIdx.x;
+  const int32_t* Is = m.idx + rep * m.idx_stride;
+  const int32_t* Js = Is + m.offJ;
+  const int32_t* Ks = Is + m.offK;
+  const double* Ap = m.Ap + rep * rs.sA;
+  const double* Bp = m.Bp + rep * rs.sB;
+  const double* Cp = m.Cp + rep * rs.sC;
+  __shared__ double PA[kMaxRank][kMaxRank + 1], PB[kMaxRank][kMaxRank + 1];
+  __shared__ double PC[kMaxRank][kMaxRank + 1];
+  __shared__ double S[kMaxRank][kMaxRank + 1];
+  __shared__ double nrm[6][kMaxRank];  // A anchor, B anchor, C anchor, A', B', C'(anchor rows)
+  __shared__ int pi_s[kMaxRank];
+  __shared__ double sigA[kMaxRank], sigB[kMaxRank];
+  __shared__ double red[256];
+  __shared__ double GA[kMaxRank * kMaxRank], GB[kMaxRank * kMaxRank];
+
+  // cross products and squared norms
+  const int nitem = 3 * R * R + 6 * R;
+  for (int q = tid; q < nitem; q += 256) {
+    double acc = 0.0;
+    if (q < 3 * R * R) {
+      const int which = q / (R * R), fg = q % (R * R), f = fg / R, g = fg % R;
+      if (which == 0) {
+        for (int a = 0; a < n1; ++a) acc += m.A[(int64_t)Is[a] * R + f] * Ap[(int64_t)a * R + g];
+        PA[f][g] = acc;
+      } else if (which == 1) {
+        for (int b = 0; b < n2; ++b) acc += m.B[(int64_t)Js[b] * R + f] * Bp[(int64_t)b * R + g];
+        PB[f][g] = acc;
+      } else {
+        for (int c = 0; c < n3; ++c) acc += m.C[(int64_t)Ks[c] * R + f] * Cp[(int64_t)c * R + g];
+        PC[f][g] = acc;
+      }
+    } else {
+      const int qq = q - 3 * R * R, which = qq / R, f = qq % R;
+      switch (which) {
+        case 0: for (int a = 0; a < n1; ++a) { const double x = m.A[(int64_t)Is[a] * R + f]; acc += x * x; } break;
+        case 1: for (int b = 0; b < n2; ++b) { const double x = m.B[(int64_t)Js[b] * R + f]; acc += x * x; } break;
+        case 2: for (int c = 0; c < n3; ++c) { const double x = m.C[(int64_t)Ks[c] * R + f]; acc += x * x; } break;
+        case 3: for (int a = 0; a < n1; ++a) { const double x = Ap[(int64_t)a * R + f]; acc += x * x; } break;
+        case 4: for (int b = 0; b < n2; ++b) { const double x = Bp[(int64_t)b * R + f]; acc += x * x; } break;
+        default: for (int c = 0; c < n3; ++c) { const double x = Cp[(int64_t)c * R + f]; acc += x * x; } break;
+      }
+      nrm[which][f] = sqrt(acc);
+    }
+  }
+  __syncthreads();
+  // similarity: product over the modes of |cosine|
+  for (int q = tid; q < R * R; q += 256) {
+    const int f = q / R, g = q % R;
+    const double dA = nrm[0][f] * nrm[3][g], dB = nrm[1][f] * nrm[4][g],
+                 dC = nrm[2][f] * nrm[5][g];
+    const double cA = dA > 0.0 ? PA[f][g] / dA : 0.0;
+    const double cB = dB > 0.0 ? PB[f][g] / dB : 0.0;
+    const double cC = dC > 0.0 ? PC[f][g] / dC : 0.0;
+    const double sv = fabs(cA) * fabs(cB) * fabs(cC);
+    S[f][g] = sv >= 0.0 ? sv : 0.0;  // a non-finite similarity counts as none
+  }
+  __syncthreads();
+  if (tid < R) pi_s[tid] = tid;
+  __syncthreads();
+  if (tid < kWave) hungarian_wave(S, R, pi_s);
+  __syncthreads();
+  if (tid < R) {
+    const int f = tid, g = pi_s[f];
+    sigA[f] = PA[f][g] < 0.0 ? -1.0 : 1.0;
+    sigB[f] = PB[f][g] < 0.0 ? -1.0 : 1.0;
+    m.pi[rep * R + f] = g;
+    m.valid[rep * R + f] = (nrm[0][f] > 0.0 && nrm[1][f] > 0.0) ? 1 : 0;
+  }
+  __syncthreads();
+  // matched sample columns, unit-normalised, in the units of A(I_s), B(J_s)
+  double* At = m.At + rep * rs.sA;
+  double* Bt = m.Bt + rep * rs.sB;
+  for (int64_t q = tid; q < (int64_t)n1 * R; q += 256) {
+    const int a = (int)(q / R), f = (int)(q % R), g = pi_s[f];
+    const double na = nrm[3][g];
+    At[q] = na > 0.0 ? sigA[f] * nrm[0][f] * (Ap[(int64_t)a * R + g] / na) : 0.0;
+  }
+  for (int64_t q = tid; q < (int64_t)n2 * R; q += 256) {
+    const int b = (int)(q / R), f = (int)(q % R), g = pi_s[f];
+    const double nb = nrm[4][g];
+    Bt[q] = nb > 0.0 ? sigB[f] * nrm[1][f] * (Bp[(int64_t)b * R + g] / nb) : 0.0;
+  }
+  __syncthreads();
+  block_gram2(At, n1, R, GA, red);
+  block_gram2(Bt, n2, R, GB, red);
+  for (int q = tid; q < R * R; q += 256) {
+    const int f = q / R, g = q % R;
+    m.Gt[rep * rs.sG + q] = GA[f * kMaxRank + g] * GB[f * kMaxRank + g];
+  }
+}
+
+// position of v in the ascending list s[0..n), or -1
+__device__ inline int find_sorted(const int32_t* s, int n, int64_t v) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if ((int64_t)s[mid] < v)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return (lo < n && (int64_t)s[lo] == v) ? lo : -1;
+}
+
+__global__ __launch_bounds__(256) void commit_kernel(CommitArgs c) {
+  if (*c.err) return;
+  const int R = c.R;
+  const int64_t nA = c.I * R, nB = c.J * R, nCo = c.Kold * R, nCn = c.Knew * R;
+  const int64_t total = nA + nB + nCo + nCn + c.I + c.J + c.Knew;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < total;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    int64_t r = q;
+    if (r < nA + nB + nCo) {
+      // zero-entry fill: mean over the valid repetitions whose sample covers the row
+      double* target;
+      const double* src;
+      int64_t srow, sstride, off;
+      int nsamp;
+      int f;
+      if (r < nA) {
+        target = c.A; src = c.At; sstride = c.sA; off = 0; nsamp = c.n1;
+        srow = r / R; f = (int)(r % R);
+      } else if (r < nA + nB) {
+        r -= nA;
+        target = c.B; src = c.Bt; sstride = c.sB; off = c.offJ; nsamp = c.n2;
+        srow = r / R; f = (int)(r % R);
+      } else {
+        r -= nA + nB;
+        target = c.C; src = c.Ct; sstride = c.sC; off = c.offK; nsamp = c.n3old;
+        srow = r / R; f = (int)(r % R);
+      }
+      if (target[srow * R + f] != 0.0) continue;
+      double acc = 0.0;
+      int cnt = 0;
+      for (int rep = 0; rep < c.nrep; ++rep) {
+        if (!c.valid[rep * R + f]) continue;
+        const int p = find_sorted(c.idx + rep * c.idx_stride + off, nsamp, srow);
+        if (p < 0) continue;
+        acc = acc + src[rep * sstride + (int64_t)p * R + f];
+        ++cnt;
+      }
+      if (cnt) target[srow * R + f] = acc / (double)cnt;
+      continue;
+    }
+    r -= nA + nB + nCo;
+    if (r < nCn) {
+      const int64_t k = r / R;
+      const int f = (int)(r % R);
+      double acc = 0.0;
+      int cnt = 0;
+      for (int rep = 0; rep < c.nrep; ++rep) {
+        if (!c.valid[rep * R + f]) continue;
+        acc = acc + c.Ct[rep * c.sC + (int64_t)(c.n3old + k) * R + f];
+        ++cnt;
+      }
+      c.C[(c.Kold + k) * R + f] = cnt ? acc / (double)cnt : 0.0;
+      continue;
+    }
+    r -= nCn;
+    if (r < c.I) {
+      c.w1[r] += c.dw1[r];
+      continue;
+    }
+    r -= c.I;
+    if (r < c.J) {
+      c.w2[r] += c.dw2[r];
+      continue;
+    }
+    r -= c.J;
+    c.w3[c.Kold + r] = c.dw3[r];
+  }
+}
+
+__global__ __launch_bounds__(256) void fit_final_kernel(const double* A, const double* B,
+                                                       const double* C, const double* lam,
+                                                       const double* M3, const double* nrm,
+                                                       int64_t I, int64_t J, int64_t K, int R,
+                                                       double* fit) {
+  __shared__ double GA[kMaxRank * kMaxRank], GB[kMaxRank * kMaxRank], GC[kMaxRank * kMaxRank];
+  __shared__ double red[256];
+  block_gram2(A, (int)I, R, GA, red);
+  block_gram2(B, (int)J, R, GB, red);
+  block_gram2(C, (int)K, R, GC, red);
+  // <X, Xhat> and ||X||^2
+  double inner = 0.0, nx = 0.0;
+  for (int64_t q = threadIdx.x; q < K * R; q += 256) inner += lam[q % R] * C[q] * M3[q];
+  for (int64_t k = threadIdx.x; k < K; k += 256) nx += nrm[k];
+  red[threadIdx.x] = inner;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  const double inner_t = red[0];
+  __syncthreads();
+  red[threadIdx.x] = nx;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  const double nx_t = red[0];
+  if (threadIdx.x == 0) {
+    double xh = 0.0;
+    for (int f = 0; f < R; ++f)
+      for (int g = 0; g < R; ++g)
+        xh += lam[f] * lam[g] * GA[f * kMaxRank + g] * GB[f * kMaxRank + g] *
+              GC[f * kMaxRank + g];
+    double res2 = nx_t - 2.0 * inner_t + xh;
+    if (res2 < 0.0) res2 = 0.0;
+    *fit = 1.0 - sqrt(res2) / sqrt(nx_t);
+  }
+}
+
+__global__ __launch_bounds__(256) void sort_components_kernel(double* A, double* B, double* C,
+                                                             double* lam, int64_t I, int64_t J,
+                                                             int64_t K, int R) {
+  __shared__ int perm[kMaxRank];
+  __shared__ double lam_s[kMaxRank];
+  if (threadIdx.x == 0) {
+    for (int f = 0; f < R; ++f) {
+      perm[f] = f;
+      lam_s[f] = lam[f];
+    }
+    // stable insertion sort, largest lambda first
+    for (int a = 1; a < R; ++a) {
+      const int pa = perm[a];
+      int b = a;
+      while (b > 0 && lam_s[perm[b - 1]] < lam_s[pa]) {
+        perm[b] = perm[b - 1];
+        --b;
+      }
+      perm[b] = pa;
+    }
+  }
+  __syncthreads();
+  double row[kMaxRank];
+  for (int64_t r = threadIdx.x; r < I + J + K; r += 256) {
+    double* M = r < I ? A + r * R : (r < I + J ? B + (r - I) * R : C + (r - I - J) * R);
+    for (int f = 0; f < R; ++f) row[f] = M[f];
+    for (int f = 0; f < R; ++f) M[f] = row[perm[f]];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int f = 0; f < R; ++f) lam[f] = lam_s[perm[f]];
+}
+
+}  // namespace
+
+hipError_t launch_match(const RepSet& rs, const MatchArgs& m, hipStream_t s) {
+  match_kernel<<<rs.nrep, 256, 0, s>>>(rs, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_commit(const CommitArgs& c, hipStream_t s) {
+  const int64_t total = (c.I + c.J + c.Kold + c.Knew) * c.R + c.I + c.J + c.Knew;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  commit_kernel<<<(unsigned)blocks, 256, 0, s>>>(c);
+  return hipGetLastError();
+}
+
+hipError_t launch_fit_final(const double* A, const double* B, const double* C, const double* lam,
+                            const double* M3, const double* nrm, int64_t I, int64_t J, int64_t K,
+                            int R, double* fit, hipStream_t s) {
+  fit_final_kernel<<<1, 256, 0, s>>>(A, B, C, lam, M3, nrm, I, J, K, R, fit);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort_components(double* A, double* B, double* C, double* lam, int64_t I,
+                                  int64_t J, int64_t K, int R, hipStream_t s) {
+  sort_components_kernel<<<1, 256, 0, s>>>(A, B, C, lam, I, J, K, R);
+  return hipGetLastError();
+}
+
+}  // namespace sbt

@@ -1,0 +1,329 @@
+// Measure of importance (Eq. 1) in exact integer form, and weighted sampling
+// without replacement of the indices of every mode (Sec. 3.1, Algorithm 1).
+//
+// Importance: q(x) = floor(x*x * 2^S) summed in uint64 per index of each mode.
+// Integer sums are associative, so the per-index totals do not depend on the
+// order the atomics land in: every run and every launch shape gives the same
+// weights, which the sampler needs to be reproducible bit for bit.
+//
+// Sampling: successive sampling proportional to the weights, realised with
+// exponential keys kappa_i = E_i / w_i (E_i = -ln U_i, U_i from Philox); the
+// n smallest keys win, ties to the smaller index.  One workgroup per
+// (repetition, mode) computes the keys, finds the n-th smallest by an 8-bit
+// radix select over the 64-bit key patterns (non-negative doubles order like
+// their bit patterns), then writes the winners in index order, which leaves
+// them sorted ascending.
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace sbt {
+
+namespace {
+
+__global__ void fill_u64_kernel(uint64_t* p, int64_t n, uint64_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void fill_f64_kernel(double* p, int64_t n, double v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+inline int fill_blocks(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  return (int)(b < 1 ? 1 : (b > 4096 ? 4096 : b));
+}
+
+__device__ inline double as_f64(double x) { return x; }
+__device__ inline double as_f64(float x) { return (double)x; }
+
+template <typename T>
+__global__ __launch_bounds__(256) void maxsq_kernel(const T* X, int64_t n, uint64_t* out) {
+  uint64_t best = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double x = as_f64(X[i]);
+    const double x2 = x * x;
+    const uint64_t b = (uint64_t)__double_as_longlong(x2) & 0x7FFFFFFFFFFFFFFFull;
+    best = b > best ? b : best;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const uint64_t o = __shfl_xor(best, off, kWave);
+    best = o > best ? o : best;
+  }
+  if (lane_id() == 0) atomicMax((unsigned long long*)out, (unsigned long long)best);
+}
+
+// q(x) = floor(x*x * scale); flags a non-finite x or q > qmax.
+__device__ inline uint64_t quantize_sq(double x, double scale, uint64_t qmax, bool& bad) {
+  const double x2s = (x * x) * scale;
+  if (!(x2s < 0x1p63)) {
+    bad = true;
+    return 0;
+  }
+  const uint64_t q = (uint64_t)x2s;
+  if (q > qmax) bad = true;
+  return q;
+}
+
+constexpr int kMoiJChunk = 64;
+
+// Block: 64 consecutive i (one per lane) x kMoiJChunk j's of one slice k; each
+// of the 4 waves takes every 4th j.  Per-i sums meet in LDS, per-j sums are
+// wave reductions, the slice sum is a block reduction; each lands with one
+// 64-bit atomic.
+template <typename T>
+__global__ __launch_bounds__(256) void moi_dense_kernel(const T* Y, int64_t I, int64_t J,
+                                                       double scale, uint64_t qmax,
+                                                       uint64_t* w1, uint64_t* w2,
+                                                       uint64_t* w3, uint32_t* err) {
+  const int lane = lane_id();
+  const int wave = threadIdx.x >> 6;
+  const int64_t i = (int64_t)blockIdx.x * kWave + lane;
+  const int64_t j0 = (int64_t)blockIdx.y * kMoiJChunk;
+  const int64_t k = blockIdx.z;
+  const int64_t jend = j0 + kMoiJChunk < J ? j0 + kMoiJChunk : J;
+  uint64_t acc_i = 0, acc_k = 0;
+  bool bad = false;
+  for (int64_t j = j0 + wave; j < jend; j += 4) {
+    uint64_t q = 0;
+    if (i < I) q = quantize_sq(as_f64(Y[i + I * (j + J * k)]), scale, qmax, bad);
+    acc_i += q;
+    acc_k += q;
+    const uint64_t qj = wave_sum_u64(q);
+    if (lane == 0 && qj) atomicAdd((unsigned long long*)&w2[j], (unsigned long long)qj);
+  }
+  __shared__ uint64_t part_i[4][kWave];
+  __shared__ uint64_t part_k[4];
+  part_i[wave][lane] = acc_i;
+  const uint64_t sk = wave_sum_u64(acc_k);
+  if (lane == 0) part_k[wave] = sk;
+  if (bad) atomicOr(err, 1u);
+  __syncthreads();
+  if (wave == 0) {
+    const uint64_t s = part_i[0][lane] + part_i[1][lane] + part_i[2][lane] + part_i[3][lane];
+    if (i < I && s) atomicAdd((unsigned long long*)&w1[i], (unsigned long long)s);
+    if (lane == 0) {
+      const uint64_t t = part_k[0] + part_k[1] + part_k[2] + part_k[3];
+      if (t) atomicAdd((unsigned long long*)&w3[k], (unsigned long long)t);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void moi_coo_kernel(const int32_t* ii, const int32_t* jj,
+                                                     const int32_t* kk, const float* v,
+                                                     int64_t nnz, int64_t I, int64_t J,
+                                                     int64_t K, double scale, uint64_t qmax,
+                                                     uint64_t* w1, uint64_t* w2, uint64_t* w3,
+                                                     uint32_t* err) {
+  bool bad = false, oob = false;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t i = ii[e], j = jj[e], k = kk[e];
+    if (i < 0 || i >= I || j < 0 || j >= J || k < 0 || k >= K) {
+      oob = true;
+      continue;
+    }
+    const uint64_t q = quantize_sq((double)v[e], scale, qmax, bad);
+    if (q) {
+      atomicAdd((unsigned long long*)&w1[i], (unsigned long long)q);
+      atomicAdd((unsigned long long*)&w2[j], (unsigned long long)q);
+      atomicAdd((unsigned long long*)&w3[k], (unsigned long long)q);
+    }
+  }
+  if (bad) atomicOr(err, 1u);
+  if (oob) atomicOr(err, 2u);
+}
+
+// ---------------------------------------------------------------------------
+// Sampler
+// ---------------------------------------------------------------------------
+constexpr int kSampleThreads = 1024;
+
+__device__ inline uint64_t lanemask_lt() {
+  const int l = lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+__global__ __launch_bounds__(kSampleThreads) void sample_kernel(SampleArgs a, uint64_t* keys_all,
+                                                               int32_t* idx_all) {
+  const int rep = blockIdx.x;
+  const int m = blockIdx.y;
+  const int tid = threadIdx.x;
+  const int64_t N = a.N[m];
+  const int64_t n = a.n[m] < N ? a.n[m] : N;
+  const uint64_t* w = a.w[m];
+  uint64_t* keys = keys_all + rep * a.key_stride + a.key_off[m];
+  int32_t* out = idx_all + rep * a.idx_stride + a.idx_off[m];
+  const RngKey key = rng_key(a.seed, a.tensor_id);
+  const uint32_t tag = rng_tag(kStreamSample, (uint32_t)(m + 1), (uint32_t)rep);
+
+  // 1. keys kappa_i = -ln(U_i) / double(w_i), +inf for w_i == 0
+  for (int64_t i = tid; i < N; i += kSampleThreads) {
+    const uint64_t u = rng_bits(key, (uint32_t)i, 0u, tag, a.t);
+    const double E = -ln_basic(uniform_open(u));
+    const uint64_t wi = w[i];
+    uint64_t bits = 0x7FF0000000000000ull;  // +inf
+    if (wi) {
+#pragma clang fp contract(off)
+      const double kap = E / (double)wi;
+      bits = (uint64_t)__double_as_longlong(kap);
+    }
+    keys[i] = bits;
+  }
+  __syncthreads();
+
+  // 2. radix select: the n-th smallest key T and how many keys equal to T to take
+  __shared__ uint32_t hist[256];
+  __shared__ uint64_t s_prefix;
+  __shared__ int64_t s_want;
+  uint64_t prefix = 0, mask = 0;
+  int64_t want = n;
+  if (n > 0) {
+    for (int shift = 56; shift >= 0; shift -= 8) {
+      for (int d = tid; d < 256; d += kSampleThreads) hist[d] = 0;
+      __syncthreads();
+      for (int64_t i = tid; i < N; i += kSampleThreads) {
+        const uint64_t kv = keys[i];
+        if ((kv & mask) == prefix) atomicAdd(&hist[(kv >> shift) & 0xFF], 1u);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        int64_t cum = 0;
+        for (int d = 0; d < 256; ++d) {
+          if (cum + (int64_t)hist[d] >= want) {
+            s_prefix = prefix | ((uint64_t)d << shift);
+            s_want = want - cum;
+            break;
+          }
+          cum += hist[d];
+        }
+      }
+      __syncthreads();
+      prefix = s_prefix;
+      want = s_want;
+      mask |= 0xFFull << shift;
+    }
+  }
+  const uint64_t T = prefix;
+  const int64_t ties_needed = n > 0 ? want : 0;
+
+  // 3. stable compaction in index order
+  __shared__ uint32_t wcnt_eq[kSampleThreads / kWave], wcnt_sel[kSampleThreads / kWave];
+  __shared__ int64_t run_eq, run_sel;
+  if (tid == 0) {
+    run_eq = 0;
+    run_sel = 0;
+  }
+  __syncthreads();
+  const int wave = tid >> 6;
+  for (int64_t base = 0; base < N; base += kSampleThreads) {
+    const int64_t i = base + tid;
+    const uint64_t kv = i < N ? keys[i] : ~0ull;
+    const bool in = i < N && n > 0;
+    const bool lt = in && kv < T;
+    const bool eq = in && kv == T;
+    const uint64_t beq = __ballot(eq);
+    if (lane_id() == 0) wcnt_eq[wave] = (uint32_t)__popcll(beq);
+    __syncthreads();
+    int64_t pre_eq = run_eq;
+    for (int q = 0; q < wave; ++q) pre_eq += wcnt_eq[q];
+    const int64_t tie_rank = pre_eq + __popcll(beq & lanemask_lt());
+    const bool sel = lt || (eq && tie_rank < ties_needed);
+    const uint64_t bsel = __ballot(sel);
+    if (lane_id() == 0) wcnt_sel[wave] = (uint32_t)__popcll(bsel);
+    __syncthreads();
+    int64_t pre_sel = run_sel;
+    for (int q = 0; q < wave; ++q) pre_sel += wcnt_sel[q];
+    const int64_t pos = pre_sel + __popcll(bsel & lanemask_lt());
+    if (sel && pos < n) out[pos] = (int32_t)i;
+    __syncthreads();
+    if (tid == 0) {
+      int64_t te = 0, ts = 0;
+      for (int q = 0; q < kSampleThreads / kWave; ++q) {
+        te += wcnt_eq[q];
+        ts += wcnt_sel[q];
+      }
+      run_eq += te;
+      run_sel += ts;
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  fill_u64_kernel<<<fill_blocks(n), 256, 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  fill_u32_kernel<<<fill_blocks(n), 256, 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  fill_f64_kernel<<<fill_blocks(n), 256, 0, s>>>(p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_maxsq_dense(int prec, const void* X, int64_t n, uint64_t* out_bits,
+                              hipStream_t s) {
+  hipError_t e = launch_fill_u64(out_bits, 1, 0, s);
+  if (e != hipSuccess || n <= 0) return e;
+  if (prec == kF64)
+    maxsq_kernel<double><<<fill_blocks(n), 256, 0, s>>>((const double*)X, n, out_bits);
+  else
+    maxsq_kernel<float><<<fill_blocks(n), 256, 0, s>>>((const float*)X, n, out_bits);
+  return hipGetLastError();
+}
+
+hipError_t launch_maxsq_coo(const float* v, int64_t n, uint64_t* out_bits, hipStream_t s) {
+  hipError_t e = launch_fill_u64(out_bits, 1, 0, s);
+  if (e != hipSuccess || n <= 0) return e;
+  maxsq_kernel<float><<<fill_blocks(n), 256, 0, s>>>(v, n, out_bits);
+  return hipGetLastError();
+}
+
+hipError_t launch_moi_dense(int prec, const void* Y, int64_t I, int64_t J, int64_t K,
+                            double scale, uint64_t qmax, uint64_t* w1, uint64_t* w2,
+                            uint64_t* w3, uint32_t* err, hipStream_t s) {
+  if (I <= 0 || J <= 0 || K <= 0) return hipSuccess;
+  dim3 grid((unsigned)((I + kWave - 1) / kWave), (unsigned)((J + kMoiJChunk - 1) / kMoiJChunk),
+            (unsigned)K);
+  if (prec == kF64)
+    moi_dense_kernel<double><<<grid, 256, 0, s>>>((const double*)Y, I, J, scale, qmax, w1, w2,
+                                                  w3, err);
+  else
+    moi_dense_kernel<float><<<grid, 256, 0, s>>>((const float*)Y, I, J, scale, qmax, w1, w2, w3,
+                                                 err);
+  return hipGetLastError();
+}
+
+hipError_t launch_moi_coo(const int32_t* ii, const int32_t* jj, const int32_t* kk,
+                          const float* v, int64_t nnz, int64_t I, int64_t J, int64_t K,
+                          double scale, uint64_t qmax, uint64_t* w1, uint64_t* w2,
+                          uint64_t* w3, uint32_t* err, hipStream_t s) {
+  if (nnz <= 0) return hipSuccess;
+  moi_coo_kernel<<<fill_blocks(nnz), 256, 0, s>>>(ii, jj, kk, v, nnz, I, J, K, scale, qmax, w1,
+                                                  w2, w3, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample(const SampleArgs& a, uint64_t* keys, int32_t* idx, hipStream_t s) {
+  if (a.nrep <= 0) return hipSuccess;
+  sample_kernel<<<dim3((unsigned)a.nrep, 3), kSampleThreads, 0, s>>>(a, keys, idx);
+  return hipGetLastError();
+}
+
+}  // namespace sbt

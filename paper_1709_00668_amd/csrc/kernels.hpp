@@ -1,0 +1,151 @@
+// Host-side launchers of the gfx950 kernels of the SamBaTen update.
+// Every launcher enqueues on `stream` and returns the launch status.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sbt {
+
+// Summary / MTTKRP element types.
+enum Prec : int { kF64 = 0, kF32 = 1, kBF16 = 2 };
+
+inline size_t prec_bytes(int p) { return p == kF64 ? 8 : (p == kF32 ? 4 : 2); }
+// Accumulation type of the MTTKRP kernels: double for FP64, float otherwise.
+inline size_t acc_bytes(int p) { return p == kF64 ? 8 : 4; }
+
+constexpr int kMaxRank = 32;
+
+// Shapes of the r summaries of one update (identical for every repetition)
+// and the per-repetition strides of every workspace array (in elements).
+struct RepSet {
+  int n1, n2, n3;   // summary dims; n3 = K' = sampled old slices + new slices
+  int R;
+  int rep0, nrep;   // repetitions [rep0, rep0 + nrep) of this launch
+  int64_t sZ;       // summary elements
+  int64_t sA, sB, sC;  // factor rows * R
+  int64_t sW;       // n1*n2*R (acc type)
+  int64_t sM;       // max rows * R (double)
+  int64_t sG;       // R*R
+};
+
+// ---- importance (Eq. 1), integer form ------------------------------------
+hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, int64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
+// max over x*x of a dense block, as the bit pattern of a non-negative double
+hipError_t launch_maxsq_dense(int prec, const void* X, int64_t n, uint64_t* out_bits,
+                              hipStream_t s);
+hipError_t launch_maxsq_coo(const float* v, int64_t n, uint64_t* out_bits, hipStream_t s);
+// per-index sums of q(x) = floor(x*x*scale) of a dense I x J x K block;
+// w3 receives one entry per slice.  err |= 1 on a non-finite x or q > qmax.
+hipError_t launch_moi_dense(int prec, const void* Y, int64_t I, int64_t J, int64_t K,
+                            double scale, uint64_t qmax, uint64_t* w1, uint64_t* w2,
+                            uint64_t* w3, uint32_t* err, hipStream_t s);
+// Same for COO entries (k relative to w3).  err |= 2 on a coordinate outside
+// I x J x K.
+hipError_t launch_moi_coo(const int32_t* ii, const int32_t* jj, const int32_t* kk,
+                          const float* v, int64_t nnz, int64_t I, int64_t J, int64_t K,
+                          double scale, uint64_t qmax, uint64_t* w1, uint64_t* w2,
+                          uint64_t* w3, uint32_t* err, hipStream_t s);
+
+// ---- weighted sampling without replacement --------------------------------
+struct SampleArgs {
+  const uint64_t* w[3];  // importance per mode
+  int64_t N[3];          // population per mode
+  int n[3];              // sample size per mode
+  int64_t key_off[3];    // offsets into the per-repetition key scratch
+  int64_t key_stride;    // per repetition
+  int64_t idx_off[3];    // offsets into the per-repetition index output
+  int64_t idx_stride;
+  uint64_t seed;
+  uint32_t tensor_id;
+  uint32_t t;
+  int nrep;
+};
+hipError_t launch_sample(const SampleArgs& a, uint64_t* keys, int32_t* idx, hipStream_t s);
+
+// ---- summaries -----------------------------------------------------------
+// Z[rep](a,b,c) = X(Is[a], Js[b], K'[c]) with K'[c] = Ks[c] for c < n3old and
+// Kold + c - n3old after; converted to the summary precision.
+hipError_t launch_gather_dense(int store_prec, int sum_prec, const void* X, int64_t I,
+                               int64_t J, const int32_t* idx, int64_t idx_stride,
+                               int64_t offJ, int64_t offK, int n3old, int64_t Kold,
+                               const RepSet& rs, void* Z, hipStream_t s);
+
+// ---- CP-ALS on the summaries --------------------------------------------
+// B', C' <- U[0,1) from Philox counters (row, col, tag(stream, mode, rep), t)
+hipError_t launch_als_init(const RepSet& rs, uint64_t seed, uint32_t tensor_id, uint32_t stream,
+                           uint32_t t, double* Bp, double* Cp, hipStream_t s);
+// G = U^T U for rows x R factors of each repetition
+hipError_t launch_gram(const RepSet& rs, const double* U, int64_t sU, int rows, double* G,
+                       hipStream_t s);
+// W(ab, f) = sum_c Z(ab, c) Cf(c, f)
+hipError_t launch_p1(int prec, const RepSet& rs, const void* Z, const double* Cf, void* W,
+                     hipStream_t s);
+// mode 0 from W: M(a, f) = sum_b W(a,b,f) Bf(b,f)
+hipError_t launch_cw1(int prec, const RepSet& rs, const void* W, const double* Bf, double* M,
+                      hipStream_t s);
+// mode 1 from W: M(b, f) = sum_a W(a,b,f) Af(a,f)
+hipError_t launch_cw2(int prec, const RepSet& rs, const void* W, const double* Af, double* M,
+                      hipStream_t s);
+// mode 2: M(c, f) = sum_ab Z(a,b,c) Af(a,f) Bf(b,f)
+hipError_t launch_p2(int prec, const RepSet& rs, const void* Z, const double* Af,
+                     const double* Bf, double* M, hipStream_t s);
+// U = M (G1 .* G2)^-1 (Cholesky, pseudo-inverse fallback).
+//  normalize=1: lam_out = column norms, U normalised, Gout = U^T U.
+//  normalize=0: U(:, f) /= lam_div[f] (0 when lam_div[f] == 0).
+hipError_t launch_solve(const RepSet& rs, int rows, const double* M, const double* G1,
+                        int64_t sG1, const double* G2, int64_t sG2, double* U, int64_t sU,
+                        double* Gout,
+                        double* lam_out, const double* lam_div, int normalize,
+                        uint32_t* pinv_count, hipStream_t s);
+
+// ---- matching, row solve inputs ------------------------------------------
+struct MatchArgs {
+  const double *A, *B, *C;      // current model (row-major)
+  const int32_t* idx;           // per-repetition sampled indices
+  int64_t idx_stride, offJ, offK;
+  int n3old;                    // anchor rows of C' (sampled old slices)
+  const double *Ap, *Bp, *Cp;   // summary factors
+  double *At, *Bt;              // matched, rescaled
+  double* Gt;                   // (At^T At) .* (Bt^T Bt)
+  int32_t *pi, *valid;
+};
+hipError_t launch_match(const RepSet& rs, const MatchArgs& m, hipStream_t s);
+
+// ---- commit ----------------------------------------------------------------
+struct CommitArgs {
+  const uint32_t* err;
+  double *A, *B, *C;  // model, updated in place
+  int64_t I, J, Kold, Knew;
+  int R, nrep, n1, n2, n3old, Kp;
+  const int32_t* idx;
+  int64_t idx_stride, offJ, offK;
+  const double *At, *Bt, *Ct;
+  int64_t sA, sB, sC;
+  const int32_t* valid;
+  uint64_t *w1, *w2, *w3;            // state importance
+  const uint64_t *dw1, *dw2, *dw3;   // batch importance
+};
+hipError_t launch_commit(const CommitArgs& c, hipStream_t s);
+
+// ---- fit -------------------------------------------------------------------
+// M3(k, f) = sum_ij X(i,j,k) A(i,f) B(j,f) and nrm(k) = sum_ij X(i,j,k)^2, FP64
+hipError_t launch_fit_slices(int prec, const void* X, int64_t I, int64_t J, int64_t K, int R,
+                             const double* A, const double* B, double* M3, double* nrm,
+                             hipStream_t s);
+hipError_t launch_fit_coo(const int32_t* ii, const int32_t* jj, const int32_t* kk,
+                          const float* v, int64_t nnz, int R, const double* A, const double* B,
+                          double* M3, double* nrm, hipStream_t s);
+// fit = 1 - sqrt(max(0, sum nrm - 2 <X,Xhat> + ||Xhat||^2)) / sqrt(sum nrm)
+hipError_t launch_fit_final(const double* A, const double* B, const double* C, const double* lam,
+                            const double* M3, const double* nrm, int64_t I, int64_t J, int64_t K,
+                            int R, double* fit, hipStream_t s);
+
+// ---- initial model ordering ----------------------------------------------
+// Order components by lam descending (ties: lower index first) in place.
+hipError_t launch_sort_components(double* A, double* B, double* C, double* lam, int64_t I,
+                                  int64_t J, int64_t K, int R, hipStream_t s);
+
+}  // namespace sbt

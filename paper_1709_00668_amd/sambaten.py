@@ -1,0 +1,243 @@
+"""ctypes binding of libsambaten.so (the gfx950 HIP library).
+
+The binding only marshals arguments: every step of the update runs in the
+library's kernels.  Function names follow the C ABI in include/sambaten.h.
+torch is used for device buffers and streams only.
+
+Raises RuntimeError at import when the library has not been built; there is
+no fallback path.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsambaten.so")
+
+SBT_OK, SBT_E_INVALID, SBT_E_SHAPE, SBT_E_NOMEM, SBT_E_DEVICE, SBT_E_NUMERIC, SBT_E_STATE = range(7)
+SBT_DENSE, SBT_COO = 0, 1
+SBT_P_F64, SBT_P_F32, SBT_P_BF16 = 0, 1, 2
+SBT_SCHED_BATCHED, SBT_SCHED_PLAIN = 0, 1
+(SBT_REP_AP, SBT_REP_BP, SBT_REP_CP, SBT_REP_LAMP, SBT_REP_PI, SBT_REP_VALID, SBT_REP_AT,
+ SBT_REP_BT, SBT_REP_CT) = range(9)
+
+
+class sbt_config(ctypes.Structure):
+    _fields_ = [
+        ("rank", ctypes.c_int32),
+        ("repetitions", ctypes.c_int32),
+        ("als_iters", ctypes.c_int32),
+        ("init_iters", ctypes.c_int32),
+        ("sample_factor", ctypes.c_int32 * 3),
+        ("format", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("schedule", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("tensor_id", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32),
+        ("k_capacity", ctypes.c_int64),
+        ("max_batch", ctypes.c_int64),
+        ("nnz_capacity", ctypes.c_int64),
+    ]
+
+
+class SbtError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_pd = ctypes.POINTER(ctypes.c_double)
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "sbt_init_dense": (ctypes.c_int, [ctypes.POINTER(sbt_config), _vp, _i64, _i64, _i64, _vp, _vp,
+                                      _vp, _vp, _vp, ctypes.POINTER(_vp)]),
+    "sbt_init_coo": (ctypes.c_int, [ctypes.POINTER(sbt_config), _vp, _vp, _vp, _vp, _i64, _i64,
+                                    _i64, _i64, _vp, _vp, _vp, _vp, _vp, ctypes.POINTER(_vp)]),
+    "sbt_destroy": (None, [_vp]),
+    "sbt_update_batch_dense": (ctypes.c_int, [_vp, _vp, _i64, _vp]),
+    "sbt_update_batch_coo": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _i64, _i64, _vp]),
+    "sbt_get_shape": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+                                     ctypes.POINTER(_i64), ctypes.POINTER(_i32)]),
+    "sbt_get_factors": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
+    "sbt_fit": (ctypes.c_int, [_vp, _pd, _vp]),
+    "sbt_get_batch_counter": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_uint32)]),
+    "sbt_last_sample": (ctypes.c_int, [_vp, _i32, _i32, _vp, ctypes.POINTER(_i64)]),
+    "sbt_last_rep": (ctypes.c_int, [_vp, _i32, _i32, _vp, _i64, ctypes.POINTER(_i64)]),
+    "sbt_mttkrp_dense": (ctypes.c_int, [_i32, _vp, _i64, _i64, _i64, _i32, _vp, _vp, _vp, _i32,
+                                        _vp, _vp]),
+    "sbt_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "sbt_last_error": (ctypes.c_char_p, [_vp]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libsambaten.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1709_00668_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return sorted(_SIGS)
+
+
+def _check(status, handle=None, what=""):
+    if status != SBT_OK:
+        lib = load()
+        msg = lib.sbt_status_str(status).decode()
+        if handle:
+            detail = lib.sbt_last_error(handle).decode()
+            if detail:
+                msg = f"{msg}: {detail}"
+        raise SbtError(status, f"{what}: {msg}" if what else msg)
+
+
+def _ptr(a):
+    """Device or host address of a torch tensor / numpy array / int / None."""
+    if a is None:
+        return None
+    if isinstance(a, int):
+        return a
+    if hasattr(a, "data_ptr"):
+        return a.data_ptr()
+    return a.ctypes.data
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+def make_config(rank, repetitions, als_iters, sample_factor, seed, *, init_iters=100,
+                fmt=SBT_DENSE, precision=SBT_P_F32, schedule=SBT_SCHED_BATCHED, tensor_id=0,
+                k_capacity, max_batch, nnz_capacity=0):
+    c = sbt_config()
+    c.rank, c.repetitions, c.als_iters, c.init_iters = rank, repetitions, als_iters, init_iters
+    s = (sample_factor,) * 3 if np.isscalar(sample_factor) else tuple(sample_factor)
+    for m in range(3):
+        c.sample_factor[m] = int(s[m])
+    c.format, c.precision, c.schedule = fmt, precision, schedule
+    c.seed, c.tensor_id, c.flags = seed, tensor_id, 0
+    c.k_capacity, c.max_batch, c.nnz_capacity = k_capacity, max_batch, nnz_capacity
+    return c
+
+
+def dense_to_device(X, dtype):
+    """(I, J, K) array -> device tensor whose memory is the column-major layout
+    the library expects (torch shape (K, J, I), contiguous)."""
+    import torch
+    arr = np.ascontiguousarray(np.asarray(X, dtype=dtype).transpose(2, 1, 0))
+    return torch.from_numpy(arr).cuda()
+
+
+class Tensor:
+    """Owning wrapper of an sbt_tensor handle."""
+
+    def __init__(self, handle):
+        self.h = handle
+
+    # -- construction -------------------------------------------------------
+    @classmethod
+    def init_dense(cls, cfg, X0_dev, I, J, K0, factors=None, stream=None):
+        lib = load()
+        out = _vp()
+        keep = []
+        fa = [None] * 4
+        if factors is not None:
+            for q, f in enumerate(factors):
+                a = np.ascontiguousarray(f, dtype=np.float64)
+                keep.append(a)
+                fa[q] = a.ctypes.data
+        st = lib.sbt_init_dense(ctypes.byref(cfg), _ptr(X0_dev), I, J, K0, fa[0], fa[1], fa[2],
+                                fa[3], _stream(stream), ctypes.byref(out))
+        _check(st, None, "sbt_init_dense")
+        return cls(out.value)
+
+    def close(self):
+        if self.h:
+            load().sbt_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- update ---------------------------------------------------------------
+    def update_batch_dense(self, Y_dev, K_new, stream=None):
+        st = load().sbt_update_batch_dense(self.h, _ptr(Y_dev), K_new, _stream(stream))
+        _check(st, self.h, "sbt_update_batch_dense")
+
+    def try_update_batch_dense(self, Y_dev, K_new, stream=None):
+        return load().sbt_update_batch_dense(self.h, _ptr(Y_dev), K_new, _stream(stream))
+
+    # -- queries -------------------------------------------------------------
+    def shape(self):
+        I, J, K, R = _i64(), _i64(), _i64(), _i32()
+        _check(load().sbt_get_shape(self.h, ctypes.byref(I), ctypes.byref(J), ctypes.byref(K),
+                                    ctypes.byref(R)), self.h)
+        return I.value, J.value, K.value, R.value
+
+    def batch_counter(self):
+        c = ctypes.c_uint32()
+        _check(load().sbt_get_batch_counter(self.h, ctypes.byref(c)), self.h)
+        return c.value
+
+    def get_factors(self, stream=None):
+        I, J, K, R = self.shape()
+        A, B = np.empty((I, R)), np.empty((J, R))
+        C, lam = np.empty((K, R)), np.empty(R)
+        _check(load().sbt_get_factors(self.h, A.ctypes.data, B.ctypes.data, C.ctypes.data,
+                                      lam.ctypes.data, _stream(stream)), self.h, "sbt_get_factors")
+        return A, B, C, lam
+
+    def fit(self, stream=None):
+        f = ctypes.c_double()
+        _check(load().sbt_fit(self.h, ctypes.byref(f), _stream(stream)), self.h, "sbt_fit")
+        return f.value
+
+    def last_sample(self, rep, mode):
+        I, J, K, R = self.shape()
+        buf = np.empty(max(I, J, K) + 1, dtype=np.int32)
+        n = _i64()
+        _check(load().sbt_last_sample(self.h, rep, mode, buf.ctypes.data, ctypes.byref(n)),
+               self.h, "sbt_last_sample")
+        return buf[:n.value].copy()
+
+    def last_rep(self, rep, item, max_rows):
+        I, J, K, R = self.shape()
+        cap = (max_rows + 1) * R
+        buf = np.empty(cap)
+        rows = _i64()
+        _check(load().sbt_last_rep(self.h, rep, item, buf.ctypes.data, cap, ctypes.byref(rows)),
+               self.h, "sbt_last_rep")
+        return buf[:rows.value * R].reshape(rows.value, R).copy()
+
+
+def mttkrp_dense(precision, Z_dev, n1, n2, n3, R, U0_dev, U1_dev, U2_dev, mode, out_dev,
+                 stream=None):
+    st = load().sbt_mttkrp_dense(precision, _ptr(Z_dev), n1, n2, n3, R, _ptr(U0_dev),
+                                 _ptr(U1_dev), _ptr(U2_dev), mode, _ptr(out_dev), _stream(stream))
+    _check(st, None, "sbt_mttkrp_dense")

@@ -1,0 +1,197 @@
+"""Parity of the HIP update path with the CPU FP64 oracle (dense tensors).
+
+Bar: sampled indices bit-exact; FP64 path within 1e-8 of the oracle on every
+intermediate; FP32 path MTTKRP relative error <= 1e-5 and final fit within 1e-3.
+"""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import cp
+from oracle import sambaten as osb
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def run_pair(lib, I, J, K0, Kn, R, reps, iters, s, seed, prec, batches=1, init="oracle",
+             schedule=None, noise=0.01):
+    """Oracle and GPU side by side on one synthetic tensor; yields per-batch debug."""
+    torch = _torch()
+    dtype = np.float64 if prec == lib.SBT_P_F64 else np.float32
+    gen = synth.DenseCP(I, J, K0 + batches * Kn, R, seed=seed, noise=noise, dtype=dtype)
+    X = gen.slices(0, K0 + batches * Kn)
+    ocfg = osb.Config(rank=R, reps=reps, als_iters=iters, sample_factor=s, seed=seed,
+                      k_capacity=K0 + batches * Kn, init_iters=60)
+    if init == "oracle":
+        ora = osb.OracleTensor(ocfg, osb.DENSE, (I, J, K0), X0=X[:, :, :K0])
+    else:
+        ora = osb.OracleTensor(ocfg, osb.DENSE, (I, J, K0), X0=X[:, :, :K0],
+                               factors=gen.true_model_prefix(K0))
+    cfg = lib.make_config(R, reps, iters, s, seed, precision=prec, k_capacity=K0 + batches * Kn,
+                          max_batch=Kn, init_iters=60,
+                          schedule=lib.SBT_SCHED_BATCHED if schedule is None else schedule)
+    gpu = lib.Tensor.init_dense(cfg, lib.dense_to_device(X[:, :, :K0], dtype), I, J, K0,
+                                factors=(ora.A, ora.B, ora.C, ora.lam))
+    out = []
+    for b in range(batches):
+        Y = X[:, :, K0 + b * Kn:K0 + (b + 1) * Kn]
+        d = ora.update(Y, debug=True)
+        gpu.update_batch_dense(lib.dense_to_device(Y, dtype), Kn)
+        torch.cuda.synchronize()
+        out.append(d)
+    return ora, gpu, out
+
+
+def check_samples(gpu, d, reps):
+    for rho in range(reps):
+        for mode, key in enumerate(("Is", "Js", "Ks")):
+            got = gpu.last_sample(rho, mode)
+            np.testing.assert_array_equal(got, d["reps"][rho][key],
+                                          err_msg=f"rep {rho} mode {mode}")
+
+
+def test_c1_fp64_update_matches_oracle(lib):
+    # 50 x 50 x 40 + one batch of 10, R = 5, s = 2, r = 4, 20 ALS sweeps
+    reps, R = 4, 5
+    ora, gpu, ds = run_pair(lib, 50, 50, 40, 10, R, reps, 20, 2, 1, lib.SBT_P_F64)
+    d = ds[0]
+    check_samples(gpu, d, reps)
+    n1, n2, Kp = 25, 25, 20 + 10
+    for rho in range(reps):
+        r = d["reps"][rho]
+        np.testing.assert_allclose(gpu.last_rep(rho, lib.SBT_REP_AP, n1), r["Ap"], rtol=1e-8,
+                                   atol=1e-10)
+        np.testing.assert_allclose(gpu.last_rep(rho, lib.SBT_REP_BP, n2), r["Bp"], rtol=1e-8,
+                                   atol=1e-10)
+        np.testing.assert_allclose(gpu.last_rep(rho, lib.SBT_REP_CP, Kp), r["Cp"], rtol=1e-8,
+                                   atol=1e-10)
+        np.testing.assert_allclose(gpu.last_rep(rho, lib.SBT_REP_LAMP, 1)[0], r["lamp"],
+                                   rtol=1e-8)
+        np.testing.assert_array_equal(gpu.last_rep(rho, lib.SBT_REP_PI, 1)[0], r["pi"])
+        np.testing.assert_allclose(gpu.last_rep(rho, lib.SBT_REP_AT, n1), r["At"], rtol=1e-8,
+                                   atol=1e-10)
+        np.testing.assert_allclose(gpu.last_rep(rho, lib.SBT_REP_CT, Kp), r["Ct"], rtol=1e-7,
+                                   atol=1e-9)
+    A, B, C, lam = gpu.get_factors()
+    np.testing.assert_allclose(C, ora.C, rtol=1e-7, atol=1e-9)
+    np.testing.assert_allclose(A, ora.A, rtol=1e-9, atol=1e-12)
+    np.testing.assert_array_equal(lam, ora.lam)
+    assert abs(gpu.fit() - ora.fit()) < 1e-9
+    assert gpu.batch_counter() == 1 and gpu.shape() == (50, 50, 50, R)
+
+
+def test_fp64_three_batches_ragged_shapes(lib):
+    # sizes that are not multiples of any tile, several batches, K_new = 7
+    reps = 3
+    ora, gpu, ds = run_pair(lib, 37, 29, 23, 7, 3, reps, 12, 3, 5, lib.SBT_P_F64, batches=3)
+    check_samples(gpu, ds[-1], reps)
+    _, _, C, _ = gpu.get_factors()
+    np.testing.assert_allclose(C, ora.C, rtol=1e-7, atol=1e-9)
+    assert abs(gpu.fit() - ora.fit()) < 1e-9
+
+
+def test_fp32_update_matches_oracle(lib):
+    # FP32 store and MTTKRP, FP64 solves; ten repetitions as in the 500^3 workload
+    reps = 10
+    ora, gpu, ds = run_pair(lib, 100, 90, 60, 12, 10, reps, 30, 5, 2, lib.SBT_P_F32,
+                            batches=2, init="true")
+    check_samples(gpu, ds[-1], reps)
+    _, _, C, _ = gpu.get_factors()
+    assert abs(gpu.fit() - ora.fit()) < 1e-3
+    err = np.linalg.norm(C[60:] - ora.C[60:]) / np.linalg.norm(ora.C[60:])
+    assert err < 1e-3, err
+
+
+def test_plain_schedule_equals_batched(lib):
+    torch = _torch()
+    res = []
+    for sched in (lib.SBT_SCHED_BATCHED, lib.SBT_SCHED_PLAIN):
+        ora, gpu, ds = run_pair(lib, 40, 30, 20, 5, 4, 3, 8, 2, 11, lib.SBT_P_F32, init="true",
+                                schedule=sched)
+        res.append(gpu.get_factors())
+        torch.cuda.synchronize()
+    for a, b in zip(res[0], res[1]):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_singleton_batch_and_unit_sample_factor(lib):
+    # K_new = 1 (singleton batches, Sec. 3.1) and s = 1 (summary = whole tensor)
+    reps = 2
+    ora, gpu, ds = run_pair(lib, 12, 10, 6, 1, 2, reps, 10, 1, 3, lib.SBT_P_F64, batches=2,
+                            init="true")
+    check_samples(gpu, ds[-1], reps)
+    np.testing.assert_array_equal(gpu.last_sample(0, 0), np.arange(12))
+    _, _, C, _ = gpu.get_factors()
+    np.testing.assert_allclose(C, ora.C, rtol=1e-7, atol=1e-9)
+
+
+def test_init_cp_als_matches_oracle(lib):
+    torch = _torch()
+    I, J, K0, R = 30, 25, 20, 3
+    gen = synth.DenseCP(I, J, K0 + 5, R, seed=9, dtype=np.float64)
+    X = gen.slices(0, K0)
+    ocfg = osb.Config(rank=R, reps=2, als_iters=5, sample_factor=2, seed=9, k_capacity=K0 + 5,
+                      init_iters=50)
+    ora = osb.OracleTensor(ocfg, osb.DENSE, (I, J, K0), X0=X)
+    cfg = lib.make_config(R, 2, 5, 2, 9, precision=lib.SBT_P_F64, k_capacity=K0 + 5,
+                          max_batch=5, init_iters=50)
+    gpu = lib.Tensor.init_dense(cfg, lib.dense_to_device(X, np.float64), I, J, K0)
+    torch.cuda.synchronize()
+    A, B, C, lam = gpu.get_factors()
+    np.testing.assert_allclose(lam, ora.lam, rtol=1e-8)
+    np.testing.assert_allclose(A, ora.A, rtol=1e-7, atol=1e-9)
+    np.testing.assert_allclose(C, ora.C, rtol=1e-7, atol=1e-9)
+    assert abs(gpu.fit() - ora.fit()) < 1e-10
+
+
+def test_numeric_error_leaves_state_unchanged(lib):
+    torch = _torch()
+    I, J, K0, Kn, R = 16, 14, 10, 4, 2
+    gen = synth.DenseCP(I, J, K0 + 2 * Kn, R, seed=4, dtype=np.float32)
+    X = gen.slices(0, K0 + 2 * Kn)
+    cfg = lib.make_config(R, 2, 5, 2, 4, precision=lib.SBT_P_F32, k_capacity=K0 + 2 * Kn,
+                          max_batch=Kn)
+    gpu = lib.Tensor.init_dense(cfg, lib.dense_to_device(X[:, :, :K0], np.float32), I, J, K0,
+                                factors=gen.true_model_prefix(K0))
+    before = gpu.get_factors()
+    Y = X[:, :, K0:K0 + Kn].copy()
+    Y[3, 2, 1] = np.nan
+    st = gpu.try_update_batch_dense(lib.dense_to_device(Y, np.float32), Kn)
+    assert st == lib.SBT_E_NUMERIC
+    after = gpu.get_factors()
+    for a, b in zip(before, after):
+        np.testing.assert_array_equal(a, b)
+    assert gpu.shape()[2] == K0 and gpu.batch_counter() == 0
+    # shape errors: empty batch, over max_batch
+    assert gpu.try_update_batch_dense(lib.dense_to_device(Y, np.float32), 0) == lib.SBT_E_SHAPE
+    assert gpu.try_update_batch_dense(lib.dense_to_device(Y, np.float32), Kn + 1) == lib.SBT_E_SHAPE
+    # the next good batch still goes through, with the counter that was not consumed
+    gpu.update_batch_dense(lib.dense_to_device(X[:, :, K0:K0 + Kn], np.float32), Kn)
+    torch.cuda.synchronize()
+    assert gpu.shape()[2] == K0 + Kn and gpu.batch_counter() == 1
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-5)])
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_mttkrp_kernel_relative_error(lib, prec, tol, mode):
+    torch = _torch()
+    g = np.random.default_rng(100 + mode)
+    n1, n2, n3, R = 97, 61, 45, 10
+    Z = g.random((n1, n2, n3))
+    U = [g.random((n, R)) for n in (n1, n2, n3)]
+    dtype = np.float64 if prec == 0 else np.float32
+    Zd = lib.dense_to_device(Z, dtype)
+    Ud = [torch.from_numpy(np.ascontiguousarray(u)).cuda() for u in U]
+    out = torch.zeros((Z.shape[mode], R), dtype=torch.float64, device="cuda")
+    lib.mttkrp_dense(prec, Zd, n1, n2, n3, R, Ud[0], Ud[1], Ud[2], mode, out)
+    torch.cuda.synchronize()
+    ref = cp.mttkrp_dense(Z.astype(dtype).astype(np.float64), U, mode)
+    rel = np.linalg.norm(out.cpu().numpy() - ref) / np.linalg.norm(ref)
+    assert rel <= tol, rel
