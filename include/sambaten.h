@@ -193,6 +193,25 @@ sbt_status sbt_mttkrp_dense(int32_t precision, const void* Z_dev, int64_t n1, in
                             int64_t n3, int32_t R, const double* U0_dev, const double* U1_dev,
                             const double* U2_dev, int32_t mode, double* out_dev, void* stream);
 
+/* --------------------------------------------------------------------------
+ * Kernel timing.  While enabled, every update records a HIP event pair on its
+ * stream around each launch of the kinds below and accumulates, per kind, the
+ * launch count, the summed device time and the algorithmic bytes the launches
+ * must move (summary elements read once plus factor rows read and outputs
+ * written).  Timing adds two event records per timed launch.
+ * ------------------------------------------------------------------------ */
+typedef enum {
+  SBT_K_MTTKRP_C = 0,   /* MTTKRP pass contracting the third mode with C'       */
+  SBT_K_MTTKRP_AB = 1,  /* MTTKRP pass producing third-mode rows (ALS + row solve) */
+  SBT_K_GATHER = 2,     /* summary gather                                        */
+  SBT_K_UPDATE = 3,     /* whole update, first to last kernel                   */
+  SBT_K_COUNT = 4
+} sbt_kernel_kind;
+
+sbt_status sbt_profile_enable(sbt_tensor* t, int32_t on);
+sbt_status sbt_profile_read(const sbt_tensor* t, int32_t kind, int64_t* launches,
+                            double* total_ms, double* alg_bytes);
+
 /* Human-readable text for a status, and the last error message of a tensor. */
 const char* sbt_status_str(sbt_status s);
 const char* sbt_last_error(const sbt_tensor* t);

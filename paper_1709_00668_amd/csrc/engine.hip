@@ -55,6 +55,14 @@ struct sbt_tensor {
          *Bt = nullptr, *Ct = nullptr, *M3 = nullptr, *nrm = nullptr, *fitv = nullptr;
   uint32_t* h_err = nullptr;  // pinned
   std::vector<void*> allocs;
+  // kernel timing (sbt_profile_*)
+  bool prof_on = false;
+  std::vector<hipEvent_t> prof_ev;     // pairs
+  std::vector<int> prof_kind;          // per recorded pair
+  std::vector<double> prof_bytes;      // per recorded pair
+  int64_t prof_n[SBT_K_COUNT] = {0, 0, 0, 0};
+  double prof_ms[SBT_K_COUNT] = {0, 0, 0, 0};
+  double prof_b[SBT_K_COUNT] = {0, 0, 0, 0};
   // last update, for the inspection calls
   bool has_last = false;
   int last_n3old = 0, last_Kp = 0;
@@ -103,6 +111,52 @@ sbt_status dalloc_bytes(sbt_tensor* t, void** p, size_t bytes) {
     sbt_status s_ = (expr);             \
     if (s_ != SBT_OK) return s_;        \
   } while (0)
+
+// Kernel timing: an event pair per timed launch, resolved after the update's
+// final synchronisation.
+constexpr size_t kProfPairs = 8192;
+
+int prof_begin(sbt_tensor* t, hipStream_t st) {
+  if (!t->prof_on) return -1;
+  const size_t q = t->prof_kind.size();
+  if (q >= kProfPairs) return -1;
+  if (t->prof_ev.size() < 2 * (q + 1)) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return -1;
+    if (hipEventCreate(&b) != hipSuccess) {
+      (void)hipEventDestroy(a);
+      return -1;
+    }
+    t->prof_ev.push_back(a);
+    t->prof_ev.push_back(b);
+  }
+  if (hipEventRecord(t->prof_ev[2 * q], st) != hipSuccess) return -1;
+  t->prof_kind.push_back(-1);
+  t->prof_bytes.push_back(0.0);
+  return (int)q;
+}
+
+void prof_end(sbt_tensor* t, int q, int kind, double bytes, hipStream_t st) {
+  if (q < 0) return;
+  if (hipEventRecord(t->prof_ev[2 * (size_t)q + 1], st) != hipSuccess) return;
+  t->prof_kind[(size_t)q] = kind;
+  t->prof_bytes[(size_t)q] = bytes;
+}
+
+// after the stream has been synchronised
+void prof_collect(sbt_tensor* t) {
+  for (size_t q = 0; q < t->prof_kind.size(); ++q) {
+    const int kind = t->prof_kind[q];
+    if (kind < 0) continue;
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, t->prof_ev[2 * q], t->prof_ev[2 * q + 1]) != hipSuccess) continue;
+    t->prof_n[kind] += 1;
+    t->prof_ms[kind] += ms;
+    t->prof_b[kind] += t->prof_bytes[q];
+  }
+  t->prof_kind.clear();
+  t->prof_bytes.clear();
+}
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -251,19 +305,32 @@ sbt_status run_als(sbt_tensor* t, const void* Zp, RepSet rs, double* Ap, double*
   SBT_CK(launch_als_init(rs, t->cfg.seed, t->cfg.tensor_id, stream, t_ctr, Bp, Cp, st));
   SBT_CK(launch_gram(rs, Bp, rs.sB, rs.n2, GB, st));
   SBT_CK(launch_gram(rs, Cp, rs.sC, rs.n3, GC, st));
+  const double zb = (double)rs.nrep * rs.n1 * rs.n2 * rs.n3 * prec_bytes(prec);
+  const double p1_bytes = zb + (double)rs.nrep * rs.R *
+                                   ((double)rs.n3 * 8 + (double)rs.n1 * rs.n2 * acc_bytes(prec));
+  const double p2_bytes =
+      zb + (double)rs.nrep * rs.R * 8.0 * ((double)rs.n1 + rs.n2 + rs.n3);
   for (int it = 0; it < iters; ++it) {
     // mode 1
+    int pq = prof_begin(t, st);
     SBT_CK(launch_p1(prec, rs, Zp, Cp, W, st));
+    prof_end(t, pq, SBT_K_MTTKRP_C, p1_bytes, st);
     SBT_CK(launch_cw1(prec, rs, W, Bp, M, st));
     SBT_CK(launch_solve(rs, rs.n1, M, GB, rs.sG, GC, rs.sG, Ap, rs.sA, GA, lam_out, nullptr, 1, t->pinv,
                         st));
     // mode 2 (the plain schedule re-runs the contraction with C')
-    if (plain) SBT_CK(launch_p1(prec, rs, Zp, Cp, W, st));
+    if (plain) {
+      pq = prof_begin(t, st);
+      SBT_CK(launch_p1(prec, rs, Zp, Cp, W, st));
+      prof_end(t, pq, SBT_K_MTTKRP_C, p1_bytes, st);
+    }
     SBT_CK(launch_cw2(prec, rs, W, Ap, M, st));
     SBT_CK(launch_solve(rs, rs.n2, M, GA, rs.sG, GC, rs.sG, Bp, rs.sB, GB, lam_out, nullptr, 1, t->pinv,
                         st));
     // mode 3
+    pq = prof_begin(t, st);
     SBT_CK(launch_p2(prec, rs, Zp, Ap, Bp, M, st));
+    prof_end(t, pq, SBT_K_MTTKRP_AB, p2_bytes, st);
     SBT_CK(launch_solve(rs, rs.n3, M, GA, rs.sG, GB, rs.sG, Cp, rs.sC, GC, lam_out, nullptr, 1, t->pinv,
                         st));
   }
@@ -338,6 +405,8 @@ sbt_status init_common(sbt_tensor* t, const double* A0, const double* B0, const 
 }
 
 void free_all(sbt_tensor* t) {
+  for (hipEvent_t e : t->prof_ev) (void)hipEventDestroy(e);
+  t->prof_ev.clear();
   for (void* p : t->allocs) (void)hipFree(p);
   t->allocs.clear();
   if (t->h_err) (void)hipHostFree(t->h_err);
@@ -355,7 +424,7 @@ sbt_status check_factor_args(const double* A0, const double* B0, const double* C
 }
 
 // The update after the batch is in the store and its importance is in dw*.
-sbt_status update_body(sbt_tensor* t, int64_t Kn, hipStream_t st) {
+sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
   const sbt_config& c = t->cfg;
   const int R = t->R, r = c.repetitions;
   const int64_t Kold = t->K;
@@ -389,8 +458,13 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, hipStream_t st) {
   RepSet all = make_repset(t, Kp, 0, r);
   const bool plain = c.schedule == SBT_SCHED_PLAIN;
   if (t->fmt == SBT_DENSE) {
+    const int gq = prof_begin(t, st);
     SBT_CK(launch_gather_dense(t->store_prec, t->sum_prec, t->X, t->I, t->J, t->idx,
                                t->idx_stride, offJ, offK, n3old, Kold, all, t->Z, st));
+    prof_end(t, gq, SBT_K_GATHER,
+             (double)r * t->n1 * t->n2 * Kp *
+                 (prec_bytes(t->store_prec) + prec_bytes(t->sum_prec)),
+             st);
   }
   const int nchunks = plain ? r : 1;
   for (int q = 0; q < nchunks; ++q) {
@@ -416,7 +490,12 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, hipStream_t st) {
     ma.valid = t->valid;
     SBT_CK(launch_match(rs, ma, st));
     // row least squares: D = Z_(3) (Bt kr At) Gt^-1, C~ = D / lambda
+    const int rq = prof_begin(t, st);
     SBT_CK(launch_p2(t->sum_prec, rs, t->Z, t->At, t->Bt, t->M, st));
+    prof_end(t, rq, SBT_K_MTTKRP_AB,
+             (double)rs.nrep * rs.n1 * rs.n2 * rs.n3 * prec_bytes(t->sum_prec) +
+                 (double)rs.nrep * rs.R * 8.0 * ((double)rs.n1 + rs.n2 + rs.n3),
+             st);
     // Gt is already the Hadamard product; the second factor is all ones
     SBT_CK(launch_solve(rs, Kp, t->M, t->Gt, rs.sG, t->ones, 0, t->Ct, rs.sC, nullptr, nullptr, t->lam,
                         0, t->pinv, st));
@@ -454,8 +533,10 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, hipStream_t st) {
   ca.dw2 = t->dw2;
   ca.dw3 = t->dw3;
   SBT_CK(launch_commit(ca, st));
+  prof_end(t, uq, SBT_K_UPDATE, 0.0, st);
   SBT_CK(hipMemcpyAsync(t->h_err, t->err, 4, hipMemcpyDeviceToHost, st));
   SBT_CK(hipStreamSynchronize(st));
+  prof_collect(t);
   if (*t->h_err) {
     set_err(t, (*t->h_err & 2u) ? "batch coordinate outside the tensor"
                                 : "batch holds a non-finite value or overflows the importance sums");
@@ -591,6 +672,7 @@ sbt_status sbt_update_batch_dense(sbt_tensor* t, const void* Y_dev, int64_t K_ne
   const size_t esz = prec_bytes(t->store_prec);
   const size_t slice = (size_t)t->I * t->J;
   void* dst = (char*)t->X + (size_t)t->K * slice * esz;
+  const int uq = prof_begin(t, st);
   // ingest: append the batch behind the stored slices (not yet part of the tensor)
   SBT_CK(hipMemcpyAsync(dst, Y_dev, slice * K_new * esz, hipMemcpyDeviceToDevice, st));
   SBT_CK(launch_fill_u64(t->dw1, t->I, 0, st));
@@ -599,7 +681,7 @@ sbt_status sbt_update_batch_dense(sbt_tensor* t, const void* Y_dev, int64_t K_ne
   SBT_CK(launch_fill_u32(t->err, 1, 0, st));
   SBT_CK(launch_moi_dense(t->store_prec, dst, t->I, t->J, K_new, t->scale, t->qmax, t->dw1,
                           t->dw2, t->dw3, t->err, st));
-  return update_body(t, K_new, st);
+  return update_body(t, K_new, uq, st);
 }
 
 sbt_status sbt_update_batch_coo(sbt_tensor* t, const int32_t* i_dev, const int32_t* j_dev,
@@ -701,6 +783,28 @@ sbt_status sbt_last_rep(const sbt_tensor* tc, int32_t rep, int32_t item, double*
     for (int64_t q = 0; q < ncol; ++q) out[q] = (double)tmp[(size_t)q];
   }
   *rows = nr;
+  return SBT_OK;
+}
+
+sbt_status sbt_profile_enable(sbt_tensor* t, int32_t on) {
+  if (!t) return SBT_E_INVALID;
+  t->prof_on = on != 0;
+  for (int k = 0; k < SBT_K_COUNT; ++k) {
+    t->prof_n[k] = 0;
+    t->prof_ms[k] = 0.0;
+    t->prof_b[k] = 0.0;
+  }
+  t->prof_kind.clear();
+  t->prof_bytes.clear();
+  return SBT_OK;
+}
+
+sbt_status sbt_profile_read(const sbt_tensor* t, int32_t kind, int64_t* launches,
+                            double* total_ms, double* alg_bytes) {
+  if (!t || kind < 0 || kind >= SBT_K_COUNT) return SBT_E_INVALID;
+  if (launches) *launches = t->prof_n[kind];
+  if (total_ms) *total_ms = t->prof_ms[kind];
+  if (alg_bytes) *alg_bytes = t->prof_b[kind];
   return SBT_OK;
 }
 

@@ -20,6 +20,7 @@ SBT_OK, SBT_E_INVALID, SBT_E_SHAPE, SBT_E_NOMEM, SBT_E_DEVICE, SBT_E_NUMERIC, SB
 SBT_DENSE, SBT_COO = 0, 1
 SBT_P_F64, SBT_P_F32, SBT_P_BF16 = 0, 1, 2
 SBT_SCHED_BATCHED, SBT_SCHED_PLAIN = 0, 1
+SBT_K_MTTKRP_C, SBT_K_MTTKRP_AB, SBT_K_GATHER, SBT_K_UPDATE = range(4)
 (SBT_REP_AP, SBT_REP_BP, SBT_REP_CP, SBT_REP_LAMP, SBT_REP_PI, SBT_REP_VALID, SBT_REP_AT,
  SBT_REP_BT, SBT_REP_CT) = range(9)
 
@@ -72,6 +73,8 @@ _SIGS = {
     "sbt_last_rep": (ctypes.c_int, [_vp, _i32, _i32, _vp, _i64, ctypes.POINTER(_i64)]),
     "sbt_mttkrp_dense": (ctypes.c_int, [_i32, _vp, _i64, _i64, _i64, _i32, _vp, _vp, _vp, _i32,
                                         _vp, _vp]),
+    "sbt_profile_enable": (ctypes.c_int, [_vp, _i32]),
+    "sbt_profile_read": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_i64), _pd, _pd]),
     "sbt_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "sbt_last_error": (ctypes.c_char_p, [_vp]),
 }
@@ -225,6 +228,15 @@ class Tensor:
         _check(load().sbt_last_sample(self.h, rep, mode, buf.ctypes.data, ctypes.byref(n)),
                self.h, "sbt_last_sample")
         return buf[:n.value].copy()
+
+    def profile_enable(self, on=True):
+        _check(load().sbt_profile_enable(self.h, 1 if on else 0), self.h)
+
+    def profile_read(self, kind):
+        n, ms, b = _i64(), ctypes.c_double(), ctypes.c_double()
+        _check(load().sbt_profile_read(self.h, kind, ctypes.byref(n), ctypes.byref(ms),
+                                       ctypes.byref(b)), self.h)
+        return n.value, ms.value, b.value
 
     def last_rep(self, rep, item, max_rows):
         I, J, K, R = self.shape()
