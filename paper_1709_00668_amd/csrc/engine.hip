@@ -47,12 +47,13 @@ struct sbt_tensor {
   int n1 = 0, n2 = 0, n3max = 0, Kpmax = 0;
   int64_t idx_stride = 0, key_stride = 0;
   uint64_t *dw1 = nullptr, *dw2 = nullptr, *dw3 = nullptr, *keys = nullptr, *bits = nullptr;
-  uint32_t *err = nullptr, *pinv = nullptr;
+  uint32_t *err = nullptr, *pinv = nullptr, *cnt = nullptr;
   int32_t *idx = nullptr, *pi = nullptr, *valid = nullptr;
   void *Z = nullptr, *W = nullptr;
   double *Ap = nullptr, *Bp = nullptr, *Cp = nullptr, *GA = nullptr, *GB = nullptr, *GC = nullptr,
          *Gt = nullptr, *ones = nullptr, *lamp = nullptr, *M = nullptr, *At = nullptr,
-         *Bt = nullptr, *Ct = nullptr, *M3 = nullptr, *nrm = nullptr, *fitv = nullptr;
+         *Bt = nullptr, *Ct = nullptr, *M3 = nullptr, *nrm = nullptr, *fitv = nullptr,
+         *Vinv = nullptr, *invlam = nullptr;
   uint32_t* h_err = nullptr;  // pinned
   std::vector<void*> allocs;
   // kernel timing (sbt_profile_*)
@@ -111,6 +112,22 @@ sbt_status dalloc_bytes(sbt_tensor* t, void** p, size_t bytes) {
     sbt_status s_ = (expr);             \
     if (s_ != SBT_OK) return s_;        \
   } while (0)
+
+// Pass 1 splits the third mode into at most this many ranges (partial W).
+constexpr int kMaxSplit = 8;
+
+// Number of third-mode ranges for pass W: about two blocks per CU in total,
+// at most 4 ranges, each at least 16 slices long.
+int choose_nsplit(int64_t n12, int n3, int nrep) {
+  const int64_t abblocks = (n12 + 255) / 256;
+  int64_t ns = (512 + abblocks * nrep - 1) / (abblocks * nrep);
+  int64_t cap = n3 / 16;
+  if (cap > 4) cap = 4;
+  if (cap < 1) cap = 1;
+  if (ns > cap) ns = cap;
+  if (ns < 1) ns = 1;
+  return (int)ns;
+}
 
 // Kernel timing: an event pair per timed launch, resolved after the update's
 // final synchronisation.
@@ -203,7 +220,8 @@ RepSet make_repset(const sbt_tensor* t, int n3, int rep0, int nrep) {
   rs.sA = (int64_t)t->n1 * t->R;
   rs.sB = (int64_t)t->n2 * t->R;
   rs.sC = (int64_t)t->Kpmax * t->R;
-  rs.sW = (int64_t)t->n1 * t->n2 * t->R;
+  rs.sW = (int64_t)kMaxSplit * t->n1 * t->n2 * t->R;
+  rs.nsplit = 1;
   int64_t mx = t->n1 > t->n2 ? t->n1 : t->n2;
   if (t->Kpmax > mx) mx = t->Kpmax;
   rs.sM = mx * t->R;
@@ -236,6 +254,7 @@ sbt_status alloc_state(sbt_tensor* t) {
   SBT_TRY(dalloc(t, &t->bits, 1));
   SBT_TRY(dalloc(t, &t->err, 1));
   SBT_TRY(dalloc(t, &t->pinv, 1));
+  SBT_TRY(dalloc(t, &t->cnt, (size_t)2 * r));
   SBT_TRY(dalloc(t, &t->idx, (size_t)r * t->idx_stride));
   SBT_TRY(dalloc(t, &t->pi, (size_t)r * R));
   SBT_TRY(dalloc(t, &t->valid, (size_t)r * R));
@@ -257,6 +276,8 @@ sbt_status alloc_state(sbt_tensor* t) {
   SBT_TRY(dalloc(t, &t->Gt, (size_t)r * rs.sG));
   SBT_TRY(dalloc(t, &t->ones, (size_t)rs.sG));
   SBT_TRY(dalloc(t, &t->lamp, (size_t)r * R));
+  SBT_TRY(dalloc(t, &t->Vinv, (size_t)r * rs.sG));
+  SBT_TRY(dalloc(t, &t->invlam, (size_t)r * 3 * R));
   SBT_TRY(dalloc(t, &t->M3, (size_t)t->Kcap * R));
   SBT_TRY(dalloc(t, &t->nrm, (size_t)t->Kcap));
   SBT_TRY(dalloc(t, &t->fitv, 1));
@@ -300,7 +321,8 @@ sbt_status set_scale(sbt_tensor* t, hipStream_t st) {
 // CP-ALS on a set of summaries (or on the whole tensor with nrep = 1).
 sbt_status run_als(sbt_tensor* t, const void* Zp, RepSet rs, double* Ap, double* Bp, double* Cp,
                    double* GA, double* GB, double* GC, double* lam_out, void* W, double* M,
-                   uint32_t stream, uint32_t t_ctr, int iters, bool plain, hipStream_t st) {
+                   double* Vinv, double* invlam, uint32_t stream, uint32_t t_ctr, int iters,
+                   bool plain, hipStream_t st) {
   const int prec = t->sum_prec;
   SBT_CK(launch_als_init(rs, t->cfg.seed, t->cfg.tensor_id, stream, t_ctr, Bp, Cp, st));
   SBT_CK(launch_gram(rs, Bp, rs.sB, rs.n2, GB, st));
@@ -310,30 +332,69 @@ sbt_status run_als(sbt_tensor* t, const void* Zp, RepSet rs, double* Ap, double*
                                    ((double)rs.n3 * 8 + (double)rs.n1 * rs.n2 * acc_bytes(prec));
   const double p2_bytes =
       zb + (double)rs.nrep * rs.R * 8.0 * ((double)rs.n1 + rs.n2 + rs.n3);
-  for (int it = 0; it < iters; ++it) {
-    // mode 1
-    int pq = prof_begin(t, st);
-    SBT_CK(launch_p1(prec, rs, Zp, Cp, W, st));
-    prof_end(t, pq, SBT_K_MTTKRP_C, p1_bytes, st);
-    SBT_CK(launch_cw1(prec, rs, W, Bp, M, st));
-    SBT_CK(launch_solve(rs, rs.n1, M, GB, rs.sG, GC, rs.sG, Ap, rs.sA, GA, lam_out, nullptr, 1, t->pinv,
-                        st));
-    // mode 2 (the plain schedule re-runs the contraction with C')
-    if (plain) {
+  if (plain) {
+    // one launch per step, three passes over the summary per sweep
+    for (int it = 0; it < iters; ++it) {
+      int pq = prof_begin(t, st);
+      SBT_CK(launch_p1(prec, rs, Zp, Cp, W, st));
+      prof_end(t, pq, SBT_K_MTTKRP_C, p1_bytes, st);
+      SBT_CK(launch_cw1(prec, rs, W, Bp, M, st));
+      SBT_CK(launch_solve(rs, rs.n1, M, GB, rs.sG, GC, rs.sG, Ap, rs.sA, GA, lam_out, nullptr, 1,
+                          t->pinv, st));
       pq = prof_begin(t, st);
       SBT_CK(launch_p1(prec, rs, Zp, Cp, W, st));
       prof_end(t, pq, SBT_K_MTTKRP_C, p1_bytes, st);
+      SBT_CK(launch_cw2(prec, rs, W, Ap, M, st));
+      SBT_CK(launch_solve(rs, rs.n2, M, GA, rs.sG, GC, rs.sG, Bp, rs.sB, GB, lam_out, nullptr, 1,
+                          t->pinv, st));
+      pq = prof_begin(t, st);
+      SBT_CK(launch_p2(prec, rs, Zp, Ap, Bp, M, st));
+      prof_end(t, pq, SBT_K_MTTKRP_AB, p2_bytes, st);
+      SBT_CK(launch_solve(rs, rs.n3, M, GA, rs.sG, GB, rs.sG, Cp, rs.sC, GC, lam_out, nullptr, 1,
+                          t->pinv, st));
     }
-    SBT_CK(launch_cw2(prec, rs, W, Ap, M, st));
-    SBT_CK(launch_solve(rs, rs.n2, M, GA, rs.sG, GC, rs.sG, Bp, rs.sB, GB, lam_out, nullptr, 1, t->pinv,
-                        st));
-    // mode 3
-    pq = prof_begin(t, st);
-    SBT_CK(launch_p2(prec, rs, Zp, Ap, Bp, M, st));
-    prof_end(t, pq, SBT_K_MTTKRP_AB, p2_bytes, st);
-    SBT_CK(launch_solve(rs, rs.n3, M, GA, rs.sG, GB, rs.sG, Cp, rs.sC, GC, lam_out, nullptr, 1, t->pinv,
-                        st));
+    return SBT_OK;
   }
+  // batched: three launches per sweep over all repetitions.  Factors stay
+  // unnormalised during the sweeps (1/lambda per column in invlam: A | B | C),
+  // V^-1 for each step is prepared by the tail of the step before.
+  const int R = rs.R;
+  double* ilA = invlam;
+  double* ilB = invlam + R;
+  double* ilC = invlam + 2 * R;
+  SBT_CK(launch_fill_f64(invlam + (int64_t)rs.rep0 * 3 * R, (int64_t)rs.nrep * 3 * R, 1.0, st));
+  SBT_CK(launch_inverse(rs, GB, rs.sG, GC, rs.sG, Vinv, t->pinv, st));
+  rs.nsplit = choose_nsplit((int64_t)rs.n1 * rs.n2, rs.n3, rs.nrep);
+  const double pw_bytes =
+      zb + (double)rs.nrep * rs.R *
+               ((double)rs.n3 * 8 + (double)rs.nsplit * rs.n1 * rs.n2 * acc_bytes(prec));
+  // invlam is laid out per repetition as [A | B | C]: strides 3R, offset by mode
+  AlsTail ta;
+  ta.sG = rs.sG;
+  ta.pinv_count = t->pinv;
+  for (int it = 0; it < iters; ++it) {
+    int pq = prof_begin(t, st);
+    SBT_CK(launch_pw(prec, rs, Zp, Cp, ilC, W, st));
+    prof_end(t, pq, SBT_K_MTTKRP_C, pw_bytes, st);
+    // mode 1: A
+    SBT_CK(launch_cw(prec, rs, 0, W, Bp, ilB, Vinv, Ap, rs.sA, st));
+    ta.U = Ap; ta.sU = rs.sA; ta.rows = rs.n1; ta.Gout = GA; ta.invlam_out = ilA;
+    ta.lam_out = nullptr; ta.Gx = GA; ta.Gy = GC; ta.Vinv_out = Vinv;
+    SBT_CK(launch_tail(rs, ta, st));
+    // mode 2: B
+    SBT_CK(launch_cw(prec, rs, 1, W, Ap, ilA, Vinv, Bp, rs.sB, st));
+    ta.U = Bp; ta.sU = rs.sB; ta.rows = rs.n2; ta.Gout = GB; ta.invlam_out = ilB;
+    ta.lam_out = nullptr; ta.Gx = GA; ta.Gy = GB; ta.Vinv_out = Vinv;
+    SBT_CK(launch_tail(rs, ta, st));
+    // mode 3: C (lambda' = its column norms)
+    pq = prof_begin(t, st);
+    SBT_CK(launch_p3(prec, rs, false, Zp, Ap, ilA, Bp, ilB, Vinv, nullptr, Cp, rs.sC, st));
+    prof_end(t, pq, SBT_K_MTTKRP_AB, p2_bytes, st);
+    ta.U = Cp; ta.sU = rs.sC; ta.rows = rs.n3; ta.Gout = GC; ta.invlam_out = ilC;
+    ta.lam_out = lam_out; ta.Gx = GB; ta.Gy = GC; ta.Vinv_out = Vinv;
+    SBT_CK(launch_tail(rs, ta, st));
+  }
+  SBT_CK(launch_normalize(rs, Ap, Bp, Cp, invlam, st));
   return SBT_OK;
 }
 
@@ -342,6 +403,7 @@ sbt_status init_common(sbt_tensor* t, const double* A0, const double* B0, const 
   const int R = t->R;
   SBT_CK(launch_fill_f64(t->ones, (int64_t)R * R, 1.0, st));
   SBT_CK(launch_fill_u32(t->pinv, 1, 0, st));
+  SBT_CK(launch_fill_u32(t->cnt, 2 * (int64_t)t->cfg.repetitions, 0, st));
   if (A0) {
     SBT_CK(hipMemcpyAsync(t->A, A0, sizeof(double) * t->I * R, hipMemcpyHostToDevice, st));
     SBT_CK(hipMemcpyAsync(t->B, B0, sizeof(double) * t->J * R, hipMemcpyHostToDevice, st));
@@ -366,7 +428,8 @@ sbt_status init_common(sbt_tensor* t, const double* A0, const double* B0, const 
   rs.sA = t->I * R;
   rs.sB = t->J * R;
   rs.sC = t->K * R;
-  rs.sW = t->I * t->J * R;
+  rs.nsplit = choose_nsplit(t->I * t->J, (int)t->K, 1);
+  rs.sW = (int64_t)rs.nsplit * t->I * t->J * R;
   int64_t mx = t->I > t->J ? t->I : t->J;
   if (t->K > mx) mx = t->K;
   rs.sM = mx * R;
@@ -385,6 +448,7 @@ sbt_status init_common(sbt_tensor* t, const double* A0, const double* B0, const 
     const int keep = t->sum_prec;
     t->sum_prec = t->store_prec;  // the whole tensor is read in its stored precision
     s = run_als(t, t->X, rs, t->A, t->B, t->C, G, G + rs.sG, G + 2 * rs.sG, t->lam, W, M,
+                t->Vinv, t->invlam,
                 kStreamInit, 0u, t->cfg.init_iters, false, st);
     t->sum_prec = keep;
     if (s == SBT_OK && t->cfg.init_iters == 0) s = SBT_E_INVALID;
@@ -470,6 +534,7 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
   for (int q = 0; q < nchunks; ++q) {
     RepSet rs = plain ? make_repset(t, Kp, q, 1) : all;
     SBT_TRY(run_als(t, t->Z, rs, t->Ap, t->Bp, t->Cp, t->GA, t->GB, t->GC, t->lamp, t->W, t->M,
+                    t->Vinv, t->invlam,
                     kStreamAlsInit, t->t, c.als_iters, plain, st));
     MatchArgs ma;
     ma.A = t->A;
@@ -490,15 +555,22 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
     ma.valid = t->valid;
     SBT_CK(launch_match(rs, ma, st));
     // row least squares: D = Z_(3) (Bt kr At) Gt^-1, C~ = D / lambda
-    const int rq = prof_begin(t, st);
-    SBT_CK(launch_p2(t->sum_prec, rs, t->Z, t->At, t->Bt, t->M, st));
-    prof_end(t, rq, SBT_K_MTTKRP_AB,
-             (double)rs.nrep * rs.n1 * rs.n2 * rs.n3 * prec_bytes(t->sum_prec) +
-                 (double)rs.nrep * rs.R * 8.0 * ((double)rs.n1 + rs.n2 + rs.n3),
-             st);
     // Gt is already the Hadamard product; the second factor is all ones
-    SBT_CK(launch_solve(rs, Kp, t->M, t->Gt, rs.sG, t->ones, 0, t->Ct, rs.sC, nullptr, nullptr, t->lam,
-                        0, t->pinv, st));
+    const double rbytes = (double)rs.nrep * rs.n1 * rs.n2 * rs.n3 * prec_bytes(t->sum_prec) +
+                          (double)rs.nrep * rs.R * 8.0 * ((double)rs.n1 + rs.n2 + rs.n3);
+    const int rq = prof_begin(t, st);
+    if (plain) {
+      SBT_CK(launch_p2(t->sum_prec, rs, t->Z, t->At, t->Bt, t->M, st));
+      prof_end(t, rq, SBT_K_MTTKRP_AB, rbytes, st);
+      SBT_CK(launch_solve(rs, Kp, t->M, t->Gt, rs.sG, t->ones, 0, t->Ct, rs.sC, nullptr, nullptr,
+                          t->lam, 0, t->pinv, st));
+    } else {
+      // V^-1 = Gt^-1, then one launch: rows of C~ = (Z_(3) (Bt kr At)) Gt^-1 / lambda
+      SBT_CK(launch_inverse(rs, t->Gt, rs.sG, t->ones, 0, t->Vinv, t->pinv, st));
+      SBT_CK(launch_p3(t->sum_prec, rs, true, t->Z, t->At, nullptr, t->Bt, nullptr, t->Vinv,
+                       t->lam, t->Ct, rs.sC, st));
+      prof_end(t, rq, SBT_K_MTTKRP_AB, rbytes, st);
+    }
   }
   CommitArgs ca;
   ca.err = t->err;
@@ -832,6 +904,7 @@ sbt_status sbt_mttkrp_dense(int32_t precision, const void* Z_dev, int64_t n1, in
   rs.sW = n1 * n2 * R;
   rs.sM = 0;
   rs.sG = (int64_t)R * R;
+  rs.nsplit = 1;
   if (mode == 2) {
     if (!U0_dev || !U1_dev) return SBT_E_INVALID;
     SBT_CK(launch_p2(prec, rs, Z_dev, U0_dev, U1_dev, out_dev, st));

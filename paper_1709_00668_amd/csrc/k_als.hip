@@ -14,6 +14,7 @@
 // forms the new Gram matrix.
 #include "device_common.hpp"
 #include "kernels.hpp"
+#include "solve_device.hpp"
 
 namespace sbt {
 
@@ -235,9 +236,7 @@ constexpr int kP2BChunk = 64;
 
 template <typename TZ, typename TA, int RP, bool kNorm>
 __device__ void p2_body(const TZ* Zc, int n1, int n2, int R, const double* Af, const double* Bf,
-                        double* out_row, double* nrm_out) {
-  __shared__ TA Bs[kP2BChunk][RP];
-  __shared__ TA red[4][RP + 1];
+                        double* out_row, double* nrm_out, TA* Bs, TA (*red)[kMaxRank + 1]) {
   const int tid = threadIdx.x;
   const int nsub = n1 >= 256 ? 1 : 256 / n1;
   const int span = n1 >= 256 ? 256 : n1;  // a values covered per chunk
@@ -259,7 +258,7 @@ __device__ void p2_body(const TZ* Zc, int n1, int n2, int R, const double* Af, c
       __syncthreads();
       for (int q = tid; q < kP2BChunk * RP; q += 256) {
         const int bb = q / RP, f = q % RP;
-        Bs[bb][f] = (bb < bn && f < R) ? (TA)Bf[(int64_t)(b0 + bb) * R + f] : (TA)0;
+        Bs[bb * RP + f] = (bb < bn && f < R) ? (TA)Bf[(int64_t)(b0 + bb) * R + f] : (TA)0;
       }
       __syncthreads();
       if (ok) {
@@ -269,7 +268,7 @@ __device__ void p2_body(const TZ* Zc, int n1, int n2, int R, const double* Af, c
           const TA z = ldz(zp + (int64_t)n1 * bb);
           if (kNorm) nacc += z * z;
 #pragma unroll
-          for (int f = 0; f < RP; ++f) acc[f] += z * Bs[bb][f];
+          for (int f = 0; f < RP; ++f) acc[f] += z * Bs[bb * RP + f];
         }
       }
     }
@@ -287,22 +286,30 @@ __device__ void p2_body(const TZ* Zc, int n1, int n2, int R, const double* Af, c
   }
   if (kNorm) {
     const TA v = wave_sum(nacc);
-    if (lane_id() == 0) red[wave][RP] = v;
+    if (lane_id() == 0) red[wave][kMaxRank] = v;
   }
   __syncthreads();
   if (tid < R) out_row[tid] = (double)(red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid]);
-  if (kNorm && tid == 0) *nrm_out = (double)(red[0][RP] + red[1][RP] + red[2][RP] + red[3][RP]);
+  if (kNorm && tid == 0)
+    *nrm_out = (double)(red[0][kMaxRank] + red[1][kMaxRank] + red[2][kMaxRank] + red[3][kMaxRank]);
 }
+
+struct P2Smem {
+  double Bs[kP2BChunk * kMaxRank];
+  double red[4][kMaxRank + 1];
+};
 
 template <typename TZ, int RP>
 __global__ __launch_bounds__(256) void p2_kernel(RepSet rs, const TZ* Z, const double* Af,
                                                 const double* Bf, double* M) {
   using TA = typename AccOf<TZ>::type;
+  __shared__ P2Smem sm;
   const int rep = rs.rep0 + blockIdx.y;
   const int c = blockIdx.x;
   const int64_t n12 = (int64_t)rs.n1 * rs.n2;
   p2_body<TZ, TA, RP, false>(Z + rep * rs.sZ + n12 * c, rs.n1, rs.n2, rs.R, Af + rep * rs.sA,
-                             Bf + rep * rs.sB, M + rep * rs.sM + (int64_t)c * rs.R, nullptr);
+                             Bf + rep * rs.sB, M + rep * rs.sM + (int64_t)c * rs.R, nullptr,
+                             (TA*)sm.Bs, (TA(*)[kMaxRank + 1])sm.red);
 }
 
 // Full-tensor pass for the fit: FP64 accumulation whatever the storage type.
@@ -310,188 +317,17 @@ template <typename TZ, int RP>
 __global__ __launch_bounds__(256) void fit_slices_kernel(const TZ* X, int64_t I, int64_t J,
                                                         int R, const double* A, const double* B,
                                                         double* M3, double* nrm) {
+  __shared__ P2Smem sm;
   const int64_t k = blockIdx.x;
-  p2_body<TZ, double, RP, true>(X + I * J * k, (int)I, (int)J, R, A, B, M3 + k * R, nrm + k);
+  p2_body<TZ, double, RP, true>(X + I * J * k, (int)I, (int)J, R, A, B, M3 + k * R, nrm + k,
+                                sm.Bs, sm.red);
 }
 
-// ---------------------------------------------------------------------------
-// Normal-equation solve U = M (G1 .* G2)^-1, one block per repetition.
-// ---------------------------------------------------------------------------
+// Stand-alone solve (one block per repetition).
 template <int RP>
-__device__ void jacobi_pinv(double (*V)[RP + 1], double (*P)[RP + 1], double (*Q)[RP + 1],
-                            int R) {
-  // cyclic Jacobi eigen-decomposition of the symmetric V (destroyed), P = pinv
-  for (int i = 0; i < R; ++i)
-    for (int j = 0; j < R; ++j) Q[i][j] = (i == j) ? 1.0 : 0.0;
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    double off = 0.0, dia = 0.0;
-    for (int i = 0; i < R; ++i) {
-      dia += V[i][i] * V[i][i];
-      for (int j = i + 1; j < R; ++j) off += V[i][j] * V[i][j];
-    }
-    if (off <= 1e-32 * dia || off == 0.0) break;
-    for (int p = 0; p < R; ++p)
-      for (int q = p + 1; q < R; ++q) {
-        const double apq = V[p][q];
-        if (apq == 0.0) continue;
-        const double theta = (V[q][q] - V[p][p]) / (2.0 * apq);
-        const double tt = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-        const double c = 1.0 / sqrt(tt * tt + 1.0), s = tt * c;
-        for (int k = 0; k < R; ++k) {  // columns p, q
-          const double vkp = V[k][p], vkq = V[k][q];
-          V[k][p] = c * vkp - s * vkq;
-          V[k][q] = s * vkp + c * vkq;
-        }
-        for (int k = 0; k < R; ++k) {  // rows p, q
-          const double vpk = V[p][k], vqk = V[q][k];
-          V[p][k] = c * vpk - s * vqk;
-          V[q][k] = s * vpk + c * vqk;
-        }
-        for (int k = 0; k < R; ++k) {
-          const double qkp = Q[k][p], qkq = Q[k][q];
-          Q[k][p] = c * qkp - s * qkq;
-          Q[k][q] = s * qkp + c * qkq;
-        }
-      }
-  }
-  double emax = 0.0;
-  for (int i = 0; i < R; ++i) emax = fmax(emax, fabs(V[i][i]));
-  const double cut = (double)R * 2.220446049250313e-16 * emax;
-  for (int i = 0; i < R; ++i)
-    for (int j = 0; j < R; ++j) {
-      double s = 0.0;
-      for (int k = 0; k < R; ++k)
-        if (fabs(V[k][k]) > cut) s += Q[i][k] * Q[j][k] / V[k][k];
-      P[i][j] = s;
-    }
-}
-
-template <int RP>
-__global__ __launch_bounds__(256) void solve_kernel(RepSet rs, int rows, const double* M,
-                                                   const double* G1, int64_t sG1,
-                                                   const double* G2, int64_t sG2, double* U,
-                                                   int64_t sU,
-                                                   double* Gout, double* lam_out,
-                                                   const double* lam_div, int normalize,
-                                                   uint32_t* pinv_count) {
-  const int rep = rs.rep0 + blockIdx.x;
-  const int R = rs.R;
-  const int tid = threadIdx.x;
-  M += rep * rs.sM;
-  U += rep * sU;
-  G1 += rep * sG1;
-  G2 += rep * sG2;
-  __shared__ double V[RP][RP + 1], L[RP][RP + 1], Q[RP][RP + 1];
-  __shared__ double red[256];
-  __shared__ double lam_s[RP];
-  __shared__ int fail;
-  for (int q = tid; q < R * R; q += 256) V[q / R][q % R] = G1[q] * G2[q];
-  if (tid == 0) fail = 0;
-  __syncthreads();
-  // Cholesky V = L L^T, column by column
-  for (int j = 0; j < R; ++j) {
-    double d = V[j][j];
-    for (int k = 0; k < j; ++k) d -= L[j][k] * L[j][k];
-    if (!(d > 0.0)) {  // identical in every thread
-      if (tid == 0) fail = 1;
-      break;
-    }
-    const double ljj = sqrt(d);
-    if (tid > j && tid < R) {
-      double sacc = V[tid][j];
-      for (int k = 0; k < j; ++k) sacc -= L[tid][k] * L[j][k];
-      L[tid][j] = sacc / ljj;
-    }
-    if (tid == 0) L[j][j] = ljj;
-    __syncthreads();
-  }
-  __syncthreads();
-  const bool use_pinv = fail != 0;
-  if (use_pinv) {
-    // V is intact (only L was written); P overwrites L
-    if (tid == 0) {
-      jacobi_pinv<RP>(V, L, Q, R);
-      if (pinv_count) atomicAdd(pinv_count, 1u);
-    }
-    __syncthreads();
-  }
-  double sq[RP];
-#pragma unroll
-  for (int f = 0; f < RP; ++f) sq[f] = 0.0;
-  for (int i = tid; i < rows; i += 256) {
-    double m[RP], x[RP];
-#pragma unroll
-    for (int f = 0; f < RP; ++f) m[f] = f < R ? M[(int64_t)i * R + f] : 0.0;
-    if (!use_pinv) {
-#pragma unroll
-      for (int k = 0; k < RP; ++k) {  // forward: L y = m
-        if (k < R) {
-          double s = m[k];
-#pragma unroll
-          for (int j = 0; j < k; ++j) s -= L[k][j] * x[j];
-          x[k] = s / L[k][k];
-        } else {
-          x[k] = 0.0;
-        }
-      }
-#pragma unroll
-      for (int k = RP - 1; k >= 0; --k) {  // backward: L^T x = y
-        if (k < R) {
-          double s = x[k];
-#pragma unroll
-          for (int j = k + 1; j < RP; ++j)
-            if (j < R) s -= L[j][k] * x[j];
-          x[k] = s / L[k][k];
-        }
-      }
-    } else {
-#pragma unroll
-      for (int f = 0; f < RP; ++f) {
-        double s = 0.0;
-#pragma unroll
-        for (int k = 0; k < RP; ++k)
-          if (f < R && k < R) s += m[k] * L[k][f];
-        x[f] = s;
-      }
-    }
-    if (normalize) {
-#pragma unroll
-      for (int f = 0; f < RP; ++f) sq[f] += x[f] * x[f];
-#pragma unroll
-      for (int f = 0; f < RP; ++f)
-        if (f < R) U[(int64_t)i * R + f] = x[f];
-    } else {
-#pragma unroll
-      for (int f = 0; f < RP; ++f)
-        if (f < R) {
-          const double l = lam_div[f];
-          U[(int64_t)i * R + f] = l > 0.0 ? x[f] / l : 0.0;
-        }
-    }
-  }
-  if (!normalize) return;
-  // column norms -> lambda'
-  const int wave = tid >> 6;
-  __shared__ double wred[4][RP];
-#pragma unroll
-  for (int f = 0; f < RP; ++f) {
-    const double v = wave_sum(sq[f]);
-    if (lane_id() == 0) wred[wave][f] = v;
-  }
-  __syncthreads();
-  if (tid < R) {
-    const double l = sqrt(wred[0][tid] + wred[1][tid] + wred[2][tid] + wred[3][tid]);
-    lam_s[tid] = l;
-    lam_out[rep * R + tid] = l;
-  }
-  __syncthreads();
-  for (int i = tid; i < rows; i += 256) {
-#pragma unroll
-    for (int f = 0; f < RP; ++f)
-      if (f < R && lam_s[f] > 0.0) U[(int64_t)i * R + f] = U[(int64_t)i * R + f] / lam_s[f];
-  }
-  __syncthreads();
-  block_gram(U, rows, R, Gout + rep * rs.sG, red);
+__global__ __launch_bounds__(256) void solve_kernel(RepSet rs, int rows, SolveArgs sa) {
+  __shared__ SolveSmem sm;
+  block_solve<RP>(sa, rs.rep0 + blockIdx.x, rows, rs.R, sm);
 }
 
 }  // namespace
@@ -584,21 +420,35 @@ hipError_t launch_p2(int prec, const RepSet& rs, const void* Z, const double* Af
   return hipGetLastError();
 }
 
+static SolveArgs make_solve_args(const RepSet& rs, const double* M, const double* G1,
+                                 int64_t sG1, const double* G2, int64_t sG2, double* U,
+                                 int64_t sU, double* Gout, double* lam_out,
+                                 const double* lam_div, int normalize, uint32_t* pinv_count) {
+  SolveArgs a;
+  a.M = M;
+  a.sM = rs.sM;
+  a.G1 = G1;
+  a.sG1 = sG1;
+  a.G2 = G2;
+  a.sG2 = sG2;
+  a.U = U;
+  a.sU = sU;
+  a.Gout = Gout;
+  a.sGout = rs.sG;
+  a.lam_out = lam_out;
+  a.lam_div = lam_div;
+  a.normalize = normalize;
+  a.pinv_count = pinv_count;
+  return a;
+}
+
 hipError_t launch_solve(const RepSet& rs, int rows, const double* M, const double* G1,
                         int64_t sG1, const double* G2, int64_t sG2, double* U, int64_t sU,
-                        double* Gout,
-                        double* lam_out, const double* lam_div, int normalize,
+                        double* Gout, double* lam_out, const double* lam_div, int normalize,
                         uint32_t* pinv_count, hipStream_t s) {
-  const int rp = rs.R <= 8 ? 8 : (rs.R <= 16 ? 16 : 32);
-  if (rp == 8)
-    solve_kernel<8><<<rs.nrep, 256, 0, s>>>(rs, rows, M, G1, sG1, G2, sG2, U, sU, Gout, lam_out,
-                                            lam_div, normalize, pinv_count);
-  else if (rp == 16)
-    solve_kernel<16><<<rs.nrep, 256, 0, s>>>(rs, rows, M, G1, sG1, G2, sG2, U, sU, Gout, lam_out,
-                                             lam_div, normalize, pinv_count);
-  else
-    solve_kernel<32><<<rs.nrep, 256, 0, s>>>(rs, rows, M, G1, sG1, G2, sG2, U, sU, Gout, lam_out,
-                                             lam_div, normalize, pinv_count);
+  const SolveArgs a = make_solve_args(rs, M, G1, sG1, G2, sG2, U, sU, Gout, lam_out, lam_div,
+                                      normalize, pinv_count);
+  SBT_DISPATCH_RP(rs.R, { solve_kernel<RP><<<rs.nrep, 256, 0, s>>>(rs, rows, a); });
   return hipGetLastError();
 }
 

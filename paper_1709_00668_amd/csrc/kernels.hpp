@@ -24,7 +24,8 @@ struct RepSet {
   int rep0, nrep;   // repetitions [rep0, rep0 + nrep) of this launch
   int64_t sZ;       // summary elements
   int64_t sA, sB, sC;  // factor rows * R
-  int64_t sW;       // n1*n2*R (acc type)
+  int64_t sW;       // W workspace per repetition: nsplit_max * R * n1*n2 (acc type)
+  int nsplit;       // pass 1 splits the third mode into nsplit ranges (partial W)
   int64_t sM;       // max rows * R (double)
   int64_t sG;       // R*R
 };
@@ -100,6 +101,44 @@ hipError_t launch_solve(const RepSet& rs, int rows, const double* M, const doubl
                         double* Gout,
                         double* lam_out, const double* lam_div, int normalize,
                         uint32_t* pinv_count, hipStream_t s);
+
+// ---- batched CP-ALS (latency-oriented) ----------------------------------
+// Outputs of one mode update: raw rows U of the new factor, its normalised
+// Gram matrix, 1/lambda, optionally lambda, and V_next^-1 = (Gx .* Gy)^-1 for
+// the next step, all per repetition.
+struct AlsTail {
+  double* U;
+  int64_t sU;
+  int rows;
+  double* Gout;
+  double* invlam_out;
+  double* lam_out;
+  const double* Gx;
+  const double* Gy;
+  double* Vinv_out;
+  int64_t sG;
+  uint32_t* pinv_count;
+};
+// V^-1 = (Gx .* Gy)^-1 per repetition (pseudo-inverse when singular)
+hipError_t launch_inverse(const RepSet& rs, const double* Gx, int64_t sGx, const double* Gy,
+                          int64_t sGy, double* Vinv, uint32_t* pinv_count, hipStream_t s);
+// raw factors -> unit columns (multiplies by the stored 1/lambda of A, B, C)
+hipError_t launch_normalize(const RepSet& rs, double* Ap, double* Bp, double* Cp,
+                            const double* invlam, hipStream_t s);
+// W[rep][split][ab][f] = sum_{c in split} Z(ab, c) C(c, f) / lambda_C(f)
+hipError_t launch_pw(int prec, const RepSet& rs, const void* Z, const double* Cf,
+                     const double* invlamC, void* W, hipStream_t s);
+// mode 0: A rows = (W x_b B~) V^-1; mode 1: B rows = (W x_a A~) V^-1
+hipError_t launch_cw(int prec, const RepSet& rs, int mode, const void* W, const double* F,
+                     const double* invlamF, const double* Vinv, double* U, int64_t sU,
+                     hipStream_t s);
+// C rows = (Z_(3) (B~ kr A~)) V^-1, or with row_solve those rows / lam_div
+hipError_t launch_p3(int prec, const RepSet& rs, bool row_solve, const void* Z, const double* Af,
+                     const double* invlamA, const double* Bf, const double* invlamB,
+                     const double* Vinv, const double* lam_div, double* U, int64_t sU,
+                     hipStream_t s);
+// tail of a mode update: Gram, lambda, normalised Gram, next V^-1
+hipError_t launch_tail(const RepSet& rs, const AlsTail& t, hipStream_t s);
 
 // ---- matching, row solve inputs ------------------------------------------
 struct MatchArgs {
