@@ -205,7 +205,8 @@ typedef enum {
   SBT_K_MTTKRP_AB = 1,  /* MTTKRP pass producing third-mode rows (ALS + row solve) */
   SBT_K_GATHER = 2,     /* summary gather                                        */
   SBT_K_UPDATE = 3,     /* whole update, first to last kernel                   */
-  SBT_K_COUNT = 4
+  SBT_K_COO_MTTKRP = 4, /* sparse MTTKRP rows of one mode (ALS + row solve)      */
+  SBT_K_COUNT = 5
 } sbt_kernel_kind;
 
 sbt_status sbt_profile_enable(sbt_tensor* t, int32_t on);

@@ -56,14 +56,25 @@ struct sbt_tensor {
          *Vinv = nullptr, *invlam = nullptr;
   uint32_t* h_err = nullptr;  // pinned
   std::vector<void*> allocs;
+  // COO path
+  int64_t* koff = nullptr;        // slice offsets of the k-sorted store (Kcap + 1)
+  int64_t pending_nnz = 0;        // batch entries appended but not yet committed
+  int32_t *posI = nullptr, *posJ = nullptr, *posK = nullptr;
+  uint64_t *bitI = nullptr, *bitJ = nullptr, *bitK = nullptr;
+  uint32_t* bcount = nullptr;
+  int64_t* bbase = nullptr;
+  CooScratch ing{};               // ingest scratch (grown on demand)
+  CooSummary z{};                 // summaries (grown on demand)
+  std::vector<void*> grow_allocs; // freed when regrown or destroyed
+  int64_t last_summary_nnz = 0;
   // kernel timing (sbt_profile_*)
   bool prof_on = false;
   std::vector<hipEvent_t> prof_ev;     // pairs
   std::vector<int> prof_kind;          // per recorded pair
   std::vector<double> prof_bytes;      // per recorded pair
-  int64_t prof_n[SBT_K_COUNT] = {0, 0, 0, 0};
-  double prof_ms[SBT_K_COUNT] = {0, 0, 0, 0};
-  double prof_b[SBT_K_COUNT] = {0, 0, 0, 0};
+  int64_t prof_n[SBT_K_COUNT] = {};
+  double prof_ms[SBT_K_COUNT] = {};
+  double prof_b[SBT_K_COUNT] = {};
   // last update, for the inspection calls
   bool has_last = false;
   int last_n3old = 0, last_Kp = 0;
@@ -281,6 +292,33 @@ sbt_status alloc_state(sbt_tensor* t) {
   SBT_TRY(dalloc(t, &t->M3, (size_t)t->Kcap * R));
   SBT_TRY(dalloc(t, &t->nrm, (size_t)t->Kcap));
   SBT_TRY(dalloc(t, &t->fitv, 1));
+  if (t->fmt == SBT_COO) {
+    const int64_t nblk = coo_scan_blocks(t->nnz_cap);
+    SBT_TRY(dalloc(t, &t->koff, (size_t)t->Kcap + 1));
+    SBT_TRY(dalloc(t, &t->posI, (size_t)r * t->I));
+    SBT_TRY(dalloc(t, &t->posJ, (size_t)r * t->J));
+    SBT_TRY(dalloc(t, &t->posK, (size_t)r * t->Kcap));
+    SBT_TRY(dalloc(t, &t->bitI, (size_t)t->I));
+    SBT_TRY(dalloc(t, &t->bitJ, (size_t)t->J));
+    SBT_TRY(dalloc(t, &t->bitK, (size_t)t->Kcap));
+    SBT_TRY(dalloc(t, &t->bcount, (size_t)r * nblk));
+    SBT_TRY(dalloc(t, &t->bbase, (size_t)r * (nblk + 1)));
+    SBT_TRY(dalloc(t, &t->ing.hist, (size_t)t->Kcap));
+    CooSummary& z = t->z;
+    z.sHa = t->n1;
+    z.sHb = t->n2;
+    z.sHc = t->Kpmax;
+    z.sOffA = t->n1 + 1;
+    z.sOffB = t->n2 + 1;
+    z.sOffC = t->Kpmax + 1;
+    SBT_TRY(dalloc(t, &z.ha, (size_t)r * z.sHa));
+    SBT_TRY(dalloc(t, &z.hb, (size_t)r * z.sHb));
+    SBT_TRY(dalloc(t, &z.hc, (size_t)r * z.sHc));
+    SBT_TRY(dalloc(t, &z.offA, (size_t)r * z.sOffA));
+    SBT_TRY(dalloc(t, &z.offB, (size_t)r * z.sOffB));
+    SBT_TRY(dalloc(t, &z.offC, (size_t)r * z.sOffC));
+    SBT_TRY(dalloc(t, &z.rep_off, 65));
+  }
   void* h = nullptr;
   hipError_t e = hipHostMalloc(&h, 64, hipHostMallocDefault);
   if (e != hipSuccess) {
@@ -288,6 +326,160 @@ sbt_status alloc_state(sbt_tensor* t) {
     return SBT_E_NOMEM;
   }
   t->h_err = (uint32_t*)h;
+  return SBT_OK;
+}
+
+// Grown-on-demand buffers (ingest scratch, summaries).
+template <typename T>
+sbt_status galloc(sbt_tensor* t, T** p, size_t count) {
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, (count ? count : 1) * sizeof(T));
+  if (e != hipSuccess) {
+    set_err(t, std::string("hipMalloc: ") + hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? SBT_E_NOMEM : SBT_E_DEVICE;
+  }
+  t->grow_allocs.push_back(q);
+  *p = (T*)q;
+  return SBT_OK;
+}
+
+void gfree(sbt_tensor* t, void* p) {
+  for (size_t q = 0; q < t->grow_allocs.size(); ++q)
+    if (t->grow_allocs[q] == p) {
+      (void)hipFree(p);
+      t->grow_allocs.erase(t->grow_allocs.begin() + (long)q);
+      return;
+    }
+}
+
+sbt_status ensure_ingest(sbt_tensor* t, int64_t n, hipStream_t st) {
+  CooScratch& w = t->ing;
+  if (n <= w.cap) return SBT_OK;
+  SBT_CK(hipStreamSynchronize(st));
+  gfree(t, w.key_in);
+  gfree(t, w.key_out);
+  gfree(t, w.val_in);
+  gfree(t, w.val_out);
+  gfree(t, w.tmp);
+  const int64_t cap = n + n / 4 + 1024;
+  SBT_TRY(galloc(t, &w.key_in, (size_t)cap));
+  SBT_TRY(galloc(t, &w.key_out, (size_t)cap));
+  SBT_TRY(galloc(t, &w.val_in, (size_t)cap));
+  SBT_TRY(galloc(t, &w.val_out, (size_t)cap));
+  SBT_CK(coo_sort_tmp_bytes(cap, &w.tmp_bytes));
+  SBT_TRY(galloc(t, (char**)&w.tmp, w.tmp_bytes));
+  w.cap = cap;
+  return SBT_OK;
+}
+
+sbt_status ensure_summary(sbt_tensor* t, int64_t n, hipStream_t st) {
+  CooSummary& z = t->z;
+  if (n <= z.cap) return SBT_OK;
+  SBT_CK(hipStreamSynchronize(st));
+  void* olds[] = {z.a, z.b, z.c, z.v, z.a_x, z.a_y, z.a_v, z.b_x, z.b_y, z.b_v,
+                  z.key_a, z.key_b, z.key_out, z.val, z.perm, z.tmp};
+  for (void* p : olds) gfree(t, p);
+  const int64_t cap = n + n / 4 + 4096;
+  SBT_TRY(galloc(t, &z.a, (size_t)cap));
+  SBT_TRY(galloc(t, &z.b, (size_t)cap));
+  SBT_TRY(galloc(t, &z.c, (size_t)cap));
+  SBT_TRY(galloc(t, &z.v, (size_t)cap));
+  SBT_TRY(galloc(t, &z.a_x, (size_t)cap));
+  SBT_TRY(galloc(t, &z.a_y, (size_t)cap));
+  SBT_TRY(galloc(t, &z.a_v, (size_t)cap));
+  SBT_TRY(galloc(t, &z.b_x, (size_t)cap));
+  SBT_TRY(galloc(t, &z.b_y, (size_t)cap));
+  SBT_TRY(galloc(t, &z.b_v, (size_t)cap));
+  SBT_TRY(galloc(t, &z.key_a, (size_t)cap));
+  SBT_TRY(galloc(t, &z.key_b, (size_t)cap));
+  SBT_TRY(galloc(t, &z.key_out, (size_t)cap));
+  SBT_TRY(galloc(t, &z.val, (size_t)cap));
+  SBT_TRY(galloc(t, &z.perm, (size_t)cap));
+  SBT_CK(coo_sort_tmp_bytes(cap, &z.tmp_bytes));
+  SBT_TRY(galloc(t, (char**)&z.tmp, z.tmp_bytes));
+  z.cap = cap;
+  return SBT_OK;
+}
+
+// Build the r COO summaries of an update: position maps and masks, count,
+// per repetition offsets, emit (sorted by c), row offsets, sorted copies.
+sbt_status coo_build_summaries(sbt_tensor* t, int64_t Kold, int n3old, int Kp, hipStream_t st) {
+  const int r = t->cfg.repetitions;
+  const int64_t offJ = t->n1, offK = (int64_t)t->n1 + t->n2;
+  const int64_t nnz_all = t->nnz + t->pending_nnz;
+  SBT_CK(launch_coo_maps(t->idx, t->idx_stride, offJ, offK, t->n1, t->n2, n3old, r, t->posI,
+                         t->posJ, t->posK, t->I, t->J, t->Kcap, t->bitI, t->bitJ, t->bitK, st));
+  SBT_CK(launch_coo_count(t->ci, t->cj, t->ck, nnz_all, t->bitI, t->bitJ, t->bitK, Kold, r,
+                          t->bcount, t->bbase, st));
+  const int64_t nblk = coo_scan_blocks(nnz_all);
+  std::vector<int64_t> tot((size_t)r);
+  for (int q = 0; q < r; ++q)
+    SBT_CK(hipMemcpyAsync(&tot[(size_t)q], t->bbase + (int64_t)q * (nblk + 1) + nblk, 8,
+                          hipMemcpyDeviceToHost, st));
+  SBT_CK(hipStreamSynchronize(st));
+  CooSummary& z = t->z;
+  z.rep_off_h[0] = 0;
+  for (int q = 0; q < r; ++q) z.rep_off_h[q + 1] = z.rep_off_h[q] + tot[(size_t)q];
+  const int64_t total = z.rep_off_h[r];
+  t->last_summary_nnz = total;
+  SBT_TRY(ensure_summary(t, total, st));
+  SBT_CK(hipMemcpyAsync(z.rep_off, z.rep_off_h, sizeof(int64_t) * (r + 1), hipMemcpyHostToDevice,
+                        st));
+  SBT_CK(launch_fill_u32(z.ha, (int64_t)r * z.sHa, 0, st));
+  SBT_CK(launch_fill_u32(z.hb, (int64_t)r * z.sHb, 0, st));
+  SBT_CK(launch_fill_u32(z.hc, (int64_t)r * z.sHc, 0, st));
+  const int gq = prof_begin(t, st);
+  SBT_CK(launch_coo_emit(t->ci, t->cj, t->ck, t->cv, nnz_all, t->bitI, t->bitJ, t->bitK, Kold,
+                         n3old, r, t->posI, t->posJ, t->posK, t->I, t->J, t->Kcap, t->bbase, z,
+                         st));
+  prof_end(t, gq, SBT_K_GATHER, (double)nnz_all * 16.0 + (double)total * 16.0, st);
+  SBT_CK(launch_coo_offsets(z, r, t->n1, t->n2, Kp, st));
+  SBT_CK(launch_coo_sorts(z, r, total, st));
+  return SBT_OK;
+}
+
+// CP-ALS on the r COO summaries: one row-producing MTTKRP launch and one tail
+// per mode update.
+sbt_status run_als_coo(sbt_tensor* t, RepSet rs, uint32_t t_ctr, hipStream_t st) {
+  const int R = rs.R;
+  double* ilA = t->invlam;
+  double* ilB = t->invlam + R;
+  double* ilC = t->invlam + 2 * R;
+  SBT_CK(launch_als_init(rs, t->cfg.seed, t->cfg.tensor_id, kStreamAlsInit, t_ctr, t->Bp, t->Cp,
+                         st));
+  SBT_CK(launch_gram(rs, t->Bp, rs.sB, rs.n2, t->GB, st));
+  SBT_CK(launch_gram(rs, t->Cp, rs.sC, rs.n3, t->GC, st));
+  SBT_CK(launch_fill_f64(t->invlam + (int64_t)rs.rep0 * 3 * R, (int64_t)rs.nrep * 3 * R, 1.0,
+                         st));
+  SBT_CK(launch_inverse(rs, t->GB, rs.sG, t->GC, rs.sG, t->Vinv, t->pinv, st));
+  const double ebytes = (double)t->last_summary_nnz * 12.0;
+  AlsTail ta;
+  ta.sG = rs.sG;
+  ta.pinv_count = t->pinv;
+  for (int it = 0; it < t->cfg.als_iters; ++it) {
+    int pq = prof_begin(t, st);
+    SBT_CK(launch_coo_rows(rs, 0, t->z, t->Bp, rs.sB, ilB, t->Cp, rs.sC, ilC, t->Vinv, nullptr,
+                           t->Ap, rs.sA, st));
+    prof_end(t, pq, SBT_K_COO_MTTKRP, ebytes, st);
+    ta.U = t->Ap; ta.sU = rs.sA; ta.rows = rs.n1; ta.Gout = t->GA; ta.invlam_out = ilA;
+    ta.lam_out = nullptr; ta.Gx = t->GA; ta.Gy = t->GC; ta.Vinv_out = t->Vinv;
+    SBT_CK(launch_tail(rs, ta, st));
+    pq = prof_begin(t, st);
+    SBT_CK(launch_coo_rows(rs, 1, t->z, t->Ap, rs.sA, ilA, t->Cp, rs.sC, ilC, t->Vinv, nullptr,
+                           t->Bp, rs.sB, st));
+    prof_end(t, pq, SBT_K_COO_MTTKRP, ebytes, st);
+    ta.U = t->Bp; ta.sU = rs.sB; ta.rows = rs.n2; ta.Gout = t->GB; ta.invlam_out = ilB;
+    ta.lam_out = nullptr; ta.Gx = t->GA; ta.Gy = t->GB; ta.Vinv_out = t->Vinv;
+    SBT_CK(launch_tail(rs, ta, st));
+    pq = prof_begin(t, st);
+    SBT_CK(launch_coo_rows(rs, 2, t->z, t->Ap, rs.sA, ilA, t->Bp, rs.sB, ilB, t->Vinv, nullptr,
+                           t->Cp, rs.sC, st));
+    prof_end(t, pq, SBT_K_COO_MTTKRP, ebytes, st);
+    ta.U = t->Cp; ta.sU = rs.sC; ta.rows = rs.n3; ta.Gout = t->GC; ta.invlam_out = ilC;
+    ta.lam_out = t->lamp; ta.Gx = t->GB; ta.Gy = t->GC; ta.Vinv_out = t->Vinv;
+    SBT_CK(launch_tail(rs, ta, st));
+  }
+  SBT_CK(launch_normalize(rs, t->Ap, t->Bp, t->Cp, t->invlam, st));
   return SBT_OK;
 }
 
@@ -469,6 +661,8 @@ sbt_status init_common(sbt_tensor* t, const double* A0, const double* B0, const 
 }
 
 void free_all(sbt_tensor* t) {
+  for (void* p : t->grow_allocs) (void)hipFree(p);
+  t->grow_allocs.clear();
   for (hipEvent_t e : t->prof_ev) (void)hipEventDestroy(e);
   t->prof_ev.clear();
   for (void* p : t->allocs) (void)hipFree(p);
@@ -529,13 +723,19 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
              (double)r * t->n1 * t->n2 * Kp *
                  (prec_bytes(t->store_prec) + prec_bytes(t->sum_prec)),
              st);
+  } else {
+    SBT_TRY(coo_build_summaries(t, Kold, n3old, Kp, st));
   }
-  const int nchunks = plain ? r : 1;
+  const bool coo = t->fmt == SBT_COO;
+  const int nchunks = (plain && !coo) ? r : 1;
   for (int q = 0; q < nchunks; ++q) {
-    RepSet rs = plain ? make_repset(t, Kp, q, 1) : all;
-    SBT_TRY(run_als(t, t->Z, rs, t->Ap, t->Bp, t->Cp, t->GA, t->GB, t->GC, t->lamp, t->W, t->M,
-                    t->Vinv, t->invlam,
-                    kStreamAlsInit, t->t, c.als_iters, plain, st));
+    RepSet rs = (plain && !coo) ? make_repset(t, Kp, q, 1) : all;
+    if (coo) {
+      SBT_TRY(run_als_coo(t, rs, t->t, st));
+    } else {
+      SBT_TRY(run_als(t, t->Z, rs, t->Ap, t->Bp, t->Cp, t->GA, t->GB, t->GC, t->lamp, t->W,
+                      t->M, t->Vinv, t->invlam, kStreamAlsInit, t->t, c.als_iters, plain, st));
+    }
     MatchArgs ma;
     ma.A = t->A;
     ma.B = t->B;
@@ -559,7 +759,12 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
     const double rbytes = (double)rs.nrep * rs.n1 * rs.n2 * rs.n3 * prec_bytes(t->sum_prec) +
                           (double)rs.nrep * rs.R * 8.0 * ((double)rs.n1 + rs.n2 + rs.n3);
     const int rq = prof_begin(t, st);
-    if (plain) {
+    if (coo) {
+      SBT_CK(launch_inverse(rs, t->Gt, rs.sG, t->ones, 0, t->Vinv, t->pinv, st));
+      SBT_CK(launch_coo_rows(rs, 2, t->z, t->At, rs.sA, nullptr, t->Bt, rs.sB, nullptr, t->Vinv,
+                             t->lam, t->Ct, rs.sC, st));
+      prof_end(t, rq, SBT_K_COO_MTTKRP, (double)t->last_summary_nnz * 12.0, st);
+    } else if (plain) {
       SBT_CK(launch_p2(t->sum_prec, rs, t->Z, t->At, t->Bt, t->M, st));
       prof_end(t, rq, SBT_K_MTTKRP_AB, rbytes, st);
       SBT_CK(launch_solve(rs, Kp, t->M, t->Gt, rs.sG, t->ones, 0, t->Ct, rs.sC, nullptr, nullptr,
@@ -610,12 +815,15 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
   SBT_CK(hipStreamSynchronize(st));
   prof_collect(t);
   if (*t->h_err) {
+    t->pending_nnz = 0;
     set_err(t, (*t->h_err & 2u) ? "batch coordinate outside the tensor"
                                 : "batch holds a non-finite value or overflows the importance sums");
     return (*t->h_err & 2u) ? SBT_E_SHAPE : SBT_E_NUMERIC;
   }
   t->K = Kold + Kn;
   t->t += 1;
+  t->nnz += t->pending_nnz;
+  t->pending_nnz = 0;
   t->has_last = true;
   t->last_n3old = n3old;
   t->last_Kp = Kp;
@@ -717,10 +925,93 @@ sbt_status sbt_init_coo(const sbt_config* cfg, const int32_t* i_dev, const int32
                         int64_t J, int64_t K0, const double* A0, const double* B0,
                         const double* C0, const double* lambda0, void* stream,
                         sbt_tensor** out) {
-  (void)cfg; (void)i_dev; (void)j_dev; (void)k_dev; (void)v_dev; (void)nnz; (void)I; (void)J;
-  (void)K0; (void)A0; (void)B0; (void)C0; (void)lambda0; (void)stream;
-  if (out) *out = nullptr;
-  return SBT_E_STATE;
+  if (!out) return SBT_E_INVALID;
+  *out = nullptr;
+  std::string why;
+  if (validate_config(cfg, why) != SBT_OK) return SBT_E_INVALID;
+  if (cfg->format != SBT_COO) return SBT_E_INVALID;
+  if (cfg->repetitions > 64) return SBT_E_INVALID;  // per index repetition bitmasks
+  // the initial decomposition of a COO tensor is given by the caller
+  if (!A0 || !B0 || !C0 || !lambda0) return SBT_E_INVALID;
+  if (nnz < 0 || (nnz > 0 && (!i_dev || !j_dev || !k_dev || !v_dev))) return SBT_E_INVALID;
+  if (I < 1 || J < 1 || K0 < 1 || I > INT32_MAX || J > INT32_MAX) return SBT_E_SHAPE;
+  if (cfg->k_capacity < K0 + 1 || cfg->k_capacity > INT32_MAX) return SBT_E_SHAPE;
+  if (cfg->nnz_capacity < nnz || cfg->nnz_capacity > INT32_MAX) return SBT_E_SHAPE;
+  sbt_tensor* t = new (std::nothrow) sbt_tensor();
+  if (!t) return SBT_E_NOMEM;
+  t->cfg = *cfg;
+  t->I = I;
+  t->J = J;
+  t->K = K0;
+  t->Kcap = cfg->k_capacity;
+  t->R = cfg->rank;
+  t->fmt = SBT_COO;
+  t->store_prec = kF32;
+  t->sum_prec = kF32;
+  t->nnz_cap = cfg->nnz_capacity;
+  int64_t nm = J * t->Kcap;
+  if (I * t->Kcap > nm) nm = I * t->Kcap;
+  if (I * J > nm) nm = I * J;
+  if (t->nnz_cap < nm) nm = t->nnz_cap;
+  t->nmax = (uint64_t)(nm < 1 ? 1 : nm);
+  hipStream_t st = (hipStream_t)stream;
+  sbt_status s = dalloc(t, &t->ci, (size_t)t->nnz_cap);
+  if (s == SBT_OK) s = dalloc(t, &t->cj, (size_t)t->nnz_cap);
+  if (s == SBT_OK) s = dalloc(t, &t->ck, (size_t)t->nnz_cap);
+  if (s == SBT_OK) s = dalloc(t, &t->cv, (size_t)t->nnz_cap);
+  if (s == SBT_OK) s = alloc_state(t);
+  // summary rows are sorted under 24-bit keys (repetition in the high bits)
+  if (s == SBT_OK && (t->n1 >= (1 << 24) || t->n2 >= (1 << 24))) {
+    set_err(t, "sampled rows per mode must stay below 2^24");
+    s = SBT_E_SHAPE;
+  }
+  if (s == SBT_OK) {
+    hipError_t e = launch_maxsq_coo(v_dev, nnz, t->bits, st);
+    if (e != hipSuccess) {
+      set_err(t, hipGetErrorString(e));
+      s = SBT_E_DEVICE;
+    }
+  }
+  if (s == SBT_OK) s = set_scale(t, st);
+  if (s == SBT_OK) {
+    hipError_t e = launch_fill_u64(t->w1, I, 0, st);
+    if (e == hipSuccess) e = launch_fill_u64(t->w2, J, 0, st);
+    if (e == hipSuccess) e = launch_fill_u64(t->w3, K0, 0, st);
+    if (e == hipSuccess) e = launch_fill_u32(t->err, 1, 0, st);
+    if (e == hipSuccess)
+      e = launch_moi_coo(i_dev, j_dev, k_dev, v_dev, nnz, I, J, K0, t->scale, t->qmax, t->w1,
+                         t->w2, t->w3, t->err, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(t->h_err, t->err, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      set_err(t, hipGetErrorString(e));
+      s = SBT_E_DEVICE;
+    } else if (*t->h_err) {
+      set_err(t, (*t->h_err & 2u) ? "coordinate outside the tensor"
+                                  : "non-finite value or importance overflow");
+      s = (*t->h_err & 2u) ? SBT_E_SHAPE : SBT_E_NUMERIC;
+    }
+  }
+  if (s == SBT_OK) s = ensure_ingest(t, nnz, st);
+  if (s == SBT_OK) {
+    hipError_t e = launch_fill_u64((uint64_t*)t->koff, 1, 0, st);
+    if (e == hipSuccess)
+      e = launch_coo_ingest(i_dev, j_dev, k_dev, v_dev, nnz, K0, 0, t->ci, t->cj, t->ck, t->cv, 0,
+                            t->koff, t->ing, st);
+    if (e != hipSuccess) {
+      set_err(t, hipGetErrorString(e));
+      s = SBT_E_DEVICE;
+    }
+    t->nnz = nnz;
+  }
+  if (s == SBT_OK) s = init_common(t, A0, B0, C0, lambda0, st);
+  if (s != SBT_OK) {
+    free_all(t);
+    delete t;
+    return s;
+  }
+  *out = t;
+  return SBT_OK;
 }
 
 void sbt_destroy(sbt_tensor* t) {
@@ -759,10 +1050,39 @@ sbt_status sbt_update_batch_dense(sbt_tensor* t, const void* Y_dev, int64_t K_ne
 sbt_status sbt_update_batch_coo(sbt_tensor* t, const int32_t* i_dev, const int32_t* j_dev,
                                 const int32_t* k_dev, const float* v_dev, int64_t nnz,
                                 int64_t K_new, void* stream) {
-  (void)i_dev; (void)j_dev; (void)k_dev; (void)v_dev; (void)nnz; (void)K_new; (void)stream;
   if (!t) return SBT_E_INVALID;
-  set_err(t, "tensor is not COO");
-  return SBT_E_STATE;
+  if (t->fmt != SBT_COO) {
+    set_err(t, "tensor is not COO");
+    return SBT_E_STATE;
+  }
+  if (nnz < 0 || (nnz > 0 && (!i_dev || !j_dev || !k_dev || !v_dev))) return SBT_E_INVALID;
+  if (K_new < 1 || K_new > t->cfg.max_batch || t->K + K_new > t->Kcap ||
+      t->nnz + nnz > t->nnz_cap) {
+    set_err(t, "batch size outside 1..max_batch or capacity exceeded");
+    return SBT_E_SHAPE;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  const int uq = prof_begin(t, st);
+  SBT_CK(launch_fill_u64(t->dw1, t->I, 0, st));
+  SBT_CK(launch_fill_u64(t->dw2, t->J, 0, st));
+  SBT_CK(launch_fill_u64(t->dw3, K_new, 0, st));
+  SBT_CK(launch_fill_u32(t->err, 1, 0, st));
+  SBT_CK(launch_moi_coo(i_dev, j_dev, k_dev, v_dev, nnz, t->I, t->J, K_new, t->scale, t->qmax,
+                        t->dw1, t->dw2, t->dw3, t->err, st));
+  // coordinates are checked before the batch enters the store
+  SBT_CK(hipMemcpyAsync(t->h_err, t->err, 4, hipMemcpyDeviceToHost, st));
+  SBT_CK(hipStreamSynchronize(st));
+  if (*t->h_err) {
+    prof_collect(t);
+    set_err(t, (*t->h_err & 2u) ? "batch coordinate outside the tensor"
+                                : "batch holds a non-finite value or overflows the importance sums");
+    return (*t->h_err & 2u) ? SBT_E_SHAPE : SBT_E_NUMERIC;
+  }
+  SBT_TRY(ensure_ingest(t, nnz, st));
+  SBT_CK(launch_coo_ingest(i_dev, j_dev, k_dev, v_dev, nnz, K_new, t->K, t->ci, t->cj, t->ck,
+                           t->cv, t->nnz, t->koff, t->ing, st));
+  t->pending_nnz = nnz;
+  return update_body(t, K_new, uq, st);
 }
 
 sbt_status sbt_get_shape(const sbt_tensor* t, int64_t* I, int64_t* J, int64_t* K, int32_t* R) {
@@ -800,7 +1120,8 @@ sbt_status sbt_fit(sbt_tensor* t, double* fit, void* stream) {
     SBT_CK(launch_fit_slices(t->store_prec, t->X, t->I, t->J, t->K, t->R, t->A, t->B, t->M3,
                              t->nrm, st));
   } else {
-    return SBT_E_STATE;
+    SBT_CK(launch_fit_coo(t->ci, t->cj, t->cv, t->koff, t->K, t->R, t->A, t->B, t->M3, t->nrm,
+                          st));
   }
   SBT_CK(launch_fit_final(t->A, t->B, t->C, t->lam, t->M3, t->nrm, t->I, t->J, t->K, t->R,
                           t->fitv, st));

@@ -1,0 +1,536 @@
+// Sparse (COO) path of the SamBaTen update: ingest, summary gather, CP-ALS
+// MTTKRP on the summaries, fit.  Everything is deterministic: no floating
+// point atomics; integer counts only.
+//
+// Store: structure of arrays (i, j, k, v), kept sorted by the slice index k
+// (each batch is stably sorted by k on ingest; batches arrive in slice
+// order), with per-slice offsets koff.
+//
+// Summary of repetition rho = the stored entries with i in I_s, j in J_s and
+// k in K_s u new (Sec. 3.1), re-indexed to (a, b, c).  Emitted in store order,
+// it is sorted by c.  Modes 1 and 2 need the entries grouped by a and by b:
+// one stable radix sort of the keys (rho, a) and (rho, b) per update gives
+// those orders (the summaries stay fixed over all ALS sweeps).  Each mode's
+// MTTKRP is then one wavefront per output row over a contiguous segment.
+#include <hipcub/hipcub.hpp>
+
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace sbt {
+
+namespace {
+
+constexpr int kCooBlock = 256;
+constexpr int kCooPerThread = 16;                       // entries per thread in scans
+constexpr int kCooChunk = kCooBlock * kCooPerThread;    // entries per block in scans
+
+inline int grid_for(int64_t n, int per_block) {
+  int64_t b = (n + per_block - 1) / per_block;
+  return (int)(b < 1 ? 1 : b);
+}
+
+// --------------------------------------------------------------------------
+// ingest
+// --------------------------------------------------------------------------
+__global__ void iota_kernel(int32_t* p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = (int32_t)i;
+}
+
+__global__ void copy_u32_kernel(const int32_t* src, uint32_t* dst, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (uint32_t)src[i];
+}
+
+// store[base + p] = batch[perm[p]] with k shifted by koff0; slice histogram
+__global__ void coo_place_kernel(const int32_t* bi, const int32_t* bj, const int32_t* bk,
+                                 const float* bv, const int32_t* perm, int64_t n, int64_t knew,
+                                 int64_t kshift,
+                                 int32_t* si, int32_t* sj, int32_t* sk, float* sv, int64_t base,
+                                 uint32_t* khist) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t e = perm[p];
+    const int32_t k = bk[e];
+    si[base + p] = bi[e];
+    sj[base + p] = bj[e];
+    sk[base + p] = (int32_t)(k + kshift);
+    sv[base + p] = bv[e];
+    if (k >= 0 && k < knew) atomicAdd(&khist[k], 1u);
+  }
+}
+
+// Exclusive scan of cnt[0..n) (uint32) into out (int64) + add base; one block.
+__global__ __launch_bounds__(1024) void scan_to_offsets_kernel(const uint32_t* cnt, int64_t n,
+                                                              int64_t base, int64_t* out) {
+  __shared__ int64_t wsum[16];
+  __shared__ int64_t carry;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  if (tid == 0) carry = base;
+  __syncthreads();
+  for (int64_t c0 = 0; c0 < n; c0 += 1024) {
+    const int64_t i = c0 + tid;
+    int64_t v = i < n ? (int64_t)cnt[i] : 0;
+    // inclusive wave scan
+    int64_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int64_t y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    int64_t pre = carry;
+    for (int w = 0; w < wave; ++w) pre += wsum[w];
+    if (i < n) out[i] = pre + x - v;
+    __syncthreads();
+    if (tid == 0) {
+      int64_t t = 0;
+      for (int w = 0; w < 16; ++w) t += wsum[w];
+      carry += t;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) out[n] = carry;
+}
+
+// --------------------------------------------------------------------------
+// summaries
+// --------------------------------------------------------------------------
+// Per repetition position maps (-1 = not sampled) and per index bitmasks of
+// the repetitions that sample it (bit rho).
+__global__ void sample_maps_kernel(const int32_t* idx, int64_t idx_stride, int64_t offJ,
+                                   int64_t offK, int n1, int n2, int n3old, int nrep,
+                                   int32_t* posI, int32_t* posJ, int32_t* posK, int64_t I,
+                                   int64_t J, int64_t Kcap, uint64_t* bitI, uint64_t* bitJ,
+                                   uint64_t* bitK) {
+  const int rep = blockIdx.y;
+  const int32_t* s = idx + rep * idx_stride;
+  const int tot = n1 + n2 + n3old;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < tot; q += gridDim.x * blockDim.x) {
+    const uint64_t bit = 1ull << rep;
+    if (q < n1) {
+      const int32_t i = s[q];
+      posI[rep * I + i] = q;
+      atomicOr((unsigned long long*)&bitI[i], (unsigned long long)bit);
+    } else if (q < n1 + n2) {
+      const int32_t j = s[offJ + (q - n1)];
+      posJ[rep * J + j] = q - n1;
+      atomicOr((unsigned long long*)&bitJ[j], (unsigned long long)bit);
+    } else {
+      const int32_t k = s[offK + (q - n1 - n2)];
+      posK[rep * Kcap + k] = q - n1 - n2;
+      atomicOr((unsigned long long*)&bitK[k], (unsigned long long)bit);
+    }
+  }
+}
+
+__device__ inline uint64_t entry_mask(int32_t i, int32_t j, int32_t k, const uint64_t* bitI,
+                                      const uint64_t* bitJ, const uint64_t* bitK, int64_t Kold,
+                                      uint64_t all) {
+  const uint64_t mk = k < Kold ? bitK[k] : all;
+  return bitI[i] & bitJ[j] & mk;
+}
+
+// Count, per block of kCooChunk stored entries, how many each repetition keeps.
+__global__ __launch_bounds__(kCooBlock) void summary_count_kernel(
+    const int32_t* si, const int32_t* sj, const int32_t* sk, int64_t nnz, const uint64_t* bitI,
+    const uint64_t* bitJ, const uint64_t* bitK, int64_t Kold, int nrep, uint32_t* bcount,
+    int64_t nblk) {
+  __shared__ uint32_t cnt[64];
+  const int tid = threadIdx.x;
+  if (tid < 64) cnt[tid] = 0;
+  __syncthreads();
+  const uint64_t all = nrep >= 64 ? ~0ull : ((1ull << nrep) - 1);
+  const int64_t e0 = (int64_t)blockIdx.x * kCooChunk;
+  for (int u = 0; u < kCooPerThread; ++u) {
+    const int64_t e = e0 + u * kCooBlock + tid;
+    uint64_t m = 0;
+    if (e < nnz) m = entry_mask(si[e], sj[e], sk[e], bitI, bitJ, bitK, Kold, all);
+    while (m) {
+      const int rep = __ffsll((unsigned long long)m) - 1;
+      m &= m - 1;
+      atomicAdd(&cnt[rep], 1u);
+    }
+  }
+  __syncthreads();
+  if (tid < nrep) bcount[(int64_t)tid * nblk + blockIdx.x] = cnt[tid];
+}
+
+__device__ inline uint64_t lmask_lt() {
+  const int l = lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+// Emit the kept entries of every repetition in store order (hence sorted by
+// c) at bbase[rep][block] + the rank within the block, and count the a, b, c
+// histograms of each repetition.
+__global__ __launch_bounds__(kCooBlock) void summary_emit_kernel(
+    const int32_t* si, const int32_t* sj, const int32_t* sk, const float* sv, int64_t nnz,
+    const uint64_t* bitI, const uint64_t* bitJ, const uint64_t* bitK, int64_t Kold, int n3old,
+    int nrep, const int32_t* posI, const int32_t* posJ, const int32_t* posK, int64_t I,
+    int64_t J, int64_t Kcap, const int64_t* bbase, const int64_t* rep_off, int64_t nblk,
+    int32_t* za, int32_t* zb,
+    int32_t* zc, float* zv, uint32_t* ha, uint32_t* hb, uint32_t* hc, int64_t sHa,
+    int64_t sHb, int64_t sHc) {
+  __shared__ uint32_t wcnt[kCooBlock / 64][64];
+  __shared__ int64_t run[64];
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const uint64_t all = nrep >= 64 ? ~0ull : ((1ull << nrep) - 1);
+  __shared__ unsigned long long bm;
+  if (tid < 64) run[tid] = tid < nrep ? rep_off[tid] + bbase[(int64_t)tid * (nblk + 1) + blockIdx.x] : 0;
+  __syncthreads();
+  const int64_t e0 = (int64_t)blockIdx.x * kCooChunk;
+  for (int u = 0; u < kCooPerThread; ++u) {
+    const int64_t e = e0 + u * kCooBlock + tid;
+    int32_t i = 0, j = 0, k = 0;
+    float v = 0.0f;
+    uint64_t m = 0;
+    if (e < nnz) {
+      i = si[e];
+      j = sj[e];
+      k = sk[e];
+      v = sv[e];
+      m = entry_mask(i, j, k, bitI, bitJ, bitK, Kold, all);
+    }
+    // block-wide union of the masks decides which repetitions need a prefix
+    if (tid == 0) bm = 0ull;
+    __syncthreads();
+    if (m) atomicOr(&bm, (unsigned long long)m);
+    __syncthreads();
+    uint64_t reps = bm;
+    __syncthreads();
+    while (reps) {
+      const int rep = __ffsll((unsigned long long)reps) - 1;
+      reps &= reps - 1;
+      const bool keep = (m >> rep) & 1ull;
+      const uint64_t bal = __ballot(keep);
+      if ((tid & 63) == 0) wcnt[wave][rep] = (uint32_t)__popcll(bal);
+      __syncthreads();
+      int64_t pos = run[rep];
+      for (int w = 0; w < wave; ++w) pos += wcnt[w][rep];
+      pos += __popcll(bal & lmask_lt());
+      if (keep) {
+        const int a = posI[rep * I + i];
+        const int b = posJ[rep * J + j];
+        const int c = k < Kold ? posK[rep * Kcap + k] : n3old + (int)(k - Kold);
+        za[pos] = a;
+        zb[pos] = b;
+        zc[pos] = c;
+        zv[pos] = v;
+        atomicAdd(&ha[rep * sHa + a], 1u);
+        atomicAdd(&hb[rep * sHb + b], 1u);
+        atomicAdd(&hc[rep * sHc + c], 1u);
+      }
+      __syncthreads();
+      if (tid == 0) {
+        int64_t t = 0;
+        for (int w = 0; w < kCooBlock / 64; ++w) t += wcnt[w][rep];
+        run[rep] += t;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// keys (rep << 24 | row) for the stable sorts by a and by b
+__global__ void summary_keys_kernel(const int32_t* za, const int32_t* zb, const int64_t* rep_off,
+                                    int nrep, int64_t total, uint32_t* key_a, uint32_t* key_b,
+                                    int32_t* val) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    int rep = 0;
+    while (rep + 1 < nrep && rep_off[rep + 1] <= e) ++rep;
+    key_a[e] = ((uint32_t)rep << 24) | (uint32_t)za[e];
+    key_b[e] = ((uint32_t)rep << 24) | (uint32_t)zb[e];
+    val[e] = (int32_t)e;
+  }
+}
+
+// mode copies: entry p of the a-sorted copy holds (b, c, v) of perm[p]
+__global__ void summary_permute_kernel(const int32_t* perm, int64_t total, const int32_t* x0,
+                                       const int32_t* x1, const float* zv, int32_t* y0,
+                                       int32_t* y1, float* yv) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < total;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t e = perm[p];
+    y0[p] = x0[e];
+    y1[p] = x1[e];
+    yv[p] = zv[e];
+  }
+}
+
+// --------------------------------------------------------------------------
+// MTTKRP on a summary, one wavefront per output row, fused with V^-1
+// --------------------------------------------------------------------------
+// rows of mode `mode` of every repetition: entries [off[row], off[row+1]) of
+// the mode's copy hold (x, y, v) with x, y the indices of the two other modes
+// (ascending mode order).  M(row, f) = sum v * X~(x, f) * Y~(y, f);
+// U(row, :) = M(row, :) V^-1 (or divided by lam_div for the row solve).
+template <int RP>
+__global__ __launch_bounds__(256) void coo_rows_kernel(
+    RepSet rs, int mode, const int64_t* off, int64_t sOff, const int32_t* cx, const int32_t* cy,
+    const float* cv, const double* X, int64_t sX, const double* invlamX, const double* Y,
+    int64_t sY, const double* invlamY, const double* Vinv, const double* lam_div, double* U,
+    int64_t sU, int rows) {
+  __shared__ double Vi[4][kMaxRank][kMaxRank + 1];
+  const int R = rs.R;
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  const int64_t gw = (int64_t)blockIdx.x * 4 + wave;  // global wave index
+  const int rep = rs.rep0 + (int)(gw / rows);
+  const int row = (int)(gw % rows);
+  const bool active = rep < rs.rep0 + rs.nrep;
+  if (active)
+    for (int q = lane; q < R * R; q += 64) Vi[wave][q / R][q % R] = Vinv[rep * rs.sG + q];
+  __syncthreads();
+  if (!active) return;
+  const int64_t* o = off + rep * sOff;
+  const int64_t b0 = o[row], b1 = o[row + 1];
+  const double* Xr = X + rep * sX;
+  const double* Yr = Y + rep * sY;
+  double sx[RP], sy[RP];
+#pragma unroll
+  for (int f = 0; f < RP; ++f) {
+    sx[f] = (f < R && invlamX) ? invlamX[rep * 3 * R + f] : 1.0;
+    sy[f] = (f < R && invlamY) ? invlamY[rep * 3 * R + f] : 1.0;
+  }
+  float acc[RP];
+#pragma unroll
+  for (int f = 0; f < RP; ++f) acc[f] = 0.0f;
+  for (int64_t e = b0 + lane; e < b1; e += 64) {
+    const int32_t x = cx[e], y = cy[e];
+    const float v = cv[e];
+    const double* xr = Xr + (int64_t)x * R;
+    const double* yr = Yr + (int64_t)y * R;
+#pragma unroll
+    for (int f = 0; f < RP; ++f)
+      if (f < R) acc[f] += v * (float)(xr[f] * sx[f]) * (float)(yr[f] * sy[f]);
+  }
+  double m[RP];
+#pragma unroll
+  for (int f = 0; f < RP; ++f) m[f] = (double)wave_sum(acc[f]);
+  // lane f < R finishes column f of the row
+  double u = 0.0;
+#pragma unroll
+  for (int k = 0; k < RP; ++k)
+    if (k < R && lane < R) u += m[k] * Vi[wave][k][lane];
+  if (lane < R) {
+    if (lam_div) {
+      const double l = lam_div[lane];
+      u = l > 0.0 ? u / l : 0.0;
+    }
+    U[rep * sU + (int64_t)row * R + lane] = u;
+  }
+}
+
+// fit over a k-sorted COO store: one wavefront per slice
+template <int RP>
+__global__ __launch_bounds__(256) void coo_fit_kernel(const int32_t* si, const int32_t* sj,
+                                                     const float* sv, const int64_t* koff,
+                                                     int64_t K, int R, const double* A,
+                                                     const double* B, double* M3, double* nrm) {
+  const int wave = threadIdx.x >> 6, lane = lane_id();
+  const int64_t k = (int64_t)blockIdx.x * 4 + wave;
+  if (k >= K) return;
+  double acc[RP];
+#pragma unroll
+  for (int f = 0; f < RP; ++f) acc[f] = 0.0;
+  double n2 = 0.0;
+  for (int64_t e = koff[k] + lane; e < koff[k + 1]; e += 64) {
+    const double v = sv[e];
+    const double* ar = A + (int64_t)si[e] * R;
+    const double* br = B + (int64_t)sj[e] * R;
+    n2 += v * v;
+#pragma unroll
+    for (int f = 0; f < RP; ++f)
+      if (f < R) acc[f] += v * ar[f] * br[f];
+  }
+#pragma unroll
+  for (int f = 0; f < RP; ++f) {
+    const double s = wave_sum(acc[f]);
+    if (lane == 0 && f < R) M3[k * R + f] = s;
+  }
+  n2 = wave_sum(n2);
+  if (lane == 0) nrm[k] = n2;
+}
+
+inline int rp_of4(int R) { return ((R + 3) / 4) * 4; }
+
+#define SBT_COO_RP(Rv, ...)                                 \
+  switch (rp_of4(Rv)) {                                     \
+    case 4: { constexpr int RP = 4; __VA_ARGS__; } break;   \
+    case 8: { constexpr int RP = 8; __VA_ARGS__; } break;   \
+    case 12: { constexpr int RP = 12; __VA_ARGS__; } break; \
+    case 16: { constexpr int RP = 16; __VA_ARGS__; } break; \
+    case 20: { constexpr int RP = 20; __VA_ARGS__; } break; \
+    case 24: { constexpr int RP = 24; __VA_ARGS__; } break; \
+    case 28: { constexpr int RP = 28; __VA_ARGS__; } break; \
+    default: { constexpr int RP = 32; __VA_ARGS__; } break; \
+  }
+
+}  // namespace
+
+// ==========================================================================
+// launchers
+// ==========================================================================
+hipError_t coo_sort_tmp_bytes(int64_t n, size_t* bytes) {
+  size_t b = 0;
+  hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, b, (const uint32_t*)nullptr,
+                                                    (uint32_t*)nullptr, (const int32_t*)nullptr,
+                                                    (int32_t*)nullptr, (int)n, 0, 32, 0);
+  *bytes = b;
+  return e;
+}
+
+hipError_t launch_coo_ingest(const int32_t* bi, const int32_t* bj, const int32_t* bk,
+                             const float* bv, int64_t n, int64_t Knew, int64_t Kold,
+                             int32_t* si, int32_t* sj, int32_t* sk, float* sv, int64_t base,
+                             int64_t* koff, CooScratch& w, hipStream_t s) {
+  if (n <= 0) {
+    // no entries: every new slice is empty
+    hipError_t e = launch_fill_u32(w.hist, Knew, 0, s);
+    if (e != hipSuccess) return e;
+    scan_to_offsets_kernel<<<1, 1024, 0, s>>>(w.hist, Knew, base, koff + Kold);
+    return hipGetLastError();
+  }
+  hipError_t e;
+  int bits = 1;
+  while ((1ll << bits) < Knew) ++bits;
+  copy_u32_kernel<<<grid_for(n, 256 * 16), 256, 0, s>>>(bk, w.key_in, n);
+  iota_kernel<<<grid_for(n, 256 * 16), 256, 0, s>>>(w.val_in, n);
+  size_t tb = w.tmp_bytes;
+  e = hipcub::DeviceRadixSort::SortPairs(w.tmp, tb, w.key_in, w.key_out, w.val_in, w.val_out,
+                                         (int)n, 0, bits, s);
+  if (e != hipSuccess) return e;
+  e = launch_fill_u32(w.hist, Knew, 0, s);
+  if (e != hipSuccess) return e;
+  coo_place_kernel<<<grid_for(n, 256 * 16), 256, 0, s>>>(bi, bj, bk, bv, w.val_out, n, Knew, Kold, si,
+                                                          sj, sk, sv, base, w.hist);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  scan_to_offsets_kernel<<<1, 1024, 0, s>>>(w.hist, Knew, base, koff + Kold);
+  return hipGetLastError();
+}
+
+hipError_t launch_coo_maps(const int32_t* idx, int64_t idx_stride, int64_t offJ, int64_t offK,
+                           int n1, int n2, int n3old, int nrep, int32_t* posI, int32_t* posJ,
+                           int32_t* posK, int64_t I, int64_t J, int64_t Kcap, uint64_t* bitI,
+                           uint64_t* bitJ, uint64_t* bitK, hipStream_t s) {
+  hipError_t e = launch_fill_u32((uint32_t*)posI, (int64_t)nrep * I, 0xFFFFFFFFu, s);
+  if (e == hipSuccess) e = launch_fill_u32((uint32_t*)posJ, (int64_t)nrep * J, 0xFFFFFFFFu, s);
+  if (e == hipSuccess) e = launch_fill_u32((uint32_t*)posK, (int64_t)nrep * Kcap, 0xFFFFFFFFu, s);
+  if (e == hipSuccess) e = launch_fill_u64(bitI, I, 0, s);
+  if (e == hipSuccess) e = launch_fill_u64(bitJ, J, 0, s);
+  if (e == hipSuccess) e = launch_fill_u64(bitK, Kcap, 0, s);
+  if (e != hipSuccess) return e;
+  const int tot = n1 + n2 + n3old;
+  sample_maps_kernel<<<dim3((unsigned)grid_for(tot, 256), (unsigned)nrep), 256, 0, s>>>(
+      idx, idx_stride, offJ, offK, n1, n2, n3old, nrep, posI, posJ, posK, I, J, Kcap, bitI, bitJ,
+      bitK);
+  return hipGetLastError();
+}
+
+int64_t coo_scan_blocks(int64_t nnz) { return (nnz + kCooChunk - 1) / kCooChunk; }
+
+hipError_t launch_coo_count(const int32_t* si, const int32_t* sj, const int32_t* sk, int64_t nnz,
+                            const uint64_t* bitI, const uint64_t* bitJ, const uint64_t* bitK,
+                            int64_t Kold, int nrep, uint32_t* bcount, int64_t* bbase,
+                            hipStream_t s) {
+  const int64_t nblk = coo_scan_blocks(nnz);
+  summary_count_kernel<<<(unsigned)nblk, kCooBlock, 0, s>>>(si, sj, sk, nnz, bitI, bitJ, bitK,
+                                                            Kold, nrep, bcount, nblk);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // per repetition exclusive scan over blocks; repetition rho starts where
+  // rho - 1 ends, so bbase[rho][0] is the offset of rho's summary
+  for (int r = 0; r < nrep; ++r) {
+    scan_to_offsets_kernel<<<1, 1024, 0, s>>>(bcount + (int64_t)r * nblk, nblk, 0,
+                                              bbase + (int64_t)r * (nblk + 1));
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_coo_emit(const int32_t* si, const int32_t* sj, const int32_t* sk,
+                           const float* sv, int64_t nnz, const uint64_t* bitI,
+                           const uint64_t* bitJ, const uint64_t* bitK, int64_t Kold, int n3old,
+                           int nrep, const int32_t* posI, const int32_t* posJ,
+                           const int32_t* posK, int64_t I, int64_t J, int64_t Kcap,
+                           const int64_t* bbase, CooSummary& z, hipStream_t s) {
+  const int64_t nblk = coo_scan_blocks(nnz);
+  summary_emit_kernel<<<(unsigned)nblk, kCooBlock, 0, s>>>(
+      si, sj, sk, sv, nnz, bitI, bitJ, bitK, Kold, n3old, nrep, posI, posJ, posK, I, J, Kcap,
+      bbase, z.rep_off, nblk, z.a, z.b, z.c, z.v, z.ha, z.hb, z.hc, z.sHa, z.sHb, z.sHc);
+  return hipGetLastError();
+}
+
+hipError_t launch_coo_offsets(CooSummary& z, int nrep, int n1, int n2, int n3, hipStream_t s) {
+  for (int r = 0; r < nrep; ++r) {
+    const int64_t base = z.rep_off_h[r];
+    scan_to_offsets_kernel<<<1, 1024, 0, s>>>(z.ha + r * z.sHa, n1, base, z.offA + r * z.sOffA);
+    scan_to_offsets_kernel<<<1, 1024, 0, s>>>(z.hb + r * z.sHb, n2, base, z.offB + r * z.sOffB);
+    scan_to_offsets_kernel<<<1, 1024, 0, s>>>(z.hc + r * z.sHc, n3, base, z.offC + r * z.sOffC);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_coo_sorts(CooSummary& z, int nrep, int64_t total, hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  summary_keys_kernel<<<grid_for(total, 256 * 16), 256, 0, s>>>(z.a, z.b, z.rep_off, nrep, total,
+                                                                 z.key_a, z.key_b, z.val);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int bits = 24;
+  while ((1ll << (bits - 24)) < nrep) ++bits;
+  size_t tb = z.tmp_bytes;
+  e = hipcub::DeviceRadixSort::SortPairs(z.tmp, tb, z.key_a, z.key_out, z.val, z.perm, (int)total,
+                                         0, bits, s);
+  if (e != hipSuccess) return e;
+  summary_permute_kernel<<<grid_for(total, 256 * 16), 256, 0, s>>>(z.perm, total, z.b, z.c, z.v,
+                                                                    z.a_x, z.a_y, z.a_v);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  tb = z.tmp_bytes;
+  e = hipcub::DeviceRadixSort::SortPairs(z.tmp, tb, z.key_b, z.key_out, z.val, z.perm, (int)total,
+                                         0, bits, s);
+  if (e != hipSuccess) return e;
+  summary_permute_kernel<<<grid_for(total, 256 * 16), 256, 0, s>>>(z.perm, total, z.a, z.c, z.v,
+                                                                    z.b_x, z.b_y, z.b_v);
+  return hipGetLastError();
+}
+
+hipError_t launch_coo_rows(const RepSet& rs, int mode, const CooSummary& z, const double* X,
+                           int64_t sX, const double* invlamX, const double* Y, int64_t sY,
+                           const double* invlamY, const double* Vinv, const double* lam_div,
+                           double* U, int64_t sU, hipStream_t s) {
+  const int rows = mode == 0 ? rs.n1 : (mode == 1 ? rs.n2 : rs.n3);
+  const int64_t* off = mode == 0 ? z.offA : (mode == 1 ? z.offB : z.offC);
+  const int64_t sOff = mode == 0 ? z.sOffA : (mode == 1 ? z.sOffB : z.sOffC);
+  const int32_t* cx = mode == 0 ? z.a_x : (mode == 1 ? z.b_x : z.a);
+  const int32_t* cy = mode == 0 ? z.a_y : (mode == 1 ? z.b_y : z.b);
+  const float* cv = mode == 0 ? z.a_v : (mode == 1 ? z.b_v : z.v);
+  const int64_t waves = (int64_t)rows * rs.nrep;
+  const unsigned blocks = (unsigned)((waves + 3) / 4);
+  SBT_COO_RP(rs.R, {
+    coo_rows_kernel<RP><<<blocks, 256, 0, s>>>(rs, mode, off, sOff, cx, cy, cv, X, sX, invlamX, Y,
+                                              sY, invlamY, Vinv, lam_div, U, sU, rows);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_fit_coo(const int32_t* ii, const int32_t* jj, const float* v,
+                          const int64_t* koff, int64_t K, int R, const double* A,
+                          const double* B, double* M3, double* nrm, hipStream_t s) {
+  if (K <= 0) return hipSuccess;
+  SBT_COO_RP(R, {
+    coo_fit_kernel<RP><<<(unsigned)((K + 3) / 4), 256, 0, s>>>(ii, jj, v, koff, K, R, A, B, M3,
+                                                              nrm);
+  });
+  return hipGetLastError();
+}
+
+}  // namespace sbt

@@ -169,14 +169,75 @@ struct CommitArgs {
 };
 hipError_t launch_commit(const CommitArgs& c, hipStream_t s);
 
+// ---- sparse (COO) path ------------------------------------------------------
+struct CooScratch {   // ingest of one batch
+  uint32_t *key_in, *key_out;
+  int32_t *val_in, *val_out;
+  uint32_t* hist;
+  void* tmp;
+  size_t tmp_bytes;
+  int64_t cap;        // entries
+};
+struct CooSummary {   // the r summaries of one update, concatenated by repetition
+  int32_t *a, *b, *c;       // sorted by c
+  float* v;
+  int32_t *a_x, *a_y;       // sorted by a: (b, c)
+  float* a_v;
+  int32_t *b_x, *b_y;       // sorted by b: (a, c)
+  float* b_v;
+  uint32_t *ha, *hb, *hc;   // per repetition histograms of a, b, c
+  int64_t sHa, sHb, sHc;
+  int64_t *offA, *offB, *offC;  // per repetition row offsets (absolute)
+  int64_t sOffA, sOffB, sOffC;
+  int64_t* rep_off;         // device copy of rep_off_h (nrep + 1)
+  int64_t rep_off_h[65];
+  uint32_t *key_a, *key_b, *key_out;
+  int32_t *val, *perm;
+  void* tmp;
+  size_t tmp_bytes;
+  int64_t cap;              // entries allocated
+};
+hipError_t coo_sort_tmp_bytes(int64_t n, size_t* bytes);
+int64_t coo_scan_blocks(int64_t nnz);
+// append a batch (k batch-relative) sorted by k at store position `base`;
+// koff[Kold .. Kold + Knew] receives the slice offsets
+hipError_t launch_coo_ingest(const int32_t* bi, const int32_t* bj, const int32_t* bk,
+                             const float* bv, int64_t n, int64_t Knew, int64_t Kold,
+                             int32_t* si, int32_t* sj, int32_t* sk, float* sv, int64_t base,
+                             int64_t* koff, CooScratch& w, hipStream_t s);
+hipError_t launch_coo_maps(const int32_t* idx, int64_t idx_stride, int64_t offJ, int64_t offK,
+                           int n1, int n2, int n3old, int nrep, int32_t* posI, int32_t* posJ,
+                           int32_t* posK, int64_t I, int64_t J, int64_t Kcap, uint64_t* bitI,
+                           uint64_t* bitJ, uint64_t* bitK, hipStream_t s);
+// per block and repetition counts of kept entries, and per repetition
+// exclusive scans bbase[rep][0..nblk] (relative to the repetition's start)
+hipError_t launch_coo_count(const int32_t* si, const int32_t* sj, const int32_t* sk, int64_t nnz,
+                            const uint64_t* bitI, const uint64_t* bitJ, const uint64_t* bitK,
+                            int64_t Kold, int nrep, uint32_t* bcount, int64_t* bbase,
+                            hipStream_t s);
+hipError_t launch_coo_emit(const int32_t* si, const int32_t* sj, const int32_t* sk,
+                           const float* sv, int64_t nnz, const uint64_t* bitI,
+                           const uint64_t* bitJ, const uint64_t* bitK, int64_t Kold, int n3old,
+                           int nrep, const int32_t* posI, const int32_t* posJ,
+                           const int32_t* posK, int64_t I, int64_t J, int64_t Kcap,
+                           const int64_t* bbase, CooSummary& z, hipStream_t s);
+hipError_t launch_coo_offsets(CooSummary& z, int nrep, int n1, int n2, int n3, hipStream_t s);
+hipError_t launch_coo_sorts(CooSummary& z, int nrep, int64_t total, hipStream_t s);
+// rows of mode `mode` (0: A from B, C; 1: B from A, C; 2: C from A, B):
+// U = (COO MTTKRP) V^-1, or divided by lam_div (row solve)
+hipError_t launch_coo_rows(const RepSet& rs, int mode, const CooSummary& z, const double* X,
+                           int64_t sX, const double* invlamX, const double* Y, int64_t sY,
+                           const double* invlamY, const double* Vinv, const double* lam_div,
+                           double* U, int64_t sU, hipStream_t s);
+
 // ---- fit -------------------------------------------------------------------
 // M3(k, f) = sum_ij X(i,j,k) A(i,f) B(j,f) and nrm(k) = sum_ij X(i,j,k)^2, FP64
 hipError_t launch_fit_slices(int prec, const void* X, int64_t I, int64_t J, int64_t K, int R,
                              const double* A, const double* B, double* M3, double* nrm,
                              hipStream_t s);
-hipError_t launch_fit_coo(const int32_t* ii, const int32_t* jj, const int32_t* kk,
-                          const float* v, int64_t nnz, int R, const double* A, const double* B,
-                          double* M3, double* nrm, hipStream_t s);
+hipError_t launch_fit_coo(const int32_t* ii, const int32_t* jj, const float* v,
+                          const int64_t* koff, int64_t K, int R, const double* A,
+                          const double* B, double* M3, double* nrm, hipStream_t s);
 // fit = 1 - sqrt(max(0, sum nrm - 2 <X,Xhat> + ||Xhat||^2)) / sqrt(sum nrm)
 hipError_t launch_fit_final(const double* A, const double* B, const double* C, const double* lam,
                             const double* M3, const double* nrm, int64_t I, int64_t J, int64_t K,

@@ -20,7 +20,7 @@ SBT_OK, SBT_E_INVALID, SBT_E_SHAPE, SBT_E_NOMEM, SBT_E_DEVICE, SBT_E_NUMERIC, SB
 SBT_DENSE, SBT_COO = 0, 1
 SBT_P_F64, SBT_P_F32, SBT_P_BF16 = 0, 1, 2
 SBT_SCHED_BATCHED, SBT_SCHED_PLAIN = 0, 1
-SBT_K_MTTKRP_C, SBT_K_MTTKRP_AB, SBT_K_GATHER, SBT_K_UPDATE = range(4)
+SBT_K_MTTKRP_C, SBT_K_MTTKRP_AB, SBT_K_GATHER, SBT_K_UPDATE, SBT_K_COO_MTTKRP = range(5)
 (SBT_REP_AP, SBT_REP_BP, SBT_REP_CP, SBT_REP_LAMP, SBT_REP_PI, SBT_REP_VALID, SBT_REP_AT,
  SBT_REP_BT, SBT_REP_CT) = range(9)
 
@@ -146,6 +146,16 @@ def make_config(rank, repetitions, als_iters, sample_factor, seed, *, init_iters
     return c
 
 
+def coo_to_device(idx, vals):
+    """(nnz, 3) integer coordinates and values -> ((i, j, k) int32, v float32) on device."""
+    import torch
+    idx = np.asarray(idx)
+    cols = tuple(torch.from_numpy(np.ascontiguousarray(idx[:, m], dtype=np.int32)).cuda()
+                 for m in range(3))
+    v = torch.from_numpy(np.ascontiguousarray(vals, dtype=np.float32)).cuda()
+    return cols, v
+
+
 def dense_to_device(X, dtype):
     """(I, J, K) array -> device tensor whose memory is the column-major layout
     the library expects (torch shape (K, J, I), contiguous)."""
@@ -177,6 +187,19 @@ class Tensor:
         _check(st, None, "sbt_init_dense")
         return cls(out.value)
 
+    @classmethod
+    def init_coo(cls, cfg, idx_dev, vals_dev, nnz, I, J, K0, factors, stream=None):
+        """idx_dev: three int32 device arrays (i, j, k); vals_dev: float32."""
+        lib = load()
+        out = _vp()
+        keep = [np.ascontiguousarray(f, dtype=np.float64) for f in factors]
+        fa = [a.ctypes.data for a in keep]
+        st = lib.sbt_init_coo(ctypes.byref(cfg), _ptr(idx_dev[0]), _ptr(idx_dev[1]),
+                              _ptr(idx_dev[2]), _ptr(vals_dev), nnz, I, J, K0, fa[0], fa[1],
+                              fa[2], fa[3], _stream(stream), ctypes.byref(out))
+        _check(st, None, "sbt_init_coo")
+        return cls(out.value)
+
     def close(self):
         if self.h:
             load().sbt_destroy(self.h)
@@ -192,6 +215,15 @@ class Tensor:
     def update_batch_dense(self, Y_dev, K_new, stream=None):
         st = load().sbt_update_batch_dense(self.h, _ptr(Y_dev), K_new, _stream(stream))
         _check(st, self.h, "sbt_update_batch_dense")
+
+    def update_batch_coo(self, idx_dev, vals_dev, nnz, K_new, stream=None):
+        st = self.try_update_batch_coo(idx_dev, vals_dev, nnz, K_new, stream)
+        _check(st, self.h, "sbt_update_batch_coo")
+
+    def try_update_batch_coo(self, idx_dev, vals_dev, nnz, K_new, stream=None):
+        return load().sbt_update_batch_coo(self.h, _ptr(idx_dev[0]), _ptr(idx_dev[1]),
+                                           _ptr(idx_dev[2]), _ptr(vals_dev), nnz, K_new,
+                                           _stream(stream))
 
     def try_update_batch_dense(self, Y_dev, K_new, stream=None):
         return load().sbt_update_batch_dense(self.h, _ptr(Y_dev), K_new, _stream(stream))
