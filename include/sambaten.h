@@ -202,11 +202,12 @@ sbt_status sbt_mttkrp_dense(int32_t precision, const void* Z_dev, int64_t n1, in
  * ------------------------------------------------------------------------ */
 typedef enum {
   SBT_K_MTTKRP_C = 0,   /* MTTKRP pass contracting the third mode with C'       */
-  SBT_K_MTTKRP_AB = 1,  /* MTTKRP pass producing third-mode rows (ALS + row solve) */
+  SBT_K_MTTKRP_AB = 1,  /* MTTKRP pass producing third-mode rows inside CP-ALS   */
   SBT_K_GATHER = 2,     /* summary gather                                        */
   SBT_K_UPDATE = 3,     /* whole update, first to last kernel                   */
   SBT_K_COO_MTTKRP = 4, /* sparse MTTKRP rows of one mode (ALS + row solve)      */
-  SBT_K_COUNT = 5
+  SBT_K_ROW_SOLVE = 5,  /* dense third-mode row least squares (one per update)   */
+  SBT_K_COUNT = 6
 } sbt_kernel_kind;
 
 sbt_status sbt_profile_enable(sbt_tensor* t, int32_t on);

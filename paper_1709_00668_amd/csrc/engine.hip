@@ -125,20 +125,6 @@ sbt_status dalloc_bytes(sbt_tensor* t, void** p, size_t bytes) {
   } while (0)
 
 // Pass 1 splits the third mode into at most this many ranges (partial W).
-constexpr int kMaxSplit = 8;
-
-// Number of third-mode ranges for pass W: about two blocks per CU in total,
-// at most 4 ranges, each at least 16 slices long.
-int choose_nsplit(int64_t n12, int n3, int nrep) {
-  const int64_t abblocks = (n12 + 255) / 256;
-  int64_t ns = (512 + abblocks * nrep - 1) / (abblocks * nrep);
-  int64_t cap = n3 / 16;
-  if (cap > 4) cap = 4;
-  if (cap < 1) cap = 1;
-  if (ns > cap) ns = cap;
-  if (ns < 1) ns = 1;
-  return (int)ns;
-}
 
 // Kernel timing: an event pair per timed launch, resolved after the update's
 // final synchronisation.
@@ -231,7 +217,7 @@ RepSet make_repset(const sbt_tensor* t, int n3, int rep0, int nrep) {
   rs.sA = (int64_t)t->n1 * t->R;
   rs.sB = (int64_t)t->n2 * t->R;
   rs.sC = (int64_t)t->Kpmax * t->R;
-  rs.sW = (int64_t)kMaxSplit * t->n1 * t->n2 * t->R;
+  rs.sW = (int64_t)t->n1 * t->n2 * t->R;
   rs.nsplit = 1;
   int64_t mx = t->n1 > t->n2 ? t->n1 : t->n2;
   if (t->Kpmax > mx) mx = t->Kpmax;
@@ -556,7 +542,7 @@ sbt_status run_als(sbt_tensor* t, const void* Zp, RepSet rs, double* Ap, double*
   double* ilC = invlam + 2 * R;
   SBT_CK(launch_fill_f64(invlam + (int64_t)rs.rep0 * 3 * R, (int64_t)rs.nrep * 3 * R, 1.0, st));
   SBT_CK(launch_inverse(rs, GB, rs.sG, GC, rs.sG, Vinv, t->pinv, st));
-  rs.nsplit = choose_nsplit((int64_t)rs.n1 * rs.n2, rs.n3, rs.nrep);
+  rs.nsplit = 1;  // pass W sums the whole third mode inside each block
   const double pw_bytes =
       zb + (double)rs.nrep * rs.R *
                ((double)rs.n3 * 8 + (double)rs.nsplit * rs.n1 * rs.n2 * acc_bytes(prec));
@@ -620,8 +606,8 @@ sbt_status init_common(sbt_tensor* t, const double* A0, const double* B0, const 
   rs.sA = t->I * R;
   rs.sB = t->J * R;
   rs.sC = t->K * R;
-  rs.nsplit = choose_nsplit(t->I * t->J, (int)t->K, 1);
-  rs.sW = (int64_t)rs.nsplit * t->I * t->J * R;
+  rs.nsplit = 1;
+  rs.sW = t->I * t->J * R;
   int64_t mx = t->I > t->J ? t->I : t->J;
   if (t->K > mx) mx = t->K;
   rs.sM = mx * R;
@@ -766,7 +752,7 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
       prof_end(t, rq, SBT_K_COO_MTTKRP, (double)t->last_summary_nnz * 12.0, st);
     } else if (plain) {
       SBT_CK(launch_p2(t->sum_prec, rs, t->Z, t->At, t->Bt, t->M, st));
-      prof_end(t, rq, SBT_K_MTTKRP_AB, rbytes, st);
+      prof_end(t, rq, SBT_K_ROW_SOLVE, rbytes, st);
       SBT_CK(launch_solve(rs, Kp, t->M, t->Gt, rs.sG, t->ones, 0, t->Ct, rs.sC, nullptr, nullptr,
                           t->lam, 0, t->pinv, st));
     } else {
@@ -774,7 +760,7 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
       SBT_CK(launch_inverse(rs, t->Gt, rs.sG, t->ones, 0, t->Vinv, t->pinv, st));
       SBT_CK(launch_p3(t->sum_prec, rs, true, t->Z, t->At, nullptr, t->Bt, nullptr, t->Vinv,
                        t->lam, t->Ct, rs.sC, st));
-      prof_end(t, rq, SBT_K_MTTKRP_AB, rbytes, st);
+      prof_end(t, rq, SBT_K_ROW_SOLVE, rbytes, st);
     }
   }
   CommitArgs ca;

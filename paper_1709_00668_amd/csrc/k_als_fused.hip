@@ -2,10 +2,10 @@
 // organised for latency: three streaming kernels per sweep, each of which
 // produces complete rows of the updated factor.
 //
-//   pass W   W(ab, f) = sum_c Z(ab, c) C~(c, f)                (all modes share)
+//   pass W   W(ab, f) = sum_c Z(ab, c) C~(c, f)                (modes 1 and 2 share)
 //   mode 1   A(a, :)  = [sum_b W(a, b, :) * B~(b, :)] V1^-1     rows of A per block
 //   mode 2   B(b, :)  = [sum_a W(a, b, :) * A~(a, :)] V2^-1     rows of B per block
-//   mode 3   C(c, :)  = [sum_ab Z(a,b,c) A~(a,:) * B~(b,:)] V3^-1   one slice per block
+//   mode 3   C(c, :)  = [sum_ab Z(a,b,c) A~(a,:) * B~(b,:)] V3^-1   two slices per block
 //
 // V_n^-1 = (Hadamard product of the other two Gram matrices)^-1 is computed
 // ahead of time, by the tail of the previous step, so the streaming blocks
@@ -63,9 +63,38 @@ constexpr int kChunk = 64;                      // factor rows staged per LDS ch
 constexpr int kTailBuf = 2304;                  // doubles; >= 2 x 32 x 33 (Jacobi scratch)
 constexpr int kLd = kMaxRank + 1;
 
+// Stage rows [0, rows) of a row-major FP64 factor (R columns) into LDS as
+// dst[row * RP + f], columns f >= R zero, each column scaled by sc[f] when sc
+// is given; blockDim.x == 256.  A thread issues all loads of a batch before
+// its first store, so their latencies overlap.
+template <typename TA, int RP>
+__device__ inline void stage_rows(TA* dst, int rows, const double* src, int R,
+                                  const double* sc) {
+  constexpr int U = 8;
+  const int n = rows * RP;
+  for (int q0 = threadIdx.x; q0 < n; q0 += U * 256) {
+    double v[U], m[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = q0 + u * 256;
+      const int r = q / RP, f = q % RP;
+      const bool in = q < n && f < R;
+      v[u] = in ? src[(int64_t)r * R + f] : 0.0;
+      m[u] = (in && sc) ? sc[f] : 1.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = q0 + u * 256;
+      if (q < n) dst[q] = (TA)(v[u] * m[u]);
+    }
+  }
+}
+
 struct TailSmem {
-  double V[kMaxRank][kLd];  // Gram of the new factor, then V_next, then V_next^-1
-  double buf[kTailBuf];     // factor rows, or Jacobi scratch
+  double V[kMaxRank][kLd];           // Gram of the new factor, then V_next, then V_next^-1
+  double Vin[kMaxRank * kMaxRank];   // V_next as given (input of the fallback)
+  double Gold[kMaxRank * kMaxRank];  // the other Gram matrix of V_next
+  double buf[kTailBuf];              // factor rows, or Jacobi scratch
   double red[256];
   double lam[kMaxRank];
   int fail;
@@ -143,62 +172,126 @@ __device__ void jacobi_pinv(double* A, double* Q, double* P, int R) {
     }
 }
 
-// Vout = (Gx .* Gy)^-1 by Gauss-Jordan in LDS (symmetric positive definite: no
-// pivoting); a pivot that is not positive switches to the pseudo-inverse.
-__device__ void block_inverse(const double* Gx, const double* Gy, int R, double* Vout,
-                              TailSmem& s, uint32_t* pinv_count) {
+// The tail runs one 256-thread block per repetition.  Its cost is latency:
+// the rows it reads were just written by another kernel, so all loads are
+// issued before any is used; the Gram matrix is shared out over the threads;
+// the R x R inversion runs in the registers of one wavefront (lane i holds
+// row i of [V | I]; the pivot row is broadcast with readlane), so it needs no
+// barriers.
+constexpr int kTailThreads = 256;
+constexpr int kTailUnroll = 8;  // row loads in flight per thread
+
+__device__ inline double readlane_f64(double v, int lane) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xFFFFFFFFull), lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Gauss-Jordan inverse of the symmetric positive definite s.V (R x R) by the
+// first wavefront, without pivoting; returns false (uniform over the wave)
+// when a pivot is not positive.  Result in s.V.
+template <int RP>
+__device__ bool wave_gj_inverse(TailSmem& s, int R) {
+  const int i = lane_id();
+  double a[RP], b[RP];
+#pragma unroll
+  for (int j = 0; j < RP; ++j) {
+    a[j] = (i < R && j < R) ? s.V[i][j] : 0.0;
+    b[j] = (i == j) ? 1.0 : 0.0;
+  }
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < RP; ++k) {
+    if (k < R) {
+      const double piv = readlane_f64(a[k], k);
+      if (!(piv > 0.0)) {
+        ok = false;
+        break;
+      }
+      const double rp = 1.0 / piv;
+      const double m = a[k] * rp;
+      // pivot row: columns j < k of a and j > k of b are zero at this point
+      double pa[RP], pb[RP];
+#pragma unroll
+      for (int j = 0; j < RP; ++j) {
+        pa[j] = j >= k ? readlane_f64(a[j], k) : 0.0;
+        pb[j] = j <= k ? readlane_f64(b[j], k) : 0.0;
+      }
+      if (i == k) {
+#pragma unroll
+        for (int j = 0; j < RP; ++j) {
+          a[j] = pa[j] * rp;
+          b[j] = pb[j] * rp;
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < RP; ++j) {
+          if (j >= k) a[j] = a[j] - m * pa[j];
+          if (j <= k) b[j] = b[j] - m * pb[j];
+        }
+      }
+    }
+  }
+  if (ok && i < R) {
+#pragma unroll
+    for (int j = 0; j < RP; ++j)
+      if (j < R) s.V[i][j] = b[j];
+  }
+  return ok;
+}
+
+// s.V (R x R, already in LDS) -> its inverse in s.V; pseudo-inverse fallback.
+template <int RP>
+__device__ void block_inverse_lds(TailSmem& s, int R, uint32_t* pinv_count, bool count) {
   const int tid = threadIdx.x;
   __syncthreads();
-  for (int q = tid; q < R * R; q += 256) s.V[q / R][q % R] = Gx[q] * Gy[q];
-  if (tid == 0) s.fail = 0;
-  __syncthreads();
-  for (int k = 0; k < R; ++k) {
-    const double piv = s.V[k][k];
-    if (!(piv > 0.0)) {  // uniform
-      if (tid == 0) s.fail = 1;
-      break;
-    }
-    double nv[4];
-    int nq = 0;
-    for (int q = tid; q < R * R; q += 256, ++nq) {
-      const int i = q / R, j = q % R;
-      const double vik = s.V[i][k], vkj = s.V[k][j];
-      double v;
-      if (i == k)
-        v = (j == k) ? 1.0 / piv : vkj / piv;
-      else
-        v = (j == k) ? -vik / piv : s.V[i][j] - vik * (vkj / piv);
-      nv[nq] = v;
-    }
-    __syncthreads();
-    nq = 0;
-    for (int q = tid; q < R * R; q += 256, ++nq) s.V[q / R][q % R] = nv[nq];
-    __syncthreads();
+  if (tid < 64) {
+    const bool ok = wave_gj_inverse<RP>(s, R);
+    if (tid == 0) s.fail = ok ? 0 : 1;
   }
   __syncthreads();
   if (s.fail) {
     double* A0 = s.buf;
     double* Q = s.buf + kMaxRank * kLd;
-    for (int q = tid; q < R * R; q += 256) A0[(q / R) * kLd + q % R] = Gx[q] * Gy[q];
+    for (int q = tid; q < R * R; q += kTailThreads) A0[(q / R) * kLd + q % R] = s.Vin[q];
     __syncthreads();
     if (tid == 0) {
       jacobi_pinv(A0, Q, &s.V[0][0], R);
-      if (pinv_count) atomicAdd(pinv_count, 1u);
+      if (pinv_count && count) atomicAdd(pinv_count, 1u);
     }
-    __syncthreads();
   }
-  for (int q = tid; q < R * R; q += 256) Vout[q] = s.V[q / R][q % R];
+  __syncthreads();
 }
 
-// Last block of a repetition: Gram of the new raw factor, lambda, normalised
-// Gram, inverse for the next step.
+// Vout = (Gx .* Gy)^-1 (start of the sweeps, row solve).
+template <int RP>
+__device__ void block_inverse(const double* Gx, const double* Gy, int R, double* Vout,
+                              TailSmem& s, uint32_t* pinv_count) {
+  const int tid = threadIdx.x;
+  for (int q = tid; q < R * R; q += kTailThreads) {
+    const double v = Gx[q] * Gy[q];
+    s.V[q / R][q % R] = v;
+    s.Vin[q] = v;
+  }
+  block_inverse_lds<RP>(s, R, pinv_count, true);
+  for (int q = tid; q < R * R; q += kTailThreads) Vout[q] = s.V[q / R][q % R];
+}
+
+// Tail of a mode update for one repetition: Gram of the new raw factor,
+// lambda, normalised Gram, inverse for the next step.
+template <int RP>
 __device__ void als_tail(const TailArgs& t, int rep, int R, TailSmem& s) {
   const int tid = threadIdx.x;
   const double* U = t.U + rep * t.sU;
   const int rows = t.rows;
   const int P = R * (R + 1) / 2;
-  const int S = P >= 256 ? 1 : 256 / P;
+  const int S = P >= kTailThreads ? 1 : kTailThreads / P;
   const int crows = kTailBuf / R;
+  // the Gram matrix of the step before, the other factor of V_next
+  const bool fresh_x = t.Gx == t.Gout;
+  const double* Gold = (fresh_x ? t.Gy : t.Gx) + rep * t.sG;
+  for (int q = tid; q < R * R; q += kTailThreads) s.Gold[q] = Gold[q];
   double gacc[3][4];
 #pragma unroll
   for (int j = 0; j < 3; ++j)
@@ -206,13 +299,23 @@ __device__ void als_tail(const TailArgs& t, int rep, int R, TailSmem& s) {
     for (int u = 0; u < 4; ++u) gacc[j][u] = 0.0;
   for (int r0 = 0; r0 < rows; r0 += crows) {
     const int cn = rows - r0 < crows ? rows - r0 : crows;
+    const int n = cn * R;
+    const double* src = U + (int64_t)r0 * R;
     __syncthreads();
-    for (int q = tid; q < cn * R; q += 256) s.buf[q] = U[(int64_t)r0 * R + q];
+    int q = tid;
+    for (; q + (kTailUnroll - 1) * kTailThreads < n; q += kTailUnroll * kTailThreads) {
+      double v[kTailUnroll];
+#pragma unroll
+      for (int u = 0; u < kTailUnroll; ++u) v[u] = src[q + u * kTailThreads];
+#pragma unroll
+      for (int u = 0; u < kTailUnroll; ++u) s.buf[q + u * kTailThreads] = v[u];
+    }
+    for (; q < n; q += kTailThreads) s.buf[q] = src[q];
     __syncthreads();
     for (int j = 0; j < 3; ++j) {
-      const int p = P <= 256 ? tid % P : tid + 256 * j;
-      const int sl = P <= 256 ? tid / P : 0;
-      if ((P <= 256 && (j > 0 || sl >= S)) || p >= P) continue;
+      const int p = P <= kTailThreads ? tid % P : tid + kTailThreads * j;
+      const int sl = P <= kTailThreads ? tid / P : 0;
+      if ((P <= kTailThreads && (j > 0 || sl >= S)) || p >= P) continue;
       int f, g;
       pair_of(p, R, f, g);
       int i = sl;
@@ -226,7 +329,7 @@ __device__ void als_tail(const TailArgs& t, int rep, int R, TailSmem& s) {
   }
   __syncthreads();
   // combine -> Gram of the raw factor in s.V
-  if (P <= 256) {
+  if (P <= kTailThreads) {
     s.red[tid] = (gacc[0][0] + gacc[0][1]) + (gacc[0][2] + gacc[0][3]);
     __syncthreads();
     if (tid < P) {
@@ -239,7 +342,7 @@ __device__ void als_tail(const TailArgs& t, int rep, int R, TailSmem& s) {
     }
   } else {
     for (int j = 0; j < 3; ++j) {
-      const int p = tid + 256 * j;
+      const int p = tid + kTailThreads * j;
       if (p < P) {
         int f, g;
         pair_of(p, R, f, g);
@@ -258,86 +361,107 @@ __device__ void als_tail(const TailArgs& t, int rep, int R, TailSmem& s) {
   }
   __syncthreads();
   double* G = t.Gout + rep * t.sG;
-  for (int q = tid; q < R * R; q += 256) {
+  for (int q = tid; q < R * R; q += kTailThreads) {
     const int f = q / R, g = q % R;
     const double lf = s.lam[f], lg = s.lam[g];
     double v = s.V[f][g];
     if (lf > 0.0) v = v / lf;
     if (lg > 0.0) v = v / lg;
     G[q] = v;
+    // V_next = Gx .* Gy with the fresh Gram in its place
+    const double vn = fresh_x ? v * s.Gold[q] : s.Gold[q] * v;
+    s.Vin[q] = vn;
   }
-  __syncthreads();  // G visible to the block before it is read back below
-  block_inverse(t.Gx + rep * t.sG, t.Gy + rep * t.sG, R, t.Vinv_out + rep * t.sG, s,
-                t.pinv_count);
+  __syncthreads();
+  for (int q = tid; q < R * R; q += kTailThreads) s.V[q / R][q % R] = s.Vin[q];
+  block_inverse_lds<RP>(s, R, t.pinv_count, true);
+  double* Vout = t.Vinv_out + rep * t.sG;
+  for (int q = tid; q < R * R; q += kTailThreads) Vout[q] = s.V[q / R][q % R];
 }
 
 // ---------------------------------------------------------------------------
 // pass W
 // ---------------------------------------------------------------------------
-template <typename TZ, int RP, int V>
-__global__ __launch_bounds__(256) void pw_kernel(RepSet rs, int csz, const TZ* Z,
-                                                const double* Cf, const double* invlamC,
+// One block = 64 consecutive (a, b) of one repetition; its four wavefronts
+// take equal shares of the third-mode index and add their partial rows in a
+// fixed order, so W holds complete sums (one partial per row).
+template <typename TZ, int RP>
+__global__ __launch_bounds__(256) void pw_kernel(RepSet rs, const TZ* Z, const double* Cf,
+                                                const double* invlamC,
                                                 typename AccT<TZ>::type* W) {
   using TA = typename AccT<TZ>::type;
-  constexpr int KU = ku_of(V);
-  const int rep = rs.rep0 + blockIdx.z;
-  const int split = blockIdx.y;
+  constexpr int KU = 16;                              // loads in flight per thread
+  constexpr int CH = sizeof(TA) == 8 ? 128 : 256;     // C~ rows staged at once
+  __shared__ TA Cs[CH][RP];
+  __shared__ TA red[64][RP];
+  const int rep = rs.rep0 + blockIdx.y;
   const int R = rs.R;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int64_t n12 = (int64_t)rs.n1 * rs.n2;
-  const int c0 = split * csz;
-  const int c1 = c0 + csz < rs.n3 ? c0 + csz : rs.n3;
+  const int n3 = rs.n3;
   Z += rep * rs.sZ;
   Cf += rep * rs.sC;
   const double* il = invlamC + rep * 3 * R;
-  __shared__ TA Cs[kChunk][RP];
-  const int64_t e0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * V;
-  const bool ok = e0 < n12;
-  TA acc[V][RP];
+  const int64_t e = (int64_t)blockIdx.x * 64 + lane;
+  const bool ok = e < n12;
+  TA acc[RP];
 #pragma unroll
-  for (int v = 0; v < V; ++v)
+  for (int f = 0; f < RP; ++f) acc[f] = 0;
+  for (int cc0 = 0; cc0 < n3; cc0 += CH) {
+    const int cn = n3 - cc0 < CH ? n3 - cc0 : CH;
+    const int lo = (wave * cn) / 4, hi = ((wave + 1) * cn) / 4;
+    const TZ* zp = Z + e + n12 * cc0;
+    // the first KU summary loads go out before C~ is staged
+    TA z[KU];
+    const bool pre = ok && lo + KU <= hi;
+    if (pre) {
 #pragma unroll
-    for (int f = 0; f < RP; ++f) acc[v][f] = 0;
-  for (int cc0 = c0; cc0 < c1; cc0 += kChunk) {
-    const int cn = c1 - cc0 < kChunk ? c1 - cc0 : kChunk;
-    __syncthreads();
-    for (int q = threadIdx.x; q < kChunk * RP; q += 256) {
-      const int cc = q / RP, f = q % RP;
-      Cs[cc][f] = (cc < cn && f < R) ? (TA)(Cf[(int64_t)(cc0 + cc) * R + f] * il[f]) : (TA)0;
+      for (int u = 0; u < KU; ++u) z[u] = ld1(zp + n12 * (lo + u));
     }
     __syncthreads();
+    stage_rows<TA, RP>(&Cs[0][0], cn, Cf + (int64_t)cc0 * R, R, il);
+    __syncthreads();
     if (ok) {
-      const TZ* zp = Z + e0 + n12 * cc0;
-      int cc = 0;
-      for (; cc + KU <= cn; cc += KU) {
-        TA z[KU][V];
-#pragma unroll
-        for (int u = 0; u < KU; ++u) ldv(zp + n12 * (cc + u), z[u]);
+      int c = lo;
+      if (pre) {
 #pragma unroll
         for (int u = 0; u < KU; ++u)
 #pragma unroll
-          for (int f = 0; f < RP; ++f) {
-            const TA cv = Cs[cc + u][f];
-#pragma unroll
-            for (int v = 0; v < V; ++v) acc[v][f] += z[u][v] * cv;
-          }
+          for (int f = 0; f < RP; ++f) acc[f] += z[u] * Cs[c + u][f];
+        c += KU;
       }
-      for (; cc < cn; ++cc) {
-        TA z[V];
-        ldv(zp + n12 * cc, z);
+      for (; c + KU <= hi; c += KU) {
 #pragma unroll
-        for (int f = 0; f < RP; ++f)
+        for (int u = 0; u < KU; ++u) z[u] = ld1(zp + n12 * (c + u));
 #pragma unroll
-          for (int v = 0; v < V; ++v) acc[v][f] += z[v] * Cs[cc][f];
+        for (int u = 0; u < KU; ++u)
+#pragma unroll
+          for (int f = 0; f < RP; ++f) acc[f] += z[u] * Cs[c + u][f];
+      }
+      for (; c < hi; ++c) {
+        const TA zc = ld1(zp + n12 * c);
+#pragma unroll
+        for (int f = 0; f < RP; ++f) acc[f] += zc * Cs[c][f];
       }
     }
   }
-  if (ok) {
-    TA* w = W + rep * rs.sW + ((int64_t)split * n12 + e0) * R;
+  for (int w = 1; w < 4; ++w) {
+    __syncthreads();
+    if (wave == w) {
 #pragma unroll
-    for (int v = 0; v < V; ++v)
+      for (int f = 0; f < RP; ++f) red[lane][f] = acc[f];
+    }
+    __syncthreads();
+    if (wave == 0) {
 #pragma unroll
-      for (int f = 0; f < RP; ++f)
-        if (f < R) w[v * R + f] = acc[v][f];
+      for (int f = 0; f < RP; ++f) acc[f] += red[lane][f];
+    }
+  }
+  if (wave == 0 && ok) {
+    TA* w = W + rep * rs.sW + e * R;
+#pragma unroll
+    for (int f = 0; f < RP; ++f)
+      if (f < R) w[f] = acc[f];
   }
 }
 
@@ -347,25 +471,24 @@ __global__ __launch_bounds__(256) void pw_kernel(RepSet rs, int csz, const TZ* Z
 constexpr int kRowsPerBlock = 8;   // factor rows produced by one block
 constexpr int kSlots = 32;         // threads sharing one row (the contracted index)
 
-template <typename TA, int RP>
-struct CwSmem {
-  TA Fs[kChunk][RP];                     // staged rows of the contracted factor
-  TA red[4][kRowsPerBlock][RP];          // per-wave partial rows
-  double Mrow[kRowsPerBlock][kMaxRank];  // contracted rows
-  double Vi[kMaxRank][kLd];              // V^-1
-};
-
 // mode = 0: rows a of A from B~;  mode = 1: rows b of B from A~.  Raw rows
-// U = M V^-1 are written; the tail kernel follows.
+// U = M V^-1 are written; the tail kernel follows.  The contracted factor is
+// staged in LDS in chunks of chr rows (one chunk when it fits); each thread's
+// first rows of W are loaded before the staging so the two latencies overlap.
+constexpr int kCwPre = 4;  // W rows in flight per thread
+
 template <typename TA, int RP>
-__global__ __launch_bounds__(256) void cw_kernel(RepSet rs, int mode, const TA* W,
+__global__ __launch_bounds__(256) void cw_kernel(RepSet rs, int mode, int chr, const TA* W,
                                                 const double* F, const double* invlamF,
                                                 const double* Vinv, double* Uout, int64_t sU) {
-  __shared__ CwSmem<TA, RP> sm;
+  extern __shared__ __align__(16) unsigned char cw_smem[];
+  __shared__ TA red[4][kRowsPerBlock][RP];
+  __shared__ double Mrow[kRowsPerBlock][kMaxRank];
+  __shared__ double Vi[kMaxRank][kLd];
+  TA* Fs = reinterpret_cast<TA*>(cw_smem);  // [chr][RP]
   const int rep = rs.rep0 + blockIdx.y;
-  const int R = rs.R, n1 = rs.n1, n2 = rs.n2, ns = rs.nsplit;
+  const int R = rs.R, n1 = rs.n1, n2 = rs.n2;
   const int tid = threadIdx.x;
-  const int64_t n12 = (int64_t)n1 * n2;
   // mode 0: row = low 3 bits of tid (consecutive a, coalesced), slot = high 5
   // mode 1: slot = low 5 bits (consecutive a, coalesced), row = high 3
   const int rl = mode == 0 ? (tid & (kRowsPerBlock - 1)) : (tid >> 5);  // row within block
@@ -377,47 +500,54 @@ __global__ __launch_bounds__(256) void cw_kernel(RepSet rs, int mode, const TA* 
   const TA* Wr = W + rep * rs.sW;
   const double* Fr = F + (mode == 0 ? rep * rs.sB : rep * rs.sA);
   const double* il = invlamF + rep * 3 * R;
-  for (int q = tid; q < R * R; q += 256) sm.Vi[q / R][q % R] = Vinv[rep * rs.sG + q];
   TA acc[RP];
 #pragma unroll
   for (int f = 0; f < RP; ++f) acc[f] = 0;
-  for (int x0 = 0; x0 < ncon; x0 += kChunk) {
-    const int xn = ncon - x0 < kChunk ? ncon - x0 : kChunk;
-    __syncthreads();
-    for (int q = tid; q < kChunk * RP; q += 256) {
-      const int xx = q / RP, f = q % RP;
-      sm.Fs[xx][f] = (xx < xn && f < R) ? (TA)(Fr[(int64_t)(x0 + xx) * R + f] * il[f]) : (TA)0;
+  for (int x0 = 0; x0 < ncon; x0 += chr) {
+    const int xn = ncon - x0 < chr ? ncon - x0 : chr;
+    TA w[kCwPre][RP];
+#pragma unroll
+    for (int u = 0; u < kCwPre; ++u) {
+      const int x = x0 + sl + u * kSlots;
+      const bool v = ok && x < x0 + xn;
+      const int64_t e = mode == 0 ? (int64_t)row + (int64_t)n1 * x : (int64_t)x + (int64_t)n1 * row;
+#pragma unroll
+      for (int f = 0; f < RP; ++f) w[u][f] = (v && f < R) ? Wr[e * R + f] : (TA)0;
     }
     __syncthreads();
-    if (ok) {
-      for (int sp = 0; sp < ns; ++sp) {
-        const TA* Ws = Wr + (int64_t)sp * n12 * R;
-        int xx = sl;
-        for (; xx + kSlots < xn; xx += 2 * kSlots) {
-          const int64_t e0 = mode == 0 ? (int64_t)row + (int64_t)n1 * (x0 + xx)
-                                       : (int64_t)(x0 + xx) + (int64_t)n1 * row;
-          const int64_t e1 = mode == 0 ? e0 + (int64_t)n1 * kSlots : e0 + kSlots;
-          TA w0[RP], w1[RP];
+    if (x0 == 0)
+      for (int q = tid; q < R * R; q += 256) Vi[q / R][q % R] = Vinv[rep * rs.sG + q];
+    stage_rows<TA, RP>(Fs, xn, Fr + (int64_t)x0 * R, R, il);
+    __syncthreads();
 #pragma unroll
-          for (int f = 0; f < RP; ++f) {
-            w0[f] = f < R ? Ws[e0 * R + f] : (TA)0;
-            w1[f] = f < R ? Ws[e1 * R + f] : (TA)0;
-          }
+    for (int u = 0; u < kCwPre; ++u) {
+      const int x = sl + u * kSlots;
+      if (x < xn) {
 #pragma unroll
-          for (int f = 0; f < RP; ++f)
-            acc[f] += w0[f] * sm.Fs[xx][f] + w1[f] * sm.Fs[xx + kSlots][f];
-        }
-        for (; xx < xn; xx += kSlots) {
-          const int64_t e0 = mode == 0 ? (int64_t)row + (int64_t)n1 * (x0 + xx)
-                                       : (int64_t)(x0 + xx) + (int64_t)n1 * row;
+        for (int f = 0; f < RP; ++f) acc[f] += w[u][f] * Fs[x * RP + f];
+      }
+    }
+    for (int xb = sl + kCwPre * kSlots; xb < xn; xb += kCwPre * kSlots) {
 #pragma unroll
-          for (int f = 0; f < RP; ++f)
-            if (f < R) acc[f] += Ws[e0 * R + f] * sm.Fs[xx][f];
+      for (int u = 0; u < kCwPre; ++u) {
+        const int x = x0 + xb + u * kSlots;
+        const bool v = ok && x < x0 + xn;
+        const int64_t e =
+            mode == 0 ? (int64_t)row + (int64_t)n1 * x : (int64_t)x + (int64_t)n1 * row;
+#pragma unroll
+        for (int f = 0; f < RP; ++f) w[u][f] = (v && f < R) ? Wr[e * R + f] : (TA)0;
+      }
+#pragma unroll
+      for (int u = 0; u < kCwPre; ++u) {
+        const int x = xb + u * kSlots;
+        if (x < xn) {
+#pragma unroll
+          for (int f = 0; f < RP; ++f) acc[f] += w[u][f] * Fs[x * RP + f];
         }
       }
     }
   }
-  // reduce over the 16 slots: within the wave first, then across waves
+  // reduce over the 32 slots: within the wave first, then across waves
   const int wave = tid >> 6;
 #pragma unroll
   for (int f = 0; f < RP; ++f) {
@@ -439,18 +569,17 @@ __global__ __launch_bounds__(256) void cw_kernel(RepSet rs, int mode, const TA* 
   if (mode == 0) {  // each wave holds 8 of the 32 slots
     if ((tid & 63) < kRowsPerBlock)
 #pragma unroll
-      for (int f = 0; f < RP; ++f) sm.red[wave][rl][f] = acc[f];
+      for (int f = 0; f < RP; ++f) red[wave][rl][f] = acc[f];
   } else {          // each wave holds two rows, all 32 slots
     if (sl == 0)
 #pragma unroll
-      for (int f = 0; f < RP; ++f) sm.red[0][rl][f] = acc[f];
+      for (int f = 0; f < RP; ++f) red[0][rl][f] = acc[f];
   }
   __syncthreads();
   for (int q = tid; q < kRowsPerBlock * R; q += 256) {
     const int r = q / R, f = q % R;
-    sm.Mrow[r][f] = mode == 0 ? (double)((sm.red[0][r][f] + sm.red[1][r][f]) +
-                                         (sm.red[2][r][f] + sm.red[3][r][f]))
-                              : (double)sm.red[0][r][f];
+    Mrow[r][f] = mode == 0 ? (double)((red[0][r][f] + red[1][r][f]) + (red[2][r][f] + red[3][r][f]))
+                           : (double)red[0][r][f];
   }
   __syncthreads();
   double* U = Uout + rep * sU;
@@ -459,26 +588,28 @@ __global__ __launch_bounds__(256) void cw_kernel(RepSet rs, int mode, const TA* 
     const int gr = blockIdx.x * kRowsPerBlock + r;
     if (gr < nrows) {
       double u = 0.0;
-      for (int k = 0; k < R; ++k) u += sm.Mrow[r][k] * sm.Vi[k][f];
+      for (int k = 0; k < R; ++k) u += Mrow[r][k] * Vi[k][f];
       U[(int64_t)gr * R + f] = u;
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-// mode 3: kSpb slices per block
+// mode 3: a team of two wavefronts per slice, two slices per block
 // ---------------------------------------------------------------------------
-constexpr int kSpb = 1;
+// The rows of A~ and B~ (scaled by 1/lambda) are staged in LDS once per block
+// in the accumulation precision; each thread streams V consecutive a of its
+// slice for a strided subset of b, contracts b against B~ then a against A~,
+// and the team reduces across its lanes before one wavefront multiplies the
+// row by V^-1.
+constexpr int kP3Team = 128;               // threads per slice
+constexpr int kP3Slices = 256 / kP3Team;   // slices per block
 
-constexpr int kP3Chunk = 128;  // B~ rows staged at once by the mode-3 kernel
-
-template <typename TA, int RP>
-struct P3Smem {
-  TA Bs[kP3Chunk][RP];
-  TA red[4][kMaxRank];
-  double Mrow[kMaxRank];
-  double Vi[kMaxRank][kLd];
-};
+template <typename TA>
+size_t p3_smem_bytes(int n1, int n2, int RP) {
+  return sizeof(double) * kMaxRank * kLd + sizeof(TA) * 4 * kMaxRank +
+         sizeof(TA) * (size_t)(n1 + n2) * RP;
+}
 
 // kRow = false: ALS update of C' (raw rows).  kRow = true: the row solve
 // (rows divided by lam_div).
@@ -489,130 +620,123 @@ __global__ __launch_bounds__(256) void p3_kernel(RepSet rs, const TZ* Z, const d
                                                 const double* lam_div, double* Uout,
                                                 int64_t sU) {
   using TA = typename AccT<TZ>::type;
-  constexpr int KU = V >= 4 ? 4 : (V == 2 ? 8 : 16);  // 16 elements in flight per thread
-  __shared__ P3Smem<TA, RP> sm;
+  constexpr int KU = V >= 2 ? 8 : 16;  // loads in flight per thread
+  extern __shared__ __align__(16) unsigned char p3_smem[];
+  double(*Vi)[kLd] = reinterpret_cast<double(*)[kLd]>(p3_smem);
+  TA(*red)[kMaxRank] =
+      reinterpret_cast<TA(*)[kMaxRank]>(p3_smem + sizeof(double) * kMaxRank * kLd);
+  TA* As = reinterpret_cast<TA*>(p3_smem + sizeof(double) * kMaxRank * kLd +
+                                 sizeof(TA) * 4 * kMaxRank);
   const int rep = rs.rep0 + blockIdx.y;
   const int R = rs.R, n1 = rs.n1, n2 = rs.n2;
   const int tid = threadIdx.x;
-  const int64_t n12 = (int64_t)n1 * n2;
-  const double* Ar = Af + rep * rs.sA;
-  const double* Br = Bf + rep * rs.sB;
-  const double* ilA = invlamA ? invlamA + rep * 3 * R : nullptr;
-  const double* ilB = invlamB ? invlamB + rep * 3 * R : nullptr;
-  for (int q = tid; q < R * R; q += 256) sm.Vi[q / R][q % R] = Vinv[rep * rs.sG + q];
-  const int ng = n1 / V;
-  const int span = ng >= 256 ? 256 : ng;
-  const int nsub = 256 / span;
-  const int sub = tid / span, gl = tid % span;
-  const bool act = sub < nsub;
+  TA* Bs = As + (size_t)n1 * RP;
+  const int team = tid / kP3Team, tt = tid % kP3Team;
   const int wave = tid >> 6;
-  const int cfirst = blockIdx.x * kSpb;
-  for (int c = cfirst; c < cfirst + kSpb && c < rs.n3; ++c) {
-    const TZ* Zc = Z + rep * rs.sZ + n12 * c;
-    TA tot[RP];
+  const int c = blockIdx.x * kP3Slices + team;
+  const int ng = n1 / V;
+  const int span = ng >= kP3Team ? kP3Team : ng;
+  const int nsub = kP3Team / span;
+  const int sub = tt / span, gl = tt % span;
+  const bool act = sub < nsub && c < rs.n3;
+  const TZ* Zc = Z + rep * rs.sZ + (int64_t)n1 * n2 * (c < rs.n3 ? c : 0);
+  // the first KU summary loads go out before A~ and B~ are staged
+  TA z[KU][V];
+  const bool pre = act && gl < ng && sub + (KU - 1) * nsub < n2;
+  if (pre) {
 #pragma unroll
-    for (int f = 0; f < RP; ++f) tot[f] = 0;
+    for (int u = 0; u < KU; ++u) ldv(Zc + (int64_t)gl * V + (int64_t)n1 * (sub + u * nsub), z[u]);
+  }
+  for (int q = tid; q < R * R; q += 256) Vi[q / R][q % R] = Vinv[rep * rs.sG + q];
+  stage_rows<TA, RP>(As, n1, Af + rep * rs.sA, R, invlamA ? invlamA + rep * 3 * R : nullptr);
+  stage_rows<TA, RP>(Bs, n2, Bf + rep * rs.sB, R, invlamB ? invlamB + rep * 3 * R : nullptr);
+  __syncthreads();
+  TA tot[RP];
+#pragma unroll
+  for (int f = 0; f < RP; ++f) tot[f] = 0;
+  if (act) {
     for (int g0 = 0; g0 < ng; g0 += span) {
       const int g = g0 + gl;
-      const bool ok = act && g < ng;
-      TA acc[V][RP];
+      if (g < ng) {
+        TA acc[V][RP];
 #pragma unroll
-      for (int v = 0; v < V; ++v)
+        for (int v = 0; v < V; ++v)
 #pragma unroll
-        for (int f = 0; f < RP; ++f) acc[v][f] = 0;
-      for (int b0 = 0; b0 < n2; b0 += kP3Chunk) {
-        const int bn = n2 - b0 < kP3Chunk ? n2 - b0 : kP3Chunk;
-        // B~ rows are staged once per block when they fit one chunk
-        if (c == cfirst || n2 > kP3Chunk || ng > span) {
-          __syncthreads();
-          for (int q = tid; q < kP3Chunk * RP; q += 256) {
-            const int bb = q / RP, f = q % RP;
-            double bv = 0.0;
-            if (bb < bn && f < R) {
-              bv = Br[(int64_t)(b0 + bb) * R + f];
-              if (ilB) bv *= ilB[f];
-            }
-            sm.Bs[bb][f] = (TA)bv;
+          for (int f = 0; f < RP; ++f) acc[v][f] = 0;
+        const TZ* zp = Zc + (int64_t)g * V;
+        int b = sub;
+        bool have = g0 == 0 && pre;
+        for (; b + (KU - 1) * nsub < n2; b += KU * nsub) {
+          if (!have) {
+#pragma unroll
+            for (int u = 0; u < KU; ++u) ldv(zp + (int64_t)n1 * (b + u * nsub), z[u]);
           }
-          __syncthreads();
-        }
-        if (ok) {
-          const TZ* zp = Zc + (int64_t)g * V + (int64_t)n1 * b0;
-          int bb = sub;
-          for (; bb + (KU - 1) * nsub < bn; bb += KU * nsub) {
-            TA z[KU][V];
+          have = false;
 #pragma unroll
-            for (int u = 0; u < KU; ++u) ldv(zp + (int64_t)n1 * (bb + u * nsub), z[u]);
-#pragma unroll
-            for (int u = 0; u < KU; ++u)
-#pragma unroll
-              for (int f = 0; f < RP; ++f) {
-                const TA bv = sm.Bs[bb + u * nsub][f];
-#pragma unroll
-                for (int v = 0; v < V; ++v) acc[v][f] += z[u][v] * bv;
-              }
-          }
-          for (; bb < bn; bb += nsub) {
-            TA z[V];
-            ldv(zp + (int64_t)n1 * bb, z);
+          for (int u = 0; u < KU; ++u) {
+            const TA* bp = Bs + (size_t)(b + u * nsub) * RP;
 #pragma unroll
             for (int f = 0; f < RP; ++f) {
-              const TA bv = sm.Bs[bb][f];
+              const TA bv = bp[f];
 #pragma unroll
-              for (int v = 0; v < V; ++v) acc[v][f] += z[v] * bv;
+              for (int v = 0; v < V; ++v) acc[v][f] += z[u][v] * bv;
             }
           }
         }
-      }
-      if (ok) {
+        for (; b < n2; b += nsub) {
+          TA zz[V];
+          ldv(zp + (int64_t)n1 * b, zz);
+          const TA* bp = Bs + (size_t)b * RP;
+#pragma unroll
+          for (int f = 0; f < RP; ++f) {
+            const TA bv = bp[f];
+#pragma unroll
+            for (int v = 0; v < V; ++v) acc[v][f] += zz[v] * bv;
+          }
+        }
 #pragma unroll
         for (int v = 0; v < V; ++v) {
-          const double* arow = Ar + (int64_t)(g * V + v) * R;
+          const TA* ap = As + (size_t)(g * V + v) * RP;
 #pragma unroll
-          for (int f = 0; f < RP; ++f)
-            if (f < R) {
-              double av = arow[f];
-              if (ilA) av *= ilA[f];
-              tot[f] += acc[v][f] * (TA)av;
-            }
+          for (int f = 0; f < RP; ++f) tot[f] += acc[v][f] * ap[f];
         }
       }
     }
+  }
 #pragma unroll
-    for (int f = 0; f < RP; ++f) {
-      const TA v = wave_sum(tot[f]);
-      if (lane_id() == 0) sm.red[wave][f] = v;
+  for (int f = 0; f < RP; ++f) {
+    const TA v = wave_sum(tot[f]);
+    if (lane_id() == 0 && f < kMaxRank) red[wave][f] = v;
+  }
+  __syncthreads();
+  if (c < rs.n3 && tt < R) {
+    const int w0 = team * (kP3Team / 64);
+    double u = 0.0;
+    for (int k = 0; k < R; ++k) u += (double)(red[w0][k] + red[w0 + 1][k]) * Vi[k][tt];
+    if (kRow) {
+      const double l = lam_div[tt];
+      u = l > 0.0 ? u / l : 0.0;
     }
-    __syncthreads();
-    if (tid < R)
-      sm.Mrow[tid] = (double)((sm.red[0][tid] + sm.red[1][tid]) + (sm.red[2][tid] + sm.red[3][tid]));
-    __syncthreads();
-    if (tid < R) {
-      double u = 0.0;
-      for (int k = 0; k < R; ++k) u += sm.Mrow[k] * sm.Vi[k][tid];
-      if (kRow) {
-        const double l = lam_div[tid];
-        u = l > 0.0 ? u / l : 0.0;
-      }
-      Uout[rep * sU + (int64_t)c * R + tid] = u;
-    }
+    Uout[rep * sU + (int64_t)c * R + tt] = u;
   }
 }
 
 // Tail of a mode update, one block per repetition.
-__global__ __launch_bounds__(256) void tail_kernel(RepSet rs, TailArgs ta) {
+template <int RP>
+__global__ __launch_bounds__(kTailThreads) void tail_kernel(RepSet rs, TailArgs ta) {
   __shared__ TailSmem sm;
-  als_tail(ta, rs.rep0 + blockIdx.x, rs.R, sm);
+  als_tail<RP>(ta, rs.rep0 + blockIdx.x, rs.R, sm);
 }
 
 // V^-1 = (Gx .* Gy)^-1 per repetition (start of the sweeps, row solve).
-__global__ __launch_bounds__(256) void inverse_kernel(RepSet rs, const double* Gx,
-                                                     int64_t sGx, const double* Gy,
-                                                     int64_t sGy, double* Vinv,
-                                                     uint32_t* pinv_count) {
+template <int RP>
+__global__ __launch_bounds__(kTailThreads) void inverse_kernel(RepSet rs, const double* Gx,
+                                                              int64_t sGx, const double* Gy,
+                                                              int64_t sGy, double* Vinv,
+                                                              uint32_t* pinv_count) {
   __shared__ TailSmem sm;
   const int rep = rs.rep0 + blockIdx.x;
-  block_inverse(Gx + rep * sGx, Gy + rep * sGy, rs.R, Vinv + rep * rs.sG, sm, pinv_count);
+  block_inverse<RP>(Gx + rep * sGx, Gy + rep * sGy, rs.R, Vinv + rep * rs.sG, sm, pinv_count);
 }
 
 // Scale raw factor rows to unit columns (end of the sweeps).
@@ -654,7 +778,9 @@ inline int rp4(int R) { return ((R + 3) / 4) * 4; }
 // ---------------------------------------------------------------------------
 hipError_t launch_inverse(const RepSet& rs, const double* Gx, int64_t sGx, const double* Gy,
                           int64_t sGy, double* Vinv, uint32_t* pinv_count, hipStream_t s) {
-  inverse_kernel<<<rs.nrep, 256, 0, s>>>(rs, Gx, sGx, Gy, sGy, Vinv, pinv_count);
+  SBT_RP_SWITCH(rs.R, {
+    inverse_kernel<RP><<<rs.nrep, kTailThreads, 0, s>>>(rs, Gx, sGx, Gy, sGy, Vinv, pinv_count);
+  });
   return hipGetLastError();
 }
 
@@ -671,30 +797,23 @@ hipError_t launch_normalize(const RepSet& rs, double* Ap, double* Bp, double* Cp
 hipError_t launch_tail(const RepSet& rs, const AlsTail& t, hipStream_t s) {
   TailArgs ta{t.U, t.sU, t.rows, t.Gout, t.invlam_out, t.lam_out, t.Gx, t.Gy, t.Vinv_out,
               t.sG, t.pinv_count};
-  tail_kernel<<<rs.nrep, 256, 0, s>>>(rs, ta);
+  SBT_RP_SWITCH(rs.R, { tail_kernel<RP><<<rs.nrep, kTailThreads, 0, s>>>(rs, ta); });
   return hipGetLastError();
 }
 
 hipError_t launch_pw(int prec, const RepSet& rs, const void* Z, const double* Cf,
                      const double* invlamC, void* W, hipStream_t s) {
   const int64_t n12 = (int64_t)rs.n1 * rs.n2;
-  const int ns = rs.nsplit < 1 ? 1 : rs.nsplit;
-  const int csz = (rs.n3 + ns - 1) / ns;
-#define SBT_PW(TZ, RPV)                                                                       \
-  do {                                                                                        \
-    dim3 grid((unsigned)((n12 + 255) / 256), (unsigned)ns, (unsigned)rs.nrep);                \
-    pw_kernel<TZ, RPV, 1><<<grid, 256, 0, s>>>(rs, csz, (const TZ*)Z, Cf, invlamC,            \
-                                               (typename AccT<TZ>::type*)W);                  \
-  } while (0)
+  dim3 grid((unsigned)((n12 + 63) / 64), (unsigned)rs.nrep);
   SBT_RP_SWITCH(rs.R, {
     if (prec == kF64)
-      SBT_PW(double, RP);
+      pw_kernel<double, RP><<<grid, 256, 0, s>>>(rs, (const double*)Z, Cf, invlamC, (double*)W);
     else if (prec == kF32)
-      SBT_PW(float, RP);
+      pw_kernel<float, RP><<<grid, 256, 0, s>>>(rs, (const float*)Z, Cf, invlamC, (float*)W);
     else
-      SBT_PW(uint16_t, RP);
+      pw_kernel<uint16_t, RP><<<grid, 256, 0, s>>>(rs, (const uint16_t*)Z, Cf, invlamC,
+                                                   (float*)W);
   });
-#undef SBT_PW
   return hipGetLastError();
 }
 
@@ -702,14 +821,21 @@ hipError_t launch_cw(int prec, const RepSet& rs, int mode, const void* W, const 
                      const double* invlamF, const double* Vinv, double* U, int64_t sU,
                      hipStream_t s) {
   const int nrows = mode == 0 ? rs.n1 : rs.n2;
+  const int ncon = mode == 0 ? rs.n2 : rs.n1;
   dim3 grid((unsigned)((nrows + kRowsPerBlock - 1) / kRowsPerBlock), (unsigned)rs.nrep);
+  // staged rows per chunk: all of them when they fit 32 KB
+  const size_t row_bytes = (size_t)rp4(rs.R) * (prec == kF64 ? 8 : 4);
+  int chr = (int)((32768 / row_bytes) / kSlots * kSlots);
+  if (chr > ncon) chr = ncon;
+  if (chr < kSlots) chr = kSlots;
+  const size_t sh = (size_t)chr * row_bytes;
   SBT_RP_SWITCH(rs.R, {
     if (prec == kF64)
-      cw_kernel<double, RP><<<grid, 256, 0, s>>>(rs, mode, (const double*)W, F, invlamF, Vinv,
-                                                 U, sU);
+      cw_kernel<double, RP><<<grid, 256, sh, s>>>(rs, mode, chr, (const double*)W, F, invlamF,
+                                                  Vinv, U, sU);
     else
-      cw_kernel<float, RP><<<grid, 256, 0, s>>>(rs, mode, (const float*)W, F, invlamF, Vinv, U,
-                                                sU);
+      cw_kernel<float, RP><<<grid, 256, sh, s>>>(rs, mode, chr, (const float*)W, F, invlamF,
+                                                 Vinv, U, sU);
   });
   return hipGetLastError();
 }
@@ -718,17 +844,25 @@ hipError_t launch_p3(int prec, const RepSet& rs, bool row_solve, const void* Z, 
                      const double* invlamA, const double* Bf, const double* invlamB,
                      const double* Vinv, const double* lam_div, double* U, int64_t sU,
                      hipStream_t s) {
-  dim3 grid((unsigned)((rs.n3 + kSpb - 1) / kSpb), (unsigned)rs.nrep);
+  dim3 grid((unsigned)((rs.n3 + kP3Slices - 1) / kP3Slices), (unsigned)rs.nrep);
   const int vw = prec == kF64 ? (rs.n1 % 2 == 0 ? 2 : 1)
                               : (rs.n1 % 4 == 0 ? 4 : (rs.n1 % 2 == 0 ? 2 : 1));
+  hipError_t err = hipSuccess;
 #define SBT_P3(TZ, RPV, VV)                                                                    \
   do {                                                                                         \
+    using TA_ = typename AccT<TZ>::type;                                                       \
+    const size_t sh = p3_smem_bytes<TA_>(rs.n1, rs.n2, RPV);                                   \
+    const void* fn = row_solve ? (const void*)p3_kernel<TZ, RPV, VV, true>                     \
+                               : (const void*)p3_kernel<TZ, RPV, VV, false>;                   \
+    if (sh > 65536)                                                                            \
+      err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);      \
+    if (err != hipSuccess) break;                                                              \
     if (row_solve)                                                                             \
-      p3_kernel<TZ, RPV, VV, true><<<grid, 256, 0, s>>>(rs, (const TZ*)Z, Af, invlamA, Bf,     \
-                                                        invlamB, Vinv, lam_div, U, sU);        \
-    else                                                                                       \
-      p3_kernel<TZ, RPV, VV, false><<<grid, 256, 0, s>>>(rs, (const TZ*)Z, Af, invlamA, Bf,    \
+      p3_kernel<TZ, RPV, VV, true><<<grid, 256, sh, s>>>(rs, (const TZ*)Z, Af, invlamA, Bf,    \
                                                          invlamB, Vinv, lam_div, U, sU);       \
+    else                                                                                       \
+      p3_kernel<TZ, RPV, VV, false><<<grid, 256, sh, s>>>(rs, (const TZ*)Z, Af, invlamA, Bf,   \
+                                                          invlamB, Vinv, lam_div, U, sU);      \
   } while (0)
   SBT_RP_SWITCH(rs.R, {
     if (prec == kF64) {
@@ -744,6 +878,7 @@ hipError_t launch_p3(int prec, const RepSet& rs, bool row_solve, const void* Z, 
     }
   });
 #undef SBT_P3
+  if (err != hipSuccess) return err;
   return hipGetLastError();
 }
 

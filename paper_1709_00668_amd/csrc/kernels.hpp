@@ -24,8 +24,8 @@ struct RepSet {
   int rep0, nrep;   // repetitions [rep0, rep0 + nrep) of this launch
   int64_t sZ;       // summary elements
   int64_t sA, sB, sC;  // factor rows * R
-  int64_t sW;       // W workspace per repetition: nsplit_max * R * n1*n2 (acc type)
-  int nsplit;       // pass 1 splits the third mode into nsplit ranges (partial W)
+  int64_t sW;       // W workspace per repetition: R * n1*n2 (acc type)
+  int nsplit;       // partial sums per row of W (1: pass W writes complete rows)
   int64_t sM;       // max rows * R (double)
   int64_t sG;       // R*R
 };

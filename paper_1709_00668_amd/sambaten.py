@@ -20,7 +20,8 @@ SBT_OK, SBT_E_INVALID, SBT_E_SHAPE, SBT_E_NOMEM, SBT_E_DEVICE, SBT_E_NUMERIC, SB
 SBT_DENSE, SBT_COO = 0, 1
 SBT_P_F64, SBT_P_F32, SBT_P_BF16 = 0, 1, 2
 SBT_SCHED_BATCHED, SBT_SCHED_PLAIN = 0, 1
-SBT_K_MTTKRP_C, SBT_K_MTTKRP_AB, SBT_K_GATHER, SBT_K_UPDATE, SBT_K_COO_MTTKRP = range(5)
+(SBT_K_MTTKRP_C, SBT_K_MTTKRP_AB, SBT_K_GATHER, SBT_K_UPDATE, SBT_K_COO_MTTKRP,
+ SBT_K_ROW_SOLVE) = range(6)
 (SBT_REP_AP, SBT_REP_BP, SBT_REP_CP, SBT_REP_LAMP, SBT_REP_PI, SBT_REP_VALID, SBT_REP_AT,
  SBT_REP_BT, SBT_REP_CT) = range(9)
 
