@@ -42,6 +42,19 @@ def reconstruct(A, B, C, lam=None):
     return np.einsum("ir,jr,kr,r->ijk", A, B, C, lam)
 
 
+def round_bf16(x):
+    """Round to the nearest bfloat16 (8-bit significand, ties to even), via
+    the nearest float32 first; returned as float64.
+
+    bfloat16 is the upper half of an IEEE binary32: rounding keeps the top 16
+    bits of the float32 pattern, adding half of the dropped unit (0x8000)
+    minus one, plus the kept last bit, so that exact halves go to the even
+    neighbour.  Finite inputs only."""
+    b = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    kept = (b + np.uint64(0x7FFF) + ((b >> np.uint64(16)) & np.uint64(1))) >> np.uint64(16)
+    return (kept.astype(np.uint32) << np.uint32(16)).view(np.float32).astype(np.float64)
+
+
 def mttkrp_dense(X, factors, mode):
     """Matricised tensor times Khatri-Rao product for a dense tensor.
 

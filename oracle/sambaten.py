@@ -151,7 +151,7 @@ def match(A_anchor, B_anchor, C_anchor, Ap, Bp, Cp_anchor):
 
 class Config:
     def __init__(self, rank, reps, als_iters, sample_factor, seed, tensor_id=0,
-                 init_iters=100, k_capacity=None, nnz_capacity=None):
+                 init_iters=100, k_capacity=None, nnz_capacity=None, summary_bf16=False):
         self.rank = int(rank)
         self.reps = int(reps)
         self.als_iters = int(als_iters)
@@ -162,6 +162,9 @@ class Config:
         self.init_iters = int(init_iters)
         self.k_capacity = k_capacity
         self.nnz_capacity = nnz_capacity
+        # dense summaries stored as bfloat16 (rounded to nearest even) before
+        # the decomposition and the row solve; everything else stays FP64
+        self.summary_bf16 = bool(summary_bf16)
 
 
 class NumericError(ValueError):
@@ -272,6 +275,8 @@ class OracleTensor:
             dims_s = (len(Is), len(Js), len(Kp))
             if self.fmt == DENSE:
                 Z = np.asarray(XY[np.ix_(Is, Js, Kp)], dtype=np.float64)
+                if cfg.summary_bf16:
+                    Z = cp.round_bf16(Z)
 
                 def mtt(F, mode, Z=Z):
                     return cp.mttkrp_dense(Z, F, mode)

@@ -50,6 +50,12 @@ struct sbt_tensor {
   uint32_t *err = nullptr, *pinv = nullptr, *cnt = nullptr;
   int32_t *idx = nullptr, *pi = nullptr, *valid = nullptr;
   void *Z = nullptr, *W = nullptr;
+  // BF16 summaries on the matrix cores (batched schedule)
+  bool mfma = false;
+  MfmaLayout ml{};
+  uint16_t *Zk = nullptr, *Zc = nullptr;
+  float* P3 = nullptr;  // mode-3 partial rows
+  int64_t sP3 = 0;
   double *Ap = nullptr, *Bp = nullptr, *Cp = nullptr, *GA = nullptr, *GB = nullptr, *GC = nullptr,
          *Gt = nullptr, *ones = nullptr, *lamp = nullptr, *M = nullptr, *At = nullptr,
          *Bt = nullptr, *Ct = nullptr, *M3 = nullptr, *nrm = nullptr, *fitv = nullptr,
@@ -256,7 +262,25 @@ sbt_status alloc_state(sbt_tensor* t) {
   SBT_TRY(dalloc(t, &t->pi, (size_t)r * R));
   SBT_TRY(dalloc(t, &t->valid, (size_t)r * R));
   RepSet rs = make_repset(t, t->Kpmax, 0, r);
-  if (t->fmt == SBT_DENSE) {
+  t->mfma = t->fmt == SBT_DENSE && t->sum_prec == kBF16 &&
+            c.schedule == SBT_SCHED_BATCHED && mfma_supported(t->n1, t->n2, R);
+  if (t->mfma) {
+    t->ml = mfma_layout(t->n1, t->n2, t->Kpmax);
+    RepSet r1 = rs;
+    r1.n3 = 1;
+    const int nsmax = mfma_mode3_splits(r1, t->ml);
+    t->sP3 = (int64_t)t->Kpmax * (R <= 16 ? 16 : 32);
+    SBT_TRY(dalloc(t, &t->Zk, (size_t)r * t->ml.sZk));
+    SBT_TRY(dalloc(t, &t->Zc, (size_t)r * t->ml.sZc));
+    SBT_TRY(dalloc(t, &t->P3, (size_t)r * nsmax * t->sP3));
+    SBT_TRY(dalloc_bytes(t, &t->W, (size_t)r * rs.sW * sizeof(float)));
+    // padding of Zk is never written by the gather: zero it once
+    hipError_t e = hipMemset(t->Zk, 0, sizeof(uint16_t) * (size_t)r * t->ml.sZk);
+    if (e != hipSuccess) {
+      set_err(t, hipGetErrorString(e));
+      return SBT_E_DEVICE;
+    }
+  } else if (t->fmt == SBT_DENSE) {
     SBT_TRY(dalloc_bytes(t, &t->Z, (size_t)r * rs.sZ * prec_bytes(t->sum_prec)));
     SBT_TRY(dalloc_bytes(t, &t->W, (size_t)r * rs.sW * acc_bytes(t->sum_prec)));
   }
@@ -550,10 +574,23 @@ sbt_status run_als(sbt_tensor* t, const void* Zp, RepSet rs, double* Ap, double*
   AlsTail ta;
   ta.sG = rs.sG;
   ta.pinv_count = t->pinv;
+  const bool mf = t->mfma && prec == kBF16;
+  const int kp32 = (rs.n3 + 31) / 32 * 32;
+  const int ns3 = mf ? mfma_mode3_splits(rs, t->ml) : 1;
+  const double pwm_bytes = (double)rs.nrep * rs.n1 * rs.n2 * (kp32 * 2.0 + rs.R * 4.0) +
+                           (double)rs.nrep * rs.n3 * rs.R * 8.0;
+  const double p3m_bytes = (double)rs.nrep * rs.n3 * t->ml.sk * 2.0 +
+                           (double)rs.nrep * rs.R * 8.0 * ((double)rs.n1 + rs.n2) +
+                           (double)rs.nrep * ns3 * rs.n3 * (rs.R <= 16 ? 16 : 32) * 4.0;
   for (int it = 0; it < iters; ++it) {
     int pq = prof_begin(t, st);
-    SBT_CK(launch_pw(prec, rs, Zp, Cp, ilC, W, st));
-    prof_end(t, pq, SBT_K_MTTKRP_C, pw_bytes, st);
+    if (mf) {
+      SBT_CK(launch_pw_mfma(rs, t->ml, t->Zc, Cp, ilC, (float*)W, st));
+      prof_end(t, pq, SBT_K_MTTKRP_C, pwm_bytes, st);
+    } else {
+      SBT_CK(launch_pw(prec, rs, Zp, Cp, ilC, W, st));
+      prof_end(t, pq, SBT_K_MTTKRP_C, pw_bytes, st);
+    }
     // mode 1: A
     SBT_CK(launch_cw(prec, rs, 0, W, Bp, ilB, Vinv, Ap, rs.sA, st));
     ta.U = Ap; ta.sU = rs.sA; ta.rows = rs.n1; ta.Gout = GA; ta.invlam_out = ilA;
@@ -566,8 +603,14 @@ sbt_status run_als(sbt_tensor* t, const void* Zp, RepSet rs, double* Ap, double*
     SBT_CK(launch_tail(rs, ta, st));
     // mode 3: C (lambda' = its column norms)
     pq = prof_begin(t, st);
-    SBT_CK(launch_p3(prec, rs, false, Zp, Ap, ilA, Bp, ilB, Vinv, nullptr, Cp, rs.sC, st));
-    prof_end(t, pq, SBT_K_MTTKRP_AB, p2_bytes, st);
+    if (mf) {
+      SBT_CK(launch_p3_mfma(rs, t->ml, ns3, t->Zk, Ap, ilA, Bp, ilB, t->P3, t->sP3, st));
+      prof_end(t, pq, SBT_K_MTTKRP_AB, p3m_bytes, st);
+      SBT_CK(launch_mode3_finish(rs, ns3, t->P3, t->sP3, Vinv, nullptr, Cp, rs.sC, st));
+    } else {
+      SBT_CK(launch_p3(prec, rs, false, Zp, Ap, ilA, Bp, ilB, Vinv, nullptr, Cp, rs.sC, st));
+      prof_end(t, pq, SBT_K_MTTKRP_AB, p2_bytes, st);
+    }
     ta.U = Cp; ta.sU = rs.sC; ta.rows = rs.n3; ta.Gout = GC; ta.invlam_out = ilC;
     ta.lam_out = lam_out; ta.Gx = GB; ta.Gy = GC; ta.Vinv_out = Vinv;
     SBT_CK(launch_tail(rs, ta, st));
@@ -701,7 +744,13 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
   const int64_t offJ = t->n1, offK = (int64_t)t->n1 + t->n2;
   RepSet all = make_repset(t, Kp, 0, r);
   const bool plain = c.schedule == SBT_SCHED_PLAIN;
-  if (t->fmt == SBT_DENSE) {
+  if (t->mfma) {
+    const int gq = prof_begin(t, st);
+    SBT_CK(launch_gather_mfma(t->store_prec, t->X, t->I, t->J, t->idx, t->idx_stride, offJ, offK,
+                              n3old, Kold, all, t->ml, t->Zk, t->Zc, st));
+    prof_end(t, gq, SBT_K_GATHER,
+             (double)r * t->n1 * t->n2 * Kp * (prec_bytes(t->store_prec) + 4.0), st);
+  } else if (t->fmt == SBT_DENSE) {
     const int gq = prof_begin(t, st);
     SBT_CK(launch_gather_dense(t->store_prec, t->sum_prec, t->X, t->I, t->J, t->idx,
                                t->idx_stride, offJ, offK, n3old, Kold, all, t->Z, st));
@@ -755,6 +804,13 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
       prof_end(t, rq, SBT_K_ROW_SOLVE, rbytes, st);
       SBT_CK(launch_solve(rs, Kp, t->M, t->Gt, rs.sG, t->ones, 0, t->Ct, rs.sC, nullptr, nullptr,
                           t->lam, 0, t->pinv, st));
+    } else if (t->mfma) {
+      SBT_CK(launch_inverse(rs, t->Gt, rs.sG, t->ones, 0, t->Vinv, t->pinv, st));
+      const int ns3 = mfma_mode3_splits(rs, t->ml);
+      SBT_CK(launch_p3_mfma(rs, t->ml, ns3, t->Zk, t->At, nullptr, t->Bt, nullptr, t->P3, t->sP3,
+                            st));
+      SBT_CK(launch_mode3_finish(rs, ns3, t->P3, t->sP3, t->Vinv, t->lam, t->Ct, rs.sC, st));
+      prof_end(t, rq, SBT_K_ROW_SOLVE, rbytes, st);
     } else {
       // V^-1 = Gt^-1, then one launch: rows of C~ = (Z_(3) (Bt kr At)) Gt^-1 / lambda
       SBT_CK(launch_inverse(rs, t->Gt, rs.sG, t->ones, 0, t->Vinv, t->pinv, st));
@@ -1212,6 +1268,46 @@ sbt_status sbt_mttkrp_dense(int32_t precision, const void* Z_dev, int64_t n1, in
   rs.sM = 0;
   rs.sG = (int64_t)R * R;
   rs.nsplit = 1;
+  if (prec == kBF16 && mfma_supported(rs.n1, rs.n2, R)) {
+    // the kernels of the batched BF16 update: relayout, then pass W and the
+    // mode-1/2 contraction, or the mode-3 kernel and its finish, with V = I
+    if ((mode != 0 && !U0_dev) || (mode != 1 && !U1_dev) || (mode != 2 && !U2_dev))
+      return SBT_E_INVALID;
+    const MfmaLayout L = mfma_layout(rs.n1, rs.n2, rs.n3);
+    rs.sZ = 0;
+    std::vector<double> eye((size_t)R * R, 0.0), one((size_t)3 * R, 1.0);
+    for (int f = 0; f < R; ++f) eye[(size_t)f * R + f] = 1.0;
+    uint16_t *Zk = nullptr, *Zc = nullptr;
+    double *I_dev = nullptr, *one_dev = nullptr;
+    void* W = nullptr;
+    float* P = nullptr;
+    const int ns = mfma_mode3_splits(rs, L);
+    const int64_t sP = (int64_t)rs.n3 * (R <= 16 ? 16 : 32);
+    SBT_CK(hipMallocAsync((void**)&Zk, sizeof(uint16_t) * L.sZk, st));
+    SBT_CK(hipMallocAsync((void**)&Zc, sizeof(uint16_t) * L.sZc, st));
+    SBT_CK(hipMallocAsync((void**)&I_dev, sizeof(double) * eye.size(), st));
+    SBT_CK(hipMallocAsync((void**)&one_dev, sizeof(double) * one.size(), st));
+    SBT_CK(hipMallocAsync(&W, sizeof(float) * rs.sW, st));
+    SBT_CK(hipMallocAsync((void**)&P, sizeof(float) * ns * sP, st));
+    SBT_CK(hipMemsetAsync(Zk, 0, sizeof(uint16_t) * L.sZk, st));
+    SBT_CK(hipMemcpyAsync(I_dev, eye.data(), sizeof(double) * eye.size(), hipMemcpyHostToDevice,
+                          st));
+    SBT_CK(hipMemcpyAsync(one_dev, one.data(), sizeof(double) * one.size(),
+                          hipMemcpyHostToDevice, st));
+    SBT_CK(launch_relayout_bf16((const uint16_t*)Z_dev, rs, L, Zk, Zc, st));
+    if (mode == 2) {
+      SBT_CK(launch_p3_mfma(rs, L, ns, Zk, U0_dev, nullptr, U1_dev, nullptr, P, sP, st));
+      SBT_CK(launch_mode3_finish(rs, ns, P, sP, I_dev, nullptr, out_dev, 0, st));
+    } else {
+      SBT_CK(launch_pw_mfma(rs, L, Zc, U2_dev, nullptr, (float*)W, st));
+      SBT_CK(launch_cw(kF32, rs, mode, W, mode == 0 ? U1_dev : U0_dev, one_dev, I_dev, out_dev,
+                       0, st));
+    }
+    SBT_CK(hipStreamSynchronize(st));  // the host vectors above are read by the copies
+    void* frees[] = {Zk, Zc, I_dev, one_dev, W, P};
+    for (void* q : frees) SBT_CK(hipFreeAsync(q, st));
+    return SBT_OK;
+  }
   if (mode == 2) {
     if (!U0_dev || !U1_dev) return SBT_E_INVALID;
     SBT_CK(launch_p2(prec, rs, Z_dev, U0_dev, U1_dev, out_dev, st));

@@ -59,7 +59,6 @@ __device__ inline void ldv(const uint16_t* p, float (&o)[2]) {
 __device__ inline void ldv(const uint16_t* p, float (&o)[1]) { o[0] = bf16_to_f32(*p); }
 
 constexpr int ku_of(int V) { return 32 / V; }  // summary elements in flight per thread
-constexpr int kChunk = 64;                      // factor rows staged per LDS chunk
 constexpr int kTailBuf = 2304;                  // doubles; >= 2 x 32 x 33 (Jacobi scratch)
 constexpr int kLd = kMaxRank + 1;
 

@@ -74,6 +74,41 @@ hipError_t launch_gather_dense(int store_prec, int sum_prec, const void* X, int6
                                int64_t offJ, int64_t offK, int n3old, int64_t Kold,
                                const RepSet& rs, void* Z, hipStream_t s);
 
+// ---- BF16 summaries on the matrix cores ----------------------------------
+// Zk[rep][c][a + ld1 b] (slice stride sk) and Zc[rep][a + n1 b][c] (row
+// stride ldc); padding entries are zero.
+struct MfmaLayout {
+  int ld1;      // n1 rounded up to 8
+  int64_t sk;   // Zk slice stride: ld1 * n2 rounded up to 32
+  int ldc;      // Zc row stride: largest K' rounded up to 32
+  int64_t sZk;  // per repetition
+  int64_t sZc;
+};
+MfmaLayout mfma_layout(int n1, int n2, int kpmax);
+// whether the MFMA kernels' LDS staging fits these summary shapes
+bool mfma_supported(int n1, int n2, int R);
+// number of K ranges of the mode-3 kernel
+int mfma_mode3_splits(const RepSet& rs, const MfmaLayout& L);
+hipError_t launch_gather_mfma(int store_prec, const void* X, int64_t I, int64_t J,
+                              const int32_t* idx, int64_t idx_stride, int64_t offJ, int64_t offK,
+                              int n3old, int64_t Kold, const RepSet& rs, const MfmaLayout& L,
+                              uint16_t* Zk, uint16_t* Zc, hipStream_t s);
+// one repetition from a column-major BF16 tensor (no sampling)
+hipError_t launch_relayout_bf16(const uint16_t* Z, const RepSet& rs, const MfmaLayout& L,
+                                uint16_t* Zk, uint16_t* Zc, hipStream_t s);
+// W(e, f) = sum_c Zc(e, c) C~(c, f), C~ = C diag(invlamC) (invlamC may be null)
+hipError_t launch_pw_mfma(const RepSet& rs, const MfmaLayout& L, const uint16_t* Zc,
+                          const double* Cf, const double* invlamC, float* W, hipStream_t s);
+// partial rows of Zk (B~ kr A~) over nsplit K ranges into P[rep][split] (stride sP,
+// row stride 16 or 32)
+hipError_t launch_p3_mfma(const RepSet& rs, const MfmaLayout& L, int nsplit, const uint16_t* Zk,
+                          const double* Af, const double* invlamA, const double* Bf,
+                          const double* invlamB, float* P, int64_t sP, hipStream_t s);
+// U(c, :) = (sum_split P) V^-1 [/ lam_div]
+hipError_t launch_mode3_finish(const RepSet& rs, int nsplit, const float* P, int64_t sP,
+                               const double* Vinv, const double* lam_div, double* U, int64_t sU,
+                               hipStream_t s);
+
 // ---- CP-ALS on the summaries --------------------------------------------
 // B', C' <- U[0,1) from Philox counters (row, col, tag(stream, mode, rep), t)
 hipError_t launch_als_init(const RepSet& rs, uint64_t seed, uint32_t tensor_id, uint32_t stream,

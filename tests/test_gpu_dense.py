@@ -21,14 +21,15 @@ def _torch():
 
 
 def run_pair(lib, I, J, K0, Kn, R, reps, iters, s, seed, prec, batches=1, init="oracle",
-             schedule=None, noise=0.01):
-    """Oracle and GPU side by side on one synthetic tensor; yields per-batch debug."""
+             schedule=None, noise=0.01, oracle_bf16=False):
+    """Oracle and GPU side by side on one synthetic tensor; yields per-batch debug.
+    oracle_bf16: the oracle rounds its summaries to bfloat16 as the BF16 path does."""
     torch = _torch()
     dtype = np.float64 if prec == lib.SBT_P_F64 else np.float32
     gen = synth.DenseCP(I, J, K0 + batches * Kn, R, seed=seed, noise=noise, dtype=dtype)
     X = gen.slices(0, K0 + batches * Kn)
     ocfg = osb.Config(rank=R, reps=reps, als_iters=iters, sample_factor=s, seed=seed,
-                      k_capacity=K0 + batches * Kn, init_iters=60)
+                      k_capacity=K0 + batches * Kn, init_iters=60, summary_bf16=oracle_bf16)
     if init == "oracle":
         ora = osb.OracleTensor(ocfg, osb.DENSE, (I, J, K0), X0=X[:, :, :K0])
     else:
@@ -182,20 +183,83 @@ def test_numeric_error_leaves_state_unchanged(lib):
     assert gpu.shape()[2] == K0 + Kn and gpu.batch_counter() == 1
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-5)])
+def bf16_round(x):
+    """float32 values rounded to the nearest bfloat16 (ties to even), as
+    (uint16 bits, float64 values)."""
+    b = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = (b + 0x7FFF + ((b >> 16) & 1)) >> 16
+    bits = r.astype(np.uint16)
+    vals = (r.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    return bits, vals
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-5), (2, 1e-2)])
 @pytest.mark.parametrize("mode", [0, 1, 2])
 def test_mttkrp_kernel_relative_error(lib, prec, tol, mode):
+    # BF16 (prec 2) runs the matrix-core kernels: n1 = 97 exercises the padding
     torch = _torch()
     g = np.random.default_rng(100 + mode)
     n1, n2, n3, R = 97, 61, 45, 10
     Z = g.random((n1, n2, n3))
     U = [g.random((n, R)) for n in (n1, n2, n3)]
-    dtype = np.float64 if prec == 0 else np.float32
-    Zd = lib.dense_to_device(Z, dtype)
+    if prec == 2:
+        bits, Zr = bf16_round(Z)
+        Zd = torch.from_numpy(np.ascontiguousarray(bits.transpose(2, 1, 0)).view(np.int16)).cuda()
+    else:
+        dtype = np.float64 if prec == 0 else np.float32
+        Zd = lib.dense_to_device(Z, dtype)
+        Zr = Z.astype(dtype).astype(np.float64)
     Ud = [torch.from_numpy(np.ascontiguousarray(u)).cuda() for u in U]
     out = torch.zeros((Z.shape[mode], R), dtype=torch.float64, device="cuda")
     lib.mttkrp_dense(prec, Zd, n1, n2, n3, R, Ud[0], Ud[1], Ud[2], mode, out)
     torch.cuda.synchronize()
-    ref = cp.mttkrp_dense(Z.astype(dtype).astype(np.float64), U, mode)
+    ref = cp.mttkrp_dense(Zr, U, mode)
     rel = np.linalg.norm(out.cpu().numpy() - ref) / np.linalg.norm(ref)
     assert rel <= tol, rel
+
+
+@pytest.mark.parametrize("R", [5, 20])
+def test_mttkrp_bf16_rank_tiles(lib, R):
+    # one (R <= 16) and two (R > 16) column tiles of the matrix-core kernels
+    torch = _torch()
+    g = np.random.default_rng(300 + R)
+    n1, n2, n3 = 40, 33, 70
+    Z = g.random((n1, n2, n3))
+    U = [g.random((n, R)) for n in (n1, n2, n3)]
+    bits, Zr = bf16_round(Z)
+    Zd = torch.from_numpy(np.ascontiguousarray(bits.transpose(2, 1, 0)).view(np.int16)).cuda()
+    Ud = [torch.from_numpy(np.ascontiguousarray(u)).cuda() for u in U]
+    for mode in range(3):
+        out = torch.zeros((Z.shape[mode], R), dtype=torch.float64, device="cuda")
+        lib.mttkrp_dense(2, Zd, n1, n2, n3, R, Ud[0], Ud[1], Ud[2], mode, out)
+        torch.cuda.synchronize()
+        ref = cp.mttkrp_dense(Zr, U, mode)
+        rel = np.linalg.norm(out.cpu().numpy() - ref) / np.linalg.norm(ref)
+        assert rel <= 1e-2, (mode, rel)
+
+
+def test_bf16_update_matches_oracle(lib):
+    # BF16 summaries on the matrix cores, FP64 solves.  Bars: samples bit-exact;
+    # fit within 1e-3 of the FP64 oracle; new rows of C within 1e-3 of the
+    # oracle that rounds its summaries to BF16 the same way (the new rows
+    # themselves move by a few percent between FP64 and BF16 summaries: the
+    # summary ALS is ill conditioned for non-negative factors, the fit is not)
+    reps = 10
+    args = (100, 90, 60, 12, 10, reps, 30, 5, 2, lib.SBT_P_BF16)
+    ora16, gpu, ds = run_pair(lib, *args, batches=2, init="true", oracle_bf16=True)
+    check_samples(gpu, ds[-1], reps)
+    ora64, gpu64, _ = run_pair(lib, *args, batches=2, init="true")
+    _, _, C, _ = gpu.get_factors()
+    assert abs(gpu.fit() - ora64.fit()) < 1e-3
+    assert abs(gpu.fit() - ora16.fit()) < 1e-4
+    err = np.linalg.norm(C[60:] - ora16.C[60:]) / np.linalg.norm(ora16.C[60:])
+    assert err < 1e-3, err
+
+
+def test_bf16_rank20_ragged_update(lib):
+    # two column tiles, n1 not a multiple of 8, K' not a multiple of 32
+    reps = 4
+    ora, gpu, ds = run_pair(lib, 90, 76, 40, 9, 20, reps, 15, 3, 8, lib.SBT_P_BF16,
+                            batches=2, init="true", oracle_bf16=True)
+    check_samples(gpu, ds[-1], reps)
+    assert abs(gpu.fit() - ora.fit()) < 1e-3

@@ -180,3 +180,31 @@ def test_fms_identity_and_permutation():
     assert abs(cp.fms(A, B, C, lam, A, B, C, lam) - 1.0) < 1e-12
     p = [2, 0, 1]
     assert abs(cp.fms(A, B, C, lam, 2 * A[:, p], B[:, p], 0.5 * C[:, p], lam) - 1.0) < 1e-12
+
+
+def test_round_bf16_nearest_even():
+    # against the definition: the nearest of the representable neighbours
+    # (8 significant bits), ties to the one with an even last bit
+    g = np.random.default_rng(5)
+    x = np.concatenate([g.standard_normal(2000).astype(np.float32),
+                        np.float32([1.0, -1.0, 0.0, 3.0e38, 1e-30, 1.00390625, 1.01171875,
+                                    1.0078125, -1.00390625])])
+    got = cp.round_bf16(x)
+    for v, r in zip(x.astype(np.float64), got):
+        if v == 0.0:
+            assert r == 0.0
+            continue
+        m, e = np.frexp(abs(v))                # |v| = m 2^e, m in [0.5, 1)
+        ulp = 2.0 ** (e - 8)                   # 8 significant bits
+        lo = np.floor(abs(v) / ulp) * ulp
+        hi = lo + ulp
+        if abs(v) - lo < hi - abs(v):
+            want = lo
+        elif abs(v) - lo > hi - abs(v):
+            want = hi
+        else:
+            want = lo if int(round(lo / ulp)) % 2 == 0 else hi
+        assert r == np.copysign(want, v), (v, r, want)
+    # exact halves: 1 + 2^-8 goes down to 1, 1 + 3 * 2^-8 goes up to 1 + 2^-6
+    assert cp.round_bf16(np.float32(1.00390625)) == 1.0
+    assert cp.round_bf16(np.float32(1.01171875)) == 1.015625
