@@ -1,32 +1,43 @@
 #!/usr/bin/env python3
 """Benchmark of the SamBaTen batch update on one MI355X.
 
-Workload (dense FP32): an existing 500 x 500 x 500 tensor from a rank-10
-U[0,1) CP model plus 1% Gaussian noise, then update batches of 50 frontal
-slices; sampling factor s = 5, r = 10 repetitions, 30 ALS sweeps per summary.
-Inputs are synthetic (seeded generator), resident in HBM before timing; the
-model starts from the generator's factors (normalised).
+Workloads (--workload; all inputs seeded and synthetic, resident in HBM
+before timing, the model starting from the generator's factors):
 
-A step is one update (sampling, gather, CP-ALS on the r summaries, matching,
-row solve, append) of one 50-slice batch.  The timed region is exactly
---steps consecutive updates of one tensor; `value` is updated slices per
-second over it.  Both schedules of the library are timed: "batched" (every
-launch covers all repetitions, two summary passes per ALS sweep) gives
-`value`; "plain" (one launch sequence per repetition, three passes per sweep)
-is reported beside it.  Per-update latency p50/p99 comes from --latency-runs
-repetitions of the whole sequence.
+  dense500    (default) dense FP32 500 x 500 x 500, rank-10 U[0,1) CP model
+              plus 1% Gaussian noise, update batches of 50 frontal slices;
+              s = 5, r = 10, 30 ALS sweeps.  `value` is the batched FP32
+              schedule; the plain FP32 schedule and the batched BF16
+              (matrix-core) path run on the same batches beside it.
+  dense2000   dense 2000 x 2000 x 1000, rank 20, batches of 100 slices, s = 5,
+              r = 10, 30 sweeps: batched BF16 (matrix cores) = `value`, batched
+              FP32 and plain FP32 beside it.
+  sparse100k  COO 100000^3 with about 1e8 nonzeros (Zipf 1.1 popularity,
+              rank-10 nonnegative model), batches of 1000 slices with about
+              1e6 nonzeros, s = 10, r = 10, 30 sweeps.
 
-The roofline entry is the dominant kernel (by summed device time), timed live
-with HIP events on the launch stream, with its algorithmic bytes (summary
-elements read once + factor rows + outputs) per launch.  cpu_baseline times
-the CPU FP64 oracle on one update of the same workload.
+A step is one update (importance, sampling, summaries, CP-ALS on the r
+summaries, matching, row solve, append) of one batch.  The timed region is
+exactly --steps consecutive updates of one tensor, after --warmup updates of a
+throwaway copy; `value` is updated slices per second over it.  Per-update
+latency p50/p99 comes from --latency-runs repetitions of the whole sequence.
 
-    python bench.py [--gpus 1] [--steps 10] [--warmup 2]
+roofline: the dominant kernel (by summed device time over the timed updates),
+timed with HIP events recorded on the stream it runs on, with its algorithmic
+bytes per launch (summary elements read once, factor rows, outputs written
+once) against 8 TB/s; `traffic` comes from hardware counters of the same
+kernel when a committed measurement of the current kernel sources exists.
+cpu_baseline (dense workloads): the CPU FP64 oracle on the first
+--cpu-updates updates of the same workload.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--workload dense500]
 """
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -35,65 +46,84 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-WORKLOAD = dict(I=500, J=500, K0=500, Kn=50, R=10, s=5, r=10, iters=30, seed=2, noise=0.01)
+WORKLOADS = {
+    "dense500": dict(kind="dense", I=500, J=500, K0=500, Kn=50, R=10, s=5, r=10, iters=30,
+                     seed=2, noise=0.01,
+                     desc="dense FP32 500x500x500 + 50-slice batches, rank 10, s=5, r=10, "
+                          "30 ALS sweeps"),
+    "dense2000": dict(kind="dense", I=2000, J=2000, K0=1000, Kn=100, R=20, s=5, r=10,
+                      iters=30, seed=5, noise=0.01,
+                      desc="dense 2000x2000x1000 + 100-slice batches, rank 20, s=5, r=10, "
+                           "30 ALS sweeps, BF16 summaries on the matrix cores"),
+    "sparse100k": dict(kind="coo", I=100000, J=100000, K0=100000, Kn=1000, R=10, s=10,
+                       r=10, iters=30, seed=3, nnz0=100_000_000, nnz_b=1_000_000,
+                       desc="sparse COO 100000^3 with 1e8 nonzeros + 1000-slice batches of "
+                            "1e6 nonzeros, rank 10, s=10, r=10, 30 ALS sweeps"),
+}
 HBM_PEAK_GBS = 8000.0
+MFMA_BF16_PEAK_TFS = 2500.0
+
+KIND_NAMES = ("mttkrp_contract_c", "mttkrp_third_mode", "row_solve", "gather", "coo_mttkrp",
+              "update")
+
+
+def kernel_of(step, path, R):
+    """HIP kernel behind a timed launch kind."""
+    rp = (R + 3) // 4 * 4
+    nt = 1 if R <= 16 else 2
+    table = {
+        "f32": {"mttkrp_contract_c": f"pw_kernel<float, {rp}>",
+                "mttkrp_third_mode": f"p3_kernel<float, {rp}, 4, false>",
+                "row_solve": f"p3_kernel<float, {rp}, 4, true>",
+                "gather": "gather_dense_kernel<float, float>"},
+        "bf16": {"mttkrp_contract_c": f"pw_mfma_kernel<{nt}>",
+                 "mttkrp_third_mode": f"p3_mfma_kernel<{nt}>",
+                 "row_solve": f"p3_mfma_kernel<{nt}> + mode3_finish_kernel",
+                 "gather": "gather_mfma_kernel<float>"},
+        "coo": {"coo_mttkrp": f"coo_rows_kernel<{rp}>", "gather": "summary_emit_kernel"},
+    }
+    return table.get(path, {}).get(step, step)
 
 
 def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if xs else None
 
 
-def run_path(sbt, torch, Xd, model, schedule, steps, warmup, latency_runs, profile):
-    w = WORKLOAD
-    I, J, K0, Kn = w["I"], w["J"], w["K0"], w["Kn"]
-    cfg = sbt.make_config(w["R"], w["r"], w["iters"], w["s"], w["seed"],
-                          precision=sbt.SBT_P_F32, schedule=schedule,
-                          k_capacity=K0 + steps * Kn, max_batch=Kn)
-
-    def batch(b):
-        return Xd[K0 + b * Kn:K0 + (b + 1) * Kn]
-
-    def fresh():
-        return sbt.Tensor.init_dense(cfg, Xd[:K0], I, J, K0, factors=model)
-
-    # untimed warmup on a throwaway tensor
+def timed_sequence(sbt, torch, fresh, apply_batch, steps, warmup, latency_runs, Kn):
+    """Warm-up on a throwaway tensor, then exactly `steps` timed updates with the
+    per-kind launch timing on; extra untimed sequences for latency samples."""
+    kinds = {"mttkrp_contract_c": sbt.SBT_K_MTTKRP_C, "mttkrp_third_mode": sbt.SBT_K_MTTKRP_AB,
+             "row_solve": sbt.SBT_K_ROW_SOLVE, "gather": sbt.SBT_K_GATHER,
+             "coo_mttkrp": sbt.SBT_K_COO_MTTKRP, "update": sbt.SBT_K_UPDATE}
     T = fresh()
     for b in range(min(warmup, steps)):
-        T.update_batch_dense(batch(b), Kn)
+        apply_batch(T, b)
     T.close()
     torch.cuda.synchronize()
-
-    # timed region: exactly `steps` updates
     T = fresh()
-    if profile:
-        T.profile_enable(True)
+    T.profile_enable(True)
     torch.cuda.synchronize()
     lat = []
     t0 = time.perf_counter()
     for b in range(steps):
         ts = time.perf_counter()
-        T.update_batch_dense(batch(b), Kn)  # returns when the update is complete
+        apply_batch(T, b)  # returns when the update is complete
         lat.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     prof = {}
-    if profile:
-        for kind, name in ((sbt.SBT_K_MTTKRP_C, "mttkrp_contract_c"),
-                           (sbt.SBT_K_MTTKRP_AB, "mttkrp_third_mode"),
-                           (sbt.SBT_K_ROW_SOLVE, "row_solve"),
-                           (sbt.SBT_K_GATHER, "gather"), (sbt.SBT_K_UPDATE, "update")):
-            n, ms, by = T.profile_read(kind)
-            prof[name] = dict(launches=n, total_ms=ms, alg_bytes=by)
-        T.profile_enable(False)
+    for name in KIND_NAMES:
+        n, ms, by = T.profile_read(kinds[name])
+        prof[name] = dict(launches=n, total_ms=ms, alg_bytes=by)
+    T.profile_enable(False)
     fit = T.fit()
     T.close()
-    # extra untimed sequences for latency percentiles
     for _ in range(max(0, latency_runs - 1)):
         T = fresh()
         torch.cuda.synchronize()
         for b in range(steps):
             ts = time.perf_counter()
-            T.update_batch_dense(batch(b), Kn)
+            apply_batch(T, b)
             lat.append(time.perf_counter() - ts)
         T.close()
     return dict(slices_per_s=steps * Kn / wall, wall_s=wall, ms_per_step=1e3 * wall / steps,
@@ -101,17 +131,82 @@ def run_path(sbt, torch, Xd, model, schedule, steps, warmup, latency_runs, profi
                 latency_samples=len(lat), fit=fit, profile=prof)
 
 
-# HIP kernel behind each timed launch kind of the batched FP32 schedule
-KERNEL_OF = {"mttkrp_contract_c": "pw_kernel<float, 12, 1>",
-             "mttkrp_third_mode": "p3_kernel<float, 12, 4, false>",
-             "row_solve": "p3_kernel<float, 12, 4, true>",
-             "gather": "gather_dense_kernel<float, float>"}
+def run_dense(sbt, torch, w, Xd, model, precision, schedule, steps, warmup, latency_runs):
+    I, J, K0, Kn = w["I"], w["J"], w["K0"], w["Kn"]
+    cfg = sbt.make_config(w["R"], w["r"], w["iters"], w["s"], w["seed"], precision=precision,
+                          schedule=schedule, k_capacity=K0 + steps * Kn, max_batch=Kn)
+
+    def fresh():
+        return sbt.Tensor.init_dense(cfg, Xd[:K0], I, J, K0, factors=model)
+
+    def apply_batch(T, b):
+        T.update_batch_dense(Xd[K0 + b * Kn:K0 + (b + 1) * Kn], Kn)
+
+    return timed_sequence(sbt, torch, fresh, apply_batch, steps, warmup, latency_runs, Kn)
 
 
-def cpu_baseline(X, model, updates=2):
+def source_digest():
+    """Digest of the HIP sources (a counter measurement is valid for one digest)."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1709_00668_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from a committed counter summary
+    (profiles/<workload>_traffic.md), if taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_traffic.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"source digest: `([0-9a-f]+)`", text)
+    if not m or m.group(1) != source_digest():
+        return None
+    for line in text.splitlines():
+        cells = [c.strip().strip("`") for c in line.split("|")]
+        if len(cells) > 3 and cells[1] == kernel:
+            try:
+                return int(float(cells[-2]))
+            except ValueError:
+                return None
+    return None
+
+
+def roofline_of(prof, path, R, workload):
+    kernels = {k: v for k, v in prof.items() if k != "update" and v["launches"]}
+    dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
+    d = kernels[dom]
+    avg_ms = d["total_ms"] / d["launches"]
+    bytes_per_launch = d["alg_bytes"] / d["launches"]
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    kname = kernel_of(dom, path, R)
+    return dict(bound="hbm", kernel=kname, step=dom, achieved=round(achieved, 1),
+                peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
+                traffic=committed_traffic(kname, workload),
+                avg_launch_us=round(avg_ms * 1e3, 2), alg_bytes_per_launch=int(bytes_per_launch),
+                share_of_update_time=round(d["total_ms"] / prof["update"]["total_ms"], 3))
+
+
+def kernels_table(prof):
+    return {k: {"launches": v["launches"],
+                "avg_us": round(1e3 * v["total_ms"] / max(1, v["launches"]), 2),
+                "GB_s": round(v["alg_bytes"] / max(1e-12, v["total_ms"] * 1e-3) / 1e9, 1)}
+            for k, v in prof.items() if v["launches"]}
+
+
+def path_summary(res):
+    return {"value": round(res["slices_per_s"], 2), "unit": "slices/s",
+            "ms_per_step": round(res["ms_per_step"], 3), "p50_ms": round(res["p50_ms"], 3),
+            "p99_ms": round(res["p99_ms"], 3), "fit": round(res["fit"], 6)}
+
+
+def cpu_baseline_dense(w, X, model, updates):
     """The CPU FP64 oracle on the first `updates` updates of the same workload."""
     from oracle import sambaten as osb
-    w = WORKLOAD
     K0, Kn = w["K0"], w["Kn"]
     cfg = osb.Config(rank=w["R"], reps=w["r"], als_iters=w["iters"], sample_factor=w["s"],
                      seed=w["seed"], k_capacity=K0 + updates * Kn)
@@ -123,9 +218,127 @@ def cpu_baseline(X, model, updates=2):
     dt = time.perf_counter() - t0
     threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
     return dict(value=round(updates * Kn / dt, 3), unit="slices/s", cores=int(threads),
-                kind="oracle",
+                kind="oracle", fit_after=round(ora.fit(), 6),
                 sample=f"the first {updates} updates ({Kn} slices each, r={w['r']}, "
                        f"{w['iters']} ALS sweeps) of the same workload, {dt:.1f} s")
+
+
+def base_line(args, w, b, dtype):
+    cfg = {"workload": w["desc"]}
+    for k in ("I", "J", "K0", "Kn", "R", "s", "r", "iters"):
+        cfg[{"Kn": "batch", "R": "rank", "iters": "als_iters"}.get(k, k)] = w[k]
+    return {
+        "metric": "updated slices/sec (p50/p99 update latency, the plain schedule and the "
+                  "other precision alongside, at equal fit)",
+        "value": round(b["slices_per_s"], 2),
+        "unit": "slices/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(b["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": cfg,
+        "p50_ms": round(b["p50_ms"], 3),
+        "p99_ms": round(b["p99_ms"], 3),
+        "latency_samples": b["latency_samples"],
+        "fit": round(b["fit"], 6),
+    }
+
+
+def bench_dense(args, sbt, torch, synth, log):
+    name = args.workload
+    w = WORKLOADS[name]
+    steps = args.steps
+    I, J, K0, Kn = w["I"], w["J"], w["K0"], w["Kn"]
+    K = K0 + steps * Kn
+    gen = synth.DenseCP(I, J, K, w["R"], seed=w["seed"], noise=w["noise"], dtype=np.float32)
+    t0 = time.perf_counter()
+    Xkji = np.empty((K, J, I), dtype=np.float32)  # memory = column-major (I, J, K)
+    gen.fill_slices_kji(Xkji, 0, K)
+    Xd = torch.from_numpy(Xkji).cuda()
+    log(f"# data ready: {I}x{J}x{K} fp32, {Xkji.nbytes / 1e9:.2f} GB on device "
+        f"({time.perf_counter() - t0:.1f} s)")
+    model = gen.true_model_prefix(K0)
+    main_prec = sbt.SBT_P_F32 if name == "dense500" else sbt.SBT_P_BF16
+    order = [("batched_f32", sbt.SBT_P_F32, sbt.SBT_SCHED_BATCHED),
+             ("batched_bf16", sbt.SBT_P_BF16, sbt.SBT_SCHED_BATCHED)]
+    if not args.no_plain:
+        order.append(("plain_f32", sbt.SBT_P_F32, sbt.SBT_SCHED_PLAIN))
+    runs = {}
+    for key, prec, sched in order:
+        main = prec == main_prec and sched == sbt.SBT_SCHED_BATCHED
+        lr = args.latency_runs if main else max(1, min(args.latency_runs, 2))
+        runs[key] = run_dense(sbt, torch, w, Xd, model, prec, sched, steps, args.warmup, lr)
+        log(f"# {key}: {runs[key]['slices_per_s']:.1f} slices/s, fit {runs[key]['fit']:.6f}")
+    main = "batched_f32" if main_prec == sbt.SBT_P_F32 else "batched_bf16"
+    b = runs[main]
+    path = "f32" if main == "batched_f32" else "bf16"
+    line = base_line(args, w, b, path)
+    line["roofline"] = roofline_of(b["profile"], path, w["R"], name)
+    if path == "bf16":
+        # useful matrix-core work of the mode-3 pass: 2 |Z| R flops per summary
+        pr = b["profile"]["mttkrp_third_mode"]
+        if pr["launches"]:
+            Kp_mean = (w["K0"] + Kn * (steps - 1) / 2.0) / w["s"] + Kn
+            flops = 2.0 * w["r"] * (I / w["s"]) * (J / w["s"]) * Kp_mean * w["R"]
+            tfs = flops / (pr["total_ms"] / pr["launches"] * 1e-3) / 1e12
+            line["roofline"]["mfma_useful_tflops"] = round(tfs, 2)
+            line["roofline"]["mfma_frac"] = round(tfs / MFMA_BF16_PEAK_TFS, 5)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_dense(w, Xkji.transpose(2, 1, 0), model, args.cpu_updates)
+    line["cpu_baseline"] = cpu
+    for key in runs:
+        if key != main:
+            line[key] = path_summary(runs[key])
+    if "plain_f32" in runs:
+        line["over_plain_f32"] = round(b["slices_per_s"] / runs["plain_f32"]["slices_per_s"], 3)
+    line["kernels"] = kernels_table(b["profile"])
+    return line
+
+
+def bench_sparse(args, sbt, torch, synth, log):
+    name = args.workload
+    w = dict(WORKLOADS[name])
+    nnz0, nnzb = int(w["nnz0"] * args.nnz_scale), int(w["nnz_b"] * args.nnz_scale)
+    steps = args.steps
+    I, J, K0, Kn = w["I"], w["J"], w["K0"], w["Kn"]
+    t0 = time.perf_counter()
+    gen = synth.SparseCP(I, J, K0 + steps * Kn, w["R"], seed=w["seed"])
+    idx0, v0 = gen.slices(0, K0, nnz0, block_id=0)
+    model = synth.sparse_model(gen, K0, gen.last_mean)
+    batches = [gen.slices(K0 + b * Kn, K0 + (b + 1) * Kn, nnzb, block_id=b + 1)
+               for b in range(steps)]
+    cols0, vd0 = sbt.coo_to_device(idx0, v0)
+    bdev = [sbt.coo_to_device(ix, v) for ix, v in batches]
+    nnz_total = len(v0) + sum(len(v) for _, v in batches)
+    log(f"# data ready: {len(v0)} + {steps} x ~{nnzb} nonzeros "
+        f"({time.perf_counter() - t0:.1f} s)")
+    cfg = sbt.make_config(w["R"], w["r"], w["iters"], w["s"], w["seed"], fmt=sbt.SBT_COO,
+                          precision=sbt.SBT_P_F32, k_capacity=K0 + steps * Kn, max_batch=Kn,
+                          nnz_capacity=nnz_total)
+
+    def fresh():
+        return sbt.Tensor.init_coo(cfg, cols0, vd0, len(v0), I, J, K0, model)
+
+    def apply_batch(T, b):
+        c, v = bdev[b]
+        T.update_batch_coo(c, v, int(v.numel()), Kn)
+
+    res = timed_sequence(sbt, torch, fresh, apply_batch, steps, args.warmup,
+                         args.latency_runs, Kn)
+    log(f"# coo: {res['slices_per_s']:.1f} slices/s, fit {res['fit']:.6f}")
+    line = base_line(args, w, res, "f32")
+    line["config"]["nnz0"] = len(v0)
+    line["config"]["nnz_batch"] = nnzb
+    line["roofline"] = roofline_of(res["profile"], "coo", w["R"], name)
+    line["cpu_baseline"] = None
+    line["kernels"] = kernels_table(res["profile"])
+    return line
 
 
 def main():
@@ -134,8 +347,12 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--latency-runs", type=int, default=10)
+    ap.add_argument("--workload", default="dense500", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-updates", type=int, default=2)
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--nnz-scale", type=float, default=1.0,
+                    help="scale the nonzero counts of the sparse workload")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a kernel of "
                          "known traffic that calibrates hardware byte counters)")
@@ -153,6 +370,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
 
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
     if args.copy_probe_mib > 0:
         n = args.copy_probe_mib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -162,84 +382,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    w = WORKLOAD
-    steps = args.steps
-    I, J, K0, Kn = w["I"], w["J"], w["K0"], w["Kn"]
-    gen = synth.DenseCP(I, J, K0 + steps * Kn, w["R"], seed=w["seed"], noise=w["noise"],
-                        dtype=np.float32)
-    X = gen.slices(0, K0 + steps * Kn)
-    Xd = torch.from_numpy(np.ascontiguousarray(X.transpose(2, 1, 0))).cuda()
-    model = gen.true_model_prefix(K0)
-    print(f"# data ready: {X.shape} fp32, {X.nbytes / 1e9:.2f} GB on device", file=sys.stderr,
-          flush=True)
-
-    res = {}
-    res["batched"] = run_path(sbt, torch, Xd, model, sbt.SBT_SCHED_BATCHED, steps, args.warmup,
-                              args.latency_runs, profile=True)
-    print(f"# batched: {res['batched']['slices_per_s']:.1f} slices/s", file=sys.stderr,
-          flush=True)
-    if not args.no_plain:
-        res["plain"] = run_path(sbt, torch, Xd, model, sbt.SBT_SCHED_PLAIN, steps, args.warmup,
-                                args.latency_runs, profile=False)
-        print(f"# plain: {res['plain']['slices_per_s']:.1f} slices/s", file=sys.stderr,
-              flush=True)
-
-    # dominant kernel by summed device time
-    prof = res["batched"]["profile"]
-    kernels = {k: v for k, v in prof.items() if k != "update" and v["launches"]}
-    dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
-    d = kernels[dom]
-    avg_ms = d["total_ms"] / d["launches"]
-    bytes_per_launch = d["alg_bytes"] / d["launches"]
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    roofline = dict(bound="hbm", kernel=KERNEL_OF.get(dom, dom), step=dom,
-                    achieved=round(achieved, 1), peak=HBM_PEAK_GBS,
-                    unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                    avg_launch_us=round(avg_ms * 1e3, 2),
-                    alg_bytes_per_launch=int(bytes_per_launch),
-                    share_of_update_time=round(d["total_ms"] / prof["update"]["total_ms"], 3))
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(X, model)
-
-    b = res["batched"]
-    line = {
-        "metric": "updated slices/sec (batched path; p50/p99 update latency and the plain "
-                  "path alongside, at equal fit)",
-        "value": round(b["slices_per_s"], 2),
-        "unit": "slices/s",
-        "n_gpus": 1,
-        "steps": steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(b["ms_per_step"], 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "dense FP32 500x500x500 + 50-slice batches, rank 10, "
-                               "s=5, r=10, 30 ALS sweeps",
-                   "I": I, "J": J, "K0": K0, "batch": Kn, "rank": w["R"], "s": w["s"],
-                   "r": w["r"], "als_iters": w["iters"]},
-        "p50_ms": round(b["p50_ms"], 3),
-        "p99_ms": round(b["p99_ms"], 3),
-        "latency_samples": b["latency_samples"],
-        "fit": round(b["fit"], 6),
-        "roofline": roofline,
-        "cpu_baseline": cpu,
-    }
-    if "plain" in res:
-        p = res["plain"]
-        line["plain"] = {"value": round(p["slices_per_s"], 2), "unit": "slices/s",
-                         "p50_ms": round(p["p50_ms"], 3), "p99_ms": round(p["p99_ms"], 3),
-                         "fit": round(p["fit"], 6)}
-        line["batched_over_plain"] = round(b["slices_per_s"] / p["slices_per_s"], 3)
-    line["kernels"] = {k: {"launches": v["launches"], "avg_us": round(1e3 * v["total_ms"] /
-                                                                      max(1, v["launches"]), 2),
-                           "GB_s": round(v["alg_bytes"] / max(1e-12, v["total_ms"] * 1e-3) / 1e9,
-                                         1)}
-                       for k, v in prof.items()}
+    if WORKLOADS[args.workload]["kind"] == "coo":
+        line = bench_sparse(args, sbt, torch, synth, log)
+    else:
+        line = bench_dense(args, sbt, torch, synth, log)
     print(json.dumps(line))
 
 

@@ -71,6 +71,11 @@ struct sbt_tensor {
   int64_t* bbase = nullptr;
   CooScratch ing{};               // ingest scratch (grown on demand)
   CooSummary z{};                 // summaries (grown on demand)
+  CooUnits cu[3]{};               // MTTKRP work units per mode (grown with the summaries)
+  float* upart = nullptr;         // unit partial rows (RP floats per unit)
+  // cross products over many rows (Gram matrices, matching), all repetitions
+  double *xpart = nullptr, *xout = nullptr, *scl = nullptr;
+  int xnblk = 1;
   std::vector<void*> grow_allocs; // freed when regrown or destroyed
   int64_t last_summary_nnz = 0;
   // kernel timing (sbt_profile_*)
@@ -299,6 +304,19 @@ sbt_status alloc_state(sbt_tensor* t) {
   SBT_TRY(dalloc(t, &t->lamp, (size_t)r * R));
   SBT_TRY(dalloc(t, &t->Vinv, (size_t)r * rs.sG));
   SBT_TRY(dalloc(t, &t->invlam, (size_t)r * 3 * R));
+  {
+    int mr = t->n1 > t->n2 ? t->n1 : t->n2;
+    if (t->Kpmax > mr) mr = t->Kpmax;
+    int64_t mf = t->I > t->J ? t->I : t->J;
+    if (t->Kcap > mf) mf = t->Kcap;
+    t->xnblk = xprod_blocks(mr);
+    const int64_t fit_nblk = xprod_blocks((int)mf);
+    int64_t np = (int64_t)r * 9 * t->xnblk;
+    if (3 * fit_nblk > np) np = 3 * fit_nblk;
+    SBT_TRY(dalloc(t, &t->xpart, (size_t)np * R * R));
+    SBT_TRY(dalloc(t, &t->xout, (size_t)r * 9 * R * R));
+    SBT_TRY(dalloc(t, &t->scl, (size_t)r * 2 * R));
+  }
   SBT_TRY(dalloc(t, &t->M3, (size_t)t->Kcap * R));
   SBT_TRY(dalloc(t, &t->nrm, (size_t)t->Kcap));
   SBT_TRY(dalloc(t, &t->fitv, 1));
@@ -328,6 +346,11 @@ sbt_status alloc_state(sbt_tensor* t) {
     SBT_TRY(dalloc(t, &z.offB, (size_t)r * z.sOffB));
     SBT_TRY(dalloc(t, &z.offC, (size_t)r * z.sOffC));
     SBT_TRY(dalloc(t, &z.rep_off, 65));
+    const int64_t mrows[3] = {t->n1, t->n2, t->Kpmax};
+    for (int m = 0; m < 3; ++m) {
+      SBT_TRY(dalloc(t, &t->cu[m].cnt, (size_t)r * mrows[m]));
+      SBT_TRY(dalloc(t, &t->cu[m].uoff, (size_t)r * mrows[m] + 1));
+    }
   }
   void* h = nullptr;
   hipError_t e = hipHostMalloc(&h, 64, hipHostMallocDefault);
@@ -408,6 +431,23 @@ sbt_status ensure_summary(sbt_tensor* t, int64_t n, hipStream_t st) {
   SBT_CK(coo_sort_tmp_bytes(cap, &z.tmp_bytes));
   SBT_TRY(galloc(t, (char**)&z.tmp, z.tmp_bytes));
   z.cap = cap;
+  // work units: at most entries / unit + one per row, per mode
+  const int r = t->cfg.repetitions;
+  const int64_t mrows[3] = {t->n1, t->n2, t->Kpmax};
+  int64_t pmax = 0;
+  for (int m = 0; m < 3; ++m) {
+    CooUnits& u = t->cu[m];
+    gfree(t, u.urow);
+    gfree(t, u.ustart);
+    gfree(t, u.ulen);
+    u.cap = cap / kCooUnit + (int64_t)r * mrows[m] + 1;
+    SBT_TRY(galloc(t, &u.urow, (size_t)u.cap));
+    SBT_TRY(galloc(t, &u.ustart, (size_t)u.cap));
+    SBT_TRY(galloc(t, &u.ulen, (size_t)u.cap));
+    if (u.cap > pmax) pmax = u.cap;
+  }
+  gfree(t, t->upart);
+  SBT_TRY(galloc(t, &t->upart, (size_t)pmax * kMaxRank));
   return SBT_OK;
 }
 
@@ -445,6 +485,40 @@ sbt_status coo_build_summaries(sbt_tensor* t, int64_t Kold, int n3old, int Kp, h
   prof_end(t, gq, SBT_K_GATHER, (double)nnz_all * 16.0 + (double)total * 16.0, st);
   SBT_CK(launch_coo_offsets(z, r, t->n1, t->n2, Kp, st));
   SBT_CK(launch_coo_sorts(z, r, total, st));
+  RepSet rs = make_repset(t, Kp, 0, r);
+  for (int m = 0; m < 3; ++m) SBT_CK(launch_coo_units_build(rs, m, z, t->cu[m], st));
+  return SBT_OK;
+}
+
+// Gram matrices U^T U of `rows` rows for every repetition of rs into G (stride sG):
+// one block per repetition for short factors, the chunked cross-product
+// kernels for long ones.
+sbt_status gram_rows(sbt_tensor* t, const RepSet& rs, const double* U, int64_t sU, int rows,
+                     double* G, hipStream_t st) {
+  if (rows <= 256) {
+    SBT_CK(launch_gram(rs, U, sU, rows, G, st));
+    return SBT_OK;
+  }
+  XProd xp{};
+  xp.job[0] = XJob{U, sU, nullptr, 0, U, sU, nullptr, 0, rows};
+  xp.njobs = 1;
+  xp.R = rs.R;
+  xp.rep0 = rs.rep0;
+  xp.nrep = rs.nrep;
+  xp.nblk = t->xnblk;
+  xp.part = t->xpart;
+  xp.out = G;  // [rep][1][R*R]: stride R*R = sG
+  SBT_CK(launch_xprod(xp, st));
+  return SBT_OK;
+}
+
+// the tail of a mode update; long factors get their Gram matrix beforehand
+sbt_status tail(sbt_tensor* t, const RepSet& rs, AlsTail ta, hipStream_t st) {
+  if (!tail_rows_fit(ta.rows, rs.R)) {
+    SBT_TRY(gram_rows(t, rs, ta.U, ta.sU, ta.rows, t->xout, st));
+    ta.Gin = t->xout;
+  }
+  SBT_CK(launch_tail(rs, ta, st));
   return SBT_OK;
 }
 
@@ -457,8 +531,8 @@ sbt_status run_als_coo(sbt_tensor* t, RepSet rs, uint32_t t_ctr, hipStream_t st)
   double* ilC = t->invlam + 2 * R;
   SBT_CK(launch_als_init(rs, t->cfg.seed, t->cfg.tensor_id, kStreamAlsInit, t_ctr, t->Bp, t->Cp,
                          st));
-  SBT_CK(launch_gram(rs, t->Bp, rs.sB, rs.n2, t->GB, st));
-  SBT_CK(launch_gram(rs, t->Cp, rs.sC, rs.n3, t->GC, st));
+  SBT_TRY(gram_rows(t, rs, t->Bp, rs.sB, rs.n2, t->GB, st));
+  SBT_TRY(gram_rows(t, rs, t->Cp, rs.sC, rs.n3, t->GC, st));
   SBT_CK(launch_fill_f64(t->invlam + (int64_t)rs.rep0 * 3 * R, (int64_t)rs.nrep * 3 * R, 1.0,
                          st));
   SBT_CK(launch_inverse(rs, t->GB, rs.sG, t->GC, rs.sG, t->Vinv, t->pinv, st));
@@ -468,26 +542,32 @@ sbt_status run_als_coo(sbt_tensor* t, RepSet rs, uint32_t t_ctr, hipStream_t st)
   ta.pinv_count = t->pinv;
   for (int it = 0; it < t->cfg.als_iters; ++it) {
     int pq = prof_begin(t, st);
-    SBT_CK(launch_coo_rows(rs, 0, t->z, t->Bp, rs.sB, ilB, t->Cp, rs.sC, ilC, t->Vinv, nullptr,
-                           t->Ap, rs.sA, st));
+    SBT_CK(launch_coo_units(rs, 0, t->z, t->cu[0], t->Bp, rs.sB, ilB, t->Cp, rs.sC, ilC,
+                            t->upart, st));
     prof_end(t, pq, SBT_K_COO_MTTKRP, ebytes, st);
+    SBT_CK(launch_coo_units_finish(rs, 0, t->cu[0], t->upart, t->Vinv, nullptr, t->Ap, rs.sA,
+                                   st));
     ta.U = t->Ap; ta.sU = rs.sA; ta.rows = rs.n1; ta.Gout = t->GA; ta.invlam_out = ilA;
     ta.lam_out = nullptr; ta.Gx = t->GA; ta.Gy = t->GC; ta.Vinv_out = t->Vinv;
-    SBT_CK(launch_tail(rs, ta, st));
+    SBT_TRY(tail(t, rs, ta, st));
     pq = prof_begin(t, st);
-    SBT_CK(launch_coo_rows(rs, 1, t->z, t->Ap, rs.sA, ilA, t->Cp, rs.sC, ilC, t->Vinv, nullptr,
-                           t->Bp, rs.sB, st));
+    SBT_CK(launch_coo_units(rs, 1, t->z, t->cu[1], t->Ap, rs.sA, ilA, t->Cp, rs.sC, ilC,
+                            t->upart, st));
     prof_end(t, pq, SBT_K_COO_MTTKRP, ebytes, st);
+    SBT_CK(launch_coo_units_finish(rs, 1, t->cu[1], t->upart, t->Vinv, nullptr, t->Bp, rs.sB,
+                                   st));
     ta.U = t->Bp; ta.sU = rs.sB; ta.rows = rs.n2; ta.Gout = t->GB; ta.invlam_out = ilB;
     ta.lam_out = nullptr; ta.Gx = t->GA; ta.Gy = t->GB; ta.Vinv_out = t->Vinv;
-    SBT_CK(launch_tail(rs, ta, st));
+    SBT_TRY(tail(t, rs, ta, st));
     pq = prof_begin(t, st);
-    SBT_CK(launch_coo_rows(rs, 2, t->z, t->Ap, rs.sA, ilA, t->Bp, rs.sB, ilB, t->Vinv, nullptr,
-                           t->Cp, rs.sC, st));
+    SBT_CK(launch_coo_units(rs, 2, t->z, t->cu[2], t->Ap, rs.sA, ilA, t->Bp, rs.sB, ilB,
+                            t->upart, st));
     prof_end(t, pq, SBT_K_COO_MTTKRP, ebytes, st);
+    SBT_CK(launch_coo_units_finish(rs, 2, t->cu[2], t->upart, t->Vinv, nullptr, t->Cp, rs.sC,
+                                   st));
     ta.U = t->Cp; ta.sU = rs.sC; ta.rows = rs.n3; ta.Gout = t->GC; ta.invlam_out = ilC;
     ta.lam_out = t->lamp; ta.Gx = t->GB; ta.Gy = t->GC; ta.Vinv_out = t->Vinv;
-    SBT_CK(launch_tail(rs, ta, st));
+    SBT_TRY(tail(t, rs, ta, st));
   }
   SBT_CK(launch_normalize(rs, t->Ap, t->Bp, t->Cp, t->invlam, st));
   return SBT_OK;
@@ -527,8 +607,8 @@ sbt_status run_als(sbt_tensor* t, const void* Zp, RepSet rs, double* Ap, double*
                    bool plain, hipStream_t st) {
   const int prec = t->sum_prec;
   SBT_CK(launch_als_init(rs, t->cfg.seed, t->cfg.tensor_id, stream, t_ctr, Bp, Cp, st));
-  SBT_CK(launch_gram(rs, Bp, rs.sB, rs.n2, GB, st));
-  SBT_CK(launch_gram(rs, Cp, rs.sC, rs.n3, GC, st));
+  SBT_TRY(gram_rows(t, rs, Bp, rs.sB, rs.n2, GB, st));
+  SBT_TRY(gram_rows(t, rs, Cp, rs.sC, rs.n3, GC, st));
   const double zb = (double)rs.nrep * rs.n1 * rs.n2 * rs.n3 * prec_bytes(prec);
   const double p1_bytes = zb + (double)rs.nrep * rs.R *
                                    ((double)rs.n3 * 8 + (double)rs.n1 * rs.n2 * acc_bytes(prec));
@@ -595,12 +675,12 @@ sbt_status run_als(sbt_tensor* t, const void* Zp, RepSet rs, double* Ap, double*
     SBT_CK(launch_cw(prec, rs, 0, W, Bp, ilB, Vinv, Ap, rs.sA, st));
     ta.U = Ap; ta.sU = rs.sA; ta.rows = rs.n1; ta.Gout = GA; ta.invlam_out = ilA;
     ta.lam_out = nullptr; ta.Gx = GA; ta.Gy = GC; ta.Vinv_out = Vinv;
-    SBT_CK(launch_tail(rs, ta, st));
+    SBT_TRY(tail(t, rs, ta, st));
     // mode 2: B
     SBT_CK(launch_cw(prec, rs, 1, W, Ap, ilA, Vinv, Bp, rs.sB, st));
     ta.U = Bp; ta.sU = rs.sB; ta.rows = rs.n2; ta.Gout = GB; ta.invlam_out = ilB;
     ta.lam_out = nullptr; ta.Gx = GA; ta.Gy = GB; ta.Vinv_out = Vinv;
-    SBT_CK(launch_tail(rs, ta, st));
+    SBT_TRY(tail(t, rs, ta, st));
     // mode 3: C (lambda' = its column norms)
     pq = prof_begin(t, st);
     if (mf) {
@@ -613,7 +693,7 @@ sbt_status run_als(sbt_tensor* t, const void* Zp, RepSet rs, double* Ap, double*
     }
     ta.U = Cp; ta.sU = rs.sC; ta.rows = rs.n3; ta.Gout = GC; ta.invlam_out = ilC;
     ta.lam_out = lam_out; ta.Gx = GB; ta.Gy = GC; ta.Vinv_out = Vinv;
-    SBT_CK(launch_tail(rs, ta, st));
+    SBT_TRY(tail(t, rs, ta, st));
   }
   SBT_CK(launch_normalize(rs, Ap, Bp, Cp, invlam, st));
   return SBT_OK;
@@ -788,6 +868,33 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
     ma.Gt = t->Gt;
     ma.pi = t->pi;
     ma.valid = t->valid;
+    ma.xo = t->xout;
+    ma.scl = t->scl;
+    {
+      // anchor and sample cross products over the sampled rows
+      const int32_t* Is = t->idx;
+      const int32_t* Js = t->idx + offJ;
+      const int32_t* Ks = t->idx + offK;
+      const int64_t is = t->idx_stride;
+      XProd xp{};
+      xp.job[0] = XJob{t->A, 0, Is, is, t->Ap, rs.sA, nullptr, 0, rs.n1};
+      xp.job[1] = XJob{t->B, 0, Js, is, t->Bp, rs.sB, nullptr, 0, rs.n2};
+      xp.job[2] = XJob{t->C, 0, Ks, is, t->Cp, rs.sC, nullptr, 0, n3old};
+      xp.job[3] = XJob{t->A, 0, Is, is, t->A, 0, Is, is, rs.n1};
+      xp.job[4] = XJob{t->B, 0, Js, is, t->B, 0, Js, is, rs.n2};
+      xp.job[5] = XJob{t->C, 0, Ks, is, t->C, 0, Ks, is, n3old};
+      xp.job[6] = XJob{t->Ap, rs.sA, nullptr, 0, t->Ap, rs.sA, nullptr, 0, rs.n1};
+      xp.job[7] = XJob{t->Bp, rs.sB, nullptr, 0, t->Bp, rs.sB, nullptr, 0, rs.n2};
+      xp.job[8] = XJob{t->Cp, rs.sC, nullptr, 0, t->Cp, rs.sC, nullptr, 0, n3old};
+      xp.njobs = 9;
+      xp.R = R;
+      xp.rep0 = rs.rep0;
+      xp.nrep = rs.nrep;
+      xp.nblk = t->xnblk;
+      xp.part = t->xpart;
+      xp.out = t->xout;
+      SBT_CK(launch_xprod(xp, st));
+    }
     SBT_CK(launch_match(rs, ma, st));
     // row least squares: D = Z_(3) (Bt kr At) Gt^-1, C~ = D / lambda
     // Gt is already the Hadamard product; the second factor is all ones
@@ -796,9 +903,11 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
     const int rq = prof_begin(t, st);
     if (coo) {
       SBT_CK(launch_inverse(rs, t->Gt, rs.sG, t->ones, 0, t->Vinv, t->pinv, st));
-      SBT_CK(launch_coo_rows(rs, 2, t->z, t->At, rs.sA, nullptr, t->Bt, rs.sB, nullptr, t->Vinv,
-                             t->lam, t->Ct, rs.sC, st));
+      SBT_CK(launch_coo_units(rs, 2, t->z, t->cu[2], t->At, rs.sA, nullptr, t->Bt, rs.sB,
+                              nullptr, t->upart, st));
       prof_end(t, rq, SBT_K_COO_MTTKRP, (double)t->last_summary_nnz * 12.0, st);
+      SBT_CK(launch_coo_units_finish(rs, 2, t->cu[2], t->upart, t->Vinv, t->lam, t->Ct, rs.sC,
+                                     st));
     } else if (plain) {
       SBT_CK(launch_p2(t->sum_prec, rs, t->Z, t->At, t->Bt, t->M, st));
       prof_end(t, rq, SBT_K_ROW_SOLVE, rbytes, st);
@@ -1165,8 +1274,23 @@ sbt_status sbt_fit(sbt_tensor* t, double* fit, void* stream) {
     SBT_CK(launch_fit_coo(t->ci, t->cj, t->cv, t->koff, t->K, t->R, t->A, t->B, t->M3, t->nrm,
                           st));
   }
-  SBT_CK(launch_fit_final(t->A, t->B, t->C, t->lam, t->M3, t->nrm, t->I, t->J, t->K, t->R,
-                          t->fitv, st));
+  {
+    XProd xp{};
+    xp.job[0] = XJob{t->A, 0, nullptr, 0, t->A, 0, nullptr, 0, (int)t->I};
+    xp.job[1] = XJob{t->B, 0, nullptr, 0, t->B, 0, nullptr, 0, (int)t->J};
+    xp.job[2] = XJob{t->C, 0, nullptr, 0, t->C, 0, nullptr, 0, (int)t->K};
+    xp.njobs = 3;
+    xp.R = t->R;
+    xp.rep0 = 0;
+    xp.nrep = 1;
+    int64_t mf = t->I > t->J ? t->I : t->J;
+    if (t->Kcap > mf) mf = t->Kcap;
+    xp.nblk = xprod_blocks((int)mf);
+    xp.part = t->xpart;
+    xp.out = t->xout;
+    SBT_CK(launch_xprod(xp, st));
+  }
+  SBT_CK(launch_fit_final(t->xout, t->C, t->lam, t->M3, t->nrm, t->K, t->R, t->fitv, st));
   SBT_CK(hipMemcpyAsync(fit, t->fitv, sizeof(double), hipMemcpyDeviceToHost, st));
   SBT_CK(hipStreamSynchronize(st));
   return SBT_OK;

@@ -101,6 +101,7 @@ struct TailSmem {
 
 // Step outputs of one mode update (per repetition strides in elements).
 struct TailArgs {
+  const double* Gin;    // raw Gram of U given (stride sG), or null: computed here
   double* U;            // raw rows of the new factor
   int64_t sU;
   int rows;
@@ -296,7 +297,7 @@ __device__ void als_tail(const TailArgs& t, int rep, int R, TailSmem& s) {
   for (int j = 0; j < 3; ++j)
 #pragma unroll
     for (int u = 0; u < 4; ++u) gacc[j][u] = 0.0;
-  for (int r0 = 0; r0 < rows; r0 += crows) {
+  for (int r0 = 0; r0 < (t.Gin ? 0 : rows); r0 += crows) {
     const int cn = rows - r0 < crows ? rows - r0 : crows;
     const int n = cn * R;
     const double* src = U + (int64_t)r0 * R;
@@ -328,7 +329,9 @@ __device__ void als_tail(const TailArgs& t, int rep, int R, TailSmem& s) {
   }
   __syncthreads();
   // combine -> Gram of the raw factor in s.V
-  if (P <= kTailThreads) {
+  if (t.Gin) {
+    for (int q = tid; q < R * R; q += kTailThreads) s.V[q / R][q % R] = t.Gin[rep * t.sG + q];
+  } else if (P <= kTailThreads) {
     s.red[tid] = (gacc[0][0] + gacc[0][1]) + (gacc[0][2] + gacc[0][3]);
     __syncthreads();
     if (tid < P) {
@@ -793,9 +796,11 @@ hipError_t launch_normalize(const RepSet& rs, double* Ap, double* Bp, double* Cp
   return hipGetLastError();
 }
 
+bool tail_rows_fit(int rows, int R) { return (int64_t)rows * R <= kTailBuf; }
+
 hipError_t launch_tail(const RepSet& rs, const AlsTail& t, hipStream_t s) {
-  TailArgs ta{t.U, t.sU, t.rows, t.Gout, t.invlam_out, t.lam_out, t.Gx, t.Gy, t.Vinv_out,
-              t.sG, t.pinv_count};
+  TailArgs ta{t.Gin, t.U, t.sU, t.rows, t.Gout, t.invlam_out, t.lam_out, t.Gx, t.Gy,
+              t.Vinv_out, t.sG, t.pinv_count};
   SBT_RP_SWITCH(rs.R, { tail_kernel<RP><<<rs.nrep, kTailThreads, 0, s>>>(rs, ta); });
   return hipGetLastError();
 }

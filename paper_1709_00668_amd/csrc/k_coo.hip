@@ -326,6 +326,115 @@ __global__ __launch_bounds__(256) void coo_rows_kernel(
   }
 }
 
+// ---------------------------------------------------------------------------
+// MTTKRP over work units (pieces of at most kCooUnit entries of one row)
+// ---------------------------------------------------------------------------
+__global__ void coo_unit_count_kernel(const int64_t* off, int64_t sOff, int rows, int nrep,
+                                      uint32_t* cnt) {
+  const int64_t n = (int64_t)rows * nrep;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int rep = (int)(q / rows), row = (int)(q % rows);
+    const int64_t len = off[rep * sOff + row + 1] - off[rep * sOff + row];
+    cnt[q] = (uint32_t)((len + kCooUnit - 1) / kCooUnit);
+  }
+}
+
+__global__ void coo_unit_fill_kernel(const int64_t* off, int64_t sOff, int rows, int nrep,
+                                     const int64_t* uoff, int64_t cap, int32_t* urow,
+                                     int64_t* ustart, int32_t* ulen) {
+  const int64_t n = (int64_t)rows * nrep;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int rep = (int)(q / rows), row = (int)(q % rows);
+    const int64_t start = off[rep * sOff + row];
+    const int64_t len = off[rep * sOff + row + 1] - start;
+    const int64_t base = uoff[q], nu = uoff[q + 1] - base;
+    for (int64_t u = 0; u < nu && base + u < cap; ++u) {
+      urow[base + u] = (int32_t)q;
+      ustart[base + u] = start + u * kCooUnit;
+      const int64_t rem = len - u * kCooUnit;
+      ulen[base + u] = (int32_t)(rem < kCooUnit ? rem : kCooUnit);
+    }
+  }
+}
+
+// one wavefront per unit: partial row sum_e v * X~(x_e, :) * Y~(y_e, :)
+template <int RP>
+__global__ __launch_bounds__(256) void coo_units_kernel(
+    RepSet rs, int rows, const int32_t* urow, const int64_t* ustart, const int32_t* ulen,
+    const int64_t* ntot, int64_t cap, const int32_t* cx, const int32_t* cy, const float* cv, const double* X,
+    int64_t sX, const double* invlamX, const double* Y, int64_t sY, const double* invlamY,
+    float* part) {
+  const int lane = lane_id();
+  const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (gw >= *ntot || gw >= cap) return;
+  const int q = urow[gw];
+  const int rep = rs.rep0 + q / rows;
+  const int R = rs.R;
+  const double* Xr = X + rep * sX;
+  const double* Yr = Y + rep * sY;
+  float sx[RP], sy[RP];
+#pragma unroll
+  for (int f = 0; f < RP; ++f) {
+    sx[f] = (float)((f < R && invlamX) ? invlamX[rep * 3 * R + f] : 1.0);
+    sy[f] = (float)((f < R && invlamY) ? invlamY[rep * 3 * R + f] : 1.0);
+  }
+  float acc[RP];
+#pragma unroll
+  for (int f = 0; f < RP; ++f) acc[f] = 0.0f;
+  const int64_t b0 = ustart[gw], b1 = b0 + ulen[gw];
+  for (int64_t e = b0 + lane; e < b1; e += 64) {
+    const int32_t x = cx[e], y = cy[e];
+    const float v = cv[e];
+    const double* xr = Xr + (int64_t)x * R;
+    const double* yr = Yr + (int64_t)y * R;
+#pragma unroll
+    for (int f = 0; f < RP; ++f)
+      if (f < R) acc[f] += v * ((float)xr[f] * sx[f]) * ((float)yr[f] * sy[f]);
+  }
+#pragma unroll
+  for (int f = 0; f < RP; ++f) {
+    const float t = wave_sum(acc[f]);
+    if (lane == f) part[gw * RP + f] = t;
+  }
+}
+
+// rows of all repetitions: sum the unit partials of the row in order, times
+// V^-1 of the repetition, divided by lam_div for the row solve
+template <int RP>
+__global__ __launch_bounds__(256) void coo_units_finish_kernel(RepSet rs, int rows,
+                                                              const int64_t* uoff, int64_t cap,
+                                                              const float* part,
+                                                              const double* Vinv,
+                                                              const double* lam_div,
+                                                              double* Uout, int64_t sU) {
+  __shared__ double M[8][kMaxRank];
+  const int R = rs.R;
+  const int tid = threadIdx.x;
+  const int r = tid / kMaxRank, f = tid % kMaxRank;
+  const int64_t q = (int64_t)blockIdx.x * 8 + r;
+  const bool ok = q < (int64_t)rows * rs.nrep;
+  if (ok && f < R) {
+    double m = 0.0;
+    const int64_t u1 = uoff[q + 1] < cap ? uoff[q + 1] : cap;
+    for (int64_t u = uoff[q]; u < u1; ++u) m += (double)part[u * RP + f];
+    M[r][f] = m;
+  }
+  __syncthreads();
+  if (ok && f < R) {
+    const int rep = rs.rep0 + (int)(q / rows), row = (int)(q % rows);
+    const double* Vi = Vinv + rep * rs.sG;
+    double u = 0.0;
+    for (int k = 0; k < R; ++k) u += M[r][k] * Vi[k * R + f];
+    if (lam_div) {
+      const double l = lam_div[f];
+      u = l > 0.0 ? u / l : 0.0;
+    }
+    Uout[rep * sU + (int64_t)row * R + f] = u;
+  }
+}
+
 // fit over a k-sorted COO store: one wavefront per slice
 template <int RP>
 __global__ __launch_bounds__(256) void coo_fit_kernel(const int32_t* si, const int32_t* sj,
@@ -500,6 +609,71 @@ hipError_t launch_coo_sorts(CooSummary& z, int nrep, int64_t total, hipStream_t 
   if (e != hipSuccess) return e;
   summary_permute_kernel<<<grid_for(total, 256 * 16), 256, 0, s>>>(z.perm, total, z.a, z.c, z.v,
                                                                     z.b_x, z.b_y, z.b_v);
+  return hipGetLastError();
+}
+
+namespace {
+struct ModeView {
+  int rows;
+  const int64_t* off;
+  int64_t sOff;
+  const int32_t *cx, *cy;
+  const float* cv;
+};
+ModeView mode_view(const RepSet& rs, int mode, const CooSummary& z) {
+  ModeView m;
+  m.rows = mode == 0 ? rs.n1 : (mode == 1 ? rs.n2 : rs.n3);
+  m.off = mode == 0 ? z.offA : (mode == 1 ? z.offB : z.offC);
+  m.sOff = mode == 0 ? z.sOffA : (mode == 1 ? z.sOffB : z.sOffC);
+  m.cx = mode == 0 ? z.a_x : (mode == 1 ? z.b_x : z.a);
+  m.cy = mode == 0 ? z.a_y : (mode == 1 ? z.b_y : z.b);
+  m.cv = mode == 0 ? z.a_v : (mode == 1 ? z.b_v : z.v);
+  return m;
+}
+}  // namespace
+
+hipError_t launch_coo_units_build(const RepSet& rs, int mode, const CooSummary& z, CooUnits& u,
+                                  hipStream_t s) {
+  const ModeView m = mode_view(rs, mode, z);
+  const int64_t n = (int64_t)m.rows * rs.nrep;
+  const int blocks = grid_for(n, 256);
+  coo_unit_count_kernel<<<blocks, 256, 0, s>>>(m.off, m.sOff, m.rows, rs.nrep, u.cnt);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  scan_to_offsets_kernel<<<1, 1024, 0, s>>>(u.cnt, n, 0, u.uoff);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  coo_unit_fill_kernel<<<blocks, 256, 0, s>>>(m.off, m.sOff, m.rows, rs.nrep, u.uoff, u.cap,
+                                              u.urow, u.ustart, u.ulen);
+  return hipGetLastError();
+}
+
+hipError_t launch_coo_units(const RepSet& rs, int mode, const CooSummary& z, const CooUnits& u,
+                            const double* X, int64_t sX, const double* invlamX, const double* Y,
+                            int64_t sY, const double* invlamY, float* part, hipStream_t s) {
+  const ModeView m = mode_view(rs, mode, z);
+  const int64_t n = (int64_t)m.rows * rs.nrep;
+  if (u.cap <= 0) return hipSuccess;
+  const unsigned blocks = (unsigned)((u.cap + 3) / 4);
+  SBT_COO_RP(rs.R, {
+    coo_units_kernel<RP><<<blocks, 256, 0, s>>>(rs, m.rows, u.urow, u.ustart, u.ulen,
+                                                u.uoff + n, u.cap, m.cx, m.cy, m.cv, X, sX,
+                                                invlamX,
+                                                Y, sY, invlamY, part);
+  });
+  return hipGetLastError();
+}
+
+hipError_t launch_coo_units_finish(const RepSet& rs, int mode, const CooUnits& u,
+                                   const float* part, const double* Vinv, const double* lam_div,
+                                   double* U, int64_t sU, hipStream_t s) {
+  const int rows = mode == 0 ? rs.n1 : (mode == 1 ? rs.n2 : rs.n3);
+  const int64_t n = (int64_t)rows * rs.nrep;
+  const unsigned blocks = (unsigned)((n + 7) / 8);
+  SBT_COO_RP(rs.R, {
+    coo_units_finish_kernel<RP><<<blocks, 256, 0, s>>>(rs, rows, u.uoff, u.cap, part, Vinv,
+                                                       lam_div, U, sU);
+  });
   return hipGetLastError();
 }
 

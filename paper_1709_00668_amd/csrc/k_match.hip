@@ -20,41 +20,6 @@ __device__ inline void pair_fg2(int p, int R, int& f, int& g) {
 }
 
 // G = U^T U, one block.
-__device__ void block_gram2(const double* U, int rows, int R, double* G, double* red) {
-  const int P = R * (R + 1) / 2;
-  const int tid = threadIdx.x;
-  if (P >= 256) {
-    for (int p = tid; p < P; p += 256) {
-      int f, g;
-      pair_fg2(p, R, f, g);
-      double acc = 0.0;
-      for (int i = 0; i < rows; ++i) acc += U[(int64_t)i * R + f] * U[(int64_t)i * R + g];
-      G[f * kMaxRank + g] = acc;
-      G[g * kMaxRank + f] = acc;
-    }
-    __syncthreads();
-    return;
-  }
-  const int nsl = 256 / P;
-  const int pl = tid % P, sl = tid / P;
-  double acc = 0.0;
-  if (sl < nsl) {
-    int f, g;
-    pair_fg2(pl, R, f, g);
-    for (int i = sl; i < rows; i += nsl) acc += U[(int64_t)i * R + f] * U[(int64_t)i * R + g];
-  }
-  red[tid] = acc;
-  __syncthreads();
-  if (tid < P) {
-    double s = 0.0;
-    for (int q = 0; q < nsl; ++q) s += red[q * P + tid];
-    int f, g;
-    pair_fg2(tid, R, f, g);
-    G[f * kMaxRank + g] = s;
-    G[g * kMaxRank + f] = s;
-  }
-  __syncthreads();
-}
 
 // Maximum-weight perfect assignment on S (R x R, R <= 32) by the Hungarian
 // method with potentials, run by one wavefront: lane j owns column j
@@ -126,63 +91,32 @@ __device__ void hungarian_wave(const double (*S)[kMaxRank + 1], int R, int* pi) 
   if (lane >= 1 && lane <= R && p >= 1 && p <= R) pi[p - 1] = lane - 1;
 }
 
+// One block per repetition, on the R x R cross products only (computed over
+// the rows beforehand): norms, similarity, assignment, signs, the column
+// scales of the matched factors and Gt = (At^T At) .* (Bt^T Bt).
 __global__ __launch_bounds__(256) void match_kernel(RepSet rs, MatchArgs m) {
   const int rep = rs.rep0 + blockIdx.x;
-  const int R = rs.R, n1 = rs.n1, n2 = rs.n2, n3 = m.n3old;
+  const int R = rs.R, RR = R * R;
   const int tid = threadIdx.x;
-  const int32_t* Is = m.idx + rep * m.idx_stride;
-  const int32_t* Js = Is + m.offJ;
-  const int32_t* Ks = Is + m.offK;
-  const double* Ap = m.Ap + rep * rs.sA;
-  const double* Bp = m.Bp + rep * rs.sB;
-  const double* Cp = m.Cp + rep * rs.sC;
-  __shared__ double PA[kMaxRank][kMaxRank + 1], PB[kMaxRank][kMaxRank + 1];
-  __shared__ double PC[kMaxRank][kMaxRank + 1];
+  const double* xo = m.xo + (int64_t)rep * 9 * RR;
   __shared__ double S[kMaxRank][kMaxRank + 1];
   __shared__ double nrm[6][kMaxRank];  // A anchor, B anchor, C anchor, A', B', C'(anchor rows)
   __shared__ int pi_s[kMaxRank];
-  __shared__ double sigA[kMaxRank], sigB[kMaxRank];
-  __shared__ double red[256];
-  __shared__ double GA[kMaxRank * kMaxRank], GB[kMaxRank * kMaxRank];
-
-  // cross products and squared norms
-  const int nitem = 3 * R * R + 6 * R;
-  for (int q = tid; q < nitem; q += 256) {
-    double acc = 0.0;
-    if (q < 3 * R * R) {
-      const int which = q / (R * R), fg = q % (R * R), f = fg / R, g = fg % R;
-      if (which == 0) {
-        for (int a = 0; a < n1; ++a) acc += m.A[(int64_t)Is[a] * R + f] * Ap[(int64_t)a * R + g];
-        PA[f][g] = acc;
-      } else if (which == 1) {
-        for (int b = 0; b < n2; ++b) acc += m.B[(int64_t)Js[b] * R + f] * Bp[(int64_t)b * R + g];
-        PB[f][g] = acc;
-      } else {
-        for (int c = 0; c < n3; ++c) acc += m.C[(int64_t)Ks[c] * R + f] * Cp[(int64_t)c * R + g];
-        PC[f][g] = acc;
-      }
-    } else {
-      const int qq = q - 3 * R * R, which = qq / R, f = qq % R;
-      switch (which) {
-        case 0: for (int a = 0; a < n1; ++a) { const double x = m.A[(int64_t)Is[a] * R + f]; acc += x * x; } break;
-        case 1: for (int b = 0; b < n2; ++b) { const double x = m.B[(int64_t)Js[b] * R + f]; acc += x * x; } break;
-        case 2: for (int c = 0; c < n3; ++c) { const double x = m.C[(int64_t)Ks[c] * R + f]; acc += x * x; } break;
-        case 3: for (int a = 0; a < n1; ++a) { const double x = Ap[(int64_t)a * R + f]; acc += x * x; } break;
-        case 4: for (int b = 0; b < n2; ++b) { const double x = Bp[(int64_t)b * R + f]; acc += x * x; } break;
-        default: for (int c = 0; c < n3; ++c) { const double x = Cp[(int64_t)c * R + f]; acc += x * x; } break;
-      }
-      nrm[which][f] = sqrt(acc);
-    }
+  __shared__ double sA[kMaxRank], sB[kMaxRank];
+  if (tid < 6 * R) {
+    const int which = tid / R, f = tid % R;
+    const double d = xo[(3 + which) * RR + f * R + f];
+    nrm[which][f] = sqrt(d > 0.0 ? d : 0.0);
   }
   __syncthreads();
   // similarity: product over the modes of |cosine|
-  for (int q = tid; q < R * R; q += 256) {
+  for (int q = tid; q < RR; q += 256) {
     const int f = q / R, g = q % R;
     const double dA = nrm[0][f] * nrm[3][g], dB = nrm[1][f] * nrm[4][g],
                  dC = nrm[2][f] * nrm[5][g];
-    const double cA = dA > 0.0 ? PA[f][g] / dA : 0.0;
-    const double cB = dB > 0.0 ? PB[f][g] / dB : 0.0;
-    const double cC = dC > 0.0 ? PC[f][g] / dC : 0.0;
+    const double cA = dA > 0.0 ? xo[0 * RR + q] / dA : 0.0;
+    const double cB = dB > 0.0 ? xo[1 * RR + q] / dB : 0.0;
+    const double cC = dC > 0.0 ? xo[2 * RR + q] / dC : 0.0;
     const double sv = fabs(cA) * fabs(cB) * fabs(cC);
     S[f][g] = sv >= 0.0 ? sv : 0.0;  // a non-finite similarity counts as none
   }
@@ -193,31 +127,43 @@ __global__ __launch_bounds__(256) void match_kernel(RepSet rs, MatchArgs m) {
   __syncthreads();
   if (tid < R) {
     const int f = tid, g = pi_s[f];
-    sigA[f] = PA[f][g] < 0.0 ? -1.0 : 1.0;
-    sigB[f] = PB[f][g] < 0.0 ? -1.0 : 1.0;
+    const double sa = xo[0 * RR + f * R + g] < 0.0 ? -1.0 : 1.0;
+    const double sb = xo[1 * RR + f * R + g] < 0.0 ? -1.0 : 1.0;
+    // At(:, f) = sigA nA(f) A'(:, g) / ||A'(:, g)||, likewise Bt
+    sA[f] = nrm[3][g] > 0.0 ? sa * nrm[0][f] / nrm[3][g] : 0.0;
+    sB[f] = nrm[4][g] > 0.0 ? sb * nrm[1][f] / nrm[4][g] : 0.0;
+    m.scl[(int64_t)rep * 2 * R + f] = sA[f];
+    m.scl[(int64_t)rep * 2 * R + R + f] = sB[f];
     m.pi[rep * R + f] = g;
     m.valid[rep * R + f] = (nrm[0][f] > 0.0 && nrm[1][f] > 0.0) ? 1 : 0;
   }
   __syncthreads();
-  // matched sample columns, unit-normalised, in the units of A(I_s), B(J_s)
-  double* At = m.At + rep * rs.sA;
-  double* Bt = m.Bt + rep * rs.sB;
-  for (int64_t q = tid; q < (int64_t)n1 * R; q += 256) {
-    const int a = (int)(q / R), f = (int)(q % R), g = pi_s[f];
-    const double na = nrm[3][g];
-    At[q] = na > 0.0 ? sigA[f] * nrm[0][f] * (Ap[(int64_t)a * R + g] / na) : 0.0;
+  for (int q = tid; q < RR; q += 256) {
+    const int f = q / R, g = q % R, pf = pi_s[f], pg = pi_s[g];
+    const double ga = sA[f] * sA[g] * xo[6 * RR + pf * R + pg];
+    const double gb = sB[f] * sB[g] * xo[7 * RR + pf * R + pg];
+    m.Gt[rep * rs.sG + q] = ga * gb;
   }
-  for (int64_t q = tid; q < (int64_t)n2 * R; q += 256) {
-    const int b = (int)(q / R), f = (int)(q % R), g = pi_s[f];
-    const double nb = nrm[4][g];
-    Bt[q] = nb > 0.0 ? sigB[f] * nrm[1][f] * (Bp[(int64_t)b * R + g] / nb) : 0.0;
-  }
-  __syncthreads();
-  block_gram2(At, n1, R, GA, red);
-  block_gram2(Bt, n2, R, GB, red);
-  for (int q = tid; q < R * R; q += 256) {
-    const int f = q / R, g = q % R;
-    m.Gt[rep * rs.sG + q] = GA[f * kMaxRank + g] * GB[f * kMaxRank + g];
+}
+
+// matched, rescaled sample factors: At(a, f) = scale_A(f) A'(a, pi(f)), Bt likewise
+__global__ __launch_bounds__(256) void match_rows_kernel(RepSet rs, MatchArgs m) {
+  const int rep = rs.rep0 + blockIdx.y;
+  const int R = rs.R;
+  const int64_t na = (int64_t)rs.n1 * R, nb = (int64_t)rs.n2 * R;
+  const double* scl = m.scl + (int64_t)rep * 2 * R;
+  const int32_t* pi = m.pi + rep * R;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < na + nb;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    if (q < na) {
+      const int64_t a = q / R;
+      const int f = (int)(q % R);
+      m.At[rep * rs.sA + q] = scl[f] * m.Ap[rep * rs.sA + a * R + pi[f]];
+    } else {
+      const int64_t qq = q - na, b = qq / R;
+      const int f = (int)(qq % R);
+      m.Bt[rep * rs.sB + qq] = scl[R + f] * m.Bp[rep * rs.sB + b * R + pi[f]];
+    }
   }
 }
 
@@ -303,16 +249,14 @@ __global__ __launch_bounds__(256) void commit_kernel(CommitArgs c) {
   }
 }
 
-__global__ __launch_bounds__(256) void fit_final_kernel(const double* A, const double* B,
-                                                       const double* C, const double* lam,
-                                                       const double* M3, const double* nrm,
-                                                       int64_t I, int64_t J, int64_t K, int R,
+__global__ __launch_bounds__(256) void fit_final_kernel(const double* G3, const double* C,
+                                                       const double* lam, const double* M3,
+                                                       const double* nrm, int64_t K, int R,
                                                        double* fit) {
-  __shared__ double GA[kMaxRank * kMaxRank], GB[kMaxRank * kMaxRank], GC[kMaxRank * kMaxRank];
   __shared__ double red[256];
-  block_gram2(A, (int)I, R, GA, red);
-  block_gram2(B, (int)J, R, GB, red);
-  block_gram2(C, (int)K, R, GC, red);
+  const double* GA = G3;
+  const double* GB = G3 + R * R;
+  const double* GC = G3 + 2 * R * R;
   // <X, Xhat> and ||X||^2
   double inner = 0.0, nx = 0.0;
   for (int64_t q = threadIdx.x; q < K * R; q += 256) inner += lam[q % R] * C[q] * M3[q];
@@ -336,8 +280,7 @@ __global__ __launch_bounds__(256) void fit_final_kernel(const double* A, const d
     double xh = 0.0;
     for (int f = 0; f < R; ++f)
       for (int g = 0; g < R; ++g)
-        xh += lam[f] * lam[g] * GA[f * kMaxRank + g] * GB[f * kMaxRank + g] *
-              GC[f * kMaxRank + g];
+        xh += lam[f] * lam[g] * GA[f * R + g] * GB[f * R + g] * GC[f * R + g];
     double res2 = nx_t - 2.0 * inner_t + xh;
     if (res2 < 0.0) res2 = 0.0;
     *fit = 1.0 - sqrt(res2) / sqrt(nx_t);
@@ -381,6 +324,12 @@ __global__ __launch_bounds__(256) void sort_components_kernel(double* A, double*
 
 hipError_t launch_match(const RepSet& rs, const MatchArgs& m, hipStream_t s) {
   match_kernel<<<rs.nrep, 256, 0, s>>>(rs, m);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t n = (int64_t)(rs.n1 + rs.n2) * rs.R;
+  int blocks = (int)((n + 255) / 256);
+  if (blocks > 512) blocks = 512;
+  match_rows_kernel<<<dim3((unsigned)blocks, (unsigned)rs.nrep), 256, 0, s>>>(rs, m);
   return hipGetLastError();
 }
 
@@ -392,10 +341,10 @@ hipError_t launch_commit(const CommitArgs& c, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_fit_final(const double* A, const double* B, const double* C, const double* lam,
-                            const double* M3, const double* nrm, int64_t I, int64_t J, int64_t K,
-                            int R, double* fit, hipStream_t s) {
-  fit_final_kernel<<<1, 256, 0, s>>>(A, B, C, lam, M3, nrm, I, J, K, R, fit);
+hipError_t launch_fit_final(const double* G3, const double* C, const double* lam,
+                            const double* M3, const double* nrm, int64_t K, int R, double* fit,
+                            hipStream_t s) {
+  fit_final_kernel<<<1, 256, 0, s>>>(G3, C, lam, M3, nrm, K, R, fit);
   return hipGetLastError();
 }
 

@@ -142,6 +142,7 @@ hipError_t launch_solve(const RepSet& rs, int rows, const double* M, const doubl
 // Gram matrix, 1/lambda, optionally lambda, and V_next^-1 = (Gx .* Gy)^-1 for
 // the next step, all per repetition.
 struct AlsTail {
+  const double* Gin = nullptr;  // raw Gram of U per repetition (stride sG), or computed here
   double* U;
   int64_t sU;
   int rows;
@@ -175,8 +176,38 @@ hipError_t launch_p3(int prec, const RepSet& rs, bool row_solve, const void* Z, 
 // tail of a mode update: Gram, lambda, normalised Gram, next V^-1
 hipError_t launch_tail(const RepSet& rs, const AlsTail& t, hipStream_t s);
 
+// ---- cross products X^T Y (R x R) over many rows ------------------------------
+struct XJob {
+  const double* X;    // rows of X: X + rep * sX + (ix ? ix[rep * six + i] : i) * R
+  int64_t sX;
+  const int32_t* ix;
+  int64_t six;
+  const double* Y;    // likewise
+  int64_t sY;
+  const int32_t* iy;
+  int64_t siy;
+  int rows;
+};
+constexpr int kXJobs = 9;
+struct XProd {
+  XJob job[kXJobs];
+  int njobs, R, rep0, nrep;
+  int nblk;       // chunks the partial buffer holds per (rep, job)
+  double* part;   // [rep][job][nblk][R * R]
+  double* out;    // [rep][job][R * R]
+};
+// chunks needed for `max_rows` rows
+int xprod_blocks(int max_rows);
+hipError_t launch_xprod(XProd xp, hipStream_t s);
+// whether the tail stages all rows at once (else pass the Gram matrix in)
+bool tail_rows_fit(int rows, int R);
+
 // ---- matching, row solve inputs ------------------------------------------
 struct MatchArgs {
+  const double* xo;             // per repetition: A(Is)^T A', B(Js)^T B', C(Ks)^T C',
+                                // A(Is)^T A(Is), B(Js)^T B(Js), C(Ks)^T C(Ks), A'^T A',
+                                // B'^T B', C'^T C' (anchor rows), each R x R
+  double* scl;                  // per repetition 2R: column scales of At, Bt
   const double *A, *B, *C;      // current model (row-major)
   const int32_t* idx;           // per-repetition sampled indices
   int64_t idx_stride, offJ, offK;
@@ -232,6 +263,18 @@ struct CooSummary {   // the r summaries of one update, concatenated by repetiti
   size_t tmp_bytes;
   int64_t cap;              // entries allocated
 };
+// Work units of the sparse MTTKRP of one mode: every row's entry segment cut
+// into pieces of at most kCooUnit entries (heavy rows of skewed data are
+// spread over many wavefronts; the pieces are added back in order).
+constexpr int kCooUnit = 512;
+struct CooUnits {
+  uint32_t* cnt;     // units per (rep, row)                     [nrep * rows]
+  int64_t* uoff;     // exclusive scan of cnt, total at the end   [nrep * rows + 1]
+  int32_t* urow;     // rep * rows + row of each unit
+  int64_t* ustart;   // first entry of each unit
+  int32_t* ulen;     // entries of each unit
+  int64_t cap;       // units allocated
+};
 hipError_t coo_sort_tmp_bytes(int64_t n, size_t* bytes);
 int64_t coo_scan_blocks(int64_t nnz);
 // append a batch (k batch-relative) sorted by k at store position `base`;
@@ -260,6 +303,18 @@ hipError_t launch_coo_offsets(CooSummary& z, int nrep, int n1, int n2, int n3, h
 hipError_t launch_coo_sorts(CooSummary& z, int nrep, int64_t total, hipStream_t s);
 // rows of mode `mode` (0: A from B, C; 1: B from A, C; 2: C from A, B):
 // U = (COO MTTKRP) V^-1, or divided by lam_div (row solve)
+// unit table of one mode from the row offsets of the summaries
+hipError_t launch_coo_units_build(const RepSet& rs, int mode, const CooSummary& z, CooUnits& u,
+                                  hipStream_t s);
+// partial rows (RP floats per unit) of the MTTKRP of one mode; the launch
+// covers u.cap wavefronts, the ones past the device-side total return
+hipError_t launch_coo_units(const RepSet& rs, int mode, const CooSummary& z, const CooUnits& u,
+                            const double* X, int64_t sX, const double* invlamX, const double* Y,
+                            int64_t sY, const double* invlamY, float* part, hipStream_t s);
+// rows U(row, :) = (sum of the row's unit partials, in order) V^-1 [/ lam_div]
+hipError_t launch_coo_units_finish(const RepSet& rs, int mode, const CooUnits& u,
+                                   const float* part, const double* Vinv, const double* lam_div,
+                                   double* U, int64_t sU, hipStream_t s);
 hipError_t launch_coo_rows(const RepSet& rs, int mode, const CooSummary& z, const double* X,
                            int64_t sX, const double* invlamX, const double* Y, int64_t sY,
                            const double* invlamY, const double* Vinv, const double* lam_div,
@@ -274,9 +329,10 @@ hipError_t launch_fit_coo(const int32_t* ii, const int32_t* jj, const float* v,
                           const int64_t* koff, int64_t K, int R, const double* A,
                           const double* B, double* M3, double* nrm, hipStream_t s);
 // fit = 1 - sqrt(max(0, sum nrm - 2 <X,Xhat> + ||Xhat||^2)) / sqrt(sum nrm)
-hipError_t launch_fit_final(const double* A, const double* B, const double* C, const double* lam,
-                            const double* M3, const double* nrm, int64_t I, int64_t J, int64_t K,
-                            int R, double* fit, hipStream_t s);
+// G3: the Gram matrices of A, B, C (3 x R x R)
+hipError_t launch_fit_final(const double* G3, const double* C, const double* lam,
+                            const double* M3, const double* nrm, int64_t K, int R, double* fit,
+                            hipStream_t s);
 
 // ---- initial model ordering ----------------------------------------------
 // Order components by lam descending (ties: lower index first) in place.

@@ -55,6 +55,24 @@ class DenseCP:
                 out[:, :, k - k0] = S.astype(self.dtype)
         return out
 
+    def fill_slices_kji(self, out, k0, k1, workers=16):
+        """Slices k0..k1-1 written into out[k - k0] as (J, I) arrays: the
+        memory of `out` (shape (k1 - k0, J, I), C order) is then the
+        column-major layout of the (I, J, k1 - k0) tensor.  Values are those of
+        slices(); slices are produced in parallel."""
+        from concurrent.futures import ThreadPoolExecutor
+
+        def one(k):
+            S = (self.A * self.C[k][None, :]) @ self.B.T
+            if self.noise > 0:
+                S = S + self.sigma * _gen(self.seed, STREAM_NOISE, k).standard_normal(
+                    (self.I, self.J))
+            out[k - k0] = S.astype(self.dtype).T
+
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            list(ex.map(one, range(k0, k1)))
+        return out
+
     def true_model(self):
         """Ground-truth factors normalised to unit columns, weights in lambda,
         ordered by lambda descending."""
@@ -147,11 +165,21 @@ class SparseCP:
         full[:, 2] += k0
         v = self._model_values(full)
         mean = v.mean() if v.size else 1.0
+        self.last_mean = float(mean)
         v = v / mean
         if self.noise > 0 and v.size:
             sigma = self.noise * np.linalg.norm(v) / np.sqrt(v.size)
             v = v + sigma * g.standard_normal(v.size)
         return idx.astype(np.int32), v.astype(np.float32)
+
+
+def sparse_model(gen, K0, mean):
+    """Factors of a SparseCP block whose values were divided by `mean`: unit
+    columns A, B, C (C over the first K0 slices) and lambda, in SparseCP's
+    component order."""
+    A, B, C = gen.pa.T.copy(), gen.pb.T.copy(), gen.pc.T[:K0].copy()
+    nA, nB, nC = (np.linalg.norm(M, axis=0) for M in (A, B, C))
+    return A / nA, B / nB, C / nC, nA * nB * nC / mean
 
 
 def poisson_arrivals(n, rate, seed):
