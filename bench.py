@@ -80,7 +80,7 @@ def kernel_of(step, path, R):
                  "mttkrp_third_mode": f"p3_mfma_kernel<{nt}>",
                  "row_solve": f"p3_mfma_kernel<{nt}> + mode3_finish_kernel",
                  "gather": "gather_mfma_kernel<float>"},
-        "coo": {"coo_mttkrp": f"coo_rows_kernel<{rp}>", "gather": "summary_emit_kernel"},
+        "coo": {"coo_mttkrp": f"coo_units_kernel<{rp}>", "gather": "summary_emit_kernel"},
     }
     return table.get(path, {}).get(step, step)
 

@@ -73,6 +73,7 @@ struct sbt_tensor {
   CooSummary z{};                 // summaries (grown on demand)
   CooUnits cu[3]{};               // MTTKRP work units per mode (grown with the summaries)
   float* upart = nullptr;         // unit partial rows (RP floats per unit)
+  float *fA = nullptr, *fB = nullptr, *fC = nullptr;  // FP32 scaled factor copies
   // cross products over many rows (Gram matrices, matching), all repetitions
   double *xpart = nullptr, *xout = nullptr, *scl = nullptr;
   int xnblk = 1;
@@ -351,6 +352,9 @@ sbt_status alloc_state(sbt_tensor* t) {
       SBT_TRY(dalloc(t, &t->cu[m].cnt, (size_t)r * mrows[m]));
       SBT_TRY(dalloc(t, &t->cu[m].uoff, (size_t)r * mrows[m] + 1));
     }
+    SBT_TRY(dalloc(t, &t->fA, (size_t)r * t->n1 * kMaxRank));
+    SBT_TRY(dalloc(t, &t->fB, (size_t)r * t->n2 * kMaxRank));
+    SBT_TRY(dalloc(t, &t->fC, (size_t)r * t->Kpmax * kMaxRank));
   }
   void* h = nullptr;
   hipError_t e = hipHostMalloc(&h, 64, hipHostMallocDefault);
@@ -536,38 +540,40 @@ sbt_status run_als_coo(sbt_tensor* t, RepSet rs, uint32_t t_ctr, hipStream_t st)
   SBT_CK(launch_fill_f64(t->invlam + (int64_t)rs.rep0 * 3 * R, (int64_t)rs.nrep * 3 * R, 1.0,
                          st));
   SBT_CK(launch_inverse(rs, t->GB, rs.sG, t->GC, rs.sG, t->Vinv, t->pinv, st));
+  SBT_CK(launch_coo_prep(rs, rs.n2, t->Bp, rs.sB, nullptr, t->fB, st));
+  SBT_CK(launch_coo_prep(rs, rs.n3, t->Cp, rs.sC, nullptr, t->fC, st));
   const double ebytes = (double)t->last_summary_nnz * 12.0;
   AlsTail ta;
   ta.sG = rs.sG;
   ta.pinv_count = t->pinv;
   for (int it = 0; it < t->cfg.als_iters; ++it) {
     int pq = prof_begin(t, st);
-    SBT_CK(launch_coo_units(rs, 0, t->z, t->cu[0], t->Bp, rs.sB, ilB, t->Cp, rs.sC, ilC,
-                            t->upart, st));
+    SBT_CK(launch_coo_units(rs, 0, t->z, t->cu[0], t->fB, rs.n2, t->fC, rs.n3, t->upart, st));
     prof_end(t, pq, SBT_K_COO_MTTKRP, ebytes, st);
     SBT_CK(launch_coo_units_finish(rs, 0, t->cu[0], t->upart, t->Vinv, nullptr, t->Ap, rs.sA,
                                    st));
     ta.U = t->Ap; ta.sU = rs.sA; ta.rows = rs.n1; ta.Gout = t->GA; ta.invlam_out = ilA;
     ta.lam_out = nullptr; ta.Gx = t->GA; ta.Gy = t->GC; ta.Vinv_out = t->Vinv;
     SBT_TRY(tail(t, rs, ta, st));
+    SBT_CK(launch_coo_prep(rs, rs.n1, t->Ap, rs.sA, ilA, t->fA, st));
     pq = prof_begin(t, st);
-    SBT_CK(launch_coo_units(rs, 1, t->z, t->cu[1], t->Ap, rs.sA, ilA, t->Cp, rs.sC, ilC,
-                            t->upart, st));
+    SBT_CK(launch_coo_units(rs, 1, t->z, t->cu[1], t->fA, rs.n1, t->fC, rs.n3, t->upart, st));
     prof_end(t, pq, SBT_K_COO_MTTKRP, ebytes, st);
     SBT_CK(launch_coo_units_finish(rs, 1, t->cu[1], t->upart, t->Vinv, nullptr, t->Bp, rs.sB,
                                    st));
     ta.U = t->Bp; ta.sU = rs.sB; ta.rows = rs.n2; ta.Gout = t->GB; ta.invlam_out = ilB;
     ta.lam_out = nullptr; ta.Gx = t->GA; ta.Gy = t->GB; ta.Vinv_out = t->Vinv;
     SBT_TRY(tail(t, rs, ta, st));
+    SBT_CK(launch_coo_prep(rs, rs.n2, t->Bp, rs.sB, ilB, t->fB, st));
     pq = prof_begin(t, st);
-    SBT_CK(launch_coo_units(rs, 2, t->z, t->cu[2], t->Ap, rs.sA, ilA, t->Bp, rs.sB, ilB,
-                            t->upart, st));
+    SBT_CK(launch_coo_units(rs, 2, t->z, t->cu[2], t->fA, rs.n1, t->fB, rs.n2, t->upart, st));
     prof_end(t, pq, SBT_K_COO_MTTKRP, ebytes, st);
     SBT_CK(launch_coo_units_finish(rs, 2, t->cu[2], t->upart, t->Vinv, nullptr, t->Cp, rs.sC,
                                    st));
     ta.U = t->Cp; ta.sU = rs.sC; ta.rows = rs.n3; ta.Gout = t->GC; ta.invlam_out = ilC;
     ta.lam_out = t->lamp; ta.Gx = t->GB; ta.Gy = t->GC; ta.Vinv_out = t->Vinv;
     SBT_TRY(tail(t, rs, ta, st));
+    SBT_CK(launch_coo_prep(rs, rs.n3, t->Cp, rs.sC, ilC, t->fC, st));
   }
   SBT_CK(launch_normalize(rs, t->Ap, t->Bp, t->Cp, t->invlam, st));
   return SBT_OK;
@@ -903,8 +909,10 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
     const int rq = prof_begin(t, st);
     if (coo) {
       SBT_CK(launch_inverse(rs, t->Gt, rs.sG, t->ones, 0, t->Vinv, t->pinv, st));
-      SBT_CK(launch_coo_units(rs, 2, t->z, t->cu[2], t->At, rs.sA, nullptr, t->Bt, rs.sB,
-                              nullptr, t->upart, st));
+      SBT_CK(launch_coo_prep(rs, rs.n1, t->At, rs.sA, nullptr, t->fA, st));
+      SBT_CK(launch_coo_prep(rs, rs.n2, t->Bt, rs.sB, nullptr, t->fB, st));
+      SBT_CK(launch_coo_units(rs, 2, t->z, t->cu[2], t->fA, rs.n1, t->fB, rs.n2, t->upart,
+                              st));
       prof_end(t, rq, SBT_K_COO_MTTKRP, (double)t->last_summary_nnz * 12.0, st);
       SBT_CK(launch_coo_units_finish(rs, 2, t->cu[2], t->upart, t->Vinv, t->lam, t->Ct, rs.sC,
                                      st));

@@ -359,44 +359,81 @@ __global__ void coo_unit_fill_kernel(const int64_t* off, int64_t sOff, int rows,
   }
 }
 
-// one wavefront per unit: partial row sum_e v * X~(x_e, :) * Y~(y_e, :)
+// FP32 copies of the scaled factor rows the sparse MTTKRP gathers:
+// Xf[rep][row][RP] = X(row, :) diag(invlam) (zero beyond R)
+__global__ void coo_prep_kernel(RepSet rs, int rows, int RP, const double* X, int64_t sX,
+                                const double* invlam, float* Xf) {
+  const int rep = rs.rep0 + blockIdx.y;
+  const int R = rs.R;
+  const int64_t n = (int64_t)rows * RP;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = q / RP;
+    const int f = (int)(q % RP);
+    float v = 0.0f;
+    if (f < R) v = (float)(X[rep * sX + row * R + f] * (invlam ? invlam[rep * 3 * R + f] : 1.0));
+    Xf[(int64_t)rep * rows * RP + q] = v;
+  }
+}
+
+// 16 lanes per unit, 4 units per wavefront: partial row
+// sum_e v * Xf(x_e, :) * Yf(y_e, :).  Units are dealt to the eight XCDs in
+// contiguous ranges (workgroup b runs on XCD b mod 8), so each XCD's L2 holds
+// the factor rows of about one and a quarter repetitions.
+constexpr int kUnitLanes = 16;
+constexpr int kXcds = 8;
+
 template <int RP>
 __global__ __launch_bounds__(256) void coo_units_kernel(
-    RepSet rs, int rows, const int32_t* urow, const int64_t* ustart, const int32_t* ulen,
-    const int64_t* ntot, int64_t cap, const int32_t* cx, const int32_t* cy, const float* cv, const double* X,
-    int64_t sX, const double* invlamX, const double* Y, int64_t sY, const double* invlamY,
-    float* part) {
-  const int lane = lane_id();
-  const int64_t gw = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (gw >= *ntot || gw >= cap) return;
-  const int q = urow[gw];
-  const int rep = rs.rep0 + q / rows;
-  const int R = rs.R;
-  const double* Xr = X + rep * sX;
-  const double* Yr = Y + rep * sY;
-  float sx[RP], sy[RP];
-#pragma unroll
-  for (int f = 0; f < RP; ++f) {
-    sx[f] = (float)((f < R && invlamX) ? invlamX[rep * 3 * R + f] : 1.0);
-    sy[f] = (float)((f < R && invlamY) ? invlamY[rep * 3 * R + f] : 1.0);
-  }
+    RepSet rs, int rows, int rowsX, int rowsY, const int32_t* urow, const int64_t* ustart,
+    const int32_t* ulen, const int64_t* ntot, int64_t cap, const int32_t* cx, const int32_t* cy,
+    const float* cv, const float* Xf, const float* Yf, float* part) {
+  constexpr int G = 256 / kUnitLanes;  // units per block
+  const int64_t T = *ntot < cap ? *ntot : cap;
+  const int64_t per = (T + kXcds - 1) / kXcds;
+  const int xcd = blockIdx.x % kXcds;
+  const int64_t lb = blockIdx.x / kXcds;
+  const int grp = threadIdx.x / kUnitLanes, l = threadIdx.x % kUnitLanes;
+  const int64_t k = lb * G + grp;
+  const int64_t gu = xcd * per + k;
+  const bool ok = k < per && gu < T;
   float acc[RP];
 #pragma unroll
   for (int f = 0; f < RP; ++f) acc[f] = 0.0f;
-  const int64_t b0 = ustart[gw], b1 = b0 + ulen[gw];
-  for (int64_t e = b0 + lane; e < b1; e += 64) {
-    const int32_t x = cx[e], y = cy[e];
-    const float v = cv[e];
-    const double* xr = Xr + (int64_t)x * R;
-    const double* yr = Yr + (int64_t)y * R;
+  if (ok) {
+    const int q = urow[gu];
+    const int rep = rs.rep0 + q / rows;
+    const float* Xr = Xf + (int64_t)rep * rowsX * RP;
+    const float* Yr = Yf + (int64_t)rep * rowsY * RP;
+    const int64_t b0 = ustart[gu], b1 = b0 + ulen[gu];
+    for (int64_t e = b0 + l; e < b1; e += kUnitLanes) {
+      const float v = cv[e];
+      const float4* xr = reinterpret_cast<const float4*>(Xr + (int64_t)cx[e] * RP);
+      const float4* yr = reinterpret_cast<const float4*>(Yr + (int64_t)cy[e] * RP);
 #pragma unroll
-    for (int f = 0; f < RP; ++f)
-      if (f < R) acc[f] += v * ((float)xr[f] * sx[f]) * ((float)yr[f] * sy[f]);
+      for (int f4 = 0; f4 < RP / 4; ++f4) {
+        const float4 a = xr[f4], b = yr[f4];
+        acc[4 * f4 + 0] += v * a.x * b.x;
+        acc[4 * f4 + 1] += v * a.y * b.y;
+        acc[4 * f4 + 2] += v * a.z * b.z;
+        acc[4 * f4 + 3] += v * a.w * b.w;
+      }
+    }
   }
+  // reduce over the 16 lanes of the group (all lanes take part)
 #pragma unroll
   for (int f = 0; f < RP; ++f) {
-    const float t = wave_sum(acc[f]);
-    if (lane == f) part[gw * RP + f] = t;
+    float t = acc[f];
+    t += __shfl_xor(t, 1, kWave);
+    t += __shfl_xor(t, 2, kWave);
+    t += __shfl_xor(t, 4, kWave);
+    t += __shfl_xor(t, 8, kWave);
+    acc[f] = t;
+  }
+  if (ok) {
+#pragma unroll
+    for (int f = 0; f < RP; ++f)
+      if (l == (f % kUnitLanes)) part[gu * RP + f] = acc[f];
   }
 }
 
@@ -648,18 +685,30 @@ hipError_t launch_coo_units_build(const RepSet& rs, int mode, const CooSummary& 
   return hipGetLastError();
 }
 
+hipError_t launch_coo_prep(const RepSet& rs, int rows, const double* X, int64_t sX,
+                           const double* invlam, float* Xf, hipStream_t s) {
+  const int RP = rp_of4(rs.R);
+  const int64_t n = (int64_t)rows * RP;
+  int blocks = grid_for(n, 256);
+  if (blocks > 1024) blocks = 1024;
+  coo_prep_kernel<<<dim3((unsigned)blocks, (unsigned)rs.nrep), 256, 0, s>>>(rs, rows, RP, X, sX,
+                                                                          invlam, Xf);
+  return hipGetLastError();
+}
+
 hipError_t launch_coo_units(const RepSet& rs, int mode, const CooSummary& z, const CooUnits& u,
-                            const double* X, int64_t sX, const double* invlamX, const double* Y,
-                            int64_t sY, const double* invlamY, float* part, hipStream_t s) {
+                            const float* Xf, int rowsX, const float* Yf, int rowsY, float* part,
+                            hipStream_t s) {
   const ModeView m = mode_view(rs, mode, z);
   const int64_t n = (int64_t)m.rows * rs.nrep;
   if (u.cap <= 0) return hipSuccess;
-  const unsigned blocks = (unsigned)((u.cap + 3) / 4);
+  constexpr int G = 256 / kUnitLanes;
+  const int64_t per = (u.cap + kXcds - 1) / kXcds;
+  const unsigned blocks = (unsigned)(kXcds * ((per + G - 1) / G));
   SBT_COO_RP(rs.R, {
-    coo_units_kernel<RP><<<blocks, 256, 0, s>>>(rs, m.rows, u.urow, u.ustart, u.ulen,
-                                                u.uoff + n, u.cap, m.cx, m.cy, m.cv, X, sX,
-                                                invlamX,
-                                                Y, sY, invlamY, part);
+    coo_units_kernel<RP><<<blocks, 256, 0, s>>>(rs, m.rows, rowsX, rowsY, u.urow, u.ustart,
+                                                u.ulen, u.uoff + n, u.cap, m.cx, m.cy, m.cv, Xf,
+                                                Yf, part);
   });
   return hipGetLastError();
 }

@@ -306,11 +306,15 @@ hipError_t launch_coo_sorts(CooSummary& z, int nrep, int64_t total, hipStream_t 
 // unit table of one mode from the row offsets of the summaries
 hipError_t launch_coo_units_build(const RepSet& rs, int mode, const CooSummary& z, CooUnits& u,
                                   hipStream_t s);
-// partial rows (RP floats per unit) of the MTTKRP of one mode; the launch
-// covers u.cap wavefronts, the ones past the device-side total return
+// FP32 scaled copies of factor rows for the sparse MTTKRP: Xf[rep][row][RP]
+hipError_t launch_coo_prep(const RepSet& rs, int rows, const double* X, int64_t sX,
+                           const double* invlam, float* Xf, hipStream_t s);
+// partial rows (RP floats per unit) of the MTTKRP of one mode from the FP32
+// copies of the two other factors (rowsX, rowsY rows per repetition); the
+// launch covers u.cap units, the ones past the device-side total return
 hipError_t launch_coo_units(const RepSet& rs, int mode, const CooSummary& z, const CooUnits& u,
-                            const double* X, int64_t sX, const double* invlamX, const double* Y,
-                            int64_t sY, const double* invlamY, float* part, hipStream_t s);
+                            const float* Xf, int rowsX, const float* Yf, int rowsY, float* part,
+                            hipStream_t s);
 // rows U(row, :) = (sum of the row's unit partials, in order) V^-1 [/ lam_div]
 hipError_t launch_coo_units_finish(const RepSet& rs, int mode, const CooUnits& u,
                                    const float* part, const double* Vinv, const double* lam_div,
