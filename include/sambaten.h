@@ -214,6 +214,52 @@ sbt_status sbt_profile_enable(sbt_tensor* t, int32_t on);
 sbt_status sbt_profile_read(const sbt_tensor* t, int32_t kind, int64_t* launches,
                             double* total_ms, double* alg_bytes);
 
+/* --------------------------------------------------------------------------
+ * Serving loop (many resident tensors, update requests arriving over time).
+ *
+ * A server owns `slots` worker threads, each driving its own HIP stream, and a
+ * device staging pool of `staging_bytes`.  Requests are admitted in arrival
+ * order when a slot is free, the request's tensor has no update in flight
+ * (updates of one tensor apply in arrival order) and its batch fits the free
+ * staging memory; a request that does not fit yet lets later requests of
+ * other tensors start first.  On admission the batch is copied into the
+ * staging pool on the slot's stream and the update runs there; updates of
+ * different tensors overlap on the GPU.  Results equal those of the same
+ * updates applied one by one with sbt_update_batch_dense.
+ *
+ * Thread safety: every sbt_server_* call may come from any host thread.  A
+ * tensor handed to a server must not be used directly (update, get_factors,
+ * fit, destroy) while it has requests queued or running.
+ * ------------------------------------------------------------------------ */
+typedef struct sbt_server sbt_server;
+
+/* slots in 1..32; staging_bytes >= 256.  SBT_E_NOMEM if the pool cannot be
+ * allocated. */
+sbt_status sbt_server_create(int32_t slots, int64_t staging_bytes, sbt_server** out);
+
+/* Queue an update of the dense tensor `t` by Y_dev (device, column-major
+ * I x J x K_new in the tensor's store type).  Y_dev must hold its values
+ * when submitted (the work that writes it complete: the server's streams do
+ * not wait on the caller's), and stays valid until sbt_server_poll reports
+ * the request running or done.  *ticket
+ * identifies the request.  SBT_E_NOMEM if the batch is larger than the whole
+ * staging pool, SBT_E_STATE for a COO tensor, SBT_E_SHAPE for K_new < 1;
+ * errors of the update itself are reported by sbt_server_poll. */
+sbt_status sbt_server_submit_dense(sbt_server* s, sbt_tensor* t, const void* Y_dev,
+                                   int64_t K_new, uint64_t* ticket);
+
+/* State of a request: *state 0 queued, 1 running, 2 done; *result the status
+ * of the update once done; times in seconds since the server was created
+ * (submission, start, completion).  Any output pointer may be null. */
+sbt_status sbt_server_poll(sbt_server* s, uint64_t ticket, int32_t* state, sbt_status* result,
+                           double* t_submit, double* t_start, double* t_done);
+
+/* Block until every submitted request is done. */
+sbt_status sbt_server_drain(sbt_server* s);
+
+/* Drain, stop the workers and release the staging pool. */
+void sbt_server_destroy(sbt_server* s);
+
 /* Human-readable text for a status, and the last error message of a tensor. */
 const char* sbt_status_str(sbt_status s);
 const char* sbt_last_error(const sbt_tensor* t);

@@ -1458,3 +1458,10 @@ sbt_status sbt_mttkrp_dense(int32_t precision, const void* Z_dev, int64_t n1, in
 }
 
 }  // extern "C"
+
+namespace sbt {
+size_t store_elem_bytes(const sbt_tensor* t) {
+  if (!t || t->fmt != SBT_DENSE) return 0;
+  return prec_bytes(t->store_prec);
+}
+}  // namespace sbt

@@ -76,6 +76,13 @@ _SIGS = {
                                         _vp, _vp]),
     "sbt_profile_enable": (ctypes.c_int, [_vp, _i32]),
     "sbt_profile_read": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_i64), _pd, _pd]),
+    "sbt_server_create": (ctypes.c_int, [_i32, _i64, ctypes.POINTER(_vp)]),
+    "sbt_server_submit_dense": (ctypes.c_int, [_vp, _vp, _vp, _i64,
+                                               ctypes.POINTER(ctypes.c_uint64)]),
+    "sbt_server_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(_i32),
+                                       ctypes.POINTER(ctypes.c_int), _pd, _pd, _pd]),
+    "sbt_server_drain": (ctypes.c_int, [_vp]),
+    "sbt_server_destroy": (None, [_vp]),
     "sbt_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "sbt_last_error": (ctypes.c_char_p, [_vp]),
 }
@@ -286,3 +293,50 @@ def mttkrp_dense(precision, Z_dev, n1, n2, n3, R, U0_dev, U1_dev, U2_dev, mode, 
     st = load().sbt_mttkrp_dense(precision, _ptr(Z_dev), n1, n2, n3, R, _ptr(U0_dev),
                                  _ptr(U1_dev), _ptr(U2_dev), mode, _ptr(out_dev), _stream(stream))
     _check(st, None, "sbt_mttkrp_dense")
+
+
+class Server:
+    """Serving loop over resident tensors (sbt_server_*)."""
+
+    def __init__(self, slots, staging_bytes):
+        out = _vp()
+        _check(load().sbt_server_create(slots, int(staging_bytes), ctypes.byref(out)), None,
+               "sbt_server_create")
+        self.h = out.value
+
+    def submit_dense(self, tensor, Y_dev, K_new):
+        """Returns the ticket; raises on a request that can never be admitted."""
+        tk = ctypes.c_uint64()
+        st = load().sbt_server_submit_dense(self.h, tensor.h, _ptr(Y_dev), K_new,
+                                            ctypes.byref(tk))
+        _check(st, None, "sbt_server_submit_dense")
+        return tk.value
+
+    def try_submit_dense(self, tensor, Y_dev, K_new):
+        tk = ctypes.c_uint64()
+        st = load().sbt_server_submit_dense(self.h, tensor.h, _ptr(Y_dev), K_new,
+                                            ctypes.byref(tk))
+        return st, tk.value
+
+    def poll(self, ticket):
+        """(state, result, t_submit, t_start, t_done)"""
+        state, res = _i32(), ctypes.c_int()
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(load().sbt_server_poll(self.h, ticket, ctypes.byref(state), ctypes.byref(res),
+                                      ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+               None, "sbt_server_poll")
+        return state.value, res.value, a.value, b.value, c.value
+
+    def drain(self):
+        _check(load().sbt_server_drain(self.h), None, "sbt_server_drain")
+
+    def close(self):
+        if self.h:
+            load().sbt_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
