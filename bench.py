@@ -15,6 +15,14 @@ before timing, the model starting from the generator's factors):
   sparse100k  COO 100000^3 with about 1e8 nonzeros (Zipf 1.1 popularity,
               rank-10 nonnegative model), batches of 1000 slices with about
               1e6 nonzeros, s = 10, r = 10, 30 sweeps.
+  serve16     16 resident dense tensors of random shapes and ranks, 512 update
+              requests of 5-100 slices through the serving loop (4 slots):
+              closed loop (all requests queued at once: `value`), then open
+              loop with Poisson arrivals at 80% of the closed-loop request
+              rate (p50/p99 of completion minus arrival), and the same
+              requests one at a time on one slot for comparison.  Tensor data
+              are generated on the GPU (CP model plus 1% noise); a request of
+              K slices appends the first K of its tensor's 100-slice pool.
 
 A step is one update (importance, sampling, summaries, CP-ALS on the r
 summaries, matching, row solve, append) of one batch.  The timed region is
@@ -55,6 +63,11 @@ WORKLOADS = {
                       iters=30, seed=5, noise=0.01,
                       desc="dense 2000x2000x1000 + 100-slice batches, rank 20, s=5, r=10, "
                            "30 ALS sweeps, BF16 summaries on the matrix cores"),
+    "serve16": dict(kind="serve", tensors=16, requests=512, seed=4, s=5, r=10, iters=30,
+                    slots=4, load=0.8,
+                    desc="serving: 16 resident dense FP32 tensors (I, J uniform in [200, 2000], "
+                         "K0 in [100, 1000], rank 5-20), 512 update requests of 5-100 slices, "
+                         "s=5, r=10, 30 ALS sweeps, 4 concurrent slots"),
     "sparse100k": dict(kind="coo", I=100000, J=100000, K0=100000, Kn=1000, R=10, s=10,
                        r=10, iters=30, seed=3, nnz0=100_000_000, nnz_b=1_000_000,
                        desc="sparse COO 100000^3 with 1e8 nonzeros + 1000-slice batches of "
@@ -341,6 +354,126 @@ def bench_sparse(args, sbt, torch, synth, log):
     return line
 
 
+def bench_serve(args, sbt, torch, synth, log):
+    w = WORKLOADS["serve16"]
+    nt, nreq = w["tensors"], args.serve_requests or w["requests"]
+    g = np.random.default_rng(np.random.SeedSequence([w["seed"], 21]))
+    Is = g.integers(200, 2001, nt)
+    Js = g.integers(200, 2001, nt)
+    K0s = g.integers(100, 1001, nt)
+    Rs = g.integers(5, 21, nt)
+    who = g.integers(0, nt, nreq)
+    kns = g.integers(5, 101, nreq)
+    grow = np.bincount(who, weights=kns, minlength=nt).astype(np.int64)
+    pool_slices = 100
+    dev = torch.device("cuda")
+
+    def gen_tensor(i):
+        """(X0 + 100-slice pool) on the device as (K, J, I) float32, and the
+        model of X0 (unit columns, lambda)."""
+        I, J, K0, R = int(Is[i]), int(Js[i]), int(K0s[i]), int(Rs[i])
+        gf = np.random.default_rng(np.random.SeedSequence([w["seed"], 22, i]))
+        A, B, C = gf.random((I, R)), gf.random((J, R)), gf.random((K0 + pool_slices, R))
+        H = (A.T @ A) * (B.T @ B) * (C.T @ C)
+        sigma = 0.01 * np.sqrt(H.sum() / (I * J * (K0 + pool_slices)))
+        At = torch.from_numpy(A.T.copy()).float().to(dev)      # (R, I)
+        Bd = torch.from_numpy(B).float().to(dev)               # (J, R)
+        Cd = torch.from_numpy(C).float().to(dev)               # (K, R)
+        X = torch.empty((K0 + pool_slices, J, I), dtype=torch.float32, device=dev)
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(int(w["seed"]) * 1000 + i)
+        for k0 in range(0, K0 + pool_slices, 64):
+            k1 = min(K0 + pool_slices, k0 + 64)
+            blk = torch.matmul(Bd[None, :, :] * Cd[k0:k1, None, :], At)   # (k, J, I)
+            blk += sigma * torch.randn(blk.shape, generator=gen, device=dev)
+            X[k0:k1] = blk
+        nA, nB, nC = (np.linalg.norm(M, axis=0) for M in (A, B, C[:K0]))
+        model = (A / nA, B / nB, C[:K0] / nC, nA * nB * nC)
+        return X, model
+
+    def fresh_tensors():
+        out = []
+        for i in range(nt):
+            X, model = gen_tensor(i)
+            K0 = int(K0s[i])
+            cfg = sbt.make_config(int(Rs[i]), w["r"], w["iters"], w["s"], w["seed"] + i,
+                                  precision=sbt.SBT_P_F32, k_capacity=K0 + int(grow[i]),
+                                  max_batch=pool_slices)
+            T = sbt.Tensor.init_dense(cfg, X[:K0], int(Is[i]), int(Js[i]), K0, factors=model)
+            pool = X[K0:].clone()
+            del X
+            torch.cuda.empty_cache()  # hand the generation buffer back for the next store
+            out.append((T, pool))
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        return out
+
+    max_batch_bytes = int((Is * Js).max()) * pool_slices * 4
+
+    def run(slots, arrivals):
+        made = fresh_tensors()
+        srv = sbt.Server(slots, slots * max_batch_bytes)
+        tickets = []
+        t0 = time.perf_counter()
+        for q in range(nreq):
+            if arrivals is not None:
+                d = arrivals[q] - (time.perf_counter() - t0)
+                if d > 0:
+                    time.sleep(d)
+            T, pool = made[who[q]]
+            tickets.append(srv.submit_dense(T, pool[:int(kns[q])], int(kns[q])))
+        srv.drain()
+        wall = time.perf_counter() - t0
+        lat, bad = [], 0
+        for tk in tickets:
+            state, res, ts, tb, te = srv.poll(tk)
+            bad += res != sbt.SBT_OK
+            lat.append(te - ts)
+        fits = [T.fit() for T, _ in made]
+        srv.close()
+        for T, pool in made:
+            T.close()
+        del made
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        return dict(slices_per_s=float(kns.sum()) / wall, wall_s=wall,
+                    req_per_s=nreq / wall, p50_ms=1e3 * percentile(lat, 50),
+                    p99_ms=1e3 * percentile(lat, 99), failed=int(bad),
+                    fit_min=float(min(fits)), fit_mean=float(np.mean(fits)))
+
+    closed = run(w["slots"], None)
+    log(f"# serve closed loop: {closed['slices_per_s']:.1f} slices/s, "
+        f"{closed['req_per_s']:.1f} req/s")
+    rate = w["load"] * closed["req_per_s"]
+    arrivals = synth.poisson_arrivals(nreq, rate, w["seed"])
+    opened = run(w["slots"], arrivals)
+    log(f"# serve open loop at {rate:.1f} req/s: p50 {opened['p50_ms']:.1f} ms, "
+        f"p99 {opened['p99_ms']:.1f} ms")
+    single = run(1, None)
+    log(f"# one slot: {single['slices_per_s']:.1f} slices/s")
+    line = {
+        "metric": "updated slices/sec (p50/p99 update latency under Poisson arrivals, one slot "
+                  "alongside, at equal fit)",
+        "value": round(closed["slices_per_s"], 2), "unit": "slices/s", "n_gpus": 1,
+        "steps": nreq, "warmup": 0, "ms_per_step": round(1e3 * closed["wall_s"] / nreq, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w["desc"], "tensors": nt, "requests": nreq, "s": w["s"],
+                   "r": w["r"], "als_iters": w["iters"], "slots": w["slots"],
+                   "slices": int(kns.sum())},
+        "p50_ms": round(closed["p50_ms"], 3), "p99_ms": round(closed["p99_ms"], 3),
+        "open_loop": {"rate_req_per_s": round(rate, 3), "p50_ms": round(opened["p50_ms"], 3),
+                      "p99_ms": round(opened["p99_ms"], 3),
+                      "slices_per_s": round(opened["slices_per_s"], 2)},
+        "one_slot": {"value": round(single["slices_per_s"], 2),
+                     "p50_ms": round(single["p50_ms"], 3), "p99_ms": round(single["p99_ms"], 3)},
+        "fit_min": round(closed["fit_min"], 6), "fit_mean": round(closed["fit_mean"], 6),
+        "failed_requests": closed["failed"] + opened["failed"] + single["failed"],
+        "roofline": None, "cpu_baseline": None,
+    }
+    return line
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -351,6 +484,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-updates", type=int, default=2)
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=0,
+                    help="requests of the serving workload (default: the workload's 512)")
     ap.add_argument("--nnz-scale", type=float, default=1.0,
                     help="scale the nonzero counts of the sparse workload")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -384,6 +519,8 @@ def main():
 
     if WORKLOADS[args.workload]["kind"] == "coo":
         line = bench_sparse(args, sbt, torch, synth, log)
+    elif WORKLOADS[args.workload]["kind"] == "serve":
+        line = bench_serve(args, sbt, torch, synth, log)
     else:
         line = bench_dense(args, sbt, torch, synth, log)
     print(json.dumps(line))
