@@ -56,6 +56,7 @@ struct sbt_tensor {
   uint16_t *Zk = nullptr, *Zc = nullptr;
   float* P3 = nullptr;  // mode-3 partial rows
   int64_t sP3 = 0;
+  float* mops = nullptr;  // staged MFMA operands
   double *Ap = nullptr, *Bp = nullptr, *Cp = nullptr, *GA = nullptr, *GB = nullptr, *GC = nullptr,
          *Gt = nullptr, *ones = nullptr, *lamp = nullptr, *M = nullptr, *At = nullptr,
          *Bt = nullptr, *Ct = nullptr, *M3 = nullptr, *nrm = nullptr, *fitv = nullptr,
@@ -279,6 +280,7 @@ sbt_status alloc_state(sbt_tensor* t) {
     SBT_TRY(dalloc(t, &t->Zk, (size_t)r * t->ml.sZk));
     SBT_TRY(dalloc(t, &t->Zc, (size_t)r * t->ml.sZc));
     SBT_TRY(dalloc(t, &t->P3, (size_t)r * nsmax * t->sP3));
+    SBT_TRY(dalloc(t, &t->mops, (size_t)r * mfma_operand_floats(t->ml, t->n2, R)));
     SBT_TRY(dalloc_bytes(t, &t->W, (size_t)r * rs.sW * sizeof(float)));
     // padding of Zk is never written by the gather: zero it once
     hipError_t e = hipMemset(t->Zk, 0, sizeof(uint16_t) * (size_t)r * t->ml.sZk);
@@ -671,7 +673,7 @@ sbt_status run_als(sbt_tensor* t, const void* Zp, RepSet rs, double* Ap, double*
   for (int it = 0; it < iters; ++it) {
     int pq = prof_begin(t, st);
     if (mf) {
-      SBT_CK(launch_pw_mfma(rs, t->ml, t->Zc, Cp, ilC, (float*)W, st));
+      SBT_CK(launch_pw_mfma(rs, t->ml, t->Zc, Cp, ilC, (float*)W, t->mops, st));
       prof_end(t, pq, SBT_K_MTTKRP_C, pwm_bytes, st);
     } else {
       SBT_CK(launch_pw(prec, rs, Zp, Cp, ilC, W, st));
@@ -690,7 +692,8 @@ sbt_status run_als(sbt_tensor* t, const void* Zp, RepSet rs, double* Ap, double*
     // mode 3: C (lambda' = its column norms)
     pq = prof_begin(t, st);
     if (mf) {
-      SBT_CK(launch_p3_mfma(rs, t->ml, ns3, t->Zk, Ap, ilA, Bp, ilB, t->P3, t->sP3, st));
+      SBT_CK(launch_p3_mfma(rs, t->ml, ns3, t->Zk, Ap, ilA, Bp, ilB, t->P3, t->sP3, t->mops,
+                            st));
       prof_end(t, pq, SBT_K_MTTKRP_AB, p3m_bytes, st);
       SBT_CK(launch_mode3_finish(rs, ns3, t->P3, t->sP3, Vinv, nullptr, Cp, rs.sC, st));
     } else {
@@ -925,7 +928,7 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
       SBT_CK(launch_inverse(rs, t->Gt, rs.sG, t->ones, 0, t->Vinv, t->pinv, st));
       const int ns3 = mfma_mode3_splits(rs, t->ml);
       SBT_CK(launch_p3_mfma(rs, t->ml, ns3, t->Zk, t->At, nullptr, t->Bt, nullptr, t->P3, t->sP3,
-                            st));
+                            t->mops, st));
       SBT_CK(launch_mode3_finish(rs, ns3, t->P3, t->sP3, t->Vinv, t->lam, t->Ct, rs.sC, st));
       prof_end(t, rq, SBT_K_ROW_SOLVE, rbytes, st);
     } else {
@@ -1421,6 +1424,8 @@ sbt_status sbt_mttkrp_dense(int32_t precision, const void* Z_dev, int64_t n1, in
     SBT_CK(hipMallocAsync((void**)&one_dev, sizeof(double) * one.size(), st));
     SBT_CK(hipMallocAsync(&W, sizeof(float) * rs.sW, st));
     SBT_CK(hipMallocAsync((void**)&P, sizeof(float) * ns * sP, st));
+    float* ops = nullptr;
+    SBT_CK(hipMallocAsync((void**)&ops, sizeof(float) * mfma_operand_floats(L, rs.n2, R), st));
     SBT_CK(hipMemsetAsync(Zk, 0, sizeof(uint16_t) * L.sZk, st));
     SBT_CK(hipMemcpyAsync(I_dev, eye.data(), sizeof(double) * eye.size(), hipMemcpyHostToDevice,
                           st));
@@ -1428,15 +1433,15 @@ sbt_status sbt_mttkrp_dense(int32_t precision, const void* Z_dev, int64_t n1, in
                           hipMemcpyHostToDevice, st));
     SBT_CK(launch_relayout_bf16((const uint16_t*)Z_dev, rs, L, Zk, Zc, st));
     if (mode == 2) {
-      SBT_CK(launch_p3_mfma(rs, L, ns, Zk, U0_dev, nullptr, U1_dev, nullptr, P, sP, st));
+      SBT_CK(launch_p3_mfma(rs, L, ns, Zk, U0_dev, nullptr, U1_dev, nullptr, P, sP, ops, st));
       SBT_CK(launch_mode3_finish(rs, ns, P, sP, I_dev, nullptr, out_dev, 0, st));
     } else {
-      SBT_CK(launch_pw_mfma(rs, L, Zc, U2_dev, nullptr, (float*)W, st));
+      SBT_CK(launch_pw_mfma(rs, L, Zc, U2_dev, nullptr, (float*)W, ops, st));
       SBT_CK(launch_cw(kF32, rs, mode, W, mode == 0 ? U1_dev : U0_dev, one_dev, I_dev, out_dev,
                        0, st));
     }
     SBT_CK(hipStreamSynchronize(st));  // the host vectors above are read by the copies
-    void* frees[] = {Zk, Zc, I_dev, one_dev, W, P};
+    void* frees[] = {Zk, Zc, I_dev, one_dev, W, P, ops};
     for (void* q : frees) SBT_CK(hipFreeAsync(q, st));
     return SBT_OK;
   }

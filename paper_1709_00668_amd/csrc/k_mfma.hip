@@ -126,79 +126,135 @@ __global__ __launch_bounds__(256) void relayout_bf16_kernel(const uint16_t* Z, R
 }
 
 // ---------------------------------------------------------------------------
+// operands staged once per launch
+// ---------------------------------------------------------------------------
+// C~^T as BF16 hi and lo parts: Ct[rep][part][f][kp32 + 8] (rows f >= R and
+// columns c >= K' zero)
+__global__ void ct_split_kernel(RepSet rs, int kp32, int nf, const double* Cf,
+                                const double* invlamC, uint16_t* Ct) {
+  const int rep = rs.rep0 + blockIdx.y;
+  const int R = rs.R, ldt = kp32 + 8;
+  const int64_t n = (int64_t)nf * ldt;
+  const double* C = Cf + rep * rs.sC;
+  uint16_t* hi = Ct + (int64_t)rep * 2 * n;
+  uint16_t* lo = hi + n;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int f = (int)(q / ldt), c = (int)(q % ldt);
+    float x = 0.0f;
+    if (f < R && c < rs.n3)
+      x = (float)(C[(int64_t)c * R + f] * (invlamC ? invlamC[rep * 3 * R + f] : 1.0));
+    const uint16_t h = f32_to_bf16_rne(x);
+    hi[q] = h;
+    lo[q] = f32_to_bf16_rne(x - bf16_to_f32(h));
+  }
+}
+
+// A~^T and B~^T in FP32: Ft[rep][f][ld] (rows f >= R and columns >= rows zero)
+__global__ void ft_kernel(RepSet rs, int rows, int ld, int nf, const double* F, int64_t sF,
+                          const double* invlam, float* Ft) {
+  const int rep = rs.rep0 + blockIdx.y;
+  const int R = rs.R;
+  const int64_t n = (int64_t)nf * ld;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int f = (int)(q / ld), a = (int)(q % ld);
+    float x = 0.0f;
+    if (f < R && a < rows)
+      x = (float)(F[rep * sF + (int64_t)a * R + f] * (invlam ? invlam[rep * 3 * R + f] : 1.0));
+    Ft[(int64_t)rep * n + q] = x;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // pass W on the matrix cores
 // ---------------------------------------------------------------------------
-// Block = 4 wavefronts x 16 rows e of one repetition; every wave runs the
-// whole K range (K' rounded up to 32) against C~^T staged in LDS as BF16.
-constexpr int kWPre = 8;  // K steps whose operand loads are in flight at once
+// Block = 4 wavefronts x 4 tiles of 16 rows e (256 rows) of one repetition;
+// every wave runs the whole K range (K' rounded up to 32) against C~^T hi and
+// lo, copied into LDS once per block.  hi and lo products go to separate
+// accumulators (no back-to-back dependence between the two MFMAs).
+constexpr int kWTiles = 4;   // row tiles per wavefront
+constexpr int kWSteps = 2;   // K steps whose operand loads are in flight at once
 
 template <int NT>
 __global__ __launch_bounds__(256) void pw_mfma_kernel(RepSet rs, MfmaLayout L, int kp32,
-                                                     const uint16_t* Zc, const double* Cf,
-                                                     const double* invlamC, float* W) {
+                                                     const uint16_t* Zc, const uint16_t* Ctg,
+                                                     float* W) {
   extern __shared__ __align__(16) unsigned char pwm_smem[];
   const int ldt = kp32 + 8;
-  uint16_t* Ct = reinterpret_cast<uint16_t*>(pwm_smem);  // hi part [16 NT][ldt]
-  uint16_t* Cl = Ct + 16 * NT * ldt;                      // lo part
+  uint16_t* Ct = reinterpret_cast<uint16_t*>(pwm_smem);  // hi part [16 NT][ldt], then lo
   const int rep = rs.rep0 + blockIdx.y;
   const int R = rs.R;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int64_t n12 = (int64_t)rs.n1 * rs.n2;
-  const int64_t e0 = (int64_t)blockIdx.x * 64 + wave * 16;
-  const int64_t erow = e0 + (lane & 15) < n12 ? e0 + (lane & 15) : n12 - 1;
+  const int64_t e0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * kWTiles);
   const int kq = lane >> 4;
-  const uint16_t* zrow = Zc + rep * L.sZc + erow * L.ldc + 8 * kq;
   const int ksteps = kp32 / 32;
-  // first operand loads before the staging
-  bf16x8_t af[kWPre];
+  const uint16_t* zrow[kWTiles];
 #pragma unroll
-  for (int u = 0; u < kWPre; ++u)
-    if (u < ksteps) af[u] = ld_bf16x8(zrow + 32 * u);
+  for (int t = 0; t < kWTiles; ++t) {
+    const int64_t e = e0 + 16 * t + (lane & 15);
+    zrow[t] = Zc + rep * L.sZc + (e < n12 ? e : n12 - 1) * L.ldc + 8 * kq;
+  }
+  // first operand loads before the staging
+  bf16x8_t af[kWSteps][kWTiles];
+#pragma unroll
+  for (int u = 0; u < kWSteps; ++u)
+#pragma unroll
+    for (int t = 0; t < kWTiles; ++t)
+      if (u < ksteps) af[u][t] = ld_bf16x8(zrow[t] + 32 * u);
   {
-    const double* C = Cf + rep * rs.sC;
-    const double* il = invlamC ? invlamC + rep * 3 * R : nullptr;
-    const int n = 16 * NT * kp32;
-    for (int q = tid; q < n; q += 256) {
-      const int f = q / kp32, c = q % kp32;
-      float x = 0.0f;
-      if (f < R && c < rs.n3) x = (float)(C[(int64_t)c * R + f] * (il ? il[f] : 1.0));
-      const uint16_t h = f32_to_bf16_rne(x);
-      Ct[f * ldt + c] = h;
-      Cl[f * ldt + c] = f32_to_bf16_rne(x - bf16_to_f32(h));
-    }
+    const int64_t n16 = (int64_t)2 * 16 * NT * ldt / 8;  // 16-byte words of hi and lo
+    const uint4* src = reinterpret_cast<const uint4*>(Ctg + (int64_t)rep * 2 * 16 * NT * ldt);
+    uint4* dst = reinterpret_cast<uint4*>(Ct);
+    for (int64_t q = tid; q < n16; q += 256) dst[q] = src[q];
   }
   __syncthreads();
-  f32x4_t acc[NT];
+  const uint16_t* Cl = Ct + 16 * NT * ldt;
+  f32x4_t ah[kWTiles][NT], al[kWTiles][NT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < ksteps; k0 += kWPre) {
+  for (int t = 0; t < kWTiles; ++t)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      ah[t][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+      al[t][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    }
+  for (int k0 = 0; k0 < ksteps; k0 += kWSteps) {
     if (k0 > 0) {
 #pragma unroll
-      for (int u = 0; u < kWPre; ++u)
-        if (k0 + u < ksteps) af[u] = ld_bf16x8(zrow + 32 * (k0 + u));
+      for (int u = 0; u < kWSteps; ++u)
+#pragma unroll
+        for (int t = 0; t < kWTiles; ++t)
+          if (k0 + u < ksteps) af[u][t] = ld_bf16x8(zrow[t] + 32 * (k0 + u));
     }
 #pragma unroll
-    for (int u = 0; u < kWPre; ++u) {
+    for (int u = 0; u < kWSteps; ++u) {
       if (k0 + u < ksteps) {
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          const int o = (16 * t + (lane & 15)) * ldt + 32 * (k0 + u) + 8 * kq;
-          acc[t] = mfma16x16x32(af[u], ld_bf16x8(Ct + o), acc[t]);
-          acc[t] = mfma16x16x32(af[u], ld_bf16x8(Cl + o), acc[t]);
+        for (int j = 0; j < NT; ++j) {
+          const int o = (16 * j + (lane & 15)) * ldt + 32 * (k0 + u) + 8 * kq;
+          const bf16x8_t bh = ld_bf16x8(Ct + o), bl = ld_bf16x8(Cl + o);
+#pragma unroll
+          for (int t = 0; t < kWTiles; ++t) {
+            ah[t][j] = mfma16x16x32(af[u][t], bh, ah[t][j]);
+            al[t][j] = mfma16x16x32(af[u][t], bl, al[t][j]);
+          }
         }
       }
     }
   }
   float* Wr = W + rep * rs.sW;
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int f = 16 * t + (lane & 15);
+  for (int t = 0; t < kWTiles; ++t)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t e = e0 + 4 * kq + v;
-      if (e < n12 && f < R) Wr[e * R + f] = acc[t][v];
+    for (int j = 0; j < NT; ++j) {
+      const int f = 16 * j + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t e = e0 + 16 * t + 4 * kq + v;
+        if (e < n12 && f < R) Wr[e * R + f] = ah[t][j][v] + al[t][j][v];
+      }
     }
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -206,20 +262,21 @@ __global__ __launch_bounds__(256) void pw_mfma_kernel(RepSet rs, MfmaLayout L, i
 // ---------------------------------------------------------------------------
 // Block = 4 wavefronts x 16 rows c (64 consecutive c) of one repetition over
 // one of nsplit ranges of the K steps; the wave forms its Khatri-Rao operand
-// from A~^T (all of it) and the B~^T rows its K range touches, both in LDS
-// as FP32.  Partial rows go to P[rep][split][c][16 NT]; mode3_finish adds the
-// ranges in order and applies V^-1.
+// from A~^T (all of it) and the B~^T rows its K range touches, both copied
+// into LDS from their FP32 transposes.  Partial rows go to
+// P[rep][split][c][16 NT]; mode3_finish adds the ranges in order and
+// applies V^-1.
+constexpr int kPSteps = 8;  // K steps whose operand loads are in flight at once
+
 template <int NT>
 __global__ __launch_bounds__(256) void p3_mfma_kernel(RepSet rs, MfmaLayout L, int nsplit,
-                                                     const uint16_t* Zk, const double* Af,
-                                                     const double* invlamA, const double* Bf,
-                                                     const double* invlamB, float* P,
-                                                     int64_t sP) {
+                                                     const uint16_t* Zk, const float* Atg,
+                                                     const float* Btg, float* P, int64_t sP) {
   extern __shared__ __align__(16) unsigned char p3m_smem[];
   float* At = reinterpret_cast<float*>(p3m_smem);  // [16 NT][ld1]
   const int rep = rs.rep0 + blockIdx.z;
   const int split = blockIdx.y;
-  const int R = rs.R, n1 = rs.n1, n2 = rs.n2, n3 = rs.n3, ld1 = L.ld1;
+  const int n2 = rs.n2, n3 = rs.n3, ld1 = L.ld1;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int ksteps = (int)(L.sk / 32);
   const int ks_lo = (int)((int64_t)split * ksteps / nsplit);
@@ -228,47 +285,43 @@ __global__ __launch_bounds__(256) void p3_mfma_kernel(RepSet rs, MfmaLayout L, i
   int b_hi = ks_hi > ks_lo ? (ks_hi * 32 - 1) / ld1 : b_lo;
   if (b_hi > n2 - 1) b_hi = n2 - 1;
   const int nb = b_hi >= b_lo ? b_hi - b_lo + 1 : 0;
-  float* Bt = At + 16 * NT * ld1;  // [16 NT][nb]
+  const int nbp = (nb + 3) / 4 * 4;  // row stride of the staged B~^T rows
+  float* Bt = At + 16 * NT * ld1;     // [16 NT][nbp]
   const int c0 = blockIdx.x * 64 + wave * 16;
   const int crow = c0 + (lane & 15) < n3 ? c0 + (lane & 15) : n3 - 1;
   const int kq = lane >> 4;
   const uint16_t* zrow = Zk + rep * L.sZk + (int64_t)crow * L.sk + 8 * kq;
-  bf16x8_t af[kWPre];
+  bf16x8_t af[kPSteps];
 #pragma unroll
-  for (int u = 0; u < kWPre; ++u)
+  for (int u = 0; u < kPSteps; ++u)
     if (ks_lo + u < ks_hi) af[u] = ld_bf16x8(zrow + 32 * (ks_lo + u));
   {
-    const double* A = Af + rep * rs.sA;
-    const double* B = Bf + rep * rs.sB;
-    const double* ilA = invlamA ? invlamA + rep * 3 * R : nullptr;
-    const double* ilB = invlamB ? invlamB + rep * 3 * R : nullptr;
-    const int na = 16 * NT * ld1;
-    for (int q = tid; q < na; q += 256) {
-      const int f = q / ld1, a = q % ld1;
-      float x = 0.0f;
-      if (f < R && a < n1) x = (float)(A[(int64_t)a * R + f] * (ilA ? ilA[f] : 1.0));
-      At[q] = x;
-    }
-    const int nbb = 16 * NT * nb;
-    for (int q = tid; q < nbb; q += 256) {
-      const int f = q / nb, bb = q % nb;
-      float x = 0.0f;
-      if (f < R) x = (float)(B[(int64_t)(b_lo + bb) * R + f] * (ilB ? ilB[f] : 1.0));
-      Bt[q] = x;
+    const int n4 = 16 * NT * ld1 / 4;
+    const float4* src = reinterpret_cast<const float4*>(Atg + (int64_t)rep * 16 * NT * ld1);
+    float4* dst = reinterpret_cast<float4*>(At);
+    for (int q = tid; q < n4; q += 256) dst[q] = src[q];
+    const int ldb = (n2 + 3) / 4 * 4;
+    const float* bsrc = Btg + (int64_t)rep * 16 * NT * ldb;
+    for (int q = tid; q < 16 * NT * nbp; q += 256) {
+      const int f = q / nbp, bb = q % nbp;
+      Bt[q] = bb < nb ? bsrc[(int64_t)f * ldb + b_lo + bb] : 0.0f;
     }
   }
   __syncthreads();
-  f32x4_t acc[NT];
+  f32x4_t ah[NT], al[NT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = ks_lo; k0 < ks_hi; k0 += kWPre) {
+  for (int t = 0; t < NT; ++t) {
+    ah[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    al[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  }
+  for (int k0 = ks_lo; k0 < ks_hi; k0 += kPSteps) {
     if (k0 > ks_lo) {
 #pragma unroll
-      for (int u = 0; u < kWPre; ++u)
+      for (int u = 0; u < kPSteps; ++u)
         if (k0 + u < ks_hi) af[u] = ld_bf16x8(zrow + 32 * (k0 + u));
     }
 #pragma unroll
-    for (int u = 0; u < kWPre; ++u) {
+    for (int u = 0; u < kPSteps; ++u) {
       if (k0 + u < ks_hi) {
         // this lane's 8 consecutive e' share one b (ld1 is a multiple of 8)
         const int ep = 32 * (k0 + u) + 8 * kq;
@@ -279,13 +332,13 @@ __global__ __launch_bounds__(256) void p3_mfma_kernel(RepSet rs, MfmaLayout L, i
           const int f = 16 * t + (lane & 15);
           const float4 x0 = *reinterpret_cast<const float4*>(At + f * ld1 + a0);
           const float4 x1 = *reinterpret_cast<const float4*>(At + f * ld1 + a0 + 4);
-          const float bv = bin ? Bt[f * nb + (b - b_lo)] : 0.0f;
+          const float bv = bin ? Bt[f * nbp + (b - b_lo)] : 0.0f;
           const float x[8] = {x0.x * bv, x0.y * bv, x0.z * bv, x0.w * bv,
                               x1.x * bv, x1.y * bv, x1.z * bv, x1.w * bv};
           bf16x8_t kh, kl;
           split_bf16x8(x, kh, kl);
-          acc[t] = mfma16x16x32(af[u], kh, acc[t]);
-          acc[t] = mfma16x16x32(af[u], kl, acc[t]);
+          ah[t] = mfma16x16x32(af[u], kh, ah[t]);
+          al[t] = mfma16x16x32(af[u], kl, al[t]);
         }
       }
     }
@@ -297,7 +350,7 @@ __global__ __launch_bounds__(256) void p3_mfma_kernel(RepSet rs, MfmaLayout L, i
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int c = c0 + 4 * kq + v;
-      if (c < n3) Pr[(int64_t)c * (16 * NT) + f] = acc[t][v];
+      if (c < n3) Pr[(int64_t)c * (16 * NT) + f] = ah[t][v] + al[t][v];
     }
   }
 }
@@ -349,11 +402,23 @@ MfmaLayout mfma_layout(int n1, int n2, int kpmax) {
   return L;
 }
 
+// B~ rows one K range of the mode-3 kernel may touch (LDS bound)
+constexpr int kMaxBRows = 64;
+
+inline int brows_cap(int n2) { return n2 < kMaxBRows ? n2 : kMaxBRows; }
+
 bool mfma_supported(int n1, int n2, int R) {
   if (R > 32 || n1 < 1 || n2 < 1) return false;
-  // LDS of the mode-3 kernel: A~^T plus at most all of B~^T
-  const size_t lds = (size_t)16 * ntiles(R) * 4 * ((size_t)(n1 + 7) / 8 * 8 + n2);
+  // LDS of the mode-3 kernel: A~^T plus the B~^T rows of one K range
+  const size_t lds =
+      (size_t)16 * ntiles(R) * 4 * ((size_t)(n1 + 7) / 8 * 8 + (brows_cap(n2) + 3) / 4 * 4);
   return lds <= 65536;
+}
+
+// rows of B~ the K range [ks_lo, ks_hi) of a split touches, at most
+inline int brows_of(int ksteps, int nsplit, int ld1) {
+  const int per = (ksteps + nsplit - 1) / nsplit;  // K steps of the longest range
+  return (per * 32 + ld1 - 1) / ld1 + 1;
 }
 
 int mfma_mode3_splits(const RepSet& rs, const MfmaLayout& L) {
@@ -363,6 +428,8 @@ int mfma_mode3_splits(const RepSet& rs, const MfmaLayout& L) {
   const int cap = ksteps / 8 > 0 ? ksteps / 8 : 1;
   if (ns > cap) ns = cap;
   if (ns < 1) ns = 1;
+  // enough ranges that each touches at most brows_cap(n2) rows of B~
+  while (ns < ksteps && brows_of(ksteps, ns, L.ld1) > brows_cap(rs.n2)) ++ns;
   return ns;
 }
 
@@ -391,33 +458,74 @@ hipError_t launch_relayout_bf16(const uint16_t* Z, const RepSet& rs, const MfmaL
   return hipGetLastError();
 }
 
+size_t mfma_operand_floats(const MfmaLayout& L, int n2, int R) {
+  const size_t nf = 16 * ntiles(R);
+  const size_t ct = nf * ((size_t)L.ldc + 8);              // hi and lo BF16 rows
+  const size_t ab = nf * ((size_t)L.ld1 + (n2 + 3) / 4 * 4);  // A~^T and B~^T in FP32
+  return ct > ab ? ct : ab;
+}
+
 hipError_t launch_pw_mfma(const RepSet& rs, const MfmaLayout& L, const uint16_t* Zc,
-                          const double* Cf, const double* invlamC, float* W, hipStream_t s) {
+                          const double* Cf, const double* invlamC, float* W, float* ops,
+                          hipStream_t s) {
   const int64_t n12 = (int64_t)rs.n1 * rs.n2;
   const int kp32 = (rs.n3 + 31) / 32 * 32;
   if (kp32 > L.ldc) return hipErrorInvalidValue;
-  dim3 grid((unsigned)((n12 + 63) / 64), (unsigned)rs.nrep);
-  const size_t sh = (size_t)2 * 16 * ntiles(rs.R) * (kp32 + 8) * 2;
+  const int nt = ntiles(rs.R), nf = 16 * nt;
+  uint16_t* Ct = reinterpret_cast<uint16_t*>(ops);
+  {
+    const int64_t n = (int64_t)nf * (kp32 + 8);
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > 256) blocks = 256;
+    ct_split_kernel<<<dim3((unsigned)blocks, (unsigned)rs.nrep), 256, 0, s>>>(rs, kp32, nf, Cf,
+                                                                            invlamC, Ct);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  const int64_t rows_per_block = 4 * 16 * kWTiles;
+  dim3 grid((unsigned)((n12 + rows_per_block - 1) / rows_per_block), (unsigned)rs.nrep);
+  const size_t sh = (size_t)2 * nf * (kp32 + 8) * 2;
   if (sh > 65536) return hipErrorInvalidValue;
-  if (ntiles(rs.R) == 1)
-    pw_mfma_kernel<1><<<grid, 256, sh, s>>>(rs, L, kp32, Zc, Cf, invlamC, W);
+  if (nt == 1)
+    pw_mfma_kernel<1><<<grid, 256, sh, s>>>(rs, L, kp32, Zc, Ct, W);
   else
-    pw_mfma_kernel<2><<<grid, 256, sh, s>>>(rs, L, kp32, Zc, Cf, invlamC, W);
+    pw_mfma_kernel<2><<<grid, 256, sh, s>>>(rs, L, kp32, Zc, Ct, W);
   return hipGetLastError();
 }
 
 hipError_t launch_p3_mfma(const RepSet& rs, const MfmaLayout& L, int nsplit, const uint16_t* Zk,
                           const double* Af, const double* invlamA, const double* Bf,
-                          const double* invlamB, float* P, int64_t sP, hipStream_t s) {
+                          const double* invlamB, float* P, int64_t sP, float* ops,
+                          hipStream_t s) {
+  const int nt = ntiles(rs.R), nf = 16 * nt;
+  const int ldb = (rs.n2 + 3) / 4 * 4;
+  float* Atg = ops;
+  float* Btg = ops + (size_t)(rs.rep0 + rs.nrep) * nf * L.ld1;
+  {
+    // transposes for repetitions [rep0, rep0 + nrep) at their absolute offsets
+    const int64_t na = (int64_t)nf * L.ld1, nb = (int64_t)nf * ldb;
+    int ba = (int)((na + 255) / 256), bb = (int)((nb + 255) / 256);
+    if (ba > 256) ba = 256;
+    if (bb > 256) bb = 256;
+    ft_kernel<<<dim3((unsigned)ba, (unsigned)rs.nrep), 256, 0, s>>>(rs, rs.n1, L.ld1, nf, Af,
+                                                                   rs.sA, invlamA, Atg);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    ft_kernel<<<dim3((unsigned)bb, (unsigned)rs.nrep), 256, 0, s>>>(rs, rs.n2, ldb, nf, Bf,
+                                                                   rs.sB, invlamB, Btg);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   dim3 grid((unsigned)((rs.n3 + 63) / 64), (unsigned)nsplit, (unsigned)rs.nrep);
-  const int nt = ntiles(rs.R);
-  // B~ rows touched by one split: at most all n2
-  const size_t sh = (size_t)16 * nt * 4 * ((size_t)L.ld1 + rs.n2);
-  if (sh > 65536 || sP < (int64_t)rs.n3 * 16 * nt) return hipErrorInvalidValue;
+  const int ksteps = (int)(L.sk / 32);
+  int nbmax = brows_of(ksteps, nsplit, L.ld1);
+  if (nbmax > rs.n2) nbmax = rs.n2;
+  const size_t sh = (size_t)nf * 4 * ((size_t)L.ld1 + (nbmax + 3) / 4 * 4);
+  if (sh > 65536 || sP < (int64_t)rs.n3 * nf) return hipErrorInvalidValue;
   if (nt == 1)
-    p3_mfma_kernel<1><<<grid, 256, sh, s>>>(rs, L, nsplit, Zk, Af, invlamA, Bf, invlamB, P, sP);
+    p3_mfma_kernel<1><<<grid, 256, sh, s>>>(rs, L, nsplit, Zk, Atg, Btg, P, sP);
   else
-    p3_mfma_kernel<2><<<grid, 256, sh, s>>>(rs, L, nsplit, Zk, Af, invlamA, Bf, invlamB, P, sP);
+    p3_mfma_kernel<2><<<grid, 256, sh, s>>>(rs, L, nsplit, Zk, Atg, Btg, P, sP);
   return hipGetLastError();
 }
 

@@ -96,14 +96,19 @@ hipError_t launch_gather_mfma(int store_prec, const void* X, int64_t I, int64_t 
 // one repetition from a column-major BF16 tensor (no sampling)
 hipError_t launch_relayout_bf16(const uint16_t* Z, const RepSet& rs, const MfmaLayout& L,
                                 uint16_t* Zk, uint16_t* Zc, hipStream_t s);
+// staged operands of the two passes, floats per repetition (the `ops` buffer
+// holds this times the repetitions)
+size_t mfma_operand_floats(const MfmaLayout& L, int n2, int R);
 // W(e, f) = sum_c Zc(e, c) C~(c, f), C~ = C diag(invlamC) (invlamC may be null)
 hipError_t launch_pw_mfma(const RepSet& rs, const MfmaLayout& L, const uint16_t* Zc,
-                          const double* Cf, const double* invlamC, float* W, hipStream_t s);
+                          const double* Cf, const double* invlamC, float* W, float* ops,
+                          hipStream_t s);
 // partial rows of Zk (B~ kr A~) over nsplit K ranges into P[rep][split] (stride sP,
 // row stride 16 or 32)
 hipError_t launch_p3_mfma(const RepSet& rs, const MfmaLayout& L, int nsplit, const uint16_t* Zk,
                           const double* Af, const double* invlamA, const double* Bf,
-                          const double* invlamB, float* P, int64_t sP, hipStream_t s);
+                          const double* invlamB, float* P, int64_t sP, float* ops,
+                          hipStream_t s);
 // U(c, :) = (sum_split P) V^-1 [/ lam_div]
 hipError_t launch_mode3_finish(const RepSet& rs, int nsplit, const float* P, int64_t sP,
                                const double* Vinv, const double* lam_div, double* U, int64_t sU,
