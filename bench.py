@@ -36,7 +36,9 @@ bytes per launch (summary elements read once, factor rows, outputs written
 once) against 8 TB/s; `traffic` comes from hardware counters of the same
 kernel when a committed measurement of the current kernel sources exists.
 cpu_baseline (dense workloads): the CPU FP64 oracle on the first
---cpu-updates updates of the same workload.
+--cpu-updates updates of the same workload.  recompute (dense workloads):
+CP-ALS of the whole grown tensor on the GPU and the relative fitness of the
+incremental result against it (Sec. 4.2).
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--workload dense500]
 """
@@ -301,6 +303,23 @@ def bench_dense(args, sbt, torch, synth, log):
             tfs = flops / (pr["total_ms"] / pr["launches"] * 1e-3) / 1e12
             line["roofline"]["mfma_useful_tflops"] = round(tfs, 2)
             line["roofline"]["mfma_frac"] = round(tfs / MFMA_BF16_PEAK_TFS, 5)
+    if not args.no_recompute:
+        # the paper's baseline for accuracy (Sec. 4.2): CP-ALS recomputed on the whole grown
+        # tensor (on the GPU), and relative fitness = ||X - X_sambaten|| / ||X - X_recomputed||
+        cfg = sbt.make_config(w["R"], w["r"], w["iters"], w["s"], w["seed"],
+                              precision=sbt.SBT_P_F32, k_capacity=K + 1, max_batch=Kn,
+                              init_iters=args.recompute_iters)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        T = sbt.Tensor.init_dense(cfg, Xd, I, J, K)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        fr = T.fit()
+        T.close()
+        line["recompute"] = {"fit": round(fr, 6), "seconds": round(dt, 4),
+                             "als_sweeps": args.recompute_iters,
+                             "relative_fitness": round((1.0 - b["fit"]) / max(1e-12, 1.0 - fr), 4)}
+        log(f"# recompute CP-ALS: fit {fr:.6f} in {dt:.2f} s")
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline_dense(w, Xkji.transpose(2, 1, 0), model, args.cpu_updates)
@@ -484,6 +503,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-updates", type=int, default=2)
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-recompute", action="store_true",
+                    help="skip the CP-ALS recompute of the grown tensor (relative fitness)")
+    ap.add_argument("--recompute-iters", type=int, default=100)
     ap.add_argument("--serve-requests", type=int, default=0,
                     help="requests of the serving workload (default: the workload's 512)")
     ap.add_argument("--nnz-scale", type=float, default=1.0,

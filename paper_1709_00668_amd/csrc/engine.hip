@@ -78,6 +78,7 @@ struct sbt_tensor {
   // cross products over many rows (Gram matrices, matching), all repetitions
   double *xpart = nullptr, *xout = nullptr, *scl = nullptr;
   int xnblk = 1;
+  int64_t xpart_mats = 0;  // R x R matrices the partial buffer holds
   std::vector<void*> grow_allocs; // freed when regrown or destroyed
   int64_t last_summary_nnz = 0;
   // kernel timing (sbt_profile_*)
@@ -317,6 +318,7 @@ sbt_status alloc_state(sbt_tensor* t) {
     int64_t np = (int64_t)r * 9 * t->xnblk;
     if (3 * fit_nblk > np) np = 3 * fit_nblk;
     SBT_TRY(dalloc(t, &t->xpart, (size_t)np * R * R));
+    t->xpart_mats = np;
     SBT_TRY(dalloc(t, &t->xout, (size_t)r * 9 * R * R));
     SBT_TRY(dalloc(t, &t->scl, (size_t)r * 2 * R));
   }
@@ -511,7 +513,11 @@ sbt_status gram_rows(sbt_tensor* t, const RepSet& rs, const double* U, int64_t s
   xp.R = rs.R;
   xp.rep0 = rs.rep0;
   xp.nrep = rs.nrep;
-  xp.nblk = t->xnblk;
+  xp.nblk = xprod_blocks(rows);  // also the whole-tensor factors of the initial CP-ALS
+  if ((int64_t)(rs.rep0 + rs.nrep) * xp.nblk > t->xpart_mats) {
+    set_err(t, "cross-product workspace too small for these rows");
+    return SBT_E_SHAPE;
+  }
   xp.part = t->xpart;
   xp.out = G;  // [rep][1][R*R]: stride R*R = sG
   SBT_CK(launch_xprod(xp, st));
@@ -757,9 +763,11 @@ sbt_status init_common(sbt_tensor* t, const double* A0, const double* B0, const 
   } else {
     const int keep = t->sum_prec;
     t->sum_prec = t->store_prec;  // the whole tensor is read in its stored precision
+    // the batched mode-3 kernel stages both whole factors in LDS; wider
+    // tensors take the one-launch-per-step schedule (the same ALS sweeps)
+    const bool plain = !p3_fits(t->sum_prec, rs.n1, rs.n2, R);
     s = run_als(t, t->X, rs, t->A, t->B, t->C, G, G + rs.sG, G + 2 * rs.sG, t->lam, W, M,
-                t->Vinv, t->invlam,
-                kStreamInit, 0u, t->cfg.init_iters, false, st);
+                t->Vinv, t->invlam, kStreamInit, 0u, t->cfg.init_iters, plain, st);
     t->sum_prec = keep;
     if (s == SBT_OK && t->cfg.init_iters == 0) s = SBT_E_INVALID;
     if (s == SBT_OK) {

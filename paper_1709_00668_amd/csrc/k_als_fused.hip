@@ -844,6 +844,13 @@ hipError_t launch_cw(int prec, const RepSet& rs, int mode, const void* W, const 
   return hipGetLastError();
 }
 
+bool p3_fits(int prec, int n1, int n2, int R) {
+  const int RP = rp4(R);
+  const size_t sh = prec == kF64 ? p3_smem_bytes<double>(n1, n2, RP)
+                                 : p3_smem_bytes<float>(n1, n2, RP);
+  return sh <= 160 * 1024;
+}
+
 hipError_t launch_p3(int prec, const RepSet& rs, bool row_solve, const void* Z, const double* Af,
                      const double* invlamA, const double* Bf, const double* invlamB,
                      const double* Vinv, const double* lam_div, double* U, int64_t sU,

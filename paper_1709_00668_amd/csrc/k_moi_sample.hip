@@ -74,48 +74,67 @@ __device__ inline uint64_t quantize_sq(double x, double scale, uint64_t qmax, bo
   return q;
 }
 
-constexpr int kMoiJChunk = 64;
+constexpr int kMoiJPerWave = 8;                   // j's per wavefront
+constexpr int kMoiJTile = 4 * kMoiJPerWave;       // j's per block
+constexpr int kMoiKTile = 8;                      // slices per block
 
-// Block: 64 consecutive i (one per lane) x kMoiJChunk j's of one slice k; each
-// of the 4 waves takes every 4th j.  Per-i sums meet in LDS, per-j sums are
-// wave reductions, the slice sum is a block reduction; each lands with one
-// 64-bit atomic.
+// Block: 64 consecutive i (one per lane) x kMoiJTile j's (wavefront w takes
+// j0 + w + 4 jj) x kMoiKTile slices.  Sums stay in registers over the tile:
+// per i (lane) over all its j and k, per j over i and k, per k over the
+// block (64-bit LDS atomics), and each lands with one 64-bit global atomic
+// per block.  Integer sums: the order of the atomics does not matter.
 template <typename T>
 __global__ __launch_bounds__(256) void moi_dense_kernel(const T* Y, int64_t I, int64_t J,
-                                                       double scale, uint64_t qmax,
+                                                       int64_t K, double scale, uint64_t qmax,
                                                        uint64_t* w1, uint64_t* w2,
                                                        uint64_t* w3, uint32_t* err) {
   const int lane = lane_id();
   const int wave = threadIdx.x >> 6;
   const int64_t i = (int64_t)blockIdx.x * kWave + lane;
-  const int64_t j0 = (int64_t)blockIdx.y * kMoiJChunk;
-  const int64_t k = blockIdx.z;
-  const int64_t jend = j0 + kMoiJChunk < J ? j0 + kMoiJChunk : J;
-  uint64_t acc_i = 0, acc_k = 0;
-  bool bad = false;
-  for (int64_t j = j0 + wave; j < jend; j += 4) {
-    uint64_t q = 0;
-    if (i < I) q = quantize_sq(as_f64(Y[i + I * (j + J * k)]), scale, qmax, bad);
-    acc_i += q;
-    acc_k += q;
-    const uint64_t qj = wave_sum_u64(q);
-    if (lane == 0 && qj) atomicAdd((unsigned long long*)&w2[j], (unsigned long long)qj);
-  }
+  const int64_t j0 = (int64_t)blockIdx.y * kMoiJTile;
+  const int64_t k0 = (int64_t)blockIdx.z * kMoiKTile;
+  __shared__ unsigned long long sk[kMoiKTile];
   __shared__ uint64_t part_i[4][kWave];
-  __shared__ uint64_t part_k[4];
+  if (threadIdx.x < kMoiKTile) sk[threadIdx.x] = 0ull;
+  __syncthreads();
+  uint64_t acc_i = 0, acc_j[kMoiJPerWave];
+#pragma unroll
+  for (int jj = 0; jj < kMoiJPerWave; ++jj) acc_j[jj] = 0;
+  bool bad = false;
+  for (int kk = 0; kk < kMoiKTile && k0 + kk < K; ++kk) {
+    const int64_t k = k0 + kk;
+    T y[kMoiJPerWave];
+#pragma unroll
+    for (int jj = 0; jj < kMoiJPerWave; ++jj) {
+      const int64_t j = j0 + wave + 4 * jj;
+      y[jj] = (i < I && j < J) ? Y[i + I * (j + J * k)] : (T)0;
+    }
+    uint64_t tk = 0;
+#pragma unroll
+    for (int jj = 0; jj < kMoiJPerWave; ++jj) {
+      const uint64_t q = quantize_sq(as_f64(y[jj]), scale, qmax, bad);
+      acc_j[jj] += q;
+      tk += q;
+    }
+    acc_i += tk;
+    tk = wave_sum_u64(tk);
+    if (lane == 0 && tk) atomicAdd(&sk[kk], (unsigned long long)tk);
+  }
+#pragma unroll
+  for (int jj = 0; jj < kMoiJPerWave; ++jj) {
+    const int64_t j = j0 + wave + 4 * jj;
+    const uint64_t qj = wave_sum_u64(acc_j[jj]);
+    if (lane == 0 && j < J && qj) atomicAdd((unsigned long long*)&w2[j], (unsigned long long)qj);
+  }
   part_i[wave][lane] = acc_i;
-  const uint64_t sk = wave_sum_u64(acc_k);
-  if (lane == 0) part_k[wave] = sk;
   if (bad) atomicOr(err, 1u);
   __syncthreads();
   if (wave == 0) {
     const uint64_t s = part_i[0][lane] + part_i[1][lane] + part_i[2][lane] + part_i[3][lane];
     if (i < I && s) atomicAdd((unsigned long long*)&w1[i], (unsigned long long)s);
-    if (lane == 0) {
-      const uint64_t t = part_k[0] + part_k[1] + part_k[2] + part_k[3];
-      if (t) atomicAdd((unsigned long long*)&w3[k], (unsigned long long)t);
-    }
   }
+  if (threadIdx.x < kMoiKTile && k0 + threadIdx.x < K && sk[threadIdx.x])
+    atomicAdd((unsigned long long*)&w3[k0 + threadIdx.x], sk[threadIdx.x]);
 }
 
 __global__ __launch_bounds__(256) void moi_coo_kernel(const int32_t* ii, const int32_t* jj,
@@ -299,14 +318,14 @@ hipError_t launch_moi_dense(int prec, const void* Y, int64_t I, int64_t J, int64
                             double scale, uint64_t qmax, uint64_t* w1, uint64_t* w2,
                             uint64_t* w3, uint32_t* err, hipStream_t s) {
   if (I <= 0 || J <= 0 || K <= 0) return hipSuccess;
-  dim3 grid((unsigned)((I + kWave - 1) / kWave), (unsigned)((J + kMoiJChunk - 1) / kMoiJChunk),
-            (unsigned)K);
+  dim3 grid((unsigned)((I + kWave - 1) / kWave), (unsigned)((J + kMoiJTile - 1) / kMoiJTile),
+            (unsigned)((K + kMoiKTile - 1) / kMoiKTile));
   if (prec == kF64)
-    moi_dense_kernel<double><<<grid, 256, 0, s>>>((const double*)Y, I, J, scale, qmax, w1, w2,
+    moi_dense_kernel<double><<<grid, 256, 0, s>>>((const double*)Y, I, J, K, scale, qmax, w1, w2,
                                                   w3, err);
   else
-    moi_dense_kernel<float><<<grid, 256, 0, s>>>((const float*)Y, I, J, scale, qmax, w1, w2, w3,
-                                                 err);
+    moi_dense_kernel<float><<<grid, 256, 0, s>>>((const float*)Y, I, J, K, scale, qmax, w1, w2,
+                                                 w3, err);
   return hipGetLastError();
 }
 

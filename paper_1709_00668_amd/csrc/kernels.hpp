@@ -173,6 +173,8 @@ hipError_t launch_pw(int prec, const RepSet& rs, const void* Z, const double* Cf
 hipError_t launch_cw(int prec, const RepSet& rs, int mode, const void* W, const double* F,
                      const double* invlamF, const double* Vinv, double* U, int64_t sU,
                      hipStream_t s);
+// whether launch_p3 can stage both factors of an n1 x n2 slice in LDS
+bool p3_fits(int prec, int n1, int n2, int R);
 // C rows = (Z_(3) (B~ kr A~)) V^-1, or with row_solve those rows / lam_div
 hipError_t launch_p3(int prec, const RepSet& rs, bool row_solve, const void* Z, const double* Af,
                      const double* invlamA, const double* Bf, const double* invlamB,

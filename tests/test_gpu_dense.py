@@ -156,6 +156,29 @@ def test_init_cp_als_matches_oracle(lib):
     assert abs(gpu.fit() - ora.fit()) < 1e-10
 
 
+@pytest.mark.parametrize("I,J,K0,R", [(300, 270, 260, 3), (600, 500, 8, 20)])
+def test_init_cp_als_long_factors(lib, I, J, K0, R):
+    """Initial CP-ALS where every factor has more rows than one block reduces
+    (chunked cross products), and where the two slice factors are too wide for
+    the batched mode-3 kernel (the per-step schedule takes over)."""
+    torch = _torch()
+    gen = synth.DenseCP(I, J, K0 + 2, R, seed=13, dtype=np.float64)
+    X = gen.slices(0, K0)
+    ocfg = osb.Config(rank=R, reps=1, als_iters=2, sample_factor=2, seed=13, k_capacity=K0 + 2,
+                      init_iters=8)
+    ora = osb.OracleTensor(ocfg, osb.DENSE, (I, J, K0), X0=X)
+    cfg = lib.make_config(R, 1, 2, 2, 13, precision=lib.SBT_P_F64, k_capacity=K0 + 2,
+                          max_batch=2, init_iters=8)
+    gpu = lib.Tensor.init_dense(cfg, lib.dense_to_device(X, np.float64), I, J, K0)
+    torch.cuda.synchronize()
+    A, B, C, lam = gpu.get_factors()
+    np.testing.assert_allclose(lam, ora.lam, rtol=1e-8)
+    np.testing.assert_allclose(A, ora.A, rtol=1e-6, atol=1e-9)
+    np.testing.assert_allclose(B, ora.B, rtol=1e-6, atol=1e-9)
+    np.testing.assert_allclose(C, ora.C, rtol=1e-6, atol=1e-9)
+    assert abs(gpu.fit() - ora.fit()) < 1e-10
+
+
 def test_numeric_error_leaves_state_unchanged(lib):
     torch = _torch()
     I, J, K0, Kn, R = 16, 14, 10, 4, 2
