@@ -82,9 +82,11 @@ KIND_NAMES = ("mttkrp_contract_c", "mttkrp_third_mode", "row_solve", "gather", "
               "update")
 
 
-def kernel_of(step, path, R):
-    """HIP kernel behind a timed launch kind."""
+def kernel_of(step, path, R, coo_row_nnz=0.0):
+    """HIP kernel behind a timed launch kind (coo_row_nnz: summary entries per
+    row, which picks the sparse kernel's lanes per unit)."""
     rp = (R + 3) // 4 * 4
+    ul = 64 if coo_row_nnz >= 128.0 else 32
     nt = 1 if R <= 16 else 2
     table = {
         "f32": {"mttkrp_contract_c": f"pw_kernel<float, {rp}>",
@@ -95,7 +97,7 @@ def kernel_of(step, path, R):
                  "mttkrp_third_mode": f"p3_mfma_kernel<{nt}>",
                  "row_solve": f"p3_mfma_kernel<{nt}> + mode3_finish_kernel",
                  "gather": "gather_mfma_kernel<float>"},
-        "coo": {"coo_mttkrp": f"coo_units_kernel<{rp}>", "gather": "summary_emit_kernel"},
+        "coo": {"coo_mttkrp": f"coo_units_kernel<{rp}, {ul}>", "gather": "summary_emit_kernel"},
     }
     return table.get(path, {}).get(step, step)
 
@@ -191,14 +193,16 @@ def committed_traffic(kernel, workload):
     return None
 
 
-def roofline_of(prof, path, R, workload):
+def roofline_of(prof, path, R, workload, summary_rows=0):
     kernels = {k: v for k, v in prof.items() if k != "update" and v["launches"]}
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     d = kernels[dom]
     avg_ms = d["total_ms"] / d["launches"]
     bytes_per_launch = d["alg_bytes"] / d["launches"]
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    kname = kernel_of(dom, path, R)
+    # sparse: 12 B per summary entry; entries per row over all repetitions' rows
+    row_nnz = bytes_per_launch / 12.0 / summary_rows if summary_rows else 0.0
+    kname = kernel_of(dom, path, R, row_nnz)
     return dict(bound="hbm", kernel=kname, step=dom, achieved=round(achieved, 1),
                 peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
                 traffic=committed_traffic(kname, workload),
@@ -367,7 +371,8 @@ def bench_sparse(args, sbt, torch, synth, log):
     line = base_line(args, w, res, "f32")
     line["config"]["nnz0"] = len(v0)
     line["config"]["nnz_batch"] = nnzb
-    line["roofline"] = roofline_of(res["profile"], "coo", w["R"], name)
+    line["roofline"] = roofline_of(res["profile"], "coo", w["R"], name,
+                                   summary_rows=w["r"] * -(-w["I"] // w["s"]))
     line["cpu_baseline"] = None
     line["kernels"] = kernels_table(res["profile"])
     return line

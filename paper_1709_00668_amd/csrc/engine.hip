@@ -551,12 +551,17 @@ sbt_status run_als_coo(sbt_tensor* t, RepSet rs, uint32_t t_ctr, hipStream_t st)
   SBT_CK(launch_coo_prep(rs, rs.n2, t->Bp, rs.sB, nullptr, t->fB, st));
   SBT_CK(launch_coo_prep(rs, rs.n3, t->Cp, rs.sC, nullptr, t->fC, st));
   const double ebytes = (double)t->last_summary_nnz * 12.0;
+  const double nrow_all = (double)t->cfg.repetitions;
+  const double avg1 = (double)t->last_summary_nnz / (nrow_all * rs.n1);
+  const double avg2 = (double)t->last_summary_nnz / (nrow_all * rs.n2);
+  const double avg3 = (double)t->last_summary_nnz / (nrow_all * rs.n3);
   AlsTail ta;
   ta.sG = rs.sG;
   ta.pinv_count = t->pinv;
   for (int it = 0; it < t->cfg.als_iters; ++it) {
     int pq = prof_begin(t, st);
-    SBT_CK(launch_coo_units(rs, 0, t->z, t->cu[0], t->fB, rs.n2, t->fC, rs.n3, t->upart, st));
+    SBT_CK(launch_coo_units(rs, 0, t->z, t->cu[0], t->fB, rs.n2, t->fC, rs.n3, t->upart, avg1,
+                            st));
     prof_end(t, pq, SBT_K_COO_MTTKRP, ebytes, st);
     SBT_CK(launch_coo_units_finish(rs, 0, t->cu[0], t->upart, t->Vinv, nullptr, t->Ap, rs.sA,
                                    st));
@@ -565,7 +570,8 @@ sbt_status run_als_coo(sbt_tensor* t, RepSet rs, uint32_t t_ctr, hipStream_t st)
     SBT_TRY(tail(t, rs, ta, st));
     SBT_CK(launch_coo_prep(rs, rs.n1, t->Ap, rs.sA, ilA, t->fA, st));
     pq = prof_begin(t, st);
-    SBT_CK(launch_coo_units(rs, 1, t->z, t->cu[1], t->fA, rs.n1, t->fC, rs.n3, t->upart, st));
+    SBT_CK(launch_coo_units(rs, 1, t->z, t->cu[1], t->fA, rs.n1, t->fC, rs.n3, t->upart, avg2,
+                            st));
     prof_end(t, pq, SBT_K_COO_MTTKRP, ebytes, st);
     SBT_CK(launch_coo_units_finish(rs, 1, t->cu[1], t->upart, t->Vinv, nullptr, t->Bp, rs.sB,
                                    st));
@@ -574,7 +580,8 @@ sbt_status run_als_coo(sbt_tensor* t, RepSet rs, uint32_t t_ctr, hipStream_t st)
     SBT_TRY(tail(t, rs, ta, st));
     SBT_CK(launch_coo_prep(rs, rs.n2, t->Bp, rs.sB, ilB, t->fB, st));
     pq = prof_begin(t, st);
-    SBT_CK(launch_coo_units(rs, 2, t->z, t->cu[2], t->fA, rs.n1, t->fB, rs.n2, t->upart, st));
+    SBT_CK(launch_coo_units(rs, 2, t->z, t->cu[2], t->fA, rs.n1, t->fB, rs.n2, t->upart, avg3,
+                            st));
     prof_end(t, pq, SBT_K_COO_MTTKRP, ebytes, st);
     SBT_CK(launch_coo_units_finish(rs, 2, t->cu[2], t->upart, t->Vinv, nullptr, t->Cp, rs.sC,
                                    st));
@@ -923,6 +930,7 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
       SBT_CK(launch_coo_prep(rs, rs.n1, t->At, rs.sA, nullptr, t->fA, st));
       SBT_CK(launch_coo_prep(rs, rs.n2, t->Bt, rs.sB, nullptr, t->fB, st));
       SBT_CK(launch_coo_units(rs, 2, t->z, t->cu[2], t->fA, rs.n1, t->fB, rs.n2, t->upart,
+                              (double)t->last_summary_nnz / ((double)t->cfg.repetitions * rs.n3),
                               st));
       prof_end(t, rq, SBT_K_COO_MTTKRP, (double)t->last_summary_nnz * 12.0, st);
       SBT_CK(launch_coo_units_finish(rs, 2, t->cu[2], t->upart, t->Vinv, t->lam, t->Ct, rs.sC,

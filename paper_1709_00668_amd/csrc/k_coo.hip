@@ -360,85 +360,128 @@ __global__ void coo_unit_fill_kernel(const int64_t* off, int64_t sOff, int rows,
 }
 
 // FP32 copies of the scaled factor rows the sparse MTTKRP gathers:
-// Xf[rep][row][RP] = X(row, :) diag(invlam) (zero beyond R)
-__global__ void coo_prep_kernel(RepSet rs, int rows, int RP, const double* X, int64_t sX,
+// Xf[rep][row][RX] = X(row, :) diag(invlam) (zero beyond R), RX = 16 or 32
+__global__ void coo_prep_kernel(RepSet rs, int rows, int RX, const double* X, int64_t sX,
                                 const double* invlam, float* Xf) {
   const int rep = rs.rep0 + blockIdx.y;
   const int R = rs.R;
-  const int64_t n = (int64_t)rows * RP;
+  const int64_t n = (int64_t)rows * RX;
   for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n;
        q += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t row = q / RP;
-    const int f = (int)(q % RP);
+    const int64_t row = q / RX;
+    const int f = (int)(q % RX);
     float v = 0.0f;
     if (f < R) v = (float)(X[rep * sX + row * R + f] * (invlam ? invlam[rep * 3 * R + f] : 1.0));
-    Xf[(int64_t)rep * rows * RP + q] = v;
+    Xf[(int64_t)rep * rows * RX + q] = v;
   }
 }
 
-// 16 lanes per unit, 4 units per wavefront: partial row
+// UL lanes per unit (32 or 64; 64 / UL units per wavefront): partial row
 // sum_e v * Xf(x_e, :) * Yf(y_e, :).  Units are dealt to the eight XCDs in
 // contiguous ranges (workgroup b runs on XCD b mod 8), so each XCD's L2 holds
-// the factor rows of about one and a quarter repetitions.
-constexpr int kUnitLanes = 16;
+// the factor rows of about one and a quarter repetitions.  The scaled factor
+// copies have rows of 16 (R <= 16) or 32 floats, whole cache-line halves or
+// lines; LE = RX / 4 lanes split a row into float4 columns, so one load
+// instruction fetches whole rows of UL / LE entries.  The unit's lanes read
+// the coordinates of UL entries at once (one per lane) and pass them round
+// with cross-lane moves; then LE steps of UL / LE entries issue all their row
+// loads before the products.
 constexpr int kXcds = 8;
 
-template <int RP>
+template <int RP, int UL>
 __global__ __launch_bounds__(256) void coo_units_kernel(
     RepSet rs, int rows, int rowsX, int rowsY, const int32_t* urow, const int64_t* ustart,
     const int32_t* ulen, const int64_t* ntot, int64_t cap, const int32_t* cx, const int32_t* cy,
     const float* cv, const float* Xf, const float* Yf, float* part) {
-  constexpr int G = 256 / kUnitLanes;  // units per block
+  constexpr int G = 256 / UL;             // units per block
+  constexpr int RX = RP <= 16 ? 16 : 32;  // floats per staged factor row
+  constexpr int LE = RX / 4;              // lanes per entry (float4 columns)
+  constexpr int EPS = UL / LE;            // entries per step
   const int64_t T = *ntot < cap ? *ntot : cap;
   const int64_t per = (T + kXcds - 1) / kXcds;
   const int xcd = blockIdx.x % kXcds;
   const int64_t lb = blockIdx.x / kXcds;
-  const int grp = threadIdx.x / kUnitLanes, l = threadIdx.x % kUnitLanes;
+  const int grp = threadIdx.x / UL, l = threadIdx.x % UL;
+  const int sub = l / LE, c = l % LE;
+  const int base = (threadIdx.x % kWave) - l;  // first lane of the unit in the wavefront
   const int64_t k = lb * G + grp;
   const int64_t gu = xcd * per + k;
   const bool ok = k < per && gu < T;
-  float acc[RP];
-#pragma unroll
-  for (int f = 0; f < RP; ++f) acc[f] = 0.0f;
+  int64_t b0 = 0, b1 = 0;
+  const float4* Xr = nullptr;
+  const float4* Yr = nullptr;
   if (ok) {
-    const int q = urow[gu];
-    const int rep = rs.rep0 + q / rows;
-    const float* Xr = Xf + (int64_t)rep * rowsX * RP;
-    const float* Yr = Yf + (int64_t)rep * rowsY * RP;
-    const int64_t b0 = ustart[gu], b1 = b0 + ulen[gu];
-    for (int64_t e = b0 + l; e < b1; e += kUnitLanes) {
-      const float v = cv[e];
-      const float4* xr = reinterpret_cast<const float4*>(Xr + (int64_t)cx[e] * RP);
-      const float4* yr = reinterpret_cast<const float4*>(Yr + (int64_t)cy[e] * RP);
+    const int rep = rs.rep0 + urow[gu] / rows;
+    Xr = reinterpret_cast<const float4*>(Xf + (int64_t)rep * rowsX * RX);
+    Yr = reinterpret_cast<const float4*>(Yf + (int64_t)rep * rowsY * RX);
+    b0 = ustart[gu];
+    b1 = b0 + ulen[gu];
+  }
+  // the wavefront runs the longest of its units (cross-lane moves need all lanes)
+  int64_t mlen = b1 - b0;
 #pragma unroll
-      for (int f4 = 0; f4 < RP / 4; ++f4) {
-        const float4 a = xr[f4], b = yr[f4];
-        acc[4 * f4 + 0] += v * a.x * b.x;
-        acc[4 * f4 + 1] += v * a.y * b.y;
-        acc[4 * f4 + 2] += v * a.z * b.z;
-        acc[4 * f4 + 3] += v * a.w * b.w;
+  for (int m = UL; m < kWave; m *= 2) {
+    const int64_t o = (int64_t)__shfl_xor((long long)mlen, m, kWave);
+    mlen = o > mlen ? o : mlen;
+  }
+  float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  for (int64_t o = 0; o < mlen; o += UL) {
+    const int64_t e = b0 + o + l;
+    float vv = 0.0f;  // past the end: row 0 times a zero value
+    int32_t xx = 0, yy = 0;
+    if (e < b1) {
+      vv = cv[e];
+      xx = cx[e];
+      yy = cy[e];
+    }
+    float v[LE];
+    int32_t ix[LE], iy[LE];
+#pragma unroll
+    for (int d = 0; d < LE; ++d) {
+      const int src = base + d * EPS + sub;
+      v[d] = __shfl(vv, src, kWave);
+      ix[d] = __shfl(xx, src, kWave);
+      iy[d] = __shfl(yy, src, kWave);
+    }
+    if (Xr) {
+      float4 a[LE], b[LE];
+#pragma unroll
+      for (int d = 0; d < LE; ++d) {
+        a[d] = Xr[(int64_t)ix[d] * LE + c];
+        b[d] = Yr[(int64_t)iy[d] * LE + c];
+      }
+#pragma unroll
+      for (int d = 0; d < LE; ++d) {
+        acc.x += v[d] * a[d].x * b[d].x;
+        acc.y += v[d] * a[d].y * b[d].y;
+        acc.z += v[d] * a[d].z * b[d].z;
+        acc.w += v[d] * a[d].w * b[d].w;
       }
     }
   }
-  // reduce over the 16 lanes of the group (all lanes take part)
+  // add the entry slots of each column (all lanes take part)
 #pragma unroll
-  for (int f = 0; f < RP; ++f) {
-    float t = acc[f];
-    t += __shfl_xor(t, 1, kWave);
-    t += __shfl_xor(t, 2, kWave);
-    t += __shfl_xor(t, 4, kWave);
-    t += __shfl_xor(t, 8, kWave);
-    acc[f] = t;
+  for (int m = LE; m < UL; m *= 2) {
+    acc.x += __shfl_xor(acc.x, m, kWave);
+    acc.y += __shfl_xor(acc.y, m, kWave);
+    acc.z += __shfl_xor(acc.z, m, kWave);
+    acc.w += __shfl_xor(acc.w, m, kWave);
   }
-  if (ok) {
-#pragma unroll
-    for (int f = 0; f < RP; ++f)
-      if (l == (f % kUnitLanes)) part[gu * RP + f] = acc[f];
+  if (ok && sub == 0) {
+    const int f = 4 * c;
+    float* out = part + gu * RP;
+    if (f + 0 < RP) out[f + 0] = acc.x;
+    if (f + 1 < RP) out[f + 1] = acc.y;
+    if (f + 2 < RP) out[f + 2] = acc.z;
+    if (f + 3 < RP) out[f + 3] = acc.w;
   }
 }
 
 // rows of all repetitions: sum the unit partials of the row in order, times
-// V^-1 of the repetition, divided by lam_div for the row solve
+// V^-1 of the repetition, divided by lam_div for the row solve.  64 rows per
+// block, four lanes per row (components f = lane, lane + 4, ...).
+constexpr int kFinRows = 64;
+
 template <int RP>
 __global__ __launch_bounds__(256) void coo_units_finish_kernel(RepSet rs, int rows,
                                                               const int64_t* uoff, int64_t cap,
@@ -446,29 +489,41 @@ __global__ __launch_bounds__(256) void coo_units_finish_kernel(RepSet rs, int ro
                                                               const double* Vinv,
                                                               const double* lam_div,
                                                               double* Uout, int64_t sU) {
-  __shared__ double M[8][kMaxRank];
+  constexpr int FL = RP / 4;  // components per lane
+  __shared__ double M[kFinRows][RP + 1];
   const int R = rs.R;
   const int tid = threadIdx.x;
-  const int r = tid / kMaxRank, f = tid % kMaxRank;
-  const int64_t q = (int64_t)blockIdx.x * 8 + r;
+  const int r = tid / 4, fl = tid % 4;
+  const int64_t q = (int64_t)blockIdx.x * kFinRows + r;
   const bool ok = q < (int64_t)rows * rs.nrep;
-  if (ok && f < R) {
-    double m = 0.0;
+  if (ok) {
+    double m[FL];
+#pragma unroll
+    for (int t = 0; t < FL; ++t) m[t] = 0.0;
     const int64_t u1 = uoff[q + 1] < cap ? uoff[q + 1] : cap;
-    for (int64_t u = uoff[q]; u < u1; ++u) m += (double)part[u * RP + f];
-    M[r][f] = m;
+    for (int64_t u = uoff[q]; u < u1; ++u) {
+#pragma unroll
+      for (int t = 0; t < FL; ++t) m[t] += (double)part[u * RP + fl + 4 * t];
+    }
+#pragma unroll
+    for (int t = 0; t < FL; ++t) M[r][fl + 4 * t] = m[t];
   }
   __syncthreads();
-  if (ok && f < R) {
+  if (ok) {
     const int rep = rs.rep0 + (int)(q / rows), row = (int)(q % rows);
     const double* Vi = Vinv + rep * rs.sG;
-    double u = 0.0;
-    for (int k = 0; k < R; ++k) u += M[r][k] * Vi[k * R + f];
-    if (lam_div) {
-      const double l = lam_div[f];
-      u = l > 0.0 ? u / l : 0.0;
+#pragma unroll
+    for (int t = 0; t < FL; ++t) {
+      const int f = fl + 4 * t;
+      if (f >= R) continue;
+      double u = 0.0;
+      for (int k = 0; k < R; ++k) u += M[r][k] * Vi[k * R + f];
+      if (lam_div) {
+        const double l = lam_div[f];
+        u = l > 0.0 ? u / l : 0.0;
+      }
+      Uout[rep * sU + (int64_t)row * R + f] = u;
     }
-    Uout[rep * sU + (int64_t)row * R + f] = u;
   }
 }
 
@@ -687,28 +742,35 @@ hipError_t launch_coo_units_build(const RepSet& rs, int mode, const CooSummary& 
 
 hipError_t launch_coo_prep(const RepSet& rs, int rows, const double* X, int64_t sX,
                            const double* invlam, float* Xf, hipStream_t s) {
-  const int RP = rp_of4(rs.R);
-  const int64_t n = (int64_t)rows * RP;
+  const int RX = rs.R <= 16 ? 16 : 32;  // row length of the staged copies
+  const int64_t n = (int64_t)rows * RX;
   int blocks = grid_for(n, 256);
   if (blocks > 1024) blocks = 1024;
-  coo_prep_kernel<<<dim3((unsigned)blocks, (unsigned)rs.nrep), 256, 0, s>>>(rs, rows, RP, X, sX,
+  coo_prep_kernel<<<dim3((unsigned)blocks, (unsigned)rs.nrep), 256, 0, s>>>(rs, rows, RX, X, sX,
                                                                           invlam, Xf);
   return hipGetLastError();
 }
 
 hipError_t launch_coo_units(const RepSet& rs, int mode, const CooSummary& z, const CooUnits& u,
                             const float* Xf, int rowsX, const float* Yf, int rowsY, float* part,
-                            hipStream_t s) {
+                            double avg_row_nnz, hipStream_t s) {
   const ModeView m = mode_view(rs, mode, z);
   const int64_t n = (int64_t)m.rows * rs.nrep;
   if (u.cap <= 0) return hipSuccess;
-  constexpr int G = 256 / kUnitLanes;
+  // a wavefront per unit when rows hold many entries on average, else two
+  const bool wide = avg_row_nnz >= 128.0;
+  const int G = wide ? 4 : 8;
   const int64_t per = (u.cap + kXcds - 1) / kXcds;
   const unsigned blocks = (unsigned)(kXcds * ((per + G - 1) / G));
   SBT_COO_RP(rs.R, {
-    coo_units_kernel<RP><<<blocks, 256, 0, s>>>(rs, m.rows, rowsX, rowsY, u.urow, u.ustart,
-                                                u.ulen, u.uoff + n, u.cap, m.cx, m.cy, m.cv, Xf,
-                                                Yf, part);
+    if (wide)
+      coo_units_kernel<RP, 64><<<blocks, 256, 0, s>>>(rs, m.rows, rowsX, rowsY, u.urow,
+                                                      u.ustart, u.ulen, u.uoff + n, u.cap, m.cx,
+                                                      m.cy, m.cv, Xf, Yf, part);
+    else
+      coo_units_kernel<RP, 32><<<blocks, 256, 0, s>>>(rs, m.rows, rowsX, rowsY, u.urow,
+                                                      u.ustart, u.ulen, u.uoff + n, u.cap, m.cx,
+                                                      m.cy, m.cv, Xf, Yf, part);
   });
   return hipGetLastError();
 }
@@ -718,7 +780,7 @@ hipError_t launch_coo_units_finish(const RepSet& rs, int mode, const CooUnits& u
                                    double* U, int64_t sU, hipStream_t s) {
   const int rows = mode == 0 ? rs.n1 : (mode == 1 ? rs.n2 : rs.n3);
   const int64_t n = (int64_t)rows * rs.nrep;
-  const unsigned blocks = (unsigned)((n + 7) / 8);
+  const unsigned blocks = (unsigned)((n + kFinRows - 1) / kFinRows);
   SBT_COO_RP(rs.R, {
     coo_units_finish_kernel<RP><<<blocks, 256, 0, s>>>(rs, rows, u.uoff, u.cap, part, Vinv,
                                                        lam_div, U, sU);

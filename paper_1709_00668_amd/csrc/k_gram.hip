@@ -65,16 +65,34 @@ __global__ __launch_bounds__(256) void xprod_partial_kernel(XProd xp) {
   }
 }
 
+// one block per 64 entries of a matrix: the four wavefronts take every fourth
+// partial, each lane with four independent sums, combined in a fixed order
 __global__ __launch_bounds__(256) void xprod_reduce_kernel(XProd xp) {
-  const int j = blockIdx.x, rep = xp.rep0 + blockIdx.y;
+  __shared__ double red[4][64];
+  const int j = blockIdx.y, rep = xp.rep0 + blockIdx.z;
   const int RR = xp.R * xp.R;
   const int nb = (xp.job[j].rows + kXChunk - 1) / kXChunk;
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  const int p = blockIdx.x * 64 + lane;
   const double* part = xp.part + ((int64_t)rep * xp.njobs + j) * xp.nblk * RR;
-  double* out = xp.out + ((int64_t)rep * xp.njobs + j) * RR;
-  for (int p = threadIdx.x; p < RR; p += 256) {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += part[(int64_t)b * RR + p];
-    out[p] = s;
+  double s = 0.0;
+  if (p < RR) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int b = w;
+    for (; b + 12 < nb; b += 16) {
+      a0 += part[(int64_t)b * RR + p];
+      a1 += part[(int64_t)(b + 4) * RR + p];
+      a2 += part[(int64_t)(b + 8) * RR + p];
+      a3 += part[(int64_t)(b + 12) * RR + p];
+    }
+    for (; b < nb; b += 4) a0 += part[(int64_t)b * RR + p];
+    s = (a0 + a1) + (a2 + a3);
+  }
+  red[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && p < RR) {
+    double* out = xp.out + ((int64_t)rep * xp.njobs + j) * RR;
+    out[p] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
   }
 }
 
@@ -92,7 +110,8 @@ hipError_t launch_xprod(XProd xp, hipStream_t s) {
   xprod_partial_kernel<<<grid, 256, 0, s>>>(xp);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  xprod_reduce_kernel<<<dim3((unsigned)xp.njobs, (unsigned)xp.nrep), 256, 0, s>>>(xp);
+  const unsigned tiles = (unsigned)((xp.R * xp.R + 63) / 64);
+  xprod_reduce_kernel<<<dim3(tiles, (unsigned)xp.njobs, (unsigned)xp.nrep), 256, 0, s>>>(xp);
   return hipGetLastError();
 }
 

@@ -313,15 +313,18 @@ hipError_t launch_coo_sorts(CooSummary& z, int nrep, int64_t total, hipStream_t 
 // unit table of one mode from the row offsets of the summaries
 hipError_t launch_coo_units_build(const RepSet& rs, int mode, const CooSummary& z, CooUnits& u,
                                   hipStream_t s);
-// FP32 scaled copies of factor rows for the sparse MTTKRP: Xf[rep][row][RP]
+// FP32 scaled copies of factor rows for the sparse MTTKRP: Xf[rep][row][RX],
+// RX = 16 for R <= 16, else 32 (zero beyond R)
 hipError_t launch_coo_prep(const RepSet& rs, int rows, const double* X, int64_t sX,
                            const double* invlam, float* Xf, hipStream_t s);
 // partial rows (RP floats per unit) of the MTTKRP of one mode from the FP32
 // copies of the two other factors (rowsX, rowsY rows per repetition); the
-// launch covers u.cap units, the ones past the device-side total return
+// launch covers u.cap units, the ones past the device-side total return.
+// avg_row_nnz (summary entries per row, a host estimate) picks the lanes per
+// unit; the result does not depend on it beyond the order of additions.
 hipError_t launch_coo_units(const RepSet& rs, int mode, const CooSummary& z, const CooUnits& u,
                             const float* Xf, int rowsX, const float* Yf, int rowsY, float* part,
-                            hipStream_t s);
+                            double avg_row_nnz, hipStream_t s);
 // rows U(row, :) = (sum of the row's unit partials, in order) V^-1 [/ lam_div]
 hipError_t launch_coo_units_finish(const RepSet& rs, int mode, const CooUnits& u,
                                    const float* part, const double* Vinv, const double* lam_div,

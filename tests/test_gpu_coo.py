@@ -66,6 +66,23 @@ def test_coo_update_matches_oracle(lib):
     assert gpu.shape()[2] == 60
 
 
+@pytest.mark.parametrize("I,J,K0,R,nnz0,nnz_b", [
+    (80, 70, 40, 20, 6000, 1500),    # rank above 16: 32-float factor rows, 8 lanes per entry
+    (60, 50, 40, 3, 50000, 6000),    # about 200 summary entries per row: a wavefront per unit
+])
+def test_coo_update_unit_shapes(lib, I, J, K0, R, nnz0, nnz_b):
+    reps = 3
+    ora, gpu, ds = run_coo_pair(lib, I, J, K0, 10, 1, R, reps, 10, 2, 23, nnz0, nnz_b)
+    d = ds[-1]
+    for rho in range(reps):
+        for mode, key in enumerate(("Is", "Js", "Ks")):
+            np.testing.assert_array_equal(gpu.last_sample(rho, mode), d["reps"][rho][key])
+    A, B, C, lam = gpu.get_factors()
+    err = np.linalg.norm(C[K0:] - ora.C[K0:]) / np.linalg.norm(ora.C[K0:])
+    assert err < 1e-3, err
+    assert abs(gpu.fit() - ora.fit()) < 1e-3
+
+
 def test_coo_fit_matches_oracle_after_init(lib):
     torch = _torch()
     idx0, v0, _ = sparse_case(50, 40, 30, 5, 1, 2, 2000, 100, 5)
