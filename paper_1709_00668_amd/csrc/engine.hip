@@ -338,15 +338,9 @@ sbt_status alloc_state(sbt_tensor* t) {
     SBT_TRY(dalloc(t, &t->bbase, (size_t)r * (nblk + 1)));
     SBT_TRY(dalloc(t, &t->ing.hist, (size_t)t->Kcap));
     CooSummary& z = t->z;
-    z.sHa = t->n1;
-    z.sHb = t->n2;
-    z.sHc = t->Kpmax;
     z.sOffA = t->n1 + 1;
     z.sOffB = t->n2 + 1;
     z.sOffC = t->Kpmax + 1;
-    SBT_TRY(dalloc(t, &z.ha, (size_t)r * z.sHa));
-    SBT_TRY(dalloc(t, &z.hb, (size_t)r * z.sHb));
-    SBT_TRY(dalloc(t, &z.hc, (size_t)r * z.sHc));
     SBT_TRY(dalloc(t, &z.offA, (size_t)r * z.sOffA));
     SBT_TRY(dalloc(t, &z.offB, (size_t)r * z.sOffB));
     SBT_TRY(dalloc(t, &z.offC, (size_t)r * z.sOffC));
@@ -483,16 +477,12 @@ sbt_status coo_build_summaries(sbt_tensor* t, int64_t Kold, int n3old, int Kp, h
   SBT_TRY(ensure_summary(t, total, st));
   SBT_CK(hipMemcpyAsync(z.rep_off, z.rep_off_h, sizeof(int64_t) * (r + 1), hipMemcpyHostToDevice,
                         st));
-  SBT_CK(launch_fill_u32(z.ha, (int64_t)r * z.sHa, 0, st));
-  SBT_CK(launch_fill_u32(z.hb, (int64_t)r * z.sHb, 0, st));
-  SBT_CK(launch_fill_u32(z.hc, (int64_t)r * z.sHc, 0, st));
   const int gq = prof_begin(t, st);
   SBT_CK(launch_coo_emit(t->ci, t->cj, t->ck, t->cv, nnz_all, t->bitI, t->bitJ, t->bitK, Kold,
                          n3old, r, t->posI, t->posJ, t->posK, t->I, t->J, t->Kcap, t->bbase, z,
                          st));
   prof_end(t, gq, SBT_K_GATHER, (double)nnz_all * 16.0 + (double)total * 16.0, st);
-  SBT_CK(launch_coo_offsets(z, r, t->n1, t->n2, Kp, st));
-  SBT_CK(launch_coo_sorts(z, r, total, st));
+  SBT_CK(launch_coo_sorts(z, r, total, t->n1, t->n2, Kp, st));
   RepSet rs = make_repset(t, Kp, 0, r);
   for (int m = 0; m < 3; ++m) SBT_CK(launch_coo_units_build(rs, m, z, t->cu[m], st));
   return SBT_OK;

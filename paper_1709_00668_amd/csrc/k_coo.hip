@@ -63,19 +63,35 @@ __global__ void coo_place_kernel(const int32_t* bi, const int32_t* bj, const int
   }
 }
 
-// Exclusive scan of cnt[0..n) (uint32) into out (int64) + add base; one block.
-__global__ __launch_bounds__(1024) void scan_to_offsets_kernel(const uint32_t* cnt, int64_t n,
-                                                              int64_t base, int64_t* out) {
+// Exclusive scans of several count arrays at once, one block per array:
+// out_b[0..n] = base_b + exclusive prefix sums of cnt_b[0..n), out_b[n] the
+// total (cnt_b = cnt + b * scnt, out_b = out + b * sout, base_b = base0 plus
+// bases[b] when given).  Each thread adds up kScanItems consecutive counts before the wave and
+// block scans, so a block covers 8192 counts per round.
+constexpr int kScanItems = 8;
+
+__global__ __launch_bounds__(1024) void scan_to_offsets_kernel(const uint32_t* cnt, int64_t scnt,
+                                                              int64_t n, int64_t base0,
+                                                              const int64_t* bases, int64_t* out,
+                                                              int64_t sout) {
   __shared__ int64_t wsum[16];
   __shared__ int64_t carry;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  if (tid == 0) carry = base;
+  const uint32_t* c = cnt + (int64_t)blockIdx.x * scnt;
+  int64_t* o = out + (int64_t)blockIdx.x * sout;
+  if (tid == 0) carry = base0 + (bases ? bases[blockIdx.x] : 0);
   __syncthreads();
-  for (int64_t c0 = 0; c0 < n; c0 += 1024) {
-    const int64_t i = c0 + tid;
-    int64_t v = i < n ? (int64_t)cnt[i] : 0;
-    // inclusive wave scan
-    int64_t x = v;
+  for (int64_t c0 = 0; c0 < n; c0 += 1024 * kScanItems) {
+    const int64_t i0 = c0 + (int64_t)tid * kScanItems;
+    int64_t v[kScanItems];
+    int64_t t = 0;
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+      v[q] = i0 + q < n ? (int64_t)c[i0 + q] : 0;
+      t += v[q];
+    }
+    // inclusive wave scan of the thread totals
+    int64_t x = t;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
       const int64_t y = __shfl_up(x, off, 64);
@@ -85,16 +101,21 @@ __global__ __launch_bounds__(1024) void scan_to_offsets_kernel(const uint32_t* c
     __syncthreads();
     int64_t pre = carry;
     for (int w = 0; w < wave; ++w) pre += wsum[w];
-    if (i < n) out[i] = pre + x - v;
+    pre += x - t;
+#pragma unroll
+    for (int q = 0; q < kScanItems; ++q) {
+      if (i0 + q < n) o[i0 + q] = pre;
+      pre += v[q];
+    }
     __syncthreads();
     if (tid == 0) {
-      int64_t t = 0;
-      for (int w = 0; w < 16; ++w) t += wsum[w];
-      carry += t;
+      int64_t s = 0;
+      for (int w = 0; w < 16; ++w) s += wsum[w];
+      carry += s;
     }
     __syncthreads();
   }
-  if (tid == 0) out[n] = carry;
+  if (tid == 0) o[n] = carry;
 }
 
 // --------------------------------------------------------------------------
@@ -165,55 +186,78 @@ __device__ inline uint64_t lmask_lt() {
   return l == 0 ? 0ull : (~0ull >> (64 - l));
 }
 
+__device__ inline uint64_t wave_or(uint64_t m) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1)
+    m |= (uint64_t)__shfl_xor((unsigned long long)m, off, 64);
+  return m;
+}
+
 // Emit the kept entries of every repetition in store order (hence sorted by
-// c) at bbase[rep][block] + the rank within the block, and count the a, b, c
-// histograms of each repetition.
+// c) at bbase[rep][block] + the rank within the block.  Each wavefront owns a contiguous run of
+// kCooPerThread * 64 of the block's entries.  A first pass counts, per wavefront and repetition, the kept
+// entries (masks stay in registers); after one block barrier every wavefront
+// knows where its entries of each repetition start and writes them in store
+// order with ballots alone.
 __global__ __launch_bounds__(kCooBlock) void summary_emit_kernel(
     const int32_t* si, const int32_t* sj, const int32_t* sk, const float* sv, int64_t nnz,
     const uint64_t* bitI, const uint64_t* bitJ, const uint64_t* bitK, int64_t Kold, int n3old,
     int nrep, const int32_t* posI, const int32_t* posJ, const int32_t* posK, int64_t I,
     int64_t J, int64_t Kcap, const int64_t* bbase, const int64_t* rep_off, int64_t nblk,
-    int32_t* za, int32_t* zb,
-    int32_t* zc, float* zv, uint32_t* ha, uint32_t* hb, uint32_t* hc, int64_t sHa,
-    int64_t sHb, int64_t sHc) {
-  __shared__ uint32_t wcnt[kCooBlock / 64][64];
-  __shared__ int64_t run[64];
-  const int tid = threadIdx.x, wave = tid >> 6;
+    int32_t* za, int32_t* zb, int32_t* zc, float* zv) {
+  constexpr int W = kCooBlock / 64;
+  __shared__ uint32_t wc[W][64];  // kept entries per wavefront and repetition
+  __shared__ int64_t wb[W][64];   // next output position per wavefront and repetition
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const uint64_t all = nrep >= 64 ? ~0ull : ((1ull << nrep) - 1);
-  __shared__ unsigned long long bm;
-  if (tid < 64) run[tid] = tid < nrep ? rep_off[tid] + bbase[(int64_t)tid * (nblk + 1) + blockIdx.x] : 0;
+  wc[wave][lane] = 0;
   __syncthreads();
-  const int64_t e0 = (int64_t)blockIdx.x * kCooChunk;
+  const int64_t e0 = (int64_t)blockIdx.x * kCooChunk + (int64_t)wave * 64 * kCooPerThread;
+  uint64_t mk[kCooPerThread];
+#pragma unroll
   for (int u = 0; u < kCooPerThread; ++u) {
-    const int64_t e = e0 + u * kCooBlock + tid;
+    const int64_t e = e0 + u * 64 + lane;
+    const uint64_t m = e < nnz ? entry_mask(si[e], sj[e], sk[e], bitI, bitJ, bitK, Kold, all) : 0;
+    mk[u] = m;
+    uint64_t un = wave_or(m);
+    while (un) {
+      const int rep = __ffsll((unsigned long long)un) - 1;
+      un &= un - 1;
+      const uint64_t bal = __ballot((m >> rep) & 1ull);
+      if (lane == 0) wc[wave][rep] += (uint32_t)__popcll(bal);
+    }
+  }
+  __syncthreads();
+  if (tid < nrep) {
+    int64_t p = rep_off[tid] + bbase[(int64_t)tid * (nblk + 1) + blockIdx.x];
+    for (int w = 0; w < W; ++w) {
+      wb[w][tid] = p;
+      p += wc[w][tid];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kCooPerThread; ++u) {
+    const uint64_t m = mk[u];
+    uint64_t un = wave_or(m);
+    if (!un) continue;
+    const int64_t e = e0 + u * 64 + lane;
     int32_t i = 0, j = 0, k = 0;
     float v = 0.0f;
-    uint64_t m = 0;
-    if (e < nnz) {
+    if (m) {
       i = si[e];
       j = sj[e];
       k = sk[e];
       v = sv[e];
-      m = entry_mask(i, j, k, bitI, bitJ, bitK, Kold, all);
     }
-    // block-wide union of the masks decides which repetitions need a prefix
-    if (tid == 0) bm = 0ull;
-    __syncthreads();
-    if (m) atomicOr(&bm, (unsigned long long)m);
-    __syncthreads();
-    uint64_t reps = bm;
-    __syncthreads();
-    while (reps) {
-      const int rep = __ffsll((unsigned long long)reps) - 1;
-      reps &= reps - 1;
+    while (un) {
+      const int rep = __ffsll((unsigned long long)un) - 1;
+      un &= un - 1;
       const bool keep = (m >> rep) & 1ull;
       const uint64_t bal = __ballot(keep);
-      if ((tid & 63) == 0) wcnt[wave][rep] = (uint32_t)__popcll(bal);
-      __syncthreads();
-      int64_t pos = run[rep];
-      for (int w = 0; w < wave; ++w) pos += wcnt[w][rep];
-      pos += __popcll(bal & lmask_lt());
+      const int64_t base = wb[wave][rep];
       if (keep) {
+        const int64_t pos = base + __popcll(bal & lmask_lt());
         const int a = posI[rep * I + i];
         const int b = posJ[rep * J + j];
         const int c = k < Kold ? posK[rep * Kcap + k] : n3old + (int)(k - Kold);
@@ -221,22 +265,56 @@ __global__ __launch_bounds__(kCooBlock) void summary_emit_kernel(
         zb[pos] = b;
         zc[pos] = c;
         zv[pos] = v;
-        atomicAdd(&ha[rep * sHa + a], 1u);
-        atomicAdd(&hb[rep * sHb + b], 1u);
-        atomicAdd(&hc[rep * sHc + c], 1u);
       }
-      __syncthreads();
-      if (tid == 0) {
-        int64_t t = 0;
-        for (int w = 0; w < kCooBlock / 64; ++w) t += wcnt[w][rep];
-        run[rep] += t;
-      }
-      __syncthreads();
+      if (lane == 0) wb[wave][rep] = base + __popcll(bal);
     }
   }
 }
 
 // keys (rep << 24 | row) for the stable sorts by a and by b
+// Row offsets of every repetition from the concatenated summaries sorted by
+// (repetition, row): off[rep * sOff + x] = position of the first entry of
+// (rep, x) or of the first later key, for x in [0, rows].  Thread p looks at
+// the keys on both sides of position p (p in [0, total]) and writes the
+// offsets of all (rep, x) pairs falling between them, so each offset is
+// written once.  Keys come from `key` ((rep << 24) | row) or, with key null,
+// from `row` and the repetition ranges rep_off.
+__device__ inline int rep_at(const int64_t* rep_off, int nrep, int64_t p) {
+  int r = 0;
+  while (r + 1 < nrep && rep_off[r + 1] <= p) ++r;
+  return r;
+}
+
+__global__ void summary_offsets_kernel(const uint32_t* key, const int32_t* row,
+                                       const int64_t* rep_off, int nrep, int64_t total, int rows,
+                                       int64_t* off, int64_t sOff) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p > total) return;
+  // (rep, x) before position p and at position p, as linear indices rep * (rows + 1) + x
+  const int64_t W = (int64_t)rows + 1;
+  int64_t lo, hi;
+  if (p == 0) {
+    lo = -1;
+  } else if (key) {
+    const uint32_t k = key[p - 1];
+    lo = (int64_t)(k >> 24) * W + (k & 0xFFFFFFu);
+  } else {
+    lo = (int64_t)rep_at(rep_off, nrep, p - 1) * W + row[p - 1];
+  }
+  if (p == total) {
+    hi = (int64_t)nrep * W - 1;  // through x = rows of the last repetition
+  } else if (key) {
+    const uint32_t k = key[p];
+    hi = (int64_t)(k >> 24) * W + (k & 0xFFFFFFu);
+  } else {
+    hi = (int64_t)rep_at(rep_off, nrep, p) * W + row[p];
+  }
+  for (int64_t q = lo + 1; q <= hi; ++q) {
+    const int64_t r = q / W, x = q % W;
+    off[r * sOff + x] = p;
+  }
+}
+
 __global__ void summary_keys_kernel(const int32_t* za, const int32_t* zb, const int64_t* rep_off,
                                     int nrep, int64_t total, uint32_t* key_a, uint32_t* key_b,
                                     int32_t* val) {
@@ -594,7 +672,7 @@ hipError_t launch_coo_ingest(const int32_t* bi, const int32_t* bj, const int32_t
     // no entries: every new slice is empty
     hipError_t e = launch_fill_u32(w.hist, Knew, 0, s);
     if (e != hipSuccess) return e;
-    scan_to_offsets_kernel<<<1, 1024, 0, s>>>(w.hist, Knew, base, koff + Kold);
+    scan_to_offsets_kernel<<<1, 1024, 0, s>>>(w.hist, 0, Knew, base, nullptr, koff + Kold, 0);
     return hipGetLastError();
   }
   hipError_t e;
@@ -612,7 +690,7 @@ hipError_t launch_coo_ingest(const int32_t* bi, const int32_t* bj, const int32_t
                                                           sj, sk, sv, base, w.hist);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  scan_to_offsets_kernel<<<1, 1024, 0, s>>>(w.hist, Knew, base, koff + Kold);
+  scan_to_offsets_kernel<<<1, 1024, 0, s>>>(w.hist, 0, Knew, base, nullptr, koff + Kold, 0);
   return hipGetLastError();
 }
 
@@ -647,13 +725,9 @@ hipError_t launch_coo_count(const int32_t* si, const int32_t* sj, const int32_t*
   if (e != hipSuccess) return e;
   // per repetition exclusive scan over blocks; repetition rho starts where
   // rho - 1 ends, so bbase[rho][0] is the offset of rho's summary
-  for (int r = 0; r < nrep; ++r) {
-    scan_to_offsets_kernel<<<1, 1024, 0, s>>>(bcount + (int64_t)r * nblk, nblk, 0,
-                                              bbase + (int64_t)r * (nblk + 1));
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  scan_to_offsets_kernel<<<(unsigned)nrep, 1024, 0, s>>>(bcount, nblk, nblk, 0, nullptr, bbase,
+                                                         nblk + 1);
+  return hipGetLastError();
 }
 
 hipError_t launch_coo_emit(const int32_t* si, const int32_t* sj, const int32_t* sk,
@@ -665,25 +739,31 @@ hipError_t launch_coo_emit(const int32_t* si, const int32_t* sj, const int32_t* 
   const int64_t nblk = coo_scan_blocks(nnz);
   summary_emit_kernel<<<(unsigned)nblk, kCooBlock, 0, s>>>(
       si, sj, sk, sv, nnz, bitI, bitJ, bitK, Kold, n3old, nrep, posI, posJ, posK, I, J, Kcap,
-      bbase, z.rep_off, nblk, z.a, z.b, z.c, z.v, z.ha, z.hb, z.hc, z.sHa, z.sHb, z.sHc);
+      bbase, z.rep_off, nblk, z.a, z.b, z.c, z.v);
   return hipGetLastError();
 }
 
-hipError_t launch_coo_offsets(CooSummary& z, int nrep, int n1, int n2, int n3, hipStream_t s) {
-  for (int r = 0; r < nrep; ++r) {
-    const int64_t base = z.rep_off_h[r];
-    scan_to_offsets_kernel<<<1, 1024, 0, s>>>(z.ha + r * z.sHa, n1, base, z.offA + r * z.sOffA);
-    scan_to_offsets_kernel<<<1, 1024, 0, s>>>(z.hb + r * z.sHb, n2, base, z.offB + r * z.sOffB);
-    scan_to_offsets_kernel<<<1, 1024, 0, s>>>(z.hc + r * z.sHc, n3, base, z.offC + r * z.sOffC);
+
+hipError_t launch_coo_sorts(CooSummary& z, int nrep, int64_t total, int n1, int n2, int n3,
+                            hipStream_t s) {
+  const unsigned go = (unsigned)grid_for(total + 1, 256);
+  // c: the summaries are in store order, sorted by c within each repetition
+  summary_offsets_kernel<<<go, 256, 0, s>>>(nullptr, z.c, z.rep_off, nrep, total, n3, z.offC,
+                                            z.sOffC);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || total <= 0) {
+    if (e == hipSuccess) {  // no entries: every row of every repetition is empty
+      summary_offsets_kernel<<<go, 256, 0, s>>>(nullptr, z.a, z.rep_off, nrep, 0, n1, z.offA,
+                                                z.sOffA);
+      summary_offsets_kernel<<<go, 256, 0, s>>>(nullptr, z.b, z.rep_off, nrep, 0, n2, z.offB,
+                                                z.sOffB);
+      e = hipGetLastError();
+    }
+    return e;
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_coo_sorts(CooSummary& z, int nrep, int64_t total, hipStream_t s) {
-  if (total <= 0) return hipSuccess;
   summary_keys_kernel<<<grid_for(total, 256 * 16), 256, 0, s>>>(z.a, z.b, z.rep_off, nrep, total,
                                                                  z.key_a, z.key_b, z.val);
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   int bits = 24;
   while ((1ll << (bits - 24)) < nrep) ++bits;
@@ -693,6 +773,8 @@ hipError_t launch_coo_sorts(CooSummary& z, int nrep, int64_t total, hipStream_t 
   if (e != hipSuccess) return e;
   summary_permute_kernel<<<grid_for(total, 256 * 16), 256, 0, s>>>(z.perm, total, z.b, z.c, z.v,
                                                                     z.a_x, z.a_y, z.a_v);
+  summary_offsets_kernel<<<go, 256, 0, s>>>(z.key_out, nullptr, z.rep_off, nrep, total, n1,
+                                            z.offA, z.sOffA);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   tb = z.tmp_bytes;
@@ -701,6 +783,8 @@ hipError_t launch_coo_sorts(CooSummary& z, int nrep, int64_t total, hipStream_t 
   if (e != hipSuccess) return e;
   summary_permute_kernel<<<grid_for(total, 256 * 16), 256, 0, s>>>(z.perm, total, z.a, z.c, z.v,
                                                                     z.b_x, z.b_y, z.b_v);
+  summary_offsets_kernel<<<go, 256, 0, s>>>(z.key_out, nullptr, z.rep_off, nrep, total, n2,
+                                            z.offB, z.sOffB);
   return hipGetLastError();
 }
 
@@ -732,7 +816,7 @@ hipError_t launch_coo_units_build(const RepSet& rs, int mode, const CooSummary& 
   coo_unit_count_kernel<<<blocks, 256, 0, s>>>(m.off, m.sOff, m.rows, rs.nrep, u.cnt);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  scan_to_offsets_kernel<<<1, 1024, 0, s>>>(u.cnt, n, 0, u.uoff);
+  scan_to_offsets_kernel<<<1, 1024, 0, s>>>(u.cnt, 0, n, 0, nullptr, u.uoff, 0);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   coo_unit_fill_kernel<<<blocks, 256, 0, s>>>(m.off, m.sOff, m.rows, rs.nrep, u.uoff, u.cap,

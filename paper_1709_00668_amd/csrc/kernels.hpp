@@ -258,8 +258,6 @@ struct CooSummary {   // the r summaries of one update, concatenated by repetiti
   float* a_v;
   int32_t *b_x, *b_y;       // sorted by b: (a, c)
   float* b_v;
-  uint32_t *ha, *hb, *hc;   // per repetition histograms of a, b, c
-  int64_t sHa, sHb, sHc;
   int64_t *offA, *offB, *offC;  // per repetition row offsets (absolute)
   int64_t sOffA, sOffB, sOffC;
   int64_t* rep_off;         // device copy of rep_off_h (nrep + 1)
@@ -306,8 +304,10 @@ hipError_t launch_coo_emit(const int32_t* si, const int32_t* sj, const int32_t* 
                            int nrep, const int32_t* posI, const int32_t* posJ,
                            const int32_t* posK, int64_t I, int64_t J, int64_t Kcap,
                            const int64_t* bbase, CooSummary& z, hipStream_t s);
-hipError_t launch_coo_offsets(CooSummary& z, int nrep, int n1, int n2, int n3, hipStream_t s);
-hipError_t launch_coo_sorts(CooSummary& z, int nrep, int64_t total, hipStream_t s);
+// the copies sorted by a and by b, and the row offsets of all three modes
+// (n1, n2, n3 rows per repetition) from the sorted keys
+hipError_t launch_coo_sorts(CooSummary& z, int nrep, int64_t total, int n1, int n2, int n3,
+                            hipStream_t s);
 // rows of mode `mode` (0: A from B, C; 1: B from A, C; 2: C from A, B):
 // U = (COO MTTKRP) V^-1, or divided by lam_div (row solve)
 // unit table of one mode from the row offsets of the summaries
