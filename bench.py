@@ -38,7 +38,8 @@ kernel when a committed measurement of the current kernel sources exists.
 cpu_baseline (dense workloads): the CPU FP64 oracle on the first
 --cpu-updates updates of the same workload.  recompute (dense workloads):
 CP-ALS of the whole grown tensor on the GPU and the relative fitness of the
-incremental result against it (Sec. 4.2).
+incremental result against it (Sec. 4.2); fms_truth: the factor match score
+(Sec. 4.4, on the GPU) of the final model against the generating components.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--workload dense500]
 """
@@ -106,9 +107,10 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if xs else None
 
 
-def timed_sequence(sbt, torch, fresh, apply_batch, steps, warmup, latency_runs, Kn):
+def timed_sequence(sbt, torch, fresh, apply_batch, steps, warmup, latency_runs, Kn, truth=None):
     """Warm-up on a throwaway tensor, then exactly `steps` timed updates with the
-    per-kind launch timing on; extra untimed sequences for latency samples."""
+    per-kind launch timing on; extra untimed sequences for latency samples.
+    truth: the generating model of the grown tensor, scored by FMS (GPU)."""
     kinds = {"mttkrp_contract_c": sbt.SBT_K_MTTKRP_C, "mttkrp_third_mode": sbt.SBT_K_MTTKRP_AB,
              "row_solve": sbt.SBT_K_ROW_SOLVE, "gather": sbt.SBT_K_GATHER,
              "coo_mttkrp": sbt.SBT_K_COO_MTTKRP, "update": sbt.SBT_K_UPDATE}
@@ -134,6 +136,10 @@ def timed_sequence(sbt, torch, fresh, apply_batch, steps, warmup, latency_runs, 
         prof[name] = dict(launches=n, total_ms=ms, alg_bytes=by)
     T.profile_enable(False)
     fit = T.fit()
+    extra = {}
+    if truth is not None:
+        extra["fms_truth"] = T.fms(*truth)
+        extra["factors"] = T.get_factors()
     T.close()
     for _ in range(max(0, latency_runs - 1)):
         T = fresh()
@@ -145,10 +151,11 @@ def timed_sequence(sbt, torch, fresh, apply_batch, steps, warmup, latency_runs, 
         T.close()
     return dict(slices_per_s=steps * Kn / wall, wall_s=wall, ms_per_step=1e3 * wall / steps,
                 p50_ms=1e3 * percentile(lat, 50), p99_ms=1e3 * percentile(lat, 99),
-                latency_samples=len(lat), fit=fit, profile=prof)
+                latency_samples=len(lat), fit=fit, profile=prof, **extra)
 
 
-def run_dense(sbt, torch, w, Xd, model, precision, schedule, steps, warmup, latency_runs):
+def run_dense(sbt, torch, w, Xd, model, precision, schedule, steps, warmup, latency_runs,
+              truth=None):
     I, J, K0, Kn = w["I"], w["J"], w["K0"], w["Kn"]
     cfg = sbt.make_config(w["R"], w["r"], w["iters"], w["s"], w["seed"], precision=precision,
                           schedule=schedule, k_capacity=K0 + steps * Kn, max_batch=Kn)
@@ -159,7 +166,8 @@ def run_dense(sbt, torch, w, Xd, model, precision, schedule, steps, warmup, late
     def apply_batch(T, b):
         T.update_batch_dense(Xd[K0 + b * Kn:K0 + (b + 1) * Kn], Kn)
 
-    return timed_sequence(sbt, torch, fresh, apply_batch, steps, warmup, latency_runs, Kn)
+    return timed_sequence(sbt, torch, fresh, apply_batch, steps, warmup, latency_runs, Kn,
+                          truth=truth)
 
 
 def source_digest():
@@ -282,6 +290,7 @@ def bench_dense(args, sbt, torch, synth, log):
     log(f"# data ready: {I}x{J}x{K} fp32, {Xkji.nbytes / 1e9:.2f} GB on device "
         f"({time.perf_counter() - t0:.1f} s)")
     model = gen.true_model_prefix(K0)
+    truth = gen.true_model_prefix(K)  # generating components of the grown tensor
     main_prec = sbt.SBT_P_F32 if name == "dense500" else sbt.SBT_P_BF16
     order = [("batched_f32", sbt.SBT_P_F32, sbt.SBT_SCHED_BATCHED),
              ("batched_bf16", sbt.SBT_P_BF16, sbt.SBT_SCHED_BATCHED)]
@@ -291,7 +300,8 @@ def bench_dense(args, sbt, torch, synth, log):
     for key, prec, sched in order:
         main = prec == main_prec and sched == sbt.SBT_SCHED_BATCHED
         lr = args.latency_runs if main else max(1, min(args.latency_runs, 2))
-        runs[key] = run_dense(sbt, torch, w, Xd, model, prec, sched, steps, args.warmup, lr)
+        runs[key] = run_dense(sbt, torch, w, Xd, model, prec, sched, steps, args.warmup, lr,
+                              truth=truth if main else None)
         log(f"# {key}: {runs[key]['slices_per_s']:.1f} slices/s, fit {runs[key]['fit']:.6f}")
     main = "batched_f32" if main_prec == sbt.SBT_P_F32 else "batched_bf16"
     b = runs[main]
@@ -319,11 +329,17 @@ def bench_dense(args, sbt, torch, synth, log):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         fr = T.fit()
+        fms_rt = T.fms(*truth)
+        fms_sr = T.fms(*b["factors"])
         T.close()
         line["recompute"] = {"fit": round(fr, 6), "seconds": round(dt, 4),
                              "als_sweeps": args.recompute_iters,
-                             "relative_fitness": round((1.0 - b["fit"]) / max(1e-12, 1.0 - fr), 4)}
-        log(f"# recompute CP-ALS: fit {fr:.6f} in {dt:.2f} s")
+                             "relative_fitness": round((1.0 - b["fit"]) / max(1e-12, 1.0 - fr), 4),
+                             "fms_vs_sambaten": round(fms_sr, 4),
+                             "fms_truth": round(fms_rt, 4)}
+        log(f"# recompute CP-ALS: fit {fr:.6f} in {dt:.2f} s, FMS vs truth {fms_rt:.4f}")
+    if "fms_truth" in b:
+        line["fms_truth"] = round(b["fms_truth"], 4)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline_dense(w, Xkji.transpose(2, 1, 0), model, args.cpu_updates)

@@ -147,6 +147,20 @@ sbt_status sbt_get_factors(sbt_tensor* t, double* A, double* B, double* C, doubl
  * over the tensor and the factor Gram matrices. */
 sbt_status sbt_fit(sbt_tensor* t, double* fit, void* stream);
 
+/* Factor match score (Sec. 4.4) of the tensor's current model against a
+ * reference model of the same shape and rank, given in device memory in the
+ * layout of sbt_get_factors (row-major A_ref I x R, B_ref J x R, C_ref K x R,
+ * lambda_ref R; K the tensor's current slice count).  Columns of both models
+ * are scaled to unit norm with the norms moved into the weights; components
+ * are paired by the maximum-weight assignment on the product over the modes
+ * of |cosine|; each pair scores that product times the weight penalty
+ * 1 - |l1 - l2| / max(l1, l2); *score (host) is the mean over the R pairs,
+ * in [0, 1] (1: the same components).  Computed on the GPU in FP64 on
+ * `stream`; returns when *score is written.  The reference buffers stay the
+ * caller's.  Errors: SBT_E_INVALID for NULL pointers, SBT_E_DEVICE. */
+sbt_status sbt_fms(sbt_tensor* t, const double* A_ref, const double* B_ref, const double* C_ref,
+                   const double* lambda_ref, double* score, void* stream);
+
 /* Number of completed updates (the batch counter that keys the sampler). */
 sbt_status sbt_get_batch_counter(const sbt_tensor* t, uint32_t* counter);
 

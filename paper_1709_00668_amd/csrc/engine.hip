@@ -316,7 +316,7 @@ sbt_status alloc_state(sbt_tensor* t) {
     t->xnblk = xprod_blocks(mr);
     const int64_t fit_nblk = xprod_blocks((int)mf);
     int64_t np = (int64_t)r * 9 * t->xnblk;
-    if (3 * fit_nblk > np) np = 3 * fit_nblk;
+    if (9 * fit_nblk > np) np = 9 * fit_nblk;  // fit: 3 products, FMS: 9
     SBT_TRY(dalloc(t, &t->xpart, (size_t)np * R * R));
     t->xpart_mats = np;
     SBT_TRY(dalloc(t, &t->xout, (size_t)r * 9 * R * R));
@@ -1309,6 +1309,41 @@ sbt_status sbt_fit(sbt_tensor* t, double* fit, void* stream) {
   }
   SBT_CK(launch_fit_final(t->xout, t->C, t->lam, t->M3, t->nrm, t->K, t->R, t->fitv, st));
   SBT_CK(hipMemcpyAsync(fit, t->fitv, sizeof(double), hipMemcpyDeviceToHost, st));
+  SBT_CK(hipStreamSynchronize(st));
+  return SBT_OK;
+}
+
+sbt_status sbt_fms(sbt_tensor* t, const double* A_ref, const double* B_ref, const double* C_ref,
+                   const double* lambda_ref, double* score, void* stream) {
+  if (!t || !A_ref || !B_ref || !C_ref || !lambda_ref || !score) return SBT_E_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  XProd xp{};
+  const int I = (int)t->I, J = (int)t->J, K = (int)t->K;
+  xp.job[0] = XJob{t->A, 0, nullptr, 0, A_ref, 0, nullptr, 0, I};
+  xp.job[1] = XJob{t->B, 0, nullptr, 0, B_ref, 0, nullptr, 0, J};
+  xp.job[2] = XJob{t->C, 0, nullptr, 0, C_ref, 0, nullptr, 0, K};
+  xp.job[3] = XJob{t->A, 0, nullptr, 0, t->A, 0, nullptr, 0, I};
+  xp.job[4] = XJob{t->B, 0, nullptr, 0, t->B, 0, nullptr, 0, J};
+  xp.job[5] = XJob{t->C, 0, nullptr, 0, t->C, 0, nullptr, 0, K};
+  xp.job[6] = XJob{A_ref, 0, nullptr, 0, A_ref, 0, nullptr, 0, I};
+  xp.job[7] = XJob{B_ref, 0, nullptr, 0, B_ref, 0, nullptr, 0, J};
+  xp.job[8] = XJob{C_ref, 0, nullptr, 0, C_ref, 0, nullptr, 0, K};
+  xp.njobs = 9;
+  xp.R = t->R;
+  xp.rep0 = 0;
+  xp.nrep = 1;
+  int mr = I > J ? I : J;
+  if (K > mr) mr = K;
+  xp.nblk = xprod_blocks(mr);
+  if (9 * (int64_t)xp.nblk > t->xpart_mats) {
+    set_err(t, "cross-product workspace too small for the factor match score");
+    return SBT_E_SHAPE;
+  }
+  xp.part = t->xpart;
+  xp.out = t->xout;
+  SBT_CK(launch_xprod(xp, st));
+  SBT_CK(launch_fms(t->xout, t->lam, lambda_ref, t->R, t->fitv, st));
+  SBT_CK(hipMemcpyAsync(score, t->fitv, sizeof(double), hipMemcpyDeviceToHost, st));
   SBT_CK(hipStreamSynchronize(st));
   return SBT_OK;
 }

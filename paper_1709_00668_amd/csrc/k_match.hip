@@ -320,6 +320,58 @@ __global__ __launch_bounds__(256) void sort_components_kernel(double* A, double*
     for (int f = 0; f < R; ++f) lam[f] = lam_s[perm[f]];
 }
 
+// Factor match score of two R-component models (Sec. 4.4) from nine R x R
+// cross products: xo[0..2] = A1^T A2, B1^T B2, C1^T C2, xo[3..5] = the Gram
+// matrices of model 1, xo[6..8] those of model 2.  Columns are compared after
+// scaling to unit norm (the norms go into the weights); the similarity of
+// component f of model 1 and g of model 2 is the product over the modes of
+// |cosine|; the components are paired by the maximum-weight assignment on it;
+// each pair scores its similarity times 1 - |l1 - l2| / max(l1, l2), and the
+// score is the mean over the pairs.  One block.
+__global__ __launch_bounds__(256) void fms_kernel(const double* xo, const double* lam1,
+                                                 const double* lam2, int R, double* out) {
+  const int RR = R * R;
+  const int tid = threadIdx.x;
+  __shared__ double S[kMaxRank][kMaxRank + 1];
+  __shared__ double nrm[6][kMaxRank];  // model 1: A, B, C; model 2: A, B, C
+  __shared__ int pi_s[kMaxRank];
+  __shared__ double part[kMaxRank];
+  if (tid < 6 * R) {
+    const int which = tid / R, f = tid % R;
+    const double d = xo[(3 + which) * RR + f * R + f];
+    nrm[which][f] = sqrt(d > 0.0 ? d : 0.0);
+  }
+  __syncthreads();
+  for (int q = tid; q < RR; q += 256) {
+    const int f = q / R, g = q % R;
+    double sv = 1.0;
+    for (int n = 0; n < 3; ++n) {
+      const double d = nrm[n][f] * nrm[3 + n][g];
+      sv *= d > 0.0 ? fabs(xo[n * RR + q]) / d : 0.0;
+    }
+    S[f][g] = sv >= 0.0 ? sv : 0.0;
+  }
+  __syncthreads();
+  if (tid < R) pi_s[tid] = tid;
+  __syncthreads();
+  if (tid < kWave) hungarian_wave(S, R, pi_s);
+  __syncthreads();
+  if (tid < R) {
+    const int f = tid, g = pi_s[f];
+    const double l1 = fabs(lam1[f]) * nrm[0][f] * nrm[1][f] * nrm[2][f];
+    const double l2 = fabs(lam2[g]) * nrm[3][g] * nrm[4][g] * nrm[5][g];
+    const double mx = l1 > l2 ? l1 : l2;
+    const double pen = mx > 0.0 ? 1.0 - fabs(l1 - l2) / mx : 1.0;
+    part[f] = pen * S[f][g];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double sc = 0.0;
+    for (int f = 0; f < R; ++f) sc += part[f];
+    *out = sc / R;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_match(const RepSet& rs, const MatchArgs& m, hipStream_t s) {
@@ -345,6 +397,12 @@ hipError_t launch_fit_final(const double* G3, const double* C, const double* lam
                             const double* M3, const double* nrm, int64_t K, int R, double* fit,
                             hipStream_t s) {
   fit_final_kernel<<<1, 256, 0, s>>>(G3, C, lam, M3, nrm, K, R, fit);
+  return hipGetLastError();
+}
+
+hipError_t launch_fms(const double* xo, const double* lam1, const double* lam2, int R,
+                      double* out, hipStream_t s) {
+  fms_kernel<<<1, 256, 0, s>>>(xo, lam1, lam2, R, out);
   return hipGetLastError();
 }
 

@@ -344,6 +344,10 @@ hipError_t launch_fit_coo(const int32_t* ii, const int32_t* jj, const float* v,
                           const double* B, double* M3, double* nrm, hipStream_t s);
 // fit = 1 - sqrt(max(0, sum nrm - 2 <X,Xhat> + ||Xhat||^2)) / sqrt(sum nrm)
 // G3: the Gram matrices of A, B, C (3 x R x R)
+// factor match score of two models from their nine cross products
+// (A1^T A2, B1^T B2, C1^T C2, the Grams of model 1, the Grams of model 2)
+hipError_t launch_fms(const double* xo, const double* lam1, const double* lam2, int R,
+                      double* out, hipStream_t s);
 hipError_t launch_fit_final(const double* G3, const double* C, const double* lam,
                             const double* M3, const double* nrm, int64_t K, int R, double* fit,
                             hipStream_t s);

@@ -69,6 +69,7 @@ _SIGS = {
                                      ctypes.POINTER(_i64), ctypes.POINTER(_i32)]),
     "sbt_get_factors": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     "sbt_fit": (ctypes.c_int, [_vp, _pd, _vp]),
+    "sbt_fms": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _pd, _vp]),
     "sbt_get_batch_counter": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_uint32)]),
     "sbt_last_sample": (ctypes.c_int, [_vp, _i32, _i32, _vp, ctypes.POINTER(_i64)]),
     "sbt_last_rep": (ctypes.c_int, [_vp, _i32, _i32, _vp, _i64, ctypes.POINTER(_i64)]),
@@ -259,6 +260,24 @@ class Tensor:
     def fit(self, stream=None):
         f = ctypes.c_double()
         _check(load().sbt_fit(self.h, ctypes.byref(f), _stream(stream)), self.h, "sbt_fit")
+        return f.value
+
+    def fms(self, A, B, C, lam, stream=None):
+        """Factor match score against a reference model (device tensors, or
+        arrays copied to the device first), shapes as get_factors returns."""
+        import torch
+        I, J, K, R = self.shape()
+        dev = []
+        for M, shp in ((A, (I, R)), (B, (J, R)), (C, (K, R)), (lam, (R,))):
+            t = M if isinstance(M, torch.Tensor) else torch.from_numpy(np.asarray(M))
+            t = t.to(device="cuda", dtype=torch.float64).contiguous()
+            if tuple(t.shape) != shp:
+                raise ValueError(f"reference factor of shape {tuple(t.shape)}, expected {shp}")
+            dev.append(t)
+        f = ctypes.c_double()
+        _check(load().sbt_fms(self.h, dev[0].data_ptr(), dev[1].data_ptr(), dev[2].data_ptr(),
+                              dev[3].data_ptr(), ctypes.byref(f), _stream(stream)), self.h,
+               "sbt_fms")
         return f.value
 
     def last_sample(self, rep, mode):

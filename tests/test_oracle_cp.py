@@ -208,3 +208,52 @@ def test_round_bf16_nearest_even():
     # exact halves: 1 + 2^-8 goes down to 1, 1 + 3 * 2^-8 goes up to 1 + 2^-6
     assert cp.round_bf16(np.float32(1.00390625)) == 1.0
     assert cp.round_bf16(np.float32(1.01171875)) == 1.015625
+
+
+def test_fms_weight_penalty():
+    # same unit components, weights differing by a factor: penalty 1 - |l1 - l2| / max
+    g = np.random.default_rng(15)
+    A, _ = cp.normalize_columns(g.random((6, 2)))
+    B, _ = cp.normalize_columns(g.random((5, 2)))
+    C, _ = cp.normalize_columns(g.random((4, 2)))
+    lam = np.array([2.0, 1.0])
+    assert abs(cp.fms(A, B, C, lam, A, B, C, 2 * lam) - 0.5) < 1e-12
+    assert abs(cp.fms(A, B, C, lam, A, B, C, lam * [1.0, 3.0]) - (1.0 + 1.0 / 3.0) / 2) < 1e-12
+    # weights carried by a column norm instead of lambda count the same
+    A3 = A.copy()
+    A3[:, 1] *= 3.0
+    assert abs(cp.fms(A, B, C, lam, A3, B, C, lam) - (1.0 + 1.0 / 3.0) / 2) < 1e-12
+
+
+def test_fms_worked_cosines():
+    # one component: cosines 1/2 (mode 1), -1 (mode 2, sign ignored), 1 (mode 3)
+    t = np.pi / 3
+    A1, A2 = np.array([[1.0], [0.0]]), np.array([[np.cos(t)], [np.sin(t)]])
+    B1, B2 = np.array([[1.0], [2.0]]), np.array([[-1.0], [-2.0]])
+    C1 = C2 = np.array([[3.0]])
+    lam = np.array([1.0])
+    assert abs(cp.fms(A1, B1, C1, lam, A2, B2, C2, lam) - 0.5) < 1e-12
+    # orthogonal components score 0
+    assert abs(cp.fms(A1, B1, C1, lam, np.array([[0.0], [1.0]]), B2, C2, lam)) < 1e-15
+
+
+def test_fms_assignment_against_all_permutations():
+    # the pairing maximises the summed similarity: brute force over R! pairings
+    import itertools
+    g = np.random.default_rng(16)
+    R = 4
+    m1 = [g.random((n, R)) for n in (7, 6, 5)]
+    m2 = [g.random((n, R)) for n in (7, 6, 5)]
+    l1, l2 = g.random(R) + 0.5, g.random(R) + 0.5
+    unit = [[M / np.linalg.norm(M, axis=0) for M in m] for m in (m1, m2)]
+    w1 = l1 * np.prod([np.linalg.norm(M, axis=0) for M in m1], axis=0)
+    w2 = l2 * np.prod([np.linalg.norm(M, axis=0) for M in m2], axis=0)
+    best, best_sim = None, -1.0
+    for perm in itertools.permutations(range(R)):
+        sims = [np.prod([abs(unit[0][n][:, f] @ unit[1][n][:, perm[f]]) for n in range(3)])
+                for f in range(R)]
+        if sum(sims) > best_sim:
+            best_sim = sum(sims)
+            best = sum(s * (1 - abs(w1[f] - w2[perm[f]]) / max(w1[f], w2[perm[f]]))
+                       for f, s in enumerate(sims)) / R
+    assert abs(cp.fms(*m1, l1, *m2, l2) - best) < 1e-12
