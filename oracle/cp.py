@@ -113,11 +113,11 @@ def normalize_columns(U):
     return out, n
 
 
-def als_init_factor(seed, tensor_id, stream, mode, rep, t, rows, R):
+def als_init_factor(seed, tensor_id, stream, mode, rep, t, rows, R, col0=0):
     """U[0,1) initial factor: entry (row, col) from Philox counter
-    (row, col, tag(stream, mode, rep), t)."""
-    rr, cc = np.meshgrid(np.arange(rows, dtype=np.uint64), np.arange(R, dtype=np.uint64),
-                         indexing="ij")
+    (row, col0 + col, tag(stream, mode, rep), t)."""
+    rr, cc = np.meshgrid(np.arange(rows, dtype=np.uint64),
+                         np.arange(col0, col0 + R, dtype=np.uint64), indexing="ij")
     u = rng.bits64(seed, tensor_id, rr, cc, rng.make_tag(stream, mode, rep), t)
     return rng.uniform_closed0(u).reshape(rows, R)
 
@@ -201,3 +201,58 @@ def fms(A1, B1, C1, lam1, A2, B2, C2, lam2):
         pen = 1.0 - abs(lam1[r] - lam2[c]) / max(lam1[r], lam2[c])
         score += pen * cos[r, c]
     return score / R
+
+
+def corcondia(Z, A, B, C, lam):
+    """Core consistency diagnostic (Sec. 3.2; Bro and Kiers) of the model
+    (A, B, C, lam) of the dense tensor Z, in percent.
+
+    The weights go into the third factor.  G = Z x1 pinv(A) x2 pinv(B)
+    x3 pinv(C diag(lam)) is the least-squares Tucker core for the model's
+    factors; the core of a perfect trilinear fit is superdiagonal with ones
+    (T), and CC = 100 (1 - ||G - T||^2 / R).
+    """
+    Z = np.asarray(Z, dtype=np.float64)
+    R = A.shape[1]
+    Pa = np.linalg.pinv(A)
+    Pb = np.linalg.pinv(B)
+    Pc = np.linalg.pinv(C * np.asarray(lam)[None, :])
+    G = np.einsum("ai,bj,ck,ijk->abc", Pa, Pb, Pc, Z, optimize=True)
+    T = np.zeros((R, R, R))
+    T[np.arange(R), np.arange(R), np.arange(R)] = 1.0
+    return 100.0 * (1.0 - float(np.sum((G - T) ** 2)) / R)
+
+
+def get_rank(Z, R, runs, threshold, iters, init):
+    """GetRank (Sec. 3.2, Alg. 2) on the dense summary Z.
+
+    Every candidate rank i = 1..R gets `runs` CP-ALS runs (fixed `iters`
+    sweeps) from the initial factors init(i, q) -> (B0, C0), q the run's
+    index (i - 1) * runs + j; each run is scored by its core consistency.
+    A core consistency of 100 is reached by every rank-1 model, so taking
+    the single highest score would always return 1; the rank returned is
+    the largest i whose best run reaches `threshold` (rank 1 always counts).
+    Returns (R_new, (A, B, C), lam, cc) with the factors of the best run at
+    R_new (the first of equal scores) and cc[i - 1][j] the scores.
+    """
+    dims = Z.shape
+
+    def mtt(F, mode):
+        return mttkrp_dense(Z, F, mode)
+
+    cc = []
+    best = None
+    for i in range(1, R + 1):
+        row = []
+        top = None  # (score, factors, lam) of the best run at rank i
+        for j in range(runs):
+            B0, C0 = init(i, (i - 1) * runs + j)
+            (A, B, C), lam, _ = cp_als(mtt, dims, i, iters, B0, C0)
+            score = corcondia(Z, A, B, C, lam)
+            row.append(score)
+            if top is None or score > top[0]:
+                top = (score, (A, B, C), lam)
+        cc.append(row)
+        if i == 1 or top[0] >= threshold:
+            best = (i, top[1], top[2])
+    return best[0], best[1], best[2], cc

@@ -34,6 +34,7 @@ PHILOX_W1 = np.uint64(0xBB67AE85)
 TAG_SAMPLE = 1
 TAG_ALSINIT = 2
 TAG_INIT = 3
+TAG_GETRANK = 4
 
 
 def philox4x32_10(c0, c1, c2, c3, k0, k1):

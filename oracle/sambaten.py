@@ -32,6 +32,13 @@ listed, with reasons, in the design notes of the repository):
 * Zero entries of A, B and the anchor rows of C are replaced by the mean over
   the valid covering repetitions, after all repetitions (order free).
 * lambda is kept unchanged by default.
+* GetRank (Sec. 3.2, optional): per summary, R_new = the largest candidate
+  rank whose best CP run reaches the core-consistency threshold (see
+  cp.get_rank); the summary's factors are that run's.  The R_new sample
+  components are matched to R_new of the R current ones (maximum-weight
+  assignment); a current component left without a partner contributes
+  nothing from that repetition (its new rows are averaged over the
+  repetitions that matched it, zero if none did).
 """
 
 import math
@@ -122,7 +129,8 @@ def sample_size(N, s):
 def match(A_anchor, B_anchor, C_anchor, Ap, Bp, Cp_anchor):
     """Returns (pi, sigA, sigB, nA, nB, S, cosA, cosB).
 
-    pi[f] is the sample column matched to current column f.
+    pi[f] is the sample column matched to current column f, -1 when the
+    sample has fewer columns than the model and f is left over.
     """
     Ah, nA = cp.normalize_columns(A_anchor)
     Bh, nB = cp.normalize_columns(B_anchor)
@@ -135,11 +143,11 @@ def match(A_anchor, B_anchor, C_anchor, Ap, Bp, Cp_anchor):
     cosC = Ch.T @ Cpn
     S = np.abs(cosA) * np.abs(cosB) * np.abs(cosC)
     rows, cols = linear_sum_assignment(S, maximize=True)
-    pi = np.empty(S.shape[0], dtype=np.int64)
+    pi = np.full(S.shape[0], -1, dtype=np.int64)  # -1: no sample column left (R_new < R)
     pi[rows] = cols
     R = S.shape[0]
-    sA = np.array([cosA[f, pi[f]] for f in range(R)])
-    sB = np.array([cosB[f, pi[f]] for f in range(R)])
+    sA = np.array([cosA[f, pi[f]] if pi[f] >= 0 else 1.0 for f in range(R)])
+    sB = np.array([cosB[f, pi[f]] if pi[f] >= 0 else 1.0 for f in range(R)])
     sigA = np.where(sA < 0, -1.0, 1.0)
     sigB = np.where(sB < 0, -1.0, 1.0)
     return pi, sigA, sigB, nA, nB, S, cosA, cosB
@@ -151,7 +159,8 @@ def match(A_anchor, B_anchor, C_anchor, Ap, Bp, Cp_anchor):
 
 class Config:
     def __init__(self, rank, reps, als_iters, sample_factor, seed, tensor_id=0,
-                 init_iters=100, k_capacity=None, nnz_capacity=None, summary_bf16=False):
+                 init_iters=100, k_capacity=None, nnz_capacity=None, summary_bf16=False,
+                 getrank_runs=0, getrank_threshold=90.0):
         self.rank = int(rank)
         self.reps = int(reps)
         self.als_iters = int(als_iters)
@@ -165,6 +174,9 @@ class Config:
         # dense summaries stored as bfloat16 (rounded to nearest even) before
         # the decomposition and the row solve; everything else stays FP64
         self.summary_bf16 = bool(summary_bf16)
+        # GetRank (Sec. 3.2, Alg. 2) on every summary when getrank_runs > 0
+        self.getrank_runs = int(getrank_runs)
+        self.getrank_threshold = float(getrank_threshold)
 
 
 class NumericError(ValueError):
@@ -285,23 +297,47 @@ class OracleTensor:
 
                 def mtt(F, mode, Zidx=Zidx, Zval=Zval, dims_s=dims_s):
                     return cp.mttkrp_coo(Zidx, Zval, F, mode, dims_s)
-            # Decompose (Sec. 3.1), B' and C' drawn U[0,1), A' computed first.
-            B0 = cp.als_init_factor(cfg.seed, cfg.tensor_id, rng.TAG_ALSINIT, 2, rho, self.t,
-                                    dims_s[1], R)
-            C0 = cp.als_init_factor(cfg.seed, cfg.tensor_id, rng.TAG_ALSINIT, 3, rho, self.t,
-                                    dims_s[2], R)
-            (Ap, Bp, Cp), lamp, npinv = cp.cp_als(mtt, dims_s, R, cfg.als_iters, B0, C0)
-            # Normalise + match (Sec. 3.1 "Project back", Lemma 1).
+            Rn, cc = R, None
+            if cfg.getrank_runs > 0:
+                # GetRank (Sec. 3.2) before the decomposition: the summary's
+                # rank R_new <= R and the best of its CP runs at that rank
+                if self.fmt != DENSE:
+                    raise NotImplementedError("GetRank runs on dense summaries")
+
+                def init(i, q, rho=rho, dims_s=dims_s):
+                    return tuple(cp.als_init_factor(cfg.seed, cfg.tensor_id, rng.TAG_GETRANK,
+                                                    m, rho, self.t, dims_s[m - 1], i,
+                                                    col0=32 * q) for m in (2, 3))
+                Rn, (Ap, Bp, Cp), lamp, cc = cp.get_rank(Z, R, cfg.getrank_runs,
+                                                         cfg.getrank_threshold, cfg.als_iters,
+                                                         init)
+                npinv = 0
+            else:
+                # Decompose (Sec. 3.1), B' and C' drawn U[0,1), A' computed first.
+                B0 = cp.als_init_factor(cfg.seed, cfg.tensor_id, rng.TAG_ALSINIT, 2, rho, self.t,
+                                        dims_s[1], R)
+                C0 = cp.als_init_factor(cfg.seed, cfg.tensor_id, rng.TAG_ALSINIT, 3, rho, self.t,
+                                        dims_s[2], R)
+                (Ap, Bp, Cp), lamp, npinv = cp.cp_als(mtt, dims_s, R, cfg.als_iters, B0, C0)
+            # Normalise + match (Sec. 3.1 "Project back", Lemma 1); with
+            # R_new < R only R_new of the current components find a partner.
             n3 = len(Ks)
             pi, sigA, sigB, nA, nB, S, cosA, cosB = match(
                 self.A[Is], self.B[Js], self.C[Ks], Ap, Bp, Cp[:n3])
-            valid = (nA > 0) & (nB > 0)
+            matched = pi >= 0
+            valid = (nA > 0) & (nB > 0) & matched
             Apn, _ = cp.normalize_columns(Ap)
             Bpn, _ = cp.normalize_columns(Bp)
-            At = Apn[:, pi] * (sigA * nA)[None, :]
-            Bt = Bpn[:, pi] * (sigB * nB)[None, :]
-            # Row least squares for every third-mode row of the summary.
+            At = np.zeros((len(Is), R))
+            Bt = np.zeros((len(Js), R))
+            At[:, matched] = Apn[:, pi[matched]] * (sigA * nA)[None, matched]
+            Bt[:, matched] = Bpn[:, pi[matched]] * (sigB * nB)[None, matched]
+            # Row least squares for every third-mode row of the summary; an
+            # unmatched component gets a unit diagonal (its rows come out zero).
             G = (At.T @ At) * (Bt.T @ Bt)
+            G[~matched, :] = 0.0
+            G[:, ~matched] = 0.0
+            G[~matched, ~matched] = 1.0
             Dm = mtt([At, Bt, None], 2)
             D, _ = cp.solve_normal(Dm, G)
             Ct = np.zeros_like(D)
@@ -309,7 +345,7 @@ class OracleTensor:
             Ct[:, lz] = D[:, lz] / self.lam[lz]
             reps.append(dict(Is=Is, Js=Js, Ks=Ks, Ap=Ap, Bp=Bp, Cp=Cp, lamp=lamp, pi=pi,
                              sigA=sigA, sigB=sigB, nA=nA, nB=nB, S=S, valid=valid, At=At,
-                             Bt=Bt, Ct=Ct, Dm=Dm, npinv=npinv))
+                             Bt=Bt, Ct=Ct, Dm=Dm, npinv=npinv, Rnew=Rn, cc=cc))
 
         A_new, B_new, C_old = self.A.copy(), self.B.copy(), self.C.copy()
         # Zero-entry update over the sampled rows (Algorithm 1), order free.
