@@ -81,6 +81,17 @@ typedef struct {
   int64_t k_capacity;        /* largest third-mode size the tensor may reach */
   int64_t max_batch;         /* largest K_new of one update */
   int64_t nnz_capacity;      /* COO only: largest number of stored nonzeros */
+  /* GetRank (Sec. 3.2, Alg. 2), dense FP64/FP32 tensors only.  With
+   * getrank_runs > 0 every summary is decomposed at each candidate rank
+   * i = 1..R, getrank_runs times (CP-ALS, als_iters sweeps, own initial
+   * factors per run), each run is scored by its core consistency (percent),
+   * and the summary's rank R_new is the largest i whose best run reaches
+   * getrank_threshold (rank 1 always counts); that run's factors are the
+   * summary's decomposition, and only R_new of the R current components are
+   * matched to it.  0 turns GetRank off. */
+  int32_t getrank_runs;
+  int32_t reserved;          /* must be 0 */
+  double getrank_threshold;  /* core consistency a candidate rank must reach */
 } sbt_config;
 
 /* --------------------------------------------------------------------------
@@ -178,11 +189,16 @@ typedef enum {
   SBT_REP_BP = 1,     /* summary factor B' (n2 x R)                        */
   SBT_REP_CP = 2,     /* summary factor C' (K' x R)                        */
   SBT_REP_LAMP = 3,   /* summary weights lambda' (R)                       */
-  SBT_REP_PI = 4,     /* matching: sample column matched to column f (R)   */
+  SBT_REP_PI = 4,     /* matching: sample column matched to column f (R);
+                         R_new or more: no partner (GetRank)               */
   SBT_REP_VALID = 5,  /* 1 where the repetition is valid for column f (R)  */
   SBT_REP_AT = 6,     /* matched, rescaled A rows (n1 x R)                 */
   SBT_REP_BT = 7,     /* matched, rescaled B rows (n2 x R)                 */
-  SBT_REP_CT = 8      /* least-squares C rows of the summary (K' x R)      */
+  SBT_REP_CT = 8,     /* least-squares C rows of the summary (K' x R)      */
+  SBT_REP_RNEW = 9,   /* rank of the summary's decomposition (1 value; R
+                         without GetRank)                                   */
+  SBT_REP_CC = 10     /* GetRank: core consistency of run j at rank i, row
+                         i - 1, column j (R x getrank_runs)                 */
 } sbt_rep_item;
 
 /* Copy one per-repetition intermediate of the last update as doubles into

@@ -48,7 +48,7 @@ __host__ __device__ inline Philox4 philox4x32_10(uint32_t c0, uint32_t c1, uint3
 
 // Streams of random numbers the update draws; packed into counter word 2 as
 // stream << 24 | mode << 20 | repetition.
-enum : uint32_t { kStreamSample = 1, kStreamAlsInit = 2, kStreamInit = 3 };
+enum : uint32_t { kStreamSample = 1, kStreamAlsInit = 2, kStreamInit = 3, kStreamGetRank = 4 };
 
 __host__ __device__ inline uint32_t rng_tag(uint32_t stream, uint32_t mode, uint32_t rep) {
   return (stream << 24) | ((mode & 0xFu) << 20) | (rep & 0xFFFFFu);

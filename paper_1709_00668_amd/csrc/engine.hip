@@ -79,6 +79,11 @@ struct sbt_tensor {
   double *xpart = nullptr, *xout = nullptr, *scl = nullptr;
   int xnblk = 1;
   int64_t xpart_mats = 0;  // R x R matrices the partial buffer holds
+  // GetRank: kept factors (rows padded to R), scores, chosen ranks, cores
+  double *gAk = nullptr, *gBk = nullptr, *gCk = nullptr, *glamk = nullptr;
+  double *gcc = nullptr, *gbest = nullptr, *gtab = nullptr, *gP = nullptr, *gX1 = nullptr,
+         *gX2 = nullptr, *gGi = nullptr;
+  int32_t* grnew = nullptr;
   std::vector<void*> grow_allocs; // freed when regrown or destroyed
   int64_t last_summary_nnz = 0;
   // kernel timing (sbt_profile_*)
@@ -214,7 +219,15 @@ sbt_status validate_config(const sbt_config* c, std::string& why) {
   if (c->format != SBT_DENSE && c->format != SBT_COO) { why = "bad format"; return SBT_E_INVALID; }
   if (c->precision < SBT_P_F64 || c->precision > SBT_P_BF16) { why = "bad precision"; return SBT_E_INVALID; }
   if (c->schedule != SBT_SCHED_BATCHED && c->schedule != SBT_SCHED_PLAIN) { why = "bad schedule"; return SBT_E_INVALID; }
-  if (c->flags != 0) { why = "flags must be 0"; return SBT_E_INVALID; }
+  if (c->flags != 0 || c->reserved != 0) { why = "flags must be 0"; return SBT_E_INVALID; }
+  if (c->getrank_runs < 0 || c->getrank_runs > 64) { why = "getrank_runs must be in 0..64"; return SBT_E_INVALID; }
+  if (c->getrank_runs > 0) {
+    if (c->format != SBT_DENSE || c->precision == SBT_P_BF16) {
+      why = "GetRank needs a dense FP64 or FP32 tensor";
+      return SBT_E_INVALID;
+    }
+    if (!(c->getrank_threshold == c->getrank_threshold)) { why = "bad GetRank threshold"; return SBT_E_INVALID; }
+  }
   if (c->max_batch < 1) { why = "max_batch must be >= 1"; return SBT_E_INVALID; }
   return SBT_OK;
 }
@@ -321,6 +334,21 @@ sbt_status alloc_state(sbt_tensor* t) {
     t->xpart_mats = np;
     SBT_TRY(dalloc(t, &t->xout, (size_t)r * 9 * R * R));
     SBT_TRY(dalloc(t, &t->scl, (size_t)r * 2 * R));
+  }
+  if (c.getrank_runs > 0) {
+    const size_t R3 = (size_t)R * R * R;
+    SBT_TRY(dalloc(t, &t->gAk, (size_t)r * rs.sA));
+    SBT_TRY(dalloc(t, &t->gBk, (size_t)r * rs.sB));
+    SBT_TRY(dalloc(t, &t->gCk, (size_t)r * rs.sC));
+    SBT_TRY(dalloc(t, &t->glamk, (size_t)r * R));
+    SBT_TRY(dalloc(t, &t->gcc, (size_t)r));
+    SBT_TRY(dalloc(t, &t->gbest, (size_t)r));
+    SBT_TRY(dalloc(t, &t->gtab, (size_t)r * R * c.getrank_runs));
+    SBT_TRY(dalloc(t, &t->gP, (size_t)r * R3));
+    SBT_TRY(dalloc(t, &t->gX1, (size_t)r * R3));
+    SBT_TRY(dalloc(t, &t->gX2, (size_t)r * R3));
+    SBT_TRY(dalloc(t, &t->gGi, (size_t)3 * r * rs.sG));
+    SBT_TRY(dalloc(t, &t->grnew, (size_t)r));
   }
   SBT_TRY(dalloc(t, &t->M3, (size_t)t->Kcap * R));
   SBT_TRY(dalloc(t, &t->nrm, (size_t)t->Kcap));
@@ -509,7 +537,8 @@ sbt_status gram_rows(sbt_tensor* t, const RepSet& rs, const double* U, int64_t s
     return SBT_E_SHAPE;
   }
   xp.part = t->xpart;
-  xp.out = G;  // [rep][1][R*R]: stride R*R = sG
+  xp.out = G;  // [rep][1][rs.R^2] at stride sG (also below the full rank)
+  xp.sOut = rs.sG;
   SBT_CK(launch_xprod(xp, st));
   return SBT_OK;
 }
@@ -615,9 +644,9 @@ sbt_status set_scale(sbt_tensor* t, hipStream_t st) {
 sbt_status run_als(sbt_tensor* t, const void* Zp, RepSet rs, double* Ap, double* Bp, double* Cp,
                    double* GA, double* GB, double* GC, double* lam_out, void* W, double* M,
                    double* Vinv, double* invlam, uint32_t stream, uint32_t t_ctr, int iters,
-                   bool plain, hipStream_t st) {
+                   bool plain, hipStream_t st, uint32_t col0 = 0) {
   const int prec = t->sum_prec;
-  SBT_CK(launch_als_init(rs, t->cfg.seed, t->cfg.tensor_id, stream, t_ctr, Bp, Cp, st));
+  SBT_CK(launch_als_init(rs, t->cfg.seed, t->cfg.tensor_id, stream, t_ctr, Bp, Cp, st, col0));
   SBT_TRY(gram_rows(t, rs, Bp, rs.sB, rs.n2, GB, st));
   SBT_TRY(gram_rows(t, rs, Cp, rs.sC, rs.n3, GC, st));
   const double zb = (double)rs.nrep * rs.n1 * rs.n2 * rs.n3 * prec_bytes(prec);
@@ -805,6 +834,53 @@ sbt_status check_factor_args(const double* A0, const double* B0, const double* C
 }
 
 // The update after the batch is in the store and its importance is in dw*.
+// GetRank (Sec. 3.2) on the dense summaries of rs: every candidate rank
+// i = 1..R gets getrank_runs CP-ALS runs (initial factors from the GetRank
+// stream, run q = (i - 1) runs + j at columns 32 q of the counter), each
+// scored by its core consistency; the kept run per repetition ends in Ap, Bp,
+// Cp, lamp (rows padded to R columns) and its rank in grnew.
+sbt_status getrank_search(sbt_tensor* t, const RepSet& rs, bool plain, hipStream_t st) {
+  const sbt_config& c = t->cfg;
+  const int R = t->R, runs = c.getrank_runs;
+  const int64_t R3 = (int64_t)R * R * R;
+  const int64_t sGi = (int64_t)c.repetitions * rs.sG;
+  for (int i = 1; i <= R; ++i) {
+    RepSet ri = rs;
+    ri.R = i;  // strides stay those of rank R
+    SBT_CK(launch_fill_f64(t->gbest + rs.rep0, rs.nrep, -1.0e308, st));
+    for (int j = 0; j < runs; ++j) {
+      const uint32_t q = (uint32_t)((i - 1) * runs + j);
+      SBT_TRY(run_als(t, t->Z, ri, t->Ap, t->Bp, t->Cp, t->GA, t->GB, t->GC, t->lamp, t->W, t->M,
+                      t->Vinv, t->invlam, kStreamGetRank, t->t, c.als_iters, plain, st,
+                      32u * q));
+      // Grams of the unit-column factors and their inverses
+      SBT_TRY(gram_rows(t, ri, t->Ap, ri.sA, ri.n1, t->GA, st));
+      SBT_TRY(gram_rows(t, ri, t->Bp, ri.sB, ri.n2, t->GB, st));
+      SBT_TRY(gram_rows(t, ri, t->Cp, ri.sC, ri.n3, t->GC, st));
+      SBT_CK(launch_inverse(ri, t->GA, ri.sG, t->ones, 0, t->gGi, t->pinv, st));
+      SBT_CK(launch_inverse(ri, t->GB, ri.sG, t->ones, 0, t->gGi + sGi, t->pinv, st));
+      SBT_CK(launch_inverse(ri, t->GC, ri.sG, t->ones, 0, t->gGi + 2 * sGi, t->pinv, st));
+      // W = Z x3 C^T, the projected core, the core consistency
+      SBT_CK(launch_p1(t->sum_prec, ri, t->Z, t->Cp, t->W, st));
+      SBT_CK(launch_core(t->sum_prec, ri, t->W, t->Ap, t->Bp, t->gP, R3, st));
+      SBT_CK(launch_corcondia(ri, t->gP, t->gX1, t->gX2, R3, t->gGi, sGi, t->lamp, t->gcc, st));
+      SBT_CK(launch_rank_select(ri, R, runs, j, i == 1 && j == 0, c.getrank_threshold, t->gcc,
+                                t->gbest, t->gtab, t->grnew, t->Ap, t->Bp, t->Cp, t->lamp,
+                                t->gAk, t->gBk, t->gCk, t->glamk, st));
+    }
+  }
+  const size_t d = sizeof(double);
+  SBT_CK(hipMemcpyAsync(t->Ap + rs.rep0 * rs.sA, t->gAk + rs.rep0 * rs.sA, d * rs.nrep * rs.sA,
+                        hipMemcpyDeviceToDevice, st));
+  SBT_CK(hipMemcpyAsync(t->Bp + rs.rep0 * rs.sB, t->gBk + rs.rep0 * rs.sB, d * rs.nrep * rs.sB,
+                        hipMemcpyDeviceToDevice, st));
+  SBT_CK(hipMemcpyAsync(t->Cp + rs.rep0 * rs.sC, t->gCk + rs.rep0 * rs.sC, d * rs.nrep * rs.sC,
+                        hipMemcpyDeviceToDevice, st));
+  SBT_CK(hipMemcpyAsync(t->lamp + (int64_t)rs.rep0 * R, t->glamk + (int64_t)rs.rep0 * R,
+                        d * rs.nrep * R, hipMemcpyDeviceToDevice, st));
+  return SBT_OK;
+}
+
 sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
   const sbt_config& c = t->cfg;
   const int R = t->R, r = c.repetitions;
@@ -861,6 +937,8 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
     RepSet rs = (plain && !coo) ? make_repset(t, Kp, q, 1) : all;
     if (coo) {
       SBT_TRY(run_als_coo(t, rs, t->t, st));
+    } else if (c.getrank_runs > 0) {
+      SBT_TRY(getrank_search(t, rs, plain, st));
     } else {
       SBT_TRY(run_als(t, t->Z, rs, t->Ap, t->Bp, t->Cp, t->GA, t->GB, t->GC, t->lamp, t->W,
                       t->M, t->Vinv, t->invlam, kStreamAlsInit, t->t, c.als_iters, plain, st));
@@ -884,6 +962,7 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
     ma.valid = t->valid;
     ma.xo = t->xout;
     ma.scl = t->scl;
+    ma.rnew = c.getrank_runs > 0 ? t->grnew : nullptr;
     {
       // anchor and sample cross products over the sampled rows
       const int32_t* Is = t->idx;
@@ -1383,6 +1462,23 @@ sbt_status sbt_last_rep(const sbt_tensor* tc, int32_t rep, int32_t item, double*
     case SBT_REP_AT: src = t->At + rep * rs.sA; nr = t->n1; break;
     case SBT_REP_BT: src = t->Bt + rep * rs.sB; nr = t->n2; break;
     case SBT_REP_CT: src = t->Ct + rep * rs.sC; nr = t->last_Kp; break;
+    case SBT_REP_RNEW:
+      if (cap < 1) return SBT_E_INVALID;
+      if (t->grnew) {
+        int32_t v = 0;
+        SBT_CK(hipMemcpy(&v, t->grnew + rep, sizeof(int32_t), hipMemcpyDeviceToHost));
+        out[0] = (double)v;
+      } else {
+        out[0] = (double)R;
+      }
+      *rows = 1;
+      return SBT_OK;
+    case SBT_REP_CC:
+      if (!t->gtab) return SBT_E_STATE;
+      src = t->gtab + (int64_t)rep * R * t->cfg.getrank_runs;
+      nr = R;
+      ncol = t->cfg.getrank_runs;
+      break;
     default: return SBT_E_INVALID;
   }
   if (cap < nr * ncol) return SBT_E_INVALID;

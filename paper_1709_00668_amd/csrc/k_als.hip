@@ -72,7 +72,7 @@ __global__ __launch_bounds__(256) void gather_dense_kernel(const TIn* X, int64_t
 // Random initial factors B', C' ~ U[0,1)
 // ---------------------------------------------------------------------------
 __global__ void als_init_kernel(RepSet rs, uint64_t seed, uint32_t tensor_id, uint32_t stream,
-                                uint32_t t, double* Bp, double* Cp) {
+                                uint32_t t, uint32_t col0, double* Bp, double* Cp) {
   const int rep = rs.rep0 + blockIdx.y;
   const RngKey key = rng_key(seed, tensor_id);
   const int64_t nb = (int64_t)rs.n2 * rs.R, nc = (int64_t)rs.n3 * rs.R;
@@ -82,7 +82,7 @@ __global__ void als_init_kernel(RepSet rs, uint64_t seed, uint32_t tensor_id, ui
     const int64_t qq = isB ? q : q - nb;
     const uint32_t row = (uint32_t)(qq / rs.R), col = (uint32_t)(qq % rs.R);
     const uint32_t tag = rng_tag(stream, isB ? 2u : 3u, (uint32_t)rep);
-    const double u = uniform_closed0(rng_bits(key, row, col, tag, t));
+    const double u = uniform_closed0(rng_bits(key, row, col0 + col, tag, t));
     if (isB)
       Bp[rep * rs.sB + qq] = u;
     else
@@ -355,12 +355,13 @@ hipError_t launch_gather_dense(int store_prec, int sum_prec, const void* X, int6
 }
 
 hipError_t launch_als_init(const RepSet& rs, uint64_t seed, uint32_t tensor_id, uint32_t stream,
-                           uint32_t t, double* Bp, double* Cp, hipStream_t s) {
+                           uint32_t t, double* Bp, double* Cp, hipStream_t s, uint32_t col0) {
   const int64_t n = (int64_t)(rs.n2 + rs.n3) * rs.R;
   int blocks = (int)((n + 255) / 256);
   if (blocks > 1024) blocks = 1024;
   als_init_kernel<<<dim3((unsigned)blocks, (unsigned)rs.nrep), 256, 0, s>>>(rs, seed, tensor_id,
-                                                                          stream, t, Bp, Cp);
+                                                                          stream, t, col0, Bp,
+                                                                          Cp);
   return hipGetLastError();
 }
 

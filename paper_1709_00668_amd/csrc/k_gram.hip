@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void xprod_reduce_kernel(XProd xp) {
   red[w][lane] = s;
   __syncthreads();
   if (w == 0 && p < RR) {
-    double* out = xp.out + ((int64_t)rep * xp.njobs + j) * RR;
+    double* out = xp.out + ((int64_t)rep * xp.njobs + j) * (xp.sOut > 0 ? xp.sOut : RR);
     out[p] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
   }
 }

@@ -99,6 +99,7 @@ __global__ __launch_bounds__(256) void match_kernel(RepSet rs, MatchArgs m) {
   const int R = rs.R, RR = R * R;
   const int tid = threadIdx.x;
   const double* xo = m.xo + (int64_t)rep * 9 * RR;
+  const int Rn = m.rnew ? m.rnew[rep] : R;
   __shared__ double S[kMaxRank][kMaxRank + 1];
   __shared__ double nrm[6][kMaxRank];  // A anchor, B anchor, C anchor, A', B', C'(anchor rows)
   __shared__ int pi_s[kMaxRank];
@@ -118,7 +119,9 @@ __global__ __launch_bounds__(256) void match_kernel(RepSet rs, MatchArgs m) {
     const double cB = dB > 0.0 ? xo[1 * RR + q] / dB : 0.0;
     const double cC = dC > 0.0 ? xo[2 * RR + q] / dC : 0.0;
     const double sv = fabs(cA) * fabs(cB) * fabs(cC);
-    S[f][g] = sv >= 0.0 ? sv : 0.0;  // a non-finite similarity counts as none
+    // a non-finite similarity counts as none; so do the sample columns past
+    // the summary's rank (GetRank), which leaves R - R_new components unmatched
+    S[f][g] = (sv >= 0.0 && g < Rn) ? sv : 0.0;
   }
   __syncthreads();
   if (tid < R) pi_s[tid] = tid;
@@ -130,19 +133,21 @@ __global__ __launch_bounds__(256) void match_kernel(RepSet rs, MatchArgs m) {
     const double sa = xo[0 * RR + f * R + g] < 0.0 ? -1.0 : 1.0;
     const double sb = xo[1 * RR + f * R + g] < 0.0 ? -1.0 : 1.0;
     // At(:, f) = sigA nA(f) A'(:, g) / ||A'(:, g)||, likewise Bt
-    sA[f] = nrm[3][g] > 0.0 ? sa * nrm[0][f] / nrm[3][g] : 0.0;
-    sB[f] = nrm[4][g] > 0.0 ? sb * nrm[1][f] / nrm[4][g] : 0.0;
+    sA[f] = (g < Rn && nrm[3][g] > 0.0) ? sa * nrm[0][f] / nrm[3][g] : 0.0;
+    sB[f] = (g < Rn && nrm[4][g] > 0.0) ? sb * nrm[1][f] / nrm[4][g] : 0.0;
     m.scl[(int64_t)rep * 2 * R + f] = sA[f];
     m.scl[(int64_t)rep * 2 * R + R + f] = sB[f];
     m.pi[rep * R + f] = g;
-    m.valid[rep * R + f] = (nrm[0][f] > 0.0 && nrm[1][f] > 0.0) ? 1 : 0;
+    m.valid[rep * R + f] = (nrm[0][f] > 0.0 && nrm[1][f] > 0.0 && g < Rn) ? 1 : 0;
   }
   __syncthreads();
   for (int q = tid; q < RR; q += 256) {
     const int f = q / R, g = q % R, pf = pi_s[f], pg = pi_s[g];
     const double ga = sA[f] * sA[g] * xo[6 * RR + pf * R + pg];
     const double gb = sB[f] * sB[g] * xo[7 * RR + pf * R + pg];
-    m.Gt[rep * rs.sG + q] = ga * gb;
+    // an unmatched component gets a unit diagonal: its rows come out zero
+    const bool un = pf >= Rn || pg >= Rn;
+    m.Gt[rep * rs.sG + q] = un ? (f == g ? 1.0 : 0.0) : ga * gb;
   }
 }
 

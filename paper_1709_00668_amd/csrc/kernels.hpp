@@ -115,9 +115,9 @@ hipError_t launch_mode3_finish(const RepSet& rs, int nsplit, const float* P, int
                                hipStream_t s);
 
 // ---- CP-ALS on the summaries --------------------------------------------
-// B', C' <- U[0,1) from Philox counters (row, col, tag(stream, mode, rep), t)
+// B', C' <- U[0,1) from Philox counters (row, col0 + col, tag(stream, mode, rep), t)
 hipError_t launch_als_init(const RepSet& rs, uint64_t seed, uint32_t tensor_id, uint32_t stream,
-                           uint32_t t, double* Bp, double* Cp, hipStream_t s);
+                           uint32_t t, double* Bp, double* Cp, hipStream_t s, uint32_t col0 = 0);
 // G = U^T U for rows x R factors of each repetition
 hipError_t launch_gram(const RepSet& rs, const double* U, int64_t sU, int rows, double* G,
                        hipStream_t s);
@@ -201,7 +201,8 @@ struct XProd {
   int njobs, R, rep0, nrep;
   int nblk;       // chunks the partial buffer holds per (rep, job)
   double* part;   // [rep][job][nblk][R * R]
-  double* out;    // [rep][job][R * R]
+  double* out;    // [rep][job][R * R], or with sOut > 0 at (rep * njobs + job) * sOut
+  int64_t sOut;
 };
 // chunks needed for `max_rows` rows
 int xprod_blocks(int max_rows);
@@ -223,6 +224,7 @@ struct MatchArgs {
   double *At, *Bt;              // matched, rescaled
   double* Gt;                   // (At^T At) .* (Bt^T Bt)
   int32_t *pi, *valid;
+  const int32_t* rnew;          // per repetition rank of the summary factors, or null (R)
 };
 hipError_t launch_match(const RepSet& rs, const MatchArgs& m, hipStream_t s);
 
@@ -344,6 +346,23 @@ hipError_t launch_fit_coo(const int32_t* ii, const int32_t* jj, const float* v,
                           const double* B, double* M3, double* nrm, hipStream_t s);
 // fit = 1 - sqrt(max(0, sum nrm - 2 <X,Xhat> + ||Xhat||^2)) / sqrt(sum nrm)
 // G3: the Gram matrices of A, B, C (3 x R x R)
+// ---- GetRank (Sec. 3.2) --------------------------------------------------------
+// projected core P = Z x1 A^T x2 B^T x3 C^T of every repetition (rank rs.R)
+// from W = Z x3 C^T in the [f][e] layout of launch_p1; P is [rep][a][b][c]
+hipError_t launch_core(int prec, const RepSet& rs, const void* W, const double* Ap,
+                       const double* Bp, double* P, int64_t sP, hipStream_t s);
+// core consistency (percent) of every repetition from P, the inverse Grams
+// (GA^-1, GB^-1, GC^-1 at Gi, Gi + sGi, Gi + 2 sGi) and the run's lambda
+hipError_t launch_corcondia(const RepSet& rs, const double* P, double* X1, double* X2, int64_t sP,
+                            const double* Gi, int64_t sGi, const double* lam, double* cc,
+                            hipStream_t s);
+// keep run j at rank rs.R where it is the best at that rank and the rank
+// counts; kept factors padded to Rf columns, rnew = rs.R
+hipError_t launch_rank_select(const RepSet& rs, int Rf, int runs, int j, bool force, double tau,
+                              const double* cc, double* bestcc, double* cctab, int32_t* rnew,
+                              const double* Ap, const double* Bp, const double* Cp,
+                              const double* lamp, double* Ak, double* Bk, double* Ck,
+                              double* lamk, hipStream_t s);
 // factor match score of two models from their nine cross products
 // (A1^T A2, B1^T B2, C1^T C2, the Grams of model 1, the Grams of model 2)
 hipError_t launch_fms(const double* xo, const double* lam1, const double* lam2, int R,

@@ -23,7 +23,7 @@ SBT_SCHED_BATCHED, SBT_SCHED_PLAIN = 0, 1
 (SBT_K_MTTKRP_C, SBT_K_MTTKRP_AB, SBT_K_GATHER, SBT_K_UPDATE, SBT_K_COO_MTTKRP,
  SBT_K_ROW_SOLVE) = range(6)
 (SBT_REP_AP, SBT_REP_BP, SBT_REP_CP, SBT_REP_LAMP, SBT_REP_PI, SBT_REP_VALID, SBT_REP_AT,
- SBT_REP_BT, SBT_REP_CT) = range(9)
+ SBT_REP_BT, SBT_REP_CT, SBT_REP_RNEW, SBT_REP_CC) = range(11)
 
 
 class sbt_config(ctypes.Structure):
@@ -42,6 +42,9 @@ class sbt_config(ctypes.Structure):
         ("k_capacity", ctypes.c_int64),
         ("max_batch", ctypes.c_int64),
         ("nnz_capacity", ctypes.c_int64),
+        ("getrank_runs", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("getrank_threshold", ctypes.c_double),
     ]
 
 
@@ -143,7 +146,8 @@ def _stream(stream):
 
 def make_config(rank, repetitions, als_iters, sample_factor, seed, *, init_iters=100,
                 fmt=SBT_DENSE, precision=SBT_P_F32, schedule=SBT_SCHED_BATCHED, tensor_id=0,
-                k_capacity, max_batch, nnz_capacity=0):
+                k_capacity, max_batch, nnz_capacity=0, getrank_runs=0,
+                getrank_threshold=90.0):
     c = sbt_config()
     c.rank, c.repetitions, c.als_iters, c.init_iters = rank, repetitions, als_iters, init_iters
     s = (sample_factor,) * 3 if np.isscalar(sample_factor) else tuple(sample_factor)
@@ -152,6 +156,7 @@ def make_config(rank, repetitions, als_iters, sample_factor, seed, *, init_iters
     c.format, c.precision, c.schedule = fmt, precision, schedule
     c.seed, c.tensor_id, c.flags = seed, tensor_id, 0
     c.k_capacity, c.max_batch, c.nnz_capacity = k_capacity, max_batch, nnz_capacity
+    c.getrank_runs, c.reserved, c.getrank_threshold = getrank_runs, 0, getrank_threshold
     return c
 
 
@@ -297,14 +302,18 @@ class Tensor:
                                        ctypes.byref(b)), self.h)
         return n.value, ms.value, b.value
 
-    def last_rep(self, rep, item, max_rows):
+    def last_rep(self, rep, item, max_rows, ncols=None):
+        """Debug copy of one repetition's item (rows x R, or rows x ncols for
+        items with another width: 1 for SBT_REP_RNEW, getrank_runs for
+        SBT_REP_CC)."""
         I, J, K, R = self.shape()
-        cap = (max_rows + 1) * R
+        nc = R if ncols is None else ncols
+        cap = (max_rows + 1) * max(R, nc)
         buf = np.empty(cap)
         rows = _i64()
         _check(load().sbt_last_rep(self.h, rep, item, buf.ctypes.data, cap, ctypes.byref(rows)),
                self.h, "sbt_last_rep")
-        return buf[:rows.value * R].reshape(rows.value, R).copy()
+        return buf[:rows.value * nc].reshape(rows.value, nc).copy()
 
 
 def mttkrp_dense(precision, Z_dev, n1, n2, n3, R, U0_dev, U1_dev, U2_dev, mode, out_dev,

@@ -4,6 +4,7 @@
 import ctypes
 import os
 import re
+import subprocess
 
 from paper_1709_00668_amd import sambaten
 
@@ -33,11 +34,22 @@ def test_binding_covers_every_declared_symbol():
     assert set(declared_functions()) == set(sambaten.exported_symbols())
 
 
-def test_config_struct_layout():
-    # int32 x 10, uint64, uint32 x 2, int64 x 3 with natural alignment
-    assert ctypes.sizeof(sambaten.sbt_config) == 80
-    assert sambaten.sbt_config.seed.offset == 40
-    assert sambaten.sbt_config.k_capacity.offset == 56
+def test_config_struct_layout(tmp_path):
+    # the ctypes mirror against the C compiler's layout of the header's struct
+    fields = [f[0] for f in sambaten.sbt_config._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stddef.h>\n#include <stdio.h>\n#include \"sambaten.h\"\n"
+                   "int main(void) {\n  printf(\"%zu\\n\", sizeof(sbt_config));\n"
+                   + "".join(f"  printf(\"%zu\\n\", offsetof(sbt_config, {f}));\n"
+                             for f in fields)
+                   + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-std=c11", "-I", inc, str(src), "-o", str(exe)], check=True)
+    out = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    assert out[0] == ctypes.sizeof(sambaten.sbt_config)
+    assert out[1:] == [getattr(sambaten.sbt_config, f).offset for f in fields]
 
 
 def test_status_strings_without_gpu():

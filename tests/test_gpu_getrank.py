@@ -1,0 +1,79 @@
+"""GetRank (Sec. 3.2) on the GPU against the CPU FP64 oracle: the core
+consistency of every run, the chosen rank of every summary, the matching of
+the R_new sample components and the resulting update."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import sambaten as osb
+
+pytestmark = pytest.mark.gpu
+
+
+def _pair(lib, I, J, K0, Kn, R_true, R, reps, iters, s, seed, prec, runs, tau, noise=1e-3):
+    import torch
+    assert torch.cuda.is_available()
+    dtype = np.float64 if prec == lib.SBT_P_F64 else np.float32
+    gen = synth.DenseCP(I, J, K0 + Kn, R_true, seed=seed, noise=noise, dtype=dtype)
+    X = gen.slices(0, K0 + Kn)
+    ocfg = osb.Config(rank=R, reps=reps, als_iters=iters, sample_factor=s, seed=seed,
+                      k_capacity=K0 + Kn, init_iters=40, getrank_runs=runs,
+                      getrank_threshold=tau)
+    ora = osb.OracleTensor(ocfg, osb.DENSE, (I, J, K0), X0=X[:, :, :K0])
+    cfg = lib.make_config(R, reps, iters, s, seed, precision=prec, k_capacity=K0 + Kn,
+                          max_batch=Kn, getrank_runs=runs, getrank_threshold=tau)
+    gpu = lib.Tensor.init_dense(cfg, lib.dense_to_device(X[:, :, :K0], dtype), I, J, K0,
+                                factors=(ora.A, ora.B, ora.C, ora.lam))
+    d = ora.update(X[:, :, K0:K0 + Kn], debug=True)
+    gpu.update_batch_dense(lib.dense_to_device(X[:, :, K0:K0 + Kn], dtype), Kn)
+    torch.cuda.synchronize()
+    return ora, gpu, d
+
+
+def _check(lib, ora, gpu, d, reps, R, runs, K0, c_tol, cc_tol):
+    for rho in range(reps):
+        r = d["reps"][rho]
+        for mode, key in enumerate(("Is", "Js", "Ks")):
+            np.testing.assert_array_equal(gpu.last_sample(rho, mode), r[key])
+        rn = int(gpu.last_rep(rho, lib.SBT_REP_RNEW, 1, ncols=1)[0, 0])
+        assert rn == r["Rnew"], (rho, rn, r["Rnew"], r["cc"])
+        cc = gpu.last_rep(rho, lib.SBT_REP_CC, R, ncols=runs)
+        want = np.array(r["cc"])
+        sane = np.abs(want) < 1e3  # degenerate runs (pinv of near-collinear columns) differ
+        np.testing.assert_allclose(cc[sane], want[sane], rtol=0, atol=cc_tol)
+        assert np.all((cc[~sane] < 0) == (want[~sane] < 0))
+        valid = gpu.last_rep(rho, lib.SBT_REP_VALID, 1)[0]
+        np.testing.assert_array_equal(valid.astype(bool), r["valid"])
+        pi = gpu.last_rep(rho, lib.SBT_REP_PI, 1)[0].astype(int)
+        m = r["pi"] >= 0
+        np.testing.assert_array_equal(pi[m], r["pi"][m])
+    A, B, C, lam = gpu.get_factors()
+    err = np.linalg.norm(C[K0:] - ora.C[K0:]) / np.linalg.norm(ora.C[K0:])
+    assert err < c_tol, err
+    assert abs(gpu.fit() - ora.fit()) < c_tol
+
+
+def test_getrank_fp64_rank_deficient_update(lib):
+    I, J, K0, Kn, R, reps, runs = 40, 36, 30, 8, 4, 3, 2
+    ora, gpu, d = _pair(lib, I, J, K0, Kn, 2, R, reps, 20, 2, 41, lib.SBT_P_F64, runs, 90.0)
+    assert all(r["Rnew"] < R for r in d["reps"])
+    _check(lib, ora, gpu, d, reps, R, runs, K0, 1e-7, 1e-6)
+
+
+def test_getrank_fp32(lib):
+    I, J, K0, Kn, R, reps, runs = 48, 40, 36, 10, 5, 3, 1
+    ora, gpu, d = _pair(lib, I, J, K0, Kn, 3, R, reps, 20, 2, 42, lib.SBT_P_F32, runs, 90.0)
+    _check(lib, ora, gpu, d, reps, R, runs, K0, 1e-3, 0.5)
+
+
+@pytest.mark.parametrize("tau,expect", [(1e9, 1), (-1e308, 3)])
+def test_getrank_threshold_edges(lib, tau, expect):
+    I, J, K0, Kn, R, reps, runs = 30, 28, 24, 6, 3, 2, 1
+    ora, gpu, d = _pair(lib, I, J, K0, Kn, 2, R, reps, 10, 2, 43, lib.SBT_P_F64, runs, tau)
+    for rho in range(reps):
+        assert d["reps"][rho]["Rnew"] == expect
+        assert int(gpu.last_rep(rho, lib.SBT_REP_RNEW, 1, ncols=1)[0, 0]) == expect
+    A, B, C, lam = gpu.get_factors()
+    err = np.linalg.norm(C[K0:] - ora.C[K0:]) / max(1e-300, np.linalg.norm(ora.C[K0:]))
+    assert err < 1e-7, err
