@@ -40,6 +40,8 @@ cpu_baseline (dense workloads): the CPU FP64 oracle on the first
 CP-ALS of the whole grown tensor on the GPU and the relative fitness of the
 incremental result against it (Sec. 4.2); fms_truth: the factor match score
 (Sec. 4.4, on the GPU) of the final model against the generating components.
+getrank (dense workloads): the batched FP32 update with GetRank (Sec. 3.2) on
+every summary.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--workload dense500]
 """
@@ -155,10 +157,11 @@ def timed_sequence(sbt, torch, fresh, apply_batch, steps, warmup, latency_runs, 
 
 
 def run_dense(sbt, torch, w, Xd, model, precision, schedule, steps, warmup, latency_runs,
-              truth=None):
+              truth=None, getrank_runs=0):
     I, J, K0, Kn = w["I"], w["J"], w["K0"], w["Kn"]
     cfg = sbt.make_config(w["R"], w["r"], w["iters"], w["s"], w["seed"], precision=precision,
-                          schedule=schedule, k_capacity=K0 + steps * Kn, max_batch=Kn)
+                          schedule=schedule, k_capacity=K0 + steps * Kn, max_batch=Kn,
+                          getrank_runs=getrank_runs)
 
     def fresh():
         return sbt.Tensor.init_dense(cfg, Xd[:K0], I, J, K0, factors=model)
@@ -340,6 +343,13 @@ def bench_dense(args, sbt, torch, synth, log):
         log(f"# recompute CP-ALS: fit {fr:.6f} in {dt:.2f} s, FMS vs truth {fms_rt:.4f}")
     if "fms_truth" in b:
         line["fms_truth"] = round(b["fms_truth"], 4)
+    if args.getrank_runs > 0:
+        # GetRank (Sec. 3.2) on every summary: ranks 1..R, getrank_runs CP runs each
+        g = run_dense(sbt, torch, w, Xd, model, sbt.SBT_P_F32, sbt.SBT_SCHED_BATCHED, steps,
+                      min(args.warmup, 1), 1, truth=truth, getrank_runs=args.getrank_runs)
+        line["getrank"] = dict(path_summary(g), runs=args.getrank_runs,
+                               fms_truth=round(g["fms_truth"], 4))
+        log(f"# getrank: {g['slices_per_s']:.1f} slices/s, fit {g['fit']:.6f}")
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline_dense(w, Xkji.transpose(2, 1, 0), model, args.cpu_updates)
@@ -527,6 +537,9 @@ def main():
     ap.add_argument("--no-recompute", action="store_true",
                     help="skip the CP-ALS recompute of the grown tensor (relative fitness)")
     ap.add_argument("--recompute-iters", type=int, default=100)
+    ap.add_argument("--getrank-runs", type=int, default=1,
+                    help="dense: also time the update with GetRank, this many CP runs per "
+                         "candidate rank (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=0,
                     help="requests of the serving workload (default: the workload's 512)")
     ap.add_argument("--nnz-scale", type=float, default=1.0,
