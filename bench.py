@@ -173,38 +173,51 @@ def run_dense(sbt, torch, w, Xd, model, precision, schedule, steps, warmup, late
                           truth=truth)
 
 
-def source_digest():
-    """Digest of the HIP sources (a counter measurement is valid for one digest)."""
+CSRC = os.path.join(ROOT, "paper_1709_00668_amd", "csrc")
+
+
+def kernel_digest(kernel):
+    """Digest of the source file that defines `kernel` (its launch code lives
+    there too) and of the shared headers: a counter measurement of the kernel
+    stays valid while this digest does."""
+    base = re.match(r"\w+", kernel).group(0)
+    pat = re.compile(r"\bvoid\s+" + re.escape(base) + r"\s*\(")
+    names = sorted(os.listdir(CSRC))
+    home = [n for n in names
+            if n.endswith(".hip") and pat.search(open(os.path.join(CSRC, n)).read())]
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1709_00668_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
-    return h.hexdigest()[:16]
+    for name in home + [n for n in names if n.endswith(".hpp")]:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16] if home else None
 
 
-def committed_traffic(kernel, workload):
+def committed_traffic(kernel, key):
     """HBM bytes per launch of `kernel` from a committed counter summary
-    (profiles/<workload>_traffic.md), if taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"{workload}_traffic.md")
+    (profiles/<workload>_traffic.md) taken on the same workload (`key`) and on
+    the kernel's current sources (per-kernel digest column)."""
+    name = key.split("@")[0]
+    path = os.path.join(ROOT, "profiles", f"{name}_traffic.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
-    m = re.search(r"source digest: `([0-9a-f]+)`", text)
-    if not m or m.group(1) != source_digest():
+    m = re.search(r"workload key: `([^`]+)`", text)
+    if not m or m.group(1) != key:
         return None
+    want = kernel_digest(kernel)
     for line in text.splitlines():
         cells = [c.strip().strip("`") for c in line.split("|")]
-        if len(cells) > 3 and cells[1] == kernel:
+        if len(cells) > 4 and cells[1] == kernel:
+            if cells[-2] != want:
+                return None
             try:
-                return int(float(cells[-2]))
+                return int(float(cells[-3]))
             except ValueError:
                 return None
     return None
 
 
-def roofline_of(prof, path, R, workload, summary_rows=0):
+def roofline_of(prof, path, R, key, summary_rows=0):
     kernels = {k: v for k, v in prof.items() if k != "update" and v["launches"]}
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     d = kernels[dom]
@@ -216,7 +229,7 @@ def roofline_of(prof, path, R, workload, summary_rows=0):
     kname = kernel_of(dom, path, R, row_nnz)
     return dict(bound="hbm", kernel=kname, step=dom, achieved=round(achieved, 1),
                 peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
-                traffic=committed_traffic(kname, workload),
+                traffic=committed_traffic(kname, key),
                 avg_launch_us=round(avg_ms * 1e3, 2), alg_bytes_per_launch=int(bytes_per_launch),
                 share_of_update_time=round(d["total_ms"] / prof["update"]["total_ms"], 3))
 
@@ -397,7 +410,7 @@ def bench_sparse(args, sbt, torch, synth, log):
     line = base_line(args, w, res, "f32")
     line["config"]["nnz0"] = len(v0)
     line["config"]["nnz_batch"] = nnzb
-    line["roofline"] = roofline_of(res["profile"], "coo", w["R"], name,
+    line["roofline"] = roofline_of(res["profile"], "coo", w["R"], f"{name}@{args.nnz_scale:g}",
                                    summary_rows=w["r"] * -(-w["I"] // w["s"]))
     line["cpu_baseline"] = None
     line["kernels"] = kernels_table(res["profile"])
