@@ -32,6 +32,12 @@ listed, with reasons, in the design notes of the repository):
 * Zero entries of A, B and the anchor rows of C are replaced by the mean over
   the valid covering repetitions, after all repetitions (order free).
 * lambda is kept unchanged by default.
+* Persistent summaries (optional; Sec. 3.1 starts from a pre-existing set
+  of summaries): the sampled I_s, J_s, K_s of an update are kept for the
+  following ones (redrawn every summary_refresh updates), so a summary is
+  X(I_s, J_s, K_s u new) with the same anchors each time, and its CP-ALS
+  starts from the previous summary factors (B', and C' on the K_s rows; the
+  rows of the new slices drawn U[0,1) as usual).
 * GetRank (Sec. 3.2, optional): per summary, R_new = the largest candidate
   rank whose best CP run reaches the core-consistency threshold (see
   cp.get_rank); the summary's factors are that run's.  The R_new sample
@@ -160,7 +166,8 @@ def match(A_anchor, B_anchor, C_anchor, Ap, Bp, Cp_anchor):
 class Config:
     def __init__(self, rank, reps, als_iters, sample_factor, seed, tensor_id=0,
                  init_iters=100, k_capacity=None, nnz_capacity=None, summary_bf16=False,
-                 getrank_runs=0, getrank_threshold=90.0):
+                 getrank_runs=0, getrank_threshold=90.0, persist_summaries=False,
+                 summary_refresh=0):
         self.rank = int(rank)
         self.reps = int(reps)
         self.als_iters = int(als_iters)
@@ -177,6 +184,14 @@ class Config:
         # GetRank (Sec. 3.2, Alg. 2) on every summary when getrank_runs > 0
         self.getrank_runs = int(getrank_runs)
         self.getrank_threshold = float(getrank_threshold)
+        # persistent summaries (Sec. 3.1 starts from a pre-existing set of
+        # summaries): the sampled indices are kept from one update to the next
+        # (redrawn every summary_refresh updates, never when 0) and the summary
+        # CP-ALS starts from the previous summary factors
+        self.persist_summaries = bool(persist_summaries)
+        self.summary_refresh = int(summary_refresh)
+        if self.persist_summaries and self.getrank_runs > 0:
+            raise ValueError("persistent summaries and GetRank do not combine")
 
 
 class NumericError(ValueError):
@@ -192,6 +207,7 @@ class OracleTensor:
         I, J, K0 = (int(d) for d in dims)
         self.I, self.J, self.K = I, J, K0
         self.t = 0
+        self.kept = None  # persistent summaries: per repetition (Is, Js, Ks, B', C')
         kcap = k_capacity or cfg.k_capacity or K0
         if fmt == DENSE:
             X0 = np.asarray(X0)
@@ -278,11 +294,16 @@ class OracleTensor:
             XYvals = np.concatenate([self.vals, yvals])
 
         n = [sample_size(I, cfg.s[0]), sample_size(J, cfg.s[1]), sample_size(Kold, cfg.s[2])]
+        reuse = (cfg.persist_summaries and self.kept is not None and
+                 not (cfg.summary_refresh > 0 and self.t % cfg.summary_refresh == 0))
         reps = []
         for rho in range(cfg.reps):
-            Is = sample_mode(self.w[0], n[0], cfg.seed, cfg.tensor_id, 1, rho, self.t)
-            Js = sample_mode(self.w[1], n[1], cfg.seed, cfg.tensor_id, 2, rho, self.t)
-            Ks = sample_mode(self.w[2], n[2], cfg.seed, cfg.tensor_id, 3, rho, self.t)
+            if reuse:
+                Is, Js, Ks = self.kept[rho][:3]
+            else:
+                Is = sample_mode(self.w[0], n[0], cfg.seed, cfg.tensor_id, 1, rho, self.t)
+                Js = sample_mode(self.w[1], n[1], cfg.seed, cfg.tensor_id, 2, rho, self.t)
+                Ks = sample_mode(self.w[2], n[2], cfg.seed, cfg.tensor_id, 3, rho, self.t)
             Kp = np.concatenate([Ks, Kold + np.arange(Kn)])
             dims_s = (len(Is), len(Js), len(Kp))
             if self.fmt == DENSE:
@@ -313,11 +334,16 @@ class OracleTensor:
                                                          init)
                 npinv = 0
             else:
-                # Decompose (Sec. 3.1), B' and C' drawn U[0,1), A' computed first.
+                # Decompose (Sec. 3.1), B' and C' drawn U[0,1), A' computed first;
+                # with kept summaries B' and the K_s rows of C' start from the
+                # previous summary factors (warm start)
                 B0 = cp.als_init_factor(cfg.seed, cfg.tensor_id, rng.TAG_ALSINIT, 2, rho, self.t,
                                         dims_s[1], R)
                 C0 = cp.als_init_factor(cfg.seed, cfg.tensor_id, rng.TAG_ALSINIT, 3, rho, self.t,
                                         dims_s[2], R)
+                if reuse:
+                    B0 = self.kept[rho][3].copy()
+                    C0[:len(Ks)] = self.kept[rho][4]
                 (Ap, Bp, Cp), lamp, npinv = cp.cp_als(mtt, dims_s, R, cfg.als_iters, B0, C0)
             # Normalise + match (Sec. 3.1 "Project back", Lemma 1); with
             # R_new < R only R_new of the current components find a partner.
@@ -366,6 +392,9 @@ class OracleTensor:
                 C_new[:, f] = acc / cnt
 
         # Commit the state.
+        if cfg.persist_summaries:
+            self.kept = [(r["Is"], r["Js"], r["Ks"], r["Bp"].copy(), r["Cp"][:len(r["Ks"])].copy())
+                         for r in reps]
         self.A, self.B = A_new, B_new
         self.C = np.vstack([C_old, C_new])
         if self.fmt == DENSE:

@@ -205,3 +205,51 @@ def test_fit_after_update_matches_explicit():
     T, X, _ = make_dense(14, 13, 12, 4, 3, 11, 0.02, 3, 10)
     T.update(X[:, :, 12:16])
     assert abs(T.fit() - T.fit_explicit()) < 1e-7
+
+
+def _persist_run(persist, refresh, batches=3, noise=0.0, iters=25):
+    I, J, K0, Kn, R = 20, 18, 16, 4, 3
+    A, B, C, X = exact_model(I, J, K0 + batches * Kn, R, 31)
+    if noise:
+        X = X + noise * np.random.default_rng(32).standard_normal(X.shape)
+    An, Bn, Cn, lam, nC = unit_model(A, B, C, K0)
+    cfg = sb.Config(rank=R, reps=3, als_iters=iters, sample_factor=2, seed=33,
+                    k_capacity=K0 + batches * Kn, persist_summaries=persist,
+                    summary_refresh=refresh)
+    t = sb.OracleTensor(cfg, sb.DENSE, (I, J, K0), X0=X[:, :, :K0], factors=(An, Bn, Cn, lam))
+    out = [t.update(X[:, :, K0 + b * Kn:K0 + (b + 1) * Kn], debug=True) for b in range(batches)]
+    return t, out, (A, B, C, nC, K0)
+
+
+def test_persistent_summaries_keep_the_sample():
+    t, out, _ = _persist_run(True, 0)
+    for d in out[1:]:
+        for rho in range(3):
+            for key in ("Is", "Js", "Ks"):
+                np.testing.assert_array_equal(d["reps"][rho][key], out[0]["reps"][rho][key])
+    # refresh every update: each update samples afresh and starts cold, which
+    # is the plain update
+    t1, out1, _ = _persist_run(True, 1, noise=0.01)
+    t0, out0, _ = _persist_run(False, 0, noise=0.01)
+    for d1, d0 in zip(out1, out0):
+        for rho in range(3):
+            for key in ("Is", "Js", "Ks"):
+                np.testing.assert_array_equal(d1["reps"][rho][key], d0["reps"][rho][key])
+    np.testing.assert_array_equal(t1.C, t0.C)
+
+
+def test_persistent_warm_start_on_exact_data():
+    # noise-free data and the true model: the kept summary factors are exact,
+    # the warm-started ALS stays there and every batch's new rows come out exact
+    t, out, (A, B, C, nC, K0) = _persist_run(True, 0, iters=2000)
+    want = C[K0:] / nC[None, :]
+    assert np.abs(t.C[K0:] - want).max() < 1e-10 * np.abs(want).max()
+    # at a fixed number of sweeps the warm-started updates end closer to the truth
+    tw, _, _ = _persist_run(True, 0, iters=600)
+    tc, _, _ = _persist_run(False, 0, iters=600)
+    assert np.abs(tw.C[K0:] - want).max() < 0.1 * np.abs(tc.C[K0:] - want).max()
+    # the second update starts from the first update's summary factors
+    r0, r1 = out[0]["reps"][0], out[1]["reps"][0]
+    Bp0 = r0["Bp"]
+    cos = np.abs(np.sum(cp.normalize_columns(r1["Bp"])[0] * Bp0, axis=0))
+    assert np.all(cos > 1 - 1e-9)
