@@ -41,7 +41,8 @@ CP-ALS of the whole grown tensor on the GPU and the relative fitness of the
 incremental result against it (Sec. 4.2); fms_truth: the factor match score
 (Sec. 4.4, on the GPU) of the final model against the generating components.
 getrank (dense workloads): the batched FP32 update with GetRank (Sec. 3.2) on
-every summary.
+every summary.  persistent (dense workloads): the main path with persistent
+summaries (samples of the first update kept, warm-started summary CP-ALS).
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--workload dense500]
 """
@@ -157,11 +158,11 @@ def timed_sequence(sbt, torch, fresh, apply_batch, steps, warmup, latency_runs, 
 
 
 def run_dense(sbt, torch, w, Xd, model, precision, schedule, steps, warmup, latency_runs,
-              truth=None, getrank_runs=0):
+              truth=None, getrank_runs=0, persist=False):
     I, J, K0, Kn = w["I"], w["J"], w["K0"], w["Kn"]
     cfg = sbt.make_config(w["R"], w["r"], w["iters"], w["s"], w["seed"], precision=precision,
                           schedule=schedule, k_capacity=K0 + steps * Kn, max_batch=Kn,
-                          getrank_runs=getrank_runs)
+                          getrank_runs=getrank_runs, persist_summaries=persist)
 
     def fresh():
         return sbt.Tensor.init_dense(cfg, Xd[:K0], I, J, K0, factors=model)
@@ -363,6 +364,12 @@ def bench_dense(args, sbt, torch, synth, log):
         line["getrank"] = dict(path_summary(g), runs=args.getrank_runs,
                                fms_truth=round(g["fms_truth"], 4))
         log(f"# getrank: {g['slices_per_s']:.1f} slices/s, fit {g['fit']:.6f}")
+    if not args.no_persist:
+        # persistent summaries: the first update's samples kept, warm-started summary CP-ALS
+        p = run_dense(sbt, torch, w, Xd, model, main_prec, sbt.SBT_SCHED_BATCHED, steps,
+                      args.warmup, 1, truth=truth, persist=True)
+        line["persistent"] = dict(path_summary(p), fms_truth=round(p["fms_truth"], 4))
+        log(f"# persistent summaries: {p['slices_per_s']:.1f} slices/s, fit {p['fit']:.6f}")
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline_dense(w, Xkji.transpose(2, 1, 0), model, args.cpu_updates)
@@ -550,6 +557,8 @@ def main():
     ap.add_argument("--no-recompute", action="store_true",
                     help="skip the CP-ALS recompute of the grown tensor (relative fitness)")
     ap.add_argument("--recompute-iters", type=int, default=100)
+    ap.add_argument("--no-persist", action="store_true",
+                    help="dense: skip the persistent-summary variant")
     ap.add_argument("--getrank-runs", type=int, default=1,
                     help="dense: also time the update with GetRank, this many CP runs per "
                          "candidate rank (0: skip)")

@@ -92,6 +92,16 @@ typedef struct {
   int32_t getrank_runs;
   int32_t reserved;          /* must be 0 */
   double getrank_threshold;  /* core consistency a candidate rank must reach */
+  /* Persistent summaries (Sec. 3.1 starts from a pre-existing set of
+   * summaries): with persist_summaries = 1 the indices I_s, J_s, K_s drawn at
+   * an update are kept for the following updates (drawn afresh at every
+   * update whose batch counter is a multiple of summary_refresh; never again
+   * when it is 0), so each summary is X(I_s, J_s, K_s u new) with the same
+   * anchors, and its CP-ALS starts from the previous summary factors (B',
+   * and C' on the K_s rows; rows of the new slices drawn U[0,1) as usual).
+   * Not combined with GetRank. */
+  int32_t persist_summaries;
+  int32_t summary_refresh;
 } sbt_config;
 
 /* --------------------------------------------------------------------------

@@ -84,6 +84,12 @@ struct sbt_tensor {
   double *gcc = nullptr, *gbest = nullptr, *gtab = nullptr, *gP = nullptr, *gX1 = nullptr,
          *gX2 = nullptr, *gGi = nullptr;
   int32_t* grnew = nullptr;
+  // persistent summaries: kept summary factors for the warm start
+  double *Bw = nullptr, *Cw = nullptr;
+  bool have_kept = false;  // I_s, J_s, K_s in idx are the kept ones
+  int n3kept = 0;
+  bool warm_now = false;   // this update's summary CP-ALS starts from Bw, Cw
+  int warm_n3 = 0;
   std::vector<void*> grow_allocs; // freed when regrown or destroyed
   int64_t last_summary_nnz = 0;
   // kernel timing (sbt_profile_*)
@@ -221,6 +227,9 @@ sbt_status validate_config(const sbt_config* c, std::string& why) {
   if (c->schedule != SBT_SCHED_BATCHED && c->schedule != SBT_SCHED_PLAIN) { why = "bad schedule"; return SBT_E_INVALID; }
   if (c->flags != 0 || c->reserved != 0) { why = "flags must be 0"; return SBT_E_INVALID; }
   if (c->getrank_runs < 0 || c->getrank_runs > 64) { why = "getrank_runs must be in 0..64"; return SBT_E_INVALID; }
+  if (c->persist_summaries != 0 && c->persist_summaries != 1) { why = "persist_summaries must be 0 or 1"; return SBT_E_INVALID; }
+  if (c->summary_refresh < 0) { why = "summary_refresh must be >= 0"; return SBT_E_INVALID; }
+  if (c->persist_summaries && c->getrank_runs > 0) { why = "persistent summaries and GetRank do not combine"; return SBT_E_INVALID; }
   if (c->getrank_runs > 0) {
     if (c->format != SBT_DENSE || c->precision == SBT_P_BF16) {
       why = "GetRank needs a dense FP64 or FP32 tensor";
@@ -334,6 +343,10 @@ sbt_status alloc_state(sbt_tensor* t) {
     t->xpart_mats = np;
     SBT_TRY(dalloc(t, &t->xout, (size_t)r * 9 * R * R));
     SBT_TRY(dalloc(t, &t->scl, (size_t)r * 2 * R));
+  }
+  if (c.persist_summaries) {
+    SBT_TRY(dalloc(t, &t->Bw, (size_t)r * rs.sB));
+    SBT_TRY(dalloc(t, &t->Cw, (size_t)r * rs.sC));
   }
   if (c.getrank_runs > 0) {
     const size_t R3 = (size_t)R * R * R;
@@ -560,8 +573,12 @@ sbt_status run_als_coo(sbt_tensor* t, RepSet rs, uint32_t t_ctr, hipStream_t st)
   double* ilA = t->invlam;
   double* ilB = t->invlam + R;
   double* ilC = t->invlam + 2 * R;
-  SBT_CK(launch_als_init(rs, t->cfg.seed, t->cfg.tensor_id, kStreamAlsInit, t_ctr, t->Bp, t->Cp,
-                         st));
+  if (t->warm_now)
+    SBT_CK(launch_als_warm(rs, t->cfg.seed, t->cfg.tensor_id, kStreamAlsInit, t_ctr, t->Bw,
+                           t->Cw, t->warm_n3, t->Bp, t->Cp, st));
+  else
+    SBT_CK(launch_als_init(rs, t->cfg.seed, t->cfg.tensor_id, kStreamAlsInit, t_ctr, t->Bp,
+                           t->Cp, st));
   SBT_TRY(gram_rows(t, rs, t->Bp, rs.sB, rs.n2, t->GB, st));
   SBT_TRY(gram_rows(t, rs, t->Cp, rs.sC, rs.n3, t->GC, st));
   SBT_CK(launch_fill_f64(t->invlam + (int64_t)rs.rep0 * 3 * R, (int64_t)rs.nrep * 3 * R, 1.0,
@@ -646,7 +663,11 @@ sbt_status run_als(sbt_tensor* t, const void* Zp, RepSet rs, double* Ap, double*
                    double* Vinv, double* invlam, uint32_t stream, uint32_t t_ctr, int iters,
                    bool plain, hipStream_t st, uint32_t col0 = 0) {
   const int prec = t->sum_prec;
-  SBT_CK(launch_als_init(rs, t->cfg.seed, t->cfg.tensor_id, stream, t_ctr, Bp, Cp, st, col0));
+  if (t->warm_now && stream == kStreamAlsInit)
+    SBT_CK(launch_als_warm(rs, t->cfg.seed, t->cfg.tensor_id, stream, t_ctr, t->Bw, t->Cw,
+                           t->warm_n3, Bp, Cp, st));
+  else
+    SBT_CK(launch_als_init(rs, t->cfg.seed, t->cfg.tensor_id, stream, t_ctr, Bp, Cp, st, col0));
   SBT_TRY(gram_rows(t, rs, Bp, rs.sB, rs.n2, GB, st));
   SBT_TRY(gram_rows(t, rs, Cp, rs.sC, rs.n3, GC, st));
   const double zb = (double)rs.nrep * rs.n1 * rs.n2 * rs.n3 * prec_bytes(prec);
@@ -885,7 +906,10 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
   const sbt_config& c = t->cfg;
   const int R = t->R, r = c.repetitions;
   const int64_t Kold = t->K;
-  const int n3old = (int)sample_size(Kold, c.sample_factor[2]);
+  // persistent summaries keep the sampled indices (and so K_s and its size)
+  const bool reuse = c.persist_summaries && t->have_kept &&
+                     !(c.summary_refresh > 0 && t->t % (uint32_t)c.summary_refresh == 0);
+  const int n3old = reuse ? t->n3kept : (int)sample_size(Kold, c.sample_factor[2]);
   const int Kp = n3old + (int)Kn;
   // sampling (from the tensor before the update)
   SampleArgs sa;
@@ -910,7 +934,7 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
   sa.tensor_id = c.tensor_id;
   sa.t = t->t;
   sa.nrep = r;
-  SBT_CK(launch_sample(sa, t->keys, t->idx, st));
+  if (!reuse) SBT_CK(launch_sample(sa, t->keys, t->idx, st));
   const int64_t offJ = t->n1, offK = (int64_t)t->n1 + t->n2;
   RepSet all = make_repset(t, Kp, 0, r);
   const bool plain = c.schedule == SBT_SCHED_PLAIN;
@@ -933,6 +957,8 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
   }
   const bool coo = t->fmt == SBT_COO;
   const int nchunks = (plain && !coo) ? r : 1;
+  t->warm_now = reuse;  // read by the summary CP-ALS initialisation
+  t->warm_n3 = n3old;
   for (int q = 0; q < nchunks; ++q) {
     RepSet rs = (plain && !coo) ? make_repset(t, Kp, q, 1) : all;
     if (coo) {
@@ -1024,6 +1050,7 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
       prof_end(t, rq, SBT_K_ROW_SOLVE, rbytes, st);
     }
   }
+  t->warm_now = false;
   CommitArgs ca;
   ca.err = t->err;
   ca.A = t->A;
@@ -1066,6 +1093,15 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
     set_err(t, (*t->h_err & 2u) ? "batch coordinate outside the tensor"
                                 : "batch holds a non-finite value or overflows the importance sums");
     return (*t->h_err & 2u) ? SBT_E_SHAPE : SBT_E_NUMERIC;
+  }
+  if (c.persist_summaries) {
+    // keep this update's summary factors for the next warm start
+    const RepSet ks = make_repset(t, Kp, 0, r);
+    SBT_CK(hipMemcpyAsync(t->Bw, t->Bp, sizeof(double) * r * ks.sB, hipMemcpyDeviceToDevice, st));
+    SBT_CK(hipMemcpyAsync(t->Cw, t->Cp, sizeof(double) * r * ks.sC, hipMemcpyDeviceToDevice, st));
+    SBT_CK(hipStreamSynchronize(st));
+    t->have_kept = true;
+    t->n3kept = n3old;
   }
   t->K = Kold + Kn;
   t->t += 1;

@@ -90,6 +90,31 @@ __global__ void als_init_kernel(RepSet rs, uint64_t seed, uint32_t tensor_id, ui
   }
 }
 
+// Warm start from kept summary factors: B' = Bw, C' rows below n3keep = Cw,
+// the other C' rows U[0,1) from the same counters as als_init_kernel.
+__global__ void als_warm_kernel(RepSet rs, uint64_t seed, uint32_t tensor_id, uint32_t stream,
+                                uint32_t t, const double* Bw, const double* Cw, int n3keep,
+                                double* Bp, double* Cp) {
+  const int rep = rs.rep0 + blockIdx.y;
+  const RngKey key = rng_key(seed, tensor_id);
+  const int64_t nb = (int64_t)rs.n2 * rs.R, nc = (int64_t)rs.n3 * rs.R;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nb + nc;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    if (q < nb) {
+      Bp[rep * rs.sB + q] = Bw[rep * rs.sB + q];
+      continue;
+    }
+    const int64_t qq = q - nb;
+    const uint32_t row = (uint32_t)(qq / rs.R), col = (uint32_t)(qq % rs.R);
+    if ((int)row < n3keep) {
+      Cp[rep * rs.sC + qq] = Cw[rep * rs.sC + qq];
+    } else {
+      const uint32_t tag = rng_tag(stream, 3u, (uint32_t)rep);
+      Cp[rep * rs.sC + qq] = uniform_closed0(rng_bits(key, row, col, tag, t));
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Gram matrix G = U^T U of a rows x R factor (one block per repetition).
 // Thread -> (pair f <= g, row slice); slices combined in LDS.
@@ -362,6 +387,17 @@ hipError_t launch_als_init(const RepSet& rs, uint64_t seed, uint32_t tensor_id, 
   als_init_kernel<<<dim3((unsigned)blocks, (unsigned)rs.nrep), 256, 0, s>>>(rs, seed, tensor_id,
                                                                           stream, t, col0, Bp,
                                                                           Cp);
+  return hipGetLastError();
+}
+
+hipError_t launch_als_warm(const RepSet& rs, uint64_t seed, uint32_t tensor_id, uint32_t stream,
+                           uint32_t t, const double* Bw, const double* Cw, int n3keep,
+                           double* Bp, double* Cp, hipStream_t s) {
+  const int64_t n = (int64_t)(rs.n2 + rs.n3) * rs.R;
+  int blocks = (int)((n + 255) / 256);
+  if (blocks > 1024) blocks = 1024;
+  als_warm_kernel<<<dim3((unsigned)blocks, (unsigned)rs.nrep), 256, 0, s>>>(
+      rs, seed, tensor_id, stream, t, Bw, Cw, n3keep, Bp, Cp);
   return hipGetLastError();
 }
 

@@ -118,6 +118,10 @@ hipError_t launch_mode3_finish(const RepSet& rs, int nsplit, const float* P, int
 // B', C' <- U[0,1) from Philox counters (row, col0 + col, tag(stream, mode, rep), t)
 hipError_t launch_als_init(const RepSet& rs, uint64_t seed, uint32_t tensor_id, uint32_t stream,
                            uint32_t t, double* Bp, double* Cp, hipStream_t s, uint32_t col0 = 0);
+// warm start: B' <- Bw, C' rows < n3keep <- Cw, the other C' rows as launch_als_init
+hipError_t launch_als_warm(const RepSet& rs, uint64_t seed, uint32_t tensor_id, uint32_t stream,
+                           uint32_t t, const double* Bw, const double* Cw, int n3keep,
+                           double* Bp, double* Cp, hipStream_t s);
 // G = U^T U for rows x R factors of each repetition
 hipError_t launch_gram(const RepSet& rs, const double* U, int64_t sU, int rows, double* G,
                        hipStream_t s);

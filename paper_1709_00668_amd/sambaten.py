@@ -45,6 +45,8 @@ class sbt_config(ctypes.Structure):
         ("getrank_runs", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
         ("getrank_threshold", ctypes.c_double),
+        ("persist_summaries", ctypes.c_int32),
+        ("summary_refresh", ctypes.c_int32),
     ]
 
 
@@ -147,7 +149,7 @@ def _stream(stream):
 def make_config(rank, repetitions, als_iters, sample_factor, seed, *, init_iters=100,
                 fmt=SBT_DENSE, precision=SBT_P_F32, schedule=SBT_SCHED_BATCHED, tensor_id=0,
                 k_capacity, max_batch, nnz_capacity=0, getrank_runs=0,
-                getrank_threshold=90.0):
+                getrank_threshold=90.0, persist_summaries=False, summary_refresh=0):
     c = sbt_config()
     c.rank, c.repetitions, c.als_iters, c.init_iters = rank, repetitions, als_iters, init_iters
     s = (sample_factor,) * 3 if np.isscalar(sample_factor) else tuple(sample_factor)
@@ -157,6 +159,7 @@ def make_config(rank, repetitions, als_iters, sample_factor, seed, *, init_iters
     c.seed, c.tensor_id, c.flags = seed, tensor_id, 0
     c.k_capacity, c.max_batch, c.nnz_capacity = k_capacity, max_batch, nnz_capacity
     c.getrank_runs, c.reserved, c.getrank_threshold = getrank_runs, 0, getrank_threshold
+    c.persist_summaries, c.summary_refresh = int(bool(persist_summaries)), summary_refresh
     return c
 
 

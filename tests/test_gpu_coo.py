@@ -23,7 +23,8 @@ def sparse_case(I, J, K0, Kn, batches, R, nnz0, nnz_b, seed):
     return idx0, v0, bat
 
 
-def run_coo_pair(lib, I, J, K0, Kn, batches, R, reps, iters, s, seed, nnz0, nnz_b):
+def run_coo_pair(lib, I, J, K0, Kn, batches, R, reps, iters, s, seed, nnz0, nnz_b,
+                 persist=False):
     torch = _torch()
     idx0, v0, bat = sparse_case(I, J, K0, Kn, batches, R, nnz0, nnz_b, seed)
     g = np.random.default_rng(seed)
@@ -32,10 +33,12 @@ def run_coo_pair(lib, I, J, K0, Kn, batches, R, reps, iters, s, seed, nnz0, nnz_
     model = (A0 / nA, B0 / nB, C0 / nC, nA * nB * nC)
     kcap = K0 + batches * Kn
     ocfg = osb.Config(rank=R, reps=reps, als_iters=iters, sample_factor=s, seed=seed,
-                      k_capacity=kcap, nnz_capacity=nnz0 + batches * nnz_b)
+                      k_capacity=kcap, nnz_capacity=nnz0 + batches * nnz_b,
+                      persist_summaries=persist)
     ora = osb.OracleTensor(ocfg, osb.COO, (I, J, K0), coo0=(idx0, v0), factors=model)
     cfg = lib.make_config(R, reps, iters, s, seed, fmt=lib.SBT_COO, precision=lib.SBT_P_F32,
-                          k_capacity=kcap, max_batch=Kn, nnz_capacity=nnz0 + batches * nnz_b)
+                          k_capacity=kcap, max_batch=Kn, nnz_capacity=nnz0 + batches * nnz_b,
+                          persist_summaries=persist)
     cols, vd = lib.coo_to_device(idx0, v0)
     gpu = lib.Tensor.init_coo(cfg, cols, vd, len(v0), I, J, K0, model)
     ds = []
@@ -79,6 +82,20 @@ def test_coo_update_unit_shapes(lib, I, J, K0, R, nnz0, nnz_b):
             np.testing.assert_array_equal(gpu.last_sample(rho, mode), d["reps"][rho][key])
     A, B, C, lam = gpu.get_factors()
     err = np.linalg.norm(C[K0:] - ora.C[K0:]) / np.linalg.norm(ora.C[K0:])
+    assert err < 1e-3, err
+    assert abs(gpu.fit() - ora.fit()) < 1e-3
+
+
+def test_coo_persistent_summaries(lib):
+    reps = 3
+    ora, gpu, ds = run_coo_pair(lib, 80, 70, 40, 10, 3, 3, reps, 12, 2, 25, 6000, 1500,
+                                persist=True)
+    for rho in range(reps):
+        for mode, key in enumerate(("Is", "Js", "Ks")):
+            np.testing.assert_array_equal(gpu.last_sample(rho, mode), ds[-1]["reps"][rho][key])
+            np.testing.assert_array_equal(ds[-1]["reps"][rho][key], ds[0]["reps"][rho][key])
+    A, B, C, lam = gpu.get_factors()
+    err = np.linalg.norm(C[40:] - ora.C[40:]) / np.linalg.norm(ora.C[40:])
     assert err < 1e-3, err
     assert abs(gpu.fit() - ora.fit()) < 1e-3
 
