@@ -177,19 +177,33 @@ def run_dense(sbt, torch, w, Xd, model, precision, schedule, steps, warmup, late
 CSRC = os.path.join(ROOT, "paper_1709_00668_amd", "csrc")
 
 
-def kernel_digest(kernel):
+def _header_defs(text):
+    """The definitions a kernel can depend on in a header: comments and
+    function declarations removed, whitespace collapsed."""
+    text = re.sub(r"//[^\n]*", "", text)
+    text = re.sub(r"\b(?:hipError_t|bool|int|size_t|int64_t)\s+\w+\([^;{}]*\)\s*;", "", text)
+    return " ".join(text.split())
+
+
+def kernel_digest(kernel, read=None):
     """Digest of the source file that defines `kernel` (its launch code lives
-    there too) and of the shared headers: a counter measurement of the kernel
-    stays valid while this digest does."""
+    there too) and of the definitions in the shared headers (declarations of
+    other launchers do not count): a counter measurement of the kernel stays
+    valid while this digest does.  `read(name)` returns a source file's text
+    (default: the working tree)."""
+    if read is None:
+        def read(name):
+            with open(os.path.join(CSRC, name)) as f:
+                return f.read()
     base = re.match(r"\w+", kernel).group(0)
     pat = re.compile(r"\bvoid\s+" + re.escape(base) + r"\s*\(")
     names = sorted(os.listdir(CSRC))
-    home = [n for n in names
-            if n.endswith(".hip") and pat.search(open(os.path.join(CSRC, n)).read())]
+    home = [n for n in names if n.endswith(".hip") and pat.search(read(n))]
     h = hashlib.sha256()
-    for name in home + [n for n in names if n.endswith(".hpp")]:
-        with open(os.path.join(CSRC, name), "rb") as f:
-            h.update(name.encode() + b"\0" + f.read())
+    for name in home:
+        h.update(name.encode() + b"\0" + read(name).encode())
+    for name in [n for n in names if n.endswith(".hpp")]:
+        h.update(name.encode() + b"\0" + _header_defs(read(name)).encode())
     return h.hexdigest()[:16] if home else None
 
 
