@@ -92,8 +92,8 @@ typedef struct {
   int32_t getrank_runs;
   int32_t reserved;          /* must be 0 */
   double getrank_threshold;  /* core consistency a candidate rank must reach */
-  /* Persistent summaries (Sec. 3.1 starts from a pre-existing set of
-   * summaries): with persist_summaries = 1 the indices I_s, J_s, K_s drawn at
+  /* Persistent summaries (Sec. 3.1 assumes summaries of the tensor exist
+   * before an update): with persist_summaries = 1 the indices I_s, J_s, K_s drawn at
    * an update are kept for the following updates (drawn afresh at every
    * update whose batch counter is a multiple of summary_refresh; never again
    * when it is 0), so each summary is X(I_s, J_s, K_s u new) with the same

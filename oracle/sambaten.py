@@ -32,8 +32,8 @@ listed, with reasons, in the design notes of the repository):
 * Zero entries of A, B and the anchor rows of C are replaced by the mean over
   the valid covering repetitions, after all repetitions (order free).
 * lambda is kept unchanged by default.
-* Persistent summaries (optional; Sec. 3.1 starts from a pre-existing set
-  of summaries): the sampled I_s, J_s, K_s of an update are kept for the
+* Persistent summaries (optional; Sec. 3.1 assumes summaries of the tensor
+  already exist when a batch arrives): the sampled I_s, J_s, K_s of an update are kept for the
   following ones (redrawn every summary_refresh updates), so a summary is
   X(I_s, J_s, K_s u new) with the same anchors each time, and its CP-ALS
   starts from the previous summary factors (B', and C' on the K_s rows; the
@@ -184,8 +184,8 @@ class Config:
         # GetRank (Sec. 3.2, Alg. 2) on every summary when getrank_runs > 0
         self.getrank_runs = int(getrank_runs)
         self.getrank_threshold = float(getrank_threshold)
-        # persistent summaries (Sec. 3.1 starts from a pre-existing set of
-        # summaries): the sampled indices are kept from one update to the next
+        # persistent summaries (Sec. 3.1 assumes summaries of the tensor exist
+        # before the update): the sampled indices are kept from one update to the next
         # (redrawn every summary_refresh updates, never when 0) and the summary
         # CP-ALS starts from the previous summary factors
         self.persist_summaries = bool(persist_summaries)
