@@ -94,6 +94,7 @@ struct sbt_tensor {
   // persistent summaries: kept summary factors for the warm start
   double *Bw = nullptr, *Cw = nullptr;
   bool have_kept = false;  // I_s, J_s, K_s in idx are the kept ones
+  bool z_kept = false;     // the summaries' K_s slices were gathered with those indices
   int n3kept = 0;
   bool warm_now = false;   // this update's summary CP-ALS starts from Bw, Cw
   int warm_n3 = 0;
@@ -1008,23 +1009,28 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
   const int64_t offJ = t->n1, offK = (int64_t)t->n1 + t->n2;
   RepSet all = make_repset(t, Kp, 0, r);
   const bool plain = c.schedule == SBT_SCHED_PLAIN;
+  // a kept summary's old part (the K_s slices) is still in place from the
+  // update before, which used the same indices: only the new slices are gathered
+  const int c0 = (reuse && t->z_kept) ? n3old : 0;
   if (t->mfma) {
     const int gq = prof_begin(t, st);
     SBT_CK(launch_gather_mfma(t->store_prec, t->X, t->I, t->J, t->idx, t->idx_stride, offJ, offK,
-                              n3old, Kold, all, t->ml, t->Zk, t->Zc, st));
+                              n3old, Kold, c0, all, t->ml, t->Zk, t->Zc, st));
     prof_end(t, gq, SBT_K_GATHER,
-             (double)r * t->n1 * t->n2 * Kp * (prec_bytes(t->store_prec) + 4.0), st);
+             (double)r * t->n1 * t->n2 * (Kp - c0) * (prec_bytes(t->store_prec) + 4.0), st);
   } else if (t->fmt == SBT_DENSE) {
     const int gq = prof_begin(t, st);
     SBT_CK(launch_gather_dense(t->store_prec, t->sum_prec, t->X, t->I, t->J, t->idx,
-                               t->idx_stride, offJ, offK, n3old, Kold, all, t->Z, st));
+                               t->idx_stride, offJ, offK, n3old, Kold, c0, all, t->Z, st));
     prof_end(t, gq, SBT_K_GATHER,
-             (double)r * t->n1 * t->n2 * Kp *
+             (double)r * t->n1 * t->n2 * (Kp - c0) *
                  (prec_bytes(t->store_prec) + prec_bytes(t->sum_prec)),
              st);
   } else {
     SBT_TRY(coo_build_summaries(t, Kold, n3old, Kp, st));
   }
+  // the summaries now hold X(I_s, J_s, K_s) for the indices in idx
+  t->z_kept = t->fmt == SBT_DENSE;
   const bool coo = t->fmt == SBT_COO;
   const int nchunks = (plain && !coo) ? r : 1;
   t->warm_now = reuse;  // read by the summary CP-ALS initialisation

@@ -55,9 +55,10 @@ template <typename TIn, typename TOut>
 __global__ __launch_bounds__(256) void gather_dense_kernel(const TIn* X, int64_t I, int64_t J,
                                                           const int32_t* idx, int64_t idx_stride,
                                                           int64_t offJ, int64_t offK, int n3old,
-                                                          int64_t Kold, RepSet rs, TOut* Z) {
+                                                          int64_t Kold, int c0, RepSet rs,
+                                                          TOut* Z) {
   const int rep = rs.rep0 + blockIdx.z;
-  const int c = blockIdx.y;
+  const int c = c0 + (int)blockIdx.y;
   const int64_t n12 = (int64_t)rs.n1 * rs.n2;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= n12) return;
@@ -362,19 +363,20 @@ __global__ __launch_bounds__(256) void solve_kernel(RepSet rs, int rows, SolveAr
 // ---------------------------------------------------------------------------
 hipError_t launch_gather_dense(int store_prec, int sum_prec, const void* X, int64_t I,
                                int64_t J, const int32_t* idx, int64_t idx_stride,
-                               int64_t offJ, int64_t offK, int n3old, int64_t Kold,
+                               int64_t offJ, int64_t offK, int n3old, int64_t Kold, int c0,
                                const RepSet& rs, void* Z, hipStream_t s) {
   const int64_t n12 = (int64_t)rs.n1 * rs.n2;
-  dim3 grid((unsigned)((n12 + 255) / 256), (unsigned)rs.n3, (unsigned)rs.nrep);
+  if (c0 < 0 || c0 >= rs.n3) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((n12 + 255) / 256), (unsigned)(rs.n3 - c0), (unsigned)rs.nrep);
   if (store_prec == kF64) {
     gather_dense_kernel<double, double><<<grid, 256, 0, s>>>(
-        (const double*)X, I, J, idx, idx_stride, offJ, offK, n3old, Kold, rs, (double*)Z);
+        (const double*)X, I, J, idx, idx_stride, offJ, offK, n3old, Kold, c0, rs, (double*)Z);
   } else if (sum_prec == kF32) {
     gather_dense_kernel<float, float><<<grid, 256, 0, s>>>(
-        (const float*)X, I, J, idx, idx_stride, offJ, offK, n3old, Kold, rs, (float*)Z);
+        (const float*)X, I, J, idx, idx_stride, offJ, offK, n3old, Kold, c0, rs, (float*)Z);
   } else {
     gather_dense_kernel<float, uint16_t><<<grid, 256, 0, s>>>(
-        (const float*)X, I, J, idx, idx_stride, offJ, offK, n3old, Kold, rs, (uint16_t*)Z);
+        (const float*)X, I, J, idx, idx_stride, offJ, offK, n3old, Kold, c0, rs, (uint16_t*)Z);
   }
   return hipGetLastError();
 }

@@ -68,10 +68,11 @@ template <typename TIn>
 __global__ __launch_bounds__(256) void gather_mfma_kernel(const TIn* X, int64_t I, int64_t J,
                                                          const int32_t* idx, int64_t idx_stride,
                                                          int64_t offJ, int64_t offK, int n3old,
-                                                         int64_t Kold, RepSet rs, MfmaLayout L,
-                                                         uint16_t* Zk, uint16_t* Zc) {
+                                                         int64_t Kold, int cg0, RepSet rs,
+                                                         MfmaLayout L, uint16_t* Zk,
+                                                         uint16_t* Zc) {
   const int rep = rs.rep0 + blockIdx.z;
-  const int cg = blockIdx.y;
+  const int cg = cg0 + (int)blockIdx.y;
   const int64_t n12 = (int64_t)rs.n1 * rs.n2;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= n12) return;
@@ -435,17 +436,19 @@ int mfma_mode3_splits(const RepSet& rs, const MfmaLayout& L) {
 
 hipError_t launch_gather_mfma(int store_prec, const void* X, int64_t I, int64_t J,
                               const int32_t* idx, int64_t idx_stride, int64_t offJ, int64_t offK,
-                              int n3old, int64_t Kold, const RepSet& rs, const MfmaLayout& L,
-                              uint16_t* Zk, uint16_t* Zc, hipStream_t s) {
+                              int n3old, int64_t Kold, int c0, const RepSet& rs,
+                              const MfmaLayout& L, uint16_t* Zk, uint16_t* Zc, hipStream_t s) {
   const int64_t n12 = (int64_t)rs.n1 * rs.n2;
   const int kp32 = (rs.n3 + 31) / 32 * 32;
-  dim3 grid((unsigned)((n12 + 255) / 256), (unsigned)(kp32 / 8), (unsigned)rs.nrep);
+  if (c0 < 0 || c0 >= rs.n3) return hipErrorInvalidValue;
+  const int cg0 = c0 / 8;  // groups of 8 slices, the first one gathered whole
+  dim3 grid((unsigned)((n12 + 255) / 256), (unsigned)(kp32 / 8 - cg0), (unsigned)rs.nrep);
   if (store_prec == kF64)
     gather_mfma_kernel<double><<<grid, 256, 0, s>>>((const double*)X, I, J, idx, idx_stride, offJ,
-                                                    offK, n3old, Kold, rs, L, Zk, Zc);
+                                                    offK, n3old, Kold, cg0, rs, L, Zk, Zc);
   else
     gather_mfma_kernel<float><<<grid, 256, 0, s>>>((const float*)X, I, J, idx, idx_stride, offJ,
-                                                   offK, n3old, Kold, rs, L, Zk, Zc);
+                                                   offK, n3old, Kold, cg0, rs, L, Zk, Zc);
   return hipGetLastError();
 }
 

@@ -68,10 +68,11 @@ hipError_t launch_sample(const SampleArgs& a, uint64_t* keys, int32_t* idx, hipS
 
 // ---- summaries -----------------------------------------------------------
 // Z[rep](a,b,c) = X(Is[a], Js[b], K'[c]) with K'[c] = Ks[c] for c < n3old and
-// Kold + c - n3old after; converted to the summary precision.
+// Kold + c - n3old after; converted to the summary precision.  Slices c < c0
+// are left as they are (a kept summary's old part).
 hipError_t launch_gather_dense(int store_prec, int sum_prec, const void* X, int64_t I,
                                int64_t J, const int32_t* idx, int64_t idx_stride,
-                               int64_t offJ, int64_t offK, int n3old, int64_t Kold,
+                               int64_t offJ, int64_t offK, int n3old, int64_t Kold, int c0,
                                const RepSet& rs, void* Z, hipStream_t s);
 
 // ---- BF16 summaries on the matrix cores ----------------------------------
@@ -89,10 +90,12 @@ MfmaLayout mfma_layout(int n1, int n2, int kpmax);
 bool mfma_supported(int n1, int n2, int R);
 // number of K ranges of the mode-3 kernel
 int mfma_mode3_splits(const RepSet& rs, const MfmaLayout& L);
+// both BF16 layouts; the groups of 8 slices from the one holding c0 on are
+// gathered (earlier slices are a kept summary's old part)
 hipError_t launch_gather_mfma(int store_prec, const void* X, int64_t I, int64_t J,
                               const int32_t* idx, int64_t idx_stride, int64_t offJ, int64_t offK,
-                              int n3old, int64_t Kold, const RepSet& rs, const MfmaLayout& L,
-                              uint16_t* Zk, uint16_t* Zc, hipStream_t s);
+                              int n3old, int64_t Kold, int c0, const RepSet& rs,
+                              const MfmaLayout& L, uint16_t* Zk, uint16_t* Zc, hipStream_t s);
 // one repetition from a column-major BF16 tensor (no sampling)
 hipError_t launch_relayout_bf16(const uint16_t* Z, const RepSet& rs, const MfmaLayout& L,
                                 uint16_t* Zk, uint16_t* Zc, hipStream_t s);

@@ -15,11 +15,12 @@ def _run(lib, prec, refresh, schedule=None, batches=3, seed=51):
     assert torch.cuda.is_available()
     I, J, K0, Kn, R, reps, iters = 40, 36, 30, 6, 3, 3, 20
     dtype = np.float64 if prec == lib.SBT_P_F64 else np.float32
+    bf16 = prec == lib.SBT_P_BF16
     gen = synth.DenseCP(I, J, K0 + batches * Kn, R, seed=seed, noise=0.01, dtype=dtype)
     X = gen.slices(0, K0 + batches * Kn)
     ocfg = osb.Config(rank=R, reps=reps, als_iters=iters, sample_factor=2, seed=seed,
                       k_capacity=K0 + batches * Kn, init_iters=40, persist_summaries=True,
-                      summary_refresh=refresh)
+                      summary_refresh=refresh, summary_bf16=bf16)
     ora = osb.OracleTensor(ocfg, osb.DENSE, (I, J, K0), X0=X[:, :, :K0])
     cfg = lib.make_config(R, reps, iters, 2, seed, precision=prec, k_capacity=K0 + batches * Kn,
                           max_batch=Kn, persist_summaries=True, summary_refresh=refresh,
@@ -71,3 +72,13 @@ def test_persistent_plain_schedule_fp64(lib):
     ora, gpu, ds, K0 = _run(lib, lib.SBT_P_F64, 0, schedule=lib.SBT_SCHED_PLAIN, batches=2)
     A, B, C, lam = gpu.get_factors()
     np.testing.assert_allclose(C[K0:], ora.C[K0:], rtol=1e-7, atol=1e-9)
+
+
+def test_persistent_bf16_matrix_cores(lib):
+    # the kept summary's old part stays in both BF16 layouts; only the new
+    # slices' groups are gathered again
+    ora, gpu, ds, K0 = _run(lib, lib.SBT_P_BF16, 0, batches=4)
+    A, B, C, lam = gpu.get_factors()
+    err = np.linalg.norm(C[K0:] - ora.C[K0:]) / np.linalg.norm(ora.C[K0:])
+    assert err < 1e-3, err
+    assert abs(gpu.fit() - ora.fit()) < 1e-4
