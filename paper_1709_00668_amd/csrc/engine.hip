@@ -104,6 +104,7 @@ struct sbt_tensor {
   bool prof_on = false;
   std::vector<hipEvent_t> prof_ev;     // pairs
   std::vector<int> prof_kind;          // per recorded pair
+  std::vector<char> prof_launch;       // pair recorded by a kernel launch itself
   std::vector<double> prof_bytes;      // per recorded pair
   int64_t prof_n[SBT_K_COUNT] = {};
   double prof_ms[SBT_K_COUNT] = {};
@@ -163,7 +164,8 @@ sbt_status dalloc_bytes(sbt_tensor* t, void** p, size_t bytes) {
 // final synchronisation.
 constexpr size_t kProfPairs = 8192;
 
-int prof_begin(sbt_tensor* t, hipStream_t st) {
+// a free event pair, or -1
+int prof_pair(sbt_tensor* t) {
   if (!t->prof_on) return -1;
   const size_t q = t->prof_kind.size();
   if (q >= kProfPairs) return -1;
@@ -177,15 +179,45 @@ int prof_begin(sbt_tensor* t, hipStream_t st) {
     t->prof_ev.push_back(a);
     t->prof_ev.push_back(b);
   }
-  if (hipEventRecord(t->prof_ev[2 * q], st) != hipSuccess) return -1;
   t->prof_kind.push_back(-1);
   t->prof_bytes.push_back(0.0);
+  t->prof_launch.push_back(0);
   return (int)q;
+}
+
+// events on the stream around what follows (the whole update)
+int prof_begin(sbt_tensor* t, hipStream_t st) {
+  const int q = prof_pair(t);
+  if (q >= 0 && hipEventRecord(t->prof_ev[2 * (size_t)q], st) != hipSuccess) {
+    t->prof_kind.pop_back();
+    t->prof_bytes.pop_back();
+    t->prof_launch.pop_back();
+    return -1;
+  }
+  return q;
+}
+
+// events the next timed kernel launch records at its own start and end
+int prof_kernel(sbt_tensor* t) {
+  const int q = prof_pair(t);
+  if (q >= 0) {
+    t->prof_launch[(size_t)q] = 1;
+    launch_timing() = LaunchTiming{t->prof_ev[2 * (size_t)q], t->prof_ev[2 * (size_t)q + 1]};
+  }
+  return q;
 }
 
 void prof_end(sbt_tensor* t, int q, int kind, double bytes, hipStream_t st) {
   if (q < 0) return;
-  if (hipEventRecord(t->prof_ev[2 * (size_t)q + 1], st) != hipSuccess) return;
+  if (t->prof_launch[(size_t)q]) {
+    LaunchTiming& lt = launch_timing();
+    if (lt.start == t->prof_ev[2 * (size_t)q]) {  // no timed launch took the pair
+      lt = LaunchTiming{};
+      return;
+    }
+  } else if (hipEventRecord(t->prof_ev[2 * (size_t)q + 1], st) != hipSuccess) {
+    return;
+  }
   t->prof_kind[(size_t)q] = kind;
   t->prof_bytes[(size_t)q] = bytes;
 }
@@ -203,6 +235,7 @@ void prof_collect(sbt_tensor* t) {
   }
   t->prof_kind.clear();
   t->prof_bytes.clear();
+  t->prof_launch.clear();
 }
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -526,7 +559,7 @@ sbt_status coo_build_summaries(sbt_tensor* t, int64_t Kold, int n3old, int Kp, h
   SBT_TRY(ensure_summary(t, total, st));
   SBT_CK(hipMemcpyAsync(z.rep_off, z.rep_off_h, sizeof(int64_t) * (r + 1), hipMemcpyHostToDevice,
                         st));
-  const int gq = prof_begin(t, st);
+  const int gq = prof_kernel(t);
   SBT_CK(launch_coo_emit(t->ci, t->cj, t->ck, t->cv, nnz_all, t->bitI, t->bitJ, t->bitK, Kold,
                          n3old, r, t->posI, t->posJ, t->posK, t->I, t->J, t->Kcap, t->bbase, z,
                          st));
@@ -603,7 +636,7 @@ sbt_status run_als_coo(sbt_tensor* t, RepSet rs, uint32_t t_ctr, hipStream_t st)
   ta.sG = rs.sG;
   ta.pinv_count = t->pinv;
   for (int it = 0; it < t->cfg.als_iters; ++it) {
-    int pq = prof_begin(t, st);
+    int pq = prof_kernel(t);
     SBT_CK(launch_coo_units(rs, 0, t->z, t->cu[0], t->fB, rs.n2, t->fC, rs.n3, t->upart, avg1,
                             st));
     prof_end(t, pq, SBT_K_COO_MTTKRP, ebytes, st);
@@ -613,7 +646,7 @@ sbt_status run_als_coo(sbt_tensor* t, RepSet rs, uint32_t t_ctr, hipStream_t st)
     ta.lam_out = nullptr; ta.Gx = t->GA; ta.Gy = t->GC; ta.Vinv_out = t->Vinv;
     SBT_TRY(tail(t, rs, ta, st));
     SBT_CK(launch_coo_prep(rs, rs.n1, t->Ap, rs.sA, ilA, t->fA, st));
-    pq = prof_begin(t, st);
+    pq = prof_kernel(t);
     SBT_CK(launch_coo_units(rs, 1, t->z, t->cu[1], t->fA, rs.n1, t->fC, rs.n3, t->upart, avg2,
                             st));
     prof_end(t, pq, SBT_K_COO_MTTKRP, ebytes, st);
@@ -623,7 +656,7 @@ sbt_status run_als_coo(sbt_tensor* t, RepSet rs, uint32_t t_ctr, hipStream_t st)
     ta.lam_out = nullptr; ta.Gx = t->GA; ta.Gy = t->GB; ta.Vinv_out = t->Vinv;
     SBT_TRY(tail(t, rs, ta, st));
     SBT_CK(launch_coo_prep(rs, rs.n2, t->Bp, rs.sB, ilB, t->fB, st));
-    pq = prof_begin(t, st);
+    pq = prof_kernel(t);
     SBT_CK(launch_coo_units(rs, 2, t->z, t->cu[2], t->fA, rs.n1, t->fB, rs.n2, t->upart, avg3,
                             st));
     prof_end(t, pq, SBT_K_COO_MTTKRP, ebytes, st);
@@ -686,19 +719,19 @@ sbt_status run_als(sbt_tensor* t, const void* Zp, RepSet rs, double* Ap, double*
   if (plain) {
     // one launch per step, three passes over the summary per sweep
     for (int it = 0; it < iters; ++it) {
-      int pq = prof_begin(t, st);
+      int pq = prof_kernel(t);
       SBT_CK(launch_p1(prec, rs, Zp, Cp, W, st));
       prof_end(t, pq, SBT_K_MTTKRP_C, p1_bytes, st);
       SBT_CK(launch_cw1(prec, rs, W, Bp, M, st));
       SBT_CK(launch_solve(rs, rs.n1, M, GB, rs.sG, GC, rs.sG, Ap, rs.sA, GA, lam_out, nullptr, 1,
                           t->pinv, st));
-      pq = prof_begin(t, st);
+      pq = prof_kernel(t);
       SBT_CK(launch_p1(prec, rs, Zp, Cp, W, st));
       prof_end(t, pq, SBT_K_MTTKRP_C, p1_bytes, st);
       SBT_CK(launch_cw2(prec, rs, W, Ap, M, st));
       SBT_CK(launch_solve(rs, rs.n2, M, GA, rs.sG, GC, rs.sG, Bp, rs.sB, GB, lam_out, nullptr, 1,
                           t->pinv, st));
-      pq = prof_begin(t, st);
+      pq = prof_kernel(t);
       SBT_CK(launch_p2(prec, rs, Zp, Ap, Bp, M, st));
       prof_end(t, pq, SBT_K_MTTKRP_AB, p2_bytes, st);
       SBT_CK(launch_solve(rs, rs.n3, M, GA, rs.sG, GB, rs.sG, Cp, rs.sC, GC, lam_out, nullptr, 1,
@@ -770,7 +803,7 @@ sbt_status run_als(sbt_tensor* t, const void* Zp, RepSet rs, double* Ap, double*
   auto sweeps = [&]() -> sbt_status {
     const hipStream_t st = lst;
   for (int it = 0; it < iters; ++it) {
-    int pq = prof_begin(t, st);
+    int pq = prof_kernel(t);
     if (mf) {
       SBT_CK(launch_pw_mfma(rs, t->ml, t->Zc, Cp, ilC, (float*)W, t->mops, st));
       prof_end(t, pq, SBT_K_MTTKRP_C, pwm_bytes, st);
@@ -789,7 +822,7 @@ sbt_status run_als(sbt_tensor* t, const void* Zp, RepSet rs, double* Ap, double*
     ta.lam_out = nullptr; ta.Gx = GA; ta.Gy = GB; ta.Vinv_out = Vinv;
     SBT_TRY(tail(t, rs, ta, st));
     // mode 3: C (lambda' = its column norms)
-    pq = prof_begin(t, st);
+    pq = prof_kernel(t);
     if (mf) {
       SBT_CK(launch_p3_mfma(rs, t->ml, ns3, t->Zk, Ap, ilA, Bp, ilB, t->P3, t->sP3, t->mops,
                             st));
@@ -1013,13 +1046,13 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
   // update before, which used the same indices: only the new slices are gathered
   const int c0 = (reuse && t->z_kept) ? n3old : 0;
   if (t->mfma) {
-    const int gq = prof_begin(t, st);
+    const int gq = prof_kernel(t);
     SBT_CK(launch_gather_mfma(t->store_prec, t->X, t->I, t->J, t->idx, t->idx_stride, offJ, offK,
                               n3old, Kold, c0, all, t->ml, t->Zk, t->Zc, st));
     prof_end(t, gq, SBT_K_GATHER,
              (double)r * t->n1 * t->n2 * (Kp - c0) * (prec_bytes(t->store_prec) + 4.0), st);
   } else if (t->fmt == SBT_DENSE) {
-    const int gq = prof_begin(t, st);
+    const int gq = prof_kernel(t);
     SBT_CK(launch_gather_dense(t->store_prec, t->sum_prec, t->X, t->I, t->J, t->idx,
                                t->idx_stride, offJ, offK, n3old, Kold, c0, all, t->Z, st));
     prof_end(t, gq, SBT_K_GATHER,
@@ -1095,7 +1128,7 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
     // Gt is already the Hadamard product; the second factor is all ones
     const double rbytes = (double)rs.nrep * rs.n1 * rs.n2 * rs.n3 * prec_bytes(t->sum_prec) +
                           (double)rs.nrep * rs.R * 8.0 * ((double)rs.n1 + rs.n2 + rs.n3);
-    const int rq = prof_begin(t, st);
+    const int rq = prof_kernel(t);
     if (coo) {
       SBT_CK(launch_inverse(rs, t->Gt, rs.sG, t->ones, 0, t->Vinv, t->pinv, st));
       SBT_CK(launch_coo_prep(rs, rs.n1, t->At, rs.sA, nullptr, t->fA, st));

@@ -369,13 +369,13 @@ hipError_t launch_gather_dense(int store_prec, int sum_prec, const void* X, int6
   if (c0 < 0 || c0 >= rs.n3) return hipErrorInvalidValue;
   dim3 grid((unsigned)((n12 + 255) / 256), (unsigned)(rs.n3 - c0), (unsigned)rs.nrep);
   if (store_prec == kF64) {
-    gather_dense_kernel<double, double><<<grid, 256, 0, s>>>(
+    timed_launch(gather_dense_kernel<double, double>, grid, dim3(256), 0, s, 
         (const double*)X, I, J, idx, idx_stride, offJ, offK, n3old, Kold, c0, rs, (double*)Z);
   } else if (sum_prec == kF32) {
-    gather_dense_kernel<float, float><<<grid, 256, 0, s>>>(
+    timed_launch(gather_dense_kernel<float, float>, grid, dim3(256), 0, s, 
         (const float*)X, I, J, idx, idx_stride, offJ, offK, n3old, Kold, c0, rs, (float*)Z);
   } else {
-    gather_dense_kernel<float, uint16_t><<<grid, 256, 0, s>>>(
+    timed_launch(gather_dense_kernel<float, uint16_t>, grid, dim3(256), 0, s, 
         (const float*)X, I, J, idx, idx_stride, offJ, offK, n3old, Kold, c0, rs, (uint16_t*)Z);
   }
   return hipGetLastError();
@@ -415,11 +415,11 @@ hipError_t launch_p1(int prec, const RepSet& rs, const void* Z, const double* Cf
   dim3 grid((unsigned)((n12 + 255) / 256), (unsigned)rs.nrep);
   SBT_DISPATCH_RP(rs.R, {
     if (prec == kF64)
-      p1_kernel<double, RP><<<grid, 256, 0, s>>>(rs, (const double*)Z, Cf, (double*)W);
+      timed_launch(p1_kernel<double, RP>, grid, dim3(256), 0, s, rs, (const double*)Z, Cf, (double*)W);
     else if (prec == kF32)
-      p1_kernel<float, RP><<<grid, 256, 0, s>>>(rs, (const float*)Z, Cf, (float*)W);
+      timed_launch(p1_kernel<float, RP>, grid, dim3(256), 0, s, rs, (const float*)Z, Cf, (float*)W);
     else
-      p1_kernel<uint16_t, RP><<<grid, 256, 0, s>>>(rs, (const uint16_t*)Z, Cf, (float*)W);
+      timed_launch(p1_kernel<uint16_t, RP>, grid, dim3(256), 0, s, rs, (const uint16_t*)Z, Cf, (float*)W);
   });
   return hipGetLastError();
 }
@@ -450,11 +450,11 @@ hipError_t launch_p2(int prec, const RepSet& rs, const void* Z, const double* Af
   dim3 grid((unsigned)rs.n3, (unsigned)rs.nrep);
   SBT_DISPATCH_RP(rs.R, {
     if (prec == kF64)
-      p2_kernel<double, RP><<<grid, 256, 0, s>>>(rs, (const double*)Z, Af, Bf, M);
+      timed_launch(p2_kernel<double, RP>, grid, dim3(256), 0, s, rs, (const double*)Z, Af, Bf, M);
     else if (prec == kF32)
-      p2_kernel<float, RP><<<grid, 256, 0, s>>>(rs, (const float*)Z, Af, Bf, M);
+      timed_launch(p2_kernel<float, RP>, grid, dim3(256), 0, s, rs, (const float*)Z, Af, Bf, M);
     else
-      p2_kernel<uint16_t, RP><<<grid, 256, 0, s>>>(rs, (const uint16_t*)Z, Af, Bf, M);
+      timed_launch(p2_kernel<uint16_t, RP>, grid, dim3(256), 0, s, rs, (const uint16_t*)Z, Af, Bf, M);
   });
   return hipGetLastError();
 }

@@ -737,7 +737,7 @@ hipError_t launch_coo_emit(const int32_t* si, const int32_t* sj, const int32_t* 
                            const int32_t* posK, int64_t I, int64_t J, int64_t Kcap,
                            const int64_t* bbase, CooSummary& z, hipStream_t s) {
   const int64_t nblk = coo_scan_blocks(nnz);
-  summary_emit_kernel<<<(unsigned)nblk, kCooBlock, 0, s>>>(
+  timed_launch(summary_emit_kernel, (unsigned)nblk, dim3(kCooBlock), 0, s, 
       si, sj, sk, sv, nnz, bitI, bitJ, bitK, Kold, n3old, nrep, posI, posJ, posK, I, J, Kcap,
       bbase, z.rep_off, nblk, z.a, z.b, z.c, z.v);
   return hipGetLastError();
@@ -848,11 +848,11 @@ hipError_t launch_coo_units(const RepSet& rs, int mode, const CooSummary& z, con
   const unsigned blocks = (unsigned)(kXcds * ((per + G - 1) / G));
   SBT_COO_RP(rs.R, {
     if (wide)
-      coo_units_kernel<RP, 64><<<blocks, 256, 0, s>>>(rs, m.rows, rowsX, rowsY, u.urow,
+      timed_launch(coo_units_kernel<RP, 64>, blocks, dim3(256), 0, s, rs, m.rows, rowsX, rowsY, u.urow,
                                                       u.ustart, u.ulen, u.uoff + n, u.cap, m.cx,
                                                       m.cy, m.cv, Xf, Yf, part);
     else
-      coo_units_kernel<RP, 32><<<blocks, 256, 0, s>>>(rs, m.rows, rowsX, rowsY, u.urow,
+      timed_launch(coo_units_kernel<RP, 32>, blocks, dim3(256), 0, s, rs, m.rows, rowsX, rowsY, u.urow,
                                                       u.ustart, u.ulen, u.uoff + n, u.cap, m.cx,
                                                       m.cy, m.cv, Xf, Yf, part);
   });

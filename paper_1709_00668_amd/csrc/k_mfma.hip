@@ -444,10 +444,10 @@ hipError_t launch_gather_mfma(int store_prec, const void* X, int64_t I, int64_t 
   const int cg0 = c0 / 8;  // groups of 8 slices, the first one gathered whole
   dim3 grid((unsigned)((n12 + 255) / 256), (unsigned)(kp32 / 8 - cg0), (unsigned)rs.nrep);
   if (store_prec == kF64)
-    gather_mfma_kernel<double><<<grid, 256, 0, s>>>((const double*)X, I, J, idx, idx_stride, offJ,
+    timed_launch(gather_mfma_kernel<double>, grid, dim3(256), 0, s, (const double*)X, I, J, idx, idx_stride, offJ,
                                                     offK, n3old, Kold, cg0, rs, L, Zk, Zc);
   else
-    gather_mfma_kernel<float><<<grid, 256, 0, s>>>((const float*)X, I, J, idx, idx_stride, offJ,
+    timed_launch(gather_mfma_kernel<float>, grid, dim3(256), 0, s, (const float*)X, I, J, idx, idx_stride, offJ,
                                                    offK, n3old, Kold, cg0, rs, L, Zk, Zc);
   return hipGetLastError();
 }
@@ -490,9 +490,9 @@ hipError_t launch_pw_mfma(const RepSet& rs, const MfmaLayout& L, const uint16_t*
   const size_t sh = (size_t)2 * nf * (kp32 + 8) * 2;
   if (sh > 65536) return hipErrorInvalidValue;
   if (nt == 1)
-    pw_mfma_kernel<1><<<grid, 256, sh, s>>>(rs, L, kp32, Zc, Ct, W);
+    timed_launch(pw_mfma_kernel<1>, grid, dim3(256), sh, s, rs, L, kp32, Zc, Ct, W);
   else
-    pw_mfma_kernel<2><<<grid, 256, sh, s>>>(rs, L, kp32, Zc, Ct, W);
+    timed_launch(pw_mfma_kernel<2>, grid, dim3(256), sh, s, rs, L, kp32, Zc, Ct, W);
   return hipGetLastError();
 }
 
@@ -526,9 +526,9 @@ hipError_t launch_p3_mfma(const RepSet& rs, const MfmaLayout& L, int nsplit, con
   const size_t sh = (size_t)nf * 4 * ((size_t)L.ld1 + (nbmax + 3) / 4 * 4);
   if (sh > 65536 || sP < (int64_t)rs.n3 * nf) return hipErrorInvalidValue;
   if (nt == 1)
-    p3_mfma_kernel<1><<<grid, 256, sh, s>>>(rs, L, nsplit, Zk, Atg, Btg, P, sP);
+    timed_launch(p3_mfma_kernel<1>, grid, dim3(256), sh, s, rs, L, nsplit, Zk, Atg, Btg, P, sP);
   else
-    p3_mfma_kernel<2><<<grid, 256, sh, s>>>(rs, L, nsplit, Zk, Atg, Btg, P, sP);
+    timed_launch(p3_mfma_kernel<2>, grid, dim3(256), sh, s, rs, L, nsplit, Zk, Atg, Btg, P, sP);
   return hipGetLastError();
 }
 

@@ -2,10 +2,37 @@
 // Every launcher enqueues on `stream` and returns the launch status.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+
 namespace sbt {
+
+// Timing of one kernel by events the launch itself records at the kernel's
+// start and end (hipExtLaunchKernel), instead of events around its dispatch:
+// when set, the next timed_launch on this host thread takes the pair.
+struct LaunchTiming {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+inline LaunchTiming& launch_timing() {
+  static thread_local LaunchTiming lt;
+  return lt;
+}
+template <typename... KArgs, typename... Args>
+inline void timed_launch(void (*kernel)(KArgs...), dim3 grid, dim3 block, size_t sh,
+                         hipStream_t s, Args&&... args) {
+  LaunchTiming& lt = launch_timing();
+  if (lt.start) {
+    hipEvent_t a = lt.start, b = lt.stop;
+    lt.start = lt.stop = nullptr;
+    hipExtLaunchKernelGGL(kernel, grid, block, (uint32_t)sh, s, a, b, 0u,
+                          std::forward<Args>(args)...);
+  } else {
+    kernel<<<grid, block, sh, s>>>(std::forward<Args>(args)...);
+  }
+}
 
 // Summary / MTTKRP element types.
 enum Prec : int { kF64 = 0, kF32 = 1, kBF16 = 2 };
