@@ -257,28 +257,40 @@ int bit_length(uint64_t v) {
 }
 
 sbt_status validate_config(const sbt_config* c, std::string& why) {
-  if (!c) { why = "null config"; return SBT_E_INVALID; }
-  if (c->rank < 1 || c->rank > kMaxRank) { why = "rank must be in 1..32"; return SBT_E_INVALID; }
-  if (c->repetitions < 1 || c->repetitions > 4096) { why = "repetitions must be in 1..4096"; return SBT_E_INVALID; }
-  if (c->als_iters < 1 || c->init_iters < 0) { why = "bad iteration counts"; return SBT_E_INVALID; }
-  for (int m = 0; m < 3; ++m)
-    if (c->sample_factor[m] < 1) { why = "sample factors must be >= 1"; return SBT_E_INVALID; }
-  if (c->format != SBT_DENSE && c->format != SBT_COO) { why = "bad format"; return SBT_E_INVALID; }
-  if (c->precision < SBT_P_F64 || c->precision > SBT_P_BF16) { why = "bad precision"; return SBT_E_INVALID; }
-  if (c->schedule != SBT_SCHED_BATCHED && c->schedule != SBT_SCHED_PLAIN) { why = "bad schedule"; return SBT_E_INVALID; }
-  if (c->flags != 0 || c->reserved != 0) { why = "flags must be 0"; return SBT_E_INVALID; }
-  if (c->getrank_runs < 0 || c->getrank_runs > 64) { why = "getrank_runs must be in 0..64"; return SBT_E_INVALID; }
-  if (c->persist_summaries != 0 && c->persist_summaries != 1) { why = "persist_summaries must be 0 or 1"; return SBT_E_INVALID; }
-  if (c->summary_refresh < 0) { why = "summary_refresh must be >= 0"; return SBT_E_INVALID; }
-  if (c->persist_summaries && c->getrank_runs > 0) { why = "persistent summaries and GetRank do not combine"; return SBT_E_INVALID; }
-  if (c->getrank_runs > 0) {
-    if (c->format != SBT_DENSE || c->precision == SBT_P_BF16) {
-      why = "GetRank needs a dense FP64 or FP32 tensor";
+  if (!c) {
+    why = "null config";
+    return SBT_E_INVALID;
+  }
+  bool sf_ok = true;
+  for (int m = 0; m < 3; ++m) sf_ok = sf_ok && c->sample_factor[m] >= 1;
+  const bool gr = c->getrank_runs > 0;
+  const struct {
+    bool bad;
+    const char* why;
+  } checks[] = {
+      {c->rank < 1 || c->rank > kMaxRank, "rank must be in 1..32"},
+      {c->repetitions < 1 || c->repetitions > 4096, "repetitions must be in 1..4096"},
+      {c->als_iters < 1 || c->init_iters < 0, "bad iteration counts"},
+      {!sf_ok, "sample factors must be >= 1"},
+      {c->format != SBT_DENSE && c->format != SBT_COO, "bad format"},
+      {c->precision < SBT_P_F64 || c->precision > SBT_P_BF16, "bad precision"},
+      {c->schedule != SBT_SCHED_BATCHED && c->schedule != SBT_SCHED_PLAIN, "bad schedule"},
+      {c->flags != 0 || c->reserved != 0, "flags and reserved must be 0"},
+      {c->getrank_runs < 0 || c->getrank_runs > 64, "getrank_runs must be in 0..64"},
+      {gr && (c->format != SBT_DENSE || c->precision == SBT_P_BF16),
+       "GetRank needs a dense FP64 or FP32 tensor"},
+      {gr && !(c->getrank_threshold == c->getrank_threshold), "bad GetRank threshold"},
+      {c->persist_summaries != 0 && c->persist_summaries != 1, "persist_summaries must be 0 or 1"},
+      {c->summary_refresh < 0, "summary_refresh must be >= 0"},
+      {c->persist_summaries && gr, "persistent summaries and GetRank do not combine"},
+      {c->max_batch < 1, "max_batch must be >= 1"},
+  };
+  for (const auto& k : checks) {
+    if (k.bad) {
+      why = k.why;
       return SBT_E_INVALID;
     }
-    if (!(c->getrank_threshold == c->getrank_threshold)) { why = "bad GetRank threshold"; return SBT_E_INVALID; }
   }
-  if (c->max_batch < 1) { why = "max_batch must be >= 1"; return SBT_E_INVALID; }
   return SBT_OK;
 }
 
@@ -1199,8 +1211,9 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
   prof_collect(t);
   if (*t->h_err) {
     t->pending_nnz = 0;
-    set_err(t, (*t->h_err & 2u) ? "batch coordinate outside the tensor"
-                                : "batch holds a non-finite value or overflows the importance sums");
+    set_err(t, (*t->h_err & 2u)
+                   ? "batch coordinate outside the tensor"
+                   : "batch holds a non-finite value or overflows the importance sums");
     return (*t->h_err & 2u) ? SBT_E_SHAPE : SBT_E_NUMERIC;
   }
   if (c.persist_summaries) {
@@ -1466,8 +1479,9 @@ sbt_status sbt_update_batch_coo(sbt_tensor* t, const int32_t* i_dev, const int32
   SBT_CK(hipStreamSynchronize(st));
   if (*t->h_err) {
     prof_collect(t);
-    set_err(t, (*t->h_err & 2u) ? "batch coordinate outside the tensor"
-                                : "batch holds a non-finite value or overflows the importance sums");
+    set_err(t, (*t->h_err & 2u)
+                   ? "batch coordinate outside the tensor"
+                   : "batch holds a non-finite value or overflows the importance sums");
     return (*t->h_err & 2u) ? SBT_E_SHAPE : SBT_E_NUMERIC;
   }
   SBT_TRY(ensure_ingest(t, nnz, st));

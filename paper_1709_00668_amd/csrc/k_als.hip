@@ -415,11 +415,14 @@ hipError_t launch_p1(int prec, const RepSet& rs, const void* Z, const double* Cf
   dim3 grid((unsigned)((n12 + 255) / 256), (unsigned)rs.nrep);
   SBT_DISPATCH_RP(rs.R, {
     if (prec == kF64)
-      timed_launch(p1_kernel<double, RP>, grid, dim3(256), 0, s, rs, (const double*)Z, Cf, (double*)W);
+      timed_launch(p1_kernel<double, RP>, grid, dim3(256), 0, s, rs, (const double*)Z, Cf,
+                   (double*)W);
     else if (prec == kF32)
-      timed_launch(p1_kernel<float, RP>, grid, dim3(256), 0, s, rs, (const float*)Z, Cf, (float*)W);
+      timed_launch(p1_kernel<float, RP>, grid, dim3(256), 0, s, rs, (const float*)Z, Cf,
+                   (float*)W);
     else
-      timed_launch(p1_kernel<uint16_t, RP>, grid, dim3(256), 0, s, rs, (const uint16_t*)Z, Cf, (float*)W);
+      timed_launch(p1_kernel<uint16_t, RP>, grid, dim3(256), 0, s, rs, (const uint16_t*)Z, Cf,
+                   (float*)W);
   });
   return hipGetLastError();
 }
@@ -454,7 +457,8 @@ hipError_t launch_p2(int prec, const RepSet& rs, const void* Z, const double* Af
     else if (prec == kF32)
       timed_launch(p2_kernel<float, RP>, grid, dim3(256), 0, s, rs, (const float*)Z, Af, Bf, M);
     else
-      timed_launch(p2_kernel<uint16_t, RP>, grid, dim3(256), 0, s, rs, (const uint16_t*)Z, Af, Bf, M);
+      timed_launch(p2_kernel<uint16_t, RP>, grid, dim3(256), 0, s, rs, (const uint16_t*)Z, Af,
+                   Bf, M);
   });
   return hipGetLastError();
 }

@@ -811,12 +811,14 @@ hipError_t launch_pw(int prec, const RepSet& rs, const void* Z, const double* Cf
   dim3 grid((unsigned)((n12 + 63) / 64), (unsigned)rs.nrep);
   SBT_RP_SWITCH(rs.R, {
     if (prec == kF64)
-      timed_launch(pw_kernel<double, RP>, grid, dim3(256), 0, s, rs, (const double*)Z, Cf, invlamC, (double*)W);
+      timed_launch(pw_kernel<double, RP>, grid, dim3(256), 0, s, rs, (const double*)Z, Cf,
+                   invlamC, (double*)W);
     else if (prec == kF32)
-      timed_launch(pw_kernel<float, RP>, grid, dim3(256), 0, s, rs, (const float*)Z, Cf, invlamC, (float*)W);
+      timed_launch(pw_kernel<float, RP>, grid, dim3(256), 0, s, rs, (const float*)Z, Cf, invlamC,
+                   (float*)W);
     else
-      timed_launch(pw_kernel<uint16_t, RP>, grid, dim3(256), 0, s, rs, (const uint16_t*)Z, Cf, invlamC,
-                                                   (float*)W);
+      timed_launch(pw_kernel<uint16_t, RP>, grid, dim3(256), 0, s, rs, (const uint16_t*)Z, Cf,
+                   invlamC, (float*)W);
   });
   return hipGetLastError();
 }
@@ -869,11 +871,11 @@ hipError_t launch_p3(int prec, const RepSet& rs, bool row_solve, const void* Z, 
       err = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);      \
     if (err != hipSuccess) break;                                                              \
     if (row_solve)                                                                             \
-      timed_launch(p3_kernel<TZ, RPV, VV, true>, grid, dim3(256), sh, s, rs, (const TZ*)Z, Af, invlamA, Bf,    \
-                                                         invlamB, Vinv, lam_div, U, sU);       \
+      timed_launch(p3_kernel<TZ, RPV, VV, true>, grid, dim3(256), sh, s, rs, (const TZ*)Z, Af, \
+                   invlamA, Bf, invlamB, Vinv, lam_div, U, sU);                                \
     else                                                                                       \
-      timed_launch(p3_kernel<TZ, RPV, VV, false>, grid, dim3(256), sh, s, rs, (const TZ*)Z, Af, invlamA, Bf,   \
-                                                          invlamB, Vinv, lam_div, U, sU);      \
+      timed_launch(p3_kernel<TZ, RPV, VV, false>, grid, dim3(256), sh, s, rs, (const TZ*)Z, Af,\
+                   invlamA, Bf, invlamB, Vinv, lam_div, U, sU);                                \
   } while (0)
   SBT_RP_SWITCH(rs.R, {
     if (prec == kF64) {

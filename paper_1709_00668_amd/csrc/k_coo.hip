@@ -194,9 +194,10 @@ __device__ inline uint64_t wave_or(uint64_t m) {
 }
 
 // Emit the kept entries of every repetition in store order (hence sorted by
-// c) at bbase[rep][block] + the rank within the block.  Each wavefront owns a contiguous run of
-// kCooPerThread * 64 of the block's entries.  A first pass counts, per wavefront and repetition, the kept
-// entries (masks stay in registers); after one block barrier every wavefront
+// c) at bbase[rep][block] + the rank within the block.  Each wavefront owns a
+// contiguous run of kCooPerThread * 64 of the block's entries.  A first pass
+// counts, per wavefront and repetition, the kept entries (masks stay in
+// registers); after one block barrier every wavefront
 // knows where its entries of each repetition start and writes them in store
 // order with ballots alone.
 __global__ __launch_bounds__(kCooBlock) void summary_emit_kernel(
@@ -686,8 +687,8 @@ hipError_t launch_coo_ingest(const int32_t* bi, const int32_t* bj, const int32_t
   if (e != hipSuccess) return e;
   e = launch_fill_u32(w.hist, Knew, 0, s);
   if (e != hipSuccess) return e;
-  coo_place_kernel<<<grid_for(n, 256 * 16), 256, 0, s>>>(bi, bj, bk, bv, w.val_out, n, Knew, Kold, si,
-                                                          sj, sk, sv, base, w.hist);
+  coo_place_kernel<<<grid_for(n, 256 * 16), 256, 0, s>>>(bi, bj, bk, bv, w.val_out, n, Knew,
+                                                          Kold, si, sj, sk, sv, base, w.hist);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   scan_to_offsets_kernel<<<1, 1024, 0, s>>>(w.hist, 0, Knew, base, nullptr, koff + Kold, 0);
@@ -848,13 +849,11 @@ hipError_t launch_coo_units(const RepSet& rs, int mode, const CooSummary& z, con
   const unsigned blocks = (unsigned)(kXcds * ((per + G - 1) / G));
   SBT_COO_RP(rs.R, {
     if (wide)
-      timed_launch(coo_units_kernel<RP, 64>, blocks, dim3(256), 0, s, rs, m.rows, rowsX, rowsY, u.urow,
-                                                      u.ustart, u.ulen, u.uoff + n, u.cap, m.cx,
-                                                      m.cy, m.cv, Xf, Yf, part);
+      timed_launch(coo_units_kernel<RP, 64>, blocks, dim3(256), 0, s, rs, m.rows, rowsX, rowsY,
+                   u.urow, u.ustart, u.ulen, u.uoff + n, u.cap, m.cx, m.cy, m.cv, Xf, Yf, part);
     else
-      timed_launch(coo_units_kernel<RP, 32>, blocks, dim3(256), 0, s, rs, m.rows, rowsX, rowsY, u.urow,
-                                                      u.ustart, u.ulen, u.uoff + n, u.cap, m.cx,
-                                                      m.cy, m.cv, Xf, Yf, part);
+      timed_launch(coo_units_kernel<RP, 32>, blocks, dim3(256), 0, s, rs, m.rows, rowsX, rowsY,
+                   u.urow, u.ustart, u.ulen, u.uoff + n, u.cap, m.cx, m.cy, m.cv, Xf, Yf, part);
   });
   return hipGetLastError();
 }

@@ -444,11 +444,11 @@ hipError_t launch_gather_mfma(int store_prec, const void* X, int64_t I, int64_t 
   const int cg0 = c0 / 8;  // groups of 8 slices, the first one gathered whole
   dim3 grid((unsigned)((n12 + 255) / 256), (unsigned)(kp32 / 8 - cg0), (unsigned)rs.nrep);
   if (store_prec == kF64)
-    timed_launch(gather_mfma_kernel<double>, grid, dim3(256), 0, s, (const double*)X, I, J, idx, idx_stride, offJ,
-                                                    offK, n3old, Kold, cg0, rs, L, Zk, Zc);
+    timed_launch(gather_mfma_kernel<double>, grid, dim3(256), 0, s, (const double*)X, I, J, idx,
+                 idx_stride, offJ, offK, n3old, Kold, cg0, rs, L, Zk, Zc);
   else
-    timed_launch(gather_mfma_kernel<float>, grid, dim3(256), 0, s, (const float*)X, I, J, idx, idx_stride, offJ,
-                                                   offK, n3old, Kold, cg0, rs, L, Zk, Zc);
+    timed_launch(gather_mfma_kernel<float>, grid, dim3(256), 0, s, (const float*)X, I, J, idx,
+                 idx_stride, offJ, offK, n3old, Kold, cg0, rs, L, Zk, Zc);
   return hipGetLastError();
 }
 
