@@ -17,6 +17,8 @@ rng       Philox4x32-10, 53-bit uniforms, the basic-operation logarithm.
 cp        unfoldings, Khatri-Rao, MTTKRP, normal-equation solve, CP-ALS, fit.
 sambaten  measure of importance, weighted sampling, summaries, matching,
           row solve, zero-fill, averaging: the batch update itself.
+nmode     the same update for a tensor of any order N >= 3 whose last mode
+          grows (Sec. 2 notes that the method carries over).
 """
 
 

@@ -186,3 +186,53 @@ def poisson_arrivals(n, rate, seed):
     """Arrival times (s) of a Poisson process with `rate` requests per second."""
     g = _gen(seed, STREAM_ARRIVAL)
     return np.cumsum(g.exponential(1.0 / rate, size=n))
+
+
+class DenseCPN:
+    """The N-mode analogue of DenseCP: X = sum_r U_0(:,r) o ... o U_{N-1}(:,r)
+    + N(0, sigma^2), factors U[0,1), the last mode the one that grows.
+
+    Slices along the last mode are produced in any order; sigma = noise *
+    ||X_clean||_F / sqrt(#entries) with ||X_clean||^2 in closed form.
+    """
+
+    def __init__(self, dims, R, seed, noise=0.01, dtype=np.float32):
+        self.dims = tuple(int(d) for d in dims)
+        self.R, self.seed, self.noise = int(R), int(seed), float(noise)
+        self.dtype = np.dtype(dtype)
+        g = _gen(seed, STREAM_FACTOR)
+        self.U = [g.random((d, self.R)) for d in self.dims]
+        H = np.ones((self.R, self.R))
+        for U in self.U:
+            H = H * (U.T @ U)
+        self.clean_norm2 = float(H.sum())
+        self.sigma = self.noise * np.sqrt(self.clean_norm2 / float(np.prod(self.dims)))
+
+    def slices(self, k0, k1):
+        """Last-mode slices k0..k1-1 as a Fortran-ordered array of shape
+        dims[:-1] + (k1 - k0,)."""
+        lead = self.dims[:-1]
+        # Khatri-Rao rows of the leading modes, the first mode fastest
+        K = np.ones((1, self.R))
+        for U in self.U[:-1]:  # row a * P + p: the new mode slowest
+            K = (U[:, None, :] * K[None, :, :]).reshape(-1, self.R)
+        out = np.empty(lead + (k1 - k0,), dtype=self.dtype, order="F")
+        n_lead = int(np.prod(lead))
+        for k in range(k0, k1):
+            v = K @ self.U[-1][k]
+            if self.noise > 0:
+                v = v + self.sigma * _gen(self.seed, STREAM_NOISE, k).standard_normal(n_lead)
+            out[..., k - k0] = v.reshape(lead, order="F").astype(self.dtype)
+        return out
+
+    def true_model(self):
+        """Unit-column factors and lambda, ordered by lambda descending."""
+        norms = [np.linalg.norm(U, axis=0) for U in self.U]
+        lam = np.prod(norms, axis=0)
+        order = np.argsort(-lam, kind="stable")
+        return [U[:, order] / n[order] for U, n in zip(self.U, norms)], lam[order]
+
+    def true_model_prefix(self, K0):
+        """true_model() with the last factor cut to its first K0 rows."""
+        Us, lam = self.true_model()
+        return Us[:-1] + [Us[-1][:K0].copy()], lam
