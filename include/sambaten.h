@@ -300,6 +300,78 @@ sbt_status sbt_server_drain(sbt_server* s);
 /* Drain, stop the workers and release the staging pool. */
 void sbt_server_destroy(sbt_server* s);
 
+/* --------------------------------------------------------------------------
+ * Tensors of order N, 3 <= N <= 8, whose last mode grows (Sec. 2: the
+ * problem and the method carry over to any number of modes).
+ *
+ * A dense order-N tensor is column-major: element (i_0, ..., i_N-1) of a
+ * D_0 x ... x D_N-1 tensor sits at i_0 + D_0*(i_1 + D_1*(...)), so a batch of
+ * last-mode slices is one contiguous block.  Factor m crossing the ABI is a
+ * row-major D_m x R double array.  The handle is an sbt_tensor: it takes
+ * sbt_update_batch_dense (a batch of K_new last-mode slices, element type
+ * per cfg->precision), sbt_fit, sbt_last_sample (mode 0..N-1),
+ * sbt_get_batch_counter, sbt_profile_* and sbt_destroy; the third-order
+ * calls sbt_get_shape, sbt_get_factors, sbt_update_batch_coo, sbt_fms and
+ * sbt_last_rep return SBT_E_STATE on it, and a server refuses it.
+ *
+ * An update follows Algorithm 1 with N - 1 fixed modes: the importance of
+ * every mode (Eq. 1, exact integer sums); per repetition and mode,
+ * n_m = ceil(D_m / s_m) indices drawn by the same sampler as for three modes
+ * (Philox tag mode field m + 1; the last mode among the existing slices);
+ * summaries X(S_0, ..., S_N-2, K_s u new); CP-ALS over modes 0..N-1 with U_1
+ * ... U_N-1 drawn U[0,1) (tag mode field m + 1); similarity = product over
+ * all N modes of |cosine| with the anchors, maximum-weight assignment, signs
+ * and scales from the fixed modes; the summary's last-mode rows by least
+ * squares against the Khatri-Rao product of the matched fixed-mode factors,
+ * divided by lambda; zero fill of every fixed-mode factor and of the last
+ * factor's anchor rows; new rows averaged over the valid repetitions.  At
+ * N = 3 it computes what the third-order update computes (plain schedule).
+ *
+ * Supported: cfg->format SBT_DENSE, cfg->precision SBT_P_F64 or SBT_P_F32
+ * (store, summaries and MTTKRP in that type; everything else FP64),
+ * getrank_runs 0, persist_summaries 0.  cfg->schedule is not read and
+ * cfg->sample_factor is replaced by the per-mode factors below (its entries
+ * must still be >= 1).
+ * ------------------------------------------------------------------------ */
+
+/* Create an order-N tensor from the dense block X0_dev (device, extents
+ * dims[0..N-1], dims[N-1] = K0 existing slices).  sample_factor: N host
+ * int32 values >= 1.  factors: NULL, or N host pointers to the row-major
+ * factors (last one K0 x R) with lambda0 (R host doubles); both NULL runs
+ * cfg->init_iters CP-ALS sweeps on X0 (U_1 ... U_N-1 drawn U[0,1)) and orders
+ * the components by lambda.  SBT_E_SHAPE when the product of the fixed
+ * extents, or a summary, exceeds 2^31 - 1 entries, or cfg->k_capacity <= K0. */
+sbt_status sbt_nd_init_dense(const sbt_config* cfg, int32_t order, const int64_t* dims,
+                             const int32_t* sample_factor, const void* X0_dev,
+                             const double* const* factors, const double* lambda0, void* stream,
+                             sbt_tensor** out);
+
+/* Order, extents (N int64 written; the last is the current slice count) and rank. */
+sbt_status sbt_nd_get_shape(const sbt_tensor* t, int32_t* order, int64_t* dims, int32_t* R);
+
+/* Copy factor `mode` (D_mode x R, row-major) or lambda (R) to host memory. */
+sbt_status sbt_nd_get_factor(sbt_tensor* t, int32_t mode, double* U, void* stream);
+sbt_status sbt_nd_get_lambda(sbt_tensor* t, double* lambda, void* stream);
+
+/* Intermediates of repetition `rep` of the last update, as doubles:
+ *   SBT_ND_REP_UP    summary factor of `mode` (rows: n_mode, the last mode K')
+ *   SBT_ND_REP_UT    matched, sign-fixed, rescaled factor of a fixed mode
+ *   SBT_ND_REP_CT    the summary's last-mode rows from the row solve (K' x R)
+ *   SBT_ND_REP_LAMP  lambda of the summary's decomposition (R)
+ *   SBT_ND_REP_PI    summary column matched to each model column (R)
+ *   SBT_ND_REP_VALID 1 where the component counts in the averages (R)
+ * *n_out = values written; SBT_E_SHAPE when max_values is too small. */
+enum {
+  SBT_ND_REP_UP = 0,
+  SBT_ND_REP_UT = 1,
+  SBT_ND_REP_CT = 2,
+  SBT_ND_REP_LAMP = 3,
+  SBT_ND_REP_PI = 4,
+  SBT_ND_REP_VALID = 5
+};
+sbt_status sbt_nd_last_rep(const sbt_tensor* t, int32_t rep, int32_t item, int32_t mode,
+                           double* out, int64_t max_values, int64_t* n_out);
+
 /* Human-readable text for a status, and the last error message of a tensor. */
 const char* sbt_status_str(sbt_status s);
 const char* sbt_last_error(const sbt_tensor* t);

@@ -11,6 +11,7 @@
 // back one status word at the end.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -27,6 +28,9 @@ using namespace sbt;
 
 // launch shapes whose CP-ALS sweep graphs a tensor keeps
 constexpr size_t kGraphCache = 8;
+
+struct NdState;  // tensors of order N (the N-mode part of this file)
+struct NdWork;
 
 struct sbt_tensor {
   sbt_config cfg{};
@@ -109,6 +113,9 @@ struct sbt_tensor {
   int64_t prof_n[SBT_K_COUNT] = {};
   double prof_ms[SBT_K_COUNT] = {};
   double prof_b[SBT_K_COUNT] = {};
+  // tensors of order N created by sbt_nd_init_dense (null otherwise)
+  NdState* nd = nullptr;
+  NdWork* nd_work = nullptr;
   // last update, for the inspection calls
   bool has_last = false;
   int last_n3old = 0, last_Kp = 0;
@@ -1028,7 +1035,7 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
   const int n3old = reuse ? t->n3kept : (int)sample_size(Kold, c.sample_factor[2]);
   const int Kp = n3old + (int)Kn;
   // sampling (from the tensor before the update)
-  SampleArgs sa;
+  SampleArgs sa{};
   sa.w[0] = t->w1;
   sa.w[1] = t->w2;
   sa.w[2] = t->w3;
@@ -1235,6 +1242,17 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
   return SBT_OK;
 }
 
+// tensors of order N: the N-mode part at the end of this file
+sbt_status nd_update(sbt_tensor* t, const void* Y_dev, int64_t Kn, hipStream_t st);
+sbt_status nd_fit(sbt_tensor* t, double* fit, hipStream_t st);
+void nd_release(sbt_tensor* t);
+bool nd_sample_span(const sbt_tensor* t, int mode, int64_t* off, int64_t* cnt);
+
+sbt_status not_for_nd(sbt_tensor* t) {
+  set_err(t, "tensor of order N: use the sbt_nd_* calls");
+  return SBT_E_STATE;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1423,11 +1441,13 @@ void sbt_destroy(sbt_tensor* t) {
   if (!t) return;
   (void)hipDeviceSynchronize();
   free_all(t);
+  nd_release(t);
   delete t;
 }
 
 sbt_status sbt_update_batch_dense(sbt_tensor* t, const void* Y_dev, int64_t K_new, void* stream) {
   if (!t || !Y_dev) return SBT_E_INVALID;
+  if (t->nd) return nd_update(t, Y_dev, K_new, (hipStream_t)stream);
   if (t->fmt != SBT_DENSE) {
     set_err(t, "tensor is not dense");
     return SBT_E_STATE;
@@ -1456,6 +1476,7 @@ sbt_status sbt_update_batch_coo(sbt_tensor* t, const int32_t* i_dev, const int32
                                 const int32_t* k_dev, const float* v_dev, int64_t nnz,
                                 int64_t K_new, void* stream) {
   if (!t) return SBT_E_INVALID;
+  if (t->nd) return not_for_nd(t);
   if (t->fmt != SBT_COO) {
     set_err(t, "tensor is not COO");
     return SBT_E_STATE;
@@ -1493,6 +1514,7 @@ sbt_status sbt_update_batch_coo(sbt_tensor* t, const int32_t* i_dev, const int32
 
 sbt_status sbt_get_shape(const sbt_tensor* t, int64_t* I, int64_t* J, int64_t* K, int32_t* R) {
   if (!t) return SBT_E_INVALID;
+  if (t->nd) return SBT_E_STATE;
   if (I) *I = t->I;
   if (J) *J = t->J;
   if (K) *K = t->K;
@@ -1509,6 +1531,7 @@ sbt_status sbt_get_batch_counter(const sbt_tensor* t, uint32_t* counter) {
 sbt_status sbt_get_factors(sbt_tensor* t, double* A, double* B, double* C, double* lambda,
                            void* stream) {
   if (!t) return SBT_E_INVALID;
+  if (t->nd) return not_for_nd(t);
   hipStream_t st = (hipStream_t)stream;
   const int R = t->R;
   if (A) SBT_CK(hipMemcpyAsync(A, t->A, sizeof(double) * t->I * R, hipMemcpyDeviceToHost, st));
@@ -1522,6 +1545,7 @@ sbt_status sbt_get_factors(sbt_tensor* t, double* A, double* B, double* C, doubl
 sbt_status sbt_fit(sbt_tensor* t, double* fit, void* stream) {
   if (!t || !fit) return SBT_E_INVALID;
   hipStream_t st = (hipStream_t)stream;
+  if (t->nd) return nd_fit(t, fit, st);
   if (t->fmt == SBT_DENSE) {
     SBT_CK(launch_fit_slices(t->store_prec, t->X, t->I, t->J, t->K, t->R, t->A, t->B, t->M3,
                              t->nrm, st));
@@ -1554,6 +1578,7 @@ sbt_status sbt_fit(sbt_tensor* t, double* fit, void* stream) {
 sbt_status sbt_fms(sbt_tensor* t, const double* A_ref, const double* B_ref, const double* C_ref,
                    const double* lambda_ref, double* score, void* stream) {
   if (!t || !A_ref || !B_ref || !C_ref || !lambda_ref || !score) return SBT_E_INVALID;
+  if (t->nd) return not_for_nd(t);
   hipStream_t st = (hipStream_t)stream;
   XProd xp{};
   const int I = (int)t->I, J = (int)t->J, K = (int)t->K;
@@ -1589,11 +1614,12 @@ sbt_status sbt_fms(sbt_tensor* t, const double* A_ref, const double* B_ref, cons
 sbt_status sbt_last_sample(const sbt_tensor* tc, int32_t rep, int32_t mode, int32_t* idx,
                            int64_t* n) {
   sbt_tensor* t = const_cast<sbt_tensor*>(tc);
-  if (!t || !idx || !n || mode < 0 || mode > 2) return SBT_E_INVALID;
+  if (!t || !idx || !n || mode < 0 || (mode > 2 && !t->nd)) return SBT_E_INVALID;
   if (!t->has_last) return SBT_E_STATE;
   if (rep < 0 || rep >= t->cfg.repetitions) return SBT_E_INVALID;
-  const int64_t cnt = mode == 0 ? t->n1 : (mode == 1 ? t->n2 : t->last_n3old);
-  const int64_t off = mode == 0 ? 0 : (mode == 1 ? t->n1 : (int64_t)t->n1 + t->n2);
+  int64_t cnt = mode == 0 ? t->n1 : (mode == 1 ? t->n2 : t->last_n3old);
+  int64_t off = mode == 0 ? 0 : (mode == 1 ? t->n1 : (int64_t)t->n1 + t->n2);
+  if (t->nd && !nd_sample_span(t, mode, &off, &cnt)) return SBT_E_INVALID;
   SBT_CK(hipMemcpy(idx, t->idx + rep * t->idx_stride + off, sizeof(int32_t) * cnt,
                    hipMemcpyDeviceToHost));
   *n = cnt;
@@ -1604,6 +1630,7 @@ sbt_status sbt_last_rep(const sbt_tensor* tc, int32_t rep, int32_t item, double*
                         int64_t cap, int64_t* rows) {
   sbt_tensor* t = const_cast<sbt_tensor*>(tc);
   if (!t || !out || !rows) return SBT_E_INVALID;
+  if (t->nd) return not_for_nd(t);
   if (!t->has_last) return SBT_E_STATE;
   if (rep < 0 || rep >= t->cfg.repetitions) return SBT_E_INVALID;
   const int R = t->R;
@@ -1760,9 +1787,11 @@ sbt_status sbt_mttkrp_dense(int32_t precision, const void* Z_dev, int64_t n1, in
 
 }  // extern "C"
 
+#include "engine_nd.inc"
+
 namespace sbt {
 size_t store_elem_bytes(const sbt_tensor* t) {
-  if (!t || t->fmt != SBT_DENSE) return 0;
+  if (!t || t->fmt != SBT_DENSE || t->nd) return 0;
   return prec_bytes(t->store_prec);
 }
 }  // namespace sbt

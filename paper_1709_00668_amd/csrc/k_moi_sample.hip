@@ -163,6 +163,74 @@ __global__ __launch_bounds__(256) void moi_coo_kernel(const int32_t* ii, const i
 }
 
 // ---------------------------------------------------------------------------
+// Importance of a dense block of order N.  The block is read as D_0 rows x
+// (D_1 ... D_N-1) columns; a wavefront takes 64 consecutive rows (one per
+// lane) of kMoiNdCols consecutive columns.  Row sums stay in the lanes; each
+// column's sum goes to every higher mode, where consecutive columns that
+// share an index are added up in registers before one atomic per run (the
+// index of mode 1 changes with every column, the last mode's rarely).
+// ---------------------------------------------------------------------------
+constexpr int kMoiNdCols = 64;
+
+template <typename T>
+__global__ __launch_bounds__(256) void moi_nd_kernel(MoiNd a) {
+  const T* X = (const T*)a.X;
+  const int N = a.N;
+  const int64_t D0 = a.D[0];
+  int64_t ncols = 1;
+  for (int m = 1; m < N; ++m) ncols *= a.D[m];
+  const int lane = lane_id();
+  const int wave = threadIdx.x >> 6;
+  const int64_t i0 = (int64_t)blockIdx.y * kWave + lane;
+  const bool in = i0 < D0;
+  const int64_t cb = ((int64_t)blockIdx.x * 4 + wave) * kMoiNdCols;
+  if (cb >= ncols) return;  // no barrier below
+  const int64_t ce = cb + kMoiNdCols < ncols ? cb + kMoiNdCols : ncols;
+  int64_t idx[kMaxOrder], cur[kMaxOrder];
+  unsigned long long run[kMaxOrder];
+  int64_t rem = cb;
+#pragma unroll
+  for (int m = 1; m < kMaxOrder; ++m) {
+    if (m < N) {
+      idx[m] = rem % a.D[m];
+      rem /= a.D[m];
+    } else {
+      idx[m] = 0;
+    }
+    cur[m] = idx[m];
+    run[m] = 0ull;
+  }
+  unsigned long long acc0 = 0ull;
+  bool bad = false;
+  for (int64_t c = cb; c < ce; ++c) {
+    const uint64_t q = in ? quantize_sq((double)X[i0 + D0 * c], a.scale, a.qmax, bad) : 0ull;
+    acc0 += q;
+    const unsigned long long col = wave_sum_u64(q);
+#pragma unroll
+    for (int m = 1; m < kMaxOrder; ++m) {
+      if (m < N) {
+        if (idx[m] != cur[m]) {
+          if (lane == 0 && run[m]) atomicAdd((unsigned long long*)&a.w[m][cur[m]], run[m]);
+          cur[m] = idx[m];
+          run[m] = 0ull;
+        }
+        run[m] += col;
+      }
+    }
+    // next column's indices (mode 1 fastest)
+    for (int m = 1; m < N; ++m) {
+      if (++idx[m] < a.D[m]) break;
+      idx[m] = 0;
+    }
+  }
+#pragma unroll
+  for (int m = 1; m < kMaxOrder; ++m)
+    if (m < N && lane == 0 && run[m]) atomicAdd((unsigned long long*)&a.w[m][cur[m]], run[m]);
+  if (in && acc0) atomicAdd((unsigned long long*)&a.w[0][i0], acc0);
+  if (bad) atomicOr(a.err, 1u);
+}
+
+// ---------------------------------------------------------------------------
 // Sampler
 // ---------------------------------------------------------------------------
 constexpr int kSampleThreads = 1024;
@@ -183,7 +251,7 @@ __global__ __launch_bounds__(kSampleThreads) void sample_kernel(SampleArgs a, ui
   uint64_t* keys = keys_all + rep * a.key_stride + a.key_off[m];
   int32_t* out = idx_all + rep * a.idx_stride + a.idx_off[m];
   const RngKey key = rng_key(a.seed, a.tensor_id);
-  const uint32_t tag = rng_tag(kStreamSample, (uint32_t)(m + 1), (uint32_t)rep);
+  const uint32_t tag = rng_tag(kStreamSample, (uint32_t)(a.mode0 + m + 1), (uint32_t)rep);
 
   // 1. keys kappa_i = -ln(U_i) / double(w_i), +inf for w_i == 0
   for (int64_t i = tid; i < N; i += kSampleThreads) {
@@ -339,9 +407,29 @@ hipError_t launch_moi_coo(const int32_t* ii, const int32_t* jj, const int32_t* k
   return hipGetLastError();
 }
 
+hipError_t launch_moi_nd(int prec, const MoiNd& a, hipStream_t s) {
+  if (a.N < 2 || a.N > kMaxOrder) return hipErrorInvalidValue;
+  int64_t ncols = 1;
+  for (int m = 0; m < a.N; ++m) {
+    if (a.D[m] <= 0) return hipSuccess;
+    if (m > 0) ncols *= a.D[m];
+  }
+  const int64_t chunks = (ncols + 4 * kMoiNdCols - 1) / (4 * kMoiNdCols);
+  const int64_t tiles = (a.D[0] + kWave - 1) / kWave;
+  if (chunks > 0x7FFFFFFF || tiles > 65535) return hipErrorInvalidValue;
+  dim3 grid((unsigned)chunks, (unsigned)tiles);
+  if (prec == kF64)
+    moi_nd_kernel<double><<<grid, 256, 0, s>>>(a);
+  else
+    moi_nd_kernel<float><<<grid, 256, 0, s>>>(a);
+  return hipGetLastError();
+}
+
 hipError_t launch_sample(const SampleArgs& a, uint64_t* keys, int32_t* idx, hipStream_t s) {
   if (a.nrep <= 0) return hipSuccess;
-  sample_kernel<<<dim3((unsigned)a.nrep, 3), kSampleThreads, 0, s>>>(a, keys, idx);
+  const int modes = a.nmodes > 0 ? a.nmodes : 3;
+  if (modes > 3 || a.mode0 < 0) return hipErrorInvalidValue;
+  sample_kernel<<<dim3((unsigned)a.nrep, (unsigned)modes), kSampleThreads, 0, s>>>(a, keys, idx);
   return hipGetLastError();
 }
 

@@ -90,6 +90,8 @@ struct SampleArgs {
   uint32_t tensor_id;
   uint32_t t;
   int nrep;
+  int nmodes;  // modes in this launch (0 = 3)
+  int mode0;   // index of the first one (its Philox tag carries mode0 + 1)
 };
 hipError_t launch_sample(const SampleArgs& a, uint64_t* keys, int32_t* idx, hipStream_t s);
 
@@ -409,5 +411,116 @@ hipError_t launch_fit_final(const double* G3, const double* C, const double* lam
 // Order components by lam descending (ties: lower index first) in place.
 hipError_t launch_sort_components(double* A, double* B, double* C, double* lam, int64_t I,
                                   int64_t J, int64_t K, int R, hipStream_t s);
+
+// ---- tensors of order N (last mode growing) ----------------------------------
+constexpr int kMaxOrder = 8;
+
+// importance of a dense block of order N (extents D, column-major): w[m][i]
+// += sum of q(x) over the entries whose m-th index is i, for every mode.
+struct MoiNd {
+  const void* X;
+  int N;
+  int64_t D[kMaxOrder];
+  uint64_t* w[kMaxOrder];
+  double scale;
+  uint64_t qmax;
+  uint32_t* err;
+};
+hipError_t launch_moi_nd(int prec, const MoiNd& a, hipStream_t s);
+
+// Rows of several factors per repetition (row-major, R columns):
+// U[m] + rep * sU[m], n[m] rows.
+struct NdFactors {
+  double* U[kMaxOrder];
+  int64_t sU[kMaxOrder];
+  int n[kMaxOrder];
+};
+
+// Khatri-Rao rows of modes [lo, hi): out(p, f) = prod_l U_l(a_l, f) with
+// p = a_lo + n_lo * (a_lo+1 + ...), per repetition at out + rep * sOut.
+hipError_t launch_krp_nd(const NdFactors& F, int lo, int hi, int R, int rep0, int nrep,
+                         double* out, int64_t sOut, hipStream_t s);
+// out = Hadamard product of the Gram matrices G + m * sMode (per repetition
+// stride sG) of the modes in `mask` (all ones when empty).
+hipError_t launch_hadamard_nd(const double* G, int64_t sMode, int64_t sG, uint32_t mask, int N,
+                              int R, int rep0, int nrep, double* out, hipStream_t s);
+// U[0,1) initial factors of modes 1..N-1: entry (row, col) of mode m from
+// Philox counter (row, col, tag(stream, m + 1, rep), t).
+hipError_t launch_als_init_nd(const NdFactors& F, int N, int R, int rep0, int nrep,
+                              uint64_t seed, uint32_t tensor_id, uint32_t stream, uint32_t t,
+                              hipStream_t s);
+
+// Summary of order N: Z[rep](a_0, ..., a_N-1) = X(S_0[a_0], ..., K'[a_N-1]),
+// S_m at idx + rep * idx_stride + off[m]; K'[c] = S_N-1[c] for c < n3old,
+// Kold + c - n3old after.
+struct GatherNd {
+  const void* X;
+  int N;
+  int64_t D[kMaxOrder];  // store extents (last one unused)
+  int n[kMaxOrder];      // summary extents
+  const int32_t* idx;
+  int64_t idx_stride;
+  int64_t off[kMaxOrder];
+  int n3old;
+  int64_t Kold;
+  int rep0, nrep;
+  void* Z;
+  int64_t sZ;
+};
+hipError_t launch_gather_nd(int prec, const GatherNd& g, hipStream_t s);
+
+// R x R cross products X^T Y over `rows` rows, one block per (job, repetition):
+// X rows X + rep * sX + (ix ? ix[rep * six + i] : i) * R, Y likewise; result
+// at out + (rep * njobs + job) * R * R.
+constexpr int kCrossJobs = 3 * kMaxOrder;
+struct CrossNd {
+  XJob job[kCrossJobs];
+  int njobs, R, rep0, nrep;
+  double* out;
+};
+hipError_t launch_cross_nd(const CrossNd& c, hipStream_t s);
+
+// Matching over N modes from the cross products of CrossNd laid out per mode
+// as (anchor^T sample, anchor^T anchor, sample^T sample): similarity = product
+// of |cosine| over the modes, assignment, signs and scales of the fixed modes
+// (scl[rep][m][f]), validity and Gt = prod over fixed modes of the matched
+// Gram matrices.
+struct MatchNd {
+  const double* xo;
+  int N, R, rep0, nrep;
+  double* scl;      // [rep][kMaxOrder][R]
+  int32_t *pi, *valid;
+  double* Gt;       // [rep][R * R]
+};
+hipError_t launch_match_nd(const MatchNd& m, hipStream_t s);
+// Ut_m(a, f) = scl_m(f) Up_m(a, pi(f)) for the fixed modes
+hipError_t launch_match_rows_nd(const NdFactors& Up, const NdFactors& Ut, int N, int R,
+                                int rep0, int nrep, const double* scl, const int32_t* pi,
+                                hipStream_t s);
+
+// Zero fill of the fixed-mode factors and of the last factor's sampled rows,
+// the new rows of the last factor (average over the valid repetitions) and
+// the importance commit; nothing is written when *err != 0.
+struct CommitNd {
+  const uint32_t* err;
+  int N, R, nrep;
+  double* U[kMaxOrder];      // model (last factor: Kcap rows)
+  int64_t D[kMaxOrder];      // fixed extents; D[N-1] = Kold
+  int64_t Knew;
+  const int32_t* idx;
+  int64_t idx_stride;
+  int64_t off[kMaxOrder];
+  int n[kMaxOrder];          // sample sizes (last: n3old)
+  const double* Ut[kMaxOrder];
+  int64_t sUt[kMaxOrder];
+  const double* Ct;          // per repetition Kp x R
+  int64_t sCt;
+  const int32_t* valid;
+  uint64_t* w[kMaxOrder];    // importance (last: Kcap entries)
+  const uint64_t* dw[kMaxOrder];
+};
+hipError_t launch_commit_nd(const CommitNd& c, hipStream_t s);
+// components ordered by lam descending (ties: lower index first), every factor
+hipError_t launch_sort_nd(const NdFactors& F, int N, int R, double* lam, hipStream_t s);
 
 }  // namespace sbt

@@ -89,6 +89,12 @@ _SIGS = {
                                        ctypes.POINTER(ctypes.c_int), _pd, _pd, _pd]),
     "sbt_server_drain": (ctypes.c_int, [_vp]),
     "sbt_server_destroy": (None, [_vp]),
+    "sbt_nd_init_dense": (ctypes.c_int, [ctypes.POINTER(sbt_config), _i32, _vp, _vp, _vp, _vp,
+                                         _vp, _vp, ctypes.POINTER(_vp)]),
+    "sbt_nd_get_shape": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), _vp, ctypes.POINTER(_i32)]),
+    "sbt_nd_get_factor": (ctypes.c_int, [_vp, _i32, _vp, _vp]),
+    "sbt_nd_get_lambda": (ctypes.c_int, [_vp, _vp, _vp]),
+    "sbt_nd_last_rep": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _i64, ctypes.POINTER(_i64)]),
     "sbt_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "sbt_last_error": (ctypes.c_char_p, [_vp]),
 }
@@ -317,6 +323,87 @@ class Tensor:
         _check(load().sbt_last_rep(self.h, rep, item, buf.ctypes.data, cap, ctypes.byref(rows)),
                self.h, "sbt_last_rep")
         return buf[:rows.value * nc].reshape(rows.value, nc).copy()
+
+
+SBT_ND_REP_UP, SBT_ND_REP_UT, SBT_ND_REP_CT, SBT_ND_REP_LAMP, SBT_ND_REP_PI, SBT_ND_REP_VALID = \
+    range(6)
+
+
+def dense_nd_to_device(X, dtype):
+    """Order-N array -> device tensor whose memory is the column-major layout
+    the library expects (first index fastest)."""
+    import torch
+    X = np.asarray(X, dtype=dtype)
+    arr = np.ascontiguousarray(X.transpose(tuple(range(X.ndim - 1, -1, -1))))
+    return torch.from_numpy(arr).cuda()
+
+
+class TensorN(Tensor):
+    """An order-N tensor (sbt_nd_*); the last mode grows."""
+
+    @classmethod
+    def init_dense_nd(cls, cfg, X0_dev, dims, sample_factor, factors=None, lam=None,
+                      stream=None):
+        lib = load()
+        N = len(dims)
+        d = np.ascontiguousarray(dims, dtype=np.int64)
+        s = (sample_factor,) * N if np.isscalar(sample_factor) else tuple(sample_factor)
+        sf = np.ascontiguousarray(s, dtype=np.int32)
+        keep = []
+        fptr = None
+        lptr = None
+        if factors is not None:
+            arrs = [np.ascontiguousarray(f, dtype=np.float64) for f in factors]
+            keep.extend(arrs)
+            fptr = (ctypes.c_void_p * N)(*[a.ctypes.data for a in arrs])
+            la = np.ascontiguousarray(lam, dtype=np.float64)
+            keep.append(la)
+            lptr = la.ctypes.data
+        out = _vp()
+        st = lib.sbt_nd_init_dense(ctypes.byref(cfg), N, d.ctypes.data, sf.ctypes.data,
+                                   _ptr(X0_dev), ctypes.cast(fptr, _vp) if fptr else None, lptr,
+                                   _stream(stream), ctypes.byref(out))
+        _check(st, None, "sbt_nd_init_dense")
+        return cls(out.value)
+
+    def shape_nd(self):
+        order, R = _i32(), _i32()
+        dims = np.zeros(8, dtype=np.int64)
+        _check(load().sbt_nd_get_shape(self.h, ctypes.byref(order), dims.ctypes.data,
+                                       ctypes.byref(R)), self.h, "sbt_nd_get_shape")
+        return [int(v) for v in dims[:order.value]], R.value
+
+    def get_factors_nd(self, stream=None):
+        dims, R = self.shape_nd()
+        out = []
+        for m, D in enumerate(dims):
+            U = np.empty((D, R))
+            _check(load().sbt_nd_get_factor(self.h, m, U.ctypes.data, _stream(stream)), self.h,
+                   "sbt_nd_get_factor")
+            out.append(U)
+        lam = np.empty(R)
+        _check(load().sbt_nd_get_lambda(self.h, lam.ctypes.data, _stream(stream)), self.h,
+               "sbt_nd_get_lambda")
+        return out, lam
+
+    def last_sample(self, rep, mode):
+        dims, R = self.shape_nd()
+        buf = np.empty(max(dims) + 1, dtype=np.int32)
+        n = _i64()
+        _check(load().sbt_last_sample(self.h, rep, mode, buf.ctypes.data, ctypes.byref(n)),
+               self.h, "sbt_last_sample")
+        return buf[:n.value].copy()
+
+    def last_rep_nd(self, rep, item, mode=0, max_rows=1 << 20):
+        dims, R = self.shape_nd()
+        cap = (max_rows + 1) * R
+        buf = np.empty(cap)
+        n = _i64()
+        _check(load().sbt_nd_last_rep(self.h, rep, item, mode, buf.ctypes.data, cap,
+                                      ctypes.byref(n)), self.h, "sbt_nd_last_rep")
+        v = buf[:n.value].copy()
+        return v if item in (SBT_ND_REP_LAMP, SBT_ND_REP_PI, SBT_ND_REP_VALID) else \
+            v.reshape(-1, R)
 
 
 def mttkrp_dense(precision, Z_dev, n1, n2, n3, R, U0_dev, U1_dev, U2_dev, mode, out_dev,
