@@ -12,6 +12,10 @@ before timing, the model starting from the generator's factors):
   dense2000   dense 2000 x 2000 x 1000, rank 20, batches of 100 slices, s = 5,
               r = 10, 30 sweeps: batched BF16 (matrix cores) = `value`, batched
               FP32 and plain FP32 beside it.
+  dense4d     dense FP32 order-4 120 x 120 x 120 x 120 (the last mode grows),
+              rank-10 U[0,1) CP model plus 1% noise, batches of 12 slices; s = 4
+              on every mode, r = 10, 30 ALS sweeps.  `value` is the FP32 path; the
+              FP64 path beside it; recompute: CP-ALS of the whole grown tensor.
   sparse100k  COO 100000^3 with about 1e8 nonzeros (Zipf 1.1 popularity,
               rank-10 nonnegative model), batches of 1000 slices with about
               1e6 nonzeros, s = 10, r = 10, 30 sweeps.
@@ -74,6 +78,10 @@ WORKLOADS = {
                     desc="serving: 16 resident dense FP32 tensors (I, J uniform in [200, 2000], "
                          "K0 in [100, 1000], rank 5-20), 512 update requests of 5-100 slices, "
                          "s=5, r=10, 30 ALS sweeps, 4 concurrent slots"),
+    "dense4d": dict(kind="nd", dims=(120, 120, 120), K0=120, Kn=12, R=10, s=4, r=10, iters=30,
+                    seed=6, noise=0.01,
+                    desc="dense FP32 order-4 120x120x120x120 + 12-slice batches along the last "
+                         "mode, rank 10, s=4 per mode, r=10, 30 ALS sweeps"),
     "sparse100k": dict(kind="coo", I=100000, J=100000, K0=100000, Kn=1000, R=10, s=10,
                        r=10, iters=30, seed=3, nnz0=100_000_000, nnz_b=1_000_000,
                        desc="sparse COO 100000^3 with 1e8 nonzeros + 1000-slice batches of "
@@ -86,10 +94,12 @@ KIND_NAMES = ("mttkrp_contract_c", "mttkrp_third_mode", "row_solve", "gather", "
               "update")
 
 
-def kernel_of(step, path, R, coo_row_nnz=0.0):
+def kernel_of(step, path, R, coo_row_nnz=0.0, n1_third=0):
     """HIP kernel behind a timed launch kind (coo_row_nnz: summary entries per
-    row, which picks the sparse kernel's lanes per unit)."""
+    row, which picks the sparse kernel's lanes per unit; n1_third: first extent
+    of the order-N third-mode view, which picks the fused pass's vector width)."""
     rp = (R + 3) // 4 * 4
+    v3 = 4 if n1_third % 4 == 0 and rp <= 16 else (2 if n1_third % 2 == 0 else 1)
     ul = 64 if coo_row_nnz >= 128.0 else 32
     nt = 1 if R <= 16 else 2
     table = {
@@ -102,6 +112,10 @@ def kernel_of(step, path, R, coo_row_nnz=0.0):
                  "row_solve": f"p3_mfma_kernel<{nt}> + mode3_finish_kernel",
                  "gather": "gather_mfma_kernel<float>"},
         "coo": {"coo_mttkrp": f"coo_units_kernel<{rp}, {ul}>", "gather": "summary_emit_kernel"},
+        "nd_f32": {"mttkrp_contract_c": f"p1s_kernel<float, {rp}>",
+                   "mttkrp_third_mode": f"p3_kernel<float, {rp}, {v3}, false>",
+                   "row_solve": f"p3_kernel<float, {rp}, {v3}, false>",
+                   "gather": "gather_nd_kernel<float>"},
     }
     return table.get(path, {}).get(step, step)
 
@@ -232,7 +246,7 @@ def committed_traffic(kernel, key):
     return None
 
 
-def roofline_of(prof, path, R, key, summary_rows=0):
+def roofline_of(prof, path, R, key, summary_rows=0, n1_third=0):
     kernels = {k: v for k, v in prof.items() if k != "update" and v["launches"]}
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     d = kernels[dom]
@@ -241,7 +255,7 @@ def roofline_of(prof, path, R, key, summary_rows=0):
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     # sparse: 12 B per summary entry; entries per row over all repetitions' rows
     row_nnz = bytes_per_launch / 12.0 / summary_rows if summary_rows else 0.0
-    kname = kernel_of(dom, path, R, row_nnz)
+    kname = kernel_of(dom, path, R, row_nnz, n1_third)
     return dict(bound="hbm", kernel=kname, step=dom, achieved=round(achieved, 1),
                 peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
                 traffic=committed_traffic(kname, key),
@@ -393,6 +407,97 @@ def bench_dense(args, sbt, torch, synth, log):
             line[key] = path_summary(runs[key])
     if "plain_f32" in runs:
         line["over_plain_f32"] = round(b["slices_per_s"] / runs["plain_f32"]["slices_per_s"], 3)
+    line["kernels"] = kernels_table(b["profile"])
+    return line
+
+
+def cpu_baseline_nd(w, X, model, updates):
+    """The CPU FP64 N-mode oracle on the first `updates` updates of the workload."""
+    from oracle import nmode
+    K0, Kn = w["K0"], w["Kn"]
+    N = len(w["dims"]) + 1
+    cfg = nmode.Config(rank=w["R"], reps=w["r"], als_iters=w["iters"], sample_factor=w["s"],
+                       seed=w["seed"], order=N, k_capacity=K0 + updates * Kn)
+    ora = nmode.OracleTensorN(cfg, X[..., :K0], factors=model[0], lam=model[1])
+    t0 = time.perf_counter()
+    for b in range(updates):
+        ora.update(X[..., K0 + b * Kn:K0 + (b + 1) * Kn])
+    dt = time.perf_counter() - t0
+    threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
+    return dict(value=round(updates * Kn / dt, 3), unit="slices/s", cores=int(threads),
+                kind="oracle", sample=f"the first {updates} update(s) ({Kn} slices each, "
+                                      f"r={w['r']}, {w['iters']} ALS sweeps) of the same "
+                                      f"workload, {dt:.1f} s")
+
+
+def bench_nd(args, sbt, torch, synth, log):
+    name = args.workload
+    w = WORKLOADS[name]
+    steps = args.steps
+    dims, K0, Kn, R = tuple(w["dims"]), w["K0"], w["Kn"], w["R"]
+    N = len(dims) + 1
+    K = K0 + steps * Kn
+    slice_n = int(np.prod(dims))
+    t0 = time.perf_counter()
+    gen = synth.DenseCPN(dims + (K,), R, seed=w["seed"], noise=w["noise"], dtype=np.float32)
+    X = gen.slices(0, K)
+    Xd = torch.from_numpy(X.ravel(order="F")).cuda()  # memory = column-major
+    log(f"# data ready: {'x'.join(map(str, dims + (K,)))} fp32, {X.nbytes / 1e9:.2f} GB "
+        f"({time.perf_counter() - t0:.1f} s)")
+    model = gen.true_model_prefix(K0)
+
+    def run(prec, lr):
+        cfg = sbt.make_config(R, w["r"], w["iters"], 1, w["seed"], precision=prec,
+                              k_capacity=K, max_batch=Kn)
+        Xp = Xd if prec == sbt.SBT_P_F32 else Xd.double()
+
+        def fresh():
+            return sbt.TensorN.init_dense_nd(cfg, Xp[:K0 * slice_n], dims + (K0,), w["s"],
+                                             factors=model[0], lam=model[1])
+
+        def apply_batch(T, b):
+            T.update_batch_dense(Xp[(K0 + b * Kn) * slice_n:(K0 + (b + 1) * Kn) * slice_n], Kn)
+
+        return timed_sequence(sbt, torch, fresh, apply_batch, steps, args.warmup, lr, Kn)
+
+    b = run(sbt.SBT_P_F32, args.latency_runs)
+    log(f"# nd fp32: {b['slices_per_s']:.1f} slices/s, fit {b['fit']:.6f}")
+    f64 = run(sbt.SBT_P_F64, max(1, min(args.latency_runs, 2)))
+    log(f"# nd fp64: {f64['slices_per_s']:.1f} slices/s, fit {f64['fit']:.6f}")
+    cfg = {"workload": w["desc"], "dims": list(dims), "K0": K0, "batch": Kn, "rank": R,
+           "s": w["s"], "r": w["r"], "als_iters": w["iters"]}
+    line = {
+        "metric": "updated slices/sec (p50/p99 update latency, the FP64 path alongside)",
+        "value": round(b["slices_per_s"], 2), "unit": "slices/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(b["ms_per_step"], 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic", "config": cfg, "p50_ms": round(b["p50_ms"], 3),
+        "p99_ms": round(b["p99_ms"], 3), "latency_samples": b["latency_samples"],
+        "fit": round(b["fit"], 6),
+    }
+    n0 = -(-dims[0] // w["s"])
+    line["roofline"] = roofline_of(b["profile"], "nd_f32", R, name, n1_third=n0)
+    if not args.no_recompute:
+        # relative fitness against CP-ALS recomputed on the whole grown tensor (Sec. 4.2)
+        cfg_r = sbt.make_config(R, w["r"], w["iters"], 1, w["seed"], precision=sbt.SBT_P_F32,
+                                k_capacity=K + 1, max_batch=Kn, init_iters=args.recompute_iters)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        T = sbt.TensorN.init_dense_nd(cfg_r, Xd, dims + (K,), w["s"])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        fr = T.fit()
+        T.close()
+        line["recompute"] = {"fit": round(fr, 6), "seconds": round(dt, 4),
+                             "als_sweeps": args.recompute_iters,
+                             "relative_fitness": round((1.0 - b["fit"]) / max(1e-12, 1.0 - fr),
+                                                       4)}
+        log(f"# recompute CP-ALS: fit {fr:.6f} in {dt:.2f} s")
+    # the oracle takes about 2 s per update of this workload on 8 host cores: three
+    # times --cpu-updates updates make a sample of about 10 s
+    line["cpu_baseline"] = None if args.no_cpu_baseline else \
+        cpu_baseline_nd(w, X, model, max(1, min(3 * args.cpu_updates, steps)))
+    line["fp64"] = path_summary(f64)
     line["kernels"] = kernels_table(b["profile"])
     return line
 
@@ -611,6 +716,8 @@ def main():
 
     if WORKLOADS[args.workload]["kind"] == "coo":
         line = bench_sparse(args, sbt, torch, synth, log)
+    elif WORKLOADS[args.workload]["kind"] == "nd":
+        line = bench_nd(args, sbt, torch, synth, log)
     elif WORKLOADS[args.workload]["kind"] == "serve":
         line = bench_serve(args, sbt, torch, synth, log)
     else:

@@ -293,6 +293,88 @@ __global__ __launch_bounds__(256) void sort_nd_kernel(NdFactors F, int N, int R,
     for (int f = 0; f < R; ++f) lam[f] = lam_s[perm[f]];
 }
 
+// W(e, f) = sum_q Z(e, q) C(q, f) on a three-way view (e = a + n1 b, q = c)
+// whose rows are few and whose contraction is long, as the leading-mode
+// views of an order-N summary are.  A block takes 64 consecutive rows (one
+// per lane) and one of S ranges of q; its four wavefronts split the range
+// again, each with kP1sLoads summary loads in flight, over C rows staged in
+// LDS.  The wavefronts' rows add up in LDS in wavefront order; with S > 1
+// each range writes a partial W that a second kernel sums in range order.
+constexpr int kP1sLoads = 8;
+constexpr int kP1sMaxRows = 128;  // C rows one block stages
+
+template <typename TZ> struct AccNd { using type = float; };
+template <> struct AccNd<double> { using type = double; };
+
+template <typename TZ, int RP>
+__global__ __launch_bounds__(256) void p1s_kernel(RepSet rs, const TZ* Z, const double* Cf, int S,
+                                                 typename AccNd<TZ>::type* Wp, int64_t sWp) {
+  using TA = typename AccNd<TZ>::type;
+  __shared__ TA Cs[kP1sMaxRows][RP];
+  __shared__ TA red[64][RP + 1];
+  const int rep = rs.rep0 + blockIdx.z, sp = blockIdx.y;
+  const int R = rs.R, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t n12 = (int64_t)rs.n1 * rs.n2;
+  const int Q = rs.n3;
+  const int qs = (int)((int64_t)sp * Q / S), qe = (int)((int64_t)(sp + 1) * Q / S);
+  const int L = qe - qs;  // <= kP1sMaxRows (host-chosen S)
+  const int64_t e = (int64_t)blockIdx.x * 64 + lane;
+  const bool ok = e < n12;
+  const double* C = Cf + rep * rs.sC + (int64_t)qs * R;
+  for (int q = threadIdx.x; q < L * RP; q += 256) {
+    const int r = q / RP, f = q % RP;
+    Cs[r][f] = f < R ? (TA)C[(int64_t)r * R + f] : (TA)0;
+  }
+  __syncthreads();
+  const int w0 = (wave * L) / 4, w1 = ((wave + 1) * L) / 4;
+  const TZ* zp = Z + rep * rs.sZ + (ok ? e : 0) + n12 * qs;
+  TA acc[RP];
+#pragma unroll
+  for (int f = 0; f < RP; ++f) acc[f] = 0;
+  int q = w0;
+  for (; q + kP1sLoads <= w1; q += kP1sLoads) {
+    TA z[kP1sLoads];
+#pragma unroll
+    for (int u = 0; u < kP1sLoads; ++u) z[u] = ok ? (TA)zp[n12 * (q + u)] : (TA)0;
+#pragma unroll
+    for (int u = 0; u < kP1sLoads; ++u)
+#pragma unroll
+      for (int f = 0; f < RP; ++f) acc[f] += z[u] * Cs[q + u][f];
+  }
+  for (; q < w1; ++q) {
+    const TA z = ok ? (TA)zp[n12 * q] : (TA)0;
+#pragma unroll
+    for (int f = 0; f < RP; ++f) acc[f] += z * Cs[q][f];
+  }
+  // the four wavefronts' rows, added in wavefront order
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int f = 0; f < RP; ++f) red[lane][f] = w == 0 ? acc[f] : red[lane][f] + acc[f];
+    }
+    __syncthreads();
+  }
+  if (ok) {
+    TA* out = Wp + rep * sWp + (int64_t)sp * R * n12;
+    for (int f = 0; f < R; ++f) out[f * n12 + e] = red[lane][f];
+  }
+}
+
+// W(f, e) = sum over the S ranges of the partials, in range order
+template <typename TA>
+__global__ __launch_bounds__(256) void p1s_sum_kernel(RepSet rs, int S, const TA* Wp,
+                                                     int64_t sWp, TA* W) {
+  const int rep = rs.rep0 + blockIdx.y;
+  const int64_t n = (int64_t)rs.n1 * rs.n2 * rs.R;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const TA* p = Wp + rep * sWp + i;
+    TA v = p[0];
+    for (int sp = 1; sp < S; ++sp) v += p[sp * n];
+    W[rep * rs.sW + i] = v;
+  }
+}
+
 int grid_blocks(int64_t n, int cap) {
   int64_t b = (n + 255) / 256;
   if (b < 1) b = 1;
@@ -300,6 +382,51 @@ int grid_blocks(int64_t n, int cap) {
 }
 
 }  // namespace
+
+int p1s_splits(int64_t n12, int Q, int nrep) {
+  const int64_t tiles = (n12 + 63) / 64;
+  int64_t S = (2048 + tiles * nrep - 1) / (tiles * nrep);  // about 2048 blocks
+  const int64_t most = Q / 32 > 1 ? Q / 32 : 1;             // at least 8 rows per wavefront
+  if (S > most) S = most;
+  const int64_t least = (Q + kP1sMaxRows - 1) / kP1sMaxRows;  // staged rows fit LDS
+  if (S < least) S = least;
+  if (S < 1) S = 1;
+  return (int)S;
+}
+
+hipError_t launch_p1s(int prec, const RepSet& rs, const void* Z, const double* Cf, int S,
+                      void* Wp, int64_t sWp, void* W, hipStream_t s) {
+  const int64_t n12 = (int64_t)rs.n1 * rs.n2;
+  if (S < 1 || (rs.n3 + S - 1) / S > kP1sMaxRows) return hipErrorInvalidValue;
+  void* out = S == 1 ? W : Wp;
+  const int64_t so = S == 1 ? rs.sW : sWp;
+  if (S > 1 && sWp < (int64_t)S * n12 * rs.R) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((n12 + 63) / 64), (unsigned)S, (unsigned)rs.nrep);
+  switch ((rs.R + 3) / 4 * 4) {
+#define SBT_P1S(RPV)                                                                          \
+  case RPV:                                                                                   \
+    if (prec == kF64)                                                                         \
+      timed_launch(p1s_kernel<double, RPV>, grid, dim3(256), 0, s, rs, (const double*)Z, Cf, \
+                   S, (double*)out, so);                                                      \
+    else                                                                                      \
+      timed_launch(p1s_kernel<float, RPV>, grid, dim3(256), 0, s, rs, (const float*)Z, Cf,   \
+                   S, (float*)out, so);                                                       \
+    break;
+    SBT_P1S(4) SBT_P1S(8) SBT_P1S(12) SBT_P1S(16) SBT_P1S(20) SBT_P1S(24) SBT_P1S(28)
+    SBT_P1S(32)
+#undef SBT_P1S
+    default:
+      return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || S == 1) return e;
+  dim3 g2((unsigned)grid_blocks(n12 * rs.R, 1024), (unsigned)rs.nrep);
+  if (prec == kF64)
+    p1s_sum_kernel<double><<<g2, 256, 0, s>>>(rs, S, (const double*)Wp, sWp, (double*)W);
+  else
+    p1s_sum_kernel<float><<<g2, 256, 0, s>>>(rs, S, (const float*)Wp, sWp, (float*)W);
+  return hipGetLastError();
+}
 
 hipError_t launch_krp_nd(const NdFactors& F, int lo, int hi, int R, int rep0, int nrep,
                          double* out, int64_t sOut, hipStream_t s) {

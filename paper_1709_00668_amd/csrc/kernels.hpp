@@ -520,6 +520,13 @@ struct CommitNd {
   const uint64_t* dw[kMaxOrder];
 };
 hipError_t launch_commit_nd(const CommitNd& c, hipStream_t s);
+// W = Z x3 C on a view with few rows and a long third index (p1's [f][e]
+// layout of W): S ranges of the third index per row tile, partial W in Wp
+// (stride sWp per repetition, S * n1 * n2 * R) summed in range order; S = 1
+// writes W directly.  p1s_splits: the S used for a view.
+int p1s_splits(int64_t n12, int Q, int nrep);
+hipError_t launch_p1s(int prec, const RepSet& rs, const void* Z, const double* Cf, int S,
+                      void* Wp, int64_t sWp, void* W, hipStream_t s);
 // components ordered by lam descending (ties: lower index first), every factor
 hipError_t launch_sort_nd(const NdFactors& F, int N, int R, double* lam, hipStream_t s);
 

@@ -194,3 +194,42 @@ def test_non_finite_batch_is_refused_without_change(lib):
     with pytest.raises(lib.SbtError):
         gpu.update_batch_dense(lib.dense_nd_to_device(np.concatenate([Y2, Y2], axis=3),
                                                       np.float64), 4)
+
+
+def test_dense4d_benchmark_configuration(lib):
+    """The order-4 benchmark workload at its full size, launched as the
+    benchmark launches it (FP32, 120^4 + one batch of 12 slices, R = 10,
+    s = 4, r = 10, 30 sweeps), against the oracle's update of the same data:
+    every sampled index and every matching exact; per repetition the summary
+    lambda and the last-mode rows, and the grown model, within 1e-3
+    (relative, in norm) of the FP64 oracle; fits within 1e-3."""
+    torch = _torch()
+    dims, K0, Kn, R, s, r, iters, seed = (120, 120, 120), 120, 12, 10, 4, 10, 30, 6
+    gen = synth.DenseCPN(dims + (K0 + Kn,), R, seed=seed, noise=0.01, dtype=np.float32)
+    X = gen.slices(0, K0 + Kn)
+    Us, lam = gen.true_model_prefix(K0)
+    slice_n = int(np.prod(dims))
+    Xd = torch.from_numpy(X.ravel(order="F")).cuda()
+    cfg = lib.make_config(R, r, iters, 1, seed, precision=lib.SBT_P_F32, k_capacity=K0 + Kn,
+                          max_batch=Kn)
+    gpu = lib.TensorN.init_dense_nd(cfg, Xd[:K0 * slice_n], dims + (K0,), s, factors=Us, lam=lam)
+    gpu.update_batch_dense(Xd[K0 * slice_n:], Kn)
+    torch.cuda.synchronize()
+    cfg_o = nmode.Config(rank=R, reps=r, als_iters=iters, sample_factor=s, seed=seed, order=4,
+                         k_capacity=K0 + Kn)
+    ora = nmode.OracleTensorN(cfg_o, X[..., :K0], factors=Us, lam=lam)
+    d = ora.update(X[..., K0:], debug=True)
+    check_samples(lib, gpu, d, 4, r)
+
+    def rel(a, b):
+        return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+    for rho in range(r):
+        rr = d["reps"][rho]
+        np.testing.assert_array_equal(gpu.last_rep_nd(rho, lib.SBT_ND_REP_PI), rr["pi"])
+        assert rel(gpu.last_rep_nd(rho, lib.SBT_ND_REP_LAMP), rr["lamp"]) < 1e-3
+        assert rel(gpu.last_rep_nd(rho, lib.SBT_ND_REP_CT), rr["Ct"]) < 1e-3
+    G, _ = gpu.get_factors_nd()
+    for m in range(4):
+        assert rel(G[m], ora.U[m]) < 1e-3, m
+    assert abs(gpu.fit() - ora.fit()) < 1e-3
