@@ -482,6 +482,9 @@ static SolveArgs make_solve_args(const RepSet& rs, const double* M, const double
   a.lam_div = lam_div;
   a.normalize = normalize;
   a.pinv_count = pinv_count;
+  a.gmask = 0;
+  a.Gm = nullptr;
+  a.sGmode = 0;
   return a;
 }
 
@@ -491,6 +494,19 @@ hipError_t launch_solve(const RepSet& rs, int rows, const double* M, const doubl
                         uint32_t* pinv_count, hipStream_t s) {
   const SolveArgs a = make_solve_args(rs, M, G1, sG1, G2, sG2, U, sU, Gout, lam_out, lam_div,
                                       normalize, pinv_count);
+  SBT_DISPATCH_RP(rs.R, { solve_kernel<RP><<<rs.nrep, 256, 0, s>>>(rs, rows, a); });
+  return hipGetLastError();
+}
+
+hipError_t launch_solve_prod(const RepSet& rs, int rows, const double* M, const double* Gm,
+                             int64_t sGmode, uint32_t mask, double* U, int64_t sU, double* Gout,
+                             double* lam_out, uint32_t* pinv_count, hipStream_t s) {
+  if (mask == 0 || (mask >> kMaxOrder) != 0) return hipErrorInvalidValue;
+  SolveArgs a = make_solve_args(rs, M, nullptr, rs.sG, nullptr, 0, U, sU, Gout, lam_out, nullptr,
+                                1, pinv_count);
+  a.gmask = mask;
+  a.Gm = Gm;
+  a.sGmode = sGmode;
   SBT_DISPATCH_RP(rs.R, { solve_kernel<RP><<<rs.nrep, 256, 0, s>>>(rs, rows, a); });
   return hipGetLastError();
 }

@@ -165,30 +165,38 @@ __global__ __launch_bounds__(256) void moi_coo_kernel(const int32_t* ii, const i
 // ---------------------------------------------------------------------------
 // Importance of a dense block of order N.  The block is read as D_0 rows x
 // (D_1 ... D_N-1) columns; a wavefront takes 64 consecutive rows (one per
-// lane) of kMoiNdCols consecutive columns.  Row sums stay in the lanes; each
-// column's sum goes to every higher mode, where consecutive columns that
-// share an index are added up in registers before one atomic per run (the
-// index of mode 1 changes with every column, the last mode's rarely).
+// lane) of kMoiNdCols consecutive columns, kMoiNdLoads column loads in
+// flight.  Row sums stay in the lanes.  Each column's sum goes to every
+// higher mode: mode 1 (whose index changes with every column) into per-block
+// sums in LDS, flushed with one atomic per index at the end; higher modes,
+// whose indices change rarely, into register runs of equal index, one atomic
+// per run.  Integer sums, so the order of the atomics does not matter.
 // ---------------------------------------------------------------------------
-constexpr int kMoiNdCols = 64;
+constexpr int kMoiNdCols = 128;
+constexpr int kMoiNdLoads = 8;
+constexpr int kMoiNdLds1 = 2048;  // mode-1 extents summed in LDS
 
 template <typename T>
 __global__ __launch_bounds__(256) void moi_nd_kernel(MoiNd a) {
+  __shared__ unsigned long long s1[kMoiNdLds1];
   const T* X = (const T*)a.X;
   const int N = a.N;
-  const int64_t D0 = a.D[0];
+  const int64_t D0 = a.D[0], D1 = a.D[1];
+  const bool priv = D1 <= kMoiNdLds1;
   int64_t ncols = 1;
   for (int m = 1; m < N; ++m) ncols *= a.D[m];
   const int lane = lane_id();
   const int wave = threadIdx.x >> 6;
   const int64_t i0 = (int64_t)blockIdx.y * kWave + lane;
   const bool in = i0 < D0;
+  if (priv)
+    for (int64_t i = threadIdx.x; i < D1; i += 256) s1[i] = 0ull;
+  __syncthreads();
   const int64_t cb = ((int64_t)blockIdx.x * 4 + wave) * kMoiNdCols;
-  if (cb >= ncols) return;  // no barrier below
   const int64_t ce = cb + kMoiNdCols < ncols ? cb + kMoiNdCols : ncols;
   int64_t idx[kMaxOrder], cur[kMaxOrder];
   unsigned long long run[kMaxOrder];
-  int64_t rem = cb;
+  int64_t rem = cb < ncols ? cb : 0;
 #pragma unroll
   for (int m = 1; m < kMaxOrder; ++m) {
     if (m < N) {
@@ -202,32 +210,50 @@ __global__ __launch_bounds__(256) void moi_nd_kernel(MoiNd a) {
   }
   unsigned long long acc0 = 0ull;
   bool bad = false;
-  for (int64_t c = cb; c < ce; ++c) {
-    const uint64_t q = in ? quantize_sq((double)X[i0 + D0 * c], a.scale, a.qmax, bad) : 0ull;
-    acc0 += q;
-    const unsigned long long col = wave_sum_u64(q);
+  for (int64_t c0 = cb; c0 < ce; c0 += kMoiNdLoads) {
+    double x[kMoiNdLoads];
 #pragma unroll
-    for (int m = 1; m < kMaxOrder; ++m) {
-      if (m < N) {
-        if (idx[m] != cur[m]) {
-          if (lane == 0 && run[m]) atomicAdd((unsigned long long*)&a.w[m][cur[m]], run[m]);
-          cur[m] = idx[m];
-          run[m] = 0ull;
-        }
-        run[m] += col;
+    for (int u = 0; u < kMoiNdLoads; ++u)
+      x[u] = (in && c0 + u < ce) ? (double)X[i0 + D0 * (c0 + u)] : 0.0;
+#pragma unroll
+    for (int u = 0; u < kMoiNdLoads; ++u) {
+      if (c0 + u >= ce) break;  // uniform over the wavefront
+      const uint64_t q = quantize_sq(x[u], a.scale, a.qmax, bad);
+      acc0 += q;
+      const unsigned long long col = wave_sum_u64(q);
+      if (lane == 0 && col) {
+        if (priv)
+          atomicAdd(&s1[idx[1]], col);
+        else
+          atomicAdd((unsigned long long*)&a.w[1][idx[1]], col);
       }
-    }
-    // next column's indices (mode 1 fastest)
-    for (int m = 1; m < N; ++m) {
-      if (++idx[m] < a.D[m]) break;
-      idx[m] = 0;
+#pragma unroll
+      for (int m = 2; m < kMaxOrder; ++m) {
+        if (m < N) {
+          if (idx[m] != cur[m]) {
+            if (lane == 0 && run[m]) atomicAdd((unsigned long long*)&a.w[m][cur[m]], run[m]);
+            cur[m] = idx[m];
+            run[m] = 0ull;
+          }
+          run[m] += col;
+        }
+      }
+      // next column's indices (mode 1 fastest)
+      for (int m = 1; m < N; ++m) {
+        if (++idx[m] < a.D[m]) break;
+        idx[m] = 0;
+      }
     }
   }
 #pragma unroll
-  for (int m = 1; m < kMaxOrder; ++m)
+  for (int m = 2; m < kMaxOrder; ++m)
     if (m < N && lane == 0 && run[m]) atomicAdd((unsigned long long*)&a.w[m][cur[m]], run[m]);
   if (in && acc0) atomicAdd((unsigned long long*)&a.w[0][i0], acc0);
   if (bad) atomicOr(a.err, 1u);
+  __syncthreads();
+  if (priv)
+    for (int64_t i = threadIdx.x; i < D1; i += 256)
+      if (s1[i]) atomicAdd((unsigned long long*)&a.w[1][i], s1[i]);
 }
 
 // ---------------------------------------------------------------------------

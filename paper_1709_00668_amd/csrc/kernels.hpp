@@ -527,6 +527,12 @@ hipError_t launch_commit_nd(const CommitNd& c, hipStream_t s);
 int p1s_splits(int64_t n12, int Q, int nrep);
 hipError_t launch_p1s(int prec, const RepSet& rs, const void* Z, const double* Cf, int S,
                       void* Wp, int64_t sWp, void* W, hipStream_t s);
+// launch_solve (normalising) with V = the Hadamard product, in mode order, of
+// the Gram matrices Gm + m * sGmode (per repetition stride R*R) of the modes
+// in `mask`
+hipError_t launch_solve_prod(const RepSet& rs, int rows, const double* M, const double* Gm,
+                             int64_t sGmode, uint32_t mask, double* U, int64_t sU, double* Gout,
+                             double* lam_out, uint32_t* pinv_count, hipStream_t s);
 // components ordered by lam descending (ties: lower index first), every factor
 hipError_t launch_sort_nd(const NdFactors& F, int N, int R, double* lam, hipStream_t s);
 

@@ -43,7 +43,21 @@ struct SolveArgs {
   const double* lam_div;  // R, shared (row solve only)
   int normalize;
   uint32_t* pinv_count;
+  // with gmask != 0, V is instead the Hadamard product, in mode order, of the
+  // Gram matrices Gm + m * sGmode (per repetition stride sG1) of the modes m
+  // whose bit is set (order-N tensors)
+  uint32_t gmask;
+  const double* Gm;
+  int64_t sGmode;
 };
+
+__device__ inline double solve_v(const SolveArgs& a, int rep, int q) {
+  if (!a.gmask) return a.G1[rep * a.sG1 + q] * a.G2[rep * a.sG2 + q];
+  double v = 1.0;
+  for (int m = 0; m < kMaxOrder; ++m)
+    if ((a.gmask >> m) & 1u) v *= a.Gm[m * a.sGmode + rep * a.sG1 + q];
+  return v;
+}
 
 __device__ inline void solve_pair_fg(int p, int R, int& f, int& g) {
   f = 0;
@@ -102,34 +116,13 @@ __device__ inline void jacobi_pinv_1t(double* A, double* Q, double* P, int ld, i
     }
 }
 
-// The "last block of a repetition" handshake: every block calls it after its
-// share of the repetition's output is written; exactly one block per
-// repetition gets true, after all the others' writes are visible to it.  The
-// counter is reset by that block, so consecutive launches need no clearing.
-__device__ inline bool last_block_of(uint32_t* cnt, uint32_t nblk, int* flag) {
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const uint32_t prev = atomicAdd(cnt, 1u);
-    const bool last = prev == nblk - 1;
-    if (last) *cnt = 0u;
-    *flag = last ? 1 : 0;
-  }
-  __syncthreads();
-  const bool last = *flag != 0;
-  if (last) __threadfence();
-  return last;
-}
-
 template <int RP>
 __device__ void block_solve(const SolveArgs& a, int rep, int rows, int R, SolveSmem& s) {
   const int tid = threadIdx.x;
   const double* M = a.M + rep * a.sM;
   double* U = a.U + rep * a.sU;
-  const double* G1 = a.G1 + rep * a.sG1;
-  const double* G2 = a.G2 + rep * a.sG2;
   __syncthreads();
-  for (int q = tid; q < R * R; q += 256) s.V[q / R][q % R] = G1[q] * G2[q];
+  for (int q = tid; q < R * R; q += 256) s.V[q / R][q % R] = solve_v(a, rep, q);
   if (tid == 0) s.fail = 0;
   __syncthreads();
   // Gauss-Jordan inversion in place
@@ -161,7 +154,7 @@ __device__ void block_solve(const SolveArgs& a, int rep, int rows, int R, SolveS
     // singular V: pseudo-inverse from the original V (rebuilt in buf)
     double* A0 = s.buf;
     double* Q = s.buf + kMaxRank * (kMaxRank + 1);
-    for (int q = tid; q < R * R; q += 256) A0[(q / R) * (kMaxRank + 1) + q % R] = G1[q] * G2[q];
+    for (int q = tid; q < R * R; q += 256) A0[(q / R) * (kMaxRank + 1) + q % R] = solve_v(a, rep, q);
     __syncthreads();
     if (tid == 0) {
       jacobi_pinv_1t(A0, Q, &s.V[0][0], kMaxRank + 1, R);
