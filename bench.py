@@ -35,7 +35,8 @@ throwaway copy; `value` is updated slices per second over it.  Per-update
 latency p50/p99 comes from --latency-runs repetitions of the whole sequence.
 
 roofline: the dominant kernel (by summed device time over the timed updates),
-timed with HIP events recorded on the stream it runs on, with its algorithmic
+timed with HIP events recorded on the stream it runs on (every fifth timed
+launch carries an event pair, so the timing costs the update little), with its algorithmic
 bytes per launch (summary elements read once, factor rows, outputs written
 once) against 8 TB/s; `traffic` comes from hardware counters of the same
 kernel when a committed measurement of the current kernel sources exists.
@@ -88,6 +89,9 @@ WORKLOADS = {
                             "1e6 nonzeros, rank 10, s=10, r=10, 30 ALS sweeps"),
 }
 HBM_PEAK_GBS = 8000.0
+# the timed updates record kernel events on every PROF_EVERY-th timed launch:
+# an event pair on every launch costs about a tenth of a 500^3 update
+PROF_EVERY = 5
 MFMA_BF16_PEAK_TFS = 2500.0
 
 KIND_NAMES = ("mttkrp_contract_c", "mttkrp_third_mode", "row_solve", "gather", "coo_mttkrp",
@@ -137,7 +141,7 @@ def timed_sequence(sbt, torch, fresh, apply_batch, steps, warmup, latency_runs, 
     T.close()
     torch.cuda.synchronize()
     T = fresh()
-    T.profile_enable(True)
+    T.profile_enable(True, every=PROF_EVERY)
     torch.cuda.synchronize()
     lat = []
     t0 = time.perf_counter()
@@ -246,7 +250,7 @@ def committed_traffic(kernel, key):
     return None
 
 
-def roofline_of(prof, path, R, key, summary_rows=0, n1_third=0):
+def roofline_of(prof, path, R, key, summary_rows=0, n1_third=0, every=PROF_EVERY):
     kernels = {k: v for k, v in prof.items() if k != "update" and v["launches"]}
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     d = kernels[dom]
@@ -260,7 +264,8 @@ def roofline_of(prof, path, R, key, summary_rows=0, n1_third=0):
                 peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
                 traffic=committed_traffic(kname, key),
                 avg_launch_us=round(avg_ms * 1e3, 2), alg_bytes_per_launch=int(bytes_per_launch),
-                share_of_update_time=round(d["total_ms"] / prof["update"]["total_ms"], 3))
+                timed_every=every,
+                share_of_update_time=round(every * d["total_ms"] / prof["update"]["total_ms"], 3))
 
 
 def kernels_table(prof):

@@ -239,6 +239,11 @@ sbt_status sbt_mttkrp_dense(int32_t precision, const void* Z_dev, int64_t n1, in
  * launch count, the summed device time and the algorithmic bytes the launches
  * must move (summary elements read once plus factor rows read and outputs
  * written).  Timing adds two event records per timed launch.
+ * sbt_profile_enable: on = 0 off; on = 1 every launch of these kinds; on = n > 1
+ * every n-th of them (counted over all kinds in launch order), which keeps the
+ * cost of the event records small while the per-kind averages stay those of
+ * the launches; the whole-update pair (SBT_K_UPDATE) is recorded every time.
+ * Enabling resets the accumulated figures.
  * ------------------------------------------------------------------------ */
 typedef enum {
   SBT_K_MTTKRP_C = 0,   /* MTTKRP pass contracting the third mode with C'       */

@@ -106,6 +106,8 @@ struct sbt_tensor {
   int64_t last_summary_nnz = 0;
   // kernel timing (sbt_profile_*)
   bool prof_on = false;
+  int prof_stride = 1;   // time every prof_stride-th kernel launch
+  uint64_t prof_seq = 0; // kernel launches offered for timing so far
   std::vector<hipEvent_t> prof_ev;     // pairs
   std::vector<int> prof_kind;          // per recorded pair
   std::vector<char> prof_launch;       // pair recorded by a kernel launch itself
@@ -206,6 +208,7 @@ int prof_begin(sbt_tensor* t, hipStream_t st) {
 
 // events the next timed kernel launch records at its own start and end
 int prof_kernel(sbt_tensor* t) {
+  if (!t->prof_on || (t->prof_seq++ % (uint64_t)t->prof_stride) != 0) return -1;
   const int q = prof_pair(t);
   if (q >= 0) {
     t->prof_launch[(size_t)q] = 1;
@@ -1680,8 +1683,10 @@ sbt_status sbt_last_rep(const sbt_tensor* tc, int32_t rep, int32_t item, double*
 }
 
 sbt_status sbt_profile_enable(sbt_tensor* t, int32_t on) {
-  if (!t) return SBT_E_INVALID;
+  if (!t || on < 0) return SBT_E_INVALID;
   t->prof_on = on != 0;
+  t->prof_stride = on > 1 ? on : 1;
+  t->prof_seq = 0;
   for (int k = 0; k < SBT_K_COUNT; ++k) {
     t->prof_n[k] = 0;
     t->prof_ms[k] = 0.0;

@@ -308,16 +308,34 @@ __global__ __launch_bounds__(kSampleThreads) void sample_kernel(SampleArgs a, ui
         const uint64_t kv = keys[i];
         if ((kv & mask) == prefix) atomicAdd(&hist[(kv >> shift) & 0xFF], 1u);
       }
-      __syncthreads();
       if (tid == 0) {
-        int64_t cum = 0;
-        for (int d = 0; d < 256; ++d) {
-          if (cum + (int64_t)hist[d] >= want) {
-            s_prefix = prefix | ((uint64_t)d << shift);
-            s_want = want - cum;
-            break;
+        s_prefix = prefix;
+        s_want = want;
+      }
+      __syncthreads();
+      // the digit where the running count reaches `want`: wavefront 0, four
+      // digits per lane, prefix sums across the lanes
+      if (tid < kWave) {
+        const int d0 = 4 * tid;
+        const int64_t h0 = hist[d0], h1 = hist[d0 + 1], h2 = hist[d0 + 2], h3 = hist[d0 + 3];
+        const int64_t tot = h0 + h1 + h2 + h3;
+        int64_t incl = tot;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+          const int64_t o = __shfl_up(incl, off, kWave);
+          if (tid >= off) incl += o;
+        }
+        int64_t cum = incl - tot;
+        if (cum < want && incl >= want) {
+          const int64_t hh[4] = {h0, h1, h2, h3};
+          for (int k = 0; k < 4; ++k) {
+            if (cum + hh[k] >= want) {
+              s_prefix = prefix | ((uint64_t)(d0 + k) << shift);
+              s_want = want - cum;
+              break;
+            }
+            cum += hh[k];
           }
-          cum += hist[d];
         }
       }
       __syncthreads();

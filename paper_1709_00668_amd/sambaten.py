@@ -302,8 +302,9 @@ class Tensor:
                self.h, "sbt_last_sample")
         return buf[:n.value].copy()
 
-    def profile_enable(self, on=True):
-        _check(load().sbt_profile_enable(self.h, 1 if on else 0), self.h)
+    def profile_enable(self, on=True, every=1):
+        """Kernel timing on/off; every=n times every n-th timed launch."""
+        _check(load().sbt_profile_enable(self.h, int(every) if on else 0), self.h)
 
     def profile_read(self, kind):
         n, ms, b = _i64(), ctypes.c_double(), ctypes.c_double()
