@@ -837,9 +837,11 @@ sbt_status run_als(sbt_tensor* t, const void* Zp, RepSet rs, double* Ap, double*
     SBT_CK(launch_cw(prec, rs, 0, W, Bp, ilB, Vinv, Ap, rs.sA, st));
     ta.U = Ap; ta.sU = rs.sA; ta.rows = rs.n1; ta.Gout = GA; ta.invlam_out = ilA;
     ta.lam_out = nullptr; ta.Gx = GA; ta.Gy = GC; ta.Vinv_out = Vinv;
-    SBT_TRY(tail(t, rs, ta, st));
-    // mode 2: B
-    SBT_CK(launch_cw(prec, rs, 1, W, Ap, ilA, Vinv, Bp, rs.sB, st));
+    // mode 2: B, with the tail of mode 1 folded into its launch when A's rows
+    // fit the tail's staging
+    const bool fold = tail_rows_fit(rs.n1, R);
+    if (!fold) SBT_TRY(tail(t, rs, ta, st));
+    SBT_CK(launch_cw(prec, rs, 1, W, Ap, ilA, Vinv, Bp, rs.sB, st, fold ? &ta : nullptr));
     ta.U = Bp; ta.sU = rs.sB; ta.rows = rs.n2; ta.Gout = GB; ta.invlam_out = ilB;
     ta.lam_out = nullptr; ta.Gx = GA; ta.Gy = GB; ta.Vinv_out = Vinv;
     SBT_TRY(tail(t, rs, ta, st));

@@ -279,9 +279,10 @@ __device__ void block_inverse(const double* Gx, const double* Gy, int R, double*
 }
 
 // Tail of a mode update for one repetition: Gram of the new raw factor,
-// lambda, normalised Gram, inverse for the next step.
+// lambda, normalised Gram, inverse for the next step.  The results stay in
+// LDS (s.V = the next V^-1, s.lam); `write` also stores them to memory.
 template <int RP>
-__device__ void als_tail(const TailArgs& t, int rep, int R, TailSmem& s) {
+__device__ void als_tail(const TailArgs& t, int rep, int R, TailSmem& s, bool write = true) {
   const int tid = threadIdx.x;
   const double* U = t.U + rep * t.sU;
   const int rows = t.rows;
@@ -358,8 +359,10 @@ __device__ void als_tail(const TailArgs& t, int rep, int R, TailSmem& s) {
   if (tid < R) {
     const double l = sqrt(s.V[tid][tid]);
     s.lam[tid] = l;
-    t.invlam_out[rep * 3 * R + tid] = l > 0.0 ? 1.0 / l : 1.0;  // [A | B | C] per repetition
-    if (t.lam_out) t.lam_out[rep * R + tid] = l;
+    if (write) {
+      t.invlam_out[rep * 3 * R + tid] = l > 0.0 ? 1.0 / l : 1.0;  // [A | B | C] per repetition
+      if (t.lam_out) t.lam_out[rep * R + tid] = l;
+    }
   }
   __syncthreads();
   double* G = t.Gout + rep * t.sG;
@@ -369,14 +372,15 @@ __device__ void als_tail(const TailArgs& t, int rep, int R, TailSmem& s) {
     double v = s.V[f][g];
     if (lf > 0.0) v = v / lf;
     if (lg > 0.0) v = v / lg;
-    G[q] = v;
+    if (write) G[q] = v;
     // V_next = Gx .* Gy with the fresh Gram in its place
     const double vn = fresh_x ? v * s.Gold[q] : s.Gold[q] * v;
     s.Vin[q] = vn;
   }
   __syncthreads();
   for (int q = tid; q < R * R; q += kTailThreads) s.V[q / R][q % R] = s.Vin[q];
-  block_inverse_lds<RP>(s, R, t.pinv_count, true);
+  block_inverse_lds<RP>(s, R, t.pinv_count, write);
+  if (!write) return;
   double* Vout = t.Vinv_out + rep * t.sG;
   for (int q = tid; q < R * R; q += kTailThreads) Vout[q] = s.V[q / R][q % R];
 }
@@ -482,11 +486,13 @@ constexpr int kCwPre = 4;  // W rows in flight per thread
 template <typename TA, int RP>
 __global__ __launch_bounds__(256) void cw_kernel(RepSet rs, int mode, int chr, const TA* W,
                                                 const double* F, const double* invlamF,
-                                                const double* Vinv, double* Uout, int64_t sU) {
+                                                const double* Vinv, double* Uout, int64_t sU,
+                                                TailArgs pro) {
   extern __shared__ __align__(16) unsigned char cw_smem[];
   __shared__ TA red[4][kRowsPerBlock][RP];
   __shared__ double Mrow[kRowsPerBlock][kMaxRank];
   __shared__ double Vi[kMaxRank][kLd];
+  __shared__ double ilp[kMaxRank];
   TA* Fs = reinterpret_cast<TA*>(cw_smem);  // [chr][RP]
   const int rep = rs.rep0 + blockIdx.y;
   const int R = rs.R, n1 = rs.n1, n2 = rs.n2;
@@ -517,9 +523,21 @@ __global__ __launch_bounds__(256) void cw_kernel(RepSet rs, int mode, int chr, c
       for (int f = 0; f < RP; ++f) w[u][f] = (v && f < R) ? Wr[e * R + f] : (TA)0;
     }
     __syncthreads();
-    if (x0 == 0)
-      for (int q = tid; q < R * R; q += 256) Vi[q / R][q % R] = Vinv[rep * rs.sG + q];
-    stage_rows<TA, RP>(Fs, xn, Fr + (int64_t)x0 * R, R, il);
+    if (x0 == 0) {
+      if (pro.U) {
+        // the tail of the step before (contracted factor's Gram, lambda, this
+        // step's V^-1) folded in: every block computes it the same way, block
+        // 0 also stores it; the dynamic LDS is free until the staging below
+        TailSmem& ts = *reinterpret_cast<TailSmem*>(cw_smem);
+        als_tail<RP>(pro, rep, R, ts, blockIdx.x == 0);
+        for (int q = tid; q < R * R; q += 256) Vi[q / R][q % R] = ts.V[q / R][q % R];
+        if (tid < R) ilp[tid] = ts.lam[tid] > 0.0 ? 1.0 / ts.lam[tid] : 1.0;
+        __syncthreads();
+      } else {
+        for (int q = tid; q < R * R; q += 256) Vi[q / R][q % R] = Vinv[rep * rs.sG + q];
+      }
+    }
+    stage_rows<TA, RP>(Fs, xn, Fr + (int64_t)x0 * R, R, pro.U ? ilp : il);
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < kCwPre; ++u) {
@@ -825,7 +843,14 @@ hipError_t launch_pw(int prec, const RepSet& rs, const void* Z, const double* Cf
 
 hipError_t launch_cw(int prec, const RepSet& rs, int mode, const void* W, const double* F,
                      const double* invlamF, const double* Vinv, double* U, int64_t sU,
-                     hipStream_t s) {
+                     hipStream_t s, const AlsTail* before) {
+  TailArgs pro{};
+  if (before) {
+    if (before->Gin || !tail_rows_fit(before->rows, rs.R)) return hipErrorInvalidValue;
+    pro = TailArgs{nullptr, before->U, before->sU, before->rows, before->Gout,
+                   before->invlam_out, before->lam_out, before->Gx, before->Gy,
+                   before->Vinv_out, before->sG, before->pinv_count};
+  }
   const int nrows = mode == 0 ? rs.n1 : rs.n2;
   const int ncon = mode == 0 ? rs.n2 : rs.n1;
   dim3 grid((unsigned)((nrows + kRowsPerBlock - 1) / kRowsPerBlock), (unsigned)rs.nrep);
@@ -834,14 +859,15 @@ hipError_t launch_cw(int prec, const RepSet& rs, int mode, const void* W, const 
   int chr = (int)((32768 / row_bytes) / kSlots * kSlots);
   if (chr > ncon) chr = ncon;
   if (chr < kSlots) chr = kSlots;
-  const size_t sh = (size_t)chr * row_bytes;
+  size_t sh = (size_t)chr * row_bytes;
+  if (before && sh < sizeof(TailSmem)) sh = sizeof(TailSmem);
   SBT_RP_SWITCH(rs.R, {
     if (prec == kF64)
       cw_kernel<double, RP><<<grid, 256, sh, s>>>(rs, mode, chr, (const double*)W, F, invlamF,
-                                                  Vinv, U, sU);
+                                                  Vinv, U, sU, pro);
     else
       cw_kernel<float, RP><<<grid, 256, sh, s>>>(rs, mode, chr, (const float*)W, F, invlamF,
-                                                 Vinv, U, sU);
+                                                 Vinv, U, sU, pro);
   });
   return hipGetLastError();
 }

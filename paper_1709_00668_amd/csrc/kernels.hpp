@@ -205,10 +205,14 @@ hipError_t launch_normalize(const RepSet& rs, double* Ap, double* Bp, double* Cp
 // W[rep][split][ab][f] = sum_{c in split} Z(ab, c) C(c, f) / lambda_C(f)
 hipError_t launch_pw(int prec, const RepSet& rs, const void* Z, const double* Cf,
                      const double* invlamC, void* W, hipStream_t s);
-// mode 0: A rows = (W x_b B~) V^-1; mode 1: B rows = (W x_a A~) V^-1
+// mode 0: A rows = (W x_b B~) V^-1; mode 1: B rows = (W x_a A~) V^-1.
+// before: the tail of the step that produced F (its rows must fit the tail's
+// staging, Gin unused), folded into this launch: every block computes it,
+// the first block of each repetition stores its outputs, and this step's
+// V^-1 and F's 1/lambda come from it instead of Vinv and invlamF.
 hipError_t launch_cw(int prec, const RepSet& rs, int mode, const void* W, const double* F,
                      const double* invlamF, const double* Vinv, double* U, int64_t sU,
-                     hipStream_t s);
+                     hipStream_t s, const AlsTail* before = nullptr);
 // whether launch_p3 can stage both factors of an n1 x n2 slice in LDS
 bool p3_fits(int prec, int n1, int n2, int R);
 // C rows = (Z_(3) (B~ kr A~)) V^-1, or with row_solve those rows / lam_div
