@@ -233,3 +233,38 @@ def test_dense4d_benchmark_configuration(lib):
     for m in range(4):
         assert rel(G[m], ora.U[m]) < 1e-3, m
     assert abs(gpu.fit() - ora.fit()) < 1e-3
+
+
+def test_order8_maximum_order_fp64(lib):
+    # the largest order the library takes, every extent small
+    N = 8
+    ora, gpu, ds = run_pair(lib, (3, 2, 3, 2, 2, 3, 2, 6), 2, 2, 2, 8, 1, 23, lib.SBT_P_F64,
+                            batches=2)
+    check_samples(lib, gpu, ds[-1], N, 2)
+    check_reps(lib, gpu, ds[-1], N, 2, 1e-8, 1e-10)
+    check_model(gpu, ora, 1e-8, 1e-10)
+
+
+def test_order4_maximum_rank_fp64(lib):
+    # rank 32 (the largest): 32-wide factor rows in every kernel
+    N = 4
+    ora, gpu, ds = run_pair(lib, (40, 36, 34, 40), 5, 32, 2, 25, (1, 1, 1, 1), 29, lib.SBT_P_F64)
+    check_samples(lib, gpu, ds[-1], N, 2)
+    check_reps(lib, gpu, ds[-1], N, 2, 1e-7, 1e-9)
+    check_model(gpu, ora, 1e-7, 1e-9)
+
+
+def test_order_and_arguments_refused(lib):
+    torch = _torch()
+    x = torch.zeros(64, dtype=torch.float64, device="cuda")
+    cfg = lib.make_config(2, 2, 5, 1, 1, precision=lib.SBT_P_F64, k_capacity=8, max_batch=2)
+    for dims, s in (((4, 4), (1, 1)), ((2,) * 9, (1,) * 9), ((4, 4, 0, 2), (1, 1, 1, 1)),
+                    ((4, 4, 2), (1, 0, 1))):
+        with pytest.raises(lib.SbtError):
+            lib.TensorN.init_dense_nd(cfg, x, dims, s)
+    bf = lib.make_config(2, 2, 5, 1, 1, precision=lib.SBT_P_BF16, k_capacity=8, max_batch=2)
+    with pytest.raises(lib.SbtError):
+        lib.TensorN.init_dense_nd(bf, x, (4, 4, 2), (1, 1, 1))
+    full = lib.make_config(2, 2, 5, 1, 1, precision=lib.SBT_P_F64, k_capacity=2, max_batch=2)
+    with pytest.raises(lib.SbtError):  # no room for a batch
+        lib.TensorN.init_dense_nd(full, x, (4, 4, 2), (1, 1, 1))
