@@ -46,8 +46,9 @@ CP-ALS of the whole grown tensor on the GPU and the relative fitness of the
 incremental result against it (Sec. 4.2); fms_truth: the factor match score
 (Sec. 4.4, on the GPU) of the final model against the generating components.
 getrank (dense workloads): the batched FP32 update with GetRank (Sec. 3.2) on
-every summary.  persistent (dense workloads): the main path with persistent
-summaries (samples of the first update kept, warm-started summary CP-ALS).
+every summary.  persistent (dense and sparse workloads): the main path with
+persistent summaries (samples of the first update kept, warm-started summary
+CP-ALS; the old part of each summary kept, so only the new slices are read).
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--workload dense500]
 """
@@ -544,6 +545,19 @@ def bench_sparse(args, sbt, torch, synth, log):
     line["roofline"] = roofline_of(res["profile"], "coo", w["R"], f"{name}@{args.nnz_scale:g}",
                                    summary_rows=w["r"] * -(-w["I"] // w["s"]))
     line["cpu_baseline"] = None
+    if not args.no_persist:
+        # persistent summaries: the first update's samples kept; each later
+        # update scans only its batch for the new slices' entries
+        cfg_p = sbt.make_config(w["R"], w["r"], w["iters"], w["s"], w["seed"], fmt=sbt.SBT_COO,
+                                precision=sbt.SBT_P_F32, k_capacity=K0 + steps * Kn,
+                                max_batch=Kn, nnz_capacity=nnz_total, persist_summaries=True)
+
+        def fresh_p():
+            return sbt.Tensor.init_coo(cfg_p, cols0, vd0, len(v0), I, J, K0, model)
+
+        p = timed_sequence(sbt, torch, fresh_p, apply_batch, steps, args.warmup, 1, Kn)
+        line["persistent"] = path_summary(p)
+        log(f"# coo persistent summaries: {p['slices_per_s']:.1f} slices/s, fit {p['fit']:.6f}")
     line["kernels"] = kernels_table(res["profile"])
     return line
 
@@ -682,7 +696,7 @@ def main():
                     help="skip the CP-ALS recompute of the grown tensor (relative fitness)")
     ap.add_argument("--recompute-iters", type=int, default=100)
     ap.add_argument("--no-persist", action="store_true",
-                    help="dense: skip the persistent-summary variant")
+                    help="dense and sparse: skip the persistent-summary variant")
     ap.add_argument("--getrank-runs", type=int, default=1,
                     help="dense: also time the update with GetRank, this many CP runs per "
                          "candidate rank (0: skip)")

@@ -99,6 +99,9 @@ struct sbt_tensor {
   double *Bw = nullptr, *Cw = nullptr;
   bool have_kept = false;  // I_s, J_s, K_s in idx are the kept ones
   bool z_kept = false;     // the summaries' K_s slices were gathered with those indices
+  bool coo_kept = false;   // COO summaries hold the old part of the kept indices
+  int64_t* keep_d = nullptr;  // device: old-part starts, counts, new starts (3 x 64)
+  int64_t keep_h[4 * 64] = {};  // host: the same, and where each batch part begins
   int n3kept = 0;
   bool warm_now = false;   // this update's summary CP-ALS starts from Bw, Cw
   int warm_n3 = 0;
@@ -449,6 +452,7 @@ sbt_status alloc_state(sbt_tensor* t) {
     SBT_TRY(dalloc(t, &z.offB, (size_t)r * z.sOffB));
     SBT_TRY(dalloc(t, &z.offC, (size_t)r * z.sOffC));
     SBT_TRY(dalloc(t, &z.rep_off, 65));
+    SBT_TRY(dalloc(t, &t->keep_d, (size_t)3 * 64));
     const int64_t mrows[3] = {t->n1, t->n2, t->Kpmax};
     for (int m = 0; m < 3; ++m) {
       SBT_TRY(dalloc(t, &t->cu[m].cnt, (size_t)r * mrows[m]));
@@ -559,12 +563,91 @@ sbt_status ensure_summary(sbt_tensor* t, int64_t n, hipStream_t st) {
 
 // Build the r COO summaries of an update: position maps and masks, count,
 // per repetition offsets, emit (sorted by c), row offsets, sorted copies.
-sbt_status coo_build_summaries(sbt_tensor* t, int64_t Kold, int n3old, int Kp, hipStream_t st) {
+// Persistent COO summaries: the old part of each summary (its rows c < n3old,
+// a prefix in c order) is what the last build left for the same indices, so
+// only the batch's entries are scanned.  The old parts move to their places
+// in the new layout (through the a-sorted copy's arrays, rebuilt afterwards),
+// the batch's entries are emitted behind them, and the arrays come out
+// exactly as a scan of the whole store would leave them.  false: the
+// summaries do not fit the allocation; nothing has been changed.
+sbt_status coo_keep_old(sbt_tensor* t, int64_t Kold, int n3old, int Kp, bool* done,
+                        hipStream_t st) {
+  *done = false;
+  const int r = t->cfg.repetitions;
+  CooSummary& z = t->z;
+  if (r > 64) return SBT_OK;
+  std::vector<int64_t> oe((size_t)r), tot((size_t)r);
+  for (int q = 0; q < r; ++q)
+    SBT_CK(hipMemcpyAsync(&oe[(size_t)q], z.offC + (int64_t)q * z.sOffC + n3old, 8,
+                          hipMemcpyDeviceToHost, st));
+  const int32_t* bi = t->ci + t->nnz;
+  const int32_t* bj = t->cj + t->nnz;
+  const int32_t* bk = t->ck + t->nnz;
+  const float* bv = t->cv + t->nnz;
+  const int64_t nb = t->pending_nnz;
+  SBT_CK(launch_coo_count(bi, bj, bk, nb, t->bitI, t->bitJ, t->bitK, Kold, r, t->bcount,
+                          t->bbase, st));
+  const int64_t nblk = coo_scan_blocks(nb);
+  for (int q = 0; q < r; ++q)
+    SBT_CK(hipMemcpyAsync(&tot[(size_t)q], t->bbase + (int64_t)q * (nblk + 1) + nblk, 8,
+                          hipMemcpyDeviceToHost, st));
+  SBT_CK(hipStreamSynchronize(st));
+  int64_t* src = t->keep_h;
+  int64_t* cnt = t->keep_h + 64;
+  int64_t* dst = t->keep_h + 128;
+  int64_t total = 0, most = 0;
+  for (int q = 0; q < r; ++q) {
+    src[q] = z.rep_off_h[q];
+    cnt[q] = oe[(size_t)q] - src[q];
+    dst[q] = total;
+    total += cnt[q] + tot[(size_t)q];
+    most = std::max(most, cnt[q]);
+  }
+  if (total > z.cap) return SBT_OK;
+  SBT_CK(hipMemcpyAsync(t->keep_d, t->keep_h, sizeof(int64_t) * 3 * 64, hipMemcpyHostToDevice,
+                        st));
+  const int64_t* src_d = t->keep_d;
+  const int64_t* cnt_d = t->keep_d + 64;
+  const int64_t* dst_d = t->keep_d + 128;
+  const int gq = prof_kernel(t);
+  SBT_CK(launch_summary_move(z.a, z.b, z.c, z.v, src_d, cnt_d, dst_d, r, most, z.a_x, z.a_y,
+                             z.b_x, z.a_v, st));
+  SBT_CK(launch_summary_move(z.a_x, z.a_y, z.b_x, z.a_v, dst_d, cnt_d, dst_d, r, most, z.a, z.b,
+                             z.c, z.v, st));
+  prof_end(t, gq, SBT_K_GATHER, 32.0 * (double)(total - nb), st);
+  // the batch's entries behind each old part: the emit writes repetition q
+  // from z.rep_off[q] on
+  int64_t* starts = t->keep_h + 192;
+  for (int q = 0; q < r; ++q) starts[q] = dst[q] + cnt[q];
+  SBT_CK(hipMemcpyAsync(z.rep_off, starts, sizeof(int64_t) * r, hipMemcpyHostToDevice, st));
+  SBT_CK(launch_coo_emit(bi, bj, bk, bv, nb, t->bitI, t->bitJ, t->bitK, Kold, n3old, r, t->posI,
+                         t->posJ, t->posK, t->I, t->J, t->Kcap, t->bbase, z, st));
+  for (int q = 0; q < r; ++q) z.rep_off_h[q] = dst[q];
+  z.rep_off_h[r] = total;
+  SBT_CK(hipMemcpyAsync(z.rep_off, z.rep_off_h, sizeof(int64_t) * (r + 1), hipMemcpyHostToDevice,
+                        st));
+  // the pinned host copies above are read by the stream before they change
+  SBT_CK(hipStreamSynchronize(st));
+  t->last_summary_nnz = total;
+  SBT_CK(launch_coo_sorts(z, r, total, t->n1, t->n2, Kp, st));
+  RepSet rs = make_repset(t, Kp, 0, r);
+  for (int m = 0; m < 3; ++m) SBT_CK(launch_coo_units_build(rs, m, z, t->cu[m], st));
+  *done = true;
+  return SBT_OK;
+}
+
+sbt_status coo_build_summaries(sbt_tensor* t, int64_t Kold, int n3old, int Kp, bool keep_old,
+                               hipStream_t st) {
   const int r = t->cfg.repetitions;
   const int64_t offJ = t->n1, offK = (int64_t)t->n1 + t->n2;
   const int64_t nnz_all = t->nnz + t->pending_nnz;
   SBT_CK(launch_coo_maps(t->idx, t->idx_stride, offJ, offK, t->n1, t->n2, n3old, r, t->posI,
                          t->posJ, t->posK, t->I, t->J, t->Kcap, t->bitI, t->bitJ, t->bitK, st));
+  if (keep_old) {
+    bool done = false;
+    SBT_TRY(coo_keep_old(t, Kold, n3old, Kp, &done, st));
+    if (done) return SBT_OK;
+  }
   SBT_CK(launch_coo_count(t->ci, t->cj, t->ck, nnz_all, t->bitI, t->bitJ, t->bitK, Kold, r,
                           t->bcount, t->bbase, st));
   const int64_t nblk = coo_scan_blocks(nnz_all);
@@ -1084,7 +1167,8 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
                  (prec_bytes(t->store_prec) + prec_bytes(t->sum_prec)),
              st);
   } else {
-    SBT_TRY(coo_build_summaries(t, Kold, n3old, Kp, st));
+    if (!reuse) t->coo_kept = false;
+    SBT_TRY(coo_build_summaries(t, Kold, n3old, Kp, reuse && t->coo_kept, st));
   }
   // the summaries now hold X(I_s, J_s, K_s) for the indices in idx
   t->z_kept = t->fmt == SBT_DENSE;
@@ -1236,6 +1320,7 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
     SBT_CK(hipStreamSynchronize(st));
     t->have_kept = true;
     t->n3kept = n3old;
+    t->coo_kept = t->fmt == SBT_COO;
   }
   t->K = Kold + Kn;
   t->t += 1;

@@ -651,6 +651,25 @@ inline int rp_of4(int R) { return ((R + 3) / 4) * 4; }
     default: { constexpr int RP = 32; __VA_ARGS__; } break; \
   }
 
+// Copy per repetition q the entries [src[q], src[q] + cnt[q]) of the four
+// summary arrays to [dst[q], dst[q] + cnt[q]) of four others (a persistent
+// summary's old part moved to its place in the next update's layout).
+__global__ __launch_bounds__(256) void summary_move_kernel(const int32_t* a, const int32_t* b,
+                                                          const int32_t* c, const float* v,
+                                                          const int64_t* src, const int64_t* cnt,
+                                                          const int64_t* dst, int32_t* oa,
+                                                          int32_t* ob, int32_t* oc, float* ov) {
+  const int q = blockIdx.y;
+  const int64_t n = cnt[q], s0 = src[q], d0 = dst[q];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    oa[d0 + e] = a[s0 + e];
+    ob[d0 + e] = b[s0 + e];
+    oc[d0 + e] = c[s0 + e];
+    ov[d0 + e] = v[s0 + e];
+  }
+}
+
 }  // namespace
 
 // ==========================================================================
@@ -745,6 +764,17 @@ hipError_t launch_coo_emit(const int32_t* si, const int32_t* sj, const int32_t* 
 }
 
 
+hipError_t launch_summary_move(const int32_t* a, const int32_t* b, const int32_t* c,
+                               const float* v, const int64_t* src, const int64_t* cnt,
+                               const int64_t* dst, int nrep, int64_t max_cnt, int32_t* oa,
+                               int32_t* ob, int32_t* oc, float* ov, hipStream_t s) {
+  if (nrep <= 0 || max_cnt <= 0) return hipSuccess;
+  const int blocks = grid_for(max_cnt, 256);
+  dim3 grid((unsigned)(blocks < 2048 ? blocks : 2048), (unsigned)nrep);
+  summary_move_kernel<<<grid, 256, 0, s>>>(a, b, c, v, src, cnt, dst, oa, ob, oc, ov);
+  return hipGetLastError();
+}
+
 hipError_t launch_coo_sorts(CooSummary& z, int nrep, int64_t total, int n1, int n2, int n3,
                             hipStream_t s) {
   const unsigned go = (unsigned)grid_for(total + 1, 256);
@@ -807,6 +837,7 @@ ModeView mode_view(const RepSet& rs, int mode, const CooSummary& z) {
   m.cv = mode == 0 ? z.a_v : (mode == 1 ? z.b_v : z.v);
   return m;
 }
+
 }  // namespace
 
 hipError_t launch_coo_units_build(const RepSet& rs, int mode, const CooSummary& z, CooUnits& u,

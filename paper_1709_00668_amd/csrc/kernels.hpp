@@ -336,6 +336,12 @@ hipError_t launch_coo_maps(const int32_t* idx, int64_t idx_stride, int64_t offJ,
                            uint64_t* bitJ, uint64_t* bitK, hipStream_t s);
 // per block and repetition counts of kept entries, and per repetition
 // exclusive scans bbase[rep][0..nblk] (relative to the repetition's start)
+// per repetition q: cnt[q] entries of (a, b, c, v) from src[q] to dst[q] of
+// (oa, ob, oc, ov); max_cnt >= every cnt[q] (device arrays src, cnt, dst)
+hipError_t launch_summary_move(const int32_t* a, const int32_t* b, const int32_t* c,
+                               const float* v, const int64_t* src, const int64_t* cnt,
+                               const int64_t* dst, int nrep, int64_t max_cnt, int32_t* oa,
+                               int32_t* ob, int32_t* oc, float* ov, hipStream_t s);
 hipError_t launch_coo_count(const int32_t* si, const int32_t* sj, const int32_t* sk, int64_t nnz,
                             const uint64_t* bitI, const uint64_t* bitJ, const uint64_t* bitK,
                             int64_t Kold, int nrep, uint32_t* bcount, int64_t* bbase,

@@ -176,3 +176,42 @@ def test_coo_and_dense_storage_agree(lib):
     Cc = gc.get_factors()[2]
     np.testing.assert_allclose(Cc, Cd, rtol=1e-4, atol=1e-6)
     assert abs(gd.fit() - gc.fit()) < 1e-6
+
+
+def test_coo_and_dense_persistent_summaries_agree(lib):
+    # persistent summaries over four batches: the COO summaries keep their old
+    # part and scan only each batch, the dense ones keep theirs in place; both
+    # hold the same entries, so the updates agree at FP32 rounding level
+    torch = _torch()
+    I, J, K0, Kn, R, reps, nb = 26, 22, 18, 3, 2, 3, 4
+    gen = synth.DenseCP(I, J, K0 + nb * Kn, R, seed=9, dtype=np.float32)
+    X = gen.slices(0, K0 + nb * Kn)
+    X[np.random.default_rng(9).random(X.shape) < 0.4] = 0.0
+    model = gen.true_model_prefix(K0)
+    kcap = K0 + nb * Kn
+    cfg_d = lib.make_config(R, reps, 10, 2, 9, precision=lib.SBT_P_F32, k_capacity=kcap,
+                            max_batch=Kn, persist_summaries=True)
+    gd = lib.Tensor.init_dense(cfg_d, lib.dense_to_device(X[:, :, :K0], np.float32), I, J, K0,
+                               factors=model)
+    nnz_all = int((X != 0).sum())
+    cfg_c = lib.make_config(R, reps, 10, 2, 9, fmt=lib.SBT_COO, k_capacity=kcap, max_batch=Kn,
+                            nnz_capacity=nnz_all, persist_summaries=True)
+    X0 = X[:, :, :K0]
+    idx0 = np.argwhere(X0 != 0)
+    cols, vd = lib.coo_to_device(idx0, X0[X0 != 0])
+    gc = lib.Tensor.init_coo(cfg_c, cols, vd, len(idx0), I, J, K0, model)
+    for b in range(nb):
+        Y = X[:, :, K0 + b * Kn:K0 + (b + 1) * Kn]
+        yidx = np.argwhere(Y != 0)
+        gd.update_batch_dense(lib.dense_to_device(Y, np.float32), Kn)
+        bcols, bv = lib.coo_to_device(yidx, Y[Y != 0])
+        gc.update_batch_coo(bcols, bv, len(yidx), Kn)
+        torch.cuda.synchronize()
+        for rho in range(reps):
+            for mode in range(3):
+                np.testing.assert_array_equal(gd.last_sample(rho, mode),
+                                              gc.last_sample(rho, mode))
+        Cd = gd.get_factors()[2]
+        Cc = gc.get_factors()[2]
+        np.testing.assert_allclose(Cc, Cd, rtol=1e-4, atol=1e-6, err_msg=f"batch {b}")
+    assert abs(gd.fit() - gc.fit()) < 1e-6
