@@ -215,3 +215,41 @@ def test_coo_and_dense_persistent_summaries_agree(lib):
         Cc = gc.get_factors()[2]
         np.testing.assert_allclose(Cc, Cd, rtol=1e-4, atol=1e-6, err_msg=f"batch {b}")
     assert abs(gd.fit() - gc.fit()) < 1e-6
+
+
+def test_coo_persistent_summaries_outgrowing_their_allocation(lib):
+    # persistent COO summaries whose second batch is twenty times the first:
+    # the summaries no longer fit what the first update allocated, so that
+    # update rebuilds them from the store; the third keeps its old part again.
+    # Dense storage of the same tensor is the reference at every step.
+    torch = _torch()
+    I, J, K0, R, reps = 40, 40, 20, 2, 3
+    sizes = [1, 20, 3]
+    Kall = K0 + sum(sizes)
+    gen = synth.DenseCP(I, J, Kall, R, seed=11, dtype=np.float32)
+    X = gen.slices(0, Kall)
+    X[np.random.default_rng(11).random(X.shape) < 0.4] = 0.0
+    model = gen.true_model_prefix(K0)
+    cfg_d = lib.make_config(R, reps, 8, 2, 11, precision=lib.SBT_P_F32, k_capacity=Kall,
+                            max_batch=max(sizes), persist_summaries=True)
+    gd = lib.Tensor.init_dense(cfg_d, lib.dense_to_device(X[:, :, :K0], np.float32), I, J, K0,
+                               factors=model)
+    cfg_c = lib.make_config(R, reps, 8, 2, 11, fmt=lib.SBT_COO, k_capacity=Kall,
+                            max_batch=max(sizes), nnz_capacity=int((X != 0).sum()),
+                            persist_summaries=True)
+    X0 = X[:, :, :K0]
+    idx0 = np.argwhere(X0 != 0)
+    cols, vd = lib.coo_to_device(idx0, X0[X0 != 0])
+    gc = lib.Tensor.init_coo(cfg_c, cols, vd, len(idx0), I, J, K0, model)
+    k = K0
+    for b, kn in enumerate(sizes):
+        Y = X[:, :, k:k + kn]
+        k += kn
+        yidx = np.argwhere(Y != 0)
+        gd.update_batch_dense(lib.dense_to_device(Y, np.float32), kn)
+        bcols, bv = lib.coo_to_device(yidx, Y[Y != 0])
+        gc.update_batch_coo(bcols, bv, len(yidx), kn)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(gc.get_factors()[2], gd.get_factors()[2], rtol=1e-4,
+                                   atol=1e-6, err_msg=f"batch {b}")
+    assert abs(gd.fit() - gc.fit()) < 1e-6
