@@ -21,6 +21,7 @@
 // one extra launch.  All reductions use a fixed assignment and order.
 #include "device_common.hpp"
 #include "kernels.hpp"
+#include "solve_device.hpp"
 
 namespace sbt {
 
@@ -181,64 +182,10 @@ __device__ void jacobi_pinv(double* A, double* Q, double* P, int R) {
 constexpr int kTailThreads = 256;
 constexpr int kTailUnroll = 8;  // row loads in flight per thread
 
-__device__ inline double readlane_f64(double v, int lane) {
-  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xFFFFFFFFull), lane);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
-// Gauss-Jordan inverse of the symmetric positive definite s.V (R x R) by the
-// first wavefront, without pivoting; returns false (uniform over the wave)
-// when a pivot is not positive.  Result in s.V.
+// Gauss-Jordan inverse of s.V in one wavefront (wave_gj_inverse_v).
 template <int RP>
 __device__ bool wave_gj_inverse(TailSmem& s, int R) {
-  const int i = lane_id();
-  double a[RP], b[RP];
-#pragma unroll
-  for (int j = 0; j < RP; ++j) {
-    a[j] = (i < R && j < R) ? s.V[i][j] : 0.0;
-    b[j] = (i == j) ? 1.0 : 0.0;
-  }
-  bool ok = true;
-#pragma unroll
-  for (int k = 0; k < RP; ++k) {
-    if (k < R) {
-      const double piv = readlane_f64(a[k], k);
-      if (!(piv > 0.0)) {
-        ok = false;
-        break;
-      }
-      const double rp = 1.0 / piv;
-      const double m = a[k] * rp;
-      // pivot row: columns j < k of a and j > k of b are zero at this point
-      double pa[RP], pb[RP];
-#pragma unroll
-      for (int j = 0; j < RP; ++j) {
-        pa[j] = j >= k ? readlane_f64(a[j], k) : 0.0;
-        pb[j] = j <= k ? readlane_f64(b[j], k) : 0.0;
-      }
-      if (i == k) {
-#pragma unroll
-        for (int j = 0; j < RP; ++j) {
-          a[j] = pa[j] * rp;
-          b[j] = pb[j] * rp;
-        }
-      } else {
-#pragma unroll
-        for (int j = 0; j < RP; ++j) {
-          if (j >= k) a[j] = a[j] - m * pa[j];
-          if (j <= k) b[j] = b[j] - m * pb[j];
-        }
-      }
-    }
-  }
-  if (ok && i < R) {
-#pragma unroll
-    for (int j = 0; j < RP; ++j)
-      if (j < R) s.V[i][j] = b[j];
-  }
-  return ok;
+  return wave_gj_inverse_v<RP>(s.V, R);
 }
 
 // s.V (R x R, already in LDS) -> its inverse in s.V; pseudo-inverse fallback.

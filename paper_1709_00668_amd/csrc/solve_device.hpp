@@ -2,8 +2,9 @@
 // "Decompose": CP-ALS), used inside the fused MTTKRP kernels and on its own.
 //
 //   V = G1 .* G2            (Hadamard product of the other two Gram matrices)
-//   V^-1 by Gauss-Jordan    (symmetric positive definite: no pivoting; a pivot
-//                            that is not positive means V is singular and the
+//   V^-1 by Gauss-Jordan    (in one wavefront's registers; symmetric positive
+//                            definite: no pivoting; a pivot that is not
+//                            positive means V is singular and the
 //                            pseudo-inverse, cut-off R eps max|eig|, is used)
 //   U = M V^-1              (rows staged through LDS in chunks)
 //   normalize: lambda_f = ||U(:,f)||, U(:,f) /= lambda_f (lambda_f > 0),
@@ -116,6 +117,68 @@ __device__ inline void jacobi_pinv_1t(double* A, double* Q, double* P, int ld, i
     }
 }
 
+__device__ inline double readlane_f64(double v, int lane) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b & 0xFFFFFFFFull), lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Gauss-Jordan inverse of the symmetric positive definite V (R x R, in LDS)
+// by the first wavefront, without pivoting: lane i holds row i of [V | I]
+// and the pivot row is broadcast with readlane, so no barriers are needed.
+// Returns false (uniform over the wave) when a pivot is not positive; the
+// result is in V only when it returns true.
+template <int RP>
+__device__ bool wave_gj_inverse_v(double (*V)[kMaxRank + 1], int R) {
+  const int i = lane_id();
+  double a[RP], b[RP];
+#pragma unroll
+  for (int j = 0; j < RP; ++j) {
+    a[j] = (i < R && j < R) ? V[i][j] : 0.0;
+    b[j] = (i == j) ? 1.0 : 0.0;
+  }
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < RP; ++k) {
+    if (k < R) {
+      const double piv = readlane_f64(a[k], k);
+      if (!(piv > 0.0)) {
+        ok = false;
+        break;
+      }
+      const double rp = 1.0 / piv;
+      const double m = a[k] * rp;
+      // pivot row: columns j < k of a and j > k of b are zero at this point
+      double pa[RP], pb[RP];
+#pragma unroll
+      for (int j = 0; j < RP; ++j) {
+        pa[j] = j >= k ? readlane_f64(a[j], k) : 0.0;
+        pb[j] = j <= k ? readlane_f64(b[j], k) : 0.0;
+      }
+      if (i == k) {
+#pragma unroll
+        for (int j = 0; j < RP; ++j) {
+          a[j] = pa[j] * rp;
+          b[j] = pb[j] * rp;
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < RP; ++j) {
+          if (j >= k) a[j] = a[j] - m * pa[j];
+          if (j <= k) b[j] = b[j] - m * pb[j];
+        }
+      }
+    }
+  }
+  if (ok && i < R) {
+#pragma unroll
+    for (int j = 0; j < RP; ++j)
+      if (j < R) V[i][j] = b[j];
+  }
+  return ok;
+}
+
 template <int RP>
 __device__ void block_solve(const SolveArgs& a, int rep, int rows, int R, SolveSmem& s) {
   const int tid = threadIdx.x;
@@ -125,29 +188,10 @@ __device__ void block_solve(const SolveArgs& a, int rep, int rows, int R, SolveS
   for (int q = tid; q < R * R; q += 256) s.V[q / R][q % R] = solve_v(a, rep, q);
   if (tid == 0) s.fail = 0;
   __syncthreads();
-  // Gauss-Jordan inversion in place
-  for (int k = 0; k < R; ++k) {
-    const double piv = s.V[k][k];
-    if (!(piv > 0.0)) {  // uniform: every thread read the same pivot
-      if (tid == 0) s.fail = 1;
-      break;
-    }
-    double nv[4];
-    int nq = 0;
-    for (int q = tid; q < R * R; q += 256, ++nq) {
-      const int i = q / R, j = q % R;
-      const double vik = s.V[i][k], vkj = s.V[k][j];
-      double v;
-      if (i == k)
-        v = (j == k) ? 1.0 / piv : vkj / piv;
-      else
-        v = (j == k) ? -vik / piv : s.V[i][j] - vik * (vkj / piv);
-      nv[nq] = v;
-    }
-    __syncthreads();
-    nq = 0;
-    for (int q = tid; q < R * R; q += 256, ++nq) s.V[q / R][q % R] = nv[nq];
-    __syncthreads();
+  // Gauss-Jordan inversion in the registers of the first wavefront
+  if (tid < kWave) {
+    const bool ok = wave_gj_inverse_v<RP>(s.V, R);
+    if (tid == 0 && !ok) s.fail = 1;
   }
   __syncthreads();
   if (s.fail) {
