@@ -308,7 +308,8 @@ template <> struct AccNd<double> { using type = double; };
 
 template <typename TZ, int RP>
 __global__ __launch_bounds__(256) void p1s_kernel(RepSet rs, const TZ* Z, const double* Cf, int S,
-                                                 typename AccNd<TZ>::type* Wp, int64_t sWp) {
+                                                 typename AccNd<TZ>::type* Wp, int64_t sWp,
+                                                 NdFactors F, int c0, int N) {
   using TA = typename AccNd<TZ>::type;
   __shared__ TA Cs[kP1sMaxRows][RP];
   __shared__ TA red[64][RP + 1];
@@ -320,10 +321,29 @@ __global__ __launch_bounds__(256) void p1s_kernel(RepSet rs, const TZ* Z, const 
   const int L = qe - qs;  // <= kP1sMaxRows (host-chosen S)
   const int64_t e = (int64_t)blockIdx.x * 64 + lane;
   const bool ok = e < n12;
-  const double* C = Cf + rep * rs.sC + (int64_t)qs * R;
-  for (int q = threadIdx.x; q < L * RP; q += 256) {
-    const int r = q / RP, f = q % RP;
-    Cs[r][f] = f < R ? (TA)C[(int64_t)r * R + f] : (TA)0;
+  if (c0 < 0) {
+    const double* C = Cf + rep * rs.sC + (int64_t)qs * R;
+    for (int q = threadIdx.x; q < L * RP; q += 256) {
+      const int r = q / RP, f = q % RP;
+      Cs[r][f] = f < R ? (TA)C[(int64_t)r * R + f] : (TA)0;
+    }
+  } else {
+    // Khatri-Rao rows of the factors of modes c0..N-1 formed while staging
+    // (the same products, in the same order, as krp_nd_kernel)
+    for (int q = threadIdx.x; q < L * RP; q += 256) {
+      const int r = q / RP, f = q % RP;
+      double v = 0.0;
+      if (f < R) {
+        int64_t p = qs + r;
+        v = 1.0;
+        for (int l = c0; l < N; ++l) {
+          const int64_t a = p % F.n[l];
+          p /= F.n[l];
+          v *= F.U[l][rep * F.sU[l] + a * R + f];
+        }
+      }
+      Cs[r][f] = (TA)v;
+    }
   }
   __syncthreads();
   const int w0 = (wave * L) / 4, w1 = ((wave + 1) * L) / 4;
@@ -395,7 +415,11 @@ int p1s_splits(int64_t n12, int Q, int nrep) {
 }
 
 hipError_t launch_p1s(int prec, const RepSet& rs, const void* Z, const double* Cf, int S,
-                      void* Wp, int64_t sWp, void* W, hipStream_t s) {
+                      void* Wp, int64_t sWp, void* W, hipStream_t s, const NdFactors* krp, int c0,
+                      int N) {
+  const NdFactors F = krp ? *krp : NdFactors{};
+  if (krp && (c0 < 0 || c0 >= N || N > kMaxOrder)) return hipErrorInvalidValue;
+  const int kc0 = krp ? c0 : -1;
   const int64_t n12 = (int64_t)rs.n1 * rs.n2;
   if (S < 1 || (rs.n3 + S - 1) / S > kP1sMaxRows) return hipErrorInvalidValue;
   void* out = S == 1 ? W : Wp;
@@ -407,10 +431,10 @@ hipError_t launch_p1s(int prec, const RepSet& rs, const void* Z, const double* C
   case RPV:                                                                                   \
     if (prec == kF64)                                                                         \
       timed_launch(p1s_kernel<double, RPV>, grid, dim3(256), 0, s, rs, (const double*)Z, Cf, \
-                   S, (double*)out, so);                                                      \
+                   S, (double*)out, so, F, kc0, N);                                           \
     else                                                                                      \
       timed_launch(p1s_kernel<float, RPV>, grid, dim3(256), 0, s, rs, (const float*)Z, Cf,   \
-                   S, (float*)out, so);                                                       \
+                   S, (float*)out, so, F, kc0, N);                                            \
     break;
     SBT_P1S(4) SBT_P1S(8) SBT_P1S(12) SBT_P1S(16) SBT_P1S(20) SBT_P1S(24) SBT_P1S(28)
     SBT_P1S(32)

@@ -535,8 +535,12 @@ hipError_t launch_commit_nd(const CommitNd& c, hipStream_t s);
 // (stride sWp per repetition, S * n1 * n2 * R) summed in range order; S = 1
 // writes W directly.  p1s_splits: the S used for a view.
 int p1s_splits(int64_t n12, int Q, int nrep);
+// krp: instead of reading Cf, form the Khatri-Rao rows of the modes c0..N-1
+// of these factors while staging them (the view's third index runs over
+// those modes, c0 fastest).
 hipError_t launch_p1s(int prec, const RepSet& rs, const void* Z, const double* Cf, int S,
-                      void* Wp, int64_t sWp, void* W, hipStream_t s);
+                      void* Wp, int64_t sWp, void* W, hipStream_t s,
+                      const NdFactors* krp = nullptr, int c0 = -1, int N = 0);
 // launch_solve (normalising) with V = the Hadamard product, in mode order, of
 // the Gram matrices Gm + m * sGmode (per repetition stride R*R) of the modes
 // in `mask`
