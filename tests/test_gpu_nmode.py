@@ -143,6 +143,20 @@ def test_order4_initial_cp_als_matches_oracle(lib):
     assert gpu.fit() == pytest.approx(ora.fit(), abs=1e-10)
 
 
+def test_order4_middle_modes_beyond_lds_take_the_plain_pass(lib):
+    # (0, 70 x 80 merged, last) views of 5600 middle rows: the staged factors
+    # of the fused last-mode pass would exceed the 160 KiB of LDS, so the
+    # initial CP-ALS, the summary sweeps (s = 1 on the middle modes) and the
+    # row solve of the new slices all take the plain pass
+    N = 4
+    ora, gpu, ds = run_pair(lib, (6, 70, 80, 10), 3, 3, 2, 8, (1, 1, 1, 2), 23, lib.SBT_P_F64,
+                            init="cp")
+    check_samples(lib, gpu, ds[-1], N, 2)
+    check_reps(lib, gpu, ds[-1], N, 2, 1e-8, 1e-10)
+    check_model(gpu, ora, 1e-8, 1e-10)
+    assert gpu.fit() == pytest.approx(ora.fit(), abs=1e-10)
+
+
 def test_order4_zero_entry_fill(lib):
     # a zero in the model at an index every repetition samples (s = 1 on mode 1)
     ora, gpu, ds = run_pair(lib, (10, 9, 8, 12), 4, 2, 3, 15, (2, 1, 2, 2), 3, lib.SBT_P_F64,
