@@ -300,7 +300,7 @@ __global__ __launch_bounds__(256) void sort_nd_kernel(NdFactors F, int N, int R,
 // again, each with kP1sLoads summary loads in flight, over C rows staged in
 // LDS.  The wavefronts' rows add up in LDS in wavefront order; with S > 1
 // each range writes a partial W that a second kernel sums in range order.
-constexpr int kP1sLoads = 8;
+constexpr int kP1sLoads = 4;
 constexpr int kP1sMaxRows = 128;  // C rows one block stages
 
 template <typename TZ> struct AccNd { using type = float; };
