@@ -587,7 +587,7 @@ __global__ __launch_bounds__(256) void p3_kernel(RepSet rs, const TZ* Z, const d
                                                 const double* lam_div, double* Uout,
                                                 int64_t sU) {
   using TA = typename AccT<TZ>::type;
-  constexpr int KU = V >= 2 ? 4 : 8;  // loads in flight per thread
+  constexpr int KU = V == 4 ? 4 : (V == 2 ? 8 : 16);  // loads in flight per thread
   extern __shared__ __align__(16) unsigned char p3_smem[];
   double(*Vi)[kLd] = reinterpret_cast<double(*)[kLd]>(p3_smem);
   TA(*red)[kMaxRank] =
