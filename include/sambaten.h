@@ -221,17 +221,44 @@ sbt_status sbt_last_rep(const sbt_tensor* t, int32_t rep, int32_t item, double* 
  * measurement.  All pointers are device pointers.
  * ------------------------------------------------------------------------ */
 
-/* MTTKRP of a dense n1 x n2 x n3 tensor Z (column-major; element type per
- * `precision`: double, float, or bfloat16 bits as uint16) with row-major
- * double factors U0 (n1 x R), U1 (n2 x R), U2 (n3 x R):
+/* MTTKRP (Sec. 2.1: the matricised tensor times the Khatri-Rao product of
+ * the other factors) of a dense n1 x n2 x n3 tensor Z (column-major; element
+ * type per `precision`: double, float, or bfloat16 bits as uint16) with
+ * row-major double factors U0 (n1 x R), U1 (n2 x R), U2 (n3 x R):
  *   mode 0: out(a,f) = sum_bc Z(a,b,c) U1(b,f) U2(c,f)     (n1 x R)
  *   mode 1: out(b,f) = sum_ac Z(a,b,c) U0(a,f) U2(c,f)     (n2 x R)
  *   mode 2: out(c,f) = sum_ab Z(a,b,c) U0(a,f) U1(b,f)     (n3 x R)
- * out is row-major double.  The factor for `mode` itself is not read.
- * Stream-ordered: returns after enqueueing. */
-sbt_status sbt_mttkrp_dense(int32_t precision, const void* Z_dev, int64_t n1, int64_t n2,
-                            int64_t n3, int32_t R, const double* U0_dev, const double* U1_dev,
-                            const double* U2_dev, int32_t mode, double* out_dev, void* stream);
+ * out is row-major double.  The factor for `mode` itself is not read (may be
+ * NULL).  `schedule` picks the kernels of that update schedule:
+ * SBT_SCHED_BATCHED the contraction with U2 followed by the contraction with
+ * the other factor (modes 0, 1) and the fused third-mode pass (mode 2);
+ * SBT_SCHED_PLAIN the per-step kernels.  BF16 always takes the matrix-core
+ * kernels when their staging fits the shape.  Temporary device buffers are
+ * allocated and freed on `stream`; returns when the result is written.
+ * Errors: SBT_E_INVALID (NULL pointers, bad mode, precision or schedule),
+ * SBT_E_SHAPE (extent above 2^31 - 1, or a batched mode-2 pass whose factors
+ * do not fit its LDS staging), SBT_E_NOMEM / SBT_E_DEVICE. */
+sbt_status sbt_mttkrp_dense(int32_t precision, int32_t schedule, const void* Z_dev, int64_t n1,
+                            int64_t n2, int64_t n3, int32_t R, const double* U0_dev,
+                            const double* U1_dev, const double* U2_dev, int32_t mode,
+                            double* out_dev, void* stream);
+
+/* The same product for a COO tensor of extents n1 x n2 x n3 (the sparse
+ * MTTKRP of the update's COO summaries, FP32 products and sums): entries
+ * (a_dev[e], b_dev[e], c_dev[e], v_dev[e]), e < nnz, device arrays in any
+ * order, coordinates inside the extents and no coordinate twice (not
+ * checked: an entry outside gives undefined output).  The entries are
+ * ordered, split into work units and contracted by the kernels of the
+ * update; `lanes` = 32 or 64 forces the lanes per work unit, 0 lets the
+ * entries per row decide as in the update.  Factors, out and the result
+ * layout as for sbt_mttkrp_dense.  Returns when the result is written.
+ * Errors: SBT_E_INVALID, SBT_E_SHAPE (an extent of 2^24 or more),
+ * SBT_E_NOMEM / SBT_E_DEVICE. */
+sbt_status sbt_mttkrp_coo(const int32_t* a_dev, const int32_t* b_dev, const int32_t* c_dev,
+                          const float* v_dev, int64_t nnz, int64_t n1, int64_t n2, int64_t n3,
+                          int32_t R, const double* U0_dev, const double* U1_dev,
+                          const double* U2_dev, int32_t mode, int32_t lanes, double* out_dev,
+                          void* stream);
 
 /* --------------------------------------------------------------------------
  * Kernel timing.  While enabled, every update records a HIP event pair on its

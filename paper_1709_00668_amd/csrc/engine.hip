@@ -1793,12 +1793,14 @@ sbt_status sbt_profile_read(const sbt_tensor* t, int32_t kind, int64_t* launches
   return SBT_OK;
 }
 
-sbt_status sbt_mttkrp_dense(int32_t precision, const void* Z_dev, int64_t n1, int64_t n2,
-                            int64_t n3, int32_t R, const double* U0_dev, const double* U1_dev,
-                            const double* U2_dev, int32_t mode, double* out_dev, void* stream) {
+sbt_status sbt_mttkrp_dense(int32_t precision, int32_t schedule, const void* Z_dev, int64_t n1,
+                            int64_t n2, int64_t n3, int32_t R, const double* U0_dev,
+                            const double* U1_dev, const double* U2_dev, int32_t mode,
+                            double* out_dev, void* stream) {
   sbt_tensor* t = nullptr;  // for SBT_CK: no tensor to record the message on
   if (!Z_dev || !out_dev || R < 1 || R > kMaxRank || n1 < 1 || n2 < 1 || n3 < 1 || mode < 0 ||
-      mode > 2 || precision < SBT_P_F64 || precision > SBT_P_BF16)
+      mode > 2 || precision < SBT_P_F64 || precision > SBT_P_BF16 ||
+      (schedule != SBT_SCHED_BATCHED && schedule != SBT_SCHED_PLAIN))
     return SBT_E_INVALID;
   if (n1 > INT32_MAX || n2 > INT32_MAX || n3 > INT32_MAX) return SBT_E_SHAPE;
   const int prec = precision == SBT_P_F64 ? kF64 : (precision == SBT_P_F32 ? kF32 : kBF16);
@@ -1860,12 +1862,41 @@ sbt_status sbt_mttkrp_dense(int32_t precision, const void* Z_dev, int64_t n1, in
     for (void* q : frees) SBT_CK(hipFreeAsync(q, st));
     return SBT_OK;
   }
+  if ((mode != 0 && !U0_dev) || (mode != 1 && !U1_dev) || (mode != 2 && !U2_dev))
+    return SBT_E_INVALID;
+  if (prec != kBF16 && schedule == SBT_SCHED_BATCHED) {
+    // the kernels of the batched update with V = I and unit column scales:
+    // pass W and the mode-1/2 contraction, or the fused mode-3 pass
+    if (mode == 2 && !p3_fits(prec, rs.n1, rs.n2, R)) return SBT_E_SHAPE;
+    std::vector<double> eye((size_t)R * R, 0.0), one((size_t)3 * R, 1.0);
+    for (int f = 0; f < R; ++f) eye[(size_t)f * R + f] = 1.0;
+    double *I_dev = nullptr, *one_dev = nullptr;
+    void* W = nullptr;
+    SBT_CK(hipMallocAsync((void**)&I_dev, sizeof(double) * eye.size(), st));
+    SBT_CK(hipMallocAsync((void**)&one_dev, sizeof(double) * one.size(), st));
+    SBT_CK(hipMemcpyAsync(I_dev, eye.data(), sizeof(double) * eye.size(), hipMemcpyHostToDevice,
+                          st));
+    SBT_CK(hipMemcpyAsync(one_dev, one.data(), sizeof(double) * one.size(),
+                          hipMemcpyHostToDevice, st));
+    if (mode == 2) {
+      SBT_CK(launch_p3(prec, rs, false, Z_dev, U0_dev, one_dev, U1_dev, one_dev, I_dev, nullptr,
+                       out_dev, 0, st));
+    } else {
+      SBT_CK(hipMallocAsync(&W, (size_t)rs.sW * acc_bytes(prec), st));
+      SBT_CK(launch_pw(prec, rs, Z_dev, U2_dev, one_dev, W, st));
+      SBT_CK(launch_cw(prec, rs, mode, W, mode == 0 ? U1_dev : U0_dev, one_dev, I_dev, out_dev,
+                       0, st));
+    }
+    SBT_CK(hipStreamSynchronize(st));  // the host vectors above are read by the copies
+    void* frees[] = {I_dev, one_dev, W};
+    for (void* q : frees)
+      if (q) SBT_CK(hipFreeAsync(q, st));
+    return SBT_OK;
+  }
   if (mode == 2) {
-    if (!U0_dev || !U1_dev) return SBT_E_INVALID;
     SBT_CK(launch_p2(prec, rs, Z_dev, U0_dev, U1_dev, out_dev, st));
     return SBT_OK;
   }
-  if (!U2_dev || (mode == 0 && !U1_dev) || (mode == 1 && !U0_dev)) return SBT_E_INVALID;
   void* W = nullptr;
   SBT_CK(hipMallocAsync(&W, (size_t)rs.sW * acc_bytes(prec), st));
   SBT_CK(launch_p1(prec, rs, Z_dev, U2_dev, W, st));
@@ -1875,6 +1906,112 @@ sbt_status sbt_mttkrp_dense(int32_t precision, const void* Z_dev, int64_t n1, in
     SBT_CK(launch_cw2(prec, rs, W, U0_dev, out_dev, st));
   SBT_CK(hipFreeAsync(W, st));
   return SBT_OK;
+}
+
+sbt_status sbt_mttkrp_coo(const int32_t* a_dev, const int32_t* b_dev, const int32_t* c_dev,
+                          const float* v_dev, int64_t nnz, int64_t n1, int64_t n2, int64_t n3,
+                          int32_t R, const double* U0_dev, const double* U1_dev,
+                          const double* U2_dev, int32_t mode, int32_t lanes, double* out_dev,
+                          void* stream) {
+  sbt_tensor* t = nullptr;  // for SBT_CK: no tensor to record the message on
+  if (!out_dev || R < 1 || R > kMaxRank || n1 < 1 || n2 < 1 || n3 < 1 || mode < 0 || mode > 2 ||
+      nnz < 0 || (nnz > 0 && (!a_dev || !b_dev || !c_dev || !v_dev)) ||
+      (lanes != 0 && lanes != 32 && lanes != 64))
+    return SBT_E_INVALID;
+  if ((mode != 0 && !U0_dev) || (mode != 1 && !U1_dev) || (mode != 2 && !U2_dev))
+    return SBT_E_INVALID;
+  // the a- and b-ordered copies sort on 24-bit row keys; entry positions are int
+  if (n1 >= (1 << 24) || n2 >= (1 << 24) || n3 >= (1 << 24) || nnz > INT32_MAX)
+    return SBT_E_SHAPE;
+  hipStream_t st = (hipStream_t)stream;
+  RepSet rs;
+  rs.n1 = (int)n1;
+  rs.n2 = (int)n2;
+  rs.n3 = (int)n3;
+  rs.R = R;
+  rs.rep0 = 0;
+  rs.nrep = 1;
+  rs.sZ = 0;
+  rs.sA = n1 * R;
+  rs.sB = n2 * R;
+  rs.sC = n3 * R;
+  rs.sW = 0;
+  rs.sM = 0;
+  rs.sG = (int64_t)R * R;
+  rs.nsplit = 1;
+  const int rows = mode == 0 ? rs.n1 : (mode == 1 ? rs.n2 : rs.n3);
+  const int rowsX = mode == 0 ? rs.n2 : rs.n1;
+  const int rowsY = mode == 2 ? rs.n2 : rs.n3;
+  const double* X = mode == 0 ? U1_dev : U0_dev;
+  const double* Y = mode == 2 ? U1_dev : U2_dev;
+  const int RX = R <= 16 ? 16 : 32;
+  const int64_t cap = nnz + 1;
+  std::vector<void*> bufs;
+  auto get = [&](void** p, size_t bytes) -> hipError_t {
+    hipError_t e = hipMallocAsync(p, bytes ? bytes : 1, st);
+    if (e == hipSuccess) bufs.push_back(*p);
+    return e;
+  };
+  auto release = [&]() {
+    for (void* q : bufs) (void)hipFreeAsync(q, st);
+    bufs.clear();
+  };
+  auto body = [&]() -> sbt_status {
+    CooSummary z{};
+    int32_t** i32s[] = {&z.a, &z.b, &z.c, &z.a_x, &z.a_y, &z.b_x, &z.b_y, &z.val, &z.perm};
+    for (int32_t** p : i32s) SBT_CK(get((void**)p, sizeof(int32_t) * cap));
+    float** f32s[] = {&z.v, &z.a_v, &z.b_v};
+    for (float** p : f32s) SBT_CK(get((void**)p, sizeof(float) * cap));
+    uint32_t** u32s[] = {&z.key_a, &z.key_b, &z.key_out};
+    for (uint32_t** p : u32s) SBT_CK(get((void**)p, sizeof(uint32_t) * cap));
+    SBT_CK(coo_sort_tmp_bytes(cap, &z.tmp_bytes));
+    SBT_CK(get(&z.tmp, z.tmp_bytes));
+    z.sOffA = n1 + 1;
+    z.sOffB = n2 + 1;
+    z.sOffC = n3 + 1;
+    SBT_CK(get((void**)&z.offA, sizeof(int64_t) * z.sOffA));
+    SBT_CK(get((void**)&z.offB, sizeof(int64_t) * z.sOffB));
+    SBT_CK(get((void**)&z.offC, sizeof(int64_t) * z.sOffC));
+    SBT_CK(get((void**)&z.rep_off, sizeof(int64_t) * 2));
+    z.rep_off_h[0] = 0;
+    z.rep_off_h[1] = nnz;
+    z.cap = cap;
+    CooUnits u{};
+    u.cap = cap / kCooUnit + rows + 1;
+    SBT_CK(get((void**)&u.cnt, sizeof(uint32_t) * rows));
+    SBT_CK(get((void**)&u.uoff, sizeof(int64_t) * (rows + 1)));
+    SBT_CK(get((void**)&u.urow, sizeof(int32_t) * u.cap));
+    SBT_CK(get((void**)&u.ustart, sizeof(int64_t) * u.cap));
+    SBT_CK(get((void**)&u.ulen, sizeof(int32_t) * u.cap));
+    float *Xf = nullptr, *Yf = nullptr, *part = nullptr;
+    SBT_CK(get((void**)&Xf, sizeof(float) * rowsX * RX));
+    SBT_CK(get((void**)&Yf, sizeof(float) * rowsY * RX));
+    SBT_CK(get((void**)&part, sizeof(float) * u.cap * kMaxRank));
+    double* I_dev = nullptr;
+    SBT_CK(get((void**)&I_dev, sizeof(double) * R * R));
+    std::vector<double> eye((size_t)R * R, 0.0);
+    for (int f = 0; f < R; ++f) eye[(size_t)f * R + f] = 1.0;
+    SBT_CK(hipMemcpyAsync(I_dev, eye.data(), sizeof(double) * eye.size(), hipMemcpyHostToDevice,
+                          st));
+    SBT_CK(hipMemcpyAsync(z.rep_off, z.rep_off_h, sizeof(int64_t) * 2, hipMemcpyHostToDevice,
+                          st));
+    SBT_CK(launch_coo_single_summary(a_dev, b_dev, c_dev, v_dev, nnz, rs.n1, rs.n2, rs.n3, z,
+                                     st));
+    SBT_CK(launch_coo_units_build(rs, mode, z, u, st));
+    SBT_CK(launch_coo_prep(rs, rowsX, X, (int64_t)rowsX * R, nullptr, Xf, st));
+    SBT_CK(launch_coo_prep(rs, rowsY, Y, (int64_t)rowsY * R, nullptr, Yf, st));
+    // the lane count of the unit kernel follows the summary entries per row
+    // (64 lanes from 128 on); `lanes` forces either variant
+    const double avg = lanes == 64 ? 1e300 : (lanes == 32 ? 0.0 : (double)nnz / rows);
+    SBT_CK(launch_coo_units(rs, mode, z, u, Xf, rowsX, Yf, rowsY, part, avg, st));
+    SBT_CK(launch_coo_units_finish(rs, mode, u, part, I_dev, nullptr, out_dev, 0, st));
+    SBT_CK(hipStreamSynchronize(st));  // the host arrays above are read by the copies
+    return SBT_OK;
+  };
+  const sbt_status r = body();
+  release();
+  if (r != SBT_OK) (void)hipStreamSynchronize(st);
+  return r;
 }
 
 }  // extern "C"

@@ -819,6 +819,30 @@ hipError_t launch_coo_sorts(CooSummary& z, int nrep, int64_t total, int n1, int 
   return hipGetLastError();
 }
 
+hipError_t launch_coo_single_summary(const int32_t* a, const int32_t* b, const int32_t* c,
+                                     const float* v, int64_t nnz, int n1, int n2, int n3,
+                                     CooSummary& z, hipStream_t s) {
+  if (nnz > 0) {
+    int bits = 1;
+    while ((1ll << bits) < n3) ++bits;
+    copy_u32_kernel<<<grid_for(nnz, 256 * 16), 256, 0, s>>>(c, z.key_a, nnz);
+    iota_kernel<<<grid_for(nnz, 256 * 16), 256, 0, s>>>(z.val, nnz);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    size_t tb = z.tmp_bytes;
+    e = hipcub::DeviceRadixSort::SortPairs(z.tmp, tb, z.key_a, z.key_out, z.val, z.perm,
+                                           (int)nnz, 0, bits, s);
+    if (e != hipSuccess) return e;
+    summary_permute_kernel<<<grid_for(nnz, 256 * 16), 256, 0, s>>>(z.perm, nnz, a, b, v, z.a,
+                                                                    z.b, z.v);
+    copy_u32_kernel<<<grid_for(nnz, 256 * 16), 256, 0, s>>>((const int32_t*)z.key_out,
+                                                             (uint32_t*)z.c, nnz);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return launch_coo_sorts(z, 1, nnz, n1, n2, n3, s);
+}
+
 namespace {
 struct ModeView {
   int rows;

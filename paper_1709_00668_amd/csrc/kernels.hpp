@@ -356,6 +356,12 @@ hipError_t launch_coo_emit(const int32_t* si, const int32_t* sj, const int32_t* 
 // (n1, n2, n3 rows per repetition) from the sorted keys
 hipError_t launch_coo_sorts(CooSummary& z, int nrep, int64_t total, int n1, int n2, int n3,
                             hipStream_t s);
+// one COO tensor (a, b, c, v) of extents n1 x n2 x n3 as the single summary
+// of z: entries ordered by c (stable), the a- and b-ordered copies and the
+// row offsets of all three modes (z.rep_off must hold {0, nnz} on the device)
+hipError_t launch_coo_single_summary(const int32_t* a, const int32_t* b, const int32_t* c,
+                                     const float* v, int64_t nnz, int n1, int n2, int n3,
+                                     CooSummary& z, hipStream_t s);
 // rows of mode `mode` (0: A from B, C; 1: B from A, C; 2: C from A, B):
 // U = (COO MTTKRP) V^-1, or divided by lam_div (row solve)
 // unit table of one mode from the row offsets of the summaries

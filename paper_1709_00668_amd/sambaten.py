@@ -78,8 +78,10 @@ _SIGS = {
     "sbt_get_batch_counter": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_uint32)]),
     "sbt_last_sample": (ctypes.c_int, [_vp, _i32, _i32, _vp, ctypes.POINTER(_i64)]),
     "sbt_last_rep": (ctypes.c_int, [_vp, _i32, _i32, _vp, _i64, ctypes.POINTER(_i64)]),
-    "sbt_mttkrp_dense": (ctypes.c_int, [_i32, _vp, _i64, _i64, _i64, _i32, _vp, _vp, _vp, _i32,
-                                        _vp, _vp]),
+    "sbt_mttkrp_dense": (ctypes.c_int, [_i32, _i32, _vp, _i64, _i64, _i64, _i32, _vp, _vp, _vp,
+                                        _i32, _vp, _vp]),
+    "sbt_mttkrp_coo": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _i64, _i64, _i64, _i32, _vp, _vp,
+                                      _vp, _i32, _i32, _vp, _vp]),
     "sbt_profile_enable": (ctypes.c_int, [_vp, _i32]),
     "sbt_profile_read": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_i64), _pd, _pd]),
     "sbt_server_create": (ctypes.c_int, [_i32, _i64, ctypes.POINTER(_vp)]),
@@ -408,10 +410,19 @@ class TensorN(Tensor):
 
 
 def mttkrp_dense(precision, Z_dev, n1, n2, n3, R, U0_dev, U1_dev, U2_dev, mode, out_dev,
-                 stream=None):
-    st = load().sbt_mttkrp_dense(precision, _ptr(Z_dev), n1, n2, n3, R, _ptr(U0_dev),
+                 stream=None, schedule=SBT_SCHED_BATCHED):
+    st = load().sbt_mttkrp_dense(precision, schedule, _ptr(Z_dev), n1, n2, n3, R, _ptr(U0_dev),
                                  _ptr(U1_dev), _ptr(U2_dev), mode, _ptr(out_dev), _stream(stream))
     _check(st, None, "sbt_mttkrp_dense")
+
+
+def mttkrp_coo(idx_dev, vals_dev, nnz, n1, n2, n3, R, U0_dev, U1_dev, U2_dev, mode, out_dev,
+               lanes=0, stream=None):
+    """idx_dev: three int32 device arrays (a, b, c); vals_dev: float32."""
+    st = load().sbt_mttkrp_coo(_ptr(idx_dev[0]), _ptr(idx_dev[1]), _ptr(idx_dev[2]),
+                               _ptr(vals_dev), nnz, n1, n2, n3, R, _ptr(U0_dev), _ptr(U1_dev),
+                               _ptr(U2_dev), mode, lanes, _ptr(out_dev), _stream(stream))
+    _check(st, None, "sbt_mttkrp_coo")
 
 
 class Server:

@@ -7,6 +7,7 @@ import pytest
 
 import synth
 from oracle import sambaten as osb
+from parity import assert_close
 
 pytestmark = pytest.mark.gpu
 
@@ -31,7 +32,7 @@ def _pair(lib, I, J, K0, Kn, R_true, R, reps, iters, s, seed, prec, runs, tau, n
     return ora, gpu, d
 
 
-def _check(lib, ora, gpu, d, reps, R, runs, K0, c_tol, cc_tol):
+def _check(lib, ora, gpu, d, reps, R, runs, K0, c_tol, cc_tol, tau=90.0):
     for rho in range(reps):
         r = d["reps"][rho]
         for mode, key in enumerate(("Is", "Js", "Ks")):
@@ -40,17 +41,24 @@ def _check(lib, ora, gpu, d, reps, R, runs, K0, c_tol, cc_tol):
         assert rn == r["Rnew"], (rho, rn, r["Rnew"], r["cc"])
         cc = gpu.last_rep(rho, lib.SBT_REP_CC, R, ncols=runs)
         want = np.array(r["cc"])
-        sane = np.abs(want) < 1e3  # degenerate runs (pinv of near-collinear columns) differ
+        # Degenerate runs (nearly collinear columns) have core consistencies of
+        # -1e3 and below; there the GPU's inverse-Gram form and the oracle's SVD
+        # pseudo-inverses differ in value.  Such a score can never reach the
+        # threshold on either side (a score is at most 100, and these lie far
+        # below any threshold the tests use), so it cannot change the chosen
+        # rank: asserted below, and the rest compared in value.
+        sane = np.abs(want) < 1e3
         np.testing.assert_allclose(cc[sane], want[sane], rtol=0, atol=cc_tol)
-        assert np.all((cc[~sane] < 0) == (want[~sane] < 0))
+        assert np.all(want[~sane] < 0) and np.all(cc[~sane] < 0)
+        assert np.all(want[~sane] < min(tau, 0.0) - 900.0)
+        assert np.all(cc[~sane] < min(tau, 0.0) - 900.0)
         valid = gpu.last_rep(rho, lib.SBT_REP_VALID, 1)[0]
         np.testing.assert_array_equal(valid.astype(bool), r["valid"])
         pi = gpu.last_rep(rho, lib.SBT_REP_PI, 1)[0].astype(int)
         m = r["pi"] >= 0
         np.testing.assert_array_equal(pi[m], r["pi"][m])
     A, B, C, lam = gpu.get_factors()
-    err = np.linalg.norm(C[K0:] - ora.C[K0:]) / np.linalg.norm(ora.C[K0:])
-    assert err < c_tol, err
+    assert_close(C[K0:], ora.C[K0:], c_tol, c_tol, "new rows of C")
     assert abs(gpu.fit() - ora.fit()) < c_tol
 
 
@@ -75,5 +83,4 @@ def test_getrank_threshold_edges(lib, tau, expect):
         assert d["reps"][rho]["Rnew"] == expect
         assert int(gpu.last_rep(rho, lib.SBT_REP_RNEW, 1, ncols=1)[0, 0]) == expect
     A, B, C, lam = gpu.get_factors()
-    err = np.linalg.norm(C[K0:] - ora.C[K0:]) / max(1e-300, np.linalg.norm(ora.C[K0:]))
-    assert err < 1e-7, err
+    assert_close(C[K0:], ora.C[K0:], 1e-7, 1e-7, "new rows of C")

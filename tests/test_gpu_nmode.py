@@ -12,6 +12,7 @@ import pytest
 import synth
 from oracle import nmode
 from oracle import sambaten as osb
+from parity import assert_close
 
 pytestmark = pytest.mark.gpu
 
@@ -176,8 +177,8 @@ def test_order4_fp32_fit_matches_oracle(lib):
     f_gpu, f_ora = gpu.fit(), ora.fit()
     assert abs(f_gpu - f_ora) <= 1e-3 * max(1.0, abs(f_ora))
     Us, _ = gpu.get_factors_nd()
-    rel = np.linalg.norm(Us[-1] - ora.U[-1]) / np.linalg.norm(ora.U[-1])
-    assert rel < 1e-3
+    for m in range(4):
+        assert_close(Us[m], ora.U[m], 1e-3, 1e-3, f"factor {m}")
 
 
 def test_non_finite_batch_is_refused_without_change(lib):
@@ -215,8 +216,9 @@ def test_dense4d_benchmark_configuration(lib):
     benchmark launches it (FP32, 120^4 + one batch of 12 slices, R = 10,
     s = 4, r = 10, 30 sweeps), against the oracle's update of the same data:
     every sampled index and every matching exact; per repetition the summary
-    lambda and the last-mode rows, and the grown model, within 1e-3
-    (relative, in norm) of the FP64 oracle; fits within 1e-3."""
+    lambda and the last-mode rows, and the grown model, element by element
+    within 1e-3 of the entry plus 1e-3 of the column's largest entry of the
+    FP64 oracle; fits within 1e-3."""
     torch = _torch()
     dims, K0, Kn, R, s, r, iters, seed = (120, 120, 120), 120, 12, 10, 4, 10, 30, 6
     gen = synth.DenseCPN(dims + (K0 + Kn,), R, seed=seed, noise=0.01, dtype=np.float32)
@@ -235,17 +237,16 @@ def test_dense4d_benchmark_configuration(lib):
     d = ora.update(X[..., K0:], debug=True)
     check_samples(lib, gpu, d, 4, r)
 
-    def rel(a, b):
-        return np.linalg.norm(a - b) / np.linalg.norm(b)
-
     for rho in range(r):
         rr = d["reps"][rho]
         np.testing.assert_array_equal(gpu.last_rep_nd(rho, lib.SBT_ND_REP_PI), rr["pi"])
-        assert rel(gpu.last_rep_nd(rho, lib.SBT_ND_REP_LAMP), rr["lamp"]) < 1e-3
-        assert rel(gpu.last_rep_nd(rho, lib.SBT_ND_REP_CT), rr["Ct"]) < 1e-3
+        assert_close(gpu.last_rep_nd(rho, lib.SBT_ND_REP_LAMP), rr["lamp"], 1e-3, 1e-3,
+                     f"lambda' rep {rho}")
+        assert_close(gpu.last_rep_nd(rho, lib.SBT_ND_REP_CT), rr["Ct"], 1e-3, 1e-3,
+                     f"C~ rep {rho}")
     G, _ = gpu.get_factors_nd()
     for m in range(4):
-        assert rel(G[m], ora.U[m]) < 1e-3, m
+        assert_close(G[m], ora.U[m], 1e-3, 1e-3, f"factor {m}")
     assert abs(gpu.fit() - ora.fit()) < 1e-3
 
 

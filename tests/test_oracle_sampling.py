@@ -162,3 +162,19 @@ def test_exponential_keys_are_successive_sampling(w, n):
     # a with-replacement or inclusion-proportional scheme would put mass elsewhere:
     # every observed subset must be one the exact enumeration allows
     assert set(counts) <= set(exact)
+
+
+def test_sample_size_is_the_ceiling_for_ragged_ratios():
+    # n = ceil(N / s) (Sec. 3.1 samples a 1/s fraction of each mode; the rounding
+    # is the reading taken): the smallest n with n * s >= N, at least 1 and at
+    # most N.  Checked by counting up rather than by a formula, over ragged and
+    # exact ratios, s larger than N and s = 1.
+    for N in list(range(1, 40)) + [99, 100, 101, 997, 100000, 100001]:
+        for s in (1, 2, 3, 5, 7, 10, 16, 41, 1000):
+            n = 1
+            while n * s < N:
+                n += 1
+            assert sb.sample_size(N, s) == min(n, N), (N, s)
+    # a floor slip would give 0 or N // s here
+    assert sb.sample_size(11, 5) == 3 and sb.sample_size(4, 5) == 1
+    assert sb.sample_size(100001, 10) == 10001
