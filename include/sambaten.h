@@ -243,6 +243,36 @@ sbt_status sbt_mttkrp_dense(int32_t precision, int32_t schedule, const void* Z_d
                             const double* U1_dev, const double* U2_dev, int32_t mode,
                             double* out_dev, void* stream);
 
+/* sbt_mttkrp_dense for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, same kernels and the same result as sbt_mttkrp_dense, but
+ * no hipMalloc/hipFree and no host-to-device copy: the temporary buffers
+ * (the contraction W, the BF16 relayouts and partial rows, the identity
+ * V^-1 and unit scales, which a kernel writes) are carved from one fixed
+ * device array of 64 MiB per GPU, held until the process ends.  The call
+ * only enqueues kernels on `stream` and returns; the result is written when
+ * the stream reaches them.  The first call on a device resolves that
+ * device's array address (hipGetSymbolAddress); make it outside graph
+ * capture.  Every call on one GPU uses the same array: calls that overlap on
+ * one GPU (two streams, two threads, or a second call enqueued before the
+ * first has run on a different stream) race and give undefined results;
+ * calls on one stream are ordered and safe.  Size limit: the bytes needed,
+ * each piece rounded up to 256, must fit 64 MiB:
+ *   FP64/FP32 modes 0, 1:  n1 n2 R x (8 for FP64, 4 for FP32) (+ 8 R^2 + 24 R
+ *                          in the batched schedule);
+ *   FP64/FP32 mode 2:      8 R^2 + 24 R (batched), nothing (plain);
+ *   BF16 (matrix cores):   both BF16 relayouts of Z (about 4 n1 n2 n3 bytes
+ *                          with padding) + 4 n1 n2 R + partial rows + staged
+ *                          operands.
+ * Errors: as sbt_mttkrp_dense; SBT_E_SHAPE also when the bytes needed exceed
+ * the 64 MiB array (nothing is enqueued then); SBT_E_DEVICE when the array's
+ * address cannot be resolved or a launch fails. */
+sbt_status sbt_mttkrp_dense_noalloc(int32_t precision, int32_t schedule, const void* Z_dev,
+                                    int64_t n1, int64_t n2, int64_t n3, int32_t R,
+                                    const double* U0_dev, const double* U1_dev,
+                                    const double* U2_dev, int32_t mode, double* out_dev,
+                                    void* stream);
+
 /* The same product for a COO tensor of extents n1 x n2 x n3 (the sparse
  * MTTKRP of the update's COO summaries, FP32 products and sums): entries
  * (a_dev[e], b_dev[e], c_dev[e], v_dev[e]), e < nnz, device arrays in any

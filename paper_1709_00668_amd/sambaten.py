@@ -80,6 +80,8 @@ _SIGS = {
     "sbt_last_rep": (ctypes.c_int, [_vp, _i32, _i32, _vp, _i64, ctypes.POINTER(_i64)]),
     "sbt_mttkrp_dense": (ctypes.c_int, [_i32, _i32, _vp, _i64, _i64, _i64, _i32, _vp, _vp, _vp,
                                         _i32, _vp, _vp]),
+    "sbt_mttkrp_dense_noalloc": (ctypes.c_int, [_i32, _i32, _vp, _i64, _i64, _i64, _i32, _vp, _vp,
+                                                _vp, _i32, _vp, _vp]),
     "sbt_mttkrp_coo": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _i64, _i64, _i64, _i32, _vp, _vp,
                                       _vp, _i32, _i32, _vp, _vp]),
     "sbt_profile_enable": (ctypes.c_int, [_vp, _i32]),
@@ -414,6 +416,16 @@ def mttkrp_dense(precision, Z_dev, n1, n2, n3, R, U0_dev, U1_dev, U2_dev, mode, 
     st = load().sbt_mttkrp_dense(precision, schedule, _ptr(Z_dev), n1, n2, n3, R, _ptr(U0_dev),
                                  _ptr(U1_dev), _ptr(U2_dev), mode, _ptr(out_dev), _stream(stream))
     _check(st, None, "sbt_mttkrp_dense")
+
+
+def mttkrp_dense_noalloc(precision, Z_dev, n1, n2, n3, R, U0_dev, U1_dev, U2_dev, mode, out_dev,
+                         stream=None, schedule=SBT_SCHED_BATCHED):
+    """Enqueues only (no allocation, no synchronisation): the result is ready
+    when `stream` reaches the launched kernels."""
+    st = load().sbt_mttkrp_dense_noalloc(precision, schedule, _ptr(Z_dev), n1, n2, n3, R,
+                                         _ptr(U0_dev), _ptr(U1_dev), _ptr(U2_dev), mode,
+                                         _ptr(out_dev), _stream(stream))
+    _check(st, None, "sbt_mttkrp_dense_noalloc")
 
 
 def mttkrp_coo(idx_dev, vals_dev, nnz, n1, n2, n3, R, U0_dev, U1_dev, U2_dev, mode, out_dev,
