@@ -167,7 +167,7 @@ class Config:
     def __init__(self, rank, reps, als_iters, sample_factor, seed, tensor_id=0,
                  init_iters=100, k_capacity=None, nnz_capacity=None, summary_bf16=False,
                  getrank_runs=0, getrank_threshold=90.0, persist_summaries=False,
-                 summary_refresh=0):
+                 summary_refresh=0, workers=1):
         self.rank = int(rank)
         self.reps = int(reps)
         self.als_iters = int(als_iters)
@@ -190,12 +190,35 @@ class Config:
         # CP-ALS starts from the previous summary factors
         self.persist_summaries = bool(persist_summaries)
         self.summary_refresh = int(summary_refresh)
+        # host threads for the independent repetitions and for blocks of slices
+        # (scheduling only: every result is the same for any count)
+        self.workers = max(1, int(workers))
         if self.persist_summaries and self.getrank_runs > 0:
             raise ValueError("persistent summaries and GetRank do not combine")
 
 
 class NumericError(ValueError):
     pass
+
+
+def _map_ordered(fn, items, workers):
+    """[fn(x) for x in items], on `workers` threads when workers > 1 (each
+    call's BLAS then runs on one thread); the results keep the items' order."""
+    items = list(items)
+    if workers <= 1 or len(items) <= 1:
+        return [fn(x) for x in items]
+    from concurrent.futures import ThreadPoolExecutor
+
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1, user_api="blas"):
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            return list(ex.map(fn, items))
+
+
+def _slice_blocks(X, block=32):
+    """Consecutive blocks of frontal slices of a dense (I, J, K) array (views)."""
+    for k0 in range(0, X.shape[2], block):
+        yield X[:, :, k0:k0 + block]
 
 
 class OracleTensor:
@@ -214,7 +237,9 @@ class OracleTensor:
             assert X0.shape == (I, J, K0)
             self.X = np.asfortranarray(X0)
             n_max = max(J * kcap, I * kcap, I * J)
-            max_x2 = float(np.max(np.asarray(X0, dtype=np.float64) ** 2)) if X0.size else 0.0
+            max_x2 = max([0.0] + _map_ordered(
+                lambda blk: float(np.max(np.asarray(blk, dtype=np.float64) ** 2)),
+                _slice_blocks(self.X), cfg.workers))
         else:
             idx, vals = coo0
             self.idx = np.asarray(idx, dtype=np.int64).reshape(-1, 3)
@@ -226,10 +251,14 @@ class OracleTensor:
             max_x2 = float(np.max(v64 * v64)) if v64.size else 0.0
         self.n_max = n_max
         self.S = moi_scale(max_x2, n_max)
-        q, ok = self._quant_all(self._data_values())
+        if fmt == DENSE:
+            w, ok = self._moi_dense(self.X)
+        else:
+            q, ok = self._quant_all(self.vals)
+            w = self._moi(q, (I, J, K0), None) if ok else None
         if not ok:
             raise NumericError("initial tensor: non-finite value or MoI overflow")
-        self.w = self._moi(q, (I, J, K0), None)
+        self.w = w
         R = cfg.rank
         if factors is None:
             A, B, C, lam = self.init_cp()
@@ -244,6 +273,25 @@ class OracleTensor:
 
     def _quant_all(self, x):
         return quantize_sq(x, self.S, self.n_max)
+
+    def _moi_dense(self, X):
+        """Eq. 1 of a dense block, taken over blocks of slices (the sums are
+        exact integers, so the blocking does not change them).  Returns
+        ([w1, w2, w3], ok)."""
+        def block_moi(blk):
+            q, ok = self._quant_all(blk)
+            return moi_dense(q) if ok else None
+
+        parts = _map_ordered(block_moi, _slice_blocks(X), self.cfg.workers)
+        if any(p is None for p in parts):
+            return None, False
+        w1 = np.zeros(X.shape[0], dtype=np.uint64)
+        w2 = np.zeros(X.shape[1], dtype=np.uint64)
+        for d1, d2, _ in parts:
+            w1 += d1
+            w2 += d2
+        w3 = np.concatenate([p[2] for p in parts]) if parts else np.zeros(0, dtype=np.uint64)
+        return [w1, w2, w3], True
 
     def _moi(self, q, dims, idx):
         if self.fmt == DENSE:
@@ -273,7 +321,7 @@ class OracleTensor:
             Y = np.asarray(Y)
             assert Y.shape[0] == I and Y.shape[1] == J
             Kn = Y.shape[2]
-            q, ok = self._quant_all(Y)
+            dw, ok = self._moi_dense(Y)
         else:
             yidx, yvals, Kn = coo
             yidx = np.asarray(yidx, dtype=np.int64).reshape(-1, 3)
@@ -286,7 +334,10 @@ class OracleTensor:
 
         # Summaries are taken from X u Y: append first, sample from the old part.
         if self.fmt == DENSE:
-            XY = np.concatenate([self.X, Y], axis=2)
+            # column-major like the stored tensor (the unfoldings are views of it)
+            XY = np.empty((I, J, Kold + Kn), dtype=np.result_type(self.X, Y), order="F")
+            XY[:, :, :Kold] = self.X
+            XY[:, :, Kold:] = Y
         else:
             shifted = yidx.copy()
             shifted[:, 2] += Kold
@@ -296,8 +347,7 @@ class OracleTensor:
         n = [sample_size(I, cfg.s[0]), sample_size(J, cfg.s[1]), sample_size(Kold, cfg.s[2])]
         reuse = (cfg.persist_summaries and self.kept is not None and
                  not (cfg.summary_refresh > 0 and self.t % cfg.summary_refresh == 0))
-        reps = []
-        for rho in range(cfg.reps):
+        def one_rep(rho):
             if reuse:
                 Is, Js, Ks = self.kept[rho][:3]
             else:
@@ -307,7 +357,7 @@ class OracleTensor:
             Kp = np.concatenate([Ks, Kold + np.arange(Kn)])
             dims_s = (len(Is), len(Js), len(Kp))
             if self.fmt == DENSE:
-                Z = np.asarray(XY[np.ix_(Is, Js, Kp)], dtype=np.float64)
+                Z = np.asfortranarray(XY[np.ix_(Is, Js, Kp)], dtype=np.float64)
                 if cfg.summary_bf16:
                     Z = cp.round_bf16(Z)
 
@@ -369,9 +419,13 @@ class OracleTensor:
             Ct = np.zeros_like(D)
             lz = self.lam > 0
             Ct[:, lz] = D[:, lz] / self.lam[lz]
-            reps.append(dict(Is=Is, Js=Js, Ks=Ks, Ap=Ap, Bp=Bp, Cp=Cp, lamp=lamp, pi=pi,
-                             sigA=sigA, sigB=sigB, nA=nA, nB=nB, S=S, valid=valid, At=At,
-                             Bt=Bt, Ct=Ct, Dm=Dm, npinv=npinv, Rnew=Rn, cc=cc))
+            return dict(Is=Is, Js=Js, Ks=Ks, Ap=Ap, Bp=Bp, Cp=Cp, lamp=lamp, pi=pi,
+                        sigA=sigA, sigB=sigB, nA=nA, nB=nB, S=S, valid=valid, At=At,
+                        Bt=Bt, Ct=Ct, Dm=Dm, npinv=npinv, Rnew=Rn, cc=cc)
+
+        # the repetitions are independent (Sec. 3.1: no synchronisation between
+        # them); with workers > 1 they run concurrently, collected in order
+        reps = _map_ordered(one_rep, range(cfg.reps), cfg.workers)
 
         A_new, B_new, C_old = self.A.copy(), self.B.copy(), self.C.copy()
         # Zero-entry update over the sampled rows (Algorithm 1), order free.
@@ -398,8 +452,7 @@ class OracleTensor:
         self.A, self.B = A_new, B_new
         self.C = np.vstack([C_old, C_new])
         if self.fmt == DENSE:
-            self.X = np.asfortranarray(XY)
-            dw = moi_dense(q)
+            self.X = XY
             self.w = [self.w[0] + dw[0], self.w[1] + dw[1], np.concatenate([self.w[2], dw[2]])]
         else:
             self.idx, self.vals = XYidx, XYvals
@@ -444,11 +497,26 @@ class OracleTensor:
 
     # -- fit (Sec. 4.2 relative error) ---------------------------------------------
     def norm2(self):
-        v = np.asarray(self._data_values(), dtype=np.float64)
+        if self.fmt == DENSE:
+            def block_sum(blk):
+                v = np.asarray(blk, dtype=np.float64)
+                return float(np.sum(v * v))
+            total = 0.0
+            for part in _map_ordered(block_sum, _slice_blocks(self.X), self.cfg.workers):
+                total += part
+            return total
+        v = np.asarray(self.vals, dtype=np.float64)
         return float(np.sum(v * v))
 
     def fit(self):
-        M3 = self.mttkrp_full([self.A, self.B, self.C], 2)
+        if self.fmt == DENSE:
+            # X_(3) (B kr A) row by row of slices: row k depends on slice k only
+            KR = cp.khatri_rao(self.B, self.A)
+            M3 = np.vstack(_map_ordered(
+                lambda blk: cp.unfold(np.asarray(blk, dtype=np.float64), 2) @ KR,
+                _slice_blocks(self.X, 64), self.cfg.workers))
+        else:
+            M3 = self.mttkrp_full([self.A, self.B, self.C], 2)
         return cp.fit_gram(self.norm2(), self.A, self.B, self.C, self.lam, M3)
 
     def fit_explicit(self):

@@ -253,3 +253,29 @@ def test_persistent_warm_start_on_exact_data():
     Bp0 = r0["Bp"]
     cos = np.abs(np.sum(cp.normalize_columns(r1["Bp"])[0] * Bp0, axis=0))
     assert np.all(cos > 1 - 1e-9)
+
+
+def test_worker_threads_change_nothing():
+    # repetitions on a thread pool and importance / fit over blocks of slices on
+    # it: the same samples, matchings and importance, factors and fit to rounding
+    g = np.random.default_rng(12)
+    I, J, K0, Kn, R = 30, 26, 70, 6, 3
+    X = g.random((I, J, K0 + 2 * Kn))
+    X[3, 4, 5] = 0.0
+    out = []
+    for workers in (1, 4):
+        cfg = sb.Config(rank=R, reps=5, als_iters=8, sample_factor=2, seed=9,
+                        k_capacity=K0 + 2 * Kn, workers=workers)
+        o = sb.OracleTensor(cfg, sb.DENSE, (I, J, K0), X0=X[:, :, :K0])
+        ds = [o.update(X[:, :, K0 + b * Kn:K0 + (b + 1) * Kn], debug=True) for b in range(2)]
+        out.append((o, ds))
+    (o1, d1), (o4, d4) = out
+    for w1, w4 in zip(o1.w, o4.w):
+        assert np.array_equal(w1, w4)
+    for a, b in zip(d1, d4):
+        for r1, r4 in zip(a["reps"], b["reps"]):
+            for key in ("Is", "Js", "Ks", "pi", "valid"):
+                assert np.array_equal(r1[key], r4[key]), key
+    for M1, M4 in ((o1.A, o4.A), (o1.B, o4.B), (o1.C, o4.C)):
+        np.testing.assert_allclose(M1, M4, rtol=1e-10, atol=1e-12)
+    assert abs(o1.fit() - o4.fit()) < 1e-12
