@@ -172,46 +172,40 @@ __global__ void ft_kernel(RepSet rs, int rows, int ld, int nf, const double* F, 
 // ---------------------------------------------------------------------------
 // Block = 4 wavefronts x 4 tiles of 16 rows e (256 rows) of one repetition;
 // every wave runs the whole K range (K' rounded up to 32) against C~^T hi and
-// lo, copied into LDS once per block.  hi and lo products go to separate
-// accumulators (no back-to-back dependence between the two MFMAs).
+// lo, copied into LDS by the block in chunks of at most pw_mfma_chunk(NT)
+// columns (one chunk, staged once, whenever K' fits; a barrier between
+// chunks otherwise).  hi and lo products go to separate accumulators (no
+// back-to-back dependence between the two MFMAs).
 constexpr int kWTiles = 4;   // row tiles per wavefront
 constexpr int kWSteps = 2;   // K steps whose operand loads are in flight at once
+
+// columns of C~ staged per chunk: hi and lo rows [16 NT][chunk + 8] of BF16
+// within 64 KB, a multiple of 32
+constexpr int pw_mfma_chunk(int nt) { return (65536 / (2 * 16 * nt * 2) - 8) / 32 * 32; }
 
 template <int NT>
 __global__ __launch_bounds__(256) void pw_mfma_kernel(RepSet rs, MfmaLayout L, int kp32,
                                                      const uint16_t* Zc, const uint16_t* Ctg,
                                                      float* W) {
   extern __shared__ __align__(16) unsigned char pwm_smem[];
-  const int ldt = kp32 + 8;
+  constexpr int kChunk = pw_mfma_chunk(NT);
+  const int ldg = kp32 + 8;                            // row stride of the global C~ rows
+  const int chunk = kp32 < kChunk ? kp32 : kChunk;
+  const int ldt = chunk + 8;                           // row stride in LDS
   uint16_t* Ct = reinterpret_cast<uint16_t*>(pwm_smem);  // hi part [16 NT][ldt], then lo
+  const uint16_t* Cl = Ct + 16 * NT * ldt;
   const int rep = rs.rep0 + blockIdx.y;
   const int R = rs.R;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int64_t n12 = (int64_t)rs.n1 * rs.n2;
   const int64_t e0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * kWTiles);
   const int kq = lane >> 4;
-  const int ksteps = kp32 / 32;
   const uint16_t* zrow[kWTiles];
 #pragma unroll
   for (int t = 0; t < kWTiles; ++t) {
     const int64_t e = e0 + 16 * t + (lane & 15);
     zrow[t] = Zc + rep * L.sZc + (e < n12 ? e : n12 - 1) * L.ldc + 8 * kq;
   }
-  // first operand loads before the staging
-  bf16x8_t af[kWSteps][kWTiles];
-#pragma unroll
-  for (int u = 0; u < kWSteps; ++u)
-#pragma unroll
-    for (int t = 0; t < kWTiles; ++t)
-      if (u < ksteps) af[u][t] = ld_bf16x8(zrow[t] + 32 * u);
-  {
-    const int64_t n16 = (int64_t)2 * 16 * NT * ldt / 8;  // 16-byte words of hi and lo
-    const uint4* src = reinterpret_cast<const uint4*>(Ctg + (int64_t)rep * 2 * 16 * NT * ldt);
-    uint4* dst = reinterpret_cast<uint4*>(Ct);
-    for (int64_t q = tid; q < n16; q += 256) dst[q] = src[q];
-  }
-  __syncthreads();
-  const uint16_t* Cl = Ct + 16 * NT * ldt;
   f32x4_t ah[kWTiles][NT], al[kWTiles][NT];
 #pragma unroll
   for (int t = 0; t < kWTiles; ++t)
@@ -220,25 +214,52 @@ __global__ __launch_bounds__(256) void pw_mfma_kernel(RepSet rs, MfmaLayout L, i
       ah[t][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
       al[t][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
     }
-  for (int k0 = 0; k0 < ksteps; k0 += kWSteps) {
-    if (k0 > 0) {
+  const uint4* src = reinterpret_cast<const uint4*>(Ctg + (int64_t)rep * 2 * 16 * NT * ldg);
+  uint4* dst = reinterpret_cast<uint4*>(Ct);
+  bf16x8_t af[kWSteps][kWTiles];
+  for (int c0 = 0; c0 < kp32; c0 += chunk) {
+    const int cw = kp32 - c0 < chunk ? kp32 - c0 : chunk;  // a multiple of 32
+    const int ksteps = cw / 32;
+    const uint16_t* zc[kWTiles];
 #pragma unroll
-      for (int u = 0; u < kWSteps; ++u)
+    for (int t = 0; t < kWTiles; ++t) zc[t] = zrow[t] + c0;
+    // first operand loads of the chunk before its staging
 #pragma unroll
-        for (int t = 0; t < kWTiles; ++t)
-          if (k0 + u < ksteps) af[u][t] = ld_bf16x8(zrow[t] + 32 * (k0 + u));
+    for (int u = 0; u < kWSteps; ++u)
+#pragma unroll
+      for (int t = 0; t < kWTiles; ++t)
+        if (u < ksteps) af[u][t] = ld_bf16x8(zc[t] + 32 * u);
+    if (c0 > 0) __syncthreads();  // every wave is done with the previous chunk
+    {
+      // 16-byte words: rows (hi, then lo) of cw / 8 words each
+      const int wpr = cw / 8;
+      const int nrow = 2 * 16 * NT;
+      for (int q = tid; q < nrow * wpr; q += 256) {
+        const int row = q / wpr, w = q - row * wpr;
+        dst[row * (ldt / 8) + w] = src[row * (ldg / 8) + c0 / 8 + w];
+      }
     }
+    __syncthreads();
+    for (int k0 = 0; k0 < ksteps; k0 += kWSteps) {
+      if (k0 > 0) {
 #pragma unroll
-    for (int u = 0; u < kWSteps; ++u) {
-      if (k0 + u < ksteps) {
+        for (int u = 0; u < kWSteps; ++u)
 #pragma unroll
-        for (int j = 0; j < NT; ++j) {
-          const int o = (16 * j + (lane & 15)) * ldt + 32 * (k0 + u) + 8 * kq;
-          const bf16x8_t bh = ld_bf16x8(Ct + o), bl = ld_bf16x8(Cl + o);
+          for (int t = 0; t < kWTiles; ++t)
+            if (k0 + u < ksteps) af[u][t] = ld_bf16x8(zc[t] + 32 * (k0 + u));
+      }
 #pragma unroll
-          for (int t = 0; t < kWTiles; ++t) {
-            ah[t][j] = mfma16x16x32(af[u][t], bh, ah[t][j]);
-            al[t][j] = mfma16x16x32(af[u][t], bl, al[t][j]);
+      for (int u = 0; u < kWSteps; ++u) {
+        if (k0 + u < ksteps) {
+#pragma unroll
+          for (int j = 0; j < NT; ++j) {
+            const int o = (16 * j + (lane & 15)) * ldt + 32 * (k0 + u) + 8 * kq;
+            const bf16x8_t bh = ld_bf16x8(Ct + o), bl = ld_bf16x8(Cl + o);
+#pragma unroll
+            for (int t = 0; t < kWTiles; ++t) {
+              ah[t][j] = mfma16x16x32(af[u][t], bh, ah[t][j]);
+              al[t][j] = mfma16x16x32(af[u][t], bl, al[t][j]);
+            }
           }
         }
       }
@@ -487,7 +508,8 @@ hipError_t launch_pw_mfma(const RepSet& rs, const MfmaLayout& L, const uint16_t*
   }
   const int64_t rows_per_block = 4 * 16 * kWTiles;
   dim3 grid((unsigned)((n12 + rows_per_block - 1) / rows_per_block), (unsigned)rs.nrep);
-  const size_t sh = (size_t)2 * nf * (kp32 + 8) * 2;
+  const int chunk = kp32 < pw_mfma_chunk(nt) ? kp32 : pw_mfma_chunk(nt);
+  const size_t sh = (size_t)2 * nf * (chunk + 8) * 2;
   if (sh > 65536) return hipErrorInvalidValue;
   if (nt == 1)
     timed_launch(pw_mfma_kernel<1>, grid, dim3(256), sh, s, rs, L, kp32, Zc, Ct, W);

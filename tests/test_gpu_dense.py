@@ -285,6 +285,44 @@ def test_mttkrp_bf16_rank_tiles(lib, R):
         assert rel <= 1e-2, (mode, rel)
 
 
+@pytest.mark.parametrize("R", [5, 20])
+def test_mttkrp_bf16_long_third_mode(lib, R):
+    # a third mode longer than one LDS chunk of C~ in the matrix-core pass W
+    # (992 columns at R <= 16, 480 above): n3 = 1100 takes two and three chunks
+    torch = _torch()
+    g = np.random.default_rng(400 + R)
+    n1, n2, n3 = 24, 21, 1100
+    Z = g.random((n1, n2, n3))
+    U = [g.random((n, R)) for n in (n1, n2, n3)]
+    bits, Zr = bf16_round(Z)
+    Zd = torch.from_numpy(np.ascontiguousarray(bits.transpose(2, 1, 0)).view(np.int16)).cuda()
+    Ud = [torch.from_numpy(np.ascontiguousarray(u)).cuda() for u in U]
+    for mode in range(3):
+        out = torch.zeros((Z.shape[mode], R), dtype=torch.float64, device="cuda")
+        lib.mttkrp_dense(2, Zd, n1, n2, n3, R, Ud[0], Ud[1], Ud[2], mode, out)
+        torch.cuda.synchronize()
+        ref = cp.mttkrp_dense(Zr, U, mode)
+        got = out.cpu().numpy()
+        rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        assert rel <= 1e-2, (mode, rel)
+        assert_close(got, ref, 1e-2, 1e-3, f"mode {mode}")
+
+
+def test_bf16_update_with_long_summaries(lib):
+    # s = 2 over 1000 old slices: K' = 500 + 10 = 510, then 505 + 10 = 515
+    # summary slices at R = 20, past one chunk (480 columns) of the matrix-core
+    # pass W staging
+    reps = 2
+    ora, gpu, ds = run_pair(lib, 40, 36, 1000, 10, 20, reps, 8, 2, 13, lib.SBT_P_BF16,
+                            batches=2, init="true", oracle_bf16=True)
+    check_samples(gpu, ds[-1], reps)
+    assert len(ds[-1]["reps"][0]["Ks"]) + 10 > 480
+    A, _, C, _ = gpu.get_factors()
+    assert abs(gpu.fit() - ora.fit()) < 1e-4
+    assert_close(C[1000:], ora.C[1000:], RT, AT, "new rows of C")
+    assert_close(A, ora.A, RT, AT, "A")
+
+
 def test_bf16_update_matches_oracle(lib):
     # BF16 summaries on the matrix cores, FP64 solves.  Bars: samples bit-exact;
     # fit within 1e-3 of the FP64 oracle; new rows of C within 1e-3 of the
