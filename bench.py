@@ -4,14 +4,14 @@
 Workloads (--workload; all inputs seeded and synthetic, resident in HBM
 before timing, the model starting from the generator's factors):
 
-  dense500    (default) dense FP32 500 x 500 x 500, rank-10 U[0,1) CP model
-              plus 1% Gaussian noise, update batches of 50 frontal slices;
-              s = 5, r = 10, 30 ALS sweeps.  `value` is the batched FP32
-              schedule; the plain FP32 schedule and the batched BF16
-              (matrix-core) path run on the same batches beside it.
-  dense2000   dense 2000 x 2000 x 1000, rank 20, batches of 100 slices, s = 5,
-              r = 10, 30 sweeps: batched BF16 (matrix cores) = `value`, batched
-              FP32 and plain FP32 beside it.
+  dense2000   (default; the largest single-GPU workload) dense FP32 2000 x 2000
+              x 1000, rank-20 U[0,1) CP model plus 1% Gaussian noise generated on
+              the GPU, batches of 100 slices, s = 5, r = 10, 30 sweeps: batched
+              BF16 (matrix cores) = `value`, batched FP32 and plain FP32 beside it.
+  dense500    dense FP32 500 x 500 x 500, rank-10 U[0,1) CP model plus 1% noise,
+              update batches of 50 frontal slices; s = 5, r = 10, 30 ALS sweeps.
+              `value` is the batched FP32 schedule; the plain FP32 schedule and
+              the batched BF16 (matrix-core) path run on the same batches.
   dense4d     dense FP32 order-4 120 x 120 x 120 x 120 (the last mode grows),
               rank-10 U[0,1) CP model plus 1% noise, batches of 12 slices; s = 4
               on every mode, r = 10, 30 ALS sweeps.  `value` is the FP32 path; the
@@ -40,17 +40,20 @@ launch carries an event pair, so the timing costs the update little), with its a
 bytes per launch (summary elements read once, factor rows, outputs written
 once) against 8 TB/s; `traffic` comes from hardware counters of the same
 kernel when a committed measurement of the current kernel sources exists.
-cpu_baseline (dense workloads): the CPU FP64 oracle on the first
---cpu-updates updates of the same workload.  recompute (dense workloads):
+cpu_baseline (dense workloads): the CPU FP64 oracle on the first update of the
+same data (its repetitions and BLAS on the host threads), and
+vs_oracle_first_update: the fit of every GPU path after that same update
+against the oracle's (|dfit|) and the relative error of its new rows of C.
+recompute (dense workloads):
 CP-ALS of the whole grown tensor on the GPU and the relative fitness of the
 incremental result against it (Sec. 4.2); fms_truth: the factor match score
 (Sec. 4.4, on the GPU) of the final model against the generating components.
-getrank (dense workloads): the batched FP32 update with GetRank (Sec. 3.2) on
-every summary.  persistent (dense and sparse workloads): the main path with
-persistent summaries (samples of the first update kept, warm-started summary
+getrank_full_rank_data (dense workloads, --getrank-runs > 0): the batched FP32
+update with GetRank (Sec. 3.2) on every summary of this full-rank data.
+persistent (dense and sparse workloads): the main path with persistent summaries (samples of the first update kept, warm-started summary
 CP-ALS; the old part of each summary kept, so only the new slices are read).
 
-    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--workload dense500]
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--workload dense2000]
 """
 
 import argparse
@@ -72,7 +75,7 @@ WORKLOADS = {
                      desc="dense FP32 500x500x500 + 50-slice batches, rank 10, s=5, r=10, "
                           "30 ALS sweeps"),
     "dense2000": dict(kind="dense", I=2000, J=2000, K0=1000, Kn=100, R=20, s=5, r=10,
-                      iters=30, seed=5, noise=0.01,
+                      iters=30, seed=5, noise=0.01, device_data=True,
                       desc="dense 2000x2000x1000 + 100-slice batches, rank 20, s=5, r=10, "
                            "30 ALS sweeps, BF16 summaries on the matrix cores"),
     "serve16": dict(kind="serve", tensors=16, requests=512, seed=4, s=5, r=10, iters=30,
@@ -129,16 +132,22 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs), q)) if xs else None
 
 
-def timed_sequence(sbt, torch, fresh, apply_batch, steps, warmup, latency_runs, Kn, truth=None):
+def timed_sequence(sbt, torch, fresh, apply_batch, steps, warmup, latency_runs, Kn, truth=None,
+                   first=None):
     """Warm-up on a throwaway tensor, then exactly `steps` timed updates with the
     per-kind launch timing on; extra untimed sequences for latency samples.
-    truth: the generating model of the grown tensor, scored by FMS (GPU)."""
+    truth: the generating model of the grown tensor, scored by FMS (GPU).
+    first: a dict that receives the fit and the factors after the first update
+    (taken on the warm-up tensor, outside the timed region)."""
     kinds = {"mttkrp_contract_c": sbt.SBT_K_MTTKRP_C, "mttkrp_third_mode": sbt.SBT_K_MTTKRP_AB,
              "row_solve": sbt.SBT_K_ROW_SOLVE, "gather": sbt.SBT_K_GATHER,
              "coo_mttkrp": sbt.SBT_K_COO_MTTKRP, "update": sbt.SBT_K_UPDATE}
     T = fresh()
-    for b in range(min(warmup, steps)):
+    for b in range(max(min(warmup, steps), 1 if first is not None else 0)):
         apply_batch(T, b)
+        if b == 0 and first is not None:
+            first["fit"] = T.fit()
+            first["factors"] = T.get_factors()
     T.close()
     torch.cuda.synchronize()
     T = fresh()
@@ -177,7 +186,7 @@ def timed_sequence(sbt, torch, fresh, apply_batch, steps, warmup, latency_runs, 
 
 
 def run_dense(sbt, torch, w, Xd, model, precision, schedule, steps, warmup, latency_runs,
-              truth=None, getrank_runs=0, persist=False):
+              truth=None, getrank_runs=0, persist=False, first=None):
     I, J, K0, Kn = w["I"], w["J"], w["K0"], w["Kn"]
     cfg = sbt.make_config(w["R"], w["r"], w["iters"], w["s"], w["seed"], precision=precision,
                           schedule=schedule, k_capacity=K0 + steps * Kn, max_batch=Kn,
@@ -190,7 +199,7 @@ def run_dense(sbt, torch, w, Xd, model, precision, schedule, steps, warmup, late
         T.update_batch_dense(Xd[K0 + b * Kn:K0 + (b + 1) * Kn], Kn)
 
     return timed_sequence(sbt, torch, fresh, apply_batch, steps, warmup, latency_runs, Kn,
-                          truth=truth)
+                          truth=truth, first=first)
 
 
 CSRC = os.path.join(ROOT, "paper_1709_00668_amd", "csrc")
@@ -282,23 +291,39 @@ def path_summary(res):
             "p99_ms": round(res["p99_ms"], 3), "fit": round(res["fit"], 6)}
 
 
-def cpu_baseline_dense(w, X, model, updates):
-    """The CPU FP64 oracle on the first `updates` updates of the same workload."""
+def host_threads():
+    """Host threads the oracle may use: the machine's CPU share (OMP_NUM_THREADS
+    there), at most 16."""
+    return max(1, min(16, int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)))
+
+
+def oracle_first_update(w, X, model, log):
+    """The CPU FP64 oracle on the first update of the same data: X is the host
+    (I, J, K0 + Kn) tensor; its r repetitions (independent, Sec. 3.1) and its
+    blocks of slices run on the host threads.  Returns (cpu_baseline entry,
+    oracle fit after the update, oracle C rows of the new slices)."""
     from oracle import sambaten as osb
     K0, Kn = w["K0"], w["Kn"]
+    threads = host_threads()
     cfg = osb.Config(rank=w["R"], reps=w["r"], als_iters=w["iters"], sample_factor=w["s"],
-                     seed=w["seed"], k_capacity=K0 + updates * Kn)
+                     seed=w["seed"], k_capacity=K0 + Kn, workers=threads)
+    t0 = time.perf_counter()
     ora = osb.OracleTensor(cfg, osb.DENSE, (w["I"], w["J"], K0), X0=X[:, :, :K0],
                            factors=model)
+    log(f"# oracle: importance of the {K0} initial slices ({time.perf_counter() - t0:.1f} s)")
     t0 = time.perf_counter()
-    for b in range(updates):
-        ora.update(X[:, :, K0 + b * Kn:K0 + (b + 1) * Kn])
+    ora.update(X[:, :, K0:K0 + Kn])
     dt = time.perf_counter() - t0
-    threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
-    return dict(value=round(updates * Kn / dt, 3), unit="slices/s", cores=int(threads),
-                kind="oracle", fit_after=round(ora.fit(), 6),
-                sample=f"the first {updates} updates ({Kn} slices each, r={w['r']}, "
-                       f"{w['iters']} ALS sweeps) of the same workload, {dt:.1f} s")
+    log(f"# oracle: first update in {dt:.1f} s")
+    t0 = time.perf_counter()
+    fit = ora.fit()
+    log(f"# oracle: fit {fit:.6f} over {K0 + Kn} slices ({time.perf_counter() - t0:.1f} s)")
+    cpu = dict(value=round(Kn / dt, 3), unit="slices/s", cores=threads, kind="oracle",
+               fit_after=round(fit, 6), seconds=round(dt, 2),
+               sample=f"the first update ({Kn} slices, all r={w['r']} repetitions, "
+                      f"{w['iters']} ALS sweeps) of the same data, repetitions and BLAS on "
+                      f"{threads} host threads")
+    return cpu, fit, ora.C[K0:K0 + Kn].copy()
 
 
 def base_line(args, w, b, dtype):
@@ -335,25 +360,37 @@ def bench_dense(args, sbt, torch, synth, log):
     K = K0 + steps * Kn
     gen = synth.DenseCP(I, J, K, w["R"], seed=w["seed"], noise=w["noise"], dtype=np.float32)
     t0 = time.perf_counter()
-    Xkji = np.empty((K, J, I), dtype=np.float32)  # memory = column-major (I, J, K)
-    gen.fill_slices_kji(Xkji, 0, K)
-    Xd = torch.from_numpy(Xkji).cuda()
-    log(f"# data ready: {I}x{J}x{K} fp32, {Xkji.nbytes / 1e9:.2f} GB on device "
+    if w.get("device_data"):
+        # generated on the GPU (a tensor of this size takes minutes on the host);
+        # the oracle reads the same bytes copied back
+        Xd = torch.empty((K, J, I), dtype=torch.float32, device="cuda")  # column-major (I,J,K)
+        gen.fill_device(torch, Xd)
+        torch.cuda.synchronize()
+        Xkji = None
+    else:
+        Xkji = np.empty((K, J, I), dtype=np.float32)  # memory = column-major (I, J, K)
+        gen.fill_slices_kji(Xkji, 0, K)
+        Xd = torch.from_numpy(Xkji).cuda()
+    log(f"# data ready: {I}x{J}x{K} fp32, {4 * I * J * K / 1e9:.2f} GB on device "
         f"({time.perf_counter() - t0:.1f} s)")
     model = gen.true_model_prefix(K0)
     truth = gen.true_model_prefix(K)  # generating components of the grown tensor
     main_prec = sbt.SBT_P_F32 if name == "dense500" else sbt.SBT_P_BF16
     order = [("batched_f32", sbt.SBT_P_F32, sbt.SBT_SCHED_BATCHED),
              ("batched_bf16", sbt.SBT_P_BF16, sbt.SBT_SCHED_BATCHED)]
+    if main_prec == sbt.SBT_P_BF16:
+        order.reverse()
     if not args.no_plain:
         order.append(("plain_f32", sbt.SBT_P_F32, sbt.SBT_SCHED_PLAIN))
-    runs = {}
+    runs, firsts = {}, {}
     for key, prec, sched in order:
         main = prec == main_prec and sched == sbt.SBT_SCHED_BATCHED
         lr = args.latency_runs if main else max(1, min(args.latency_runs, 2))
+        firsts[key] = {}
         runs[key] = run_dense(sbt, torch, w, Xd, model, prec, sched, steps, args.warmup, lr,
-                              truth=truth if main else None)
-        log(f"# {key}: {runs[key]['slices_per_s']:.1f} slices/s, fit {runs[key]['fit']:.6f}")
+                              truth=truth if main else None, first=firsts[key])
+        log(f"# {key}: {runs[key]['slices_per_s']:.1f} slices/s, fit {runs[key]['fit']:.6f} "
+            f"(after the first update {firsts[key]['fit']:.6f})")
     main = "batched_f32" if main_prec == sbt.SBT_P_F32 else "batched_bf16"
     b = runs[main]
     path = "f32" if main == "batched_f32" else "bf16"
@@ -392,21 +429,41 @@ def bench_dense(args, sbt, torch, synth, log):
     if "fms_truth" in b:
         line["fms_truth"] = round(b["fms_truth"], 4)
     if args.getrank_runs > 0:
-        # GetRank (Sec. 3.2) on every summary: ranks 1..R, getrank_runs CP runs each
+        # GetRank (Sec. 3.2) on every summary: ranks 1..R, getrank_runs CP runs each.  This
+        # data is full rank R, where core consistency picks much lower ranks: a timing of
+        # the GetRank path, not an accuracy result (the rank-deficient workload is that)
         g = run_dense(sbt, torch, w, Xd, model, sbt.SBT_P_F32, sbt.SBT_SCHED_BATCHED, steps,
                       min(args.warmup, 1), 1, truth=truth, getrank_runs=args.getrank_runs)
-        line["getrank"] = dict(path_summary(g), runs=args.getrank_runs,
-                               fms_truth=round(g["fms_truth"], 4))
+        line["getrank_full_rank_data"] = dict(path_summary(g), runs=args.getrank_runs,
+                                              fms_truth=round(g["fms_truth"], 4))
         log(f"# getrank: {g['slices_per_s']:.1f} slices/s, fit {g['fit']:.6f}")
     if not args.no_persist:
         # persistent summaries: the first update's samples kept, warm-started summary CP-ALS
+        firsts["persistent"] = {}
         p = run_dense(sbt, torch, w, Xd, model, main_prec, sbt.SBT_SCHED_BATCHED, steps,
-                      args.warmup, 1, truth=truth, persist=True)
+                      args.warmup, 1, truth=truth, persist=True, first=firsts["persistent"])
         line["persistent"] = dict(path_summary(p), fms_truth=round(p["fms_truth"], 4))
         log(f"# persistent summaries: {p['slices_per_s']:.1f} slices/s, fit {p['fit']:.6f}")
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline_dense(w, Xkji.transpose(2, 1, 0), model, args.cpu_updates)
+        # the oracle on the first update of the same data, and every GPU path's fit and new
+        # rows after that update against it
+        t0 = time.perf_counter()
+        if Xkji is None:
+            Xkji = Xd[:K0 + Kn].cpu().numpy()
+        Xh = Xkji.transpose(2, 1, 0)[:, :, :K0 + Kn]   # (I, J, K) column-major view
+        log(f"# host copy of the first {K0 + Kn} slices ({time.perf_counter() - t0:.1f} s)")
+        cpu, fit_o, cnew_o = oracle_first_update(w, Xh, model, log)
+        par = {"oracle_fit": round(fit_o, 6), "paths": {}}
+        for key, f in firsts.items():
+            cnew = f["factors"][2][K0:K0 + Kn]
+            par["paths"][key] = {
+                "fit": round(f["fit"], 6), "abs_dfit": float(f"{abs(f['fit'] - fit_o):.3g}"),
+                "c_new_rel_err": float(f"{np.linalg.norm(cnew - cnew_o) / np.linalg.norm(cnew_o):.3g}")}
+        par["max_abs_dfit"] = max(v["abs_dfit"] for v in par["paths"].values())
+        line["vs_oracle_first_update"] = par
+        log(f"# |dfit| against the oracle after the first update: "
+            + ", ".join(f"{k} {v['abs_dfit']:.2e}" for k, v in par["paths"].items()))
     line["cpu_baseline"] = cpu
     for key in runs:
         if key != main:
@@ -723,7 +780,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--latency-runs", type=int, default=10)
-    ap.add_argument("--workload", default="dense500", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="dense2000", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-updates", type=int, default=2)
     ap.add_argument("--no-plain", action="store_true")
@@ -732,9 +789,9 @@ def main():
     ap.add_argument("--recompute-iters", type=int, default=100)
     ap.add_argument("--no-persist", action="store_true",
                     help="dense and sparse: skip the persistent-summary variant")
-    ap.add_argument("--getrank-runs", type=int, default=1,
-                    help="dense: also time the update with GetRank, this many CP runs per "
-                         "candidate rank (0: skip)")
+    ap.add_argument("--getrank-runs", type=int, default=0,
+                    help="dense: also time the update with GetRank on this full-rank data, "
+                         "this many CP runs per candidate rank (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=0,
                     help="requests of the serving workload (default: the workload's 512)")
     ap.add_argument("--nnz-scale", type=float, default=1.0,

@@ -73,6 +73,31 @@ class DenseCP:
             list(ex.map(one, range(k0, k1)))
         return out
 
+    def fill_device(self, torch, out, k0=0, block=64):
+        """The same model with noise drawn on the GPU, for tensors too large to
+        generate on the host: out (a CUDA tensor of shape (k1 - k0, J, I), the
+        column-major layout of the (I, J, k1 - k0) tensor) receives slices
+        k0..k1-1, each B diag(C(k, :)) A^T in FP64 plus sigma times standard
+        normals from a CUDA generator seeded per block of slices, rounded to
+        out's dtype.  The noise differs from slices(); both sides of a
+        comparison must read the bytes written here (copy them to the host for
+        the oracle)."""
+        dev = out.device
+        At = torch.from_numpy(np.ascontiguousarray(self.A.T)).to(dev)     # (R, I)
+        Bd = torch.from_numpy(self.B).to(dev)                              # (J, R)
+        Cd = torch.from_numpy(self.C).to(dev)                              # (K, R)
+        k1 = k0 + out.shape[0]
+        gen = torch.Generator(device=dev)
+        for b0 in range(k0, k1, block):
+            b1 = min(k1, b0 + block)
+            blk = torch.matmul(Bd[None, :, :] * Cd[b0:b1, None, :], At)   # (k, J, I)
+            if self.noise > 0:
+                gen.manual_seed((self.seed * 1000003 + STREAM_NOISE) * 1000003 + b0)
+                blk += self.sigma * torch.randn(blk.shape, generator=gen, device=dev,
+                                                dtype=torch.float64)
+            out[b0 - k0:b1 - k0] = blk.to(out.dtype)
+        return out
+
     def true_model(self):
         """Ground-truth factors normalised to unit columns, weights in lambda,
         ordered by lambda descending."""
