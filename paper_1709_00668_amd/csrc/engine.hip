@@ -315,7 +315,12 @@ RepSet make_repset(const sbt_tensor* t, int n3, int rep0, int nrep) {
   rs.R = t->R;
   rs.rep0 = rep0;
   rs.nrep = nrep;
-  rs.sZ = (int64_t)t->n1 * t->n2 * t->Kpmax;
+  // dense summary slices start on 128-byte lines: the streaming passes read
+  // each slice's rows in 256-byte pieces, which then never straddle a line
+  // shared with a piece another block reads
+  const int64_t al = 128 / (int64_t)prec_bytes(t->sum_prec);
+  rs.ldz = ((int64_t)t->n1 * t->n2 + al - 1) / al * al;
+  rs.sZ = rs.ldz * t->Kpmax;
   rs.sA = (int64_t)t->n1 * t->R;
   rs.sB = (int64_t)t->n2 * t->R;
   rs.sC = (int64_t)t->Kpmax * t->R;

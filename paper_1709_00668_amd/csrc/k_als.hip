@@ -66,7 +66,7 @@ __global__ __launch_bounds__(256) void gather_dense_kernel(const TIn* X, int64_t
   const int32_t* Is = idx + rep * idx_stride;
   const int64_t kk = c < n3old ? (int64_t)Is[offK + c] : Kold + (c - n3old);
   const int64_t src = (int64_t)Is[a] + I * ((int64_t)Is[offJ + b] + J * kk);
-  Z[rep * rs.sZ + e + n12 * c] = cvt_out(X[src], (TOut*)nullptr);
+  Z[rep * rs.sZ + e + zslice(rs) * c] = cvt_out(X[src], (TOut*)nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(256) void p1_kernel(RepSet rs, const TZ* Z, const d
   using TA = typename AccOf<TZ>::type;
   const int rep = rs.rep0 + blockIdx.y;
   const int R = rs.R;
-  const int64_t n12 = (int64_t)rs.n1 * rs.n2;
+  const int64_t n12 = (int64_t)rs.n1 * rs.n2, ldzc = zslice(rs);
   const int n3 = rs.n3;
   Z += rep * rs.sZ;
   Cf += rep * rs.sC;
@@ -202,10 +202,10 @@ __global__ __launch_bounds__(256) void p1_kernel(RepSet rs, const TZ* Z, const d
     }
     __syncthreads();
     if (e < n12) {
-      const TZ* zp = Z + e + n12 * c0;
+      const TZ* zp = Z + e + ldzc * c0;
 #pragma unroll 4
       for (int cc = 0; cc < cn; ++cc) {
-        const TA z = ldz(zp + n12 * cc);
+        const TA z = ldz(zp + ldzc * cc);
 #pragma unroll
         for (int f = 0; f < RP; ++f) acc[f] += z * Cs[cc][f];
       }
@@ -332,10 +332,10 @@ __global__ __launch_bounds__(256) void p2_kernel(RepSet rs, const TZ* Z, const d
   __shared__ P2Smem sm;
   const int rep = rs.rep0 + blockIdx.y;
   const int c = blockIdx.x;
-  const int64_t n12 = (int64_t)rs.n1 * rs.n2;
-  p2_body<TZ, TA, RP, false>(Z + rep * rs.sZ + n12 * c, rs.n1, rs.n2, rs.R, Af + rep * rs.sA,
-                             Bf + rep * rs.sB, M + rep * rs.sM + (int64_t)c * rs.R, nullptr,
-                             (TA*)sm.Bs, (TA(*)[kMaxRank + 1])sm.red);
+  p2_body<TZ, TA, RP, false>(Z + rep * rs.sZ + zslice(rs) * c, rs.n1, rs.n2, rs.R,
+                             Af + rep * rs.sA, Bf + rep * rs.sB,
+                             M + rep * rs.sM + (int64_t)c * rs.R, nullptr, (TA*)sm.Bs,
+                             (TA(*)[kMaxRank + 1])sm.red);
 }
 
 // Full-tensor pass for the fit: FP64 accumulation whatever the storage type.

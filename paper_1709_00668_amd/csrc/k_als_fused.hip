@@ -350,7 +350,7 @@ __global__ __launch_bounds__(256) void pw_kernel(RepSet rs, const TZ* Z, const d
   const int rep = rs.rep0 + blockIdx.y;
   const int R = rs.R;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int64_t n12 = (int64_t)rs.n1 * rs.n2;
+  const int64_t n12 = (int64_t)rs.n1 * rs.n2, ldzc = zslice(rs);
   const int n3 = rs.n3;
   Z += rep * rs.sZ;
   Cf += rep * rs.sC;
@@ -363,13 +363,13 @@ __global__ __launch_bounds__(256) void pw_kernel(RepSet rs, const TZ* Z, const d
   for (int cc0 = 0; cc0 < n3; cc0 += CH) {
     const int cn = n3 - cc0 < CH ? n3 - cc0 : CH;
     const int lo = (wave * cn) / 4, hi = ((wave + 1) * cn) / 4;
-    const TZ* zp = Z + e + n12 * cc0;
+    const TZ* zp = Z + e + ldzc * cc0;
     // the first KU summary loads go out before C~ is staged
     TA z[KU];
     const bool pre = ok && lo + KU <= hi;
     if (pre) {
 #pragma unroll
-      for (int u = 0; u < KU; ++u) z[u] = ld1(zp + n12 * (lo + u));
+      for (int u = 0; u < KU; ++u) z[u] = ld1(zp + ldzc * (lo + u));
     }
     __syncthreads();
     stage_rows<TA, RP>(&Cs[0][0], cn, Cf + (int64_t)cc0 * R, R, il);
@@ -385,14 +385,14 @@ __global__ __launch_bounds__(256) void pw_kernel(RepSet rs, const TZ* Z, const d
       }
       for (; c + KU <= hi; c += KU) {
 #pragma unroll
-        for (int u = 0; u < KU; ++u) z[u] = ld1(zp + n12 * (c + u));
+        for (int u = 0; u < KU; ++u) z[u] = ld1(zp + ldzc * (c + u));
 #pragma unroll
         for (int u = 0; u < KU; ++u)
 #pragma unroll
           for (int f = 0; f < RP; ++f) acc[f] += z[u] * Cs[c + u][f];
       }
       for (; c < hi; ++c) {
-        const TA zc = ld1(zp + n12 * c);
+        const TA zc = ld1(zp + ldzc * c);
 #pragma unroll
         for (int f = 0; f < RP; ++f) acc[f] += zc * Cs[c][f];
       }
@@ -606,7 +606,7 @@ __global__ __launch_bounds__(256) void p3_kernel(RepSet rs, const TZ* Z, const d
   const int nsub = kP3Team / span;
   const int sub = tt / span, gl = tt % span;
   const bool act = sub < nsub && c < rs.n3;
-  const TZ* Zc = Z + rep * rs.sZ + (int64_t)n1 * n2 * (c < rs.n3 ? c : 0);
+  const TZ* Zc = Z + rep * rs.sZ + zslice(rs) * (c < rs.n3 ? c : 0);
   // the first KU summary loads go out before A~ and B~ are staged
   TA z[KU][V];
   const bool pre = act && gl < ng && sub + (KU - 1) * nsub < n2;

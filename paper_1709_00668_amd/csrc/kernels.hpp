@@ -55,7 +55,12 @@ struct RepSet {
   int nsplit;       // partial sums per row of W (1: pass W writes complete rows)
   int64_t sM;       // max rows * R (double)
   int64_t sG;       // R*R
+  int64_t ldz = 0;  // stride between the slices c of a dense summary (0: n1*n2)
 };
+// elements from one slice of a dense summary to the next
+__host__ __device__ inline int64_t zslice(const RepSet& rs) {
+  return rs.ldz > 0 ? rs.ldz : (int64_t)rs.n1 * rs.n2;
+}
 
 // ---- importance (Eq. 1), integer form ------------------------------------
 hipError_t launch_fill_u64(uint64_t* p, int64_t n, uint64_t v, hipStream_t s);
