@@ -386,11 +386,12 @@ def bench_dense(args, sbt, torch, synth, log):
     for key, prec, sched in order:
         main = prec == main_prec and sched == sbt.SBT_SCHED_BATCHED
         lr = args.latency_runs if main else max(1, min(args.latency_runs, 2))
-        firsts[key] = {}
+        # the state after the first update, for the comparison with the oracle
+        first = None if args.no_cpu_baseline else firsts.setdefault(key, {})
         runs[key] = run_dense(sbt, torch, w, Xd, model, prec, sched, steps, args.warmup, lr,
-                              truth=truth if main else None, first=firsts[key])
-        log(f"# {key}: {runs[key]['slices_per_s']:.1f} slices/s, fit {runs[key]['fit']:.6f} "
-            f"(after the first update {firsts[key]['fit']:.6f})")
+                              truth=truth if main else None, first=first)
+        log(f"# {key}: {runs[key]['slices_per_s']:.1f} slices/s, fit {runs[key]['fit']:.6f}"
+            + (f" (after the first update {first['fit']:.6f})" if first else ""))
     main = "batched_f32" if main_prec == sbt.SBT_P_F32 else "batched_bf16"
     b = runs[main]
     path = "f32" if main == "batched_f32" else "bf16"
@@ -439,9 +440,9 @@ def bench_dense(args, sbt, torch, synth, log):
         log(f"# getrank: {g['slices_per_s']:.1f} slices/s, fit {g['fit']:.6f}")
     if not args.no_persist:
         # persistent summaries: the first update's samples kept, warm-started summary CP-ALS
-        firsts["persistent"] = {}
+        first = None if args.no_cpu_baseline else firsts.setdefault("persistent", {})
         p = run_dense(sbt, torch, w, Xd, model, main_prec, sbt.SBT_SCHED_BATCHED, steps,
-                      args.warmup, 1, truth=truth, persist=True, first=firsts["persistent"])
+                      args.warmup, 1, truth=truth, persist=True, first=first)
         line["persistent"] = dict(path_summary(p), fms_truth=round(p["fms_truth"], 4))
         log(f"# persistent summaries: {p['slices_per_s']:.1f} slices/s, fit {p['fit']:.6f}")
     cpu = None

@@ -25,7 +25,13 @@
  * - No C++ exception or abort crosses the ABI.  Every call returns an
  *   sbt_status; sbt_last_error() gives a message for the last failure on a
  *   tensor.  A failed sbt_update_* leaves the tensor exactly as it was.
- * - An sbt_tensor is not thread-safe: one call at a time per tensor.
+ * - One call at a time per tensor: a call made while another call on the
+ *   same tensor is in flight (another host thread), or while a server holds
+ *   queued or running requests of the tensor, returns SBT_E_BUSY and changes
+ *   nothing (the first call is unaffected).  sbt_destroy must not overlap
+ *   any other call on the tensor.
+ * - sbt_last_error(NULL) gives the message of the last failed call of the
+ *   calling host thread that had no tensor to record it on (sbt_load).
  */
 #ifndef SAMBATEN_H
 #define SAMBATEN_H
@@ -45,7 +51,9 @@ typedef enum {
   SBT_E_NOMEM = 3,    /* device allocation failed */
   SBT_E_DEVICE = 4,   /* a HIP runtime call failed */
   SBT_E_NUMERIC = 5,  /* non-finite input, or the integer importance sums would overflow */
-  SBT_E_STATE = 6     /* call not valid in the tensor's current state */
+  SBT_E_STATE = 6,    /* call not valid in the tensor's current state */
+  SBT_E_BUSY = 7      /* another call on the tensor is in flight, or a server
+                         holds requests of it; nothing was done */
 } sbt_status;
 
 typedef enum { SBT_DENSE = 0, SBT_COO = 1 } sbt_format;
@@ -181,6 +189,41 @@ sbt_status sbt_fit(sbt_tensor* t, double* fit, void* stream);
  * caller's.  Errors: SBT_E_INVALID for NULL pointers, SBT_E_DEVICE. */
 sbt_status sbt_fms(sbt_tensor* t, const double* A_ref, const double* B_ref, const double* C_ref,
                    const double* lambda_ref, double* score, void* stream);
+
+/* --------------------------------------------------------------------------
+ * Checkpoint and resume.  A checkpoint holds what the next updates depend
+ * on: the stored tensor (its K slices, or its nonzeros with their slice
+ * offsets), the model (A, B, C, lambda), the importance vectors of the three
+ * modes with their fixed-point scale, the batch counter that keys the
+ * sampler, the configuration, and with persistent summaries the kept sample
+ * indices and warm-start summary factors.  Updates applied to a loaded
+ * tensor give exactly the results they give on the tensor that was saved
+ * (the kept summaries are gathered again from the kept indices).  Third-order
+ * tensors only (an order-N tensor gives SBT_E_STATE).
+ * ------------------------------------------------------------------------ */
+
+/* Write the tensor's state to the file `path` (created or truncated; a
+ * little-endian binary of this library version).  Device data is copied out
+ * on `stream` through a pinned host buffer; returns when the file is
+ * written.  Errors: SBT_E_INVALID (NULL arguments, the file cannot be
+ * opened), SBT_E_DEVICE (a copy or a write failed: the file is incomplete),
+ * SBT_E_BUSY, SBT_E_STATE.  The tensor is not changed. */
+sbt_status sbt_save(sbt_tensor* t, const char* path, void* stream);
+
+/* Create a tensor from a file written by sbt_save, on the current device,
+ * allocating the capacity its configuration names.  *out receives the
+ * handle (NULL on error).  Errors: SBT_E_INVALID (cannot open, not a
+ * checkpoint of this version, inconsistent header, truncated file; message
+ * in sbt_last_error(NULL)), SBT_E_NOMEM, SBT_E_DEVICE. */
+sbt_status sbt_load(const char* path, void* stream, sbt_tensor** out);
+
+/* Device memory of a third-order tensor: *resident = its store at capacity,
+ * model and importance vectors; *workspace = everything else it holds (the
+ * r summaries and their factors, sampling, ALS and matching buffers, COO
+ * buffers grown so far), which is what an update works in and what a server
+ * charges a request against its HBM budget.  Either pointer may be NULL.
+ * SBT_E_STATE for an order-N tensor. */
+sbt_status sbt_memory_bytes(const sbt_tensor* t, int64_t* resident, int64_t* workspace);
 
 /* Number of completed updates (the batch counter that keys the sampler). */
 sbt_status sbt_get_batch_counter(const sbt_tensor* t, uint32_t* counter);
@@ -319,36 +362,57 @@ sbt_status sbt_profile_read(const sbt_tensor* t, int32_t kind, int64_t* launches
 /* --------------------------------------------------------------------------
  * Serving loop (many resident tensors, update requests arriving over time).
  *
- * A server owns `slots` worker threads, each driving its own HIP stream, and a
- * device staging pool of `staging_bytes`.  Requests are admitted in arrival
- * order when a slot is free, the request's tensor has no update in flight
- * (updates of one tensor apply in arrival order) and its batch fits the free
- * staging memory; a request that does not fit yet lets later requests of
- * other tensors start first.  On admission the batch is copied into the
- * staging pool on the slot's stream and the update runs there; updates of
- * different tensors overlap on the GPU.  Results equal those of the same
- * updates applied one by one with sbt_update_batch_dense.
+ * A server owns `slots` worker threads, each driving its own HIP stream, a
+ * device staging pool of `staging_bytes`, and an HBM budget for the working
+ * sets of the updates it runs at once.  A request's working set is its
+ * tensor's update workspace (everything the tensor holds besides its store,
+ * model and importance vectors: the r summaries, their factors, the sampling
+ * and ALS buffers and grown COO buffers, as they stand when the request is
+ * admitted; a COO tensor's summary buffers grow to fit its first updates)
+ * plus the request's staged batch.  Requests are admitted in arrival order
+ * when a slot is free, the request's tensor has no update in flight (updates
+ * of one tensor apply in arrival order), its batch fits the free staging
+ * memory and its working set fits what the running requests leave of the
+ * budget; a request that cannot start yet lets later requests of other
+ * tensors start first.  A request whose working set exceeds the whole budget
+ * fails with SBT_E_NOMEM when it comes up (reported by sbt_server_poll).  On
+ * admission the batch is copied into the staging pool on the slot's stream
+ * and the update runs there; updates of different tensors overlap on the
+ * GPU.  Results equal those of the same updates applied one by one with
+ * sbt_update_batch_dense / sbt_update_batch_coo.
  *
- * Thread safety: every sbt_server_* call may come from any host thread.  A
- * tensor handed to a server must not be used directly (update, get_factors,
- * fit, destroy) while it has requests queued or running.
+ * Thread safety: every sbt_server_* call may come from any host thread.
+ * While a server holds queued or running requests of a tensor, direct calls
+ * on it (update, get_factors, fit, fms, save) return SBT_E_BUSY; it must not
+ * be destroyed then.
  * ------------------------------------------------------------------------ */
 typedef struct sbt_server sbt_server;
 
-/* slots in 1..32; staging_bytes >= 256.  SBT_E_NOMEM if the pool cannot be
- * allocated. */
-sbt_status sbt_server_create(int32_t slots, int64_t staging_bytes, sbt_server** out);
+/* slots in 1..32; staging_bytes >= 256; hbm_budget_bytes >= 0 (0: no
+ * budget, admission by slots and staging memory only).  SBT_E_NOMEM if the
+ * pool cannot be allocated. */
+sbt_status sbt_server_create(int32_t slots, int64_t staging_bytes, int64_t hbm_budget_bytes,
+                             sbt_server** out);
 
 /* Queue an update of the dense tensor `t` by Y_dev (device, column-major
  * I x J x K_new in the tensor's store type).  Y_dev must hold its values
  * when submitted (the work that writes it complete: the server's streams do
  * not wait on the caller's), and stays valid until sbt_server_poll reports
- * the request running or done.  *ticket
- * identifies the request.  SBT_E_NOMEM if the batch is larger than the whole
- * staging pool, SBT_E_STATE for a COO tensor, SBT_E_SHAPE for K_new < 1;
- * errors of the update itself are reported by sbt_server_poll. */
+ * the request running or done.  *ticket identifies the request.
+ * SBT_E_NOMEM if the batch is larger than the whole staging pool or the
+ * budget, SBT_E_STATE for a COO or order-N tensor, SBT_E_SHAPE for
+ * K_new < 1; errors of the update itself are reported by sbt_server_poll. */
 sbt_status sbt_server_submit_dense(sbt_server* s, sbt_tensor* t, const void* Y_dev,
                                    int64_t K_new, uint64_t* ticket);
+
+/* Queue an update of the COO tensor `t` by nnz entries (i_dev, j_dev, k_dev,
+ * v_dev: device arrays as for sbt_update_batch_coo, k batch-relative); the
+ * four arrays are staged (16 bytes per entry, each array 256-byte aligned).
+ * Buffer lifetime, ticket and errors as for sbt_server_submit_dense
+ * (SBT_E_STATE for a dense tensor). */
+sbt_status sbt_server_submit_coo(sbt_server* s, sbt_tensor* t, const int32_t* i_dev,
+                                 const int32_t* j_dev, const int32_t* k_dev, const float* v_dev,
+                                 int64_t nnz, int64_t K_new, uint64_t* ticket);
 
 /* State of a request: *state 0 queued, 1 running, 2 done; *result the status
  * of the update once done; times in seconds since the server was created

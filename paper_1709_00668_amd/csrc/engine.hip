@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -105,7 +106,7 @@ struct sbt_tensor {
   int n3kept = 0;
   bool warm_now = false;   // this update's summary CP-ALS starts from Bw, Cw
   int warm_n3 = 0;
-  std::vector<void*> grow_allocs; // freed when regrown or destroyed
+  std::vector<std::pair<void*, size_t>> grow_allocs; // freed when regrown or destroyed
   int64_t last_summary_nnz = 0;
   // kernel timing (sbt_profile_*)
   bool prof_on = false;
@@ -125,6 +126,12 @@ struct sbt_tensor {
   bool has_last = false;
   int last_n3old = 0, last_Kp = 0;
   std::string errmsg;
+  // device bytes held: fixed allocations, of which the store and the model
+  // (store + A, B, C, lambda, importance); grown buffers are in grow_allocs
+  size_t bytes_fixed = 0, bytes_resident = 0;
+  // one call at a time (SBT_E_BUSY otherwise); server requests queued or running
+  std::atomic<bool> busy{false};
+  std::atomic<int> leases{0};
 };
 
 namespace {
@@ -156,6 +163,7 @@ sbt_status dalloc(sbt_tensor* t, T** p, size_t count) {
     return e == hipErrorOutOfMemory ? SBT_E_NOMEM : SBT_E_DEVICE;
   }
   t->allocs.push_back(q);
+  t->bytes_fixed += count * sizeof(T);
   *p = (T*)q;
   return SBT_OK;
 }
@@ -486,14 +494,14 @@ sbt_status galloc(sbt_tensor* t, T** p, size_t count) {
     set_err(t, std::string("hipMalloc: ") + hipGetErrorString(e));
     return e == hipErrorOutOfMemory ? SBT_E_NOMEM : SBT_E_DEVICE;
   }
-  t->grow_allocs.push_back(q);
+  t->grow_allocs.emplace_back(q, (count ? count : 1) * sizeof(T));
   *p = (T*)q;
   return SBT_OK;
 }
 
 void gfree(sbt_tensor* t, void* p) {
   for (size_t q = 0; q < t->grow_allocs.size(); ++q)
-    if (t->grow_allocs[q] == p) {
+    if (t->grow_allocs[q].first == p) {
       (void)hipFree(p);
       t->grow_allocs.erase(t->grow_allocs.begin() + (long)q);
       return;
@@ -1050,7 +1058,7 @@ void free_all(sbt_tensor* t) {
   t->graphs.clear();
   if (t->capst) (void)hipStreamDestroy(t->capst);
   t->capst = nullptr;
-  for (void* p : t->grow_allocs) (void)hipFree(p);
+  for (auto& g : t->grow_allocs) (void)hipFree(g.first);
   t->grow_allocs.clear();
   for (hipEvent_t e : t->prof_ev) (void)hipEventDestroy(e);
   t->prof_ev.clear();
@@ -1343,6 +1351,127 @@ sbt_status nd_fit(sbt_tensor* t, double* fit, hipStream_t st);
 void nd_release(sbt_tensor* t);
 bool nd_sample_span(const sbt_tensor* t, int mode, int64_t* off, int64_t* cnt);
 
+// One call at a time on a tensor: a second concurrent call, or a direct call
+// on a tensor a server holds requests of, gets SBT_E_BUSY (the first keeps
+// running; the tensor's error message is left alone).
+struct CallGuard {
+  sbt_tensor* t;
+  bool ok = false;
+  CallGuard(sbt_tensor* tt, bool from_server) : t(tt) {
+    if (!from_server && t->leases.load() > 0) return;
+    ok = !t->busy.exchange(true);
+  }
+  ~CallGuard() {
+    if (ok) t->busy.store(false);
+  }
+  CallGuard(const CallGuard&) = delete;
+  CallGuard& operator=(const CallGuard&) = delete;
+};
+
+// Message of the last failure of a call that has no tensor to record it on
+// (sbt_load, the stand-alone kernels), per host thread.
+thread_local std::string g_errmsg;
+
+// device bytes of the store, the model and the importance vectors
+size_t resident_bytes(const sbt_tensor* t) {
+  const size_t R = (size_t)t->R;
+  size_t b = ((size_t)t->I + t->J + t->Kcap) * (R + 1) * 8 + R * 8;
+  if (t->fmt == SBT_DENSE) b += (size_t)t->I * t->J * t->Kcap * prec_bytes(t->store_prec);
+  else b += (size_t)t->nnz_cap * 16;
+  return b;
+}
+
+// ---- checkpoint files ---------------------------------------------------
+// Little-endian binary: the header below, then the arrays in the order of
+// ckpt_arrays(), each as raw bytes (device layout).
+constexpr char kCkptMagic[8] = {'S', 'B', 'T', 'C', 'K', 'P', 'T', '1'};
+constexpr uint32_t kCkptVersion = 1;
+
+struct CkptHeader {
+  char magic[8];
+  uint32_t version, header_bytes;
+  sbt_config cfg;
+  int64_t I, J, K, Kcap, nnz;
+  int32_t R, fmt, store_prec, sum_prec, S;
+  uint32_t t;
+  uint64_t nmax;
+  int32_t have_kept, n3kept;
+  uint64_t payload_bytes;
+};
+
+struct CkptArray {
+  void* dev;
+  size_t bytes;
+};
+
+// The state a checkpoint holds: the stored tensor, the model, the importance
+// and, for persistent summaries, the kept indices and warm-start factors.
+std::vector<CkptArray> ckpt_arrays(sbt_tensor* t, bool have_kept) {
+  const size_t R = (size_t)t->R, K = (size_t)t->K;
+  std::vector<CkptArray> a;
+  if (t->fmt == SBT_DENSE) {
+    a.push_back({t->X, (size_t)t->I * t->J * K * prec_bytes(t->store_prec)});
+  } else {
+    const size_t n = (size_t)t->nnz;
+    a.push_back({t->ci, n * 4});
+    a.push_back({t->cj, n * 4});
+    a.push_back({t->ck, n * 4});
+    a.push_back({t->cv, n * 4});
+    a.push_back({t->koff, (K + 1) * 8});
+  }
+  a.push_back({t->A, (size_t)t->I * R * 8});
+  a.push_back({t->B, (size_t)t->J * R * 8});
+  a.push_back({t->C, K * R * 8});
+  a.push_back({t->lam, R * 8});
+  a.push_back({t->w1, (size_t)t->I * 8});
+  a.push_back({t->w2, (size_t)t->J * 8});
+  a.push_back({t->w3, K * 8});
+  if (have_kept) {
+    const int r = t->cfg.repetitions;
+    const RepSet rs = make_repset(t, t->Kpmax, 0, r);
+    a.push_back({t->idx, (size_t)r * t->idx_stride * 4});
+    a.push_back({t->Bw, (size_t)r * rs.sB * 8});
+    a.push_back({t->Cw, (size_t)r * rs.sC * 8});
+  }
+  return a;
+}
+
+// Copies between device arrays and a file through a pinned staging buffer.
+struct CkptIO {
+  FILE* f = nullptr;
+  void* stage = nullptr;
+  size_t cap = size_t(64) << 20;
+  hipStream_t st = nullptr;
+  ~CkptIO() {
+    if (stage) (void)hipHostFree(stage);
+    if (f) fclose(f);
+  }
+  bool open(const char* path, const char* mode) {
+    f = fopen(path, mode);
+    return f && hipHostMalloc(&stage, cap, hipHostMallocDefault) == hipSuccess;
+  }
+  bool put(const void* dev, size_t n) {
+    for (size_t off = 0; off < n; off += cap) {
+      const size_t m = n - off < cap ? n - off : cap;
+      if (hipMemcpyAsync(stage, (const char*)dev + off, m, hipMemcpyDeviceToHost, st) !=
+              hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess || fwrite(stage, 1, m, f) != m)
+        return false;
+    }
+    return true;
+  }
+  bool get(void* dev, size_t n) {
+    for (size_t off = 0; off < n; off += cap) {
+      const size_t m = n - off < cap ? n - off : cap;
+      if (fread(stage, 1, m, f) != m ||
+          hipMemcpyAsync((char*)dev + off, stage, m, hipMemcpyHostToDevice, st) != hipSuccess ||
+          hipStreamSynchronize(st) != hipSuccess)
+        return false;
+    }
+    return true;
+  }
+};
+
 sbt_status not_for_nd(sbt_tensor* t) {
   set_err(t, "tensor of order N: use the sbt_nd_* calls");
   return SBT_E_STATE;
@@ -1364,11 +1493,14 @@ const char* sbt_status_str(sbt_status s) {
     case SBT_E_DEVICE: return "HIP runtime error";
     case SBT_E_NUMERIC: return "non-finite input or importance overflow";
     case SBT_E_STATE: return "invalid state";
+    case SBT_E_BUSY: return "another call on this tensor is in flight";
   }
   return "unknown status";
 }
 
-const char* sbt_last_error(const sbt_tensor* t) { return t ? t->errmsg.c_str() : ""; }
+const char* sbt_last_error(const sbt_tensor* t) {
+  return t ? t->errmsg.c_str() : g_errmsg.c_str();
+}
 
 sbt_status sbt_init_dense(const sbt_config* cfg, const void* X0_dev, int64_t I, int64_t J,
                           int64_t K0, const double* A0, const double* B0, const double* C0,
@@ -1540,8 +1672,11 @@ void sbt_destroy(sbt_tensor* t) {
   delete t;
 }
 
-sbt_status sbt_update_batch_dense(sbt_tensor* t, const void* Y_dev, int64_t K_new, void* stream) {
-  if (!t || !Y_dev) return SBT_E_INVALID;
+}  // extern "C"
+
+namespace {
+
+sbt_status update_dense_body(sbt_tensor* t, const void* Y_dev, int64_t K_new, void* stream) {
   if (t->nd) return nd_update(t, Y_dev, K_new, (hipStream_t)stream);
   if (t->fmt != SBT_DENSE) {
     set_err(t, "tensor is not dense");
@@ -1567,10 +1702,9 @@ sbt_status sbt_update_batch_dense(sbt_tensor* t, const void* Y_dev, int64_t K_ne
   return update_body(t, K_new, uq, st);
 }
 
-sbt_status sbt_update_batch_coo(sbt_tensor* t, const int32_t* i_dev, const int32_t* j_dev,
-                                const int32_t* k_dev, const float* v_dev, int64_t nnz,
-                                int64_t K_new, void* stream) {
-  if (!t) return SBT_E_INVALID;
+sbt_status update_coo_body(sbt_tensor* t, const int32_t* i_dev, const int32_t* j_dev,
+                           const int32_t* k_dev, const float* v_dev, int64_t nnz, int64_t K_new,
+                           void* stream) {
   if (t->nd) return not_for_nd(t);
   if (t->fmt != SBT_COO) {
     set_err(t, "tensor is not COO");
@@ -1607,6 +1741,52 @@ sbt_status sbt_update_batch_coo(sbt_tensor* t, const int32_t* i_dev, const int32
   return update_body(t, K_new, uq, st);
 }
 
+}  // namespace
+
+namespace sbt {
+sbt_status server_update_dense(sbt_tensor* t, const void* Y_dev, int64_t K_new,
+                               hipStream_t st) {
+  if (!t || !Y_dev) return SBT_E_INVALID;
+  CallGuard g(t, true);
+  if (!g.ok) return SBT_E_BUSY;
+  return update_dense_body(t, Y_dev, K_new, st);
+}
+sbt_status server_update_coo(sbt_tensor* t, const int32_t* i_dev, const int32_t* j_dev,
+                             const int32_t* k_dev, const float* v_dev, int64_t nnz,
+                             int64_t K_new, hipStream_t st) {
+  if (!t) return SBT_E_INVALID;
+  CallGuard g(t, true);
+  if (!g.ok) return SBT_E_BUSY;
+  return update_coo_body(t, i_dev, j_dev, k_dev, v_dev, nnz, K_new, st);
+}
+void server_lease(sbt_tensor* t, int delta) { t->leases.fetch_add(delta); }
+size_t update_workspace_bytes(const sbt_tensor* t) {
+  size_t b = t->bytes_fixed;
+  for (const auto& g : t->grow_allocs) b += g.second;
+  const size_t res = resident_bytes(t);
+  return b > res ? b - res : 0;
+}
+bool is_coo(const sbt_tensor* t) { return t && !t->nd && t->fmt == SBT_COO; }
+}  // namespace sbt
+
+extern "C" {
+
+sbt_status sbt_update_batch_dense(sbt_tensor* t, const void* Y_dev, int64_t K_new, void* stream) {
+  if (!t || !Y_dev) return SBT_E_INVALID;
+  CallGuard g(t, false);
+  if (!g.ok) return SBT_E_BUSY;
+  return update_dense_body(t, Y_dev, K_new, stream);
+}
+
+sbt_status sbt_update_batch_coo(sbt_tensor* t, const int32_t* i_dev, const int32_t* j_dev,
+                                const int32_t* k_dev, const float* v_dev, int64_t nnz,
+                                int64_t K_new, void* stream) {
+  if (!t) return SBT_E_INVALID;
+  CallGuard g(t, false);
+  if (!g.ok) return SBT_E_BUSY;
+  return update_coo_body(t, i_dev, j_dev, k_dev, v_dev, nnz, K_new, stream);
+}
+
 sbt_status sbt_get_shape(const sbt_tensor* t, int64_t* I, int64_t* J, int64_t* K, int32_t* R) {
   if (!t) return SBT_E_INVALID;
   if (t->nd) return SBT_E_STATE;
@@ -1617,15 +1797,167 @@ sbt_status sbt_get_shape(const sbt_tensor* t, int64_t* I, int64_t* J, int64_t* K
   return SBT_OK;
 }
 
+sbt_status sbt_memory_bytes(const sbt_tensor* t, int64_t* resident, int64_t* workspace) {
+  if (!t) return SBT_E_INVALID;
+  if (t->nd) return SBT_E_STATE;
+  if (resident) *resident = (int64_t)resident_bytes(t);
+  if (workspace) *workspace = (int64_t)sbt::update_workspace_bytes(t);
+  return SBT_OK;
+}
+
 sbt_status sbt_get_batch_counter(const sbt_tensor* t, uint32_t* counter) {
   if (!t || !counter) return SBT_E_INVALID;
   *counter = t->t;
   return SBT_OK;
 }
 
+sbt_status sbt_save(sbt_tensor* t, const char* path, void* stream) {
+  if (!t || !path) return SBT_E_INVALID;
+  if (t->nd) return not_for_nd(t);
+  CallGuard g(t, false);
+  if (!g.ok) return SBT_E_BUSY;
+  CkptHeader h;
+  std::memset(&h, 0, sizeof(h));
+  std::memcpy(h.magic, kCkptMagic, 8);
+  h.version = kCkptVersion;
+  h.header_bytes = (uint32_t)sizeof(CkptHeader);
+  h.cfg = t->cfg;
+  h.I = t->I;
+  h.J = t->J;
+  h.K = t->K;
+  h.Kcap = t->Kcap;
+  h.nnz = t->nnz;
+  h.R = t->R;
+  h.fmt = t->fmt;
+  h.store_prec = t->store_prec;
+  h.sum_prec = t->sum_prec;
+  h.S = t->S;
+  h.t = t->t;
+  h.nmax = t->nmax;
+  h.have_kept = t->have_kept ? 1 : 0;
+  h.n3kept = t->n3kept;
+  const std::vector<CkptArray> arrs = ckpt_arrays(t, t->have_kept);
+  for (const auto& a : arrs) h.payload_bytes += a.bytes;
+  CkptIO io;
+  io.st = (hipStream_t)stream;
+  if (!io.open(path, "wb")) {
+    set_err(t, std::string("cannot open ") + path + " for writing");
+    return SBT_E_INVALID;
+  }
+  if (fwrite(&h, sizeof(h), 1, io.f) != 1) {
+    set_err(t, std::string("write failed: ") + path);
+    return SBT_E_DEVICE;
+  }
+  for (const auto& a : arrs)
+    if (!io.put(a.dev, a.bytes)) {
+      set_err(t, std::string("write failed: ") + path);
+      return SBT_E_DEVICE;
+    }
+  if (fflush(io.f) != 0) {
+    set_err(t, std::string("write failed: ") + path);
+    return SBT_E_DEVICE;
+  }
+  return SBT_OK;
+}
+
+sbt_status sbt_load(const char* path, void* stream, sbt_tensor** out) {
+  if (!path || !out) return SBT_E_INVALID;
+  *out = nullptr;
+  auto fail = [](const std::string& m, sbt_status s) {
+    g_errmsg = m;
+    return s;
+  };
+  CkptIO io;
+  io.st = (hipStream_t)stream;
+  if (!io.open(path, "rb")) return fail(std::string("cannot open ") + path, SBT_E_INVALID);
+  CkptHeader h;
+  if (fread(&h, sizeof(h), 1, io.f) != 1 || std::memcmp(h.magic, kCkptMagic, 8) != 0 ||
+      h.version != kCkptVersion || h.header_bytes != sizeof(CkptHeader))
+    return fail(std::string(path) + " is not a checkpoint of this library version",
+                SBT_E_INVALID);
+  std::string why;
+  if (validate_config(&h.cfg, why) != SBT_OK) return fail("checkpoint config: " + why,
+                                                          SBT_E_INVALID);
+  const bool dense = h.fmt == SBT_DENSE;
+  if (h.fmt != h.cfg.format || h.R != h.cfg.rank || h.Kcap != h.cfg.k_capacity || h.I < 1 ||
+      h.J < 1 || h.K < 1 || h.K > h.Kcap || h.I > INT32_MAX || h.J > INT32_MAX ||
+      (!dense && (h.nnz < 0 || h.nnz > h.cfg.nnz_capacity)) ||
+      (h.have_kept && !h.cfg.persist_summaries))
+    return fail(std::string(path) + ": inconsistent checkpoint header", SBT_E_INVALID);
+  sbt_tensor* t = new (std::nothrow) sbt_tensor();
+  if (!t) return SBT_E_NOMEM;
+  t->cfg = h.cfg;
+  t->I = h.I;
+  t->J = h.J;
+  t->K = h.K;
+  t->Kcap = h.Kcap;
+  t->R = h.R;
+  t->fmt = h.fmt;
+  t->store_prec = h.store_prec;
+  t->sum_prec = h.sum_prec;
+  t->nmax = h.nmax ? h.nmax : 1;
+  t->nnz_cap = dense ? 0 : h.cfg.nnz_capacity;
+  sbt_status s = SBT_OK;
+  if (dense) {
+    s = dalloc_bytes(t, &t->X, (size_t)t->I * t->J * t->Kcap * prec_bytes(t->store_prec));
+  } else {
+    s = dalloc(t, &t->ci, (size_t)t->nnz_cap);
+    if (s == SBT_OK) s = dalloc(t, &t->cj, (size_t)t->nnz_cap);
+    if (s == SBT_OK) s = dalloc(t, &t->ck, (size_t)t->nnz_cap);
+    if (s == SBT_OK) s = dalloc(t, &t->cv, (size_t)t->nnz_cap);
+  }
+  if (s == SBT_OK) s = alloc_state(t);
+  if (s == SBT_OK) {
+    t->nnz = dense ? 0 : h.nnz;
+    uint64_t payload = 0;
+    const std::vector<CkptArray> arrs = ckpt_arrays(t, h.have_kept != 0);
+    for (const auto& a : arrs) payload += a.bytes;
+    if (payload != h.payload_bytes) {
+      set_err(t, "checkpoint payload size does not match its header");
+      s = SBT_E_INVALID;
+    }
+    for (size_t q = 0; s == SBT_OK && q < arrs.size(); ++q)
+      if (!io.get(arrs[q].dev, arrs[q].bytes)) {
+        set_err(t, std::string("read failed or file truncated: ") + path);
+        s = SBT_E_INVALID;
+      }
+  }
+  if (s == SBT_OK) {
+    const int R = t->R;
+    hipError_t e = launch_fill_f64(t->ones, (int64_t)R * R, 1.0, io.st);
+    if (e == hipSuccess) e = launch_fill_u32(t->pinv, 1, 0, io.st);
+    if (e == hipSuccess) e = launch_fill_u32(t->cnt, 2 * (int64_t)t->cfg.repetitions, 0, io.st);
+    if (e == hipSuccess) e = hipStreamSynchronize(io.st);
+    if (e != hipSuccess) {
+      set_err(t, hipGetErrorString(e));
+      s = SBT_E_DEVICE;
+    }
+    t->S = h.S;
+    t->scale = std::ldexp(1.0, t->S);
+    t->qmax = (uint64_t)((((unsigned __int128)1) << 63) / t->nmax);
+    t->t = h.t;
+    // the kept summaries themselves are rebuilt from the kept indices at the
+    // next update (the same values a kept copy would hold)
+    t->have_kept = h.have_kept != 0;
+    t->n3kept = h.n3kept;
+    t->z_kept = false;
+    t->coo_kept = false;
+  }
+  if (s != SBT_OK) {
+    g_errmsg = t->errmsg;
+    free_all(t);
+    delete t;
+    return s;
+  }
+  *out = t;
+  return SBT_OK;
+}
+
 sbt_status sbt_get_factors(sbt_tensor* t, double* A, double* B, double* C, double* lambda,
                            void* stream) {
   if (!t) return SBT_E_INVALID;
+  CallGuard g(t, false);
+  if (!g.ok) return SBT_E_BUSY;
   if (t->nd) return not_for_nd(t);
   hipStream_t st = (hipStream_t)stream;
   const int R = t->R;
@@ -1639,6 +1971,8 @@ sbt_status sbt_get_factors(sbt_tensor* t, double* A, double* B, double* C, doubl
 
 sbt_status sbt_fit(sbt_tensor* t, double* fit, void* stream) {
   if (!t || !fit) return SBT_E_INVALID;
+  CallGuard g(t, false);
+  if (!g.ok) return SBT_E_BUSY;
   hipStream_t st = (hipStream_t)stream;
   if (t->nd) return nd_fit(t, fit, st);
   if (t->fmt == SBT_DENSE) {
@@ -1674,6 +2008,8 @@ sbt_status sbt_fms(sbt_tensor* t, const double* A_ref, const double* B_ref, cons
                    const double* lambda_ref, double* score, void* stream) {
   if (!t || !A_ref || !B_ref || !C_ref || !lambda_ref || !score) return SBT_E_INVALID;
   if (t->nd) return not_for_nd(t);
+  CallGuard g(t, false);
+  if (!g.ok) return SBT_E_BUSY;
   hipStream_t st = (hipStream_t)stream;
   XProd xp{};
   const int I = (int)t->I, J = (int)t->J, K = (int)t->K;

@@ -16,7 +16,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsambaten.so")
 
-SBT_OK, SBT_E_INVALID, SBT_E_SHAPE, SBT_E_NOMEM, SBT_E_DEVICE, SBT_E_NUMERIC, SBT_E_STATE = range(7)
+(SBT_OK, SBT_E_INVALID, SBT_E_SHAPE, SBT_E_NOMEM, SBT_E_DEVICE, SBT_E_NUMERIC, SBT_E_STATE,
+ SBT_E_BUSY) = range(8)
 SBT_DENSE, SBT_COO = 0, 1
 SBT_P_F64, SBT_P_F32, SBT_P_BF16 = 0, 1, 2
 SBT_SCHED_BATCHED, SBT_SCHED_PLAIN = 0, 1
@@ -76,6 +77,9 @@ _SIGS = {
     "sbt_fit": (ctypes.c_int, [_vp, _pd, _vp]),
     "sbt_fms": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _pd, _vp]),
     "sbt_get_batch_counter": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_uint32)]),
+    "sbt_memory_bytes": (ctypes.c_int, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+    "sbt_save": (ctypes.c_int, [_vp, ctypes.c_char_p, _vp]),
+    "sbt_load": (ctypes.c_int, [ctypes.c_char_p, _vp, ctypes.POINTER(_vp)]),
     "sbt_last_sample": (ctypes.c_int, [_vp, _i32, _i32, _vp, ctypes.POINTER(_i64)]),
     "sbt_last_rep": (ctypes.c_int, [_vp, _i32, _i32, _vp, _i64, ctypes.POINTER(_i64)]),
     "sbt_mttkrp_dense": (ctypes.c_int, [_i32, _i32, _vp, _i64, _i64, _i64, _i32, _vp, _vp, _vp,
@@ -86,9 +90,11 @@ _SIGS = {
                                       _vp, _i32, _i32, _vp, _vp]),
     "sbt_profile_enable": (ctypes.c_int, [_vp, _i32]),
     "sbt_profile_read": (ctypes.c_int, [_vp, _i32, ctypes.POINTER(_i64), _pd, _pd]),
-    "sbt_server_create": (ctypes.c_int, [_i32, _i64, ctypes.POINTER(_vp)]),
+    "sbt_server_create": (ctypes.c_int, [_i32, _i64, _i64, ctypes.POINTER(_vp)]),
     "sbt_server_submit_dense": (ctypes.c_int, [_vp, _vp, _vp, _i64,
                                                ctypes.POINTER(ctypes.c_uint64)]),
+    "sbt_server_submit_coo": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp, _i64, _i64,
+                                             ctypes.POINTER(ctypes.c_uint64)]),
     "sbt_server_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(_i32),
                                        ctypes.POINTER(ctypes.c_int), _pd, _pd, _pd]),
     "sbt_server_drain": (ctypes.c_int, [_vp]),
@@ -127,12 +133,12 @@ def exported_symbols():
     return sorted(_SIGS)
 
 
-def _check(status, handle=None, what=""):
+def _check(status, handle=None, what="", global_msg=False):
     if status != SBT_OK:
         lib = load()
         msg = lib.sbt_status_str(status).decode()
-        if handle:
-            detail = lib.sbt_last_error(handle).decode()
+        if handle or global_msg:
+            detail = lib.sbt_last_error(handle if handle else None).decode()
             if detail:
                 msg = f"{msg}: {detail}"
         raise SbtError(status, f"{what}: {msg}" if what else msg)
@@ -226,6 +232,25 @@ class Tensor:
                               fa[2], fa[3], _stream(stream), ctypes.byref(out))
         _check(st, None, "sbt_init_coo")
         return cls(out.value)
+
+    @classmethod
+    def load_file(cls, path, stream=None):
+        """A tensor resumed from a checkpoint written by save()."""
+        out = _vp()
+        st = load().sbt_load(os.fsencode(path), _stream(stream), ctypes.byref(out))
+        _check(st, None, "sbt_load", global_msg=True)
+        return cls(out.value)
+
+    def memory_bytes(self):
+        """(resident, workspace) device bytes."""
+        a, b = _i64(), _i64()
+        _check(load().sbt_memory_bytes(self.h, ctypes.byref(a), ctypes.byref(b)), self.h,
+               "sbt_memory_bytes")
+        return a.value, b.value
+
+    def save(self, path, stream=None):
+        st = load().sbt_save(self.h, os.fsencode(path), _stream(stream))
+        _check(st, self.h, "sbt_save")
 
     def close(self):
         if self.h:
@@ -440,10 +465,10 @@ def mttkrp_coo(idx_dev, vals_dev, nnz, n1, n2, n3, R, U0_dev, U1_dev, U2_dev, mo
 class Server:
     """Serving loop over resident tensors (sbt_server_*)."""
 
-    def __init__(self, slots, staging_bytes):
+    def __init__(self, slots, staging_bytes, hbm_budget_bytes=0):
         out = _vp()
-        _check(load().sbt_server_create(slots, int(staging_bytes), ctypes.byref(out)), None,
-               "sbt_server_create")
+        _check(load().sbt_server_create(slots, int(staging_bytes), int(hbm_budget_bytes),
+                                        ctypes.byref(out)), None, "sbt_server_create")
         self.h = out.value
 
     def submit_dense(self, tensor, Y_dev, K_new):
@@ -459,6 +484,15 @@ class Server:
         st = load().sbt_server_submit_dense(self.h, tensor.h, _ptr(Y_dev), K_new,
                                             ctypes.byref(tk))
         return st, tk.value
+
+    def submit_coo(self, tensor, idx_dev, vals_dev, nnz, K_new):
+        """idx_dev: three int32 device arrays (i, j, k batch-relative); vals_dev: float32."""
+        tk = ctypes.c_uint64()
+        st = load().sbt_server_submit_coo(self.h, tensor.h, _ptr(idx_dev[0]), _ptr(idx_dev[1]),
+                                          _ptr(idx_dev[2]), _ptr(vals_dev), nnz, K_new,
+                                          ctypes.byref(tk))
+        _check(st, None, "sbt_server_submit_coo")
+        return tk.value
 
     def poll(self, ticket):
         """(state, result, t_submit, t_start, t_done)"""

@@ -54,5 +54,5 @@ def test_config_struct_layout(tmp_path):
 
 def test_status_strings_without_gpu():
     lib = sambaten.load()
-    for s in range(7):
+    for s in range(8):
         assert lib.sbt_status_str(s)
