@@ -575,7 +575,7 @@ def bench_sparse(args, sbt, torch, synth, log):
     t0 = time.perf_counter()
     gen = synth.SparseCP(I, J, K0 + steps * Kn, w["R"], seed=w["seed"])
     idx0, v0 = gen.slices(0, K0, nnz0, block_id=0)
-    model = synth.sparse_model(gen, K0, gen.last_mean)
+    model = synth.sparse_model(gen, K0, gen.last_mean)  # the generator's (replaced below)
     batches = [gen.slices(K0 + b * Kn, K0 + (b + 1) * Kn, nnzb, block_id=b + 1)
                for b in range(steps)]
     cols0, vd0 = sbt.coo_to_device(idx0, v0)
@@ -585,7 +585,21 @@ def bench_sparse(args, sbt, torch, synth, log):
         f"({time.perf_counter() - t0:.1f} s)")
     cfg = sbt.make_config(w["R"], w["r"], w["iters"], w["s"], w["seed"], fmt=sbt.SBT_COO,
                           precision=sbt.SBT_P_F32, k_capacity=K0 + steps * Kn, max_batch=Kn,
-                          nnz_capacity=nnz_total)
+                          nnz_capacity=nnz_total, init_iters=max(1, args.coo_init_iters))
+    init = None
+    if args.coo_init_iters > 0:
+        # the initial decomposition is CP-ALS of the initial block on the GPU (run once;
+        # every timed tensor starts from its factors)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        T0 = sbt.Tensor.init_coo(cfg, cols0, vd0, len(v0), I, J, K0)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        model = T0.get_factors()
+        init = {"fit": round(T0.fit(), 6), "seconds": round(dt, 3),
+                "als_sweeps": args.coo_init_iters}
+        T0.close()
+        log(f"# initial CP-ALS of {len(v0)} nonzeros: fit {init['fit']:.6f} in {dt:.2f} s")
 
     def fresh():
         return sbt.Tensor.init_coo(cfg, cols0, vd0, len(v0), I, J, K0, model)
@@ -600,6 +614,7 @@ def bench_sparse(args, sbt, torch, synth, log):
     line = base_line(args, w, res, "f32")
     line["config"]["nnz0"] = len(v0)
     line["config"]["nnz_batch"] = nnzb
+    line["initial_cp_als"] = init
     line["roofline"] = roofline_of(res["profile"], "coo", w["R"], f"{name}@{args.nnz_scale:g}",
                                    summary_rows=w["r"] * -(-w["I"] // w["s"]))
     line["cpu_baseline"] = None
@@ -795,6 +810,9 @@ def main():
                          "this many CP runs per candidate rank (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=0,
                     help="requests of the serving workload (default: the workload's 512)")
+    ap.add_argument("--coo-init-iters", type=int, default=30,
+                    help="sparse: CP-ALS sweeps of the initial decomposition on the GPU "
+                         "(0: start from the generator's model)")
     ap.add_argument("--nnz-scale", type=float, default=1.0,
                     help="scale the nonzero counts of the sparse workload")
     ap.add_argument("--copy-probe-mib", type=int, default=0,

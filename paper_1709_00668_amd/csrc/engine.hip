@@ -725,68 +725,214 @@ sbt_status tail(sbt_tensor* t, const RepSet& rs, AlsTail ta, hipStream_t st) {
   return SBT_OK;
 }
 
-// CP-ALS on the r COO summaries: one row-producing MTTKRP launch and one tail
-// per mode update.
-sbt_status run_als_coo(sbt_tensor* t, RepSet rs, uint32_t t_ctr, hipStream_t st) {
+// Buffers of a CP-ALS run on COO summaries (the r summaries of an update, or
+// the whole tensor as one summary for the initial decomposition).
+struct CooAlsBufs {
+  const CooSummary* z;
+  CooUnits* cu;                       // work units of the three modes
+  float *fA, *fB, *fC, *upart;        // staged FP32 factor rows, unit partial rows
+  double *Ap, *Bp, *Cp;               // factors (raw during the sweeps, unit at the end)
+  double *GA, *GB, *GC, *Vinv, *invlam, *lamp;
+  double avg[3];                      // summary entries per row, per mode
+  double ebytes;                      // algorithmic bytes of one MTTKRP launch
+  int iters;
+  uint32_t stream;                    // Philox stream of the initial factors
+  uint32_t t_ctr;
+  bool warm;                          // start from the kept summary factors
+};
+
+// CP-ALS on COO summaries: one row-producing MTTKRP launch and one tail per
+// mode update.
+sbt_status als_coo_core(sbt_tensor* t, RepSet rs, const CooAlsBufs& b, hipStream_t st) {
   const int R = rs.R;
-  double* ilA = t->invlam;
-  double* ilB = t->invlam + R;
-  double* ilC = t->invlam + 2 * R;
-  if (t->warm_now)
-    SBT_CK(launch_als_warm(rs, t->cfg.seed, t->cfg.tensor_id, kStreamAlsInit, t_ctr, t->Bw,
-                           t->Cw, t->warm_n3, t->Bp, t->Cp, st));
+  double* ilA = b.invlam;
+  double* ilB = b.invlam + R;
+  double* ilC = b.invlam + 2 * R;
+  if (b.warm)
+    SBT_CK(launch_als_warm(rs, t->cfg.seed, t->cfg.tensor_id, b.stream, b.t_ctr, t->Bw, t->Cw,
+                           t->warm_n3, b.Bp, b.Cp, st));
   else
-    SBT_CK(launch_als_init(rs, t->cfg.seed, t->cfg.tensor_id, kStreamAlsInit, t_ctr, t->Bp,
-                           t->Cp, st));
-  SBT_TRY(gram_rows(t, rs, t->Bp, rs.sB, rs.n2, t->GB, st));
-  SBT_TRY(gram_rows(t, rs, t->Cp, rs.sC, rs.n3, t->GC, st));
-  SBT_CK(launch_fill_f64(t->invlam + (int64_t)rs.rep0 * 3 * R, (int64_t)rs.nrep * 3 * R, 1.0,
+    SBT_CK(launch_als_init(rs, t->cfg.seed, t->cfg.tensor_id, b.stream, b.t_ctr, b.Bp, b.Cp,
+                           st));
+  SBT_TRY(gram_rows(t, rs, b.Bp, rs.sB, rs.n2, b.GB, st));
+  SBT_TRY(gram_rows(t, rs, b.Cp, rs.sC, rs.n3, b.GC, st));
+  SBT_CK(launch_fill_f64(b.invlam + (int64_t)rs.rep0 * 3 * R, (int64_t)rs.nrep * 3 * R, 1.0,
                          st));
-  SBT_CK(launch_inverse(rs, t->GB, rs.sG, t->GC, rs.sG, t->Vinv, t->pinv, st));
-  SBT_CK(launch_coo_prep(rs, rs.n2, t->Bp, rs.sB, nullptr, t->fB, st));
-  SBT_CK(launch_coo_prep(rs, rs.n3, t->Cp, rs.sC, nullptr, t->fC, st));
-  const double ebytes = (double)t->last_summary_nnz * 12.0;
-  const double nrow_all = (double)t->cfg.repetitions;
-  const double avg1 = (double)t->last_summary_nnz / (nrow_all * rs.n1);
-  const double avg2 = (double)t->last_summary_nnz / (nrow_all * rs.n2);
-  const double avg3 = (double)t->last_summary_nnz / (nrow_all * rs.n3);
+  SBT_CK(launch_inverse(rs, b.GB, rs.sG, b.GC, rs.sG, b.Vinv, t->pinv, st));
+  SBT_CK(launch_coo_prep(rs, rs.n2, b.Bp, rs.sB, nullptr, b.fB, st));
+  SBT_CK(launch_coo_prep(rs, rs.n3, b.Cp, rs.sC, nullptr, b.fC, st));
   AlsTail ta;
   ta.sG = rs.sG;
   ta.pinv_count = t->pinv;
-  for (int it = 0; it < t->cfg.als_iters; ++it) {
+  for (int it = 0; it < b.iters; ++it) {
     int pq = prof_kernel(t);
-    SBT_CK(launch_coo_units(rs, 0, t->z, t->cu[0], t->fB, rs.n2, t->fC, rs.n3, t->upart, avg1,
+    SBT_CK(launch_coo_units(rs, 0, *b.z, b.cu[0], b.fB, rs.n2, b.fC, rs.n3, b.upart, b.avg[0],
                             st));
-    prof_end(t, pq, SBT_K_COO_MTTKRP, ebytes, st);
-    SBT_CK(launch_coo_units_finish(rs, 0, t->cu[0], t->upart, t->Vinv, nullptr, t->Ap, rs.sA,
-                                   st));
-    ta.U = t->Ap; ta.sU = rs.sA; ta.rows = rs.n1; ta.Gout = t->GA; ta.invlam_out = ilA;
-    ta.lam_out = nullptr; ta.Gx = t->GA; ta.Gy = t->GC; ta.Vinv_out = t->Vinv;
+    prof_end(t, pq, SBT_K_COO_MTTKRP, b.ebytes, st);
+    SBT_CK(launch_coo_units_finish(rs, 0, b.cu[0], b.upart, b.Vinv, nullptr, b.Ap, rs.sA, st));
+    ta.U = b.Ap; ta.sU = rs.sA; ta.rows = rs.n1; ta.Gout = b.GA; ta.invlam_out = ilA;
+    ta.lam_out = nullptr; ta.Gx = b.GA; ta.Gy = b.GC; ta.Vinv_out = b.Vinv;
     SBT_TRY(tail(t, rs, ta, st));
-    SBT_CK(launch_coo_prep(rs, rs.n1, t->Ap, rs.sA, ilA, t->fA, st));
+    SBT_CK(launch_coo_prep(rs, rs.n1, b.Ap, rs.sA, ilA, b.fA, st));
     pq = prof_kernel(t);
-    SBT_CK(launch_coo_units(rs, 1, t->z, t->cu[1], t->fA, rs.n1, t->fC, rs.n3, t->upart, avg2,
+    SBT_CK(launch_coo_units(rs, 1, *b.z, b.cu[1], b.fA, rs.n1, b.fC, rs.n3, b.upart, b.avg[1],
                             st));
-    prof_end(t, pq, SBT_K_COO_MTTKRP, ebytes, st);
-    SBT_CK(launch_coo_units_finish(rs, 1, t->cu[1], t->upart, t->Vinv, nullptr, t->Bp, rs.sB,
-                                   st));
-    ta.U = t->Bp; ta.sU = rs.sB; ta.rows = rs.n2; ta.Gout = t->GB; ta.invlam_out = ilB;
-    ta.lam_out = nullptr; ta.Gx = t->GA; ta.Gy = t->GB; ta.Vinv_out = t->Vinv;
+    prof_end(t, pq, SBT_K_COO_MTTKRP, b.ebytes, st);
+    SBT_CK(launch_coo_units_finish(rs, 1, b.cu[1], b.upart, b.Vinv, nullptr, b.Bp, rs.sB, st));
+    ta.U = b.Bp; ta.sU = rs.sB; ta.rows = rs.n2; ta.Gout = b.GB; ta.invlam_out = ilB;
+    ta.lam_out = nullptr; ta.Gx = b.GA; ta.Gy = b.GB; ta.Vinv_out = b.Vinv;
     SBT_TRY(tail(t, rs, ta, st));
-    SBT_CK(launch_coo_prep(rs, rs.n2, t->Bp, rs.sB, ilB, t->fB, st));
+    SBT_CK(launch_coo_prep(rs, rs.n2, b.Bp, rs.sB, ilB, b.fB, st));
     pq = prof_kernel(t);
-    SBT_CK(launch_coo_units(rs, 2, t->z, t->cu[2], t->fA, rs.n1, t->fB, rs.n2, t->upart, avg3,
+    SBT_CK(launch_coo_units(rs, 2, *b.z, b.cu[2], b.fA, rs.n1, b.fB, rs.n2, b.upart, b.avg[2],
                             st));
-    prof_end(t, pq, SBT_K_COO_MTTKRP, ebytes, st);
-    SBT_CK(launch_coo_units_finish(rs, 2, t->cu[2], t->upart, t->Vinv, nullptr, t->Cp, rs.sC,
-                                   st));
-    ta.U = t->Cp; ta.sU = rs.sC; ta.rows = rs.n3; ta.Gout = t->GC; ta.invlam_out = ilC;
-    ta.lam_out = t->lamp; ta.Gx = t->GB; ta.Gy = t->GC; ta.Vinv_out = t->Vinv;
+    prof_end(t, pq, SBT_K_COO_MTTKRP, b.ebytes, st);
+    SBT_CK(launch_coo_units_finish(rs, 2, b.cu[2], b.upart, b.Vinv, nullptr, b.Cp, rs.sC, st));
+    ta.U = b.Cp; ta.sU = rs.sC; ta.rows = rs.n3; ta.Gout = b.GC; ta.invlam_out = ilC;
+    ta.lam_out = b.lamp; ta.Gx = b.GB; ta.Gy = b.GC; ta.Vinv_out = b.Vinv;
     SBT_TRY(tail(t, rs, ta, st));
-    SBT_CK(launch_coo_prep(rs, rs.n3, t->Cp, rs.sC, ilC, t->fC, st));
+    SBT_CK(launch_coo_prep(rs, rs.n3, b.Cp, rs.sC, ilC, b.fC, st));
   }
-  SBT_CK(launch_normalize(rs, t->Ap, t->Bp, t->Cp, t->invlam, st));
+  SBT_CK(launch_normalize(rs, b.Ap, b.Bp, b.Cp, b.invlam, st));
   return SBT_OK;
+}
+
+// CP-ALS on the r COO summaries of an update.
+sbt_status run_als_coo(sbt_tensor* t, RepSet rs, uint32_t t_ctr, hipStream_t st) {
+  CooAlsBufs b;
+  b.z = &t->z;
+  b.cu = t->cu;
+  b.fA = t->fA;
+  b.fB = t->fB;
+  b.fC = t->fC;
+  b.upart = t->upart;
+  b.Ap = t->Ap;
+  b.Bp = t->Bp;
+  b.Cp = t->Cp;
+  b.GA = t->GA;
+  b.GB = t->GB;
+  b.GC = t->GC;
+  b.Vinv = t->Vinv;
+  b.invlam = t->invlam;
+  b.lamp = t->lamp;
+  const double nrow_all = (double)t->cfg.repetitions;
+  b.avg[0] = (double)t->last_summary_nnz / (nrow_all * rs.n1);
+  b.avg[1] = (double)t->last_summary_nnz / (nrow_all * rs.n2);
+  b.avg[2] = (double)t->last_summary_nnz / (nrow_all * rs.n3);
+  b.ebytes = (double)t->last_summary_nnz * 12.0;
+  b.iters = t->cfg.als_iters;
+  b.stream = kStreamAlsInit;
+  b.t_ctr = t_ctr;
+  b.warm = t->warm_now;
+  return als_coo_core(t, rs, b, st);
+}
+
+// The initial decomposition of a COO tensor: CP-ALS (init_iters sweeps from
+// U[0,1) factors of the init stream) on the whole stored tensor, taken as one
+// summary with every index kept, then components ordered by lambda.  The
+// summary's sorted copies and work units live in temporary buffers.
+sbt_status init_cp_als_coo(sbt_tensor* t, hipStream_t st) {
+  const int R = t->R;
+  const int64_t nnz = t->nnz, I = t->I, J = t->J, K = t->K;
+  if (I >= (1 << 24) || J >= (1 << 24) || K >= (1 << 24) || nnz > INT32_MAX) {
+    set_err(t, "the initial CP-ALS of a COO tensor needs extents below 2^24");
+    return SBT_E_SHAPE;
+  }
+  RepSet rs;
+  rs.n1 = (int)I;
+  rs.n2 = (int)J;
+  rs.n3 = (int)K;
+  rs.R = R;
+  rs.rep0 = 0;
+  rs.nrep = 1;
+  rs.sZ = 0;
+  rs.sA = I * R;
+  rs.sB = J * R;
+  rs.sC = K * R;
+  rs.sW = 0;
+  rs.sM = 0;
+  rs.sG = (int64_t)R * R;
+  rs.nsplit = 1;
+  std::vector<void*> bufs;
+  auto get = [&](void** p, size_t bytes) -> hipError_t {
+    hipError_t e = hipMalloc(p, bytes ? bytes : 1);
+    if (e == hipSuccess) bufs.push_back(*p);
+    return e;
+  };
+  auto body = [&]() -> sbt_status {
+    const int64_t cap = nnz + 1;
+    CooSummary z{};
+    int32_t** i32s[] = {&z.a, &z.b, &z.c, &z.a_x, &z.a_y, &z.b_x, &z.b_y, &z.val, &z.perm};
+    for (int32_t** q : i32s) SBT_CK(get((void**)q, sizeof(int32_t) * cap));
+    float** f32s[] = {&z.v, &z.a_v, &z.b_v};
+    for (float** q : f32s) SBT_CK(get((void**)q, sizeof(float) * cap));
+    uint32_t** u32s[] = {&z.key_a, &z.key_b, &z.key_out};
+    for (uint32_t** q : u32s) SBT_CK(get((void**)q, sizeof(uint32_t) * cap));
+    SBT_CK(coo_sort_tmp_bytes(cap, &z.tmp_bytes));
+    SBT_CK(get(&z.tmp, z.tmp_bytes));
+    z.sOffA = I + 1;
+    z.sOffB = J + 1;
+    z.sOffC = K + 1;
+    SBT_CK(get((void**)&z.offA, sizeof(int64_t) * z.sOffA));
+    SBT_CK(get((void**)&z.offB, sizeof(int64_t) * z.sOffB));
+    SBT_CK(get((void**)&z.offC, sizeof(int64_t) * z.sOffC));
+    SBT_CK(get((void**)&z.rep_off, sizeof(int64_t) * 2));
+    z.rep_off_h[0] = 0;
+    z.rep_off_h[1] = nnz;
+    z.cap = cap;
+    SBT_CK(hipMemcpyAsync(z.rep_off, z.rep_off_h, sizeof(int64_t) * 2, hipMemcpyHostToDevice,
+                          st));
+    SBT_CK(launch_coo_single_summary(t->ci, t->cj, t->ck, t->cv, nnz, rs.n1, rs.n2, rs.n3, z,
+                                     st));
+    CooUnits cu[3]{};
+    const int64_t rows[3] = {I, J, K};
+    int64_t pmax = 0;
+    for (int m = 0; m < 3; ++m) {
+      CooUnits& u = cu[m];
+      u.cap = cap / kCooUnit + rows[m] + 1;
+      SBT_CK(get((void**)&u.cnt, sizeof(uint32_t) * rows[m]));
+      SBT_CK(get((void**)&u.uoff, sizeof(int64_t) * (rows[m] + 1)));
+      SBT_CK(get((void**)&u.urow, sizeof(int32_t) * u.cap));
+      SBT_CK(get((void**)&u.ustart, sizeof(int64_t) * u.cap));
+      SBT_CK(get((void**)&u.ulen, sizeof(int32_t) * u.cap));
+      SBT_CK(launch_coo_units_build(rs, m, z, u, st));
+      if (u.cap > pmax) pmax = u.cap;
+    }
+    CooAlsBufs b;
+    b.z = &z;
+    b.cu = cu;
+    SBT_CK(get((void**)&b.fA, sizeof(float) * I * kMaxRank));
+    SBT_CK(get((void**)&b.fB, sizeof(float) * J * kMaxRank));
+    SBT_CK(get((void**)&b.fC, sizeof(float) * K * kMaxRank));
+    SBT_CK(get((void**)&b.upart, sizeof(float) * pmax * kMaxRank));
+    double* G = nullptr;
+    SBT_CK(get((void**)&G, sizeof(double) * (4 * rs.sG + 3 * R)));
+    b.GA = G;
+    b.GB = G + rs.sG;
+    b.GC = G + 2 * rs.sG;
+    b.Vinv = G + 3 * rs.sG;
+    b.invlam = G + 4 * rs.sG;
+    b.Ap = t->A;
+    b.Bp = t->B;
+    b.Cp = t->C;
+    b.lamp = t->lam;
+    b.avg[0] = (double)nnz / (double)I;
+    b.avg[1] = (double)nnz / (double)J;
+    b.avg[2] = (double)nnz / (double)K;
+    b.ebytes = 0.0;
+    b.iters = t->cfg.init_iters;
+    b.stream = kStreamInit;
+    b.t_ctr = 0;
+    b.warm = false;
+    SBT_TRY(als_coo_core(t, rs, b, st));
+    SBT_CK(launch_sort_components(t->A, t->B, t->C, t->lam, I, J, K, R, st));
+    SBT_CK(hipStreamSynchronize(st));
+    return SBT_OK;
+  };
+  const sbt_status r = body();
+  (void)hipStreamSynchronize(st);
+  for (void* q : bufs) (void)hipFree(q);
+  return r;
 }
 
 // Scale S of the importance from max x^2 of the initial tensor (device bits).
@@ -994,8 +1140,11 @@ sbt_status init_common(sbt_tensor* t, const double* A0, const double* B0, const 
     return SBT_OK;
   }
   if (t->fmt != SBT_DENSE) {
-    set_err(t, "the initial CP-ALS needs a dense tensor; pass A0, B0, C0, lambda0");
-    return SBT_E_INVALID;
+    if (t->cfg.init_iters < 1) {
+      set_err(t, "the initial CP-ALS needs init_iters >= 1");
+      return SBT_E_INVALID;
+    }
+    return init_cp_als_coo(t, st);
   }
   // CP-ALS on the whole initial tensor, then components ordered by lambda.
   RepSet rs;
@@ -1581,8 +1730,7 @@ sbt_status sbt_init_coo(const sbt_config* cfg, const int32_t* i_dev, const int32
   if (validate_config(cfg, why) != SBT_OK) return SBT_E_INVALID;
   if (cfg->format != SBT_COO) return SBT_E_INVALID;
   if (cfg->repetitions > 64) return SBT_E_INVALID;  // per index repetition bitmasks
-  // the initial decomposition of a COO tensor is given by the caller
-  if (!A0 || !B0 || !C0 || !lambda0) return SBT_E_INVALID;
+  if (check_factor_args(A0, B0, C0, lambda0, why) != SBT_OK) return SBT_E_INVALID;
   if (nnz < 0 || (nnz > 0 && (!i_dev || !j_dev || !k_dev || !v_dev))) return SBT_E_INVALID;
   if (I < 1 || J < 1 || K0 < 1 || I > INT32_MAX || J > INT32_MAX) return SBT_E_SHAPE;
   if (cfg->k_capacity < K0 + 1 || cfg->k_capacity > INT32_MAX) return SBT_E_SHAPE;

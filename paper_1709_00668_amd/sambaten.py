@@ -221,12 +221,13 @@ class Tensor:
         return cls(out.value)
 
     @classmethod
-    def init_coo(cls, cfg, idx_dev, vals_dev, nnz, I, J, K0, factors, stream=None):
-        """idx_dev: three int32 device arrays (i, j, k); vals_dev: float32."""
+    def init_coo(cls, cfg, idx_dev, vals_dev, nnz, I, J, K0, factors=None, stream=None):
+        """idx_dev: three int32 device arrays (i, j, k); vals_dev: float32.
+        factors None: the initial decomposition is CP-ALS on the tensor."""
         lib = load()
         out = _vp()
-        keep = [np.ascontiguousarray(f, dtype=np.float64) for f in factors]
-        fa = [a.ctypes.data for a in keep]
+        keep = [np.ascontiguousarray(f, dtype=np.float64) for f in (factors or ())]
+        fa = [a.ctypes.data for a in keep] if keep else [None] * 4
         st = lib.sbt_init_coo(ctypes.byref(cfg), _ptr(idx_dev[0]), _ptr(idx_dev[1]),
                               _ptr(idx_dev[2]), _ptr(vals_dev), nnz, I, J, K0, fa[0], fa[1],
                               fa[2], fa[3], _stream(stream), ctypes.byref(out))

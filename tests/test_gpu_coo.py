@@ -373,3 +373,30 @@ def test_coo_persistent_summaries_outgrowing_their_allocation(lib):
         np.testing.assert_allclose(gc.get_factors()[2], gd.get_factors()[2], rtol=1e-4,
                                    atol=1e-6, err_msg=f"batch {b}")
     assert abs(gd.fit() - gc.fit()) < 1e-6
+
+
+@pytest.mark.parametrize("I,J,K0,R,nnz0,iters", [(80, 70, 40, 4, 6000, 25),
+                                                 (300, 260, 90, 10, 40000, 15)])
+def test_coo_initial_cp_als_matches_oracle(lib, I, J, K0, R, nnz0, iters):
+    # no factors given: the initial decomposition is CP-ALS on the whole COO tensor
+    # (the initial-stream U[0,1) start, init_iters sweeps, components by lambda);
+    # FP32 sparse products against the oracle's FP64 CP-ALS of the same entries
+    torch = _torch()
+    gen = synth.SparseCP(I, J, K0 + 5, R, seed=91 + R)
+    idx0, v0 = gen.slices(0, K0, nnz0, block_id=0)
+    ocfg = osb.Config(rank=R, reps=2, als_iters=5, sample_factor=2, seed=91, k_capacity=K0 + 5,
+                      nnz_capacity=nnz0 + 2000, init_iters=iters)
+    ora = osb.OracleTensor(ocfg, osb.COO, (I, J, K0), coo0=(idx0, v0))
+    cfg = lib.make_config(R, 2, 5, 2, 91, fmt=lib.SBT_COO, precision=lib.SBT_P_F32,
+                          k_capacity=K0 + 5, max_batch=5, nnz_capacity=nnz0 + 2000,
+                          init_iters=iters)
+    cols, vd = lib.coo_to_device(idx0, v0)
+    gpu = lib.Tensor.init_coo(cfg, cols, vd, len(v0), I, J, K0)
+    torch.cuda.synchronize()
+    A, B, C, lam = gpu.get_factors()
+    assert_close(lam, ora.lam, RT, AT, "lambda")
+    assert_close(A, ora.A, RT, AT, "A")
+    assert_close(B, ora.B, RT, AT, "B")
+    assert_close(C, ora.C, RT, AT, "C")
+    assert abs(gpu.fit() - ora.fit()) < 1e-5
+    gpu.close()
