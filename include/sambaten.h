@@ -129,7 +129,12 @@ sbt_status sbt_init_dense(const sbt_config* cfg, const void* X0_dev, int64_t I, 
                           const double* lambda0, void* stream, sbt_tensor** out);
 
 /* Same for a COO tensor: nnz entries (i_dev[e], j_dev[e], k_dev[e], v_dev[e]),
- * device arrays; coordinates must lie inside I x J x K0. */
+ * device arrays; coordinates must lie inside I x J x K0, no coordinate
+ * twice.  With the factors NULL the initial decomposition is CP-ALS on the
+ * whole tensor (cfg->init_iters >= 1 sweeps from U[0,1) factors, the sparse
+ * MTTKRP kernels of the update on the tensor taken as one summary with
+ * every index; I, J and K0 must stay below 2^24), components ordered by
+ * lambda, largest first. */
 sbt_status sbt_init_coo(const sbt_config* cfg, const int32_t* i_dev, const int32_t* j_dev,
                         const int32_t* k_dev, const float* v_dev, int64_t nnz, int64_t I,
                         int64_t J, int64_t K0, const double* A0, const double* B0,
