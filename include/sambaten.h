@@ -74,6 +74,21 @@ typedef enum { SBT_P_F64 = 0, SBT_P_F32 = 1, SBT_P_BF16 = 2 } sbt_precision;
  *     sweep (one per mode).  Same arithmetic, used as the baseline.        */
 typedef enum { SBT_SCHED_BATCHED = 0, SBT_SCHED_PLAIN = 1 } sbt_schedule;
 
+/* Reading switches (sbt_config.flags).
+ *   SBT_FLAG_LAMBDA_AVG: the last step of Algorithm 1 taken literally:
+ *     lambda becomes the average of its previous value and the new one, the
+ *     new one being, per component f, the mean over the repetitions valid for
+ *     f (whose anchor column C(K_s, f) is not zero) of the summary's matched
+ *     weight in the current model's units,
+ *       lambda'_pi(f) ||C'(anchor rows, pi(f))|| /
+ *         (||A(I_s, f)|| ||B(J_s, f)|| ||C(K_s, f)||),
+ *     which equals lambda_f when the summary recovers the restriction of the
+ *     model.  The new rows of C are still divided by the previous lambda, and
+ *     the change of lambda rescales the old slices' reconstruction too.
+ *     Default (flag off): lambda is kept, the new rows carry the scale.
+ *     Third-order tensors only. */
+enum { SBT_FLAG_LAMBDA_AVG = 1 };
+
 typedef struct {
   int32_t rank;              /* R, 1..32 */
   int32_t repetitions;       /* r >= 1 (Algorithm 1) */
@@ -85,7 +100,7 @@ typedef struct {
   int32_t schedule;          /* sbt_schedule */
   uint64_t seed;             /* Philox key, low word */
   uint32_t tensor_id;        /* xored into the high key word */
-  uint32_t flags;            /* reserved, must be 0 */
+  uint32_t flags;            /* readings of the paper, SBT_FLAG_* (0: defaults) */
   int64_t k_capacity;        /* largest third-mode size the tensor may reach */
   int64_t max_batch;         /* largest K_new of one update */
   int64_t nnz_capacity;      /* COO only: largest number of stored nonzeros */

@@ -31,7 +31,14 @@ listed, with reasons, in the design notes of the repository):
   by lambda; they are averaged over the valid repetitions in ascending order.
 * Zero entries of A, B and the anchor rows of C are replaced by the mean over
   the valid covering repetitions, after all repetitions (order free).
-* lambda is kept unchanged by default.
+* lambda is kept unchanged by default.  With lambda_avg (the last step of
+  Algorithm 1 read literally), lambda becomes the average of its previous
+  value and the new one, the new one being the mean over the repetitions
+  valid for the component (with a non-zero C(K_s) column) of the summary's
+  matched weight in the current model's units:
+  lambda'_pi(f) ||C'(anchor rows, pi(f))|| / (||A(I_s, f)|| ||B(J_s, f)||
+  ||C(K_s, f)||), which equals lambda_f when the summary recovers the
+  restriction of the current model exactly.
 * Persistent summaries (optional; Sec. 3.1 assumes summaries of the tensor
   already exist when a batch arrives): the sampled I_s, J_s, K_s of an update are kept for the
   following ones (redrawn every summary_refresh updates), so a summary is
@@ -167,7 +174,7 @@ class Config:
     def __init__(self, rank, reps, als_iters, sample_factor, seed, tensor_id=0,
                  init_iters=100, k_capacity=None, nnz_capacity=None, summary_bf16=False,
                  getrank_runs=0, getrank_threshold=90.0, persist_summaries=False,
-                 summary_refresh=0, workers=1):
+                 summary_refresh=0, workers=1, lambda_avg=False):
         self.rank = int(rank)
         self.reps = int(reps)
         self.als_iters = int(als_iters)
@@ -193,6 +200,8 @@ class Config:
         # host threads for the independent repetitions and for blocks of slices
         # (scheduling only: every result is the same for any count)
         self.workers = max(1, int(workers))
+        # the paper's lambda update (Alg. 1, last step) instead of keeping lambda
+        self.lambda_avg = bool(lambda_avg)
         if self.persist_summaries and self.getrank_runs > 0:
             raise ValueError("persistent summaries and GetRank do not combine")
 
@@ -419,7 +428,14 @@ class OracleTensor:
             Ct = np.zeros_like(D)
             lz = self.lam > 0
             Ct[:, lz] = D[:, lz] / self.lam[lz]
-            return dict(Is=Is, Js=Js, Ks=Ks, Ap=Ap, Bp=Bp, Cp=Cp, lamp=lamp, pi=pi,
+            # the summary's weights of the matched components in the current units
+            nC = np.linalg.norm(self.C[Ks], axis=0)
+            ncp = np.linalg.norm(Cp[:n3], axis=0)
+            lhat = np.full(R, np.nan)
+            for f in range(R):
+                if valid[f] and nC[f] > 0:
+                    lhat[f] = lamp[pi[f]] * ncp[pi[f]] / (nA[f] * nB[f] * nC[f])
+            return dict(Is=Is, Js=Js, Ks=Ks, Ap=Ap, Bp=Bp, Cp=Cp, lamp=lamp, pi=pi, lhat=lhat,
                         sigA=sigA, sigB=sigB, nA=nA, nB=nB, S=S, valid=valid, At=At,
                         Bt=Bt, Ct=Ct, Dm=Dm, npinv=npinv, Rnew=Rn, cc=cc)
 
@@ -445,12 +461,25 @@ class OracleTensor:
             if cnt:
                 C_new[:, f] = acc / cnt
 
+        # lambda: kept, or the average of the previous and the new value
+        lam_new = self.lam.copy()
+        if cfg.lambda_avg:
+            for f in range(R):
+                acc, cnt = 0.0, 0
+                for r in reps:
+                    if not np.isnan(r["lhat"][f]):
+                        acc = acc + r["lhat"][f]
+                        cnt += 1
+                if cnt:
+                    lam_new[f] = 0.5 * (self.lam[f] + acc / cnt)
+
         # Commit the state.
         if cfg.persist_summaries:
             self.kept = [(r["Is"], r["Js"], r["Ks"], r["Bp"].copy(), r["Cp"][:len(r["Ks"])].copy())
                          for r in reps]
         self.A, self.B = A_new, B_new
         self.C = np.vstack([C_old, C_new])
+        self.lam = lam_new
         if self.fmt == DENSE:
             self.X = XY
             self.w = [self.w[0] + dw[0], self.w[1] + dw[1], np.concatenate([self.w[2], dw[2]])]

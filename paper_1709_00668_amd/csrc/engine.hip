@@ -98,6 +98,8 @@ struct sbt_tensor {
   hipStream_t capst = nullptr;
   // persistent summaries: kept summary factors for the warm start
   double *Bw = nullptr, *Cw = nullptr;
+  // SBT_FLAG_LAMBDA_AVG: per repetition the matched summary weights
+  double* lhat = nullptr;
   bool have_kept = false;  // I_s, J_s, K_s in idx are the kept ones
   bool z_kept = false;     // the summaries' K_s slices were gathered with those indices
   bool coo_kept = false;   // COO summaries hold the old part of the kept indices
@@ -296,7 +298,8 @@ sbt_status validate_config(const sbt_config* c, std::string& why) {
       {c->format != SBT_DENSE && c->format != SBT_COO, "bad format"},
       {c->precision < SBT_P_F64 || c->precision > SBT_P_BF16, "bad precision"},
       {c->schedule != SBT_SCHED_BATCHED && c->schedule != SBT_SCHED_PLAIN, "bad schedule"},
-      {c->flags != 0 || c->reserved != 0, "flags and reserved must be 0"},
+      {(c->flags & ~(uint32_t)SBT_FLAG_LAMBDA_AVG) != 0 || c->reserved != 0,
+       "unknown flags, or reserved not 0"},
       {c->getrank_runs < 0 || c->getrank_runs > 64, "getrank_runs must be in 0..64"},
       {gr && (c->format != SBT_DENSE || c->precision == SBT_P_BF16),
        "GetRank needs a dense FP64 or FP32 tensor"},
@@ -427,6 +430,7 @@ sbt_status alloc_state(sbt_tensor* t) {
     SBT_TRY(dalloc(t, &t->Bw, (size_t)r * rs.sB));
     SBT_TRY(dalloc(t, &t->Cw, (size_t)r * rs.sC));
   }
+  if (c.flags & SBT_FLAG_LAMBDA_AVG) SBT_TRY(dalloc(t, &t->lhat, (size_t)r * R));
   if (c.getrank_runs > 0) {
     const size_t R3 = (size_t)R * R * R;
     SBT_TRY(dalloc(t, &t->gAk, (size_t)r * rs.sA));
@@ -1394,6 +1398,8 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
       SBT_CK(launch_xprod(xp, st));
     }
     SBT_CK(launch_match(rs, ma, st));
+    if (t->lhat)
+      SBT_CK(launch_lambda_hat(rs, t->xout, t->lamp, t->pi, t->valid, t->lhat, st));
     // row least squares: D = Z_(3) (Bt kr At) Gt^-1, C~ = D / lambda
     // Gt is already the Hadamard product; the second factor is all ones
     const double rbytes = (double)rs.nrep * rs.n1 * rs.n2 * rs.n3 * prec_bytes(t->sum_prec) +
@@ -1463,6 +1469,7 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
   ca.dw2 = t->dw2;
   ca.dw3 = t->dw3;
   SBT_CK(launch_commit(ca, st));
+  if (t->lhat) SBT_CK(launch_lambda_avg(t->err, t->lam, t->lhat, r, R, st));
   prof_end(t, uq, SBT_K_UPDATE, 0.0, st);
   SBT_CK(hipMemcpyAsync(t->h_err, t->err, 4, hipMemcpyDeviceToHost, st));
   SBT_CK(hipStreamSynchronize(st));

@@ -304,7 +304,64 @@ __global__ __launch_bounds__(256) void fms_kernel(const double* xo, const double
   }
 }
 
+// Weight of each matched summary component in the current model's units:
+// lambda'_g ||C'(anchor rows, g)|| / (||A(I_s, f)|| ||B(J_s, f)|| ||C(K_s, f)||)
+// for g = pi(f), from the cross products of the matching (the diagonals of
+// A(Is)^T A(Is), B(Js)^T B(Js), C(Ks)^T C(Ks) and of C'^T C' over the anchor
+// rows); -1 where the repetition is not valid for f or C(K_s, f) is zero.
+__global__ void lambda_hat_kernel(RepSet rs, const double* xo, const double* lamp,
+                                  const int32_t* pi, const int32_t* valid, double* lhat) {
+  const int R = rs.R;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= rs.nrep * R) return;
+  const int rep = rs.rep0 + q / R, f = q % R;
+  const int64_t RR = (int64_t)R * R;
+  const double* x = xo + (int64_t)rep * 9 * RR;
+  const int g = pi[rep * R + f];
+  double out = -1.0;
+  if (valid[rep * R + f] && g >= 0 && g < R) {
+    const double nA2 = x[3 * RR + f * R + f], nB2 = x[4 * RR + f * R + f];
+    const double nC2 = x[5 * RR + f * R + f], cp2 = x[8 * RR + g * R + g];
+    if (nA2 > 0.0 && nB2 > 0.0 && nC2 > 0.0)
+      out = lamp[rep * R + g] * sqrt(cp2) / (sqrt(nA2) * sqrt(nB2) * sqrt(nC2));
+  }
+  lhat[rep * R + f] = out;
+}
+
+// lambda <- (lambda + mean over the repetitions of lhat) / 2 where some
+// repetition gives a weight (ascending repetition order); nothing after a
+// device error (the commit is predicated the same way)
+__global__ void lambda_avg_kernel(const uint32_t* err, double* lam, const double* lhat, int nrep,
+                                  int R) {
+  const int f = threadIdx.x;
+  if (f >= R || *err) return;
+  double acc = 0.0;
+  int cnt = 0;
+  for (int rep = 0; rep < nrep; ++rep) {
+    const double v = lhat[rep * R + f];
+    if (v >= 0.0) {
+      acc = acc + v;
+      ++cnt;
+    }
+  }
+  if (cnt) lam[f] = 0.5 * (lam[f] + acc / cnt);
+}
+
 }  // namespace
+
+hipError_t launch_lambda_hat(const RepSet& rs, const double* xo, const double* lamp,
+                             const int32_t* pi, const int32_t* valid, double* lhat,
+                             hipStream_t s) {
+  const int n = rs.nrep * rs.R;
+  lambda_hat_kernel<<<(n + 255) / 256, 256, 0, s>>>(rs, xo, lamp, pi, valid, lhat);
+  return hipGetLastError();
+}
+
+hipError_t launch_lambda_avg(const uint32_t* err, double* lam, const double* lhat, int nrep,
+                             int R, hipStream_t s) {
+  lambda_avg_kernel<<<1, 64, 0, s>>>(err, lam, lhat, nrep, R);
+  return hipGetLastError();
+}
 
 hipError_t launch_match(const RepSet& rs, const MatchArgs& m, hipStream_t s) {
   match_kernel<<<rs.nrep, 256, 0, s>>>(rs, m);

@@ -288,6 +288,14 @@ struct CommitArgs {
   const uint64_t *dw1, *dw2, *dw3;   // batch importance
 };
 hipError_t launch_commit(const CommitArgs& c, hipStream_t s);
+// per repetition and component, the matched summary weight in the current
+// model's units (-1: none), from the matching's cross products xo
+hipError_t launch_lambda_hat(const RepSet& rs, const double* xo, const double* lamp,
+                             const int32_t* pi, const int32_t* valid, double* lhat,
+                             hipStream_t s);
+// lambda <- (lambda + mean of the valid lhat) / 2, unless *err
+hipError_t launch_lambda_avg(const uint32_t* err, double* lam, const double* lhat, int nrep,
+                             int R, hipStream_t s);
 
 // ---- sparse (COO) path ------------------------------------------------------
 struct CooScratch {   // ingest of one batch

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libsambaten.so")
 (SBT_OK, SBT_E_INVALID, SBT_E_SHAPE, SBT_E_NOMEM, SBT_E_DEVICE, SBT_E_NUMERIC, SBT_E_STATE,
  SBT_E_BUSY) = range(8)
 SBT_DENSE, SBT_COO = 0, 1
+SBT_FLAG_LAMBDA_AVG = 1
 SBT_P_F64, SBT_P_F32, SBT_P_BF16 = 0, 1, 2
 SBT_SCHED_BATCHED, SBT_SCHED_PLAIN = 0, 1
 (SBT_K_MTTKRP_C, SBT_K_MTTKRP_AB, SBT_K_GATHER, SBT_K_UPDATE, SBT_K_COO_MTTKRP,
@@ -165,14 +166,14 @@ def _stream(stream):
 def make_config(rank, repetitions, als_iters, sample_factor, seed, *, init_iters=100,
                 fmt=SBT_DENSE, precision=SBT_P_F32, schedule=SBT_SCHED_BATCHED, tensor_id=0,
                 k_capacity, max_batch, nnz_capacity=0, getrank_runs=0,
-                getrank_threshold=90.0, persist_summaries=False, summary_refresh=0):
+                getrank_threshold=90.0, persist_summaries=False, summary_refresh=0, flags=0):
     c = sbt_config()
     c.rank, c.repetitions, c.als_iters, c.init_iters = rank, repetitions, als_iters, init_iters
     s = (sample_factor,) * 3 if np.isscalar(sample_factor) else tuple(sample_factor)
     for m in range(3):
         c.sample_factor[m] = int(s[m])
     c.format, c.precision, c.schedule = fmt, precision, schedule
-    c.seed, c.tensor_id, c.flags = seed, tensor_id, 0
+    c.seed, c.tensor_id, c.flags = seed, tensor_id, flags
     c.k_capacity, c.max_batch, c.nnz_capacity = k_capacity, max_batch, nnz_capacity
     c.getrank_runs, c.reserved, c.getrank_threshold = getrank_runs, 0, getrank_threshold
     c.persist_summaries, c.summary_refresh = int(bool(persist_summaries)), summary_refresh

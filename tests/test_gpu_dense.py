@@ -431,3 +431,36 @@ def test_full_size_dense500_update(lib):
     assert_close(C[K0:], ora.C[K0:], RT, AT, "new rows of C")
     np.testing.assert_array_equal(A, ora.A)  # no zero entries: A is kept as it was
     assert abs(gpu.fit() - ora.fit()) < 1e-3
+
+
+@pytest.mark.parametrize("prec,sched", [(0, 0), (0, 1), (1, 0), (2, 0)])
+def test_lambda_average_reading(lib, prec, sched):
+    # SBT_FLAG_LAMBDA_AVG: lambda becomes the average of its previous value and the
+    # summaries' matched weights, against the oracle with the same reading; FP64 at
+    # rounding level, FP32 and BF16 (against the BF16-summary oracle) at 1e-3; the
+    # given weights are off by a factor so that lambda really moves
+    torch = _torch()
+    I, J, K0, Kn, R, reps = 44, 40, 30, 5, 4, 3
+    dtype = np.float64 if prec == 0 else np.float32
+    gen = synth.DenseCP(I, J, K0 + 2 * Kn, R, seed=41, dtype=dtype)
+    X = gen.slices(0, K0 + 2 * Kn)
+    A, B, C, lam = gen.true_model_prefix(K0)
+    lam = lam * np.array([1.5, 0.8, 1.0, 1.2])
+    ocfg = osb.Config(rank=R, reps=reps, als_iters=20, sample_factor=2, seed=41,
+                      k_capacity=K0 + 2 * Kn, lambda_avg=True, summary_bf16=prec == 2)
+    ora = osb.OracleTensor(ocfg, osb.DENSE, (I, J, K0), X0=X[:, :, :K0], factors=(A, B, C, lam))
+    cfg = lib.make_config(R, reps, 20, 2, 41, precision=prec, schedule=sched,
+                          k_capacity=K0 + 2 * Kn, max_batch=Kn, flags=lib.SBT_FLAG_LAMBDA_AVG)
+    gpu = lib.Tensor.init_dense(cfg, lib.dense_to_device(X[:, :, :K0], dtype), I, J, K0,
+                                factors=(A, B, C, lam))
+    for b in range(2):
+        Y = X[:, :, K0 + b * Kn:K0 + (b + 1) * Kn]
+        ora.update(Y)
+        gpu.update_batch_dense(lib.dense_to_device(Y, dtype), Kn)
+    torch.cuda.synchronize()
+    _, _, Cg, lg = gpu.get_factors()
+    assert np.abs(lg - lam).max() > 1e-3 * lam.max()  # lambda moved
+    tol = 1e-8 if prec == 0 else 1e-3
+    np.testing.assert_allclose(lg, ora.lam, rtol=tol)
+    assert_close(Cg, ora.C, tol, tol, "C")
+    assert abs(gpu.fit() - ora.fit()) < (1e-9 if prec == 0 else 1e-3)

@@ -279,3 +279,43 @@ def test_worker_threads_change_nothing():
     for M1, M4 in ((o1.A, o4.A), (o1.B, o4.B), (o1.C, o4.C)):
         np.testing.assert_allclose(M1, M4, rtol=1e-10, atol=1e-12)
     assert abs(o1.fit() - o4.fit()) < 1e-12
+
+
+def test_lambda_average_is_invariant_on_exact_data():
+    # noise-free rank-R data: every summary recovers the restriction of the model,
+    # so the new weight equals lambda whatever scale the given model splits between
+    # lambda and C, and the paper's average leaves lambda as it was
+    I, J, K0, Kn, R = 24, 22, 20, 4, 3
+    A, B, C, X = exact_model(I, J, K0 + Kn, R, 14)
+    An, Bn, Cn, lam, _ = unit_model(A, B, C, K0)
+    for scale in (1.0, 2.0, 0.25):
+        cfg = sb.Config(rank=R, reps=3, als_iters=1000, sample_factor=2, seed=14,
+                        k_capacity=K0 + Kn, lambda_avg=True)
+        o = sb.OracleTensor(cfg, sb.DENSE, (I, J, K0), X0=X[:, :, :K0],
+                            factors=(An, Bn, Cn / scale, lam * scale))
+        d = o.update(X[:, :, K0:], debug=True)
+        for r in d["reps"]:
+            np.testing.assert_allclose(r["lhat"], lam * scale, rtol=1e-6)
+        np.testing.assert_allclose(o.lam, lam * scale, rtol=1e-6)
+        assert o.fit() > 1 - 1e-6
+
+
+def test_lambda_average_moves_halfway():
+    # a model whose weights are wrong by a factor (A, B, C right): the summaries see
+    # the true weights, so lambda moves half way towards them
+    I, J, K0, Kn, R = 24, 22, 20, 4, 3
+    A, B, C, X = exact_model(I, J, K0 + Kn, R, 15)
+    An, Bn, Cn, lam, _ = unit_model(A, B, C, K0)
+    off = np.array([2.0, 0.5, 1.0])
+    cfg = sb.Config(rank=R, reps=3, als_iters=1000, sample_factor=2, seed=15,
+                    k_capacity=K0 + Kn, lambda_avg=True)
+    o = sb.OracleTensor(cfg, sb.DENSE, (I, J, K0), X0=X[:, :, :K0],
+                        factors=(An, Bn, Cn, lam * off))
+    o.update(X[:, :, K0:])
+    np.testing.assert_allclose(o.lam, 0.5 * (lam * off + lam), rtol=1e-6)
+    cfg0 = sb.Config(rank=R, reps=3, als_iters=1000, sample_factor=2, seed=15,
+                     k_capacity=K0 + Kn)
+    o0 = sb.OracleTensor(cfg0, sb.DENSE, (I, J, K0), X0=X[:, :, :K0],
+                         factors=(An, Bn, Cn, lam * off))
+    o0.update(X[:, :, K0:])
+    np.testing.assert_array_equal(o0.lam, lam * off)
