@@ -282,13 +282,16 @@ __global__ __launch_bounds__(256) void pw_mfma_kernel(RepSet rs, MfmaLayout L, i
 // ---------------------------------------------------------------------------
 // mode 3 on the matrix cores
 // ---------------------------------------------------------------------------
-// Block = 4 wavefronts x 16 rows c (64 consecutive c) of one repetition over
-// one of nsplit ranges of the K steps; the wave forms its Khatri-Rao operand
-// from A~^T (all of it) and the B~^T rows its K range touches, both copied
-// into LDS from their FP32 transposes.  Partial rows go to
-// P[rep][split][c][16 NT]; mode3_finish adds the ranges in order and
-// applies V^-1.
-constexpr int kPSteps = 8;  // K steps whose operand loads are in flight at once
+// Block = 64 consecutive rows c of one repetition over one of nsplit ranges
+// of the K steps; each of its four wavefronts takes all 64 rows (four row
+// tiles) over a quarter of the block's K range, so the Khatri-Rao operand a
+// wave forms per lane (from A~^T, all of it, and the B~^T rows the block's
+// range touches, both copied into LDS from their FP32 transposes) serves four
+// MFMA row tiles.  The four quarters' partial rows are added through LDS in
+// wave order; the block's partial rows go to P[rep][split][c][16 NT], and
+// mode3_finish adds the ranges in order and applies V^-1.
+constexpr int kPTiles = 4;  // row tiles of 16 per wavefront (the block's 64 rows)
+constexpr int kPSteps = 2;  // K steps whose operand loads are in flight at once
 
 template <int NT>
 __global__ __launch_bounds__(256) void p3_mfma_kernel(RepSet rs, MfmaLayout L, int nsplit,
@@ -309,14 +312,23 @@ __global__ __launch_bounds__(256) void p3_mfma_kernel(RepSet rs, MfmaLayout L, i
   const int nb = b_hi >= b_lo ? b_hi - b_lo + 1 : 0;
   const int nbp = (nb + 3) / 4 * 4;  // row stride of the staged B~^T rows
   float* Bt = At + 16 * NT * ld1;     // [16 NT][nbp]
-  const int c0 = blockIdx.x * 64 + wave * 16;
-  const int crow = c0 + (lane & 15) < n3 ? c0 + (lane & 15) : n3 - 1;
+  // this wave's quarter of the block's K range
+  const int kw_lo = ks_lo + (int)((int64_t)wave * (ks_hi - ks_lo) / 4);
+  const int kw_hi = ks_lo + (int)((int64_t)(wave + 1) * (ks_hi - ks_lo) / 4);
+  const int c0 = blockIdx.x * 64;
   const int kq = lane >> 4;
-  const uint16_t* zrow = Zk + rep * L.sZk + (int64_t)crow * L.sk + 8 * kq;
-  bf16x8_t af[kPSteps];
+  const uint16_t* zrow[kPTiles];
+#pragma unroll
+  for (int t = 0; t < kPTiles; ++t) {
+    const int c = c0 + 16 * t + (lane & 15);
+    zrow[t] = Zk + rep * L.sZk + (int64_t)(c < n3 ? c : n3 - 1) * L.sk + 8 * kq;
+  }
+  bf16x8_t af[kPSteps][kPTiles];
 #pragma unroll
   for (int u = 0; u < kPSteps; ++u)
-    if (ks_lo + u < ks_hi) af[u] = ld_bf16x8(zrow + 32 * (ks_lo + u));
+#pragma unroll
+    for (int t = 0; t < kPTiles; ++t)
+      if (kw_lo + u < kw_hi) af[u][t] = ld_bf16x8(zrow[t] + 32 * (kw_lo + u));
   {
     const int n4 = 16 * NT * ld1 / 4;
     const float4* src = reinterpret_cast<const float4*>(Atg + (int64_t)rep * 16 * NT * ld1);
@@ -330,28 +342,32 @@ __global__ __launch_bounds__(256) void p3_mfma_kernel(RepSet rs, MfmaLayout L, i
     }
   }
   __syncthreads();
-  f32x4_t ah[NT], al[NT];
+  f32x4_t ah[kPTiles][NT], al[kPTiles][NT];
 #pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    ah[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-    al[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-  }
-  for (int k0 = ks_lo; k0 < ks_hi; k0 += kPSteps) {
-    if (k0 > ks_lo) {
+  for (int t = 0; t < kPTiles; ++t)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      ah[t][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+      al[t][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    }
+  for (int k0 = kw_lo; k0 < kw_hi; k0 += kPSteps) {
+    if (k0 > kw_lo) {
 #pragma unroll
       for (int u = 0; u < kPSteps; ++u)
-        if (k0 + u < ks_hi) af[u] = ld_bf16x8(zrow + 32 * (k0 + u));
+#pragma unroll
+        for (int t = 0; t < kPTiles; ++t)
+          if (k0 + u < kw_hi) af[u][t] = ld_bf16x8(zrow[t] + 32 * (k0 + u));
     }
 #pragma unroll
     for (int u = 0; u < kPSteps; ++u) {
-      if (k0 + u < ks_hi) {
+      if (k0 + u < kw_hi) {
         // this lane's 8 consecutive e' share one b (ld1 is a multiple of 8)
         const int ep = 32 * (k0 + u) + 8 * kq;
         const int a0 = ep % ld1, b = ep / ld1;
         const bool bin = b <= b_hi;
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-          const int f = 16 * t + (lane & 15);
+        for (int j = 0; j < NT; ++j) {
+          const int f = 16 * j + (lane & 15);
           const float4 x0 = *reinterpret_cast<const float4*>(At + f * ld1 + a0);
           const float4 x1 = *reinterpret_cast<const float4*>(At + f * ld1 + a0 + 4);
           const float bv = bin ? Bt[f * nbp + (b - b_lo)] : 0.0f;
@@ -359,21 +375,34 @@ __global__ __launch_bounds__(256) void p3_mfma_kernel(RepSet rs, MfmaLayout L, i
                               x1.x * bv, x1.y * bv, x1.z * bv, x1.w * bv};
           bf16x8_t kh, kl;
           split_bf16x8(x, kh, kl);
-          ah[t] = mfma16x16x32(af[u], kh, ah[t]);
-          al[t] = mfma16x16x32(af[u], kl, al[t]);
+#pragma unroll
+          for (int t = 0; t < kPTiles; ++t) {
+            ah[t][j] = mfma16x16x32(af[u][t], kh, ah[t][j]);
+            al[t][j] = mfma16x16x32(af[u][t], kl, al[t][j]);
+          }
         }
       }
     }
   }
+  // the quarters' partial rows, added in wave order (the staging is no longer read)
+  __syncthreads();
+  float* red = reinterpret_cast<float*>(p3m_smem);  // [wave][64 rows][16 NT]
+  constexpr int kRow = 16 * NT;
+#pragma unroll
+  for (int t = 0; t < kPTiles; ++t)
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        red[(wave * 64 + 16 * t + 4 * kq + v) * kRow + 16 * j + (lane & 15)] =
+            ah[t][j][v] + al[t][j][v];
+  __syncthreads();
   float* Pr = P + (rep * (int64_t)nsplit + split) * sP;
-#pragma unroll
-  for (int t = 0; t < NT; ++t) {
-    const int f = 16 * t + (lane & 15);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int c = c0 + 4 * kq + v;
-      if (c < n3) Pr[(int64_t)c * (16 * NT) + f] = ah[t][v] + al[t][v];
-    }
+  for (int q = tid; q < 64 * kRow; q += 256) {
+    const int c = c0 + q / kRow;
+    if (c < n3)
+      Pr[(int64_t)c0 * kRow + q] = ((red[q] + red[64 * kRow + q]) + red[2 * 64 * kRow + q]) +
+                                   red[3 * 64 * kRow + q];
   }
 }
 
@@ -545,7 +574,9 @@ hipError_t launch_p3_mfma(const RepSet& rs, const MfmaLayout& L, int nsplit, con
   const int ksteps = (int)(L.sk / 32);
   int nbmax = brows_of(ksteps, nsplit, L.ld1);
   if (nbmax > rs.n2) nbmax = rs.n2;
-  const size_t sh = (size_t)nf * 4 * ((size_t)L.ld1 + (nbmax + 3) / 4 * 4);
+  size_t sh = (size_t)nf * 4 * ((size_t)L.ld1 + (nbmax + 3) / 4 * 4);
+  const size_t red = (size_t)4 * 64 * nf * 4;  // the four quarters' partial rows
+  if (sh < red) sh = red;
   if (sh > 65536 || sP < (int64_t)rs.n3 * nf) return hipErrorInvalidValue;
   if (nt == 1)
     timed_launch(p3_mfma_kernel<1>, grid, dim3(256), sh, s, rs, L, nsplit, Zk, Atg, Btg, P, sP);
