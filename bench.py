@@ -746,6 +746,7 @@ def bench_serve(args, sbt, torch, synth, log):
             bad += res != sbt.SBT_OK
             lat.append(te - ts)
         fits = [T.fit() for T, _ in made]
+        factors = [T.get_factors() for T, _ in made]
         srv.close()
         for T, pool in made:
             T.close()
@@ -755,11 +756,52 @@ def bench_serve(args, sbt, torch, synth, log):
         return dict(slices_per_s=float(kns.sum()) / wall, wall_s=wall,
                     req_per_s=nreq / wall, p50_ms=1e3 * percentile(lat, 50),
                     p99_ms=1e3 * percentile(lat, 99), failed=int(bad),
-                    fit_min=float(min(fits)), fit_mean=float(np.mean(fits)))
+                    fit_min=float(min(fits)), fit_mean=float(np.mean(fits)), fits=fits,
+                    factors=factors)
+
+    def replay(i, fit_gpu, factors_gpu):
+        """Tensor i's requests replayed in arrival order through the FP64 oracle on
+        the same data (copied from the GPU): its fit and model against the served
+        tensor's."""
+        from oracle import sambaten as osb
+        X, model = gen_tensor(i)
+        K0 = int(K0s[i])
+        Xh = X.cpu().numpy().transpose(2, 1, 0)  # (I, J, K0 + pool) column-major view
+        del X
+        torch.cuda.empty_cache()
+        ocfg = osb.Config(rank=int(Rs[i]), reps=w["r"], als_iters=w["iters"],
+                          sample_factor=w["s"], seed=w["seed"] + i,
+                          k_capacity=K0 + int(grow[i]), workers=host_threads())
+        t0 = time.perf_counter()
+        ora = osb.OracleTensor(ocfg, osb.DENSE, (int(Is[i]), int(Js[i]), K0),
+                               X0=Xh[:, :, :K0], factors=model)
+        nup = 0
+        for q in range(nreq):
+            if who[q] == i:
+                ora.update(Xh[:, :, K0:K0 + int(kns[q])])
+                nup += 1
+        fo = ora.fit()
+        C = factors_gpu[2]
+        return {"tensor": int(i), "I": int(Is[i]), "J": int(Js[i]), "K0": K0,
+                "rank": int(Rs[i]), "updates": nup, "slices_added": int(grow[i]),
+                "gpu_fit": round(fit_gpu, 6), "oracle_fit": round(fo, 6),
+                "abs_dfit": float(f"{abs(fit_gpu - fo):.3g}"),
+                "c_rel_err": float(f"{np.linalg.norm(C - ora.C) / np.linalg.norm(ora.C):.3g}"),
+                "seconds": round(time.perf_counter() - t0, 1)}
 
     closed = run(w["slots"], None)
     log(f"# serve closed loop: {closed['slices_per_s']:.1f} slices/s, "
         f"{closed['req_per_s']:.1f} req/s")
+    replays = []
+    if not args.no_cpu_baseline:
+        # the lowest-fit served tensors of moderate size, replayed through the oracle
+        order = np.argsort(closed["fits"])
+        size = Is * Js * (K0s + grow)
+        for i in [int(i) for i in order if size[i] <= args.serve_replay_max][:2]:
+            rp = replay(i, closed["fits"][i], closed["factors"][i])
+            replays.append(rp)
+            log(f"# oracle replay of tensor {i} ({rp['updates']} requests): fit gpu "
+                f"{rp['gpu_fit']:.6f} oracle {rp['oracle_fit']:.6f}")
     rate = w["load"] * closed["req_per_s"]
     arrivals = synth.poisson_arrivals(nreq, rate, w["seed"])
     opened = run(w["slots"], arrivals)
@@ -784,6 +826,7 @@ def bench_serve(args, sbt, torch, synth, log):
         "one_slot": {"value": round(single["slices_per_s"], 2),
                      "p50_ms": round(single["p50_ms"], 3), "p99_ms": round(single["p99_ms"], 3)},
         "fit_min": round(closed["fit_min"], 6), "fit_mean": round(closed["fit_mean"], 6),
+        "oracle_replay": replays,
         "failed_requests": closed["failed"] + opened["failed"] + single["failed"],
         "roofline": None, "cpu_baseline": None,
     }
@@ -810,6 +853,9 @@ def main():
                          "this many CP runs per candidate rank (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=0,
                     help="requests of the serving workload (default: the workload's 512)")
+    ap.add_argument("--serve-replay-max", type=float, default=4e8,
+                    help="serving: replay through the oracle the two lowest-fit tensors with "
+                         "at most this many entries at their final size")
     ap.add_argument("--coo-init-iters", type=int, default=30,
                     help="sparse: CP-ALS sweeps of the initial decomposition on the GPU "
                          "(0: start from the generator's model)")

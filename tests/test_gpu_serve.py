@@ -111,3 +111,56 @@ def test_error_stays_with_its_request(lib):
     assert T1.batch_counter() == 0 and T2.batch_counter() == 1
     srv.close()
     torch.cuda.synchronize()
+
+
+def test_served_tensors_replayed_through_the_oracle(lib):
+    # FP64 tensors served with interleaved requests on three slots; each tensor's
+    # requests replayed in arrival order through the oracle: samples of the last
+    # update bit-exact, model element by element at 1e-7, fit within 1e-9
+    from oracle import sambaten as osb
+    torch = _torch()
+    made, oracles, data = [], [], []
+    for q, (I, J, K0, R, kns, seed) in enumerate(SHAPES):
+        Ktot = K0 + sum(kns)
+        gen = synth.DenseCP(I, J, Ktot, R, seed=seed, dtype=np.float64)
+        X = gen.slices(0, Ktot)
+        model = gen.true_model_prefix(K0)
+        ocfg = osb.Config(rank=R, reps=4, als_iters=12, sample_factor=2, seed=seed,
+                          tensor_id=q, k_capacity=Ktot)
+        oracles.append(osb.OracleTensor(ocfg, osb.DENSE, (I, J, K0), X0=X[:, :, :K0],
+                                        factors=model))
+        cfg = lib.make_config(R, 4, 12, 2, seed, precision=lib.SBT_P_F64, k_capacity=Ktot,
+                              max_batch=max(kns), tensor_id=q)
+        Xd = lib.dense_to_device(X, np.float64)
+        made.append(lib.Tensor.init_dense(cfg, Xd[:K0], I, J, K0, factors=model))
+        data.append((X, Xd))
+    torch.cuda.synchronize()
+    srv = lib.Server(3, 64 << 20)
+    order = []
+    g = np.random.default_rng(3)
+    pending = [list(kns) for *_, kns, _ in SHAPES]
+    pos = [K0 for _, _, K0, *_ in SHAPES]
+    while any(pending):
+        q = int(g.choice([i for i in range(3) if pending[i]]))
+        kn = pending[q].pop(0)
+        Xd = data[q][1]
+        srv.submit_dense(made[q], Xd[pos[q]:pos[q] + kn], kn)
+        order.append((q, pos[q], kn))
+        pos[q] += kn
+    srv.drain()
+    for q, k0, kn in order:  # the oracle in the same per-tensor arrival order
+        d = oracles[q].update(data[q][0][:, :, k0:k0 + kn], debug=True)
+        if k0 + kn == pos[q]:
+            for rho in range(4):
+                for mode, key in enumerate(("Is", "Js", "Ks")):
+                    np.testing.assert_array_equal(made[q].last_sample(rho, mode),
+                                                  d["reps"][rho][key])
+    for T, ora in zip(made, oracles):
+        A, B, C, lam = T.get_factors()
+        np.testing.assert_allclose(A, ora.A, rtol=1e-7, atol=1e-9)
+        np.testing.assert_allclose(B, ora.B, rtol=1e-7, atol=1e-9)
+        np.testing.assert_allclose(C, ora.C, rtol=1e-7, atol=1e-9)
+        assert abs(T.fit() - ora.fit()) < 1e-9
+    srv.close()
+    for T in made:
+        T.close()
