@@ -12,6 +12,13 @@ before timing, the model starting from the generator's factors):
               update batches of 50 frontal slices; s = 5, r = 10, 30 ALS sweeps.
               `value` is the batched FP32 schedule; the plain FP32 schedule and
               the batched BF16 (matrix-core) path run on the same batches.
+  getrank400  GetRank on rank-deficient updates (Sec. 3.2; Q3 of Sec. 4): dense
+              FP32 400 x 400 x 400 of true rank 3 (N(0,1) factors, nearly
+              orthogonal components) with a rank-5 model (the three generating
+              components and two small ones the data do not hold), batches of
+              50, s = 2, r = 4: the
+              update with GetRank (`value`) and without, factor match score of
+              each against the generating components.
   dense4d     dense FP32 order-4 120 x 120 x 120 x 120 (the last mode grows),
               rank-10 U[0,1) CP model plus 1% noise, batches of 12 slices; s = 4
               on every mode, r = 10, 30 ALS sweeps.  `value` is the FP32 path; the
@@ -83,6 +90,11 @@ WORKLOADS = {
                     desc="serving: 16 resident dense FP32 tensors (I, J uniform in [200, 2000], "
                          "K0 in [100, 1000], rank 5-20), 512 update requests of 5-100 slices, "
                          "s=5, r=10, 30 ALS sweeps, 4 concurrent slots"),
+    "getrank400": dict(kind="getrank", I=400, J=400, K0=400, Kn=50, R=5, R_true=3, s=2, r=4,
+                       iters=30, seed=7, noise=0.01,
+                       desc="GetRank (Sec. 3.2): dense FP32 400x400x400 of true rank 3 "
+                            "(N(0,1) factors) with a rank-5 model, 50-slice batches, s=2, r=4, "
+                            "30 ALS sweeps; the update with and without GetRank"),
     "dense4d": dict(kind="nd", dims=(120, 120, 120), K0=120, Kn=12, R=10, s=4, r=10, iters=30,
                     seed=6, noise=0.01,
                     desc="dense FP32 order-4 120x120x120x120 + 12-slice batches along the last "
@@ -472,6 +484,89 @@ def bench_dense(args, sbt, torch, synth, log):
     if "plain_f32" in runs:
         line["over_plain_f32"] = round(b["slices_per_s"] / runs["plain_f32"]["slices_per_s"], 3)
     line["kernels"] = kernels_table(b["profile"])
+    return line
+
+
+def bench_getrank(args, sbt, torch, synth, log):
+    """Rank-deficient updates (Sec. 3.2, Q3 of Sec. 4): the data hold R_true < R
+    components, the model R (the generating components of the initial block
+    and R - R_true small components the data do not hold).  The update
+    with GetRank (one CP run per candidate rank, threshold 90) against the one
+    without, on the same batches: factor match score against the generating
+    components (padded with zero components to rank R: those pairs score 0, so
+    R_true / R is the best possible score) and fit."""
+    w = WORKLOADS[args.workload]
+    steps = args.steps
+    I, J, K0, Kn, R = w["I"], w["J"], w["K0"], w["Kn"], w["R"]
+    K = K0 + steps * Kn
+    gen = synth.DenseCP(I, J, K, w["R_true"], seed=w["seed"], noise=w["noise"],
+                        dtype=np.float32, factors="normal")
+    Xd = torch.empty((K, J, I), dtype=torch.float32, device="cuda")
+    gen.fill_device(torch, Xd)
+    torch.cuda.synchronize()
+    A, B, C, lam = gen.true_model_prefix(K)
+    pad = R - w["R_true"]
+    truth = (np.hstack([A, np.zeros((I, pad))]), np.hstack([B, np.zeros((J, pad))]),
+             np.hstack([C, np.zeros((K, pad))]), np.concatenate([lam, np.zeros(pad)]))
+    # the model: the generating components of the initial block and R - R_true
+    # components that the data do not hold (random unit columns, weight 1% of the
+    # smallest true one): an R-component model whose updates have rank R_true
+    g = np.random.default_rng(np.random.SeedSequence([w["seed"], 31]))
+    extra = [g.standard_normal((n, pad)) for n in (I, J, K0)]
+    extra = [M / np.linalg.norm(M, axis=0) for M in extra]
+    A0, B0, C0, lam0 = gen.true_model_prefix(K0)
+    model = (np.hstack([A0, extra[0]]), np.hstack([B0, extra[1]]), np.hstack([C0, extra[2]]),
+             np.concatenate([lam0, np.full(pad, 0.01 * lam0.min())]))
+    cfg0 = sbt.make_config(R, w["r"], w["iters"], w["s"], w["seed"], precision=sbt.SBT_P_F32,
+                           k_capacity=K, max_batch=Kn)
+    T0 = sbt.Tensor.init_dense(cfg0, Xd[:K0], I, J, K0, factors=model)
+    init_fit = T0.fit()
+    T0.close()
+    log(f"# rank-{R} model of rank-{w['R_true']} data: fit {init_fit:.6f}")
+    out, firsts = {}, {}
+    for name, runs in (("without", 0), ("with", 1)):
+        first = None if args.no_cpu_baseline else firsts.setdefault(name, {})
+        res = run_dense(sbt, torch, w, Xd, model, sbt.SBT_P_F32, sbt.SBT_SCHED_BATCHED, steps,
+                        args.warmup, 1, truth=truth, getrank_runs=runs, first=first)
+        out[name] = dict(path_summary(res), fms_truth=round(res["fms_truth"], 4))
+        log(f"# {name} GetRank: {res['slices_per_s']:.1f} slices/s, fit {res['fit']:.6f}, "
+            f"FMS vs truth {res['fms_truth']:.4f}")
+    line = {
+        "metric": "updated slices/sec with GetRank on rank-deficient data (factor match score "
+                  "against the generating components and fit, with and without GetRank)",
+        "value": out["with"]["value"], "unit": "slices/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": out["with"]["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w["desc"], "I": I, "J": J, "K0": K0, "batch": Kn, "rank": R,
+                   "true_rank": w["R_true"], "s": w["s"], "r": w["r"], "als_iters": w["iters"],
+                   "getrank_runs": 1, "getrank_threshold": 90.0},
+        "fms_truth_best_possible": round(w["R_true"] / R, 4),
+        "with_getrank": out["with"], "without_getrank": out["without"],
+        "initial_fit": round(init_fit, 6), "roofline": None, "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        # the oracle with GetRank on the first update of the same data
+        from oracle import sambaten as osb
+        Xh = Xd[:K0 + Kn].cpu().numpy().transpose(2, 1, 0)
+        ocfg = osb.Config(rank=R, reps=w["r"], als_iters=w["iters"], sample_factor=w["s"],
+                          seed=w["seed"], k_capacity=K0 + Kn, getrank_runs=1,
+                          workers=host_threads())
+        ora = osb.OracleTensor(ocfg, osb.DENSE, (I, J, K0), X0=Xh[:, :, :K0], factors=model)
+        t0 = time.perf_counter()
+        d = ora.update(Xh[:, :, K0:K0 + Kn], debug=True)
+        dt = time.perf_counter() - t0
+        fo = ora.fit()
+        line["cpu_baseline"] = {"value": round(Kn / dt, 3), "unit": "slices/s",
+                                "cores": host_threads(), "kind": "oracle",
+                                "sample": f"the first update with GetRank ({Kn} slices, "
+                                          f"r={w['r']}) of the same data, {dt:.1f} s",
+                                "fit_after": round(fo, 6),
+                                "rnew": [int(r["Rnew"]) for r in d["reps"]]}
+        f = firsts["with"]
+        line["vs_oracle_first_update"] = {"abs_dfit": float(f"{abs(f['fit'] - fo):.3g}")}
+        log(f"# oracle with GetRank: R_new {line['cpu_baseline']['rnew']}, fit {fo:.6f} "
+            f"(GPU {f['fit']:.6f})")
     return line
 
 
@@ -896,6 +991,8 @@ def main():
         line = bench_nd(args, sbt, torch, synth, log)
     elif WORKLOADS[args.workload]["kind"] == "serve":
         line = bench_serve(args, sbt, torch, synth, log)
+    elif WORKLOADS[args.workload]["kind"] == "getrank":
+        line = bench_getrank(args, sbt, torch, synth, log)
     else:
         line = bench_dense(args, sbt, torch, synth, log)
     print(json.dumps(line))

@@ -23,20 +23,24 @@ def _gen(seed, stream, block=0):
 
 
 class DenseCP:
-    """X = sum_r A(:,r) o B(:,r) o C(:,r) + N(0, sigma^2), factors U[0,1).
+    """X = sum_r A(:,r) o B(:,r) o C(:,r) + N(0, sigma^2), factors U[0,1) (or
+    N(0,1) with factors="normal").
 
     sigma = noise * ||X_clean||_F / sqrt(I*J*K), with ||X_clean||^2 taken in
     closed form from the factor Gram matrices, so the noise is `noise` of the
     tensor norm in expectation and slices can be produced in any order.
     """
 
-    def __init__(self, I, J, K, R, seed, noise=0.01, dtype=np.float32):
+    def __init__(self, I, J, K, R, seed, noise=0.01, dtype=np.float32, factors="uniform"):
         self.I, self.J, self.K, self.R = int(I), int(J), int(K), int(R)
         self.seed, self.noise, self.dtype = int(seed), float(noise), np.dtype(dtype)
         g = _gen(seed, STREAM_FACTOR)
-        self.A = g.random((self.I, self.R))
-        self.B = g.random((self.J, self.R))
-        self.C = g.random((self.K, self.R))
+        # factor entries U[0,1) (nonnegative, nearly collinear columns) or N(0,1)
+        # (nearly orthogonal columns)
+        draw = g.random if factors == "uniform" else g.standard_normal
+        self.A = draw((self.I, self.R))
+        self.B = draw((self.J, self.R))
+        self.C = draw((self.K, self.R))
         H = (self.A.T @ self.A) * (self.B.T @ self.B) * (self.C.T @ self.C)
         self.clean_norm2 = float(H.sum())
         self.sigma = self.noise * np.sqrt(self.clean_norm2 / (self.I * self.J * self.K))
