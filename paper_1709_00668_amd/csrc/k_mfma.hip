@@ -342,14 +342,14 @@ __global__ __launch_bounds__(256) void p3_mfma_kernel(RepSet rs, MfmaLayout L, i
     }
   }
   __syncthreads();
-  f32x4_t ah[kPTiles][NT], al[kPTiles][NT];
+  // one accumulator per tile takes both the hi and the lo product: the four
+  // tiles' hi products go first, then their lo products, so each accumulation
+  // has three independent MFMAs between it and the one it depends on
+  f32x4_t acc[kPTiles][NT];
 #pragma unroll
   for (int t = 0; t < kPTiles; ++t)
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
-      ah[t][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-      al[t][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-    }
+    for (int j = 0; j < NT; ++j) acc[t][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
   for (int k0 = kw_lo; k0 < kw_hi; k0 += kPSteps) {
     if (k0 > kw_lo) {
 #pragma unroll
@@ -376,10 +376,9 @@ __global__ __launch_bounds__(256) void p3_mfma_kernel(RepSet rs, MfmaLayout L, i
           bf16x8_t kh, kl;
           split_bf16x8(x, kh, kl);
 #pragma unroll
-          for (int t = 0; t < kPTiles; ++t) {
-            ah[t][j] = mfma16x16x32(af[u][t], kh, ah[t][j]);
-            al[t][j] = mfma16x16x32(af[u][t], kl, al[t][j]);
-          }
+          for (int t = 0; t < kPTiles; ++t) acc[t][j] = mfma16x16x32(af[u][t], kh, acc[t][j]);
+#pragma unroll
+          for (int t = 0; t < kPTiles; ++t) acc[t][j] = mfma16x16x32(af[u][t], kl, acc[t][j]);
         }
       }
     }
@@ -394,8 +393,7 @@ __global__ __launch_bounds__(256) void p3_mfma_kernel(RepSet rs, MfmaLayout L, i
     for (int j = 0; j < NT; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        red[(wave * 64 + 16 * t + 4 * kq + v) * kRow + 16 * j + (lane & 15)] =
-            ah[t][j][v] + al[t][j][v];
+        red[(wave * 64 + 16 * t + 4 * kq + v) * kRow + 16 * j + (lane & 15)] = acc[t][j][v];
   __syncthreads();
   float* Pr = P + (rep * (int64_t)nsplit + split) * sP;
   for (int q = tid; q < 64 * kRow; q += 256) {
