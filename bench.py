@@ -249,8 +249,9 @@ def kernel_digest(kernel, read=None):
 
 def committed_traffic(kernel, key):
     """HBM bytes per launch of `kernel` from a committed counter summary
-    (profiles/<workload>_traffic.md) taken on the same workload (`key`) and on
-    the kernel's current sources (per-kernel digest column)."""
+    (profiles/<workload>_traffic.md) taken on the same workload and step count
+    (`key`, so the same launches) and on the kernel's current sources
+    (per-kernel digest column)."""
     name = key.split("@")[0]
     path = os.path.join(ROOT, "profiles", f"{name}_traffic.md")
     if not os.path.exists(path):
@@ -408,7 +409,7 @@ def bench_dense(args, sbt, torch, synth, log):
     b = runs[main]
     path = "f32" if main == "batched_f32" else "bf16"
     line = base_line(args, w, b, path)
-    line["roofline"] = roofline_of(b["profile"], path, w["R"], name)
+    line["roofline"] = roofline_of(b["profile"], path, w["R"], f"{name}@steps{steps}")
     if path == "bf16":
         # useful matrix-core work of the mode-3 pass: 2 |Z| R flops per summary
         pr = b["profile"]["mttkrp_third_mode"]
@@ -635,7 +636,8 @@ def bench_nd(args, sbt, torch, synth, log):
         "fit": round(b["fit"], 6),
     }
     n0 = -(-dims[0] // w["s"])
-    line["roofline"] = roofline_of(b["profile"], "nd_f32", R, name, n1_third=n0)
+    line["roofline"] = roofline_of(b["profile"], "nd_f32", R, f"{name}@steps{steps}",
+                                   n1_third=n0)
     if not args.no_recompute:
         # relative fitness against CP-ALS recomputed on the whole grown tensor (Sec. 4.2)
         cfg_r = sbt.make_config(R, w["r"], w["iters"], 1, w["seed"], precision=sbt.SBT_P_F32,
@@ -710,7 +712,8 @@ def bench_sparse(args, sbt, torch, synth, log):
     line["config"]["nnz0"] = len(v0)
     line["config"]["nnz_batch"] = nnzb
     line["initial_cp_als"] = init
-    line["roofline"] = roofline_of(res["profile"], "coo", w["R"], f"{name}@{args.nnz_scale:g}",
+    line["roofline"] = roofline_of(res["profile"], "coo", w["R"],
+                                   f"{name}@{args.nnz_scale:g}@steps{steps}",
                                    summary_rows=w["r"] * -(-w["I"] // w["s"]))
     line["cpu_baseline"] = None
     if not args.no_recompute:
