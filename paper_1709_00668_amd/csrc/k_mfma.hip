@@ -62,17 +62,21 @@ __device__ inline void split_bf16x8(const float (&x)[8], bf16x8_t& hi, bf16x8_t&
 // ---------------------------------------------------------------------------
 // gather: both layouts from the resident store in one pass
 // ---------------------------------------------------------------------------
-// thread = (e, group of 8 third-mode positions); c >= K' are written as zeros
-// in Zc (the K range of pass W is K' rounded up to 32).
+// thread = (e, run of kGatherGroups groups of 8 third-mode positions): the
+// thread writes whole 128-byte lines of its Zc row (the groups of a run are
+// consecutive), gathering one group of 8 slices at a time; c >= K' are
+// written as zeros in Zc (the K range of pass W is K' rounded up to 32).
+constexpr int kGatherGroups = 8;
+
 template <typename TIn>
 __global__ __launch_bounds__(256) void gather_mfma_kernel(const TIn* X, int64_t I, int64_t J,
                                                          const int32_t* idx, int64_t idx_stride,
                                                          int64_t offJ, int64_t offK, int n3old,
-                                                         int64_t Kold, int cg0, RepSet rs,
-                                                         MfmaLayout L, uint16_t* Zk,
+                                                         int64_t Kold, int cg0, int ncg,
+                                                         RepSet rs, MfmaLayout L, uint16_t* Zk,
                                                          uint16_t* Zc) {
   const int rep = rs.rep0 + blockIdx.z;
-  const int cg = cg0 + (int)blockIdx.y;
+  const int g0 = cg0 + (int)blockIdx.y * kGatherGroups;
   const int64_t n12 = (int64_t)rs.n1 * rs.n2;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= n12) return;
@@ -80,23 +84,26 @@ __global__ __launch_bounds__(256) void gather_mfma_kernel(const TIn* X, int64_t 
   const int32_t* Is = idx + rep * idx_stride;
   const int64_t base = (int64_t)Is[a] + I * (int64_t)Is[offJ + b];
   uint16_t* zk = Zk + rep * L.sZk + a + (int64_t)L.ld1 * b;
-  uint16_t v[8];
+  uint16_t* zc = Zc + rep * L.sZc + e * L.ldc;
+  for (int cg = g0; cg < g0 + kGatherGroups && cg < cg0 + ncg; ++cg) {
+    uint16_t v[8];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const int c = cg * 8 + j;
-    v[j] = 0;
-    if (c < rs.n3) {
-      const int64_t kk = c < n3old ? (int64_t)Is[offK + c] : Kold + (c - n3old);
-      v[j] = f32_to_bf16_rne((float)X[base + I * J * kk]);
-      zk[L.sk * c] = v[j];
+    for (int j = 0; j < 8; ++j) {
+      const int c = cg * 8 + j;
+      v[j] = 0;
+      if (c < rs.n3) {
+        const int64_t kk = c < n3old ? (int64_t)Is[offK + c] : Kold + (c - n3old);
+        v[j] = f32_to_bf16_rne((float)X[base + I * J * kk]);
+        zk[L.sk * c] = v[j];
+      }
     }
+    uint4 pk;
+    pk.x = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
+    pk.y = (uint32_t)v[2] | ((uint32_t)v[3] << 16);
+    pk.z = (uint32_t)v[4] | ((uint32_t)v[5] << 16);
+    pk.w = (uint32_t)v[6] | ((uint32_t)v[7] << 16);
+    *reinterpret_cast<uint4*>(zc + cg * 8) = pk;
   }
-  uint4 pk;
-  pk.x = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
-  pk.y = (uint32_t)v[2] | ((uint32_t)v[3] << 16);
-  pk.z = (uint32_t)v[4] | ((uint32_t)v[5] << 16);
-  pk.w = (uint32_t)v[6] | ((uint32_t)v[7] << 16);
-  *reinterpret_cast<uint4*>(Zc + rep * L.sZc + e * L.ldc + cg * 8) = pk;
 }
 
 // BF16 tensor (column-major bits) -> both layouts, for the stand-alone MTTKRP.
@@ -490,13 +497,15 @@ hipError_t launch_gather_mfma(int store_prec, const void* X, int64_t I, int64_t 
   const int kp32 = (rs.n3 + 31) / 32 * 32;
   if (c0 < 0 || c0 >= rs.n3) return hipErrorInvalidValue;
   const int cg0 = c0 / 8;  // groups of 8 slices, the first one gathered whole
-  dim3 grid((unsigned)((n12 + 255) / 256), (unsigned)(kp32 / 8 - cg0), (unsigned)rs.nrep);
+  const int ncg = kp32 / 8 - cg0;
+  dim3 grid((unsigned)((n12 + 255) / 256), (unsigned)((ncg + kGatherGroups - 1) / kGatherGroups),
+            (unsigned)rs.nrep);
   if (store_prec == kF64)
     timed_launch(gather_mfma_kernel<double>, grid, dim3(256), 0, s, (const double*)X, I, J, idx,
-                 idx_stride, offJ, offK, n3old, Kold, cg0, rs, L, Zk, Zc);
+                 idx_stride, offJ, offK, n3old, Kold, cg0, ncg, rs, L, Zk, Zc);
   else
     timed_launch(gather_mfma_kernel<float>, grid, dim3(256), 0, s, (const float*)X, I, J, idx,
-                 idx_stride, offJ, offK, n3old, Kold, cg0, rs, L, Zk, Zc);
+                 idx_stride, offJ, offK, n3old, Kold, cg0, ncg, rs, L, Zk, Zc);
   return hipGetLastError();
 }
 
