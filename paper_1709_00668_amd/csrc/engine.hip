@@ -719,9 +719,12 @@ sbt_status gram_rows(sbt_tensor* t, const RepSet& rs, const double* U, int64_t s
   return SBT_OK;
 }
 
-// the tail of a mode update; long factors get their Gram matrix beforehand
+// the tail of a mode update; the tail kernel takes the factor's rows in
+// chunks of its staging buffer (one block per repetition), and factors longer
+// than two chunks get their Gram matrix from the chunked cross products
+// (many blocks) beforehand
 sbt_status tail(sbt_tensor* t, const RepSet& rs, AlsTail ta, hipStream_t st) {
-  if (!tail_rows_fit(ta.rows, rs.R)) {
+  if (!tail_rows_fit(ta.rows / 2, rs.R)) {
     SBT_TRY(gram_rows(t, rs, ta.U, ta.sU, ta.rows, t->xout, st));
     ta.Gin = t->xout;
   }
