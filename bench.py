@@ -671,10 +671,28 @@ def bench_sparse(args, sbt, torch, synth, log):
     I, J, K0, Kn = w["I"], w["J"], w["K0"], w["Kn"]
     t0 = time.perf_counter()
     gen = synth.SparseCP(I, J, K0 + steps * Kn, w["R"], seed=w["seed"])
-    idx0, v0 = gen.slices(0, K0, nnz0, block_id=0)
+    cache = None
+    if args.data_cache:
+        os.makedirs(args.data_cache, exist_ok=True)
+        cache = os.path.join(args.data_cache, f"sparse_{w['seed']}_{nnz0}_{nnzb}_{steps}.npz")
+    if cache and os.path.exists(cache):
+        # the generator's output of an earlier run (same seed, counts and steps)
+        z = np.load(cache)
+        idx0, v0 = z["idx0"], z["v0"]
+        batches = [(z[f"idx{b + 1}"], z[f"v{b + 1}"]) for b in range(steps)]
+        gen.last_mean = float(z["last_mean"])
+    else:
+        idx0, v0 = gen.slices(0, K0, nnz0, block_id=0)
+        mean0 = gen.last_mean
+        batches = [gen.slices(K0 + b * Kn, K0 + (b + 1) * Kn, nnzb, block_id=b + 1)
+                   for b in range(steps)]
+        gen.last_mean = mean0
+        if cache:
+            arrs = {"idx0": idx0, "v0": v0, "last_mean": np.float64(mean0)}
+            for b, (ix, v) in enumerate(batches):
+                arrs[f"idx{b + 1}"], arrs[f"v{b + 1}"] = ix, v
+            np.savez(cache, **arrs)
     model = synth.sparse_model(gen, K0, gen.last_mean)  # the generator's (replaced below)
-    batches = [gen.slices(K0 + b * Kn, K0 + (b + 1) * Kn, nnzb, block_id=b + 1)
-               for b in range(steps)]
     cols0, vd0 = sbt.coo_to_device(idx0, v0)
     bdev = [sbt.coo_to_device(ix, v) for ix, v in batches]
     nnz_total = len(v0) + sum(len(v) for _, v in batches)
@@ -957,6 +975,8 @@ def main():
     ap.add_argument("--coo-init-iters", type=int, default=30,
                     help="sparse: CP-ALS sweeps of the initial decomposition on the GPU "
                          "(0: start from the generator's model)")
+    ap.add_argument("--data-cache", default="",
+                    help="sparse: keep the generated nonzeros in this folder and reuse them")
     ap.add_argument("--nnz-scale", type=float, default=1.0,
                     help="scale the nonzero counts of the sparse workload")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
