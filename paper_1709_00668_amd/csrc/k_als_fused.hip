@@ -421,22 +421,49 @@ __global__ __launch_bounds__(256) void pw_kernel(RepSet rs, const TZ* Z, const d
 // ---------------------------------------------------------------------------
 // modes 1 and 2 from W
 // ---------------------------------------------------------------------------
+// W of one repetition is stored [b][a][f] (row e = a + n1 b of R entries), and
+// both contractions read all of it:
+//   mode 0: rows a of A, M(a, f) = sum_b W(a, b, f) B~(b, f);
+//   mode 1: rows b of B, M(b, f) = sum_a W(a, b, f) A~(a, f).
+// Every W element is read by a vector load of V consecutive entries (V the
+// widest of 16 bytes, 8, one element that divides R), and the threads of a
+// block are laid out so that their loads form contiguous runs in memory:
+//   mode 0: the block's 8 rows a form one run of 8 R entries per b; G = 8 R / V
+//           threads cover the run and 256 / G slots of G threads step through b;
+//   mode 1: row b is one run of n1 R entries; 32 threads per row, of which
+//           T = (32 / (R / V)) (R / V) step through it by T vectors, so each
+//           keeps the same V columns f throughout.
+// The partials of a row are added through LDS in a fixed order, the row is
+// multiplied by V^-1 (raw rows U = M V^-1 are written; the tail follows).
+// The contracted factor is staged in LDS in chunks of chr rows (one chunk when
+// it fits); each thread's first W loads of a chunk go out before its staging.
 constexpr int kRowsPerBlock = 8;   // factor rows produced by one block
-constexpr int kSlots = 32;         // threads sharing one row (the contracted index)
+constexpr int kSlots = 32;         // chunk rows are a multiple of this
+constexpr int kCwPre = 8;          // W vector loads in flight per thread
 
-// mode = 0: rows a of A from B~;  mode = 1: rows b of B from A~.  Raw rows
-// U = M V^-1 are written; the tail kernel follows.  The contracted factor is
-// staged in LDS in chunks of chr rows (one chunk when it fits); each thread's
-// first rows of W are loaded before the staging so the two latencies overlap.
-constexpr int kCwPre = 4;  // W rows in flight per thread
+template <typename TA, int V>
+__device__ inline void ldw(const TA* p, TA (&o)[V]) {
+  if constexpr (V == 4) {
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+  } else if constexpr (V == 2 && sizeof(TA) == 4) {
+    const float2 v = *reinterpret_cast<const float2*>(p);
+    o[0] = v.x; o[1] = v.y;
+  } else if constexpr (V == 2) {
+    const double2 v = *reinterpret_cast<const double2*>(p);
+    o[0] = v.x; o[1] = v.y;
+  } else {
+    o[0] = *p;
+  }
+}
 
-template <typename TA, int RP>
+template <typename TA, int RP, int V>
 __global__ __launch_bounds__(256) void cw_kernel(RepSet rs, int mode, int chr, const TA* W,
                                                 const double* F, const double* invlamF,
                                                 const double* Vinv, double* Uout, int64_t sU,
                                                 TailArgs pro) {
   extern __shared__ __align__(16) unsigned char cw_smem[];
-  __shared__ TA red[4][kRowsPerBlock][RP];
+  __shared__ TA red[256 * V];
   __shared__ double Mrow[kRowsPerBlock][kMaxRank];
   __shared__ double Vi[kMaxRank][kLd];
   __shared__ double ilp[kMaxRank];
@@ -444,30 +471,48 @@ __global__ __launch_bounds__(256) void cw_kernel(RepSet rs, int mode, int chr, c
   const int rep = rs.rep0 + blockIdx.y;
   const int R = rs.R, n1 = rs.n1, n2 = rs.n2;
   const int tid = threadIdx.x;
-  // mode 0: row = low 3 bits of tid (consecutive a, coalesced), slot = high 5
-  // mode 1: slot = low 5 bits (consecutive a, coalesced), row = high 3
-  const int rl = mode == 0 ? (tid & (kRowsPerBlock - 1)) : (tid >> 5);  // row within block
-  const int sl = mode == 0 ? (tid >> 3) : (tid & (kSlots - 1));         // slot
-  const int row = blockIdx.x * kRowsPerBlock + rl;
+  const int gpr = R / V;  // vectors per row of W
   const int nrows = mode == 0 ? n1 : n2;
   const int ncon = mode == 0 ? n2 : n1;  // contracted extent
-  const bool ok = row < nrows;
+  // mode 0: G threads per run, S slots;  mode 1: 32 threads per row, T active
+  const int G = kRowsPerBlock * gpr, S = 256 / G;
+  const int T = (32 / gpr) * gpr;
+  int rl, slot, f0, step;
+  if (mode == 0) {
+    const int grp = tid % G;
+    slot = tid / G;
+    rl = grp / gpr;
+    f0 = (grp % gpr) * V;
+    step = S;  // contracted rows b per step of a slot
+  } else {
+    rl = tid / 32;
+    slot = tid % 32;
+    f0 = (slot % gpr) * V;
+    step = T;  // vectors per step along the row
+  }
+  const int row = blockIdx.x * kRowsPerBlock + rl;
+  const bool act = (mode == 0 ? slot < S : slot < T) && row < nrows;
   const TA* Wr = W + rep * rs.sW;
+  // mode 0: vector of contracted row x is at (x n1 + row) R + f0
+  // mode 1: vector q of the row is at row n1 R + q V, contracted row q / gpr
+  const TA* wbase = mode == 0 ? Wr + (int64_t)row * R + f0 : Wr + (int64_t)row * n1 * R;
+  const int64_t wstep = mode == 0 ? (int64_t)n1 * R : (int64_t)V;
   const double* Fr = F + (mode == 0 ? rep * rs.sB : rep * rs.sA);
   const double* il = invlamF + rep * 3 * R;
-  TA acc[RP];
+  TA acc[V];
 #pragma unroll
-  for (int f = 0; f < RP; ++f) acc[f] = 0;
+  for (int v = 0; v < V; ++v) acc[v] = 0;
   for (int x0 = 0; x0 < ncon; x0 += chr) {
     const int xn = ncon - x0 < chr ? ncon - x0 : chr;
-    TA w[kCwPre][RP];
+    // positions of this thread in the chunk: contracted rows (mode 0) or
+    // vectors of the row (mode 1), from p0 by step, below pn
+    const int p0 = mode == 0 ? x0 + slot : x0 * gpr + slot;
+    const int pn = mode == 0 ? x0 + xn : (x0 + xn) * gpr;
+    TA w[kCwPre][V];
 #pragma unroll
     for (int u = 0; u < kCwPre; ++u) {
-      const int x = x0 + sl + u * kSlots;
-      const bool v = ok && x < x0 + xn;
-      const int64_t e = mode == 0 ? (int64_t)row + (int64_t)n1 * x : (int64_t)x + (int64_t)n1 * row;
-#pragma unroll
-      for (int f = 0; f < RP; ++f) w[u][f] = (v && f < R) ? Wr[e * R + f] : (TA)0;
+      const int p = p0 + u * step;
+      if (act && p < pn) ldw<TA, V>(wbase + wstep * p, w[u]);
     }
     __syncthreads();
     if (x0 == 0) {
@@ -486,67 +531,41 @@ __global__ __launch_bounds__(256) void cw_kernel(RepSet rs, int mode, int chr, c
     }
     stage_rows<TA, RP>(Fs, xn, Fr + (int64_t)x0 * R, R, pro.U ? ilp : il);
     __syncthreads();
+    if (act) {
+      int p = p0;
+      for (bool first = true; p < pn; first = false) {
+        if (!first) {
 #pragma unroll
-    for (int u = 0; u < kCwPre; ++u) {
-      const int x = sl + u * kSlots;
-      if (x < xn) {
-#pragma unroll
-        for (int f = 0; f < RP; ++f) acc[f] += w[u][f] * Fs[x * RP + f];
-      }
-    }
-    for (int xb = sl + kCwPre * kSlots; xb < xn; xb += kCwPre * kSlots) {
-#pragma unroll
-      for (int u = 0; u < kCwPre; ++u) {
-        const int x = x0 + xb + u * kSlots;
-        const bool v = ok && x < x0 + xn;
-        const int64_t e =
-            mode == 0 ? (int64_t)row + (int64_t)n1 * x : (int64_t)x + (int64_t)n1 * row;
-#pragma unroll
-        for (int f = 0; f < RP; ++f) w[u][f] = (v && f < R) ? Wr[e * R + f] : (TA)0;
-      }
-#pragma unroll
-      for (int u = 0; u < kCwPre; ++u) {
-        const int x = xb + u * kSlots;
-        if (x < xn) {
-#pragma unroll
-          for (int f = 0; f < RP; ++f) acc[f] += w[u][f] * Fs[x * RP + f];
+          for (int u = 0; u < kCwPre; ++u)
+            if (p + u * step < pn) ldw<TA, V>(wbase + wstep * (p + u * step), w[u]);
         }
+#pragma unroll
+        for (int u = 0; u < kCwPre; ++u) {
+          const int q = p + u * step;
+          if (q < pn) {
+            const int x = (mode == 0 ? q : q / gpr) - x0;
+            const TA* fs = Fs + x * RP + f0;
+#pragma unroll
+            for (int v = 0; v < V; ++v) acc[v] += w[u][v] * fs[v];
+          }
+        }
+        p += kCwPre * step;
       }
     }
   }
-  // reduce over the 32 slots: within the wave first, then across waves
-  const int wave = tid >> 6;
+  // partials of the threads, then each output added in a fixed order
 #pragma unroll
-  for (int f = 0; f < RP; ++f) {
-    TA v = acc[f];
-    if (mode == 0) {  // slots differ in tid bits 3..5 within a wave
-      v += __shfl_xor(v, 8, kWave);
-      v += __shfl_xor(v, 16, kWave);
-      v += __shfl_xor(v, 32, kWave);
-    } else {          // slots are tid bits 0..4
-      v += __shfl_xor(v, 1, kWave);
-      v += __shfl_xor(v, 2, kWave);
-      v += __shfl_xor(v, 4, kWave);
-      v += __shfl_xor(v, 8, kWave);
-      v += __shfl_xor(v, 16, kWave);
-    }
-    acc[f] = v;
-  }
-  __syncthreads();
-  if (mode == 0) {  // each wave holds 8 of the 32 slots
-    if ((tid & 63) < kRowsPerBlock)
-#pragma unroll
-      for (int f = 0; f < RP; ++f) red[wave][rl][f] = acc[f];
-  } else {          // each wave holds two rows, all 32 slots
-    if (sl == 0)
-#pragma unroll
-      for (int f = 0; f < RP; ++f) red[0][rl][f] = acc[f];
-  }
+  for (int v = 0; v < V; ++v) red[tid * V + v] = act ? acc[v] : (TA)0;
   __syncthreads();
   for (int q = tid; q < kRowsPerBlock * R; q += 256) {
-    const int r = q / R, f = q % R;
-    Mrow[r][f] = mode == 0 ? (double)((red[0][r][f] + red[1][r][f]) + (red[2][r][f] + red[3][r][f]))
-                           : (double)red[0][r][f];
+    const int r = q / R, f = q % R, fg = f / V, v = f % V;
+    TA s = 0;
+    if (mode == 0) {
+      for (int sl = 0; sl < S; ++sl) s += red[(sl * G + r * gpr + fg) * V + v];
+    } else {
+      for (int sl = fg; sl < T; sl += gpr) s += red[(r * 32 + sl) * V + v];
+    }
+    Mrow[r][f] = (double)s;
   }
   __syncthreads();
   double* U = Uout + rep * sU;
@@ -808,14 +827,22 @@ hipError_t launch_cw(int prec, const RepSet& rs, int mode, const void* W, const 
   if (chr < kSlots) chr = kSlots;
   size_t sh = (size_t)chr * row_bytes;
   if (before && sh < sizeof(TailSmem)) sh = sizeof(TailSmem);
+  // widest vector of W entries that divides R (16 bytes at most)
+  const int vw = prec == kF64 ? (rs.R % 2 == 0 ? 2 : 1)
+                              : (rs.R % 4 == 0 ? 4 : (rs.R % 2 == 0 ? 2 : 1));
+#define SBT_CW(TA_, RPV, VV)                                                                    \
+  cw_kernel<TA_, RPV, VV><<<grid, 256, sh, s>>>(rs, mode, chr, (const TA_*)W, F, invlamF, Vinv, \
+                                                U, sU, pro)
   SBT_RP_SWITCH(rs.R, {
-    if (prec == kF64)
-      cw_kernel<double, RP><<<grid, 256, sh, s>>>(rs, mode, chr, (const double*)W, F, invlamF,
-                                                  Vinv, U, sU, pro);
-    else
-      cw_kernel<float, RP><<<grid, 256, sh, s>>>(rs, mode, chr, (const float*)W, F, invlamF,
-                                                 Vinv, U, sU, pro);
+    if (prec == kF64) {
+      if (vw == 2) SBT_CW(double, RP, 2); else SBT_CW(double, RP, 1);
+    } else {
+      if (vw == 4) SBT_CW(float, RP, 4);
+      else if (vw == 2) SBT_CW(float, RP, 2);
+      else SBT_CW(float, RP, 1);
+    }
   });
+#undef SBT_CW
   return hipGetLastError();
 }
 
