@@ -44,6 +44,8 @@ __device__ inline f32x4_t mfma16x16x32(const bf16x8_t& a, const bf16x8_t& b,
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
 __device__ inline bf16x8_t ld_bf16x8(const uint16_t* p) {
   return *reinterpret_cast<const bf16x8_t*>(p);
 }
@@ -179,30 +181,31 @@ __global__ void ft_kernel(RepSet rs, int rows, int ld, int nf, const double* F, 
 // ---------------------------------------------------------------------------
 // Block = 4 wavefronts x 4 tiles of 16 rows e (256 rows) of one repetition;
 // every wave runs the whole K range (K' rounded up to 32) against C~^T hi and
-// lo, copied into LDS by the block in chunks of at most pw_mfma_chunk(NT)
-// columns (one chunk, staged once, whenever K' fits; a barrier between
-// chunks otherwise).  hi and lo products go to separate accumulators (no
+// lo, whose R live rows are copied into LDS by the block in chunks of at most
+// pw_mfma_chunk(R) columns (one chunk, staged once, whenever K' fits; a
+// barrier between chunks otherwise); lanes of the column tiles beyond R take
+// zero operands.  hi and lo products go to separate accumulators (no
 // back-to-back dependence between the two MFMAs).
+constexpr int kStageBatch = 4;  // staging loads a thread issues before its stores
 constexpr int kWTiles = 4;   // row tiles per wavefront
 constexpr int kWSteps = 2;   // K steps whose operand loads are in flight at once
 
-// columns of C~ staged per chunk: hi and lo rows [16 NT][chunk + 8] of BF16
-// within 64 KB, a multiple of 32
-constexpr int pw_mfma_chunk(int nt) { return (65536 / (2 * 16 * nt * 2) - 8) / 32 * 32; }
+// columns of C~ staged per chunk: hi and lo rows [R][chunk + 8] of BF16 within
+// 52 KB (three blocks per compute unit), a multiple of 32
+constexpr int kPwLds = 52 * 1024;
+constexpr int pw_mfma_chunk(int R) { return (kPwLds / (2 * R * 2) - 8) / 32 * 32; }
 
 template <int NT>
 __global__ __launch_bounds__(256) void pw_mfma_kernel(RepSet rs, MfmaLayout L, int kp32,
-                                                     const uint16_t* Zc, const uint16_t* Ctg,
-                                                     float* W) {
+                                                     int chunk, const uint16_t* Zc,
+                                                     const uint16_t* Ctg, float* W) {
   extern __shared__ __align__(16) unsigned char pwm_smem[];
-  constexpr int kChunk = pw_mfma_chunk(NT);
-  const int ldg = kp32 + 8;                            // row stride of the global C~ rows
-  const int chunk = kp32 < kChunk ? kp32 : kChunk;
-  const int ldt = chunk + 8;                           // row stride in LDS
-  uint16_t* Ct = reinterpret_cast<uint16_t*>(pwm_smem);  // hi part [16 NT][ldt], then lo
-  const uint16_t* Cl = Ct + 16 * NT * ldt;
-  const int rep = rs.rep0 + blockIdx.y;
   const int R = rs.R;
+  const int ldg = kp32 + 8;                            // row stride of the global C~ rows
+  const int ldt = chunk + 8;                           // row stride in LDS
+  uint16_t* Ct = reinterpret_cast<uint16_t*>(pwm_smem);  // hi part [R][ldt], then lo
+  const uint16_t* Cl = Ct + R * ldt;
+  const int rep = rs.rep0 + blockIdx.y;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int64_t n12 = (int64_t)rs.n1 * rs.n2;
   const int64_t e0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * kWTiles);
@@ -221,8 +224,8 @@ __global__ __launch_bounds__(256) void pw_mfma_kernel(RepSet rs, MfmaLayout L, i
       ah[t][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
       al[t][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
     }
-  const uint4* src = reinterpret_cast<const uint4*>(Ctg + (int64_t)rep * 2 * 16 * NT * ldg);
-  uint4* dst = reinterpret_cast<uint4*>(Ct);
+  const u32x4_t* src = reinterpret_cast<const u32x4_t*>(Ctg + (int64_t)rep * 2 * 16 * NT * ldg);
+  u32x4_t* dst = reinterpret_cast<u32x4_t*>(Ct);
   bf16x8_t af[kWSteps][kWTiles];
   for (int c0 = 0; c0 < kp32; c0 += chunk) {
     const int cw = kp32 - c0 < chunk ? kp32 - c0 : chunk;  // a multiple of 32
@@ -238,12 +241,28 @@ __global__ __launch_bounds__(256) void pw_mfma_kernel(RepSet rs, MfmaLayout L, i
         if (u < ksteps) af[u][t] = ld_bf16x8(zc[t] + 32 * u);
     if (c0 > 0) __syncthreads();  // every wave is done with the previous chunk
     {
-      // 16-byte words: rows (hi, then lo) of cw / 8 words each
-      const int wpr = cw / 8;
-      const int nrow = 2 * 16 * NT;
-      for (int q = tid; q < nrow * wpr; q += 256) {
-        const int row = q / wpr, w = q - row * wpr;
-        dst[row * (ldt / 8) + w] = src[row * (ldg / 8) + c0 / 8 + w];
+      // 16-byte words: the R live rows of hi, then of lo, cw / 8 words each;
+      // a thread issues a batch of loads before its stores
+      const int wpr = cw / 8, nw = 2 * R * wpr;
+      for (int q0 = tid; q0 < nw; q0 += kStageBatch * 256) {
+        // (loads past the end read word 0 again, so the batch has no branch)
+        u32x4_t v[kStageBatch];
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+          const int q = q0 + u * 256 < nw ? q0 + u * 256 : 0;
+          const int row = q / wpr, w = q - row * wpr;
+          const int grow = row < R ? row : 16 * NT + row - R;  // row in the global layout
+          v[u] = src[grow * (ldg / 8) + c0 / 8 + w];
+        }
+        __builtin_amdgcn_sched_barrier(0);  // keep the whole batch of loads ahead of the stores
+#pragma unroll
+        for (int u = 0; u < kStageBatch; ++u) {
+          const int q = q0 + u * 256;
+          if (q < nw) {
+            const int row = q / wpr, w = q - row * wpr;
+            dst[row * (ldt / 8) + w] = v[u];
+          }
+        }
       }
     }
     __syncthreads();
@@ -260,8 +279,13 @@ __global__ __launch_bounds__(256) void pw_mfma_kernel(RepSet rs, MfmaLayout L, i
         if (k0 + u < ksteps) {
 #pragma unroll
           for (int j = 0; j < NT; ++j) {
-            const int o = (16 * j + (lane & 15)) * ldt + 32 * (k0 + u) + 8 * kq;
-            const bf16x8_t bh = ld_bf16x8(Ct + o), bl = ld_bf16x8(Cl + o);
+            const int f = 16 * j + (lane & 15);
+            const int o = f * ldt + 32 * (k0 + u) + 8 * kq;
+            bf16x8_t bh = {}, bl = {};
+            if (f < R) {
+              bh = ld_bf16x8(Ct + o);
+              bl = ld_bf16x8(Cl + o);
+            }
 #pragma unroll
             for (int t = 0; t < kWTiles; ++t) {
               ah[t][j] = mfma16x16x32(af[u][t], bh, ah[t][j]);
@@ -337,15 +361,37 @@ __global__ __launch_bounds__(256) void p3_mfma_kernel(RepSet rs, MfmaLayout L, i
     for (int t = 0; t < kPTiles; ++t)
       if (kw_lo + u < kw_hi) af[u][t] = ld_bf16x8(zrow[t] + 32 * (kw_lo + u));
   {
+    // a thread issues a batch of loads before its stores
     const int n4 = 16 * NT * ld1 / 4;
-    const float4* src = reinterpret_cast<const float4*>(Atg + (int64_t)rep * 16 * NT * ld1);
-    float4* dst = reinterpret_cast<float4*>(At);
-    for (int q = tid; q < n4; q += 256) dst[q] = src[q];
+    const u32x4_t* src = reinterpret_cast<const u32x4_t*>(Atg + (int64_t)rep * 16 * NT * ld1);
+    u32x4_t* dst = reinterpret_cast<u32x4_t*>(At);
+    for (int q0 = tid; q0 < n4; q0 += kStageBatch * 256) {
+      // (loads past the end read word 0 again, so the batch has no branch)
+      u32x4_t v[kStageBatch];
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u) v[u] = src[q0 + u * 256 < n4 ? q0 + u * 256 : 0];
+      __builtin_amdgcn_sched_barrier(0);  // keep the whole batch of loads ahead of the stores
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u)
+        if (q0 + u * 256 < n4) dst[q0 + u * 256] = v[u];
+    }
     const int ldb = (n2 + 3) / 4 * 4;
     const float* bsrc = Btg + (int64_t)rep * 16 * NT * ldb;
-    for (int q = tid; q < 16 * NT * nbp; q += 256) {
-      const int f = q / nbp, bb = q % nbp;
-      Bt[q] = bb < nb ? bsrc[(int64_t)f * ldb + b_lo + bb] : 0.0f;
+    const int nbt = 16 * NT * nbp;
+    for (int q0 = tid; q0 < nbt; q0 += kStageBatch * 256) {
+      float v[kStageBatch];
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u) {
+        const int q = q0 + u * 256;
+        const int f = q / nbp, bb = q % nbp;
+        const bool in = q < nbt && bb < nb;
+        const float x = bsrc[in ? (int64_t)f * ldb + b_lo + bb : 0];
+        v[u] = in ? x : 0.0f;
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int u = 0; u < kStageBatch; ++u)
+        if (q0 + u * 256 < nbt) Bt[q0 + u * 256] = v[u];
     }
   }
   __syncthreads();
@@ -544,13 +590,13 @@ hipError_t launch_pw_mfma(const RepSet& rs, const MfmaLayout& L, const uint16_t*
   }
   const int64_t rows_per_block = 4 * 16 * kWTiles;
   dim3 grid((unsigned)((n12 + rows_per_block - 1) / rows_per_block), (unsigned)rs.nrep);
-  const int chunk = kp32 < pw_mfma_chunk(nt) ? kp32 : pw_mfma_chunk(nt);
-  const size_t sh = (size_t)2 * nf * (chunk + 8) * 2;
+  const int chunk = kp32 < pw_mfma_chunk(rs.R) ? kp32 : pw_mfma_chunk(rs.R);
+  const size_t sh = (size_t)2 * rs.R * (chunk + 8) * 2;
   if (sh > 65536) return hipErrorInvalidValue;
   if (nt == 1)
-    timed_launch(pw_mfma_kernel<1>, grid, dim3(256), sh, s, rs, L, kp32, Zc, Ct, W);
+    timed_launch(pw_mfma_kernel<1>, grid, dim3(256), sh, s, rs, L, kp32, chunk, Zc, Ct, W);
   else
-    timed_launch(pw_mfma_kernel<2>, grid, dim3(256), sh, s, rs, L, kp32, Zc, Ct, W);
+    timed_launch(pw_mfma_kernel<2>, grid, dim3(256), sh, s, rs, L, kp32, chunk, Zc, Ct, W);
   return hipGetLastError();
 }
 
