@@ -12,17 +12,19 @@
 //
 // Both passes run v_mfma_f32_16x16x32_bf16 with FP32 accumulation.  The
 // second operand (C~ for pass W, the Khatri-Rao rows A~(a, f) B~(b, f) for
-// mode 3) is formed in FP32 and split into two BF16 parts, hi = bf16(x) and
-// lo = bf16(x - hi), each contracted with the summary (two MFMAs into one
-// accumulator): the factor side then carries about 16 bits, and only the data
-// are BF16.  Rounding the factor operand itself to BF16 makes the MTTKRP
-// inconsistent with the FP64 Gram matrices of the normal equations, and with
-// the nearly collinear factors of non-negative data that inconsistency is
-// amplified by the conditioning of the solve (the fit of an update drops by
-// several 1e-3); the split removes it at the price of MFMA issue slots the
-// memory-bound passes have to spare.  Modes 1 and 2 then contract W (FP32) as
-// in the other precisions; Gram matrices, solves and normalisation stay in
-// FP64.
+// mode 3) is formed in FP32 and split into BF16 parts, each contracted with
+// the summary into one accumulator: three parts for C~ (hi = bf16(x), mid =
+// bf16(x - hi), lo = bf16(x - hi - mid): about 24 bits, as in FP32), two for
+// the Khatri-Rao rows (hi and lo: about 16 bits; they are formed per lane in
+// every K step, where a third part would cost VALU work the pass cannot
+// hide).  Only the data are BF16.  Rounding the factor operand itself to
+// BF16 makes the MTTKRP inconsistent with the FP64 Gram matrices of the
+// normal equations, and with the nearly collinear factors of non-negative
+// data that inconsistency is amplified by the conditioning of the solve (the
+// fit of an update drops by several 1e-3).  The split costs MFMA issue slots
+// the memory-bound passes have to spare.  Modes 1 and 2 then contract W
+// (FP32) as in the other precisions; Gram matrices, solves and normalisation
+// stay in FP64.
 //
 // Lane layout of the 16 x 16 x 32 operation (wave of 64): operand A row
 // i = lane % 16 holds 8 consecutive K entries of group lane / 16; operand B
@@ -138,7 +140,7 @@ __global__ __launch_bounds__(256) void relayout_bf16_kernel(const uint16_t* Z, R
 // ---------------------------------------------------------------------------
 // operands staged once per launch
 // ---------------------------------------------------------------------------
-// C~^T as BF16 hi and lo parts: Ct[rep][part][f][kp32 + 8] (rows f >= R and
+// C~^T as three BF16 parts: Ct[rep][part][f][kp32 + 8] (rows f >= R and
 // columns c >= K' zero)
 __global__ void ct_split_kernel(RepSet rs, int kp32, int nf, const double* Cf,
                                 const double* invlamC, uint16_t* Ct) {
@@ -146,8 +148,9 @@ __global__ void ct_split_kernel(RepSet rs, int kp32, int nf, const double* Cf,
   const int R = rs.R, ldt = kp32 + 8;
   const int64_t n = (int64_t)nf * ldt;
   const double* C = Cf + rep * rs.sC;
-  uint16_t* hi = Ct + (int64_t)rep * 2 * n;
-  uint16_t* lo = hi + n;
+  uint16_t* hi = Ct + (int64_t)rep * 3 * n;
+  uint16_t* mid = hi + n;
+  uint16_t* lo = mid + n;
   for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n;
        q += (int64_t)gridDim.x * blockDim.x) {
     const int f = (int)(q / ldt), c = (int)(q % ldt);
@@ -155,8 +158,11 @@ __global__ void ct_split_kernel(RepSet rs, int kp32, int nf, const double* Cf,
     if (f < R && c < rs.n3)
       x = (float)(C[(int64_t)c * R + f] * (invlamC ? invlamC[rep * 3 * R + f] : 1.0));
     const uint16_t h = f32_to_bf16_rne(x);
+    const float r1 = x - bf16_to_f32(h);  // exact
+    const uint16_t m = f32_to_bf16_rne(r1);
     hi[q] = h;
-    lo[q] = f32_to_bf16_rne(x - bf16_to_f32(h));
+    mid[q] = m;
+    lo[q] = f32_to_bf16_rne(r1 - bf16_to_f32(m));
   }
 }
 
@@ -180,20 +186,22 @@ __global__ void ft_kernel(RepSet rs, int rows, int ld, int nf, const double* F, 
 // pass W on the matrix cores
 // ---------------------------------------------------------------------------
 // Block = 4 wavefronts x 4 tiles of 16 rows e (256 rows) of one repetition;
-// every wave runs the whole K range (K' rounded up to 32) against C~^T hi and
-// lo, whose R live rows are copied into LDS by the block in chunks of at most
-// pw_mfma_chunk(R) columns (one chunk, staged once, whenever K' fits; a
-// barrier between chunks otherwise); lanes of the column tiles beyond R take
-// zero operands.  hi and lo products go to separate accumulators (no
-// back-to-back dependence between the two MFMAs).
+// every wave runs the whole K range (K' rounded up to 32) against the three
+// parts of C~^T, whose R live rows are copied into LDS by the block in chunks
+// of at most pw_mfma_chunk(R) columns (one chunk, staged once, whenever K'
+// fits; a barrier between chunks otherwise); lanes of the column tiles
+// beyond R take zero operands.  One accumulator per tile takes the three
+// products: the four tiles' hi products go first, then mid, then lo, so each
+// accumulation has three independent MFMAs between it and the one it
+// depends on.
 constexpr int kStageBatch = 4;  // staging loads a thread issues before its stores
 constexpr int kWTiles = 4;   // row tiles per wavefront
 constexpr int kWSteps = 2;   // K steps whose operand loads are in flight at once
 
-// columns of C~ staged per chunk: hi and lo rows [R][chunk + 8] of BF16 within
-// 52 KB (three blocks per compute unit), a multiple of 32
+// columns of C~ staged per chunk: three parts' rows [R][chunk + 8] of BF16
+// within 52 KB (three blocks per compute unit), a multiple of 32
 constexpr int kPwLds = 52 * 1024;
-constexpr int pw_mfma_chunk(int R) { return (kPwLds / (2 * R * 2) - 8) / 32 * 32; }
+constexpr int pw_mfma_chunk(int R) { return (kPwLds / (3 * R * 2) - 8) / 32 * 32; }
 
 template <int NT>
 __global__ __launch_bounds__(256) void pw_mfma_kernel(RepSet rs, MfmaLayout L, int kp32,
@@ -203,10 +211,12 @@ __global__ __launch_bounds__(256) void pw_mfma_kernel(RepSet rs, MfmaLayout L, i
   const int R = rs.R;
   const int ldg = kp32 + 8;                            // row stride of the global C~ rows
   const int ldt = chunk + 8;                           // row stride in LDS
-  uint16_t* Ct = reinterpret_cast<uint16_t*>(pwm_smem);  // hi part [R][ldt], then lo
-  const uint16_t* Cl = Ct + R * ldt;
+  uint16_t* Ct = reinterpret_cast<uint16_t*>(pwm_smem);  // hi part [R][ldt], then mid, lo
+  const uint16_t* Cm = Ct + R * ldt;
+  const uint16_t* Cl = Cm + R * ldt;
   const int rep = rs.rep0 + blockIdx.y;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform (scalar)
   const int64_t n12 = (int64_t)rs.n1 * rs.n2;
   const int64_t e0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * kWTiles);
   const int kq = lane >> 4;
@@ -216,15 +226,12 @@ __global__ __launch_bounds__(256) void pw_mfma_kernel(RepSet rs, MfmaLayout L, i
     const int64_t e = e0 + 16 * t + (lane & 15);
     zrow[t] = Zc + rep * L.sZc + (e < n12 ? e : n12 - 1) * L.ldc + 8 * kq;
   }
-  f32x4_t ah[kWTiles][NT], al[kWTiles][NT];
+  f32x4_t acc[kWTiles][NT];
 #pragma unroll
   for (int t = 0; t < kWTiles; ++t)
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
-      ah[t][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-      al[t][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-    }
-  const u32x4_t* src = reinterpret_cast<const u32x4_t*>(Ctg + (int64_t)rep * 2 * 16 * NT * ldg);
+    for (int j = 0; j < NT; ++j) acc[t][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  const u32x4_t* src = reinterpret_cast<const u32x4_t*>(Ctg + (int64_t)rep * 3 * 16 * NT * ldg);
   u32x4_t* dst = reinterpret_cast<u32x4_t*>(Ct);
   bf16x8_t af[kWSteps][kWTiles];
   for (int c0 = 0; c0 < kp32; c0 += chunk) {
@@ -241,9 +248,9 @@ __global__ __launch_bounds__(256) void pw_mfma_kernel(RepSet rs, MfmaLayout L, i
         if (u < ksteps) af[u][t] = ld_bf16x8(zc[t] + 32 * u);
     if (c0 > 0) __syncthreads();  // every wave is done with the previous chunk
     {
-      // 16-byte words: the R live rows of hi, then of lo, cw / 8 words each;
-      // a thread issues a batch of loads before its stores
-      const int wpr = cw / 8, nw = 2 * R * wpr;
+      // 16-byte words: the R live rows of hi, then of mid and lo, cw / 8 words
+      // each; a thread issues a batch of loads before its stores
+      const int wpr = cw / 8, nw = 3 * R * wpr;
       for (int q0 = tid; q0 < nw; q0 += kStageBatch * 256) {
         // (loads past the end read word 0 again, so the batch has no branch)
         u32x4_t v[kStageBatch];
@@ -251,7 +258,7 @@ __global__ __launch_bounds__(256) void pw_mfma_kernel(RepSet rs, MfmaLayout L, i
         for (int u = 0; u < kStageBatch; ++u) {
           const int q = q0 + u * 256 < nw ? q0 + u * 256 : 0;
           const int row = q / wpr, w = q - row * wpr;
-          const int grow = row < R ? row : 16 * NT + row - R;  // row in the global layout
+          const int grow = (row / R) * 16 * NT + row % R;  // row in the global layout
           v[u] = src[grow * (ldg / 8) + c0 / 8 + w];
         }
         __builtin_amdgcn_sched_barrier(0);  // keep the whole batch of loads ahead of the stores
@@ -281,16 +288,18 @@ __global__ __launch_bounds__(256) void pw_mfma_kernel(RepSet rs, MfmaLayout L, i
           for (int j = 0; j < NT; ++j) {
             const int f = 16 * j + (lane & 15);
             const int o = f * ldt + 32 * (k0 + u) + 8 * kq;
-            bf16x8_t bh = {}, bl = {};
+            bf16x8_t bh = {}, bm = {}, bl = {};
             if (f < R) {
               bh = ld_bf16x8(Ct + o);
+              bm = ld_bf16x8(Cm + o);
               bl = ld_bf16x8(Cl + o);
             }
 #pragma unroll
-            for (int t = 0; t < kWTiles; ++t) {
-              ah[t][j] = mfma16x16x32(af[u][t], bh, ah[t][j]);
-              al[t][j] = mfma16x16x32(af[u][t], bl, al[t][j]);
-            }
+            for (int t = 0; t < kWTiles; ++t) acc[t][j] = mfma16x16x32(af[u][t], bh, acc[t][j]);
+#pragma unroll
+            for (int t = 0; t < kWTiles; ++t) acc[t][j] = mfma16x16x32(af[u][t], bm, acc[t][j]);
+#pragma unroll
+            for (int t = 0; t < kWTiles; ++t) acc[t][j] = mfma16x16x32(af[u][t], bl, acc[t][j]);
           }
         }
       }
@@ -305,7 +314,7 @@ __global__ __launch_bounds__(256) void pw_mfma_kernel(RepSet rs, MfmaLayout L, i
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t e = e0 + 16 * t + 4 * kq + v;
-        if (e < n12 && f < R) Wr[e * R + f] = ah[t][j][v] + al[t][j][v];
+        if (e < n12 && f < R) Wr[e * R + f] = acc[t][j][v];
       }
     }
 }
@@ -566,7 +575,7 @@ hipError_t launch_relayout_bf16(const uint16_t* Z, const RepSet& rs, const MfmaL
 
 size_t mfma_operand_floats(const MfmaLayout& L, int n2, int R) {
   const size_t nf = 16 * ntiles(R);
-  const size_t ct = nf * ((size_t)L.ldc + 8);              // hi and lo BF16 rows
+  const size_t ct = nf * ((size_t)L.ldc + 8) * 3 / 2;      // three parts' BF16 rows
   const size_t ab = nf * ((size_t)L.ld1 + (n2 + 3) / 4 * 4);  // A~^T and B~^T in FP32
   return ct > ab ? ct : ab;
 }
@@ -591,7 +600,7 @@ hipError_t launch_pw_mfma(const RepSet& rs, const MfmaLayout& L, const uint16_t*
   const int64_t rows_per_block = 4 * 16 * kWTiles;
   dim3 grid((unsigned)((n12 + rows_per_block - 1) / rows_per_block), (unsigned)rs.nrep);
   const int chunk = kp32 < pw_mfma_chunk(rs.R) ? kp32 : pw_mfma_chunk(rs.R);
-  const size_t sh = (size_t)2 * rs.R * (chunk + 8) * 2;
+  const size_t sh = (size_t)3 * rs.R * (chunk + 8) * 2;
   if (sh > 65536) return hipErrorInvalidValue;
   if (nt == 1)
     timed_launch(pw_mfma_kernel<1>, grid, dim3(256), sh, s, rs, L, kp32, chunk, Zc, Ct, W);
