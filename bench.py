@@ -609,7 +609,7 @@ def bench_nd(args, sbt, torch, synth, log):
     def run(prec, lr):
         cfg = sbt.make_config(R, w["r"], w["iters"], 1, w["seed"], precision=prec,
                               k_capacity=K, max_batch=Kn)
-        Xp = Xd if prec == sbt.SBT_P_F32 else Xd.double()
+        Xp = Xd.double() if prec == sbt.SBT_P_F64 else Xd  # BF16 summaries: FP32 store
 
         def fresh():
             return sbt.TensorN.init_dense_nd(cfg, Xp[:K0 * slice_n], dims + (K0,), w["s"],
@@ -624,10 +624,13 @@ def bench_nd(args, sbt, torch, synth, log):
     log(f"# nd fp32: {b['slices_per_s']:.1f} slices/s, fit {b['fit']:.6f}")
     f64 = run(sbt.SBT_P_F64, max(1, min(args.latency_runs, 2)))
     log(f"# nd fp64: {f64['slices_per_s']:.1f} slices/s, fit {f64['fit']:.6f}")
+    bf = run(sbt.SBT_P_BF16, max(1, min(args.latency_runs, 2)))
+    log(f"# nd bf16 summaries: {bf['slices_per_s']:.1f} slices/s, fit {bf['fit']:.6f}")
     cfg = {"workload": w["desc"], "dims": list(dims), "K0": K0, "batch": Kn, "rank": R,
            "s": w["s"], "r": w["r"], "als_iters": w["iters"]}
     line = {
-        "metric": "updated slices/sec (p50/p99 update latency, the FP64 path alongside)",
+        "metric": "updated slices/sec (p50/p99 update latency, the FP64 and BF16-summary "
+                  "paths alongside)",
         "value": round(b["slices_per_s"], 2), "unit": "slices/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(b["ms_per_step"], 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -659,6 +662,8 @@ def bench_nd(args, sbt, torch, synth, log):
     line["cpu_baseline"] = None if args.no_cpu_baseline else \
         cpu_baseline_nd(w, X, model, max(1, min(3 * args.cpu_updates, steps)))
     line["fp64"] = path_summary(f64)
+    line["bf16"] = path_summary(bf)
+    line["bf16"]["kernels"] = kernels_table(bf["profile"])
     line["kernels"] = kernels_table(b["profile"])
     return line
 

@@ -473,8 +473,10 @@ void sbt_server_destroy(sbt_server* s);
  * factor's anchor rows; new rows averaged over the valid repetitions.  At
  * N = 3 it computes what the third-order update computes (plain schedule).
  *
- * Supported: cfg->format SBT_DENSE, cfg->precision SBT_P_F64 or SBT_P_F32
- * (store, summaries and MTTKRP in that type; everything else FP64),
+ * Supported: cfg->format SBT_DENSE; cfg->precision SBT_P_F64 or SBT_P_F32
+ * (store, summaries and MTTKRP in that type; everything else FP64) or
+ * SBT_P_BF16 (FP32 store, summaries rounded to BF16 to nearest even, MTTKRP
+ * on the vector units with FP32 accumulation; everything else FP64);
  * getrank_runs 0, persist_summaries 0.  cfg->schedule is not read and
  * cfg->sample_factor is replaced by the per-mode factors below (its entries
  * must still be >= 1).

@@ -162,8 +162,12 @@ def match(anchors, samples):
 # ----------------------------------------------------------------------------
 
 class Config:
+    """summary_bf16: the summaries are rounded to bfloat16 (nearest, ties to
+    even) before their CP-ALS, as a path that stores them in BF16 does; every
+    other step stays in FP64."""
+
     def __init__(self, rank, reps, als_iters, sample_factor, seed, order, tensor_id=0,
-                 init_iters=100, k_capacity=None):
+                 init_iters=100, k_capacity=None, summary_bf16=False):
         self.rank = int(rank)
         self.reps = int(reps)
         self.als_iters = int(als_iters)
@@ -175,6 +179,7 @@ class Config:
         self.tensor_id = int(tensor_id)
         self.init_iters = int(init_iters)
         self.k_capacity = k_capacity
+        self.summary_bf16 = bool(summary_bf16)
 
 
 class OracleTensorN:
@@ -240,6 +245,8 @@ class OracleTensorN:
             Ks = Ss[-1]
             Kp = np.concatenate([Ks, Kold + np.arange(Kn)])
             Z = np.asarray(XY[np.ix_(*(Ss[:-1] + [Kp]))], dtype=np.float64)
+            if cfg.summary_bf16:
+                Z = cp.round_bf16(Z)
             dims_s = list(Z.shape)
             U0 = [None] + [cp.als_init_factor(cfg.seed, cfg.tensor_id, rng.TAG_ALSINIT, m + 1,
                                               rho, self.t, dims_s[m], R) for m in range(1, N)]

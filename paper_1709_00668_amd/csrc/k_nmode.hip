@@ -61,15 +61,21 @@ __global__ void als_init_nd_kernel(NdFactors F, int N, int R, int rep0, uint64_t
   }
 }
 
+// summary element from a store element: the same type, or BF16 (nearest even)
+// from FP32
+__device__ inline double to_summary(double x, double*) { return x; }
+__device__ inline float to_summary(float x, float*) { return x; }
+__device__ inline uint16_t to_summary(float x, uint16_t*) { return f32_to_bf16_rne(x); }
+
 // one thread per summary element, the first summary index fastest
-template <typename T>
+template <typename TIn, typename TZ>
 __global__ __launch_bounds__(256) void gather_nd_kernel(GatherNd g) {
   const int rep = g.rep0 + blockIdx.y;
   int64_t total = 1;
   for (int m = 0; m < g.N; ++m) total *= g.n[m];
   const int32_t* S = g.idx + rep * g.idx_stride;
-  const T* X = (const T*)g.X;
-  T* Z = (T*)g.Z + rep * g.sZ;
+  const TIn* X = (const TIn*)g.X;
+  TZ* Z = (TZ*)g.Z + rep * g.sZ;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     int64_t rem = e, src = 0, stride = 1;
@@ -82,7 +88,7 @@ __global__ __launch_bounds__(256) void gather_nd_kernel(GatherNd g) {
     const int c = (int)rem;
     const int64_t kk = c < g.n3old ? (int64_t)S[g.off[g.N - 1] + c] : g.Kold + (c - g.n3old);
     src += kk * stride;
-    Z[e] = X[src];
+    Z[e] = to_summary(X[src], Z);
   }
 }
 
@@ -295,32 +301,47 @@ __global__ __launch_bounds__(256) void sort_nd_kernel(NdFactors F, int N, int R,
 
 // W(e, f) = sum_q Z(e, q) C(q, f) on a three-way view (e = a + n1 b, q = c)
 // whose rows are few and whose contraction is long, as the leading-mode
-// views of an order-N summary are.  A block takes 64 consecutive rows (one
-// per lane) and one of S ranges of q; its four wavefronts split the range
-// again, each with kP1sLoads summary loads in flight, over C rows staged in
-// LDS.  The wavefronts' rows add up in LDS in wavefront order; with S > 1
-// each range writes a partial W that a second kernel sums in range order.
+// views of an order-N summary are.  A block takes 64 V consecutive rows (V
+// per lane: BF16 summaries take two, so that a lane reads 4 bytes per load)
+// and one of S ranges of q; its four wavefronts split the range again, each
+// with kP1sLoads summary loads in flight, over C rows staged in LDS.  The
+// wavefronts' rows add up in LDS in wavefront order; with S > 1 each range
+// writes a partial W that a second kernel sums in range order.
 constexpr int kP1sLoads = 4;
 constexpr int kP1sMaxRows = 128;  // C rows one block stages
 
 template <typename TZ> struct AccNd { using type = float; };
 template <> struct AccNd<double> { using type = double; };
 
-template <typename TZ, int RP>
+// V consecutive summary elements in the accumulation type (BF16 summaries
+// widen to FP32; two BF16 elements come from one 4-byte load)
+template <int V> __device__ inline void acc_of(const double* p, double (&z)[V]) { z[0] = *p; }
+template <int V> __device__ inline void acc_of(const float* p, float (&z)[V]) { z[0] = *p; }
+template <int V> __device__ inline void acc_of(const uint16_t* p, float (&z)[V]) {
+  if constexpr (V == 2) {
+    const uint32_t w = *reinterpret_cast<const uint32_t*>(p);
+    z[0] = bf16_to_f32((uint16_t)(w & 0xFFFFu));
+    z[1] = bf16_to_f32((uint16_t)(w >> 16));
+  } else {
+    z[0] = bf16_to_f32(*p);
+  }
+}
+
+template <typename TZ, int RP, int V>
 __global__ __launch_bounds__(256) void p1s_kernel(RepSet rs, const TZ* Z, const double* Cf, int S,
                                                  typename AccNd<TZ>::type* Wp, int64_t sWp,
                                                  NdFactors F, int c0, int N) {
   using TA = typename AccNd<TZ>::type;
   __shared__ TA Cs[kP1sMaxRows][RP];
-  __shared__ TA red[64][RP + 1];
+  __shared__ TA red[64 * V][RP + 1];
   const int rep = rs.rep0 + blockIdx.z, sp = blockIdx.y;
   const int R = rs.R, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t n12 = (int64_t)rs.n1 * rs.n2;
   const int Q = rs.n3;
   const int qs = (int)((int64_t)sp * Q / S), qe = (int)((int64_t)(sp + 1) * Q / S);
   const int L = qe - qs;  // <= kP1sMaxRows (host-chosen S)
-  const int64_t e = (int64_t)blockIdx.x * 64 + lane;
-  const bool ok = e < n12;
+  const int64_t e = ((int64_t)blockIdx.x * 64 + lane) * V;  // first of the lane's V rows
+  const bool ok = e < n12;  // (V = 2 only when n12 is even)
   if (c0 < 0) {
     const double* C = Cf + rep * rs.sC + (int64_t)qs * R;
     for (int q = threadIdx.x; q < L * RP; q += 256) {
@@ -348,35 +369,63 @@ __global__ __launch_bounds__(256) void p1s_kernel(RepSet rs, const TZ* Z, const 
   __syncthreads();
   const int w0 = (wave * L) / 4, w1 = ((wave + 1) * L) / 4;
   const TZ* zp = Z + rep * rs.sZ + (ok ? e : 0) + n12 * qs;
-  TA acc[RP];
+  TA acc[V][RP];
 #pragma unroll
-  for (int f = 0; f < RP; ++f) acc[f] = 0;
+  for (int v = 0; v < V; ++v)
+#pragma unroll
+    for (int f = 0; f < RP; ++f) acc[v][f] = 0;
   int q = w0;
   for (; q + kP1sLoads <= w1; q += kP1sLoads) {
-    TA z[kP1sLoads];
+    TA z[kP1sLoads][V];
 #pragma unroll
-    for (int u = 0; u < kP1sLoads; ++u) z[u] = ok ? (TA)zp[n12 * (q + u)] : (TA)0;
+    for (int u = 0; u < kP1sLoads; ++u) {
+      if (ok) {
+        acc_of<V>(zp + n12 * (q + u), z[u]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) z[u][v] = 0;
+      }
+    }
 #pragma unroll
     for (int u = 0; u < kP1sLoads; ++u)
 #pragma unroll
-      for (int f = 0; f < RP; ++f) acc[f] += z[u] * Cs[q + u][f];
+      for (int f = 0; f < RP; ++f) {
+        const TA c = Cs[q + u][f];
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[v][f] += z[u][v] * c;
+      }
   }
   for (; q < w1; ++q) {
-    const TA z = ok ? (TA)zp[n12 * q] : (TA)0;
+    TA z[V];
+    if (ok) {
+      acc_of<V>(zp + n12 * q, z);
+    } else {
 #pragma unroll
-    for (int f = 0; f < RP; ++f) acc[f] += z * Cs[q][f];
+      for (int v = 0; v < V; ++v) z[v] = 0;
+    }
+#pragma unroll
+    for (int f = 0; f < RP; ++f) {
+      const TA c = Cs[q][f];
+#pragma unroll
+      for (int v = 0; v < V; ++v) acc[v][f] += z[v] * c;
+    }
   }
   // the four wavefronts' rows, added in wavefront order
   for (int w = 0; w < 4; ++w) {
     if (wave == w) {
 #pragma unroll
-      for (int f = 0; f < RP; ++f) red[lane][f] = w == 0 ? acc[f] : red[lane][f] + acc[f];
+      for (int v = 0; v < V; ++v)
+#pragma unroll
+        for (int f = 0; f < RP; ++f)
+          red[lane * V + v][f] = w == 0 ? acc[v][f] : red[lane * V + v][f] + acc[v][f];
     }
     __syncthreads();
   }
   if (ok) {
     TA* out = Wp + rep * sWp + (int64_t)sp * R * n12;
-    for (int f = 0; f < R; ++f) out[f * n12 + e] = red[lane][f];
+    for (int f = 0; f < R; ++f)
+#pragma unroll
+      for (int v = 0; v < V; ++v) out[f * n12 + e + v] = red[lane * V + v][f];
   }
 }
 
@@ -425,16 +474,25 @@ hipError_t launch_p1s(int prec, const RepSet& rs, const void* Z, const double* C
   void* out = S == 1 ? W : Wp;
   const int64_t so = S == 1 ? rs.sW : sWp;
   if (S > 1 && sWp < (int64_t)S * n12 * rs.R) return hipErrorInvalidValue;
-  dim3 grid((unsigned)((n12 + 63) / 64), (unsigned)S, (unsigned)rs.nrep);
+  // BF16 summaries: two rows per lane when every lane's pair is 4-byte aligned
+  const bool pair = prec != kF64 && prec != kF32 && n12 % 2 == 0 && rs.sZ % 2 == 0;
+  dim3 grid((unsigned)((n12 + (pair ? 127 : 63)) / (pair ? 128 : 64)), (unsigned)S,
+            (unsigned)rs.nrep);
   switch ((rs.R + 3) / 4 * 4) {
 #define SBT_P1S(RPV)                                                                          \
   case RPV:                                                                                   \
     if (prec == kF64)                                                                         \
-      timed_launch(p1s_kernel<double, RPV>, grid, dim3(256), 0, s, rs, (const double*)Z, Cf, \
-                   S, (double*)out, so, F, kc0, N);                                           \
-    else                                                                                      \
-      timed_launch(p1s_kernel<float, RPV>, grid, dim3(256), 0, s, rs, (const float*)Z, Cf,   \
+      timed_launch(p1s_kernel<double, RPV, 1>, grid, dim3(256), 0, s, rs, (const double*)Z,  \
+                   Cf, S, (double*)out, so, F, kc0, N);                                       \
+    else if (prec == kF32)                                                                    \
+      timed_launch(p1s_kernel<float, RPV, 1>, grid, dim3(256), 0, s, rs, (const float*)Z, Cf,\
                    S, (float*)out, so, F, kc0, N);                                            \
+    else if (pair)                                                                            \
+      timed_launch(p1s_kernel<uint16_t, RPV, 2>, grid, dim3(256), 0, s, rs,                   \
+                   (const uint16_t*)Z, Cf, S, (float*)out, so, F, kc0, N);                    \
+    else                                                                                      \
+      timed_launch(p1s_kernel<uint16_t, RPV, 1>, grid, dim3(256), 0, s, rs,                   \
+                   (const uint16_t*)Z, Cf, S, (float*)out, so, F, kc0, N);                    \
     break;
     SBT_P1S(4) SBT_P1S(8) SBT_P1S(12) SBT_P1S(16) SBT_P1S(20) SBT_P1S(24) SBT_P1S(28)
     SBT_P1S(32)
@@ -487,10 +545,13 @@ hipError_t launch_gather_nd(int prec, const GatherNd& g, hipStream_t s) {
   for (int m = 0; m < g.N; ++m) total *= g.n[m];
   if (total > g.sZ && g.nrep > 1) return hipErrorInvalidValue;
   dim3 grid((unsigned)grid_blocks(total, 8192), (unsigned)g.nrep);
+  // (a BF16 summary is gathered from an FP32 store)
   if (prec == kF64)
-    timed_launch(gather_nd_kernel<double>, grid, dim3(256), 0, s, g);
+    timed_launch(gather_nd_kernel<double, double>, grid, dim3(256), 0, s, g);
+  else if (prec == kF32)
+    timed_launch(gather_nd_kernel<float, float>, grid, dim3(256), 0, s, g);
   else
-    timed_launch(gather_nd_kernel<float>, grid, dim3(256), 0, s, g);
+    timed_launch(gather_nd_kernel<float, uint16_t>, grid, dim3(256), 0, s, g);
   return hipGetLastError();
 }
 

@@ -3,7 +3,9 @@
 Bar: sampled indices and matchings bit-exact; FP64 path within 1e-8 of the
 oracle on every per-repetition intermediate and on the model after each
 batch; FP32 path (FP32 store and MTTKRP, FP64 everything else) within 1e-3 of
-the oracle's fit, the same relative bound as the third-order FP32 path.
+the oracle's fit, the same relative bound as the third-order FP32 path; BF16
+path (summaries rounded to BF16, FP32 accumulation) within 1e-3 of the
+oracle that rounds its summaries the same way, factor entries and fit.
 """
 
 import numpy as np
@@ -24,8 +26,9 @@ def _torch():
 
 
 def run_pair(lib, dims, Kn, R, reps, iters, s, seed, prec, batches=1, init="model", noise=0.02,
-             zero=None):
-    """The oracle and the GPU side by side; returns (oracle, gpu, debug per batch)."""
+             zero=None, oracle_bf16=False):
+    """The oracle and the GPU side by side; returns (oracle, gpu, debug per batch).
+    oracle_bf16: the oracle rounds its summaries to bfloat16 as the BF16 path does."""
     torch = _torch()
     dtype = np.float64 if prec == lib.SBT_P_F64 else np.float32
     N = len(dims)
@@ -34,7 +37,7 @@ def run_pair(lib, dims, Kn, R, reps, iters, s, seed, prec, batches=1, init="mode
     gen = synth.DenseCPN(tuple(dims[:-1]) + (Kall,), R, seed=seed, noise=noise, dtype=dtype)
     X = gen.slices(0, Kall)
     cfg_o = nmode.Config(rank=R, reps=reps, als_iters=iters, sample_factor=s, seed=seed, order=N,
-                         k_capacity=Kall, init_iters=40)
+                         k_capacity=Kall, init_iters=40, summary_bf16=oracle_bf16)
     if init == "model":
         Us, lam = gen.true_model_prefix(K0)
         if zero is not None:
@@ -181,6 +184,31 @@ def test_order4_fp32_fit_matches_oracle(lib):
         assert_close(Us[m], ora.U[m], 1e-3, 1e-3, f"factor {m}")
 
 
+@pytest.mark.parametrize("dims,Kn,R,s,seed", [((24, 20, 18, 30), 6, 4, (2, 2, 3, 2), 19),
+                                              ((10, 9, 8, 7, 12), 3, 3, (2, 1, 2, 2, 2), 23)])
+def test_bf16_summaries_match_the_bf16_oracle(lib, dims, Kn, R, s, seed):
+    # orders 4 and 5, two batches: samples and matchings bit-exact; every
+    # repetition's summary factors, the model and the fit within 1e-3 of the
+    # oracle with BF16 summaries; the fit also within 1e-3 of the FP64 oracle
+    N, reps = len(dims), 3
+    ora, gpu, ds = run_pair(lib, dims, Kn, R, reps, 20, s, seed, lib.SBT_P_BF16, batches=2,
+                            oracle_bf16=True)
+    check_samples(lib, gpu, ds[-1], N, reps)
+    for rho in range(reps):
+        r = ds[-1]["reps"][rho]
+        np.testing.assert_array_equal(gpu.last_rep_nd(rho, lib.SBT_ND_REP_PI), r["pi"])
+        for m in range(N):
+            assert_close(gpu.last_rep_nd(rho, lib.SBT_ND_REP_UP, m), r["Up"][m], 1e-3, 1e-3,
+                         f"rep {rho} U'_{m}")
+    Us, _ = gpu.get_factors_nd()
+    for m in range(N):
+        assert_close(Us[m], ora.U[m], 1e-3, 1e-3, f"factor {m}")
+    f_gpu, f_ora = gpu.fit(), ora.fit()
+    assert abs(f_gpu - f_ora) <= 1e-4 * max(1.0, abs(f_ora))
+    ora64, _, _ = run_pair(lib, dims, Kn, R, reps, 20, s, seed, lib.SBT_P_F64, batches=2)
+    assert abs(f_gpu - ora64.fit()) <= 1e-3 * max(1.0, abs(ora64.fit()))
+
+
 def test_non_finite_batch_is_refused_without_change(lib):
     torch = _torch()
     gen = synth.DenseCPN((6, 5, 4, 10), 2, seed=1, noise=0.1, dtype=np.float64)
@@ -277,9 +305,6 @@ def test_order_and_arguments_refused(lib):
                     ((4, 4, 2), (1, 0, 1))):
         with pytest.raises(lib.SbtError):
             lib.TensorN.init_dense_nd(cfg, x, dims, s)
-    bf = lib.make_config(2, 2, 5, 1, 1, precision=lib.SBT_P_BF16, k_capacity=8, max_batch=2)
-    with pytest.raises(lib.SbtError):
-        lib.TensorN.init_dense_nd(bf, x, (4, 4, 2), (1, 1, 1))
     full = lib.make_config(2, 2, 5, 1, 1, precision=lib.SBT_P_F64, k_capacity=2, max_batch=2)
     with pytest.raises(lib.SbtError):  # no room for a batch
         lib.TensorN.init_dense_nd(full, x, (4, 4, 2), (1, 1, 1))

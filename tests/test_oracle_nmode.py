@@ -94,14 +94,16 @@ def test_cp_als_recovers_exact_low_rank_order4():
     np.testing.assert_allclose(np.sort(o.lam), np.sort(lt), rtol=1e-6)
 
 
-def test_order3_update_is_the_third_order_update():
+@pytest.mark.parametrize("bf16", [False, True])
+def test_order3_update_is_the_third_order_update(bf16):
     # the same configuration through both oracles: identical up to rounding
+    # (also with the summaries rounded to bfloat16)
     g = synth.DenseCP(30, 28, 40, 4, seed=3, noise=0.05, dtype=np.float64)
     X = g.slices(0, 40)
     c3 = osb.Config(rank=4, reps=3, als_iters=15, sample_factor=(2, 3, 2), seed=5,
-                    k_capacity=40, init_iters=30)
+                    k_capacity=40, init_iters=30, summary_bf16=bf16)
     cn = nmode.Config(rank=4, reps=3, als_iters=15, sample_factor=(2, 3, 2), seed=5, order=3,
-                      k_capacity=40, init_iters=30)
+                      k_capacity=40, init_iters=30, summary_bf16=bf16)
     o3 = osb.OracleTensor(c3, osb.DENSE, (30, 28, 30), X0=X[:, :, :30])
     on = nmode.OracleTensorN(cn, X[:, :, :30])
     for a, b in zip((o3.A, o3.B, o3.C, o3.lam), (*on.U, on.lam)):
@@ -117,6 +119,13 @@ def test_order3_update_is_the_third_order_update():
         for a, c in zip((o3.A, o3.B, o3.C), on.U):
             np.testing.assert_allclose(c, a, rtol=1e-10, atol=1e-12)
         assert abs(o3.fit() - on.fit()) < 1e-12
+    if bf16:  # the rounding is applied: FP64 summaries give other new rows
+        cf = nmode.Config(rank=4, reps=3, als_iters=15, sample_factor=(2, 3, 2), seed=5,
+                          order=3, k_capacity=40, init_iters=30)
+        of = nmode.OracleTensorN(cf, X[:, :, :30])
+        for b in range(2):
+            of.update(X[:, :, 30 + 5 * b:35 + 5 * b])
+        assert np.max(np.abs(of.U[2][30:] - on.U[2][30:])) > 1e-6
 
 
 @pytest.mark.parametrize("dims,R,flip", [((12, 10, 9, 30), 3, (1, 2)),
