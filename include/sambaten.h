@@ -473,7 +473,8 @@ void sbt_server_destroy(sbt_server* s);
  * factor's anchor rows; new rows averaged over the valid repetitions.  At
  * N = 3 it computes what the third-order update computes (plain schedule).
  *
- * Supported: cfg->format SBT_DENSE; cfg->precision SBT_P_F64 or SBT_P_F32
+ * Supported (dense; the COO form below): cfg->format SBT_DENSE; cfg->precision
+ * SBT_P_F64 or SBT_P_F32
  * (store, summaries and MTTKRP in that type; everything else FP64) or
  * SBT_P_BF16 (FP32 store, summaries rounded to BF16 to nearest even, MTTKRP
  * on the vector units with FP32 accumulation; everything else FP64);
@@ -493,6 +494,35 @@ sbt_status sbt_nd_init_dense(const sbt_config* cfg, int32_t order, const int64_t
                              const int32_t* sample_factor, const void* X0_dev,
                              const double* const* factors, const double* lambda0, void* stream,
                              sbt_tensor** out);
+
+/* The same for a sparse tensor in COO form (cfg->format SBT_COO, cfg->precision
+ * SBT_P_F32: FP32 values, every product and sum FP64): nnz entries with
+ * coordinates idx_dev[m][e] (N host pointers to device int32 arrays; the
+ * last coordinate in 0..dims[N-1]-1) and values v_dev[e] (device FP32), no
+ * coordinate twice; the entries are copied.  cfg->nnz_capacity bounds the
+ * entries the tensor can hold; cfg->repetitions <= 255; every extent and
+ * cfg->k_capacity below 2^24.  With factors NULL the initial decomposition is
+ * CP-ALS on the whole tensor (the sparse MTTKRP of the update on the tensor
+ * taken as one summary).  SBT_E_SHAPE for a coordinate outside the extents or
+ * more entries than the capacity; SBT_E_NUMERIC for a non-finite value.
+ * The update (sbt_nd_update_batch_coo) follows the dense order-N update with
+ * the summaries kept sparse: the stored entries whose every coordinate is
+ * sampled, re-indexed to the sample positions (Sec. 3.1). */
+sbt_status sbt_nd_init_coo(const sbt_config* cfg, int32_t order, const int64_t* dims,
+                           const int32_t* sample_factor, const int32_t* const* idx_dev,
+                           const float* v_dev, int64_t nnz, const double* const* factors,
+                           const double* lambda0, void* stream, sbt_tensor** out);
+
+/* A batch of K_new last-mode slices of a COO order-N tensor: nnz entries
+ * (idx_dev: N host pointers to device int32 arrays, the last coordinate
+ * batch-relative 0..K_new-1; v_dev device FP32).  Returns when the update is
+ * complete.  SBT_E_SHAPE for a coordinate outside the extents, K_new outside
+ * 1..max_batch, or capacity (slices or entries) exceeded; SBT_E_NUMERIC for a
+ * non-finite value; the tensor is unchanged in both cases.  SBT_E_STATE on a
+ * dense tensor. */
+sbt_status sbt_nd_update_batch_coo(sbt_tensor* t, const int32_t* const* idx_dev,
+                                   const float* v_dev, int64_t nnz, int64_t K_new,
+                                   void* stream);
 
 /* Order, extents (N int64 written; the last is the current slice count) and rank. */
 sbt_status sbt_nd_get_shape(const sbt_tensor* t, int32_t* order, int64_t* dims, int32_t* R);

@@ -2516,6 +2516,7 @@ sbt_status sbt_mttkrp_coo(const int32_t* a_dev, const int32_t* b_dev, const int3
 }  // extern "C"
 
 #include "engine_nd.inc"
+#include "engine_nd_coo.inc"
 
 namespace sbt {
 size_t store_elem_bytes(const sbt_tensor* t) {

@@ -137,6 +137,31 @@ __global__ __launch_bounds__(256) void moi_dense_kernel(const T* Y, int64_t I, i
     atomicAdd((unsigned long long*)&w3[k0 + threadIdx.x], sk[threadIdx.x]);
 }
 
+// q(v) = floor(v*v*scale) added to the importance of every mode's coordinate;
+// err bit 1: non-finite value or overflow, bit 2: coordinate out of range
+__global__ void moi_coo_nd_kernel(CooNd b, double scale, uint64_t qmax, NdWeights w,
+                                  uint32_t* err) {
+  bool bad = false, oob = false;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < b.nnz;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    bool in = true;
+    for (int m = 0; m < b.N; ++m) {
+      const int32_t x = b.idx[m][e];
+      in = in && x >= 0 && x < b.D[m];
+    }
+    if (!in) {
+      oob = true;
+      continue;
+    }
+    const uint64_t q = quantize_sq((double)b.v[e], scale, qmax, bad);
+    if (q == 0) continue;
+    for (int m = 0; m < b.N; ++m)
+      atomicAdd((unsigned long long*)&w.w[m][b.idx[m][e]], (unsigned long long)q);
+  }
+  if (bad) atomicOr(err, 1u);
+  if (oob) atomicOr(err, 2u);
+}
+
 __global__ __launch_bounds__(256) void moi_coo_kernel(const int32_t* ii, const int32_t* jj,
                                                      const int32_t* kk, const float* v,
                                                      int64_t nnz, int64_t I, int64_t J,
@@ -448,6 +473,13 @@ hipError_t launch_moi_coo(const int32_t* ii, const int32_t* jj, const int32_t* k
   if (nnz <= 0) return hipSuccess;
   moi_coo_kernel<<<fill_blocks(nnz), 256, 0, s>>>(ii, jj, kk, v, nnz, I, J, K, scale, qmax, w1,
                                                   w2, w3, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_moi_coo_nd(const CooNd& b, double scale, uint64_t qmax, const NdWeights& w,
+                             uint32_t* err, hipStream_t s) {
+  if (b.nnz <= 0) return hipSuccess;
+  moi_coo_nd_kernel<<<fill_blocks(b.nnz), 256, 0, s>>>(b, scale, qmax, w, err);
   return hipGetLastError();
 }
 

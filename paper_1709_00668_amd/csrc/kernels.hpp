@@ -569,4 +569,95 @@ hipError_t launch_solve_prod(const RepSet& rs, int rows, const double* M, const 
 // components ordered by lam descending (ties: lower index first), every factor
 hipError_t launch_sort_nd(const NdFactors& F, int N, int R, double* lam, hipStream_t s);
 
+// ---------------------------------------------------------------------------
+// Sparse (COO) tensors of order N
+// ---------------------------------------------------------------------------
+// A batch (or the initial entries): coordinates per mode, values; D the
+// extents the coordinates must lie in (the last: the batch's slices).
+struct CooNd {
+  int N;
+  const int32_t* idx[kMaxOrder];
+  const float* v;
+  int64_t nnz;
+  int64_t D[kMaxOrder];
+};
+struct NdWeights {
+  uint64_t* w[kMaxOrder];
+};
+struct CooStoreNd {
+  int32_t* idx[kMaxOrder];
+  float* v;
+};
+// concatenated summaries: coordinates (positions in the samples), values and
+// the repetition of every entry (null: all repetition 0)
+struct CooSumNd {
+  int32_t* idx[kMaxOrder];
+  float* v;
+  uint8_t* rep;
+};
+// position maps per repetition: mode m's part at posoff[m], stride entries
+struct PosViewNd {
+  int N;
+  int64_t posoff[kMaxOrder];
+  int64_t stride;
+};
+struct PosMapsNd {
+  int N;
+  const int32_t* idx;  // samples (per repetition at rep * idx_stride, mode m at off[m])
+  int64_t idx_stride;
+  int64_t off[kMaxOrder];
+  int n[kMaxOrder];    // sample sizes (the last: old slices)
+  int64_t posoff[kMaxOrder];
+  int64_t stride;
+  int64_t Kold, Knew;
+};
+// M(rep, row, f) over the entries [off[rep (rows + 1) + row], ... + 1) in the
+// order perm (null: positions themselves) of mode `mode`
+struct MttkrpCooNd {
+  int N, mode, R, rows, rep0, nrep;
+  const int32_t* idx[kMaxOrder];
+  const float* v;
+  const int32_t* perm;
+  const int64_t* off;
+  NdFactors F;
+  double* M;
+  int64_t sM;
+};
+// importance of a batch for every mode (integer atomics); err bit 1:
+// non-finite or overflow, bit 2: coordinate out of range
+hipError_t launch_moi_coo_nd(const CooNd& b, double scale, uint64_t qmax, const NdWeights& w,
+                             uint32_t* err, hipStream_t s);
+// scratch of launch_coo_ingest_nd for a batch of n entries
+size_t coo_nd_sort_bytes(int64_t n);
+// the batch stably sorted by its last coordinate, placed at base.. of the
+// store with the last coordinate shifted by k0 (nbits: bits of the largest
+// batch-relative last coordinate)
+hipError_t launch_coo_ingest_nd(const CooNd& b, int64_t base, int64_t k0, int nbits,
+                                const CooStoreNd& st, void* tmp, size_t tmp_bytes,
+                                hipStream_t s);
+// off[x] = lower bound of x in the ascending key[0..n), x in [x0, x1]
+hipError_t launch_lower_bounds(const int32_t* key, int64_t n, int64_t x0, int64_t x1,
+                               int64_t* off, hipStream_t s);
+hipError_t launch_pos_maps_nd(const PosMapsNd& a, int nrep, int32_t* pos, hipStream_t s);
+// keep flags of the stored entries per repetition (nrep * nnz + 1 entries)
+// and their exclusive scan `at` (at[nrep * nnz] = total kept)
+size_t coo_nd_scan_bytes(int64_t n);
+hipError_t launch_keep_flags_nd(const CooStoreNd& st, int64_t nnz, const PosViewNd& pv,
+                                const int32_t* pos, int nrep, uint32_t* flag, uint32_t* at,
+                                void* tmp, size_t tmp_bytes, hipStream_t s);
+hipError_t launch_summary_emit_nd(const CooStoreNd& st, int64_t nnz, const PosViewNd& pv,
+                                  const int32_t* pos, int nrep, const uint32_t* flag,
+                                  const uint32_t* at, const CooSumNd& z, hipStream_t s);
+// the summary positions sorted by (repetition, coordinate of mode m) and the
+// row offsets off[rep * (rows + 1) + x]
+size_t coo_nd_mode_sort_bytes(int64_t n);
+hipError_t launch_mode_sort_nd(const CooSumNd& z, int64_t total, int m, int rows, int nrep,
+                               uint32_t* key, uint32_t* key_sorted, int32_t* iota,
+                               int32_t* perm, int64_t* off, void* tmp, size_t tmp_bytes,
+                               hipStream_t s);
+hipError_t launch_mttkrp_coo_nd(const MttkrpCooNd& a, hipStream_t s);
+// nrm[k] = sum of v^2 over the entries [koff[k], koff[k + 1])
+hipError_t launch_slice_norms(const float* v, const int64_t* koff, int64_t K, double* nrm,
+                              hipStream_t s);
+
 }  // namespace sbt

@@ -102,6 +102,9 @@ _SIGS = {
     "sbt_server_destroy": (None, [_vp]),
     "sbt_nd_init_dense": (ctypes.c_int, [ctypes.POINTER(sbt_config), _i32, _vp, _vp, _vp, _vp,
                                          _vp, _vp, ctypes.POINTER(_vp)]),
+    "sbt_nd_init_coo": (ctypes.c_int, [ctypes.POINTER(sbt_config), _i32, _vp, _vp, _vp, _vp,
+                                       _i64, _vp, _vp, _vp, ctypes.POINTER(_vp)]),
+    "sbt_nd_update_batch_coo": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i64, _vp]),
     "sbt_nd_get_shape": (ctypes.c_int, [_vp, ctypes.POINTER(_i32), _vp, ctypes.POINTER(_i32)]),
     "sbt_nd_get_factor": (ctypes.c_int, [_vp, _i32, _vp, _vp]),
     "sbt_nd_get_lambda": (ctypes.c_int, [_vp, _vp, _vp]),
@@ -361,6 +364,17 @@ SBT_ND_REP_UP, SBT_ND_REP_UT, SBT_ND_REP_CT, SBT_ND_REP_LAMP, SBT_ND_REP_PI, SBT
     range(6)
 
 
+def coo_nd_to_device(idx, vals):
+    """(nnz, N) integer coordinates and values -> (N int32 coordinate arrays, float32
+    values) on the device."""
+    import torch
+    idx = np.asarray(idx)
+    cols = tuple(torch.from_numpy(np.ascontiguousarray(idx[:, m], dtype=np.int32)).cuda()
+                 for m in range(idx.shape[1]))
+    v = torch.from_numpy(np.ascontiguousarray(vals, dtype=np.float32)).cuda()
+    return cols, v
+
+
 def dense_nd_to_device(X, dtype):
     """Order-N array -> device tensor whose memory is the column-major layout
     the library expects (first index fastest)."""
@@ -397,6 +411,43 @@ class TensorN(Tensor):
                                    _stream(stream), ctypes.byref(out))
         _check(st, None, "sbt_nd_init_dense")
         return cls(out.value)
+
+    @classmethod
+    def init_coo_nd(cls, cfg, cols, v, dims, sample_factor, factors=None, lam=None,
+                    stream=None):
+        """cols: N device int32 coordinate arrays (the last inside 0..dims[-1]-1), v:
+        device float32 values."""
+        lib = load()
+        N = len(dims)
+        d = np.ascontiguousarray(dims, dtype=np.int64)
+        s = (sample_factor,) * N if np.isscalar(sample_factor) else tuple(sample_factor)
+        sf = np.ascontiguousarray(s, dtype=np.int32)
+        nnz = int(v.numel())
+        iptr = (ctypes.c_void_p * N)(*[_ptr(c) for c in cols])
+        keep = []
+        fptr = None
+        lptr = None
+        if factors is not None:
+            arrs = [np.ascontiguousarray(f, dtype=np.float64) for f in factors]
+            keep.extend(arrs)
+            fptr = (ctypes.c_void_p * N)(*[a.ctypes.data for a in arrs])
+            la = np.ascontiguousarray(lam, dtype=np.float64)
+            keep.append(la)
+            lptr = la.ctypes.data
+        out = _vp()
+        st = lib.sbt_nd_init_coo(ctypes.byref(cfg), N, d.ctypes.data, sf.ctypes.data,
+                                 ctypes.cast(iptr, _vp), _ptr(v), nnz,
+                                 ctypes.cast(fptr, _vp) if fptr else None, lptr,
+                                 _stream(stream), ctypes.byref(out))
+        _check(st, None, "sbt_nd_init_coo")
+        return cls(out.value)
+
+    def update_batch_coo_nd(self, cols, v, K_new, stream=None):
+        """cols: N device int32 coordinate arrays, the last batch-relative (0..K_new-1)."""
+        iptr = (ctypes.c_void_p * len(cols))(*[_ptr(c) for c in cols])
+        _check(load().sbt_nd_update_batch_coo(self.h, ctypes.cast(iptr, _vp), _ptr(v),
+                                              int(v.numel()), int(K_new), _stream(stream)),
+               self.h, "sbt_nd_update_batch_coo")
 
     def shape_nd(self):
         order, R = _i32(), _i32()
