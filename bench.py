@@ -132,10 +132,10 @@ def kernel_of(step, path, R, coo_row_nnz=0.0, n1_third=0):
                  "row_solve": f"p3_mfma_kernel<{nt}> + mode3_finish_kernel",
                  "gather": "gather_mfma_kernel<float>"},
         "coo": {"coo_mttkrp": f"coo_units_kernel<{rp}, {ul}>", "gather": "summary_emit_kernel"},
-        "nd_f32": {"mttkrp_contract_c": f"p1s_kernel<float, {rp}>",
+        "nd_f32": {"mttkrp_contract_c": f"p1s_kernel<float, {rp}, 1>",
                    "mttkrp_third_mode": f"p3_kernel<float, {rp}, {v3}, false>",
                    "row_solve": f"p3_kernel<float, {rp}, {v3}, false>",
-                   "gather": "gather_nd_kernel<float>"},
+                   "gather": "gather_nd_kernel<float, float>"},
     }
     return table.get(path, {}).get(step, step)
 
@@ -249,8 +249,8 @@ def kernel_digest(kernel, read=None):
 
 def committed_traffic(kernel, key):
     """HBM bytes per launch of `kernel` from a committed counter summary
-    (profiles/<workload>_traffic.md) taken on the same workload and step count
-    (`key`, so the same launches) and on the kernel's current sources
+    (profiles/<workload>_traffic.md) taken on the same workload, step count and
+    warmup (`key`, so the same launches) and on the kernel's current sources
     (per-kernel digest column)."""
     name = key.split("@")[0]
     path = os.path.join(ROOT, "profiles", f"{name}_traffic.md")
@@ -409,7 +409,8 @@ def bench_dense(args, sbt, torch, synth, log):
     b = runs[main]
     path = "f32" if main == "batched_f32" else "bf16"
     line = base_line(args, w, b, path)
-    line["roofline"] = roofline_of(b["profile"], path, w["R"], f"{name}@steps{steps}")
+    line["roofline"] = roofline_of(b["profile"], path, w["R"],
+                                   f"{name}@steps{steps}w{args.warmup}")
     if path == "bf16":
         # useful matrix-core work of the mode-3 pass: 2 |Z| R flops per summary
         pr = b["profile"]["mttkrp_third_mode"]
@@ -639,8 +640,8 @@ def bench_nd(args, sbt, torch, synth, log):
         "fit": round(b["fit"], 6),
     }
     n0 = -(-dims[0] // w["s"])
-    line["roofline"] = roofline_of(b["profile"], "nd_f32", R, f"{name}@steps{steps}",
-                                   n1_third=n0)
+    line["roofline"] = roofline_of(b["profile"], "nd_f32", R,
+                                   f"{name}@steps{steps}w{args.warmup}", n1_third=n0)
     if not args.no_recompute:
         # relative fitness against CP-ALS recomputed on the whole grown tensor (Sec. 4.2)
         cfg_r = sbt.make_config(R, w["r"], w["iters"], 1, w["seed"], precision=sbt.SBT_P_F32,
@@ -736,7 +737,7 @@ def bench_sparse(args, sbt, torch, synth, log):
     line["config"]["nnz_batch"] = nnzb
     line["initial_cp_als"] = init
     line["roofline"] = roofline_of(res["profile"], "coo", w["R"],
-                                   f"{name}@{args.nnz_scale:g}@steps{steps}",
+                                   f"{name}@{args.nnz_scale:g}@steps{steps}w{args.warmup}",
                                    summary_rows=w["r"] * -(-w["I"] // w["s"]))
     line["cpu_baseline"] = None
     if not args.no_recompute:
