@@ -19,6 +19,10 @@ before timing, the model starting from the generator's factors):
               50, s = 2, r = 4: the
               update with GetRank (`value`) and without, factor match score of
               each against the generating components.
+  getrank_sparse  the same on COO summaries: 2000 x 2000 x 400 of true rank 3
+              whose factor columns are nonzero on 5% of their rows (about
+              5.7e5 nonzeros in the initial block, 5.6e4 per batch), a rank-5
+              model, batches of 40, s = 2, r = 4.
   dense4d     dense FP32 order-4 120 x 120 x 120 x 120 (the last mode grows),
               rank-10 U[0,1) CP model plus 1% noise, batches of 12 slices; s = 4
               on every mode, r = 10, 30 ALS sweeps.  `value` is the FP32 path; the
@@ -95,6 +99,12 @@ WORKLOADS = {
                        desc="GetRank (Sec. 3.2): dense FP32 400x400x400 of true rank 3 "
                             "(N(0,1) factors) with a rank-5 model, 50-slice batches, s=2, r=4, "
                             "30 ALS sweeps; the update with and without GetRank"),
+    "getrank_sparse": dict(kind="getrank", fmt="coo", I=2000, J=2000, K0=400, Kn=40, R=5,
+                           R_true=3, s=2, r=4, iters=30, seed=8, support=0.05, noise=1e-3,
+                           desc="GetRank (Sec. 3.2) on COO summaries: 2000x2000x400 sparse "
+                                "tensor of true rank 3 (factor columns nonzero on 5% of their "
+                                "rows) with a rank-5 model, 40-slice batches, s=2, r=4, 30 ALS "
+                                "sweeps; the update with and without GetRank"),
     "dense4d": dict(kind="nd", dims=(120, 120, 120), K0=120, Kn=12, R=10, s=4, r=10, iters=30,
                     seed=6, noise=0.01,
                     desc="dense FP32 order-4 120x120x120x120 + 12-slice batches along the last "
@@ -496,18 +506,35 @@ def bench_getrank(args, sbt, torch, synth, log):
     with GetRank (one CP run per candidate rank, threshold 90) against the one
     without, on the same batches: factor match score against the generating
     components (padded with zero components to rank R: those pairs score 0, so
-    R_true / R is the best possible score) and fit."""
+    R_true / R is the best possible score) and fit.  Dense FP32 tensors, or
+    COO tensors of sparse support (fmt "coo")."""
     w = WORKLOADS[args.workload]
+    coo = w.get("fmt") == "coo"
     steps = args.steps
     I, J, K0, Kn, R = w["I"], w["J"], w["K0"], w["Kn"], w["R"]
     K = K0 + steps * Kn
-    gen = synth.DenseCP(I, J, K, w["R_true"], seed=w["seed"], noise=w["noise"],
-                        dtype=np.float32, factors="normal")
-    Xd = torch.empty((K, J, I), dtype=torch.float32, device="cuda")
-    gen.fill_device(torch, Xd)
-    torch.cuda.synchronize()
-    A, B, C, lam = gen.true_model_prefix(K)
     pad = R - w["R_true"]
+    if coo:
+        gen = synth.SparseSupportCP(I, J, K, w["R_true"], w["seed"], support=w["support"],
+                                    noise=w["noise"])
+        idx0, v0 = gen.entries(0, K0)
+        batches = [gen.entries(K0 + b * Kn, K0 + (b + 1) * Kn) for b in range(steps)]
+        cols0, vd0 = sbt.coo_to_device(idx0, v0)
+        bdev = [sbt.coo_to_device(ix, v) for ix, v in batches]
+        nnz_total = len(v0) + sum(len(v) for _, v in batches)
+        log(f"# data ready: {len(v0)} + {steps} x ~{len(batches[0][1])} nonzeros")
+        Fn = [np.linalg.norm(M, axis=0) for M in gen.F]
+        A, B, C = (M / n for M, n in zip(gen.F, Fn))
+        lam = Fn[0] * Fn[1] * Fn[2]
+        A0, B0, C0, lam0 = A, B, C[:K0], lam
+    else:
+        gen = synth.DenseCP(I, J, K, w["R_true"], seed=w["seed"], noise=w["noise"],
+                            dtype=np.float32, factors="normal")
+        Xd = torch.empty((K, J, I), dtype=torch.float32, device="cuda")
+        gen.fill_device(torch, Xd)
+        torch.cuda.synchronize()
+        A, B, C, lam = gen.true_model_prefix(K)
+        A0, B0, C0, lam0 = gen.true_model_prefix(K0)
     truth = (np.hstack([A, np.zeros((I, pad))]), np.hstack([B, np.zeros((J, pad))]),
              np.hstack([C, np.zeros((K, pad))]), np.concatenate([lam, np.zeros(pad)]))
     # the model: the generating components of the initial block and R - R_true
@@ -516,33 +543,62 @@ def bench_getrank(args, sbt, torch, synth, log):
     g = np.random.default_rng(np.random.SeedSequence([w["seed"], 31]))
     extra = [g.standard_normal((n, pad)) for n in (I, J, K0)]
     extra = [M / np.linalg.norm(M, axis=0) for M in extra]
-    A0, B0, C0, lam0 = gen.true_model_prefix(K0)
     model = (np.hstack([A0, extra[0]]), np.hstack([B0, extra[1]]), np.hstack([C0, extra[2]]),
              np.concatenate([lam0, np.full(pad, 0.01 * lam0.min())]))
-    cfg0 = sbt.make_config(R, w["r"], w["iters"], w["s"], w["seed"], precision=sbt.SBT_P_F32,
-                           k_capacity=K, max_batch=Kn)
-    T0 = sbt.Tensor.init_dense(cfg0, Xd[:K0], I, J, K0, factors=model)
+
+    def make_cfg(runs):
+        if coo:
+            return sbt.make_config(R, w["r"], w["iters"], w["s"], w["seed"], fmt=sbt.SBT_COO,
+                                   precision=sbt.SBT_P_F32, k_capacity=K, max_batch=Kn,
+                                   nnz_capacity=nnz_total, getrank_runs=runs)
+        return sbt.make_config(R, w["r"], w["iters"], w["s"], w["seed"],
+                               precision=sbt.SBT_P_F32, k_capacity=K, max_batch=Kn,
+                               getrank_runs=runs)
+
+    def run(runs, first):
+        if not coo:
+            return run_dense(sbt, torch, w, Xd, model, sbt.SBT_P_F32, sbt.SBT_SCHED_BATCHED,
+                             steps, args.warmup, 1, truth=truth, getrank_runs=runs,
+                             first=first)
+        cfg = make_cfg(runs)
+
+        def fresh():
+            return sbt.Tensor.init_coo(cfg, cols0, vd0, len(v0), I, J, K0, model)
+
+        def apply_batch(T, b):
+            c, v = bdev[b]
+            T.update_batch_coo(c, v, int(v.numel()), Kn)
+
+        return timed_sequence(sbt, torch, fresh, apply_batch, steps, args.warmup, 1, Kn,
+                              truth=truth, first=first)
+
+    if coo:
+        T0 = sbt.Tensor.init_coo(make_cfg(0), cols0, vd0, len(v0), I, J, K0, model)
+    else:
+        T0 = sbt.Tensor.init_dense(make_cfg(0), Xd[:K0], I, J, K0, factors=model)
     init_fit = T0.fit()
     T0.close()
     log(f"# rank-{R} model of rank-{w['R_true']} data: fit {init_fit:.6f}")
     out, firsts = {}, {}
     for name, runs in (("without", 0), ("with", 1)):
         first = None if args.no_cpu_baseline else firsts.setdefault(name, {})
-        res = run_dense(sbt, torch, w, Xd, model, sbt.SBT_P_F32, sbt.SBT_SCHED_BATCHED, steps,
-                        args.warmup, 1, truth=truth, getrank_runs=runs, first=first)
+        res = run(runs, first)
         out[name] = dict(path_summary(res), fms_truth=round(res["fms_truth"], 4))
         log(f"# {name} GetRank: {res['slices_per_s']:.1f} slices/s, fit {res['fit']:.6f}, "
             f"FMS vs truth {res['fms_truth']:.4f}")
+    config = {"workload": w["desc"], "I": I, "J": J, "K0": K0, "batch": Kn, "rank": R,
+              "true_rank": w["R_true"], "s": w["s"], "r": w["r"], "als_iters": w["iters"],
+              "getrank_runs": 1, "getrank_threshold": 90.0}
+    if coo:
+        config["nnz0"] = len(v0)
+        config["nnz_batch"] = int(np.mean([len(v) for _, v in batches]))
     line = {
         "metric": "updated slices/sec with GetRank on rank-deficient data (factor match score "
                   "against the generating components and fit, with and without GetRank)",
         "value": out["with"]["value"], "unit": "slices/s", "n_gpus": 1, "steps": steps,
         "warmup": args.warmup, "ms_per_step": out["with"]["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": w["desc"], "I": I, "J": J, "K0": K0, "batch": Kn, "rank": R,
-                   "true_rank": w["R_true"], "s": w["s"], "r": w["r"], "als_iters": w["iters"],
-                   "getrank_runs": 1, "getrank_threshold": 90.0},
+        "data": "synthetic", "config": config,
         "fms_truth_best_possible": round(w["R_true"] / R, 4),
         "with_getrank": out["with"], "without_getrank": out["without"],
         "initial_fit": round(init_fit, 6), "roofline": None, "cpu_baseline": None,
@@ -550,13 +606,20 @@ def bench_getrank(args, sbt, torch, synth, log):
     if not args.no_cpu_baseline:
         # the oracle with GetRank on the first update of the same data
         from oracle import sambaten as osb
-        Xh = Xd[:K0 + Kn].cpu().numpy().transpose(2, 1, 0)
         ocfg = osb.Config(rank=R, reps=w["r"], als_iters=w["iters"], sample_factor=w["s"],
                           seed=w["seed"], k_capacity=K0 + Kn, getrank_runs=1,
+                          nnz_capacity=(len(v0) + len(batches[0][1])) if coo else None,
                           workers=host_threads())
-        ora = osb.OracleTensor(ocfg, osb.DENSE, (I, J, K0), X0=Xh[:, :, :K0], factors=model)
-        t0 = time.perf_counter()
-        d = ora.update(Xh[:, :, K0:K0 + Kn], debug=True)
+        if coo:
+            ora = osb.OracleTensor(ocfg, osb.COO, (I, J, K0), coo0=(idx0, v0), factors=model)
+            t0 = time.perf_counter()
+            d = ora.update(coo=(batches[0][0], batches[0][1], Kn), debug=True)
+        else:
+            Xh = Xd[:K0 + Kn].cpu().numpy().transpose(2, 1, 0)
+            ora = osb.OracleTensor(ocfg, osb.DENSE, (I, J, K0), X0=Xh[:, :, :K0],
+                                   factors=model)
+            t0 = time.perf_counter()
+            d = ora.update(Xh[:, :, K0:K0 + Kn], debug=True)
         dt = time.perf_counter() - t0
         fo = ora.fit()
         line["cpu_baseline"] = {"value": round(Kn / dt, 3), "unit": "slices/s",

@@ -104,7 +104,9 @@ typedef struct {
   int64_t k_capacity;        /* largest third-mode size the tensor may reach */
   int64_t max_batch;         /* largest K_new of one update */
   int64_t nnz_capacity;      /* COO only: largest number of stored nonzeros */
-  /* GetRank (Sec. 3.2, Alg. 2), dense FP64/FP32 tensors only.  With
+  /* GetRank (Sec. 3.2, Alg. 2), third-order tensors with FP64 or FP32
+   * summaries (dense, or COO, whose core consistency is computed from the
+   * summary's entries slice by slice, the sparse form the paper uses).  With
    * getrank_runs > 0 every summary is decomposed at each candidate rank
    * i = 1..R, getrank_runs times (CP-ALS, als_iters sweeps, own initial
    * factors per run), each run is scored by its core consistency (percent),

@@ -223,8 +223,30 @@ def corcondia(Z, A, B, C, lam):
     return 100.0 * (1.0 - float(np.sum((G - T) ** 2)) / R)
 
 
+def corcondia_coo(idx, vals, dims, A, B, C, lam):
+    """The core consistency of corcondia() for a COO tensor: the same core
+    G = Z x1 pinv(A) x2 pinv(B) x3 pinv(C diag(lam)), summed nonzero by
+    nonzero, G(a, b, c) = sum over (x, y, z, v) of v Pa(a, x) Pb(b, y) Pc(c, z)
+    (the zero entries add nothing; the sparse form the paper uses).  idx is
+    (nnz, 3) int, vals (nnz,) float; dims only checks the coordinates."""
+    idx = np.asarray(idx, dtype=np.int64).reshape(-1, 3)
+    v = np.asarray(vals, dtype=np.float64)
+    assert all(idx[:, m].max(initial=-1) < dims[m] for m in range(3))
+    R = A.shape[1]
+    Pa = np.linalg.pinv(A)
+    Pb = np.linalg.pinv(B)
+    Pc = np.linalg.pinv(C * np.asarray(lam)[None, :])
+    G = np.einsum("e,ae,be,ce->abc", v, Pa[:, idx[:, 0]], Pb[:, idx[:, 1]], Pc[:, idx[:, 2]],
+                  optimize=True)
+    T = np.zeros((R, R, R))
+    T[np.arange(R), np.arange(R), np.arange(R)] = 1.0
+    return 100.0 * (1.0 - float(np.sum((G - T) ** 2)) / R)
+
+
 def get_rank(Z, R, runs, threshold, iters, init):
-    """GetRank (Sec. 3.2, Alg. 2) on the dense summary Z.
+    """GetRank (Sec. 3.2, Alg. 2) on the summary Z: a dense array, or a COO
+    tensor given as (idx, vals, dims), whose CP-ALS runs over its entries
+    and whose core consistency is summed over them (corcondia_coo).
 
     Every candidate rank i = 1..R gets `runs` CP-ALS runs (fixed `iters`
     sweeps) from the initial factors init(i, q) -> (B0, C0), q the run's
@@ -235,10 +257,22 @@ def get_rank(Z, R, runs, threshold, iters, init):
     Returns (R_new, (A, B, C), lam, cc) with the factors of the best run at
     R_new (the first of equal scores) and cc[i - 1][j] the scores.
     """
-    dims = Z.shape
+    if isinstance(Z, tuple):
+        idx, vals, dims = Z
 
-    def mtt(F, mode):
-        return mttkrp_dense(Z, F, mode)
+        def mtt(F, mode):
+            return mttkrp_coo(idx, vals, F, mode, dims)
+
+        def score_of(A, B, C, lam):
+            return corcondia_coo(idx, vals, dims, A, B, C, lam)
+    else:
+        dims = Z.shape
+
+        def mtt(F, mode):
+            return mttkrp_dense(Z, F, mode)
+
+        def score_of(A, B, C, lam):
+            return corcondia(Z, A, B, C, lam)
 
     cc = []
     best = None
@@ -248,7 +282,7 @@ def get_rank(Z, R, runs, threshold, iters, init):
         for j in range(runs):
             B0, C0 = init(i, (i - 1) * runs + j)
             (A, B, C), lam, _ = cp_als(mtt, dims, i, iters, B0, C0)
-            score = corcondia(Z, A, B, C, lam)
+            score = score_of(A, B, C, lam)
             row.append(score)
             if top is None or score > top[0]:
                 top = (score, (A, B, C), lam)

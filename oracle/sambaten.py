@@ -381,8 +381,9 @@ class OracleTensor:
             if cfg.getrank_runs > 0:
                 # GetRank (Sec. 3.2) before the decomposition: the summary's
                 # rank R_new <= R and the best of its CP runs at that rank
+                # (a sparse summary's runs and scores go over its entries)
                 if self.fmt != DENSE:
-                    raise NotImplementedError("GetRank runs on dense summaries")
+                    Z = (Zidx, Zval, dims_s)
 
                 def init(i, q, rho=rho, dims_s=dims_s):
                     return tuple(cp.als_init_factor(cfg.seed, cfg.tensor_id, rng.TAG_GETRANK,

@@ -92,6 +92,7 @@ struct sbt_tensor {
   double *gAk = nullptr, *gBk = nullptr, *gCk = nullptr, *glamk = nullptr;
   double *gcc = nullptr, *gbest = nullptr, *gtab = nullptr, *gP = nullptr, *gX1 = nullptr,
          *gX2 = nullptr, *gGi = nullptr;
+  double* gWz = nullptr;  // COO: per-slice partial cores [rep][z][R x R]
   int32_t* grnew = nullptr;
   // captured CP-ALS sweep sequences by launch shape (null: seen once)
   std::map<uint64_t, hipGraphExec_t> graphs;
@@ -301,8 +302,7 @@ sbt_status validate_config(const sbt_config* c, std::string& why) {
       {(c->flags & ~(uint32_t)SBT_FLAG_LAMBDA_AVG) != 0 || c->reserved != 0,
        "unknown flags, or reserved not 0"},
       {c->getrank_runs < 0 || c->getrank_runs > 64, "getrank_runs must be in 0..64"},
-      {gr && (c->format != SBT_DENSE || c->precision == SBT_P_BF16),
-       "GetRank needs a dense FP64 or FP32 tensor"},
+      {gr && c->precision == SBT_P_BF16, "GetRank needs FP64 or FP32 summaries"},
       {gr && !(c->getrank_threshold == c->getrank_threshold), "bad GetRank threshold"},
       {c->persist_summaries != 0 && c->persist_summaries != 1, "persist_summaries must be 0 or 1"},
       {c->summary_refresh < 0, "summary_refresh must be >= 0"},
@@ -445,6 +445,7 @@ sbt_status alloc_state(sbt_tensor* t) {
     SBT_TRY(dalloc(t, &t->gX2, (size_t)r * R3));
     SBT_TRY(dalloc(t, &t->gGi, (size_t)3 * r * rs.sG));
     SBT_TRY(dalloc(t, &t->grnew, (size_t)r));
+    if (t->fmt == SBT_COO) SBT_TRY(dalloc(t, &t->gWz, (size_t)r * t->Kpmax * R * R));
   }
   SBT_TRY(dalloc(t, &t->M3, (size_t)t->Kcap * R));
   SBT_TRY(dalloc(t, &t->nrm, (size_t)t->Kcap));
@@ -745,6 +746,7 @@ struct CooAlsBufs {
   int iters;
   uint32_t stream;                    // Philox stream of the initial factors
   uint32_t t_ctr;
+  uint32_t col0;                      // first counter column of the initial factors
   bool warm;                          // start from the kept summary factors
 };
 
@@ -760,7 +762,7 @@ sbt_status als_coo_core(sbt_tensor* t, RepSet rs, const CooAlsBufs& b, hipStream
                            t->warm_n3, b.Bp, b.Cp, st));
   else
     SBT_CK(launch_als_init(rs, t->cfg.seed, t->cfg.tensor_id, b.stream, b.t_ctr, b.Bp, b.Cp,
-                           st));
+                           st, b.col0));
   SBT_TRY(gram_rows(t, rs, b.Bp, rs.sB, rs.n2, b.GB, st));
   SBT_TRY(gram_rows(t, rs, b.Cp, rs.sC, rs.n3, b.GC, st));
   SBT_CK(launch_fill_f64(b.invlam + (int64_t)rs.rep0 * 3 * R, (int64_t)rs.nrep * 3 * R, 1.0,
@@ -804,8 +806,10 @@ sbt_status als_coo_core(sbt_tensor* t, RepSet rs, const CooAlsBufs& b, hipStream
   return SBT_OK;
 }
 
-// CP-ALS on the r COO summaries of an update.
-sbt_status run_als_coo(sbt_tensor* t, RepSet rs, uint32_t t_ctr, hipStream_t st) {
+// CP-ALS on the r COO summaries of an update (at rank rs.R, initial factors
+// from the given stream at counter columns col0 + f).
+sbt_status run_als_coo(sbt_tensor* t, RepSet rs, uint32_t t_ctr, hipStream_t st,
+                       uint32_t stream = kStreamAlsInit, uint32_t col0 = 0) {
   CooAlsBufs b;
   b.z = &t->z;
   b.cu = t->cu;
@@ -828,9 +832,10 @@ sbt_status run_als_coo(sbt_tensor* t, RepSet rs, uint32_t t_ctr, hipStream_t st)
   b.avg[2] = (double)t->last_summary_nnz / (nrow_all * rs.n3);
   b.ebytes = (double)t->last_summary_nnz * 12.0;
   b.iters = t->cfg.als_iters;
-  b.stream = kStreamAlsInit;
+  b.stream = stream;
   b.t_ctr = t_ctr;
-  b.warm = t->warm_now;
+  b.col0 = col0;
+  b.warm = t->warm_now && stream == kStreamAlsInit;
   return als_coo_core(t, rs, b, st);
 }
 
@@ -930,6 +935,7 @@ sbt_status init_cp_als_coo(sbt_tensor* t, hipStream_t st) {
     b.iters = t->cfg.init_iters;
     b.stream = kStreamInit;
     b.t_ctr = 0;
+    b.col0 = 0;
     b.warm = false;
     SBT_TRY(als_coo_core(t, rs, b, st));
     SBT_CK(launch_sort_components(t->A, t->B, t->C, t->lam, I, J, K, R, st));
@@ -1235,25 +1241,31 @@ sbt_status check_factor_args(const double* A0, const double* B0, const double* C
 }
 
 // The update after the batch is in the store and its importance is in dw*.
-// GetRank (Sec. 3.2) on the dense summaries of rs: every candidate rank
-// i = 1..R gets getrank_runs CP-ALS runs (initial factors from the GetRank
-// stream, run q = (i - 1) runs + j at columns 32 q of the counter), each
-// scored by its core consistency; the kept run per repetition ends in Ap, Bp,
-// Cp, lamp (rows padded to R columns) and its rank in grnew.
+// GetRank (Sec. 3.2) on the summaries of rs: every candidate rank i = 1..R
+// gets getrank_runs CP-ALS runs (initial factors from the GetRank stream, run
+// q = (i - 1) runs + j at columns 32 q of the counter), each scored by its
+// core consistency; the kept run per repetition ends in Ap, Bp, Cp, lamp (rows
+// padded to R columns) and its rank in grnew.  Dense summaries get the
+// projected core through Z x3 C^T, COO summaries through their third-mode
+// slices (the sparse form of the diagnostic the paper uses).
 sbt_status getrank_search(sbt_tensor* t, const RepSet& rs, bool plain, hipStream_t st) {
   const sbt_config& c = t->cfg;
   const int R = t->R, runs = c.getrank_runs;
   const int64_t R3 = (int64_t)R * R * R;
   const int64_t sGi = (int64_t)c.repetitions * rs.sG;
+  const bool coo = t->fmt == SBT_COO;
   for (int i = 1; i <= R; ++i) {
     RepSet ri = rs;
     ri.R = i;  // strides stay those of rank R
     SBT_CK(launch_fill_f64(t->gbest + rs.rep0, rs.nrep, -1.0e308, st));
     for (int j = 0; j < runs; ++j) {
       const uint32_t q = (uint32_t)((i - 1) * runs + j);
-      SBT_TRY(run_als(t, t->Z, ri, t->Ap, t->Bp, t->Cp, t->GA, t->GB, t->GC, t->lamp, t->W, t->M,
-                      t->Vinv, t->invlam, kStreamGetRank, t->t, c.als_iters, plain, st,
-                      32u * q));
+      if (coo)
+        SBT_TRY(run_als_coo(t, ri, t->t, st, kStreamGetRank, 32u * q));
+      else
+        SBT_TRY(run_als(t, t->Z, ri, t->Ap, t->Bp, t->Cp, t->GA, t->GB, t->GC, t->lamp, t->W,
+                        t->M, t->Vinv, t->invlam, kStreamGetRank, t->t, c.als_iters, plain, st,
+                        32u * q));
       // Grams of the unit-column factors and their inverses
       SBT_TRY(gram_rows(t, ri, t->Ap, ri.sA, ri.n1, t->GA, st));
       SBT_TRY(gram_rows(t, ri, t->Bp, ri.sB, ri.n2, t->GB, st));
@@ -1261,9 +1273,14 @@ sbt_status getrank_search(sbt_tensor* t, const RepSet& rs, bool plain, hipStream
       SBT_CK(launch_inverse(ri, t->GA, ri.sG, t->ones, 0, t->gGi, t->pinv, st));
       SBT_CK(launch_inverse(ri, t->GB, ri.sG, t->ones, 0, t->gGi + sGi, t->pinv, st));
       SBT_CK(launch_inverse(ri, t->GC, ri.sG, t->ones, 0, t->gGi + 2 * sGi, t->pinv, st));
-      // W = Z x3 C^T, the projected core, the core consistency
-      SBT_CK(launch_p1(t->sum_prec, ri, t->Z, t->Cp, t->W, st));
-      SBT_CK(launch_core(t->sum_prec, ri, t->W, t->Ap, t->Bp, t->gP, R3, st));
+      // the projected core (dense: W = Z x3 C^T first), the core consistency
+      if (coo) {
+        SBT_CK(launch_core_coo(ri, t->z.a, t->z.b, t->z.v, t->z.offC, t->z.sOffC, t->Ap, t->Bp,
+                               t->Cp, t->gWz, (int64_t)t->Kpmax * R * R, t->gP, R3, st));
+      } else {
+        SBT_CK(launch_p1(t->sum_prec, ri, t->Z, t->Cp, t->W, st));
+        SBT_CK(launch_core(t->sum_prec, ri, t->W, t->Ap, t->Bp, t->gP, R3, st));
+      }
       SBT_CK(launch_corcondia(ri, t->gP, t->gX1, t->gX2, R3, t->gGi, sGi, t->lamp, t->gcc, st));
       SBT_CK(launch_rank_select(ri, R, runs, j, i == 1 && j == 0, c.getrank_threshold, t->gcc,
                                 t->gbest, t->gtab, t->grnew, t->Ap, t->Bp, t->Cp, t->lamp,
@@ -1347,10 +1364,10 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
   t->warm_n3 = n3old;
   for (int q = 0; q < nchunks; ++q) {
     RepSet rs = (plain && !coo) ? make_repset(t, Kp, q, 1) : all;
-    if (coo) {
-      SBT_TRY(run_als_coo(t, rs, t->t, st));
-    } else if (c.getrank_runs > 0) {
+    if (c.getrank_runs > 0) {
       SBT_TRY(getrank_search(t, rs, plain, st));
+    } else if (coo) {
+      SBT_TRY(run_als_coo(t, rs, t->t, st));
     } else {
       SBT_TRY(run_als(t, t->Z, rs, t->Ap, t->Bp, t->Cp, t->GA, t->GB, t->GC, t->lamp, t->W,
                       t->M, t->Vinv, t->invlam, kStreamAlsInit, t->t, c.als_iters, plain, st));

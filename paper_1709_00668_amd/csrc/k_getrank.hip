@@ -67,6 +67,76 @@ __global__ __launch_bounds__(256) void core_kernel(RepSet rs, const TA* W, const
   }
 }
 
+// The projected core of sparse summaries, P(a, b, c) = sum over the entries
+// (x, y, z, v) of v A(x, a) B(y, b) C(z, c), in two steps through the slices
+// of the third mode (the entries are stored slice by slice):
+//   Wz(a, b) = sum over the entries of slice z of v A(x, a) B(y, b),
+//   P(a, b, c) = sum_z C(z, c) Wz(a, b).
+// Every product and sum in FP64.  One block per (slice, repetition); the
+// slice's entries pass through LDS in chunks with their two factor rows.
+constexpr int kCoreE = 64;  // entries per staged chunk
+
+__global__ __launch_bounds__(256) void core_slices_coo_kernel(
+    RepSet rs, const int32_t* za, const int32_t* zb, const float* zv, const int64_t* offC,
+    int64_t sOffC, const double* Ap, const double* Bp, double* Wz, int64_t sWz) {
+  const int z = blockIdx.x, rep = rs.rep0 + blockIdx.y;
+  const int ir = rs.R;
+  const int64_t o0 = offC[rep * sOffC + z], o1 = offC[rep * sOffC + z + 1];
+  const double* A = Ap + rep * rs.sA;
+  const double* B = Bp + rep * rs.sB;
+  __shared__ double As[kCoreE][kMaxRank + 1];
+  __shared__ double Bs[kCoreE][kMaxRank + 1];
+  const int tid = threadIdx.x;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};  // pairs (a, b) = tid + 256 k
+  for (int64_t e0 = o0; e0 < o1; e0 += kCoreE) {
+    const int en = o1 - e0 < kCoreE ? (int)(o1 - e0) : kCoreE;
+    for (int q = tid; q < en * ir; q += 256) {
+      const int e = q / ir, f = q % ir;
+      const double v = (double)zv[e0 + e];
+      As[e][f] = v * A[(int64_t)za[e0 + e] * ir + f];
+      Bs[e][f] = B[(int64_t)zb[e0 + e] * ir + f];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int p = tid + 256 * k;
+      if (p < ir * ir) {
+        const int a = p / ir, b = p % ir;
+        double s = acc[k];
+        for (int e = 0; e < en; ++e) s += As[e][a] * Bs[e][b];
+        acc[k] = s;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int p = tid + 256 * k;
+    if (p < ir * ir) Wz[rep * sWz + (int64_t)z * ir * ir + p] = acc[k];
+  }
+}
+
+// P(a, b, c) = sum_z C(z, c) Wz(a, b): one block per (c, repetition), P
+// stored [rep][a][b][c] (stride sP) as the dense core kernel writes it
+__global__ __launch_bounds__(256) void core_from_slices_kernel(RepSet rs, const double* Wz,
+                                                               int64_t sWz, const double* Cp,
+                                                               double* P, int64_t sP) {
+  const int c = blockIdx.x, rep = rs.rep0 + blockIdx.y;
+  const int ir = rs.R, n3 = rs.n3;
+  const double* W = Wz + rep * sWz;
+  const double* C = Cp + rep * rs.sC;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int p = tid + 256 * k;
+    if (p < ir * ir) {
+      double s = 0.0;
+      for (int z = 0; z < n3; ++z) s += C[(int64_t)z * ir + c] * W[(int64_t)z * ir * ir + p];
+      P[rep * sP + (int64_t)p * ir + c] = s;
+    }
+  }
+}
+
 // G from P by the three small inverses (Gi: GA^-1, GB^-1, GC^-1 at offsets 0,
 // sGi, 2 sGi, each [rep][i x i] with stride sG), lambda of the run (stride i),
 // then cc[rep].  X1, X2: scratch of the same shape as P.  One block per
@@ -172,6 +242,22 @@ hipError_t launch_core(int prec, const RepSet& rs, const void* W, const double* 
     core_kernel<double><<<grid, 256, 0, s>>>(rs, (const double*)W, Ap, Bp, P, sP);
   else
     core_kernel<float><<<grid, 256, 0, s>>>(rs, (const float*)W, Ap, Bp, P, sP);
+  return hipGetLastError();
+}
+
+hipError_t launch_core_coo(const RepSet& rs, const int32_t* za, const int32_t* zb,
+                           const float* zv, const int64_t* offC, int64_t sOffC, const double* Ap,
+                           const double* Bp, const double* Cp, double* Wz, int64_t sWz,
+                           double* P, int64_t sP, hipStream_t s) {
+  if (rs.R * rs.R > 1024 || (int64_t)rs.n3 * rs.R * rs.R > sWz) return hipErrorInvalidValue;
+  if (rs.n3 > 0) {
+    core_slices_coo_kernel<<<dim3((unsigned)rs.n3, (unsigned)rs.nrep), 256, 0, s>>>(
+        rs, za, zb, zv, offC, sOffC, Ap, Bp, Wz, sWz);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  core_from_slices_kernel<<<dim3((unsigned)rs.R, (unsigned)rs.nrep), 256, 0, s>>>(rs, Wz, sWz, Cp,
+                                                                                 P, sP);
   return hipGetLastError();
 }
 

@@ -416,6 +416,13 @@ hipError_t launch_fit_coo(const int32_t* ii, const int32_t* jj, const float* v,
 // from W = Z x3 C^T in the [f][e] layout of launch_p1; P is [rep][a][b][c]
 hipError_t launch_core(int prec, const RepSet& rs, const void* W, const double* Ap,
                        const double* Bp, double* P, int64_t sP, hipStream_t s);
+// the same projected core from COO summaries (entries stored slice by slice
+// of the third mode, slice z of repetition rep at offC[rep sOffC + z ..
+// + 1]): the slice partials go to Wz ([rep][z][a][b], stride sWz >= n3 R^2)
+hipError_t launch_core_coo(const RepSet& rs, const int32_t* za, const int32_t* zb,
+                           const float* zv, const int64_t* offC, int64_t sOffC, const double* Ap,
+                           const double* Bp, const double* Cp, double* Wz, int64_t sWz,
+                           double* P, int64_t sP, hipStream_t s);
 // core consistency (percent) of every repetition from P, the inverse Grams
 // (GA^-1, GB^-1, GC^-1 at Gi, Gi + sGi, Gi + 2 sGi) and the run's lambda
 hipError_t launch_corcondia(const RepSet& rs, const double* P, double* X1, double* X2, int64_t sP,

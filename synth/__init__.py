@@ -120,6 +120,63 @@ class DenseCP:
         return A, B, C[:K0].copy(), lam
 
 
+class SparseSupportCP:
+    """A sparse tensor of exact low rank: X = sum_r A(:,r) o B(:,r) o C(:,r)
+    with factor entries 0.5 + U[0,1) on about `support` of the rows of each
+    column and zero elsewhere, so X is zero outside the union of R boxes.  The
+    nonzeros of slice k get N(0, noise^2) from the noise stream of block k (in
+    the order of (i, j)) and are rounded to FP32.  For rank estimation on
+    sparse data (the rank is R wherever the boxes are sampled); built box by
+    box, so large tensors need no dense array.
+    """
+
+    def __init__(self, I, J, K, R, seed, support=0.4, noise=1e-3):
+        self.I, self.J, self.K, self.R = int(I), int(J), int(K), int(R)
+        self.seed, self.noise = int(seed), float(noise)
+        g = _gen(seed, STREAM_FACTOR)
+        self.F = [np.where(g.random((n, self.R)) < support, 0.5 + g.random((n, self.R)), 0.0)
+                  for n in (self.I, self.J, self.K)]
+
+    def entries(self, k0, k1):
+        """The nonzeros of slices k0..k1-1: coordinates (third one relative to
+        k0), ordered by k, then i, then j, and FP32 values."""
+        A, B, C = self.F
+        I, J = self.I, self.J
+        keys, vals = [], []
+        for r in range(self.R):
+            ia = np.nonzero(A[:, r])[0]
+            jb = np.nonzero(B[:, r])[0]
+            kc = np.nonzero(C[k0:k1, r])[0]
+            if len(ia) == 0 or len(jb) == 0 or len(kc) == 0:
+                continue
+            key = (kc[:, None, None] * I + ia[None, :, None]) * J + jb[None, None, :]
+            v = C[k0 + kc, r][:, None, None] * A[ia, r][None, :, None] * B[jb, r][None, None, :]
+            keys.append(key.ravel())
+            vals.append(v.ravel())
+        if not keys:
+            return np.zeros((0, 3), dtype=np.int64), np.zeros(0, dtype=np.float32)
+        key, inv = np.unique(np.concatenate(keys), return_inverse=True)
+        x = np.bincount(inv, weights=np.concatenate(vals), minlength=len(key))
+        k = key // (I * J)
+        i = (key // J) % I
+        j = key % J
+        if self.noise > 0:
+            bounds = np.searchsorted(k, np.arange(k1 - k0 + 1))
+            for kk in range(k1 - k0):
+                a, b = bounds[kk], bounds[kk + 1]
+                if b > a:
+                    x[a:b] += self.noise * _gen(self.seed, STREAM_NOISE, k0 + kk).standard_normal(
+                        b - a)
+        return np.stack([i, j, k], axis=1), x.astype(np.float32)
+
+    def dense(self, k0, k1):
+        """Slices k0..k1-1 as an FP64 array holding the values of entries()."""
+        idx, v = self.entries(k0, k1)
+        X = np.zeros((self.I, self.J, k1 - k0))
+        X[tuple(idx.T)] = v
+        return X
+
+
 class SparseCP:
     """COO nonzeros drawn from a nonnegative rank-R model.
 

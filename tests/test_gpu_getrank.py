@@ -84,3 +84,50 @@ def test_getrank_threshold_edges(lib, tau, expect):
         assert int(gpu.last_rep(rho, lib.SBT_REP_RNEW, 1, ncols=1)[0, 0]) == expect
     A, B, C, lam = gpu.get_factors()
     assert_close(C[K0:], ora.C[K0:], 1e-7, 1e-7, "new rows of C")
+
+
+def _pair_coo(lib, I, J, K0, Kn, R_true, R, reps, iters, s, seed, runs, tau):
+    import torch
+    assert torch.cuda.is_available()
+    gen = synth.SparseSupportCP(I, J, K0 + Kn, R_true, seed)
+    idx0, v0 = gen.entries(0, K0)
+    yi, yv = gen.entries(K0, K0 + Kn)
+    nnz = len(v0) + len(yv)
+    ocfg = osb.Config(rank=R, reps=reps, als_iters=iters, sample_factor=s, seed=seed,
+                      k_capacity=K0 + Kn, nnz_capacity=nnz, init_iters=40, getrank_runs=runs,
+                      getrank_threshold=tau)
+    ora = osb.OracleTensor(ocfg, osb.COO, (I, J, K0), coo0=(idx0, v0))
+    cfg = lib.make_config(R, reps, iters, s, seed, fmt=lib.SBT_COO, precision=lib.SBT_P_F32,
+                          k_capacity=K0 + Kn, max_batch=Kn, nnz_capacity=nnz,
+                          getrank_runs=runs, getrank_threshold=tau)
+    cols, vd = lib.coo_to_device(idx0, v0)
+    gpu = lib.Tensor.init_coo(cfg, cols, vd, len(v0), I, J, K0,
+                              (ora.A, ora.B, ora.C, ora.lam))
+    d = ora.update(coo=(yi, yv, Kn), debug=True)
+    bcols, bv = lib.coo_to_device(yi, yv)
+    gpu.update_batch_coo(bcols, bv, len(yv), Kn)
+    torch.cuda.synchronize()
+    return ora, gpu, d
+
+
+@pytest.mark.parametrize("R,R_true,runs,seed", [(4, 2, 2, 44), (6, 3, 1, 45)])
+def test_getrank_coo_summaries(lib, R, R_true, runs, seed):
+    # sparse data of exact low rank (factor columns zero on most rows): the
+    # COO summaries' CP-ALS runs over their entries and their core
+    # consistency is taken slice by slice; FP32 summary arithmetic, so the
+    # FP32 bars of the dense test
+    I, J, K0, Kn, reps = 44, 40, 30, 8, 3
+    ora, gpu, d = _pair_coo(lib, I, J, K0, Kn, R_true, R, reps, 20, 2, seed, runs, 90.0)
+    assert all(r["Rnew"] < R for r in d["reps"])
+    _check(lib, ora, gpu, d, reps, R, runs, K0, 1e-3, 0.5)
+
+
+@pytest.mark.parametrize("tau,expect", [(1e9, 1), (-1e308, 3)])
+def test_getrank_coo_threshold_edges(lib, tau, expect):
+    I, J, K0, Kn, R, reps = 30, 28, 24, 6, 3, 2
+    ora, gpu, d = _pair_coo(lib, I, J, K0, Kn, 2, R, reps, 10, 2, 46, 1, tau)
+    for rho in range(reps):
+        assert d["reps"][rho]["Rnew"] == expect
+        assert int(gpu.last_rep(rho, lib.SBT_REP_RNEW, 1, ncols=1)[0, 0]) == expect
+    A, B, C, lam = gpu.get_factors()
+    assert_close(C[K0:], ora.C[K0:], 1e-3, 1e-3, "new rows of C")

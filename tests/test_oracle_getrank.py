@@ -2,6 +2,7 @@
 
 import numpy as np
 
+import synth
 from oracle import cp
 from oracle import sambaten as osb
 
@@ -56,6 +57,25 @@ def _init(dims, seed):
     return init
 
 
+def test_corcondia_over_entries_equals_the_dense_form():
+    # the core summed nonzero by nonzero is the dense core of the same tensor;
+    # duplicate coordinates add up as the tensor's entry
+    g = np.random.default_rng(9)
+    dims = (7, 6, 5)
+    X = np.where(g.random(dims) < 0.3, g.standard_normal(dims), 0.0)
+    idx = np.argwhere(X != 0.0)
+    vals = X[tuple(idx.T)]
+    for R in (1, 2, 3):
+        F = [g.random((n, R)) for n in dims]
+        lam = g.random(R) + 0.5
+        want = cp.corcondia(X, *F, lam)
+        assert abs(cp.corcondia_coo(idx, vals, dims, *F, lam) - want) < 1e-9 * max(1, abs(want))
+        half = np.concatenate([vals[:1] / 2, vals])
+        idx2 = np.concatenate([idx[:1], idx])
+        half[1] = vals[0] / 2
+        assert abs(cp.corcondia_coo(idx2, half, dims, *F, lam) - want) < 1e-9 * max(1, abs(want))
+
+
 def test_get_rank_finds_the_rank_of_noiseless_data():
     (A, B, C), lam = _model((12, 11, 10), 2, 3)
     Z = cp.reconstruct(A, B, C, lam)
@@ -84,3 +104,39 @@ def test_match_leaves_components_without_partner():
     Ap, Bp, Cp = A[:, [2, 0]], B[:, [2, 0]], C[:, [2, 0]]
     pi = osb.match(A, B, C, Ap, Bp, Cp)[0]
     np.testing.assert_array_equal(pi, [1, -1, 0])
+
+
+def test_get_rank_on_coo_summaries_equals_dense():
+    # the same sparse tensor stored both ways: GetRank on the COO summaries
+    # (CP-ALS over the entries, the core consistency of the tensor they hold)
+    # decides and computes what it does on the dense summaries
+    I, J, K0, Kn, R, reps = 30, 26, 24, 6, 4, 3
+    gen = synth.SparseSupportCP(I, J, K0 + Kn, 2, 61)
+    X = gen.dense(0, K0 + Kn)
+    assert 0.05 < np.count_nonzero(X) / X.size < 0.6
+    g = np.random.default_rng(62)
+    F = [cp.normalize_columns(g.random((n, R)))[0] for n in (I, J, K0)]
+    model = (F[0], F[1], F[2], np.ones(R))
+    out = []
+    for fmt in (osb.DENSE, osb.COO):
+        cfg = osb.Config(rank=R, reps=reps, als_iters=25, sample_factor=2, seed=63,
+                         k_capacity=K0 + Kn, getrank_runs=2, getrank_threshold=90.0)
+        if fmt == osb.DENSE:
+            ora = osb.OracleTensor(cfg, fmt, (I, J, K0), X0=X[:, :, :K0], factors=model)
+            d = ora.update(X[:, :, K0:], debug=True)
+        else:
+            ora = osb.OracleTensor(cfg, fmt, (I, J, K0), coo0=gen.entries(0, K0),
+                                   factors=model)
+            yi, yv = gen.entries(K0, K0 + Kn)
+            d = ora.update(coo=(yi, yv, Kn), debug=True)
+        out.append((ora, d))
+    (od, dd), (oc, dc) = out
+    for rd, rc in zip(dd["reps"], dc["reps"]):
+        for key in ("Is", "Js", "Ks", "pi", "valid"):
+            np.testing.assert_array_equal(rd[key], rc[key])
+        assert rd["Rnew"] == rc["Rnew"]
+        np.testing.assert_allclose(np.array(rc["cc"]), np.array(rd["cc"]), rtol=1e-7, atol=1e-7)
+    # rank-2 data: GetRank keeps fewer than R components
+    assert all(r["Rnew"] < R for r in dd["reps"])
+    for Ud, Uc in zip((od.A, od.B, od.C, od.lam), (oc.A, oc.B, oc.C, oc.lam)):
+        np.testing.assert_allclose(Uc, Ud, rtol=1e-8, atol=1e-10)
