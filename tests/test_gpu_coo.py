@@ -81,6 +81,19 @@ def test_coo_update_matches_oracle(lib):
     assert gpu.shape()[2] == 60
 
 
+def test_coo_ten_updates_track_the_oracle(lib):
+    # Alg. 1 applied ten times over sparse batches: samples, matchings and the
+    # last update's intermediates as above, the whole model at the end
+    reps = 4
+    ora, gpu, ds = run_coo_pair(lib, 60, 50, 30, 5, 10, 3, reps, 12, 2, 73, 4000, 700)
+    check_coo_update(lib, ora, gpu, ds[-1], reps, 30, 30)
+    A, B, C, lam = gpu.get_factors()
+    assert_close(B, ora.B, RT, AT, "B")
+    assert_close(C, ora.C, RT, AT, "C")
+    assert gpu.batch_counter() == 10
+    assert gpu.shape()[2] == 80
+
+
 @pytest.mark.parametrize("I,J,K0,R,nnz0,nnz_b", [
     (80, 70, 40, 20, 6000, 1500),    # rank above 16: 32-float factor rows, 8 lanes per entry
     (60, 50, 40, 3, 50000, 6000),    # about 200 summary entries per row: a wavefront per unit

@@ -117,6 +117,43 @@ def test_fp64_three_batches_ragged_shapes(lib):
     assert abs(gpu.fit() - ora.fit()) < 1e-9
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_twelve_updates_track_the_oracle(lib, prec):
+    # Alg. 1 applied again and again: samples exact at every update, the fit
+    # after every update and the whole model at the end element by element
+    # (FP64 at 1e-8, FP32 at the FP32 bars)
+    torch = _torch()
+    I, J, K0, Kn, R, reps, nb = 40, 36, 30, 5, 4, 4, 12
+    dtype = np.float64 if prec == lib.SBT_P_F64 else np.float32
+    gen = synth.DenseCP(I, J, K0 + nb * Kn, R, seed=71, noise=0.01, dtype=dtype)
+    X = gen.slices(0, K0 + nb * Kn)
+    ocfg = osb.Config(rank=R, reps=reps, als_iters=12, sample_factor=2, seed=71,
+                      k_capacity=K0 + nb * Kn)
+    ora = osb.OracleTensor(ocfg, osb.DENSE, (I, J, K0), X0=X[:, :, :K0],
+                           factors=gen.true_model_prefix(K0))
+    cfg = lib.make_config(R, reps, 12, 2, 71, precision=prec, k_capacity=K0 + nb * Kn,
+                          max_batch=Kn)
+    gpu = lib.Tensor.init_dense(cfg, lib.dense_to_device(X[:, :, :K0], dtype), I, J, K0,
+                                factors=(ora.A, ora.B, ora.C, ora.lam))
+    ftol = 1e-9 if prec == lib.SBT_P_F64 else 1e-3
+    for b in range(nb):
+        Y = X[:, :, K0 + b * Kn:K0 + (b + 1) * Kn]
+        d = ora.update(Y, debug=True)
+        gpu.update_batch_dense(lib.dense_to_device(Y, dtype), Kn)
+        torch.cuda.synchronize()
+        check_samples(gpu, d, reps)
+        assert abs(gpu.fit() - ora.fit()) < ftol, (b, gpu.fit(), ora.fit())
+    A, B, C, lam = gpu.get_factors()
+    if prec == lib.SBT_P_F64:
+        for got, want in ((A, ora.A), (B, ora.B), (C, ora.C)):
+            np.testing.assert_allclose(got, want, rtol=1e-8, atol=1e-10)
+        np.testing.assert_allclose(lam, ora.lam, rtol=1e-8)
+    else:
+        for got, want, name in ((A, ora.A, "A"), (B, ora.B, "B"), (C, ora.C, "C")):
+            assert_close(got, want, RT, AT, name)
+    assert gpu.batch_counter() == nb
+
+
 def test_fp32_update_matches_oracle(lib):
     # FP32 store and MTTKRP, FP64 solves; ten repetitions as in the 500^3 workload
     reps = 10
