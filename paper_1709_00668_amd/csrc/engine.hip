@@ -720,11 +720,29 @@ sbt_status gram_rows(sbt_tensor* t, const RepSet& rs, const double* U, int64_t s
   return SBT_OK;
 }
 
+// Partial Gram matrices of a row kernel (one per block of rows) go to the
+// cross-product workspace, one slab of this many elements per repetition.
+int64_t gram_part_stride(const sbt_tensor* t) { return (int64_t)9 * t->xnblk * t->R * t->R; }
+
+// The buffer for the partial Gram matrices of `rows` rows, when the tail
+// would otherwise take the chunked cross products and they fit the workspace.
+double* gram_parts_buf(sbt_tensor* t, const RepSet& rs, int rows) {
+  if (tail_rows_fit(rows / 2, rs.R)) return nullptr;
+  const int64_t mats = gram_part_stride(t) / ((int64_t)t->R * t->R);
+  const int64_t need = (int64_t)(rs.rep0 + rs.nrep - 1) * mats + gram_parts(rows);
+  return need <= t->xpart_mats ? t->xpart : nullptr;
+}
+
 // the tail of a mode update; the tail kernel takes the factor's rows in
 // chunks of its staging buffer (one block per repetition), and factors longer
-// than two chunks get their Gram matrix from the chunked cross products
-// (many blocks) beforehand
-sbt_status tail(sbt_tensor* t, const RepSet& rs, AlsTail ta, hipStream_t st) {
+// than two chunks get their Gram matrix from the partial ones the row kernel
+// wrote (parts), or else from the chunked cross products (many blocks)
+sbt_status tail(sbt_tensor* t, const RepSet& rs, AlsTail ta, hipStream_t st,
+                const double* parts = nullptr) {
+  if (parts) {
+    SBT_CK(launch_tail_parts(rs, ta, parts, gram_part_stride(t), gram_parts(ta.rows), st));
+    return SBT_OK;
+  }
   if (!tail_rows_fit(ta.rows / 2, rs.R)) {
     SBT_TRY(gram_rows(t, rs, ta.U, ta.sU, ta.rows, t->xout, st));
     ta.Gin = t->xout;
@@ -1088,32 +1106,39 @@ sbt_status run_als(sbt_tensor* t, const void* Zp, RepSet rs, double* Ap, double*
       SBT_CK(launch_pw(prec, rs, Zp, Cp, ilC, W, st));
       prof_end(t, pq, SBT_K_MTTKRP_C, pw_bytes, st);
     }
-    // mode 1: A
-    SBT_CK(launch_cw(prec, rs, 0, W, Bp, ilB, Vinv, Ap, rs.sA, st));
+    // mode 1: A (long factors: with the partial Gram matrices of its row blocks)
+    const int64_t sgp = gram_part_stride(t);
+    double* gpa = gram_parts_buf(t, rs, rs.n1);
+    SBT_CK(launch_cw(prec, rs, 0, W, Bp, ilB, Vinv, Ap, rs.sA, st, nullptr, gpa, sgp));
     ta.U = Ap; ta.sU = rs.sA; ta.rows = rs.n1; ta.Gout = GA; ta.invlam_out = ilA;
     ta.lam_out = nullptr; ta.Gx = GA; ta.Gy = GC; ta.Vinv_out = Vinv;
     // mode 2: B, with the tail of mode 1 folded into its launch when A's rows
     // fit the tail's staging
     const bool fold = tail_rows_fit(rs.n1, R);
-    if (!fold) SBT_TRY(tail(t, rs, ta, st));
-    SBT_CK(launch_cw(prec, rs, 1, W, Ap, ilA, Vinv, Bp, rs.sB, st, fold ? &ta : nullptr));
+    if (!fold) SBT_TRY(tail(t, rs, ta, st, gpa));
+    double* gpb = gram_parts_buf(t, rs, rs.n2);
+    SBT_CK(launch_cw(prec, rs, 1, W, Ap, ilA, Vinv, Bp, rs.sB, st, fold ? &ta : nullptr, gpb,
+                     sgp));
     ta.U = Bp; ta.sU = rs.sB; ta.rows = rs.n2; ta.Gout = GB; ta.invlam_out = ilB;
     ta.lam_out = nullptr; ta.Gx = GA; ta.Gy = GB; ta.Vinv_out = Vinv;
-    SBT_TRY(tail(t, rs, ta, st));
+    SBT_TRY(tail(t, rs, ta, st, gpb));
     // mode 3: C (lambda' = its column norms)
     pq = prof_kernel(t);
+    double* gpc = nullptr;
     if (mf) {
       SBT_CK(launch_p3_mfma(rs, t->ml, ns3, t->Zk, Ap, ilA, Bp, ilB, t->P3, t->sP3, t->mops,
                             st));
       prof_end(t, pq, SBT_K_MTTKRP_AB, p3m_bytes, st);
-      SBT_CK(launch_mode3_finish(rs, ns3, t->P3, t->sP3, Vinv, nullptr, Cp, rs.sC, st));
+      gpc = gram_parts_buf(t, rs, rs.n3);
+      SBT_CK(launch_mode3_finish(rs, ns3, t->P3, t->sP3, Vinv, nullptr, Cp, rs.sC, st, gpc,
+                                 sgp));
     } else {
       SBT_CK(launch_p3(prec, rs, false, Zp, Ap, ilA, Bp, ilB, Vinv, nullptr, Cp, rs.sC, st));
       prof_end(t, pq, SBT_K_MTTKRP_AB, p2_bytes, st);
     }
     ta.U = Cp; ta.sU = rs.sC; ta.rows = rs.n3; ta.Gout = GC; ta.invlam_out = ilC;
     ta.lam_out = lam_out; ta.Gx = GB; ta.Gy = GC; ta.Vinv_out = Vinv;
-    SBT_TRY(tail(t, rs, ta, st));
+    SBT_TRY(tail(t, rs, ta, st, gpc));
   }
     return SBT_OK;
   };

@@ -60,6 +60,7 @@ __device__ inline void ldv(const uint16_t* p, float (&o)[2]) {
 __device__ inline void ldv(const uint16_t* p, float (&o)[1]) { o[0] = bf16_to_f32(*p); }
 
 constexpr int ku_of(int V) { return 32 / V; }  // summary elements in flight per thread
+constexpr int kTailParts = 16;                 // partial Gram loads in flight per thread
 constexpr int kTailBuf = 2304;                  // doubles; >= 2 x 32 x 33 (Jacobi scratch)
 constexpr int kLd = kMaxRank + 1;
 
@@ -103,6 +104,9 @@ struct TailSmem {
 // Step outputs of one mode update (per repetition strides in elements).
 struct TailArgs {
   const double* Gin;    // raw Gram of U given (stride sG), or null: computed here
+  const double* Gparts; // or the partial Gram matrices of U's row blocks, summed here in
+  int64_t sGparts;      // block order ([rep][part][R x R], stride sGparts per repetition)
+  int nparts;
   double* U;            // raw rows of the new factor
   int64_t sU;
   int rows;
@@ -245,7 +249,7 @@ __device__ void als_tail(const TailArgs& t, int rep, int R, TailSmem& s, bool wr
   for (int j = 0; j < 3; ++j)
 #pragma unroll
     for (int u = 0; u < 4; ++u) gacc[j][u] = 0.0;
-  for (int r0 = 0; r0 < (t.Gin ? 0 : rows); r0 += crows) {
+  for (int r0 = 0; r0 < ((t.Gin || t.Gparts) ? 0 : rows); r0 += crows) {
     const int cn = rows - r0 < crows ? rows - r0 : crows;
     const int n = cn * R;
     const double* src = U + (int64_t)r0 * R;
@@ -279,6 +283,37 @@ __device__ void als_tail(const TailArgs& t, int rep, int R, TailSmem& s, bool wr
   // combine -> Gram of the raw factor in s.V
   if (t.Gin) {
     for (int q = tid; q < R * R; q += kTailThreads) s.V[q / R][q % R] = t.Gin[rep * t.sG + q];
+  } else if (t.Gparts) {
+    // kTailParts loads in flight per thread: part b goes to partial sum
+    // b mod kTailParts, and the partial sums are added in a fixed tree
+    // (the parts are symmetric: the upper triangle is summed and mirrored)
+    const double* gp = t.Gparts + rep * t.sGparts;
+    const int RR = R * R;
+    for (int p = tid; p < P; p += kTailThreads) {
+      int f, g;
+      pair_of(p, R, f, g);
+      const int q = f * R + g;
+      double a[kTailParts];
+#pragma unroll
+      for (int u = 0; u < kTailParts; ++u) a[u] = 0.0;
+      int b = 0;
+      for (; b + kTailParts <= t.nparts; b += kTailParts) {
+        double v[kTailParts];
+#pragma unroll
+        for (int u = 0; u < kTailParts; ++u) v[u] = gp[(int64_t)(b + u) * RR + q];
+#pragma unroll
+        for (int u = 0; u < kTailParts; ++u) a[u] += v[u];
+      }
+#pragma unroll
+      for (int u = 0; u < kTailParts; ++u)
+        if (b + u < t.nparts) a[u] += gp[(int64_t)(b + u) * RR + q];
+#pragma unroll
+      for (int w = kTailParts / 2; w > 0; w /= 2)
+#pragma unroll
+        for (int u = 0; u < w; ++u) a[u] += a[u + w];
+      s.V[f][g] = a[0];
+      s.V[g][f] = a[0];
+    }
   } else if (P <= kTailThreads) {
     s.red[tid] = (gacc[0][0] + gacc[0][1]) + (gacc[0][2] + gacc[0][3]);
     __syncthreads();
@@ -438,6 +473,19 @@ __global__ __launch_bounds__(256) void pw_kernel(RepSet rs, const TZ* Z, const d
 // The contracted factor is staged in LDS in chunks of chr rows (one chunk when
 // it fits); each thread's first W loads of a chunk go out before its staging.
 constexpr int kRowsPerBlock = 8;   // factor rows produced by one block
+
+// out(f, g) = sum over the kRowsPerBlock rows r of U(r, f) U(r, g), rows in
+// order (rows past the factor's end hold zeros); both triangles are written
+// and are equal, since each product is formed the same way either side.
+__device__ inline void block_gram_part(const double (*U)[kMaxRank], int R, double* out) {
+  for (int q = threadIdx.x; q < R * R; q += blockDim.x) {
+    const int f = q / R, g = q % R;
+    double acc = 0.0;
+#pragma unroll
+    for (int r = 0; r < kRowsPerBlock; ++r) acc += U[r][f] * U[r][g];
+    out[q] = acc;
+  }
+}
 constexpr int kSlots = 32;         // chunk rows are a multiple of this
 constexpr int kCwPre = 8;          // W vector loads in flight per thread
 
@@ -461,10 +509,11 @@ template <typename TA, int RP, int V>
 __global__ __launch_bounds__(256) void cw_kernel(RepSet rs, int mode, int chr, const TA* W,
                                                 const double* F, const double* invlamF,
                                                 const double* Vinv, double* Uout, int64_t sU,
-                                                TailArgs pro) {
+                                                TailArgs pro, double* gpart, int64_t sGpart) {
   extern __shared__ __align__(16) unsigned char cw_smem[];
   __shared__ TA red[256 * V];
   __shared__ double Mrow[kRowsPerBlock][kMaxRank];
+  __shared__ double Urow[kRowsPerBlock][kMaxRank];
   __shared__ double Vi[kMaxRank][kLd];
   __shared__ double ilp[kMaxRank];
   TA* Fs = reinterpret_cast<TA*>(cw_smem);  // [chr][RP]
@@ -572,11 +621,17 @@ __global__ __launch_bounds__(256) void cw_kernel(RepSet rs, int mode, int chr, c
   for (int q = tid; q < kRowsPerBlock * R; q += 256) {
     const int r = q / R, f = q % R;
     const int gr = blockIdx.x * kRowsPerBlock + r;
+    double u = 0.0;
     if (gr < nrows) {
-      double u = 0.0;
       for (int k = 0; k < R; ++k) u += Mrow[r][k] * Vi[k][f];
       U[(int64_t)gr * R + f] = u;
     }
+    Urow[r][f] = u;
+  }
+  if (gpart) {
+    // the Gram matrix of this block's rows, summed over the blocks by the tail
+    __syncthreads();
+    block_gram_part(Urow, R, gpart + rep * sGpart + (int64_t)blockIdx.x * R * R);
   }
 }
 
@@ -783,8 +838,16 @@ hipError_t launch_normalize(const RepSet& rs, double* Ap, double* Bp, double* Cp
 bool tail_rows_fit(int rows, int R) { return (int64_t)rows * R <= kTailBuf; }
 
 hipError_t launch_tail(const RepSet& rs, const AlsTail& t, hipStream_t s) {
-  TailArgs ta{t.Gin, t.U, t.sU, t.rows, t.Gout, t.invlam_out, t.lam_out, t.Gx, t.Gy,
-              t.Vinv_out, t.sG, t.pinv_count};
+  return launch_tail_parts(rs, t, nullptr, 0, 0, s);
+}
+
+int gram_parts(int rows) { return (rows + kRowsPerBlock - 1) / kRowsPerBlock; }
+
+hipError_t launch_tail_parts(const RepSet& rs, const AlsTail& t, const double* parts,
+                             int64_t sParts, int nparts, hipStream_t s) {
+  if (parts && (t.Gin || nparts < 1)) return hipErrorInvalidValue;
+  TailArgs ta{t.Gin, parts, sParts, nparts, t.U, t.sU, t.rows, t.Gout, t.invlam_out,
+              t.lam_out, t.Gx, t.Gy, t.Vinv_out, t.sG, t.pinv_count};
   SBT_RP_SWITCH(rs.R, { tail_kernel<RP><<<rs.nrep, kTailThreads, 0, s>>>(rs, ta); });
   return hipGetLastError();
 }
@@ -809,13 +872,13 @@ hipError_t launch_pw(int prec, const RepSet& rs, const void* Z, const double* Cf
 
 hipError_t launch_cw(int prec, const RepSet& rs, int mode, const void* W, const double* F,
                      const double* invlamF, const double* Vinv, double* U, int64_t sU,
-                     hipStream_t s, const AlsTail* before) {
+                     hipStream_t s, const AlsTail* before, double* gpart, int64_t sGpart) {
   TailArgs pro{};
   if (before) {
     if (before->Gin || !tail_rows_fit(before->rows, rs.R)) return hipErrorInvalidValue;
-    pro = TailArgs{nullptr, before->U, before->sU, before->rows, before->Gout,
-                   before->invlam_out, before->lam_out, before->Gx, before->Gy,
-                   before->Vinv_out, before->sG, before->pinv_count};
+    pro = TailArgs{nullptr, nullptr, 0, 0, before->U, before->sU, before->rows,
+                   before->Gout, before->invlam_out, before->lam_out, before->Gx,
+                   before->Gy, before->Vinv_out, before->sG, before->pinv_count};
   }
   const int nrows = mode == 0 ? rs.n1 : rs.n2;
   const int ncon = mode == 0 ? rs.n2 : rs.n1;
@@ -832,7 +895,7 @@ hipError_t launch_cw(int prec, const RepSet& rs, int mode, const void* W, const 
                               : (rs.R % 4 == 0 ? 4 : (rs.R % 2 == 0 ? 2 : 1));
 #define SBT_CW(TA_, RPV, VV)                                                                    \
   cw_kernel<TA_, RPV, VV><<<grid, 256, sh, s>>>(rs, mode, chr, (const TA_*)W, F, invlamF, Vinv, \
-                                                U, sU, pro)
+                                                U, sU, pro, gpart, sGpart)
   SBT_RP_SWITCH(rs.R, {
     if (prec == kF64) {
       if (vw == 2) SBT_CW(double, RP, 2); else SBT_CW(double, RP, 1);

@@ -472,8 +472,10 @@ __global__ __launch_bounds__(256) void mode3_finish_kernel(RepSet rs, int nsplit
                                                           const float* P, int64_t sP,
                                                           const double* Vinv,
                                                           const double* lam_div, double* Uout,
-                                                          int64_t sU) {
+                                                          int64_t sU, double* gpart,
+                                                          int64_t sGpart) {
   __shared__ double M[8][kMaxRank];
+  __shared__ double Ub[8][kMaxRank];
   __shared__ double Vi[kMaxRank][kMaxRank + 1];
   const int rep = rs.rep0 + blockIdx.y;
   const int R = rs.R;
@@ -488,14 +490,28 @@ __global__ __launch_bounds__(256) void mode3_finish_kernel(RepSet rs, int nsplit
     M[r][f] = m;
   }
   __syncthreads();
+  double u = 0.0;
   if (c < rs.n3 && f < R) {
-    double u = 0.0;
     for (int k = 0; k < R; ++k) u += M[r][k] * Vi[k][f];
     if (lam_div) {
       const double l = lam_div[f];
       u = l > 0.0 ? u / l : 0.0;
     }
     Uout[rep * sU + (int64_t)c * R + f] = u;
+  }
+  if (gpart) {
+    // the Gram matrix of the block's eight rows (rows past n3 are zero), in
+    // row order, both triangles
+    Ub[r][f] = u;
+    __syncthreads();
+    double* out = gpart + rep * sGpart + (int64_t)blockIdx.x * R * R;
+    for (int q = tid; q < R * R; q += 256) {
+      const int a = q / R, b = q % R;
+      double acc = 0.0;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) acc += Ub[i][a] * Ub[i][b];
+      out[q] = acc;
+    }
   }
 }
 
@@ -649,10 +665,12 @@ hipError_t launch_p3_mfma(const RepSet& rs, const MfmaLayout& L, int nsplit, con
 
 hipError_t launch_mode3_finish(const RepSet& rs, int nsplit, const float* P, int64_t sP,
                                const double* Vinv, const double* lam_div, double* U, int64_t sU,
-                               hipStream_t s) {
+                               hipStream_t s, double* gpart, int64_t sGpart) {
+  // eight rows per block: gram_parts(rows) blocks when gpart is given
+  if (gpart && gram_parts(8) != 1) return hipErrorInvalidValue;
   dim3 grid((unsigned)((rs.n3 + 7) / 8), (unsigned)rs.nrep);
   mode3_finish_kernel<<<grid, 256, 0, s>>>(rs, nsplit, 16 * ntiles(rs.R), P, sP, Vinv, lam_div,
-                                           U, sU);
+                                           U, sU, gpart, sGpart);
   return hipGetLastError();
 }
 

@@ -307,7 +307,13 @@ __global__ __launch_bounds__(256) void sort_nd_kernel(NdFactors F, int N, int R,
 // with kP1sLoads summary loads in flight, over C rows staged in LDS.  The
 // wavefronts' rows add up in LDS in wavefront order; with S > 1 each range
 // writes a partial W that a second kernel sums in range order.
+// The row tiles of one (range, repetition) go to one XCD: workgroup b runs
+// on XCD b mod 8, and the (tile, range, repetition) triples are dealt to the
+// XCDs in contiguous runs.  A view's rows of one q start wherever n12 q puts
+// them, so two neighbouring tiles share a 128-byte line at their boundary;
+// with both tiles on one XCD that line comes from HBM once, into one L2.
 constexpr int kP1sLoads = 4;
+constexpr int kP1sXcds = 8;
 constexpr int kP1sMaxRows = 128;  // C rows one block stages
 
 template <typename TZ> struct AccNd { using type = float; };
@@ -330,17 +336,23 @@ template <int V> __device__ inline void acc_of(const uint16_t* p, float (&z)[V])
 template <typename TZ, int RP, int V>
 __global__ __launch_bounds__(256) void p1s_kernel(RepSet rs, const TZ* Z, const double* Cf, int S,
                                                  typename AccNd<TZ>::type* Wp, int64_t sWp,
-                                                 NdFactors F, int c0, int N) {
+                                                 NdFactors F, int c0, int N, int tiles) {
   using TA = typename AccNd<TZ>::type;
   __shared__ TA Cs[kP1sMaxRows][RP];
   __shared__ TA red[64 * V][RP + 1];
-  const int rep = rs.rep0 + blockIdx.z, sp = blockIdx.y;
+  const int64_t total = (int64_t)tiles * S * rs.nrep;
+  const int64_t per = (total + kP1sXcds - 1) / kP1sXcds;
+  const int64_t lin = (int64_t)(blockIdx.x % kP1sXcds) * per + blockIdx.x / kP1sXcds;
+  if (lin >= total) return;  // the whole block: no barrier has been reached
+  const int tile = (int)(lin % tiles);
+  const int sp = (int)((lin / tiles) % S);
+  const int rep = rs.rep0 + (int)(lin / ((int64_t)tiles * S));
   const int R = rs.R, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t n12 = (int64_t)rs.n1 * rs.n2;
   const int Q = rs.n3;
   const int qs = (int)((int64_t)sp * Q / S), qe = (int)((int64_t)(sp + 1) * Q / S);
   const int L = qe - qs;  // <= kP1sMaxRows (host-chosen S)
-  const int64_t e = ((int64_t)blockIdx.x * 64 + lane) * V;  // first of the lane's V rows
+  const int64_t e = ((int64_t)tile * 64 + lane) * V;  // first of the lane's V rows
   const bool ok = e < n12;  // (V = 2 only when n12 is even)
   if (c0 < 0) {
     const double* C = Cf + rep * rs.sC + (int64_t)qs * R;
@@ -476,23 +488,26 @@ hipError_t launch_p1s(int prec, const RepSet& rs, const void* Z, const double* C
   if (S > 1 && sWp < (int64_t)S * n12 * rs.R) return hipErrorInvalidValue;
   // BF16 summaries: two rows per lane when every lane's pair is 4-byte aligned
   const bool pair = prec != kF64 && prec != kF32 && n12 % 2 == 0 && rs.sZ % 2 == 0;
-  dim3 grid((unsigned)((n12 + (pair ? 127 : 63)) / (pair ? 128 : 64)), (unsigned)S,
-            (unsigned)rs.nrep);
+  const int tiles = (int)((n12 + (pair ? 127 : 63)) / (pair ? 128 : 64));
+  const int64_t total = (int64_t)tiles * S * rs.nrep;
+  const int64_t nblk = kP1sXcds * ((total + kP1sXcds - 1) / kP1sXcds);
+  if (nblk > INT32_MAX) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)nblk);
   switch ((rs.R + 3) / 4 * 4) {
 #define SBT_P1S(RPV)                                                                          \
   case RPV:                                                                                   \
     if (prec == kF64)                                                                         \
       timed_launch(p1s_kernel<double, RPV, 1>, grid, dim3(256), 0, s, rs, (const double*)Z,  \
-                   Cf, S, (double*)out, so, F, kc0, N);                                       \
+                   Cf, S, (double*)out, so, F, kc0, N, tiles);                                \
     else if (prec == kF32)                                                                    \
       timed_launch(p1s_kernel<float, RPV, 1>, grid, dim3(256), 0, s, rs, (const float*)Z, Cf,\
-                   S, (float*)out, so, F, kc0, N);                                            \
+                   S, (float*)out, so, F, kc0, N, tiles);                                     \
     else if (pair)                                                                            \
       timed_launch(p1s_kernel<uint16_t, RPV, 2>, grid, dim3(256), 0, s, rs,                   \
-                   (const uint16_t*)Z, Cf, S, (float*)out, so, F, kc0, N);                    \
+                   (const uint16_t*)Z, Cf, S, (float*)out, so, F, kc0, N, tiles);             \
     else                                                                                      \
       timed_launch(p1s_kernel<uint16_t, RPV, 1>, grid, dim3(256), 0, s, rs,                   \
-                   (const uint16_t*)Z, Cf, S, (float*)out, so, F, kc0, N);                    \
+                   (const uint16_t*)Z, Cf, S, (float*)out, so, F, kc0, N, tiles);             \
     break;
     SBT_P1S(4) SBT_P1S(8) SBT_P1S(12) SBT_P1S(16) SBT_P1S(20) SBT_P1S(24) SBT_P1S(28)
     SBT_P1S(32)

@@ -147,9 +147,10 @@ hipError_t launch_p3_mfma(const RepSet& rs, const MfmaLayout& L, int nsplit, con
                           const double* invlamB, float* P, int64_t sP, float* ops,
                           hipStream_t s);
 // U(c, :) = (sum_split P) V^-1 [/ lam_div]
+// gpart: also the Gram matrix of each block's rows, as launch_cw writes them
 hipError_t launch_mode3_finish(const RepSet& rs, int nsplit, const float* P, int64_t sP,
                                const double* Vinv, const double* lam_div, double* U, int64_t sU,
-                               hipStream_t s);
+                               hipStream_t s, double* gpart = nullptr, int64_t sGpart = 0);
 
 // ---- CP-ALS on the summaries --------------------------------------------
 // B', C' <- U[0,1) from Philox counters (row, col0 + col, tag(stream, mode, rep), t)
@@ -215,9 +216,12 @@ hipError_t launch_pw(int prec, const RepSet& rs, const void* Z, const double* Cf
 // staging, Gin unused), folded into this launch: every block computes it,
 // the first block of each repetition stores its outputs, and this step's
 // V^-1 and F's 1/lambda come from it instead of Vinv and invlamF.
+// gpart: also the Gram matrix of each block's rows, [rep][block][R x R] at
+// stride sGpart per repetition (gram_parts(rows) blocks), for launch_tail_parts.
 hipError_t launch_cw(int prec, const RepSet& rs, int mode, const void* W, const double* F,
                      const double* invlamF, const double* Vinv, double* U, int64_t sU,
-                     hipStream_t s, const AlsTail* before = nullptr);
+                     hipStream_t s, const AlsTail* before = nullptr, double* gpart = nullptr,
+                     int64_t sGpart = 0);
 // whether launch_p3 can stage both factors of an n1 x n2 slice in LDS
 bool p3_fits(int prec, int n1, int n2, int R);
 // C rows = (Z_(3) (B~ kr A~)) V^-1, or with row_solve those rows / lam_div
@@ -227,6 +231,12 @@ hipError_t launch_p3(int prec, const RepSet& rs, bool row_solve, const void* Z, 
                      hipStream_t s);
 // tail of a mode update: Gram, lambda, normalised Gram, next V^-1
 hipError_t launch_tail(const RepSet& rs, const AlsTail& t, hipStream_t s);
+// the same with the Gram matrix summed from the partial ones of the kernel
+// that wrote the rows (nparts of them, in block order, t.Gin null)
+hipError_t launch_tail_parts(const RepSet& rs, const AlsTail& t, const double* parts,
+                             int64_t sParts, int nparts, hipStream_t s);
+// row blocks of the kernels that write partial Gram matrices
+int gram_parts(int rows);
 
 // ---- cross products X^T Y (R x R) over many rows ------------------------------
 struct XJob {
