@@ -27,6 +27,10 @@ before timing, the model starting from the generator's factors):
               rank-10 U[0,1) CP model plus 1% noise, batches of 12 slices; s = 4
               on every mode, r = 10, 30 ALS sweeps.  `value` is the FP32 path; the
               FP64 path beside it; recompute: CP-ALS of the whole grown tensor.
+  coo4d       order-4 COO 500 x 500 x 500 x 100 with 1e7 nonzeros (Zipf 1.1
+              popularity over every leading mode, rank-10 nonnegative model),
+              batches of 10 slices with 1e6 nonzeros, s = 4 per mode, r = 10,
+              30 sweeps, from the model of the GPU's initial CP-ALS.
   sparse100k  COO 100000^3 with about 1e8 nonzeros (Zipf 1.1 popularity,
               rank-10 nonnegative model), batches of 1000 slices with about
               1e6 nonzeros, s = 10, r = 10, 30 sweeps.
@@ -109,6 +113,11 @@ WORKLOADS = {
                     seed=6, noise=0.01,
                     desc="dense FP32 order-4 120x120x120x120 + 12-slice batches along the last "
                          "mode, rank 10, s=4 per mode, r=10, 30 ALS sweeps"),
+    "coo4d": dict(kind="nd_coo", dims=(500, 500, 500), K0=100, Kn=10, R=10, s=4, r=10,
+                  iters=30, seed=9, nnz0=10_000_000, nnz_b=1_000_000,
+                  desc="sparse COO order-4 500x500x500x100 with 1e7 nonzeros (Zipf 1.1 "
+                       "popularity per leading mode) + 10-slice batches of 1e6, rank 10, s=4 "
+                       "per mode, r=10, 30 ALS sweeps, fitted initial model"),
     "sparse100k": dict(kind="coo", I=100000, J=100000, K0=100000, Kn=1000, R=10, s=10,
                        r=10, iters=30, seed=3, nnz0=100_000_000, nnz_b=1_000_000,
                        desc="sparse COO 100000^3 with 1e8 nonzeros + 1000-slice batches of "
@@ -732,6 +741,87 @@ def bench_nd(args, sbt, torch, synth, log):
     return line
 
 
+def bench_nd_coo(args, sbt, torch, synth, log):
+    """Order-N COO tensors: the update of the N-mode COO path (FP32 values, FP64
+    arithmetic) from a model fitted by its own initial CP-ALS on the GPU."""
+    name = args.workload
+    w = WORKLOADS[name]
+    steps = args.steps
+    dims, K0, Kn, R = tuple(w["dims"]), w["K0"], w["Kn"], w["R"]
+    K = K0 + steps * Kn
+    t0 = time.perf_counter()
+    gen = synth.SparseCPN(dims + (K,), R, seed=w["seed"])
+    c0, v0 = gen.slices(0, K0, w["nnz0"], 0)
+    batches = [gen.slices(K0 + b * Kn, K0 + (b + 1) * Kn, w["nnz_b"], b + 1)
+               for b in range(steps)]
+
+    def to_dev(cols, v):
+        return [torch.from_numpy(c).cuda() for c in cols], torch.from_numpy(v).cuda()
+
+    d0 = to_dev(c0, v0)
+    bdev = [to_dev(c, v) for c, v in batches]
+    nnz_total = len(v0) + sum(len(v) for _, v in batches)
+    log(f"# data ready: {len(v0)} + {steps} x ~{w['nnz_b']} nonzeros "
+        f"({time.perf_counter() - t0:.1f} s)")
+    cfg = sbt.make_config(R, w["r"], w["iters"], 1, w["seed"], fmt=sbt.SBT_COO,
+                          precision=sbt.SBT_P_F32, k_capacity=K, max_batch=Kn,
+                          nnz_capacity=nnz_total, init_iters=max(1, args.coo_init_iters))
+    # the initial decomposition: CP-ALS of the initial block on the GPU, run once
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    T0 = sbt.TensorN.init_coo_nd(cfg, d0[0], d0[1], dims + (K0,), w["s"])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    Us, lam = T0.get_factors_nd()
+    init = {"fit": round(T0.fit(), 6), "seconds": round(dt, 3), "als_sweeps": cfg.init_iters}
+    T0.close()
+    log(f"# initial CP-ALS of {len(v0)} nonzeros: fit {init['fit']:.6f} in {dt:.2f} s")
+
+    def fresh():
+        return sbt.TensorN.init_coo_nd(cfg, d0[0], d0[1], dims + (K0,), w["s"], factors=Us,
+                                       lam=lam)
+
+    def apply_batch(T, b):
+        T.update_batch_coo_nd(bdev[b][0], bdev[b][1], Kn)
+
+    res = timed_sequence(sbt, torch, fresh, apply_batch, steps, args.warmup, args.latency_runs,
+                         Kn)
+    log(f"# nd coo: {res['slices_per_s']:.1f} slices/s, fit {res['fit']:.6f}")
+    cfgl = {"workload": w["desc"], "dims": list(dims), "K0": K0, "batch": Kn, "rank": R,
+            "s": w["s"], "r": w["r"], "als_iters": w["iters"], "nnz0": len(v0),
+            "nnz_batch": w["nnz_b"]}
+    line = {
+        "metric": "updated slices/sec (p50/p99 update latency)",
+        "value": round(res["slices_per_s"], 2), "unit": "slices/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(res["ms_per_step"], 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic", "config": cfgl, "p50_ms": round(res["p50_ms"], 3),
+        "p99_ms": round(res["p99_ms"], 3), "latency_samples": res["latency_samples"],
+        "fit": round(res["fit"], 6), "initial_cp_als": init,
+    }
+    prof = res["profile"]
+    kinds = {k: v for k, v in prof.items() if k != "update" and v["launches"]}
+    dom = max(kinds, key=lambda k: kinds[k]["total_ms"])
+    d = kinds[dom]
+    avg_ms = d["total_ms"] / d["launches"]
+    by = d["alg_bytes"] / d["launches"]
+    kname = {"coo_mttkrp": "mttkrp_coo_nd_kernel", "gather": "summary_emit_nd_kernel"}.get(dom,
+                                                                                           dom)
+    line["roofline"] = dict(bound="hbm", kernel=kname, step=dom,
+                            achieved=round(by / (avg_ms * 1e-3) / 1e9, 1), peak=HBM_PEAK_GBS,
+                            unit="GB/s", frac=round(by / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                            traffic=committed_traffic(kname, f"{name}@steps{steps}w{args.warmup}"),
+                            avg_launch_us=round(avg_ms * 1e3, 2), alg_bytes_per_launch=int(by),
+                            timed_every=PROF_EVERY,
+                            share_of_update_time=round(PROF_EVERY * d["total_ms"] /
+                                                       prof["update"]["total_ms"], 3))
+    # the N-mode oracle works on dense arrays: a tensor of 1.25e10 entries per
+    # hundred slices is out of its reach
+    line["cpu_baseline"] = None
+    line["kernels"] = kernels_table(prof)
+    return line
+
+
 def bench_sparse(args, sbt, torch, synth, log):
     name = args.workload
     w = dict(WORKLOADS[name])
@@ -1081,6 +1171,8 @@ def main():
         line = bench_sparse(args, sbt, torch, synth, log)
     elif WORKLOADS[args.workload]["kind"] == "nd":
         line = bench_nd(args, sbt, torch, synth, log)
+    elif WORKLOADS[args.workload]["kind"] == "nd_coo":
+        line = bench_nd_coo(args, sbt, torch, synth, log)
     elif WORKLOADS[args.workload]["kind"] == "serve":
         line = bench_serve(args, sbt, torch, synth, log)
     elif WORKLOADS[args.workload]["kind"] == "getrank":

@@ -139,31 +139,83 @@ __global__ void mode_keys_kernel(CooSumNd z, int64_t total, int m, uint32_t* key
     key[p] = ((uint32_t)(z.rep ? z.rep[p] : 0) << 24) | (uint32_t)z.idx[m][p];
 }
 
-// M(rep, row, f) = sum over the row's entries (in their sorted order) of
-// v * prod over the other modes l of U_l(coordinate l, f).  One wavefront
-// per (rep, row): lane f of each half-wavefront, the halves taking every
-// other entry; the halves add up in a fixed order.  R <= 32.
-__global__ __launch_bounds__(256) void mttkrp_coo_nd_kernel(MttkrpCooNd a) {
-  const int lane = threadIdx.x & 63, half = lane >> 5, f = lane & 31;
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+// M(rep, row, f) = sum over the row's entries of v * prod over the other
+// modes l of U_l(coordinate l, f).  A row's entries are cut into S equal
+// ranges (S from the launch shape alone, so that few long rows of skewed
+// data still spread over many wavefronts); one wavefront per (rep, row,
+// range), a lane per entry: lane i takes entries i, i + 64, ... of the range
+// (two per step, so that the gathers of both are in flight together) and
+// keeps the RP sums of its entries in registers; the lanes' sums are added
+// by a fixed butterfly.  With S = 1 the wavefront writes M's row, else its
+// partial row, and the ranges' partial rows are added in range order.
+template <int RP>
+__global__ __launch_bounds__(256) void mttkrp_coo_nd_kernel(MttkrpCooNd a, int S,
+                                                           double* part) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wv = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int rep = a.rep0 + blockIdx.y;
-  if (row >= a.rows) return;
+  if (wv >= (int64_t)a.rows * S) return;  // a whole wavefront; no block barrier follows
+  const int row = (int)(wv / S), sl = (int)(wv % S);
+  const int R = a.R;
   const int64_t* off = a.off + (int64_t)rep * (a.rows + 1);
-  const int64_t p0 = off[row], p1 = off[row + 1];
-  double acc = 0.0;
-  if (f < a.R) {
-    for (int64_t p = p0 + half; p < p1; p += 2) {
-      const int64_t e = a.perm ? a.perm[p] : p;
-      double prod = (double)a.v[e];
-      for (int l = 0; l < a.N; ++l) {
-        if (l == a.mode) continue;
-        prod *= a.F.U[l][rep * a.F.sU[l] + (int64_t)a.idx[l][e] * a.R + f];
-      }
-      acc += prod;
+  const int64_t r0 = off[row], len = off[row + 1] - r0;
+  const int64_t cs = (len + S - 1) / S;
+  const int64_t p0 = r0 + sl * cs;
+  const int64_t p1 = r0 + ((sl + 1) * cs < len ? (sl + 1) * cs : len);
+  double acc[RP];
+#pragma unroll
+  for (int f = 0; f < RP; ++f) acc[f] = 0.0;
+  for (int64_t p = p0 + lane; p < p1; p += 128) {
+    const bool two = p + 64 < p1;
+    const int64_t e0 = a.perm ? a.perm[p] : p;
+    const int64_t e1 = two ? (a.perm ? a.perm[p + 64] : p + 64) : e0;
+    double q0[RP], q1[RP];
+    const double v0 = (double)a.v[e0], v1 = two ? (double)a.v[e1] : 0.0;
+#pragma unroll
+    for (int f = 0; f < RP; ++f) {
+      q0[f] = v0;
+      q1[f] = v1;
     }
+    for (int l = 0; l < a.N; ++l) {
+      if (l == a.mode) continue;
+      const double* U = a.F.U[l] + rep * a.F.sU[l];
+      const double* u0 = U + (int64_t)a.idx[l][e0] * R;
+      const double* u1 = U + (int64_t)a.idx[l][e1] * R;
+#pragma unroll
+      for (int f = 0; f < RP; ++f) {
+        if (f < R) {
+          q0[f] *= u0[f];
+          q1[f] *= u1[f];
+        }
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < RP; ++f) acc[f] += q0[f] + q1[f];
   }
-  const double other = __shfl_down(acc, 32, 64);
-  if (half == 0 && f < a.R) a.M[rep * a.sM + (int64_t)row * a.R + f] = acc + other;
+#pragma unroll
+  for (int f = 0; f < RP; ++f) acc[f] = wave_sum(acc[f]);
+  if (lane == 0) {
+    double* out = S == 1 ? a.M + rep * a.sM + (int64_t)row * R
+                         : part + (((int64_t)blockIdx.y * a.rows + row) * S + sl) * R;
+#pragma unroll
+    for (int f = 0; f < RP; ++f)
+      if (f < R) out[f] = acc[f];
+  }
+}
+
+// M(rep, row, f) = the S partial rows added in range order
+__global__ void mttkrp_coo_nd_sum_kernel(MttkrpCooNd a, int S, const double* part) {
+  const int64_t n = (int64_t)a.nrep * a.rows * a.R;
+  for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n;
+       q += (int64_t)gridDim.x * blockDim.x) {
+    const int f = (int)(q % a.R);
+    const int64_t rr = q / a.R;  // local repetition * rows + row
+    const int rl = (int)(rr / a.rows), row = (int)(rr % a.rows);
+    const double* p = part + rr * S * a.R + f;
+    double s = 0.0;
+    for (int k = 0; k < S; ++k) s += p[(int64_t)k * a.R];
+    a.M[(a.rep0 + rl) * a.sM + (int64_t)row * a.R + f] = s;
+  }
 }
 
 // nrm[k] = sum of v^2 over slice k of the store (entries [koff[k], koff[k+1]))
@@ -180,6 +232,10 @@ __global__ __launch_bounds__(256) void slice_norms_kernel(const float* v, const 
   s = wave_sum(s);
   if (lane == 0) nrm[k] = s;
 }
+
+// wavefronts the order-N COO MTTKRP aims at (rows x ranges); its partial rows
+// take at most this many R-vectors
+constexpr int64_t kNdCooWaves = 16384;
 
 int blocks_for(int64_t n, int cap) {
   int64_t b = (n + 255) / 256;
@@ -301,11 +357,31 @@ hipError_t launch_mode_sort_nd(const CooSumNd& z, int64_t total, int m, int rows
   return hipGetLastError();
 }
 
-hipError_t launch_mttkrp_coo_nd(const MttkrpCooNd& a, hipStream_t s) {
+int64_t mttkrp_coo_nd_parts(int R) { return kNdCooWaves * R; }
+
+int mttkrp_coo_nd_ranges(int rows, int nrep) {
+  const int64_t rr = (int64_t)rows * nrep;
+  int64_t S = rr > 0 ? kNdCooWaves / rr : 1;
+  if (S > 64) S = 64;
+  return S < 1 ? 1 : (int)S;
+}
+
+hipError_t launch_mttkrp_coo_nd(const MttkrpCooNd& a, double* part, hipStream_t s) {
   if (a.R < 1 || a.R > 32 || a.N < 3 || a.N > kMaxOrder || a.nrep <= 0) return hipErrorInvalidValue;
   if (a.rows <= 0) return hipSuccess;
-  dim3 g((unsigned)((a.rows + 3) / 4), (unsigned)a.nrep);
-  mttkrp_coo_nd_kernel<<<g, 256, 0, s>>>(a);
+  const int S = part ? mttkrp_coo_nd_ranges(a.rows, a.nrep) : 1;
+  dim3 g((unsigned)(((int64_t)a.rows * S + 3) / 4), (unsigned)a.nrep);
+  switch ((a.R + 3) / 4 * 4) {
+#define SBT_MCN(RPV) \
+  case RPV: timed_launch(mttkrp_coo_nd_kernel<RPV>, g, dim3(256), 0, s, a, S, part); break;
+    SBT_MCN(4) SBT_MCN(8) SBT_MCN(12) SBT_MCN(16) SBT_MCN(20) SBT_MCN(24) SBT_MCN(28)
+    default: timed_launch(mttkrp_coo_nd_kernel<32>, g, dim3(256), 0, s, a, S, part); break;
+#undef SBT_MCN
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || S == 1) return e;
+  mttkrp_coo_nd_sum_kernel<<<blocks_for((int64_t)a.nrep * a.rows * a.R, 1024), 256, 0, s>>>(
+      a, S, part);
   return hipGetLastError();
 }
 

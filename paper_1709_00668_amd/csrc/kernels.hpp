@@ -672,7 +672,10 @@ hipError_t launch_mode_sort_nd(const CooSumNd& z, int64_t total, int m, int rows
                                uint32_t* key, uint32_t* key_sorted, int32_t* iota,
                                int32_t* perm, int64_t* off, void* tmp, size_t tmp_bytes,
                                hipStream_t s);
-hipError_t launch_mttkrp_coo_nd(const MttkrpCooNd& a, hipStream_t s);
+// part: room for mttkrp_coo_nd_parts(R) doubles, where the ranges of long
+// rows leave their partial rows (null: one wavefront per row)
+hipError_t launch_mttkrp_coo_nd(const MttkrpCooNd& a, double* part, hipStream_t s);
+int64_t mttkrp_coo_nd_parts(int R);
 // nrm[k] = sum of v^2 over the entries [koff[k], koff[k + 1])
 hipError_t launch_slice_norms(const float* v, const int64_t* koff, int64_t K, double* nrm,
                               hipStream_t s);

@@ -259,6 +259,73 @@ class SparseCP:
         return idx.astype(np.int32), v.astype(np.float32)
 
 
+class SparseCPN:
+    """The N-mode analogue of SparseCP: for component r, Zipf(zipf) popularity
+    over a random permutation of the indices of every leading mode and a
+    U[0,1) profile over the last mode; a nonzero picks a component uniformly,
+    then one index per mode from the profiles; duplicates are dropped and the
+    draw topped up.  The value is sum_r prod_m P_m(i_m, r) scaled to mean 1,
+    plus N(0, sigma^2) with sigma = noise * ||v|| / sqrt(nnz)."""
+
+    def __init__(self, dims, R, seed, zipf=1.1, noise=0.01):
+        self.dims = tuple(int(d) for d in dims)
+        self.R, self.seed, self.zipf, self.noise = int(R), int(seed), float(zipf), float(noise)
+        g = _gen(seed, STREAM_FACTOR)
+        self.P = []
+        for d in self.dims[:-1]:
+            P = np.empty((self.R, d))
+            for r in range(self.R):
+                P[r, g.permutation(d)] = (1.0 + np.arange(d)) ** (-self.zipf)
+            self.P.append(P / P.sum(axis=1, keepdims=True))
+        pc = g.random((self.R, self.dims[-1]))
+        self.P.append(pc / pc.sum(axis=1, keepdims=True))
+
+    def slices(self, k0, k1, nnz, block_id=0):
+        """About `nnz` distinct nonzeros with last index in [k0, k1): a list of
+        N int32 coordinate arrays (the last relative to k0) ordered by the
+        linear index with the first mode slowest, and FP32 values."""
+        g = _gen(self.seed, STREAM_SPARSE, block_id)
+        ext = list(self.dims[:-1]) + [k1 - k0]
+        N = len(ext)
+        prof = [P for P in self.P[:-1]] + [self.P[-1][:, k0:k1]]
+        cums = [np.cumsum(P, axis=1) for P in prof]
+        keys = np.empty(0, dtype=np.int64)
+        while keys.size < nnz:
+            m = int((nnz - keys.size) * 1.2) + 16
+            comp = g.integers(0, self.R, size=m)
+            co = [np.empty(m, dtype=np.int64) for _ in range(N)]
+            for r in range(self.R):
+                sel = comp == r
+                cnt = int(sel.sum())
+                if cnt == 0:
+                    continue
+                for q in range(N):
+                    c = cums[q][r]
+                    co[q][sel] = np.minimum(np.searchsorted(c, g.random(cnt) * c[-1]), ext[q] - 1)
+            new = co[0]
+            for q in range(1, N):
+                new = new * ext[q] + co[q]
+            keys = np.unique(np.concatenate([keys, new]))
+        keys = keys[g.permutation(keys.size)[:nnz]]
+        keys.sort()
+        cols = []
+        rest = keys
+        for q in range(N - 1, -1, -1):
+            cols.append(rest % ext[q])
+            rest = rest // ext[q]
+        cols = cols[::-1]
+        v = np.zeros(keys.size)
+        for r in range(self.R):
+            t = np.ones(keys.size)
+            for q in range(N):
+                t = t * prof[q][r, cols[q]]
+            v += t
+        v = v / (v.mean() if v.size else 1.0)
+        if self.noise > 0 and v.size:
+            v = v + self.noise * np.linalg.norm(v) / np.sqrt(v.size) * g.standard_normal(v.size)
+        return [c.astype(np.int32) for c in cols], v.astype(np.float32)
+
+
 def sparse_model(gen, K0, mean):
     """Factors of a SparseCP block whose values were divided by `mean`: unit
     columns A, B, C (C over the first K0 slices) and lambda, in SparseCP's

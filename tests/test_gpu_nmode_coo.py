@@ -98,9 +98,12 @@ def check_update(lib, gpu, ora, d, N, reps, rtol=1e-8, atol=1e-10):
 
 
 @pytest.mark.parametrize("dims,Kn,R,s,seed", [((14, 12, 10, 16), 4, 3, (2, 3, 2, 2), 41),
-                                              ((9, 8, 7, 6, 10), 3, 2, (2, 1, 2, 2, 2), 43)])
+                                              ((9, 8, 7, 6, 10), 3, 2, (2, 1, 2, 2, 2), 43),
+                                              ((6000, 6, 5, 8), 3, 2, (2, 1, 1, 2), 49)])
 def test_coo_update_matches_the_oracle(lib, dims, Kn, R, s, seed):
-    # orders 4 and 5, two batches, the generating model given
+    # orders 4 and 5, two batches, the generating model given; the last case
+    # has 3000 summary rows in mode 0 (three repetitions), so that mode's
+    # MTTKRP takes one wavefront per row and the others split their rows
     N, reps = len(dims), 3
     ora, gpu, ds, _ = run_pair(lib, dims, Kn, R, reps, 15, s, seed)
     check_update(lib, gpu, ora, ds[-1], N, reps)
