@@ -218,6 +218,19 @@ __global__ void mttkrp_coo_nd_sum_kernel(MttkrpCooNd a, int S, const double* par
   }
 }
 
+// out = the entries of z in the order perm (every coordinate but mode m's,
+// and the value): out.idx[l][p] = z.idx[l][perm[p]]
+__global__ void gather_sorted_nd_kernel(CooSumNd z, int64_t total, int m, int N,
+                                        const int32_t* perm, CooSumNd out) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < total;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = perm[p];
+    for (int l = 0; l < N; ++l)
+      if (l != m) out.idx[l][p] = z.idx[l][e];
+    out.v[p] = z.v[e];
+  }
+}
+
 // nrm[k] = sum of v^2 over slice k of the store (entries [koff[k], koff[k+1]))
 __global__ __launch_bounds__(256) void slice_norms_kernel(const float* v, const int64_t* koff,
                                                          int64_t K, double* nrm) {
@@ -354,6 +367,14 @@ hipError_t launch_mode_sort_nd(const CooSumNd& z, int64_t total, int m, int rows
   }
   const int64_t q = (int64_t)nrep * (rows + 1);
   row_offsets_kernel<<<blocks_for(q, 4096), 256, 0, s>>>(key_sorted, total, rows, nrep, off);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_sorted_nd(const CooSumNd& z, int N, int64_t total, int m,
+                                  const int32_t* perm, const CooSumNd& out, hipStream_t s) {
+  if (N < 3 || N > kMaxOrder || m < 0 || m >= N) return hipErrorInvalidValue;
+  if (total <= 0) return hipSuccess;
+  gather_sorted_nd_kernel<<<blocks_for(total, 4096), 256, 0, s>>>(z, total, m, N, perm, out);
   return hipGetLastError();
 }
 

@@ -675,6 +675,10 @@ hipError_t launch_mode_sort_nd(const CooSumNd& z, int64_t total, int m, int rows
 // part: room for mttkrp_coo_nd_parts(R) doubles, where the ranges of long
 // rows leave their partial rows (null: one wavefront per row)
 hipError_t launch_mttkrp_coo_nd(const MttkrpCooNd& a, double* part, hipStream_t s);
+// out.idx[l][p] = z.idx[l][perm[p]] for every mode l < N but m,
+// out.v[p] = z.v[perm[p]], p < total
+hipError_t launch_gather_sorted_nd(const CooSumNd& z, int N, int64_t total, int m,
+                                  const int32_t* perm, const CooSumNd& out, hipStream_t s);
 int64_t mttkrp_coo_nd_parts(int R);
 // nrm[k] = sum of v^2 over the entries [koff[k], koff[k + 1])
 hipError_t launch_slice_norms(const float* v, const int64_t* koff, int64_t K, double* nrm,
