@@ -470,6 +470,44 @@ def test_full_size_dense500_update(lib):
     assert abs(gpu.fit() - ora.fit()) < 1e-3
 
 
+def test_full_size_dense2000_bf16_update(lib):
+    # one update of the default benchmark workload at its full size: a
+    # 2000 x 2000 x 1000 FP32 store from a rank-20 U[0,1) model plus 1% noise
+    # generated on the GPU as the benchmark generates it, 100 new slices,
+    # s = 5, r = 10, 30 sweeps, launched as the benchmark launches it (batched,
+    # BF16 summaries on the matrix cores).  The oracle reads the same bytes
+    # (copied back) and rounds its summaries to BF16 as the path does.  Every
+    # sampled index and every matching exact; the new rows of C at the
+    # FP32/BF16 bars; fit within 1e-4 of the oracle's.
+    import os
+    torch = _torch()
+    I = J = 2000
+    K0, Kn, R, reps, iters, s = 1000, 100, 20, 10, 30, 5
+    gen = synth.DenseCP(I, J, K0 + Kn, R, seed=5, noise=0.01, dtype=np.float32)
+    Xd = torch.empty((K0 + Kn, J, I), dtype=torch.float32, device="cuda")
+    gen.fill_device(torch, Xd)
+    torch.cuda.synchronize()
+    X = Xd.cpu().numpy().transpose(2, 1, 0)  # (I, J, K), column-major
+    model = gen.true_model_prefix(K0)
+    ocfg = osb.Config(rank=R, reps=reps, als_iters=iters, sample_factor=s, seed=5,
+                      k_capacity=K0 + Kn, summary_bf16=True,
+                      workers=max(1, min(16, os.cpu_count() or 1)))
+    ora = osb.OracleTensor(ocfg, osb.DENSE, (I, J, K0), X0=X[:, :, :K0], factors=model)
+    cfg = lib.make_config(R, reps, iters, s, 5, precision=lib.SBT_P_BF16, k_capacity=K0 + Kn,
+                          max_batch=Kn)
+    gpu = lib.Tensor.init_dense(cfg, Xd[:K0], I, J, K0, factors=model)
+    d = ora.update(X[:, :, K0:], debug=True)
+    gpu.update_batch_dense(Xd[K0:], Kn)
+    torch.cuda.synchronize()
+    check_samples(gpu, d, reps)
+    for rho in range(reps):
+        np.testing.assert_array_equal(gpu.last_rep(rho, lib.SBT_REP_PI, 1)[0],
+                                      d["reps"][rho]["pi"], err_msg=f"rep {rho}")
+    _, _, C, _ = gpu.get_factors()
+    assert_close(C[K0:], ora.C[K0:], RT, AT, "new rows of C")
+    assert abs(gpu.fit() - ora.fit()) < 1e-4
+
+
 @pytest.mark.parametrize("prec,sched", [(0, 0), (0, 1), (1, 0), (2, 0)])
 def test_lambda_average_reading(lib, prec, sched):
     # SBT_FLAG_LAMBDA_AVG: lambda becomes the average of its previous value and the
