@@ -83,21 +83,37 @@ __global__ __launch_bounds__(256) void gather_mfma_kernel(const TIn* X, int64_t 
   const int g0 = cg0 + (int)blockIdx.y * kGatherGroups;
   const int64_t n12 = (int64_t)rs.n1 * rs.n2;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int32_t* Is = idx + rep * idx_stride;
+  // the slices of the block's positions, read once into LDS (-1: c >= K')
+  __shared__ int64_t ksl[kGatherGroups * 8];
+  if (threadIdx.x < kGatherGroups * 8) {
+    const int c = g0 * 8 + (int)threadIdx.x;
+    int64_t k = -1;
+    if (c < rs.n3) k = c < n3old ? (int64_t)Is[offK + c] : Kold + (c - n3old);
+    ksl[threadIdx.x] = k;
+  }
+  __syncthreads();
   if (e >= n12) return;
   const int a = (int)(e % rs.n1), b = (int)(e / rs.n1);
-  const int32_t* Is = idx + rep * idx_stride;
   const int64_t base = (int64_t)Is[a] + I * (int64_t)Is[offJ + b];
   uint16_t* zk = Zk + rep * L.sZk + a + (int64_t)L.ld1 * b;
   uint16_t* zc = Zc + rep * L.sZc + e * L.ldc;
   for (int cg = g0; cg < g0 + kGatherGroups && cg < cg0 + ncg; ++cg) {
+    // the group's eight loads in flight together (positions c >= K' read
+    // slice 0 of the store and are dropped)
+    TIn x[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int64_t kk = ksl[(cg - g0) * 8 + j];
+      x[j] = X[base + I * J * (kk >= 0 ? kk : 0)];
+    }
     uint16_t v[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int c = cg * 8 + j;
       v[j] = 0;
       if (c < rs.n3) {
-        const int64_t kk = c < n3old ? (int64_t)Is[offK + c] : Kold + (c - n3old);
-        v[j] = f32_to_bf16_rne((float)X[base + I * J * kk]);
+        v[j] = f32_to_bf16_rne((float)x[j]);
         zk[L.sk * c] = v[j];
       }
     }

@@ -103,11 +103,15 @@ __global__ __launch_bounds__(256) void moi_dense_kernel(const T* Y, int64_t I, i
   bool bad = false;
   for (int kk = 0; kk < kMoiKTile && k0 + kk < K; ++kk) {
     const int64_t k = k0 + kk;
+    // branch-free loads (an element outside the tile reads element (0, 0, k)
+    // and counts as zero), so that all of them are in flight at once
     T y[kMoiJPerWave];
 #pragma unroll
     for (int jj = 0; jj < kMoiJPerWave; ++jj) {
       const int64_t j = j0 + wave + 4 * jj;
-      y[jj] = (i < I && j < J) ? Y[i + I * (j + J * k)] : (T)0;
+      const bool in = i < I && j < J;
+      const T v = Y[(in ? i : 0) + I * ((in ? j : 0) + J * k)];
+      y[jj] = in ? v : (T)0;
     }
     uint64_t tk = 0;
 #pragma unroll
@@ -236,10 +240,14 @@ __global__ __launch_bounds__(256) void moi_nd_kernel(MoiNd a) {
   unsigned long long acc0 = 0ull;
   bool bad = false;
   for (int64_t c0 = cb; c0 < ce; c0 += kMoiNdLoads) {
+    // branch-free loads (outside the tile: element (0, column c0), dropped)
     double x[kMoiNdLoads];
 #pragma unroll
-    for (int u = 0; u < kMoiNdLoads; ++u)
-      x[u] = (in && c0 + u < ce) ? (double)X[i0 + D0 * (c0 + u)] : 0.0;
+    for (int u = 0; u < kMoiNdLoads; ++u) {
+      const bool v = in && c0 + u < ce;
+      const double y = (double)X[(v ? i0 : 0) + D0 * (v ? c0 + u : c0)];
+      x[u] = v ? y : 0.0;
+    }
 #pragma unroll
     for (int u = 0; u < kMoiNdLoads; ++u) {
       if (c0 + u >= ce) break;  // uniform over the wavefront

@@ -388,15 +388,13 @@ __global__ __launch_bounds__(256) void p1s_kernel(RepSet rs, const TZ* Z, const 
     for (int f = 0; f < RP; ++f) acc[v][f] = 0;
   int q = w0;
   for (; q + kP1sLoads <= w1; q += kP1sLoads) {
+    // branch-free loads (zp is a valid row when !ok; its values are dropped)
     TA z[kP1sLoads][V];
 #pragma unroll
     for (int u = 0; u < kP1sLoads; ++u) {
-      if (ok) {
-        acc_of<V>(zp + n12 * (q + u), z[u]);
-      } else {
+      acc_of<V>(zp + n12 * (q + u), z[u]);
 #pragma unroll
-        for (int v = 0; v < V; ++v) z[u][v] = 0;
-      }
+      for (int v = 0; v < V; ++v) z[u][v] = ok ? z[u][v] : (TA)0;
     }
 #pragma unroll
     for (int u = 0; u < kP1sLoads; ++u)
@@ -409,12 +407,9 @@ __global__ __launch_bounds__(256) void p1s_kernel(RepSet rs, const TZ* Z, const 
   }
   for (; q < w1; ++q) {
     TA z[V];
-    if (ok) {
-      acc_of<V>(zp + n12 * q, z);
-    } else {
+    acc_of<V>(zp + n12 * q, z);
 #pragma unroll
-      for (int v = 0; v < V; ++v) z[v] = 0;
-    }
+    for (int v = 0; v < V; ++v) z[v] = ok ? z[v] : (TA)0;
 #pragma unroll
     for (int f = 0; f < RP; ++f) {
       const TA c = Cs[q][f];

@@ -54,9 +54,18 @@ struct SolveArgs {
 
 __device__ inline double solve_v(const SolveArgs& a, int rep, int q) {
   if (!a.gmask) return a.G1[rep * a.sG1 + q] * a.G2[rep * a.sG2 + q];
+  // branch-free: every mode's load in flight at once (a mode outside the
+  // mask reads mode 0's matrix and contributes a factor of one)
+  double g[kMaxOrder];
+#pragma unroll
+  for (int m = 0; m < kMaxOrder; ++m) {
+    const bool on = (a.gmask >> m) & 1u;
+    g[m] = a.Gm[(on ? m : 0) * a.sGmode + rep * a.sG1 + q];
+  }
   double v = 1.0;
+#pragma unroll
   for (int m = 0; m < kMaxOrder; ++m)
-    if ((a.gmask >> m) & 1u) v *= a.Gm[m * a.sGmode + rep * a.sG1 + q];
+    if ((a.gmask >> m) & 1u) v *= g[m];
   return v;
 }
 
