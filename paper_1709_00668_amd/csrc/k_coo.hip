@@ -86,8 +86,10 @@ __global__ __launch_bounds__(1024) void scan_to_offsets_kernel(const uint32_t* c
     int64_t v[kScanItems];
     int64_t t = 0;
 #pragma unroll
-    for (int q = 0; q < kScanItems; ++q) {
-      v[q] = i0 + q < n ? (int64_t)c[i0 + q] : 0;
+    for (int q = 0; q < kScanItems; ++q) {  // branch-free: all loads in flight
+      const bool in = i0 + q < n;
+      const int64_t x = (int64_t)c[in ? i0 + q : 0];
+      v[q] = in ? x : 0;
       t += v[q];
     }
     // inclusive wave scan of the thread totals
