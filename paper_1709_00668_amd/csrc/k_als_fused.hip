@@ -304,9 +304,15 @@ __device__ void als_tail(const TailArgs& t, int rep, int R, TailSmem& s, bool wr
 #pragma unroll
         for (int u = 0; u < kTailParts; ++u) a[u] += v[u];
       }
+      {  // the last parts, branch-free (past the end: part 0, dropped)
+        double v[kTailParts];
 #pragma unroll
-      for (int u = 0; u < kTailParts; ++u)
-        if (b + u < t.nparts) a[u] += gp[(int64_t)(b + u) * RR + q];
+        for (int u = 0; u < kTailParts; ++u)
+          v[u] = gp[(int64_t)(b + u < t.nparts ? b + u : 0) * RR + q];
+#pragma unroll
+        for (int u = 0; u < kTailParts; ++u)
+          if (b + u < t.nparts) a[u] += v[u];
+      }
 #pragma unroll
       for (int w = kTailParts / 2; w > 0; w /= 2)
 #pragma unroll
