@@ -77,6 +77,7 @@ import json
 import os
 import re
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -133,10 +134,38 @@ KIND_NAMES = ("mttkrp_contract_c", "mttkrp_third_mode", "row_solve", "gather", "
               "update")
 
 
-def kernel_of(step, path, R, coo_row_nnz=0.0, n1_third=0):
+# launch shapes of the matrix-core path, in the library's choice order: rows
+# tiles per wavefront of pass W, K steps in flight of the mode-3 pass, slice
+# groups per gathering thread
+PW_TILES, P3_STEPS, GATHER_GROUPS = (4, 2, 1), (2, 1, 4), (8, 4, 16)
+# the launch-shape table the benchmark loads (decided on MI355X by a run of
+# this script with --tune-save)
+TILE_CACHE = os.path.join(ROOT, "paper_1709_00668_amd", "tiles_gfx950.txt")
+
+
+def tuned_shapes(sbt, R, n12, r, store_prec=1):
+    """Shapes the tuner holds for a summary shape: {0: gather, 1: pass W,
+    2: mode 3} -> choice (a kernel missing from the dict runs shape 0)."""
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "shapes.txt")
+        sbt.autotune_save(path)
+        rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    got = {}
+    for a in rows:
+        k, sh, c = int(a[1]), [int(x) for x in a[2:6]], int(a[6])
+        if k in (1, 2) and sh == [R, n12, r, 0]:
+            got[k] = c
+        elif k == 0 and sh == [store_prec, n12, r, 0]:
+            got[k] = c
+    return got
+
+
+def kernel_of(step, path, R, coo_row_nnz=0.0, n1_third=0, tiles=None):
     """HIP kernel behind a timed launch kind (coo_row_nnz: summary entries per
     row, which picks the sparse kernel's lanes per unit; n1_third: first extent
-    of the order-N third-mode view, which picks the fused pass's vector width)."""
+    of the order-N third-mode view, which picks the fused pass's vector width;
+    tiles: the tuner's launch shapes of the matrix-core path)."""
+    tiles = tiles or {}
     rp = (R + 3) // 4 * 4
     v3 = 4 if n1_third % 4 == 0 and rp <= 16 else (2 if n1_third % 2 == 0 else 1)
     ul = 64 if coo_row_nnz >= 128.0 else 32
@@ -146,10 +175,10 @@ def kernel_of(step, path, R, coo_row_nnz=0.0, n1_third=0):
                 "mttkrp_third_mode": f"p3_kernel<float, {rp}, 4, false>",
                 "row_solve": f"p3_kernel<float, {rp}, 4, true>",
                 "gather": "gather_dense_kernel<float, float>"},
-        "bf16": {"mttkrp_contract_c": f"pw_mfma_kernel<{nt}>",
-                 "mttkrp_third_mode": f"p3_mfma_kernel<{nt}>",
-                 "row_solve": f"p3_mfma_kernel<{nt}> + mode3_finish_kernel",
-                 "gather": "gather_mfma_kernel<float>"},
+        "bf16": {"mttkrp_contract_c": f"pw_mfma_kernel<{nt}, {PW_TILES[tiles.get(1, 0)]}>",
+                 "mttkrp_third_mode": f"p3_mfma_kernel<{nt}, {P3_STEPS[tiles.get(2, 0)]}>",
+                 "row_solve": f"p3_mfma_kernel<{nt}, 2> + mode3_finish_kernel",
+                 "gather": f"gather_mfma_kernel<float, {GATHER_GROUPS[tiles.get(0, 0)]}>"},
         "coo": {"coo_mttkrp": f"coo_units_kernel<{rp}, {ul}>", "gather": "summary_emit_kernel"},
         "nd_f32": {"mttkrp_contract_c": f"p1s_kernel<float, {rp}, 1>",
                    "mttkrp_third_mode": f"p3_kernel<float, {rp}, {v3}, false>",
@@ -246,10 +275,11 @@ def _header_defs(text):
 
 def kernel_digest(kernel, read=None):
     """Digest of the source file that defines `kernel` (its launch code lives
-    there too) and of the definitions in the shared headers (declarations of
-    other launchers do not count): a counter measurement of the kernel stays
-    valid while this digest does.  `read(name)` returns a source file's text
-    (default: the working tree)."""
+    there too) and of the definitions in the shared device headers (`.hpp`;
+    declarations of other launchers do not count, nor does the host-only
+    `autotune.h`, which no kernel source includes): a counter measurement of
+    the kernel stays valid while this digest does.  `read(name)` returns a
+    source file's text (default: the working tree)."""
     if read is None:
         def read(name):
             with open(os.path.join(CSRC, name)) as f:
@@ -292,7 +322,7 @@ def committed_traffic(kernel, key):
     return None
 
 
-def roofline_of(prof, path, R, key, summary_rows=0, n1_third=0, every=PROF_EVERY):
+def roofline_of(prof, path, R, key, summary_rows=0, n1_third=0, every=PROF_EVERY, tiles=None):
     kernels = {k: v for k, v in prof.items() if k != "update" and v["launches"]}
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     d = kernels[dom]
@@ -301,7 +331,7 @@ def roofline_of(prof, path, R, key, summary_rows=0, n1_third=0, every=PROF_EVERY
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     # sparse: 12 B per summary entry; entries per row over all repetitions' rows
     row_nnz = bytes_per_launch / 12.0 / summary_rows if summary_rows else 0.0
-    kname = kernel_of(dom, path, R, row_nnz, n1_third)
+    kname = kernel_of(dom, path, R, row_nnz, n1_third, tiles)
     return dict(bound="hbm", kernel=kname, step=dom, achieved=round(achieved, 1),
                 peak=HBM_PEAK_GBS, unit="GB/s", frac=round(achieved / HBM_PEAK_GBS, 4),
                 traffic=committed_traffic(kname, key),
@@ -428,9 +458,16 @@ def bench_dense(args, sbt, torch, synth, log):
     b = runs[main]
     path = "f32" if main == "batched_f32" else "bf16"
     line = base_line(args, w, b, path)
+    n12 = -(-I // w["s"]) * -(-J // w["s"])
+    tiles = tuned_shapes(sbt, w["R"], n12, w["r"]) if path == "bf16" else None
     line["roofline"] = roofline_of(b["profile"], path, w["R"],
-                                   f"{name}@steps{steps}w{args.warmup}")
+                                   f"{name}@steps{steps}w{args.warmup}", tiles=tiles)
     if path == "bf16":
+        line["launch_shapes"] = {
+            "source": args.tune_cache or "online",
+            "pw_mfma_row_tiles": PW_TILES[tiles.get(1, 0)],
+            "p3_mfma_steps_in_flight": P3_STEPS[tiles.get(2, 0)],
+            "gather_slice_groups": GATHER_GROUPS[tiles.get(0, 0)]}
         # useful matrix-core work of the mode-3 pass: 2 |Z| R flops per summary
         pr = b["profile"]["mttkrp_third_mode"]
         if pr["launches"]:
@@ -1138,6 +1175,11 @@ def main():
                     help="sparse: keep the generated nonzeros in this folder and reuse them")
     ap.add_argument("--nnz-scale", type=float, default=1.0,
                     help="scale the nonzero counts of the sparse workload")
+    ap.add_argument("--tune-cache", default=os.path.relpath(TILE_CACHE, ROOT),
+                    help="launch-shape table to load before the run (\"\": none, every "
+                         "shape is then decided online by timing the first launches)")
+    ap.add_argument("--tune-save", default="",
+                    help="write the launch-shape table to this file after the run")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a kernel of "
                          "known traffic that calibrates hardware byte counters)")
@@ -1154,6 +1196,10 @@ def main():
     sbt.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.tune_cache and os.path.exists(os.path.join(ROOT, args.tune_cache)):
+        sbt.autotune_load(os.path.join(ROOT, args.tune_cache))
+    else:
+        args.tune_cache = ""  # none: every launch shape is decided online
 
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
@@ -1179,6 +1225,8 @@ def main():
         line = bench_getrank(args, sbt, torch, synth, log)
     else:
         line = bench_dense(args, sbt, torch, synth, log)
+    if args.tune_save:
+        sbt.autotune_save(args.tune_save)
     print(json.dumps(line))
 
 

@@ -31,7 +31,8 @@
  *   nothing (the first call is unaffected).  sbt_destroy must not overlap
  *   any other call on the tensor.
  * - sbt_last_error(NULL) gives the message of the last failed call of the
- *   calling host thread that had no tensor to record it on (sbt_load).
+ *   calling host thread that had no tensor to record it on (sbt_load, and
+ *   the sbt_init_* and sbt_nd_init_* calls, whose tensor is released).
  */
 #ifndef SAMBATEN_H
 #define SAMBATEN_H
@@ -380,6 +381,50 @@ typedef enum {
 sbt_status sbt_profile_enable(sbt_tensor* t, int32_t on);
 sbt_status sbt_profile_read(const sbt_tensor* t, int32_t kind, int64_t* launches,
                             double* total_ms, double* alg_bytes);
+
+/* --------------------------------------------------------------------------
+ * Launch-shape tuner (process-wide; not part of the method).
+ *
+ * The BF16 matrix-core path of the update (the summary gather and the two
+ * MTTKRP passes of each CP-ALS sweep, Algorithm 1's inner decompositions)
+ * can launch its kernels in SBT_TUNE_SHAPES shapes (rows per block, operand
+ * loads in flight, slices per gathering thread) whose results are identical
+ * bit for bit: every output sums the same terms in the same order.  The
+ * tuner keys each launch by the kernel, the device architecture and the
+ * summary shape (R, n1 n2 and the repetitions; K' only scales the work) and, for a
+ * key it has not decided, times the hot path's own launches in the shapes in
+ * turn (two each, event pairs read back without waiting); from then on the
+ * shape with the least time per unit of work is used for that key.  A
+ * launch whose key is still undecided, or that is captured into a graph,
+ * uses shape 0.  The choice never changes a result, only the time.
+ *
+ * sbt_autotune_set: mode SBT_TUNE_OFF (shape 0 always), SBT_TUNE_ON (the
+ *   default: decide unseen keys online), SBT_TUNE_CACHED (decided keys only,
+ *   no trials), SBT_TUNE_FIXED (every launch in `shape`, 0 <= shape < 8; a
+ *   kernel with fewer shapes takes shape 0).  SBT_E_INVALID otherwise.
+ * sbt_autotune_clear: forget every key (trials in flight are dropped).
+ * sbt_autotune_count: keys decided and keys with trials running.
+ * sbt_autotune_save: write the decided keys to the text file `path` (written
+ *   to path.tmp, then renamed); SBT_E_INVALID if it cannot be written.
+ * sbt_autotune_load: merge the keys of a file written by sbt_autotune_save
+ *   into the table (a key present in both takes the file's shape); a file
+ *   that cannot be read or has a malformed line changes nothing and gives
+ *   SBT_E_INVALID.
+ * Thread safety: every sbt_autotune_* call may come from any host thread.
+ * ------------------------------------------------------------------------ */
+typedef enum {
+  SBT_TUNE_OFF = 0,
+  SBT_TUNE_ON = 1,
+  SBT_TUNE_CACHED = 2,
+  SBT_TUNE_FIXED = 3
+} sbt_tune_mode;
+#define SBT_TUNE_SHAPES 3
+
+sbt_status sbt_autotune_set(int32_t mode, int32_t shape);
+sbt_status sbt_autotune_clear(void);
+sbt_status sbt_autotune_count(int64_t* decided, int64_t* tuning);
+sbt_status sbt_autotune_save(const char* path);
+sbt_status sbt_autotune_load(const char* path);
 
 /* --------------------------------------------------------------------------
  * Serving loop (many resident tensors, update requests arriving over time).

@@ -15,7 +15,7 @@ OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsambaten.so")
 SOURCES = ["k_moi_sample.hip", "k_als.hip", "k_als_fused.hip", "k_mfma.hip", "k_match.hip",
            "k_coo.hip", "k_gram.hip", "k_getrank.hip", "k_nmode.hip", "k_nmode_coo.hip",
-           "server.hip", "noalloc.hip", "engine.hip"]
+           "server.hip", "noalloc.hip", "autotune.hip", "engine.hip"]
 ARCH = os.environ.get("SBT_OFFLOAD_ARCH", "gfx950")
 
 # Packed FP32 instructions are disabled: the compiler emits them on its own

@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "../../include/sambaten.h"
+#include "autotune.h"
 #include "device_common.hpp"
 #include "kernels.hpp"
 
@@ -1056,6 +1057,12 @@ sbt_status run_als(sbt_tensor* t, const void* Zp, RepSet rs, double* Ap, double*
   const int ns3 = mf ? mfma_mode3_splits(rs, t->ml) : 1;
   const double pwm_bytes = (double)rs.nrep * rs.n1 * rs.n2 * (kp32 * 2.0 + rs.R * 4.0) +
                            (double)rs.nrep * rs.n3 * rs.R * 8.0;
+  // launch-shape keys of the two matrix-core passes (rank, summary rows,
+  // repetitions: K' grows with every update and only scales the work) and
+  // their units of work (summary elements read)
+  const int64_t pw_key[4] = {rs.R, (int64_t)rs.n1 * rs.n2, rs.nrep, 0};
+  const int64_t p3_key[4] = {rs.R, (int64_t)rs.n1 * rs.n2, rs.nrep, 0};
+  const double mf_work = (double)rs.nrep * rs.n1 * rs.n2 * rs.n3;
   const double p3m_bytes = (double)rs.nrep * rs.n3 * t->ml.sk * 2.0 +
                            (double)rs.nrep * rs.R * 8.0 * ((double)rs.n1 + rs.n2) +
                            (double)rs.nrep * ns3 * rs.n3 * (rs.R <= 16 ? 16 : 32) * 4.0;
@@ -1100,7 +1107,9 @@ sbt_status run_als(sbt_tensor* t, const void* Zp, RepSet rs, double* Ap, double*
   for (int it = 0; it < iters; ++it) {
     int pq = prof_kernel(t);
     if (mf) {
-      SBT_CK(launch_pw_mfma(rs, t->ml, t->Zc, Cp, ilC, (float*)W, t->mops, st));
+      const TuneSlot ts = tune_begin(kTunePw, SBT_TUNE_SHAPES, pw_key, mf_work, !capture, st);
+      SBT_CK(launch_pw_mfma(rs, t->ml, t->Zc, Cp, ilC, (float*)W, t->mops, st, ts.choice));
+      tune_end(ts, st);
       prof_end(t, pq, SBT_K_MTTKRP_C, pwm_bytes, st);
     } else {
       SBT_CK(launch_pw(prec, rs, Zp, Cp, ilC, W, st));
@@ -1126,8 +1135,10 @@ sbt_status run_als(sbt_tensor* t, const void* Zp, RepSet rs, double* Ap, double*
     pq = prof_kernel(t);
     double* gpc = nullptr;
     if (mf) {
+      const TuneSlot ts = tune_begin(kTuneP3, SBT_TUNE_SHAPES, p3_key, mf_work, !capture, st);
       SBT_CK(launch_p3_mfma(rs, t->ml, ns3, t->Zk, Ap, ilA, Bp, ilB, t->P3, t->sP3, t->mops,
-                            st));
+                            st, ts.choice));
+      tune_end(ts, st);
       prof_end(t, pq, SBT_K_MTTKRP_AB, p3m_bytes, st);
       gpc = gram_parts_buf(t, rs, rs.n3);
       SBT_CK(launch_mode3_finish(rs, ns3, t->P3, t->sP3, Vinv, nullptr, Cp, rs.sC, st, gpc,
@@ -1365,8 +1376,13 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
   const int c0 = (reuse && t->z_kept) ? n3old : 0;
   if (t->mfma) {
     const int gq = prof_kernel(t);
+    // (a kept summary's gather reads only the new slices: a key of its own)
+    const int64_t gkey[4] = {t->store_prec, (int64_t)t->n1 * t->n2, r, c0 > 0 ? 1 : 0};
+    const TuneSlot ts = tune_begin(kTuneGather, SBT_TUNE_SHAPES, gkey,
+                                   (double)r * t->n1 * t->n2 * (Kp - c0), true, st);
     SBT_CK(launch_gather_mfma(t->store_prec, t->X, t->I, t->J, t->idx, t->idx_stride, offJ, offK,
-                              n3old, Kold, c0, all, t->ml, t->Zk, t->Zc, st));
+                              n3old, Kold, c0, all, t->ml, t->Zk, t->Zc, st, ts.choice));
+    tune_end(ts, st);
     prof_end(t, gq, SBT_K_GATHER,
              (double)r * t->n1 * t->n2 * (Kp - c0) * (prec_bytes(t->store_prec) + 4.0), st);
   } else if (t->fmt == SBT_DENSE) {
@@ -1706,6 +1722,7 @@ const char* sbt_last_error(const sbt_tensor* t) {
 sbt_status sbt_init_dense(const sbt_config* cfg, const void* X0_dev, int64_t I, int64_t J,
                           int64_t K0, const double* A0, const double* B0, const double* C0,
                           const double* lambda0, void* stream, sbt_tensor** out) {
+  g_errmsg.clear();
   if (!out) return SBT_E_INVALID;
   *out = nullptr;
   std::string why;
@@ -1763,6 +1780,7 @@ sbt_status sbt_init_dense(const sbt_config* cfg, const void* X0_dev, int64_t I, 
   }
   if (s == SBT_OK) s = init_common(t, A0, B0, C0, lambda0, st);
   if (s != SBT_OK) {
+    g_errmsg = t->errmsg;  // the tensor is gone: sbt_last_error(NULL) keeps it
     free_all(t);
     delete t;
     return s;
@@ -1776,6 +1794,7 @@ sbt_status sbt_init_coo(const sbt_config* cfg, const int32_t* i_dev, const int32
                         int64_t J, int64_t K0, const double* A0, const double* B0,
                         const double* C0, const double* lambda0, void* stream,
                         sbt_tensor** out) {
+  g_errmsg.clear();
   if (!out) return SBT_E_INVALID;
   *out = nullptr;
   std::string why;
@@ -1856,6 +1875,7 @@ sbt_status sbt_init_coo(const sbt_config* cfg, const int32_t* i_dev, const int32
   }
   if (s == SBT_OK) s = init_common(t, A0, B0, C0, lambda0, st);
   if (s != SBT_OK) {
+    g_errmsg = t->errmsg;  // the tensor is gone: sbt_last_error(NULL) keeps it
     free_all(t);
     delete t;
     return s;

@@ -31,6 +31,7 @@
 // column j = lane % 16 likewise; result lane holds rows 4 (lane / 16) + v,
 // v = 0..3, of column lane % 16.  A and B use the same K grouping, so the
 // hardware's internal order of K does not matter.
+#include "../../include/sambaten.h"
 #include "device_common.hpp"
 #include "kernels.hpp"
 
@@ -66,13 +67,14 @@ __device__ inline void split_bf16x8(const float (&x)[8], bf16x8_t& hi, bf16x8_t&
 // ---------------------------------------------------------------------------
 // gather: both layouts from the resident store in one pass
 // ---------------------------------------------------------------------------
-// thread = (e, run of kGatherGroups groups of 8 third-mode positions): the
+// thread = (e, run of G groups of 8 third-mode positions): with G = 8 the
 // thread writes whole 128-byte lines of its Zc row (the groups of a run are
 // consecutive), gathering one group of 8 slices at a time; c >= K' are
 // written as zeros in Zc (the K range of pass W is K' rounded up to 32).
-constexpr int kGatherGroups = 8;
+// G only shapes the launch: every choice writes the same bytes.
+constexpr int kGatherChoices[3] = {8, 4, 16};
 
-template <typename TIn>
+template <typename TIn, int G>
 __global__ __launch_bounds__(256) void gather_mfma_kernel(const TIn* X, int64_t I, int64_t J,
                                                          const int32_t* idx, int64_t idx_stride,
                                                          int64_t offJ, int64_t offK, int n3old,
@@ -80,13 +82,13 @@ __global__ __launch_bounds__(256) void gather_mfma_kernel(const TIn* X, int64_t 
                                                          RepSet rs, MfmaLayout L, uint16_t* Zk,
                                                          uint16_t* Zc) {
   const int rep = rs.rep0 + blockIdx.z;
-  const int g0 = cg0 + (int)blockIdx.y * kGatherGroups;
+  const int g0 = cg0 + (int)blockIdx.y * G;
   const int64_t n12 = (int64_t)rs.n1 * rs.n2;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int32_t* Is = idx + rep * idx_stride;
   // the slices of the block's positions, read once into LDS (-1: c >= K')
-  __shared__ int64_t ksl[kGatherGroups * 8];
-  if (threadIdx.x < kGatherGroups * 8) {
+  __shared__ int64_t ksl[G * 8];
+  if (threadIdx.x < G * 8) {
     const int c = g0 * 8 + (int)threadIdx.x;
     int64_t k = -1;
     if (c < rs.n3) k = c < n3old ? (int64_t)Is[offK + c] : Kold + (c - n3old);
@@ -98,7 +100,7 @@ __global__ __launch_bounds__(256) void gather_mfma_kernel(const TIn* X, int64_t 
   const int64_t base = (int64_t)Is[a] + I * (int64_t)Is[offJ + b];
   uint16_t* zk = Zk + rep * L.sZk + a + (int64_t)L.ld1 * b;
   uint16_t* zc = Zc + rep * L.sZc + e * L.ldc;
-  for (int cg = g0; cg < g0 + kGatherGroups && cg < cg0 + ncg; ++cg) {
+  for (int cg = g0; cg < g0 + G && cg < cg0 + ncg; ++cg) {
     // the group's eight loads in flight together (positions c >= K' read
     // slice 0 of the store and are dropped)
     TIn x[8];
@@ -201,7 +203,7 @@ __global__ void ft_kernel(RepSet rs, int rows, int ld, int nf, const double* F, 
 // ---------------------------------------------------------------------------
 // pass W on the matrix cores
 // ---------------------------------------------------------------------------
-// Block = 4 wavefronts x 4 tiles of 16 rows e (256 rows) of one repetition;
+// Block = 4 wavefronts x WT tiles of 16 rows e (64 WT rows) of one repetition;
 // every wave runs the whole K range (K' rounded up to 32) against the three
 // parts of C~^T, whose R live rows are copied into LDS by the block in chunks
 // of at most pw_mfma_chunk(R) columns (one chunk, staged once, whenever K'
@@ -211,7 +213,9 @@ __global__ void ft_kernel(RepSet rs, int rows, int ld, int nf, const double* F, 
 // accumulation has three independent MFMAs between it and the one it
 // depends on.
 constexpr int kStageBatch = 4;  // staging loads a thread issues before its stores
-constexpr int kWTiles = 4;   // row tiles per wavefront
+// row tiles per wavefront (WT): 4, 2 or 1; each output row's sums run over
+// the same K steps in the same order whatever WT, so it only shapes the launch
+constexpr int kWTileChoices[3] = {4, 2, 1};
 constexpr int kWSteps = 2;   // K steps whose operand loads are in flight at once
 
 // columns of C~ staged per chunk: three parts' rows [R][chunk + 8] of BF16
@@ -219,7 +223,7 @@ constexpr int kWSteps = 2;   // K steps whose operand loads are in flight at onc
 constexpr int kPwLds = 52 * 1024;
 constexpr int pw_mfma_chunk(int R) { return (kPwLds / (3 * R * 2) - 8) / 32 * 32; }
 
-template <int NT>
+template <int NT, int WT>
 __global__ __launch_bounds__(256) void pw_mfma_kernel(RepSet rs, MfmaLayout L, int kp32,
                                                      int chunk, const uint16_t* Zc,
                                                      const uint16_t* Ctg, float* W) {
@@ -234,33 +238,33 @@ __global__ __launch_bounds__(256) void pw_mfma_kernel(RepSet rs, MfmaLayout L, i
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform (scalar)
   const int64_t n12 = (int64_t)rs.n1 * rs.n2;
-  const int64_t e0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * kWTiles);
+  const int64_t e0 = ((int64_t)blockIdx.x * 4 + wave) * (16 * WT);
   const int kq = lane >> 4;
-  const uint16_t* zrow[kWTiles];
+  const uint16_t* zrow[WT];
 #pragma unroll
-  for (int t = 0; t < kWTiles; ++t) {
+  for (int t = 0; t < WT; ++t) {
     const int64_t e = e0 + 16 * t + (lane & 15);
     zrow[t] = Zc + rep * L.sZc + (e < n12 ? e : n12 - 1) * L.ldc + 8 * kq;
   }
-  f32x4_t acc[kWTiles][NT];
+  f32x4_t acc[WT][NT];
 #pragma unroll
-  for (int t = 0; t < kWTiles; ++t)
+  for (int t = 0; t < WT; ++t)
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[t][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
   const u32x4_t* src = reinterpret_cast<const u32x4_t*>(Ctg + (int64_t)rep * 3 * 16 * NT * ldg);
   u32x4_t* dst = reinterpret_cast<u32x4_t*>(Ct);
-  bf16x8_t af[kWSteps][kWTiles];
+  bf16x8_t af[kWSteps][WT];
   for (int c0 = 0; c0 < kp32; c0 += chunk) {
     const int cw = kp32 - c0 < chunk ? kp32 - c0 : chunk;  // a multiple of 32
     const int ksteps = cw / 32;
-    const uint16_t* zc[kWTiles];
+    const uint16_t* zc[WT];
 #pragma unroll
-    for (int t = 0; t < kWTiles; ++t) zc[t] = zrow[t] + c0;
+    for (int t = 0; t < WT; ++t) zc[t] = zrow[t] + c0;
     // first operand loads of the chunk before its staging
 #pragma unroll
     for (int u = 0; u < kWSteps; ++u)
 #pragma unroll
-      for (int t = 0; t < kWTiles; ++t)
+      for (int t = 0; t < WT; ++t)
         if (u < ksteps) af[u][t] = ld_bf16x8(zc[t] + 32 * u);
     if (c0 > 0) __syncthreads();  // every wave is done with the previous chunk
     {
@@ -294,7 +298,7 @@ __global__ __launch_bounds__(256) void pw_mfma_kernel(RepSet rs, MfmaLayout L, i
 #pragma unroll
         for (int u = 0; u < kWSteps; ++u)
 #pragma unroll
-          for (int t = 0; t < kWTiles; ++t)
+          for (int t = 0; t < WT; ++t)
             if (k0 + u < ksteps) af[u][t] = ld_bf16x8(zc[t] + 32 * (k0 + u));
       }
 #pragma unroll
@@ -311,11 +315,11 @@ __global__ __launch_bounds__(256) void pw_mfma_kernel(RepSet rs, MfmaLayout L, i
               bl = ld_bf16x8(Cl + o);
             }
 #pragma unroll
-            for (int t = 0; t < kWTiles; ++t) acc[t][j] = mfma16x16x32(af[u][t], bh, acc[t][j]);
+            for (int t = 0; t < WT; ++t) acc[t][j] = mfma16x16x32(af[u][t], bh, acc[t][j]);
 #pragma unroll
-            for (int t = 0; t < kWTiles; ++t) acc[t][j] = mfma16x16x32(af[u][t], bm, acc[t][j]);
+            for (int t = 0; t < WT; ++t) acc[t][j] = mfma16x16x32(af[u][t], bm, acc[t][j]);
 #pragma unroll
-            for (int t = 0; t < kWTiles; ++t) acc[t][j] = mfma16x16x32(af[u][t], bl, acc[t][j]);
+            for (int t = 0; t < WT; ++t) acc[t][j] = mfma16x16x32(af[u][t], bl, acc[t][j]);
           }
         }
       }
@@ -323,7 +327,7 @@ __global__ __launch_bounds__(256) void pw_mfma_kernel(RepSet rs, MfmaLayout L, i
   }
   float* Wr = W + rep * rs.sW;
 #pragma unroll
-  for (int t = 0; t < kWTiles; ++t)
+  for (int t = 0; t < WT; ++t)
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
       const int f = 16 * j + (lane & 15);
@@ -347,9 +351,12 @@ __global__ __launch_bounds__(256) void pw_mfma_kernel(RepSet rs, MfmaLayout L, i
 // wave order; the block's partial rows go to P[rep][split][c][16 NT], and
 // mode3_finish adds the ranges in order and applies V^-1.
 constexpr int kPTiles = 4;  // row tiles of 16 per wavefront (the block's 64 rows)
-constexpr int kPSteps = 2;  // K steps whose operand loads are in flight at once
+// K steps whose operand loads are in flight at once (PS): 2, 1 or 4; the
+// steps are taken in the same order whatever PS, so it only shapes the launch
+constexpr int kPStepChoices[3] = {2, 1, 4};
+static_assert(SBT_TUNE_SHAPES == 3, "one entry per launch shape in each choice table");
 
-template <int NT>
+template <int NT, int PS>
 __global__ __launch_bounds__(256) void p3_mfma_kernel(RepSet rs, MfmaLayout L, int nsplit,
                                                      const uint16_t* Zk, const float* Atg,
                                                      const float* Btg, float* P, int64_t sP) {
@@ -379,9 +386,9 @@ __global__ __launch_bounds__(256) void p3_mfma_kernel(RepSet rs, MfmaLayout L, i
     const int c = c0 + 16 * t + (lane & 15);
     zrow[t] = Zk + rep * L.sZk + (int64_t)(c < n3 ? c : n3 - 1) * L.sk + 8 * kq;
   }
-  bf16x8_t af[kPSteps][kPTiles];
+  bf16x8_t af[PS][kPTiles];
 #pragma unroll
-  for (int u = 0; u < kPSteps; ++u)
+  for (int u = 0; u < PS; ++u)
 #pragma unroll
     for (int t = 0; t < kPTiles; ++t)
       if (kw_lo + u < kw_hi) af[u][t] = ld_bf16x8(zrow[t] + 32 * (kw_lo + u));
@@ -428,16 +435,16 @@ __global__ __launch_bounds__(256) void p3_mfma_kernel(RepSet rs, MfmaLayout L, i
   for (int t = 0; t < kPTiles; ++t)
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[t][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = kw_lo; k0 < kw_hi; k0 += kPSteps) {
+  for (int k0 = kw_lo; k0 < kw_hi; k0 += PS) {
     if (k0 > kw_lo) {
 #pragma unroll
-      for (int u = 0; u < kPSteps; ++u)
+      for (int u = 0; u < PS; ++u)
 #pragma unroll
         for (int t = 0; t < kPTiles; ++t)
           if (k0 + u < kw_hi) af[u][t] = ld_bf16x8(zrow[t] + 32 * (k0 + u));
     }
 #pragma unroll
-    for (int u = 0; u < kPSteps; ++u) {
+    for (int u = 0; u < PS; ++u) {
       if (k0 + u < kw_hi) {
         // this lane's 8 consecutive e' share one b (ld1 is a multiple of 8)
         const int ep = 32 * (k0 + u) + 8 * kq;
@@ -579,20 +586,28 @@ int mfma_mode3_splits(const RepSet& rs, const MfmaLayout& L) {
 hipError_t launch_gather_mfma(int store_prec, const void* X, int64_t I, int64_t J,
                               const int32_t* idx, int64_t idx_stride, int64_t offJ, int64_t offK,
                               int n3old, int64_t Kold, int c0, const RepSet& rs,
-                              const MfmaLayout& L, uint16_t* Zk, uint16_t* Zc, hipStream_t s) {
+                              const MfmaLayout& L, uint16_t* Zk, uint16_t* Zc, hipStream_t s,
+                              int choice) {
   const int64_t n12 = (int64_t)rs.n1 * rs.n2;
   const int kp32 = (rs.n3 + 31) / 32 * 32;
-  if (c0 < 0 || c0 >= rs.n3) return hipErrorInvalidValue;
+  if (c0 < 0 || c0 >= rs.n3 || choice < 0 || choice >= SBT_TUNE_SHAPES) return hipErrorInvalidValue;
   const int cg0 = c0 / 8;  // groups of 8 slices, the first one gathered whole
   const int ncg = kp32 / 8 - cg0;
-  dim3 grid((unsigned)((n12 + 255) / 256), (unsigned)((ncg + kGatherGroups - 1) / kGatherGroups),
-            (unsigned)rs.nrep);
-  if (store_prec == kF64)
-    timed_launch(gather_mfma_kernel<double>, grid, dim3(256), 0, s, (const double*)X, I, J, idx,
-                 idx_stride, offJ, offK, n3old, Kold, cg0, ncg, rs, L, Zk, Zc);
-  else
-    timed_launch(gather_mfma_kernel<float>, grid, dim3(256), 0, s, (const float*)X, I, J, idx,
-                 idx_stride, offJ, offK, n3old, Kold, cg0, ncg, rs, L, Zk, Zc);
+  const int G = kGatherChoices[choice];
+  dim3 grid((unsigned)((n12 + 255) / 256), (unsigned)((ncg + G - 1) / G), (unsigned)rs.nrep);
+#define SBT_GATHER(T, GG)                                                                    \
+  timed_launch(gather_mfma_kernel<T, GG>, grid, dim3(256), 0, s, (const T*)X, I, J, idx,      \
+               idx_stride, offJ, offK, n3old, Kold, cg0, ncg, rs, L, Zk, Zc)
+  if (store_prec == kF64) {
+    if (G == 8) SBT_GATHER(double, 8);
+    else if (G == 4) SBT_GATHER(double, 4);
+    else SBT_GATHER(double, 16);
+  } else {
+    if (G == 8) SBT_GATHER(float, 8);
+    else if (G == 4) SBT_GATHER(float, 4);
+    else SBT_GATHER(float, 16);
+  }
+#undef SBT_GATHER
   return hipGetLastError();
 }
 
@@ -614,7 +629,8 @@ size_t mfma_operand_floats(const MfmaLayout& L, int n2, int R) {
 
 hipError_t launch_pw_mfma(const RepSet& rs, const MfmaLayout& L, const uint16_t* Zc,
                           const double* Cf, const double* invlamC, float* W, float* ops,
-                          hipStream_t s) {
+                          hipStream_t s, int choice) {
+  if (choice < 0 || choice >= SBT_TUNE_SHAPES) return hipErrorInvalidValue;
   const int64_t n12 = (int64_t)rs.n1 * rs.n2;
   const int kp32 = (rs.n3 + 31) / 32 * 32;
   if (kp32 > L.ldc) return hipErrorInvalidValue;
@@ -629,22 +645,32 @@ hipError_t launch_pw_mfma(const RepSet& rs, const MfmaLayout& L, const uint16_t*
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  const int64_t rows_per_block = 4 * 16 * kWTiles;
+  const int WT = kWTileChoices[choice];
+  const int64_t rows_per_block = 4 * 16 * WT;
   dim3 grid((unsigned)((n12 + rows_per_block - 1) / rows_per_block), (unsigned)rs.nrep);
   const int chunk = kp32 < pw_mfma_chunk(rs.R) ? kp32 : pw_mfma_chunk(rs.R);
   const size_t sh = (size_t)3 * rs.R * (chunk + 8) * 2;
   if (sh > 65536) return hipErrorInvalidValue;
-  if (nt == 1)
-    timed_launch(pw_mfma_kernel<1>, grid, dim3(256), sh, s, rs, L, kp32, chunk, Zc, Ct, W);
-  else
-    timed_launch(pw_mfma_kernel<2>, grid, dim3(256), sh, s, rs, L, kp32, chunk, Zc, Ct, W);
+#define SBT_PW(NTT, WTT)                                                                      \
+  timed_launch(pw_mfma_kernel<NTT, WTT>, grid, dim3(256), sh, s, rs, L, kp32, chunk, Zc, Ct, W)
+  if (nt == 1) {
+    if (WT == 4) SBT_PW(1, 4);
+    else if (WT == 2) SBT_PW(1, 2);
+    else SBT_PW(1, 1);
+  } else {
+    if (WT == 4) SBT_PW(2, 4);
+    else if (WT == 2) SBT_PW(2, 2);
+    else SBT_PW(2, 1);
+  }
+#undef SBT_PW
   return hipGetLastError();
 }
 
 hipError_t launch_p3_mfma(const RepSet& rs, const MfmaLayout& L, int nsplit, const uint16_t* Zk,
                           const double* Af, const double* invlamA, const double* Bf,
                           const double* invlamB, float* P, int64_t sP, float* ops,
-                          hipStream_t s) {
+                          hipStream_t s, int choice) {
+  if (choice < 0 || choice >= SBT_TUNE_SHAPES) return hipErrorInvalidValue;
   const int nt = ntiles(rs.R), nf = 16 * nt;
   const int ldb = (rs.n2 + 3) / 4 * 4;
   float* Atg = ops;
@@ -672,10 +698,20 @@ hipError_t launch_p3_mfma(const RepSet& rs, const MfmaLayout& L, int nsplit, con
   const size_t red = (size_t)4 * 64 * nf * 4;  // the four quarters' partial rows
   if (sh < red) sh = red;
   if (sh > 65536 || sP < (int64_t)rs.n3 * nf) return hipErrorInvalidValue;
-  if (nt == 1)
-    timed_launch(p3_mfma_kernel<1>, grid, dim3(256), sh, s, rs, L, nsplit, Zk, Atg, Btg, P, sP);
-  else
-    timed_launch(p3_mfma_kernel<2>, grid, dim3(256), sh, s, rs, L, nsplit, Zk, Atg, Btg, P, sP);
+  const int PS = kPStepChoices[choice];
+#define SBT_P3(NTT, PSS)                                                                      \
+  timed_launch(p3_mfma_kernel<NTT, PSS>, grid, dim3(256), sh, s, rs, L, nsplit, Zk, Atg, Btg, \
+               P, sP)
+  if (nt == 1) {
+    if (PS == 2) SBT_P3(1, 2);
+    else if (PS == 1) SBT_P3(1, 1);
+    else SBT_P3(1, 4);
+  } else {
+    if (PS == 2) SBT_P3(2, 2);
+    else if (PS == 1) SBT_P3(2, 1);
+    else SBT_P3(2, 4);
+  }
+#undef SBT_P3
   return hipGetLastError();
 }
 

@@ -124,12 +124,16 @@ MfmaLayout mfma_layout(int n1, int n2, int kpmax);
 bool mfma_supported(int n1, int n2, int R);
 // number of K ranges of the mode-3 kernel
 int mfma_mode3_splits(const RepSet& rs, const MfmaLayout& L);
+// Launch shapes of the gather and of the two matrix-core passes that give
+// identical results: `choice` in [0, SBT_TUNE_SHAPES) picks one (0 is the
+// default shape; the tuner in autotune.h picks the others by their time).
 // both BF16 layouts; the groups of 8 slices from the one holding c0 on are
 // gathered (earlier slices are a kept summary's old part)
 hipError_t launch_gather_mfma(int store_prec, const void* X, int64_t I, int64_t J,
                               const int32_t* idx, int64_t idx_stride, int64_t offJ, int64_t offK,
                               int n3old, int64_t Kold, int c0, const RepSet& rs,
-                              const MfmaLayout& L, uint16_t* Zk, uint16_t* Zc, hipStream_t s);
+                              const MfmaLayout& L, uint16_t* Zk, uint16_t* Zc, hipStream_t s,
+                              int choice = 0);
 // one repetition from a column-major BF16 tensor (no sampling)
 hipError_t launch_relayout_bf16(const uint16_t* Z, const RepSet& rs, const MfmaLayout& L,
                                 uint16_t* Zk, uint16_t* Zc, hipStream_t s);
@@ -139,13 +143,13 @@ size_t mfma_operand_floats(const MfmaLayout& L, int n2, int R);
 // W(e, f) = sum_c Zc(e, c) C~(c, f), C~ = C diag(invlamC) (invlamC may be null)
 hipError_t launch_pw_mfma(const RepSet& rs, const MfmaLayout& L, const uint16_t* Zc,
                           const double* Cf, const double* invlamC, float* W, float* ops,
-                          hipStream_t s);
+                          hipStream_t s, int choice = 0);
 // partial rows of Zk (B~ kr A~) over nsplit K ranges into P[rep][split] (stride sP,
 // row stride 16 or 32)
 hipError_t launch_p3_mfma(const RepSet& rs, const MfmaLayout& L, int nsplit, const uint16_t* Zk,
                           const double* Af, const double* invlamA, const double* Bf,
                           const double* invlamB, float* P, int64_t sP, float* ops,
-                          hipStream_t s);
+                          hipStream_t s, int choice = 0);
 // U(c, :) = (sum_split P) V^-1 [/ lam_div]
 // gpart: also the Gram matrix of each block's rows, as launch_cw writes them
 hipError_t launch_mode3_finish(const RepSet& rs, int nsplit, const float* P, int64_t sP,

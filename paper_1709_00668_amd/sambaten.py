@@ -22,6 +22,8 @@ SBT_DENSE, SBT_COO = 0, 1
 SBT_FLAG_LAMBDA_AVG = 1
 SBT_P_F64, SBT_P_F32, SBT_P_BF16 = 0, 1, 2
 SBT_SCHED_BATCHED, SBT_SCHED_PLAIN = 0, 1
+SBT_TUNE_OFF, SBT_TUNE_ON, SBT_TUNE_CACHED, SBT_TUNE_FIXED = 0, 1, 2, 3
+SBT_TUNE_SHAPES = 3
 (SBT_K_MTTKRP_C, SBT_K_MTTKRP_AB, SBT_K_GATHER, SBT_K_UPDATE, SBT_K_COO_MTTKRP,
  SBT_K_ROW_SOLVE) = range(6)
 (SBT_REP_AP, SBT_REP_BP, SBT_REP_CP, SBT_REP_LAMP, SBT_REP_PI, SBT_REP_VALID, SBT_REP_AT,
@@ -109,6 +111,11 @@ _SIGS = {
     "sbt_nd_get_factor": (ctypes.c_int, [_vp, _i32, _vp, _vp]),
     "sbt_nd_get_lambda": (ctypes.c_int, [_vp, _vp, _vp]),
     "sbt_nd_last_rep": (ctypes.c_int, [_vp, _i32, _i32, _i32, _vp, _i64, ctypes.POINTER(_i64)]),
+    "sbt_autotune_set": (ctypes.c_int, [_i32, _i32]),
+    "sbt_autotune_clear": (ctypes.c_int, []),
+    "sbt_autotune_count": (ctypes.c_int, [ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
+    "sbt_autotune_save": (ctypes.c_int, [ctypes.c_char_p]),
+    "sbt_autotune_load": (ctypes.c_int, [ctypes.c_char_p]),
     "sbt_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "sbt_last_error": (ctypes.c_char_p, [_vp]),
 }
@@ -124,6 +131,12 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                            "`python -m paper_1709_00668_amd.build`")
+    # torch ships its own HIP runtime; loaded first, it is the one the
+    # library's libamdhip64 dependency resolves to, so device pointers and
+    # streams from torch are valid in the library's calls.  Loading the
+    # library first would bind it to the system runtime and leave torch and
+    # the library on two runtimes in one process.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib, name)
@@ -221,7 +234,7 @@ class Tensor:
                 fa[q] = a.ctypes.data
         st = lib.sbt_init_dense(ctypes.byref(cfg), _ptr(X0_dev), I, J, K0, fa[0], fa[1], fa[2],
                                 fa[3], _stream(stream), ctypes.byref(out))
-        _check(st, None, "sbt_init_dense")
+        _check(st, None, "sbt_init_dense", global_msg=True)
         return cls(out.value)
 
     @classmethod
@@ -235,7 +248,7 @@ class Tensor:
         st = lib.sbt_init_coo(ctypes.byref(cfg), _ptr(idx_dev[0]), _ptr(idx_dev[1]),
                               _ptr(idx_dev[2]), _ptr(vals_dev), nnz, I, J, K0, fa[0], fa[1],
                               fa[2], fa[3], _stream(stream), ctypes.byref(out))
-        _check(st, None, "sbt_init_coo")
+        _check(st, None, "sbt_init_coo", global_msg=True)
         return cls(out.value)
 
     @classmethod
@@ -409,7 +422,7 @@ class TensorN(Tensor):
         st = lib.sbt_nd_init_dense(ctypes.byref(cfg), N, d.ctypes.data, sf.ctypes.data,
                                    _ptr(X0_dev), ctypes.cast(fptr, _vp) if fptr else None, lptr,
                                    _stream(stream), ctypes.byref(out))
-        _check(st, None, "sbt_nd_init_dense")
+        _check(st, None, "sbt_nd_init_dense", global_msg=True)
         return cls(out.value)
 
     @classmethod
@@ -439,7 +452,7 @@ class TensorN(Tensor):
                                  ctypes.cast(iptr, _vp), _ptr(v), nnz,
                                  ctypes.cast(fptr, _vp) if fptr else None, lptr,
                                  _stream(stream), ctypes.byref(out))
-        _check(st, None, "sbt_nd_init_coo")
+        _check(st, None, "sbt_nd_init_coo", global_msg=True)
         return cls(out.value)
 
     def update_batch_coo_nd(self, cols, v, K_new, stream=None):
@@ -487,6 +500,32 @@ class TensorN(Tensor):
         v = buf[:n.value].copy()
         return v if item in (SBT_ND_REP_LAMP, SBT_ND_REP_PI, SBT_ND_REP_VALID) else \
             v.reshape(-1, R)
+
+
+def autotune_set(mode, shape=0):
+    """Launch-shape tuner mode (process-wide): SBT_TUNE_OFF / ON / CACHED, or
+    SBT_TUNE_FIXED with every tuned launch in `shape`."""
+    _check(load().sbt_autotune_set(int(mode), int(shape)), None, "sbt_autotune_set")
+
+
+def autotune_clear():
+    _check(load().sbt_autotune_clear(), None, "sbt_autotune_clear")
+
+
+def autotune_count():
+    """(keys decided, keys with trials running)."""
+    d, u = _i64(), _i64()
+    _check(load().sbt_autotune_count(ctypes.byref(d), ctypes.byref(u)), None,
+           "sbt_autotune_count")
+    return d.value, u.value
+
+
+def autotune_save(path):
+    _check(load().sbt_autotune_save(os.fsencode(path)), None, "sbt_autotune_save")
+
+
+def autotune_load(path):
+    _check(load().sbt_autotune_load(os.fsencode(path)), None, "sbt_autotune_load")
 
 
 def mttkrp_dense(precision, Z_dev, n1, n2, n3, R, U0_dev, U1_dev, U2_dev, mode, out_dev,

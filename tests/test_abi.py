@@ -56,3 +56,20 @@ def test_status_strings_without_gpu():
     lib = sambaten.load()
     for s in range(8):
         assert lib.sbt_status_str(s)
+
+
+def test_library_shares_torch_hip_runtime():
+    # torch ships its own HIP runtime: loading the library through the
+    # binding, even before anything imported torch, must leave one runtime
+    # mapped in the process (two would not share devices, pointers or streams)
+    import sys
+    code = ("import os\n"
+            "from paper_1709_00668_amd import sambaten\n"
+            "sambaten.load()\n"
+            "import torch\n"
+            "m = open(f'/proc/{os.getpid()}/maps').read()\n"
+            "print(sorted({l.split()[-1] for l in m.splitlines() if 'amdhip64' in l}))\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], cwd=root, check=True,
+                         capture_output=True, text=True).stdout.strip()
+    assert out.count("libamdhip64") == 1, out
