@@ -93,6 +93,9 @@ void harvest() {
     Pending& p = g_pending[i];
     const hipError_t q = hipEventQuery(p.b);
     if (q == hipErrorNotReady) {
+      // not a failure, but HIP may keep it as the thread's last error, which
+      // the next launch's error check would read
+      (void)hipGetLastError();
       g_pending[w++] = p;
       continue;
     }
@@ -214,6 +217,7 @@ sbt_status sbt_autotune_clear(void) {
   size_t w = 0;
   for (size_t i = 0; i < g_pending.size(); ++i) {
     if (hipEventQuery(g_pending[i].b) == hipErrorNotReady) {
+      (void)hipGetLastError();
       g_pending[w++] = g_pending[i];
     } else {
       (void)hipGetLastError();
