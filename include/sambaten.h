@@ -395,8 +395,9 @@ sbt_status sbt_profile_read(const sbt_tensor* t, int32_t kind, int64_t* launches
  * key it has not decided, times the hot path's own launches in the shapes in
  * turn (two each, event pairs read back without waiting); from then on the
  * shape with the least time per unit of work is used for that key.  A
- * launch whose key is still undecided, or that is captured into a graph,
- * uses shape 0.  The choice never changes a result, only the time.
+ * launch whose key is still undecided uses shape 0 unless it is a trial (a
+ * launch captured into a graph never is).  The choice never changes a
+ * result, only the time.
  *
  * sbt_autotune_set: mode SBT_TUNE_OFF (shape 0 always), SBT_TUNE_ON (the
  *   default: decide unseen keys online), SBT_TUNE_CACHED (decided keys only,
