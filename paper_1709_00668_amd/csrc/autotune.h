@@ -42,5 +42,8 @@ TuneSlot tune_begin(int kernel, int nchoices, const int64_t (&shape)[4], double 
                     bool may_time, hipStream_t s);
 // Records the trial's stop event after the launch (no-op for other launches).
 void tune_end(const TuneSlot& slot, hipStream_t s);
+// In place of tune_end when the launch failed: the trial does not count and
+// its events go back to the pool.
+void tune_cancel(const TuneSlot& slot);
 
 }  // namespace sbt

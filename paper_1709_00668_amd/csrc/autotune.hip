@@ -194,6 +194,16 @@ void tune_end(const TuneSlot& slot, hipStream_t s) {
   g_pending.push_back(Pending{k, slot.choice, slot.device, slot.work, slot.start, slot.stop});
 }
 
+void tune_cancel(const TuneSlot& slot) {
+  if (!slot.timed) return;
+  std::lock_guard<std::mutex> lock(g_mu);
+  Key k{arch_of(slot.device), slot.kernel,
+        {slot.shape[0], slot.shape[1], slot.shape[2], slot.shape[3]}};
+  auto it = g_table.find(k);
+  if (it != g_table.end() && it->second.issued[slot.choice] > 0) --it->second.issued[slot.choice];
+  g_free[slot.device].push_back({slot.start, slot.stop});
+}
+
 }  // namespace sbt
 
 using namespace sbt;

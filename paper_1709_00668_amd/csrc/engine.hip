@@ -1108,8 +1108,10 @@ sbt_status run_als(sbt_tensor* t, const void* Zp, RepSet rs, double* Ap, double*
     int pq = prof_kernel(t);
     if (mf) {
       const TuneSlot ts = tune_begin(kTunePw, SBT_TUNE_SHAPES, pw_key, mf_work, !capture, st);
-      SBT_CK(launch_pw_mfma(rs, t->ml, t->Zc, Cp, ilC, (float*)W, t->mops, st, ts.choice));
-      tune_end(ts, st);
+      const hipError_t pw_mfma_launch =
+          launch_pw_mfma(rs, t->ml, t->Zc, Cp, ilC, (float*)W, t->mops, st, ts.choice);
+      if (pw_mfma_launch == hipSuccess) tune_end(ts, st); else tune_cancel(ts);
+      SBT_CK(pw_mfma_launch);
       prof_end(t, pq, SBT_K_MTTKRP_C, pwm_bytes, st);
     } else {
       SBT_CK(launch_pw(prec, rs, Zp, Cp, ilC, W, st));
@@ -1136,9 +1138,10 @@ sbt_status run_als(sbt_tensor* t, const void* Zp, RepSet rs, double* Ap, double*
     double* gpc = nullptr;
     if (mf) {
       const TuneSlot ts = tune_begin(kTuneP3, SBT_TUNE_SHAPES, p3_key, mf_work, !capture, st);
-      SBT_CK(launch_p3_mfma(rs, t->ml, ns3, t->Zk, Ap, ilA, Bp, ilB, t->P3, t->sP3, t->mops,
-                            st, ts.choice));
-      tune_end(ts, st);
+      const hipError_t p3_mfma_launch = launch_p3_mfma(
+          rs, t->ml, ns3, t->Zk, Ap, ilA, Bp, ilB, t->P3, t->sP3, t->mops, st, ts.choice);
+      if (p3_mfma_launch == hipSuccess) tune_end(ts, st); else tune_cancel(ts);
+      SBT_CK(p3_mfma_launch);
       prof_end(t, pq, SBT_K_MTTKRP_AB, p3m_bytes, st);
       gpc = gram_parts_buf(t, rs, rs.n3);
       SBT_CK(launch_mode3_finish(rs, ns3, t->P3, t->sP3, Vinv, nullptr, Cp, rs.sC, st, gpc,
@@ -1380,9 +1383,11 @@ sbt_status update_body(sbt_tensor* t, int64_t Kn, int uq, hipStream_t st) {
     const int64_t gkey[4] = {t->store_prec, (int64_t)t->n1 * t->n2, r, c0 > 0 ? 1 : 0};
     const TuneSlot ts = tune_begin(kTuneGather, SBT_TUNE_SHAPES, gkey,
                                    (double)r * t->n1 * t->n2 * (Kp - c0), true, st);
-    SBT_CK(launch_gather_mfma(t->store_prec, t->X, t->I, t->J, t->idx, t->idx_stride, offJ, offK,
-                              n3old, Kold, c0, all, t->ml, t->Zk, t->Zc, st, ts.choice));
-    tune_end(ts, st);
+    const hipError_t gather_mfma_launch =
+        launch_gather_mfma(t->store_prec, t->X, t->I, t->J, t->idx, t->idx_stride, offJ, offK,
+                           n3old, Kold, c0, all, t->ml, t->Zk, t->Zc, st, ts.choice);
+    if (gather_mfma_launch == hipSuccess) tune_end(ts, st); else tune_cancel(ts);
+    SBT_CK(gather_mfma_launch);
     prof_end(t, gq, SBT_K_GATHER,
              (double)r * t->n1 * t->n2 * (Kp - c0) * (prec_bytes(t->store_prec) + 4.0), st);
   } else if (t->fmt == SBT_DENSE) {
